@@ -1,0 +1,150 @@
+/*
+ * dgsem.h -- C ABI of the MI355X (gfx950) DGSEM operator library, libdgsem.so.
+ *
+ * The library evaluates the semi-discrete discontinuous Galerkin spectral element
+ * operator U -> U_t for the compressible Euler / Navier-Stokes equations on conforming
+ * curvilinear hexahedra (Krais et al., "FLEXI", Sec. 3.1, eq. semiDiscrete; strong form
+ * eq. semiDiscreteStrong; split form Sec. 3.3, eq. semiDiscreteSplit), with BR1 lifting of
+ * the gradients (Sec. 3.1, eq. discreteGradient) and advances it with the two-register
+ * low-storage Runge-Kutta scheme (Sec. 4.4).  Every step runs in HIP kernels on the GPU;
+ * the host only validates arguments, builds the geometry once in dg_init and launches.
+ *
+ * Conventions shared by every entry point
+ *  - Solution arrays are DEVICE pointers to FP64, owned by the caller, layout
+ *    U[e][v][k][j][i] (i fastest), v = (rho, rho u, rho v, rho w, E), n = N+1 nodes per
+ *    direction.  Element e's block of one variable is n^3 contiguous doubles.
+ *  - Side numbering: side 2d is the face xi_d = -1, side 2d+1 the face xi_d = +1.
+ *  - Calls are asynchronous and ordered on the HIP stream given to dg_init (or
+ *    dg_set_stream), except the ones marked "synchronous".  A handle is not thread-safe.
+ *  - Errors: every int-returning call returns a dg_status; nothing aborts or throws across
+ *    the ABI.  Argument checks happen on the host before any launch; a HIP error is
+ *    reported as DG_ERR_HIP.  dg_last_error() gives a readable message for the handle.
+ *  - Inputs and outputs of one call must not overlap unless stated.
+ */
+#ifndef DGSEM_H
+#define DGSEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_handle dg_handle; /* owns geometry, tables and scratch on the device */
+typedef struct dg_batch dg_batch;   /* owns the work list of a batched launch        */
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = -1,         /* null/misaligned pointer, bad size, aliasing, bad enum value */
+  DG_ERR_MESH = -2,        /* J <= 0 somewhere, or inconsistent connectivity               */
+  DG_ERR_UNSUPPORTED = -3, /* valid request outside what this build implements            */
+  DG_ERR_HIP = -4,         /* a HIP runtime call failed                                    */
+  DG_ERR_NONFINITE = -5,   /* NaN or Inf found by dg_check_finite                          */
+  DG_ERR_OOM = -6          /* device allocation failed                                     */
+} dg_status;
+
+/* interpolation / quadrature nodes (Sec. 3.1: LG or LGL) */
+enum { DG_NODES_LG = 0, DG_NODES_LGL = 1 };
+/* equation system (Sec. 3.1, eq. 3DconsLaw; viscous part via BR1) */
+enum { DG_EULER = 0, DG_NAVIER_STOKES = 1 };
+/* discretisation of the volume integral: weak (eq. semiDiscrete), split flux
+ * differencing (eq. semiDiscreteSplit, LGL only), strong (eq. semiDiscreteStrong, LGL only) */
+enum { DG_FORM_WEAK = 0, DG_FORM_SPLIT = 1, DG_FORM_STRONG = 2 };
+/* two-point volume flux of the split form (Sec. 3.3): kinetic-energy preserving
+ * (Pirozzoli), entropy conserving (Chandrashekar), or the mean of the two Euler fluxes */
+enum { DG_VF_KEP = 0, DG_VF_EC = 1, DG_VF_CENTRAL = 2 };
+/* convective surface flux (Sec. 2.2.3 names LLF and Roe; Sec. 3.3 allows the volume's
+ * two-point flux, optionally with Roe-type dissipation) */
+enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
+
+typedef struct {
+  int32_t n_elems;         /* K >= 1                                                        */
+  int32_t n_geo;           /* polynomial degree of the geometry; must equal N               */
+  const double *xgeo;      /* HOST [K][3][(n_geo+1)^3] physical coordinates at the LGL nodes
+                              of degree n_geo (node i + n*(j + n*k))                         */
+  const int32_t *nbr_elem; /* HOST [K][6] element across each side                          */
+  const int8_t *nbr_side;  /* HOST [K][6] side of that neighbour (must be the opposite side) */
+  const int8_t *flip;      /* HOST [K][6] orientation; NULL or all 0 (only 0 supported)      */
+} dg_mesh;
+
+typedef struct {
+  int32_t eqn, form, volflux, riemann; /* enums above                                      */
+  double gamma;                        /* ratio of specific heats (> 1)                    */
+  double R;                            /* gas constant (> 0), T = p/(rho R)                */
+  double mu;                           /* dynamic viscosity (>= 0, Navier-Stokes only)     */
+  double Pr;                           /* Prandtl number (> 0)                             */
+} dg_scheme;
+
+/* Reference nodes and quadrature weights of degree N (n = N+1 values each), host arrays.
+ * Sec. 3.1: roots of P_{N+1} (LG) or +-1 and the roots of P_N' (LGL).  Synchronous. */
+int dg_nodes(int N, int node_type, double *x, double *w);
+
+/* Carpenter-Kennedy 5-stage 4th-order 2N-storage coefficients a[5], b[5], c[5] (host). */
+int dg_rk_coefficients(double *a, double *b, double *c);
+
+/* Build the operator for a mesh (Sec. 3.1: metric terms in curl form, eq.
+ * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
+ * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
+ * Supported: 1 <= N <= 8, periodic/conforming meshes with flip 0.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
+int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
+            dg_handle **out);
+
+/* Change the stream later calls are ordered on. */
+int dg_set_stream(dg_handle *h, void *hip_stream);
+
+/* U_t = L(U) (eq. semiDiscrete / semiDiscreteStrong / semiDiscreteSplit, BR1 lifting for
+ * Navier-Stokes).  U, Ut: device [K][5][n^3]; Ut is overwritten; U and Ut must differ. */
+int dg_rhs(dg_handle *h, const double *U, double *Ut);
+
+/* One stage of the 2N-storage Runge-Kutta scheme (Sec. 4.4):
+ *   R <- a*R + dt*L(U_in);   U_out <- U_in + b*R.
+ * U_in, U_out, R: device [K][5][n^3].  U_in == U_out is rejected (DG_ERR_ARG): neighbours
+ * read the old face values of U_in during the stage.  R is read and written in place. */
+int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
+
+/* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
+ * Supported for LGL split/strong forms; derivative of |x| at 0 and of max at a tie are
+ * the mean of the one-sided derivatives.  Device arrays [K][5][n^3], pairwise distinct. */
+int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_bar);
+
+/* Reverse of dg_rk_stage at the stage input U_in.  On entry U_bar, R_bar hold the
+ * adjoints of (U_out, R after the stage); on return they hold the adjoints of
+ * (U_in, R before the stage):
+ *   R_bar <- R_bar + b*U_bar;  U_bar <- U_bar + dt*(dL/dU)(U_in)^T R_bar;  R_bar <- a*R_bar. */
+int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt);
+
+/* Largest stable step (eqs. CFLCondition and DFLCondition with gamma_RK = 1, evaluated per
+ * reference direction from the metric terms).  Synchronous; result in *dt_out (host). */
+int dg_timestep(dg_handle *h, const double *U, double cfl, double dfl, double *dt_out);
+
+/* Quadrature integrals sum_e sum_ijk J w_i w_j w_k X over the mesh, synchronous, host
+ * out[8] = {rho, rho u, rho v, rho w, E, kinetic energy, entropy -rho s/(gamma-1), min J}. */
+int dg_integrals(dg_handle *h, const double *U, double out[8]);
+
+/* DG_ERR_NONFINITE if any entry of U is NaN or Inf, DG_OK otherwise.  Synchronous. */
+int dg_check_finite(dg_handle *h, const double *U);
+
+/* Physical coordinates of the solution nodes, HOST out [K][3][n^3].  Synchronous. */
+int dg_node_coords(dg_handle *h, double *x_host);
+
+/* Sizes: out[0] = K, out[1] = N, out[2] = n^3, out[3] = node type. */
+int dg_info(const dg_handle *h, int64_t out[4]);
+
+void dg_destroy(dg_handle *h);
+const char *dg_status_string(int status);
+const char *dg_last_error(const dg_handle *h);
+
+/* ---- batched ensembles: many independent handles advanced by one launch per stage ----
+ * The members keep their own meshes, degrees and schemes (LGL split/strong forms);
+ * dg_batch_rk_stage applies dg_rk_stage to every member with its own a[i], b[i], dt[i]
+ * using one persistent kernel launch per kernel phase on the stream of members[0]. */
+int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out);
+int dg_batch_rk_stage(dg_batch *b, const double *const *U_in, double *const *U_out, double *const *R,
+                      const double *a, const double *b_coef, const double *dt);
+void dg_batch_destroy(dg_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGSEM_H */

@@ -1,0 +1,1005 @@
+// Plain FP64 CPU oracle of the DGSEM operator and its low-storage Runge-Kutta stage.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+// leg of the benchmark load this library.  It shares no code with the GPU path:
+// basis, geometry, fluxes and operator are written out here a second time, in the
+// order the paper derives them, with plain loops and no blocking or fusion.
+//
+// Paper map (Krais et al., FLEXI, Section 3 "Numerical methods"):
+//   basis / differentiation matrix .... Sec. 3.1, eq. approxSol, definition of D
+//   curl-form metric terms ............ Sec. 3.1, eq. contravariantBasisVectorsCurl
+//   weak-form operator ................ Sec. 3.1, eqs. discVolInt, discSurfInt, semiDiscrete
+//   strong-form operator .............. Sec. 3.1, eq. semiDiscreteStrong
+//   BR1 lifting ....................... Sec. 3.1 "Approximation for second order equations",
+//                                       eqs. weakFormulationGradient, discreteGradient
+//   split form ........................ Sec. 3.3 "Split DG", eq. semiDiscreteSplit
+//   low-storage RK, time step ......... Sec. 4.4 "Time integration", eqs. CFLCondition, DFLCondition
+//
+// Readings of the paper taken here (each is also listed in the design notes):
+//   * Dhat_ij = -(w_j/w_i) D_ji, which is what the derivation of the volume integral
+//     gives (the printed ratio is inverted).
+//   * LG prolongation contracts along the face-normal index.
+//   * every face term enters with the outward normal; the strong-form interior term is
+//     F_int . N_out (so -F^1 on the -xi1 face).
+//   * the split form carries the same -1/J scaling as the weak form.
+//   * geometry: mapping sampled at degree-N LGL nodes, curl form on LGL nodes, exact
+//     interpolation to LG nodes; J = det of the D-derived mapping Jacobian.
+//   * face normals and surface elements are taken from the master (the element that
+//     owns the face as its +xi side); the slave uses the negated master normal and
+//     the negated master flux.
+//   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
+//     Stokes' hypothesis, Fourier heat flux, constant viscosity.
+//   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
+//   * the split-form viscous part uses the strong form with D; the BR1 viscous surface
+//     flux is the mean of both sides.
+//   * two-point fluxes: kinetic-energy preserving (Pirozzoli) and entropy conserving
+//     (Chandrashekar), written from their defining properties; the logarithmic mean uses
+//     a 4-term series when ((a-b)/(a+b))^2 < 1e-4.
+//   * RK: Carpenter-Kennedy five-stage fourth-order 2N-storage scheme.
+//   * derivative of |x| at 0 is 0, of max(a,b) at a tie is 1/2 for each argument, where
+//     "at 0" and "tie" include rounding-level distances (relative 1e-12).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace orc {
+
+// ------------------------------------------------------------------------------ dual numbers
+struct dual {
+  double v, d;
+  dual() : v(0), d(0) {}
+  dual(double a) : v(a), d(0) {}
+  dual(double a, double b) : v(a), d(b) {}
+};
+inline dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
+inline dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
+inline dual operator-(dual a) { return dual(-a.v, -a.d); }
+inline dual operator*(dual a, dual b) { return dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline dual operator/(dual a, dual b) { return dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+inline dual& operator+=(dual& a, dual b) { a = a + b; return a; }
+inline dual& operator-=(dual& a, dual b) { a = a - b; return a; }
+inline dual& operator*=(dual& a, dual b) { a = a * b; return a; }
+inline bool operator<(dual a, dual b) { return a.v < b.v; }
+inline bool operator>(dual a, dual b) { return a.v > b.v; }
+inline double val(double a) { return a; }
+inline double val(dual a) { return a.v; }
+inline dual sqrt(dual a) { double s = std::sqrt(a.v); return dual(s, a.d / (2.0 * s)); }
+inline dual log(dual a) { return dual(std::log(a.v), a.d / a.v); }
+inline dual fabs(dual a) {
+  if (a.v > 0) return a;
+  if (a.v < 0) return -a;
+  return dual(0.0, 0.0);  // derivative of |x| at 0 taken as 0 (mean of one-sided derivatives)
+}
+inline double fabs(double a) { return std::fabs(a); }
+inline double sqrt(double a) { return std::sqrt(a); }
+inline double log(double a) { return std::log(a); }
+// Kinks.  |x| whose value lies within 1e-12 of its natural scale (a sound speed) is taken
+// as sitting on the kink, with derivative 0 (the mean of the one-sided derivatives); this
+// covers symmetry planes where x is zero up to rounding.  max(a,b) with a relative gap below
+// 1e-12 is a tie whose derivative is split evenly.  Values are unaffected.
+inline double kabs(double a, double) { return std::fabs(a); }
+inline dual kabs(dual a, double scale) {
+  if (std::fabs(a.v) <= 1e-12 * scale) return dual(std::fabs(a.v), 0.0);
+  return fabs(a);
+}
+inline double tmax(double a, double b) { return a > b ? a : b; }
+inline dual tmax(dual a, dual b) {
+  double m = std::max(std::fabs(a.v), std::fabs(b.v));
+  if (std::fabs(a.v - b.v) <= 1e-12 * m) return dual(std::max(a.v, b.v), 0.5 * (a.d + b.d));
+  return a.v > b.v ? a : b;
+}
+
+// ------------------------------------------------------------------------------ basis
+// Legendre polynomial P_n(x) and its derivative by the three-term recurrence.
+static void legendre(int n, double x, double& P, double& dP) {
+  if (n == 0) { P = 1; dP = 0; return; }
+  double p0 = 1, p1 = x, d0 = 0, d1 = 1;
+  for (int k = 1; k < n; ++k) {
+    double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    double d2 = d0 + (2 * k + 1) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  P = p1; dP = d1;
+}
+
+struct Basis {
+  int N = 0, n = 0, type = 0;           // type 0: LG, 1: LGL
+  std::vector<double> x, w, lam;        // nodes, weights, barycentric weights
+  std::vector<double> D, Dhat;          // [r*n+s]
+  std::vector<double> lm, lp;           // l_j(-1), l_j(+1)
+  std::vector<double> lhm, lhp;         // l_j(+-1)/w_j
+};
+
+// Gauss nodes: roots of P_{N+1}; Gauss-Lobatto: +-1 and the roots of P_N'.
+static void gauss_nodes(int N, int type, std::vector<double>& x, std::vector<double>& w) {
+  const int n = N + 1;
+  x.assign(n, 0.0); w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  if (type == 0) {
+    for (int j = 0; j < (n + 1) / 2; ++j) {  // lower half; the upper half by symmetry
+      double xi = -std::cos((2.0 * j + 1.0) * pi / (2.0 * N + 2.0));
+      for (int it = 0; it < 100; ++it) {
+        double P, dP; legendre(n, xi, P, dP);
+        double dx = P / dP; xi -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      double P, dP; legendre(n, xi, P, dP);
+      x[j] = xi; w[j] = 2.0 / ((1.0 - xi * xi) * dP * dP);
+    }
+  } else {
+    x[0] = -1; x[N] = 1;
+    for (int j = 1; j < (n + 1) / 2; ++j) {  // lower half; the upper half by symmetry
+      // Newton on q = P_{N+1} - P_{N-1}, whose interior roots are those of P_N'; q' = (2N+1) P_N
+      double xi = -std::cos((j + 0.25) * pi / N - 3.0 / (8.0 * N * pi * (j + 0.25)));
+      for (int it = 0; it < 100; ++it) {
+        double Pa, dPa, Pb, dPb, Pn, dPn;
+        legendre(N + 1, xi, Pa, dPa); legendre(N - 1, xi, Pb, dPb); legendre(N, xi, Pn, dPn);
+        double dx = (Pa - Pb) / ((2.0 * N + 1.0) * Pn); xi -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      x[j] = xi;
+    }
+    for (int j = 0; j < (n + 1) / 2; ++j) {
+      double P, dP; legendre(N, x[j], P, dP);
+      w[j] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+  }
+  // the node set is symmetric about 0
+  if (n % 2 == 1) {
+    x[N / 2] = 0.0;
+    double P, dP;
+    if (type == 0) { legendre(n, 0.0, P, dP); w[N / 2] = 2.0 / (dP * dP); }
+    else { legendre(N, 0.0, P, dP); w[N / 2] = 2.0 / (N * (N + 1.0) * P * P); }
+  }
+  for (int j = 0; j < n / 2; ++j) { x[N - j] = -x[j]; w[N - j] = w[j]; }
+}
+
+// Lagrange polynomial l_j(t) of the node set x (barycentric form).
+static double lagrange(const std::vector<double>& x, const std::vector<double>& lam, int j, double t) {
+  const int n = (int)x.size();
+  for (int k = 0; k < n; ++k)
+    if (t == x[k]) return (k == j) ? 1.0 : 0.0;
+  double den = 0;
+  for (int k = 0; k < n; ++k) den += lam[k] / (t - x[k]);
+  return (lam[j] / (t - x[j])) / den;
+}
+
+static Basis make_basis(int N, int type) {
+  Basis b; b.N = N; b.n = N + 1; b.type = type;
+  const int n = b.n;
+  gauss_nodes(N, type, b.x, b.w);
+  b.lam.assign(n, 1.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k)
+      if (k != j) b.lam[j] /= (b.x[j] - b.x[k]);
+  // D_rs = l_s'(x_r)
+  b.D.assign(n * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    double s_sum = 0;
+    for (int s = 0; s < n; ++s) {
+      if (s == r) continue;
+      double v = (b.lam[s] / b.lam[r]) / (b.x[r] - b.x[s]);
+      b.D[r * n + s] = v; s_sum += v;
+    }
+    b.D[r * n + r] = -s_sum;
+  }
+  // weak-form matrix from the volume-integral derivation: Dhat_ij = -(w_j/w_i) D_ji
+  b.Dhat.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) b.Dhat[i * n + j] = -(b.w[j] / b.w[i]) * b.D[j * n + i];
+  b.lm.resize(n); b.lp.resize(n); b.lhm.resize(n); b.lhp.resize(n);
+  for (int j = 0; j < n; ++j) {
+    b.lm[j] = lagrange(b.x, b.lam, j, -1.0);
+    b.lp[j] = lagrange(b.x, b.lam, j, 1.0);
+    b.lhm[j] = b.lm[j] / b.w[j];
+    b.lhp[j] = b.lp[j] / b.w[j];
+  }
+  return b;
+}
+
+// ------------------------------------------------------------------------------ mesh + metrics
+struct Mesh {
+  int K = 0, N = 0, n = 0, n2 = 0, n3 = 0, type = 0;
+  Basis sol, lgl;
+  std::vector<int32_t> nbr;        // [e][6]
+  std::vector<int8_t> nside;       // [e][6]
+  std::vector<double> Ja;          // [e][i*3+d][node]: Ja^i_d
+  std::vector<double> J;           // [e][node]
+  std::vector<double> xs;          // [e][3][node] solution-node positions
+  std::vector<double> fn;          // [e][s][3][p]: outward scaled normal of side s (master's)
+};
+
+static inline int nid(int n, int i, int j, int k) { return i + n * (j + n * k); }
+
+// position of face point (a,b) of side s within the element volume index space (LGL only)
+static inline void face_dirs(int s, int& dn, int& da, int& db) {
+  dn = s / 2;
+  da = (dn == 0) ? 1 : 0;
+  db = (dn == 2) ? 1 : 2;
+}
+
+// node of the line through face point (a,b) of direction dn at position m along dn
+static inline int line_node(int n, int dn, int a, int b, int m) {
+  int idx[3];
+  int da = (dn == 0) ? 1 : 0, db = (dn == 2) ? 1 : 2;
+  idx[dn] = m; idx[da] = a; idx[db] = b;
+  return nid(n, idx[0], idx[1], idx[2]);
+}
+
+// apply the 1D matrix A (rows x n) along direction dir to field f on an n^3 grid
+static void apply_dir(const std::vector<double>& A, int n, int dir, const double* f, double* out) {
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        int id[3] = {i, j, k};
+        double s = 0;
+        for (int m = 0; m < n; ++m) {
+          int jd[3] = {i, j, k};
+          jd[dir] = m;
+          s += A[id[dir] * n + m] * f[nid(n, jd[0], jd[1], jd[2])];
+        }
+        out[nid(n, i, j, k)] = s;
+      }
+}
+
+static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, const int32_t* nbr,
+                       const int8_t* nside) {
+  M.K = K; M.N = N; M.n = N + 1; M.n2 = M.n * M.n; M.n3 = M.n2 * M.n; M.type = type;
+  const int n = M.n, n2 = M.n2, n3 = M.n3;
+  M.sol = make_basis(N, type);
+  M.lgl = make_basis(N, 1);
+  M.nbr.assign(nbr, nbr + 6 * (size_t)K);
+  M.nside.assign(nside, nside + 6 * (size_t)K);
+  M.Ja.assign((size_t)K * 9 * n3, 0.0);
+  M.J.assign((size_t)K * n3, 0.0);
+  M.xs.assign((size_t)K * 3 * n3, 0.0);
+  M.fn.assign((size_t)K * 6 * 3 * n2, 0.0);
+  // interpolation matrix LGL -> solution nodes
+  std::vector<double> V(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = lagrange(M.lgl.x, M.lgl.lam, j, M.sol.x[i]);
+  bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+  for (int e = 0; e < K; ++e) {
+    std::vector<double> dx(9 * n3), Vf(3 * n3), tmp(n3), tmp2(n3), JaL(9 * n3);
+    const double* xe = xgeo + (size_t)e * 3 * n3;
+    // dx[(d*3+k)] = d x_d / d xi_k on LGL nodes
+    for (int d = 0; d < 3; ++d)
+      for (int k = 0; k < 3; ++k) apply_dir(M.lgl.D, n, k, xe + d * n3, &dx[(d * 3 + k) * n3]);
+    // curl form: Ja^i_nn = -(curl_xi (x_l grad_xi x_m))_i, (nn,m,l) cyclic
+    for (int nn = 0; nn < 3; ++nn) {
+      int m = (nn + 1) % 3, l = (nn + 2) % 3;
+      for (int k = 0; k < 3; ++k)
+        for (int q = 0; q < n3; ++q) Vf[k * n3 + q] = xe[l * n3 + q] * dx[(m * 3 + k) * n3 + q];
+      for (int i = 0; i < 3; ++i) {
+        int a = (i + 1) % 3, b = (i + 2) % 3;
+        apply_dir(M.lgl.D, n, a, &Vf[b * n3], tmp.data());
+        apply_dir(M.lgl.D, n, b, &Vf[a * n3], tmp2.data());
+        for (int q = 0; q < n3; ++q) JaL[(i * 3 + nn) * n3 + q] = -(tmp[q] - tmp2[q]);
+      }
+    }
+    double* Jae = &M.Ja[(size_t)e * 9 * n3];
+    double* xse = &M.xs[(size_t)e * 3 * n3];
+    if (type == 1) {
+      std::copy(JaL.begin(), JaL.end(), Jae);
+      std::copy(xe, xe + 3 * n3, xse);
+    } else {
+      for (int c = 0; c < 9; ++c) {
+        apply_dir(V, n, 0, &JaL[c * n3], tmp.data());
+        apply_dir(V, n, 1, tmp.data(), tmp2.data());
+        apply_dir(V, n, 2, tmp2.data(), Jae + c * n3);
+      }
+      for (int d = 0; d < 3; ++d) {
+        apply_dir(V, n, 0, xe + d * n3, tmp.data());
+        apply_dir(V, n, 1, tmp.data(), tmp2.data());
+        apply_dir(V, n, 2, tmp2.data(), xse + d * n3);
+      }
+    }
+    // J = det(dx/dxi) at solution nodes from the solution-node D
+    std::vector<double> g(9 * n3);
+    for (int d = 0; d < 3; ++d)
+      for (int k = 0; k < 3; ++k) apply_dir(M.sol.D, n, k, xse + d * n3, &g[(d * 3 + k) * n3]);
+    for (int q = 0; q < n3; ++q) {
+      double a[9];
+      for (int c = 0; c < 9; ++c) a[c] = g[c * n3 + q];
+      double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                   a[2] * (a[3] * a[7] - a[4] * a[6]);
+      M.J[(size_t)e * n3 + q] = det;
+      if (!(det > 0)) ok = false;
+    }
+  }
+  if (!ok) return false;
+  // master (+xi side) normals: Ja^dn evaluated on the face
+  for (int e = 0; e < K; ++e)
+    for (int s = 1; s < 6; s += 2) {
+      int dn = s / 2;
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a)
+          for (int d = 0; d < 3; ++d) {
+            double v = 0;
+            for (int m = 0; m < n; ++m)
+              v += M.sol.lp[m] * M.Ja[((size_t)e * 9 + dn * 3 + d) * n3 + line_node(n, dn, a, b, m)];
+            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = v;
+          }
+    }
+  // slave (-xi side): negated normal of the neighbour's matching + side
+  for (int e = 0; e < K; ++e)
+    for (int s = 0; s < 6; s += 2) {
+      int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
+      for (int d = 0; d < 3; ++d)
+        for (int p = 0; p < n2; ++p)
+          M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + p] = -M.fn[(((size_t)nb * 6 + ns) * 3 + d) * n2 + p];
+    }
+  return true;
+}
+
+// ------------------------------------------------------------------------------ physics
+struct Scheme {
+  int eqn;      // 0 Euler, 1 Navier-Stokes
+  int form;     // 0 weak, 1 split, 2 strong
+  int vf;       // 0 KEP (Pirozzoli), 1 EC (Chandrashekar), 2 central
+  int rs;       // 0 LLF, 1 Roe, 2 volume two-point flux, 3 volume two-point flux + Roe dissipation
+  double gamma, R, mu, Pr;
+};
+
+template <class T> struct Prim { T rho, u[3], p; };
+
+template <class T> static Prim<T> prim(const T* U, double gamma) {
+  Prim<T> P;
+  P.rho = U[0];
+  for (int d = 0; d < 3; ++d) P.u[d] = U[1 + d] / P.rho;
+  P.p = T(gamma - 1.0) * (U[4] - T(0.5) * P.rho * (P.u[0] * P.u[0] + P.u[1] * P.u[1] + P.u[2] * P.u[2]));
+  return P;
+}
+
+// Euler flux contracted with a (non-unit) direction vector nv: sum_d F_d nv_d
+template <class T> static void euler_flux(const T* U, const Prim<T>& P, const double* nv, T* F) {
+  T un = P.u[0] * nv[0] + P.u[1] * nv[1] + P.u[2] * nv[2];
+  F[0] = U[0] * un;
+  for (int d = 0; d < 3; ++d) F[1 + d] = U[1 + d] * un + P.p * nv[d];
+  F[4] = (U[4] + P.p) * un;
+}
+
+// viscous flux contracted with nv; g[d*4+v] = d W_v / d x_d, W = (u,v,w,T)
+template <class T>
+static void viscous_flux(const Prim<T>& P, const T* g, const Scheme& S, const double* nv, T* F) {
+  const double mu = S.mu;
+  const double cp = S.gamma * S.R / (S.gamma - 1.0);
+  const double kappa = mu * cp / S.Pr;
+  T div = g[0 * 4 + 0] + g[1 * 4 + 1] + g[2 * 4 + 2];
+  T tau[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      // du_a/dx_b = g[b*4+a]
+      tau[a][b] = T(mu) * (g[b * 4 + a] + g[a * 4 + b]);
+      if (a == b) tau[a][b] = tau[a][b] - T(2.0 / 3.0 * mu) * div;
+    }
+  F[0] = T(0.0);
+  for (int a = 0; a < 3; ++a) {
+    T s = T(0.0);
+    for (int d = 0; d < 3; ++d) s = s + tau[a][d] * nv[d];
+    F[1 + a] = s;
+  }
+  T e = T(0.0);
+  for (int d = 0; d < 3; ++d) {
+    T work = tau[d][0] * P.u[0] + tau[d][1] * P.u[1] + tau[d][2] * P.u[2];
+    e = e + (work + T(kappa) * g[d * 4 + 3]) * nv[d];
+  }
+  F[4] = e;
+}
+
+template <class T> static T logmean(T a, T b) {
+  T s = a + b;
+  T f = (a - b) / s;
+  T u = f * f;
+  if (val(u) < 1e-4) return s / (T(2.0) + u * (T(2.0 / 3.0) + u * (T(2.0 / 5.0) + u * T(2.0 / 7.0))));
+  return (a - b) / (log(a) - log(b));
+}
+
+// two-point volume flux in direction nv (nv may be unnormalised)
+template <class T>
+static void twopoint(const T* Ua, const T* Ub, const double* nv, const Scheme& S, T* F) {
+  Prim<T> A = prim(Ua, S.gamma), B = prim(Ub, S.gamma);
+  if (S.vf == 2) {  // central: mean of the two Euler fluxes
+    T Fa[5], Fb[5];
+    euler_flux(Ua, A, nv, Fa); euler_flux(Ub, B, nv, Fb);
+    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (Fa[v] + Fb[v]);
+    return;
+  }
+  T um[3];
+  for (int d = 0; d < 3; ++d) um[d] = T(0.5) * (A.u[d] + B.u[d]);
+  T umn = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+  if (S.vf == 0) {  // kinetic-energy preserving, Pirozzoli
+    T rhom = T(0.5) * (A.rho + B.rho);
+    T pm = T(0.5) * (A.p + B.p);
+    T Ha = (Ua[4] + A.p) / A.rho, Hb = (Ub[4] + B.p) / B.rho;
+    T Hm = T(0.5) * (Ha + Hb);
+    F[0] = rhom * umn;
+    for (int d = 0; d < 3; ++d) F[1 + d] = F[0] * um[d] + pm * nv[d];
+    F[4] = F[0] * Hm;
+    return;
+  }
+  // entropy conserving, Chandrashekar: beta = rho/(2p)
+  T ba = A.rho / (T(2.0) * A.p), bb = B.rho / (T(2.0) * B.p);
+  T rholn = logmean(A.rho, B.rho);
+  T betaln = logmean(ba, bb);
+  T rhom = T(0.5) * (A.rho + B.rho);
+  T betam = T(0.5) * (ba + bb);
+  T phat = rhom / (T(2.0) * betam);
+  T q2m = T(0.5) * ((A.u[0] * A.u[0] + A.u[1] * A.u[1] + A.u[2] * A.u[2]) +
+                    (B.u[0] * B.u[0] + B.u[1] * B.u[1] + B.u[2] * B.u[2]));
+  F[0] = rholn * umn;
+  for (int d = 0; d < 3; ++d) F[1 + d] = F[0] * um[d] + phat * nv[d];
+  F[4] = F[0] * (T(1.0) / (T(2.0 * (S.gamma - 1.0)) * betaln) - T(0.5) * q2m) +
+         um[0] * F[1] + um[1] * F[2] + um[2] * F[3];
+}
+
+// Roe dissipation sum_k |lambda_k| alpha_k r_k (signed=false) or sum_k lambda_k alpha_k r_k
+// (signed=true) in a frame rotated to (n, t1, t2); nh is a unit normal.
+template <class T>
+static void roe_waves(const T* UL, const T* UR, const double* nh, const Scheme& S, bool signed_, T* Dout) {
+  const double g = S.gamma;
+  // orthonormal completion of nh
+  double t1[3], t2[3];
+  {
+    int ax = 0;
+    double am = std::fabs(nh[0]);
+    for (int d = 1; d < 3; ++d)
+      if (std::fabs(nh[d]) < am) { am = std::fabs(nh[d]); ax = d; }
+    double e[3] = {0, 0, 0}; e[ax] = 1.0;
+    t1[0] = nh[1] * e[2] - nh[2] * e[1];
+    t1[1] = nh[2] * e[0] - nh[0] * e[2];
+    t1[2] = nh[0] * e[1] - nh[1] * e[0];
+    double nt = std::sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    for (int d = 0; d < 3; ++d) t1[d] /= nt;
+    t2[0] = nh[1] * t1[2] - nh[2] * t1[1];
+    t2[1] = nh[2] * t1[0] - nh[0] * t1[2];
+    t2[2] = nh[0] * t1[1] - nh[1] * t1[0];
+  }
+  Prim<T> L = prim(UL, g), R = prim(UR, g);
+  auto rot = [&](const Prim<T>& P, T* q) {
+    q[0] = P.u[0] * nh[0] + P.u[1] * nh[1] + P.u[2] * nh[2];
+    q[1] = P.u[0] * t1[0] + P.u[1] * t1[1] + P.u[2] * t1[2];
+    q[2] = P.u[0] * t2[0] + P.u[1] * t2[1] + P.u[2] * t2[2];
+  };
+  T qL[3], qR[3];
+  rot(L, qL); rot(R, qR);
+  T HL = (UL[4] + L.p) / L.rho, HR = (UR[4] + R.p) / R.rho;
+  T sL = sqrt(L.rho), sR = sqrt(R.rho);
+  T isum = T(1.0) / (sL + sR);
+  T q[3];
+  for (int d = 0; d < 3; ++d) q[d] = (sL * qL[d] + sR * qR[d]) * isum;
+  T H = (sL * HL + sR * HR) * isum;
+  T q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  T c2 = T(g - 1.0) * (H - T(0.5) * q2);
+  T c = sqrt(c2);
+  T rt = sL * sR;
+  T drho = R.rho - L.rho, dp = R.p - L.p;
+  T dq[3];
+  for (int d = 0; d < 3; ++d) dq[d] = qR[d] - qL[d];
+  T a1 = (dp - rt * c * dq[0]) / (T(2.0) * c2);
+  T a2 = drho - dp / c2;
+  T a3 = rt * dq[1];
+  T a4 = rt * dq[2];
+  T a5 = (dp + rt * c * dq[0]) / (T(2.0) * c2);
+  T l1 = q[0] - c, l2 = q[0], l5 = q[0] + c;
+  if (!signed_) {
+    double cs = val(c);
+    l1 = kabs(l1, cs); l2 = kabs(l2, cs); l5 = kabs(l5, cs);
+  }
+  // rotated-frame dissipation in (rho, m_n, m_t1, m_t2, E)
+  T Dr[5];
+  Dr[0] = l1 * a1 + l2 * a2 + l5 * a5;
+  Dr[1] = l1 * a1 * (q[0] - c) + l2 * a2 * q[0] + l5 * a5 * (q[0] + c);
+  Dr[2] = l1 * a1 * q[1] + l2 * a2 * q[1] + l2 * a3 + l5 * a5 * q[1];
+  Dr[3] = l1 * a1 * q[2] + l2 * a2 * q[2] + l2 * a4 + l5 * a5 * q[2];
+  Dr[4] = l1 * a1 * (H - q[0] * c) + l2 * a2 * T(0.5) * q2 + l2 * (a3 * q[1] + a4 * q[2]) +
+          l5 * a5 * (H + q[0] * c);
+  Dout[0] = Dr[0];
+  for (int d = 0; d < 3; ++d) Dout[1 + d] = Dr[1] * nh[d] + Dr[2] * t1[d] + Dr[3] * t2[d];
+  Dout[4] = Dr[4];
+}
+
+// convective numerical flux f*(UL, UR, nh) (unit normal nh)
+template <class T>
+static void riemann(const T* UL, const T* UR, const double* nh, const Scheme& S, T* F) {
+  Prim<T> L = prim(UL, S.gamma), R = prim(UR, S.gamma);
+  if (S.rs == 2 || S.rs == 3) {
+    twopoint(UL, UR, nh, S, F);
+    if (S.rs == 3) {
+      T Dd[5];
+      roe_waves(UL, UR, nh, S, false, Dd);
+      for (int v = 0; v < 5; ++v) F[v] = F[v] - T(0.5) * Dd[v];
+    }
+    return;
+  }
+  T FL[5], FR[5];
+  euler_flux(UL, L, nh, FL); euler_flux(UR, R, nh, FR);
+  if (S.rs == 0) {
+    T cL = sqrt(T(S.gamma) * L.p / L.rho), cR = sqrt(T(S.gamma) * R.p / R.rho);
+    T unL = L.u[0] * nh[0] + L.u[1] * nh[1] + L.u[2] * nh[2];
+    T unR = R.u[0] * nh[0] + R.u[1] * nh[1] + R.u[2] * nh[2];
+    T lam = tmax(kabs(unL, val(cL)) + cL, kabs(unR, val(cR)) + cR);
+    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * lam * (UR[v] - UL[v]);
+    return;
+  }
+  T Dd[5];
+  roe_waves(UL, UR, nh, S, false, Dd);
+  for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * Dd[v];
+}
+
+// ------------------------------------------------------------------------------ operator
+template <class T> struct Work {
+  std::vector<T> W;  // [e][4][node] lifted variables (u,v,w,T)
+  std::vector<T> G;  // [e][12][node] gradients g[d*4+v]
+};
+
+// value of field X (nv components, [e][v][node]) on face point (a,b) of side s of element e
+template <class T>
+static void trace(const Mesh& M, const T* X, int nv, int e, int s, int a, int b, T* out) {
+  const int n = M.n, n3 = M.n3, dn = s / 2;
+  const bool plus = (s % 2) == 1;
+  for (int v = 0; v < nv; ++v) {
+    const T* f = X + ((size_t)e * nv + v) * n3;
+    if (M.type == 1) {
+      out[v] = f[line_node(n, dn, a, b, plus ? M.N : 0)];
+    } else {
+      T acc = T(0.0);
+      const std::vector<double>& l = plus ? M.sol.lp : M.sol.lm;
+      for (int m = 0; m < n; ++m) acc = acc + T(l[m]) * f[line_node(n, dn, a, b, m)];
+      out[v] = acc;
+    }
+  }
+}
+
+// BR1 lifting of W = (u,v,w,T) for the elements with need[e] != 0
+template <class T>
+static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vector<char>& need, Work<T>& wk) {
+  const int K = M.K, n = M.n, n2 = M.n2, n3 = M.n3;
+  wk.W.assign((size_t)K * 4 * n3, T(0.0));
+  wk.G.assign((size_t)K * 12 * n3, T(0.0));
+  // W on every element that a lifted element or its neighbours touch
+  std::vector<char> needW(K, 0);
+  for (int e = 0; e < K; ++e)
+    if (need[e]) {
+      needW[e] = 1;
+      for (int s = 0; s < 6; ++s) needW[M.nbr[e * 6 + s]] = 1;
+    }
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < K; ++e) {
+    if (!needW[e]) continue;
+    for (int q = 0; q < n3; ++q) {
+      T Uq[5];
+      for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + q];
+      Prim<T> P = prim(Uq, S.gamma);
+      for (int d = 0; d < 3; ++d) wk.W[((size_t)e * 4 + d) * n3 + q] = P.u[d];
+      wk.W[((size_t)e * 4 + 3) * n3 + q] = P.p / (P.rho * T(S.R));
+    }
+  }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int e = 0; e < K; ++e) {
+    if (!need[e]) continue;
+    const double* Ja = &M.Ja[(size_t)e * 9 * n3];
+    std::vector<T> acc(12 * n3, T(0.0));
+    // volume: sum_alpha Dhat_{i alpha} Ja^1_d(alpha jk) W(alpha jk) + two more directions
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int id[3] = {i, j, k};
+          int q = nid(n, i, j, k);
+          for (int dir = 0; dir < 3; ++dir)
+            for (int m = 0; m < n; ++m) {
+              int jd[3] = {i, j, k};
+              jd[dir] = m;
+              int qm = nid(n, jd[0], jd[1], jd[2]);
+              double Dh = M.sol.Dhat[id[dir] * n + m];
+              for (int d = 0; d < 3; ++d)
+                for (int v = 0; v < 4; ++v)
+                  acc[(d * 4 + v) * n3 + q] =
+                      acc[(d * 4 + v) * n3 + q] + T(Dh * Ja[(dir * 3 + d) * n3 + qm]) * wk.W[((size_t)e * 4 + v) * n3 + qm];
+            }
+        }
+    // surface: [W* nt_d]^{face} lhat(+-1), W* = (W_L + W_R)/2, nt = outward scaled normal
+    for (int s = 0; s < 6; ++s) {
+      int dn = s / 2;
+      bool plus = (s % 2) == 1;
+      int nb = M.nbr[e * 6 + s];
+      const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          T WL[4], WR[4];
+          trace(M, wk.W.data(), 4, e, s, a, b, WL);
+          trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a, b, WR);
+          const double* nt = &M.fn[((size_t)e * 6 + s) * 3 * n2];
+          for (int m = 0; m < n; ++m) {
+            if (lh[m] == 0.0) continue;
+            int q = line_node(n, dn, a, b, m);
+            for (int d = 0; d < 3; ++d)
+              for (int v = 0; v < 4; ++v)
+                acc[(d * 4 + v) * n3 + q] =
+                    acc[(d * 4 + v) * n3 + q] + T(lh[m] * nt[d * n2 + a + n * b]) * (T(0.5) * (WL[v] + WR[v]));
+          }
+        }
+    }
+    for (int c = 0; c < 12; ++c)
+      for (int q = 0; q < n3; ++q) wk.G[((size_t)e * 12 + c) * n3 + q] = acc[c * n3 + q] / T(M.J[(size_t)e * n3 + q]);
+  }
+}
+
+// full operator U_t = L(U) for the elements with out_mask[e] != 0
+template <class T>
+static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::vector<char>& out_mask) {
+  const int K = M.K, n = M.n, n2 = M.n2, n3 = M.n3;
+  const bool ns = (S.eqn == 1);
+  Work<T> wk;
+  if (ns) {
+    std::vector<char> need(K, 0);
+    for (int e = 0; e < K; ++e)
+      if (out_mask[e]) {
+        need[e] = 1;
+        for (int s = 0; s < 6; ++s) need[M.nbr[e * 6 + s]] = 1;
+      }
+    lifting(M, S, U, need, wk);
+  }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int e = 0; e < K; ++e) {
+    if (!out_mask[e]) continue;
+    const double* Ja = &M.Ja[(size_t)e * 9 * n3];
+    std::vector<T> acc(5 * n3, T(0.0));
+    // node-wise contravariant fluxes: Fc[i][v][q] = sum_d Ja^i_d F^c_d, Fv likewise
+    std::vector<T> Fc(15 * n3), Fv(15 * n3, T(0.0));
+    for (int q = 0; q < n3; ++q) {
+      T Uq[5];
+      for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + q];
+      Prim<T> P = prim(Uq, S.gamma);
+      T g[12];
+      if (ns)
+        for (int c = 0; c < 12; ++c) g[c] = wk.G[((size_t)e * 12 + c) * n3 + q];
+      for (int i = 0; i < 3; ++i) {
+        double nv[3] = {Ja[(i * 3 + 0) * n3 + q], Ja[(i * 3 + 1) * n3 + q], Ja[(i * 3 + 2) * n3 + q]};
+        T F[5];
+        euler_flux(Uq, P, nv, F);
+        for (int v = 0; v < 5; ++v) Fc[(i * 5 + v) * n3 + q] = F[v];
+        if (ns) {
+          viscous_flux(P, g, S, nv, F);
+          for (int v = 0; v < 5; ++v) Fv[(i * 5 + v) * n3 + q] = F[v];
+        }
+      }
+    }
+    // volume integral
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int id[3] = {i, j, k};
+          int q = nid(n, i, j, k);
+          for (int dir = 0; dir < 3; ++dir)
+            for (int m = 0; m < n; ++m) {
+              int jd[3] = {i, j, k};
+              jd[dir] = m;
+              int qm = nid(n, jd[0], jd[1], jd[2]);
+              if (S.form == 0) {  // weak: sum Dhat (Fc - Fv)
+                double Dh = M.sol.Dhat[id[dir] * n + m];
+                for (int v = 0; v < 5; ++v)
+                  acc[v * n3 + q] = acc[v * n3 + q] + T(Dh) * (Fc[(dir * 5 + v) * n3 + qm] - Fv[(dir * 5 + v) * n3 + qm]);
+              } else if (S.form == 2) {  // strong: sum D (Fc - Fv)
+                double Dd = M.sol.D[id[dir] * n + m];
+                for (int v = 0; v < 5; ++v)
+                  acc[v * n3 + q] = acc[v * n3 + q] + T(Dd) * (Fc[(dir * 5 + v) * n3 + qm] - Fv[(dir * 5 + v) * n3 + qm]);
+              } else {  // split: 2 sum D F#(U_q, U_qm; {Ja^dir}) - sum D Fv
+                double Dd = M.sol.D[id[dir] * n + m];
+                double nv[3];
+                for (int d = 0; d < 3; ++d) nv[d] = 0.5 * (Ja[(dir * 3 + d) * n3 + q] + Ja[(dir * 3 + d) * n3 + qm]);
+                T Ua[5], Ub[5], F[5];
+                for (int v = 0; v < 5; ++v) {
+                  Ua[v] = U[((size_t)e * 5 + v) * n3 + q];
+                  Ub[v] = U[((size_t)e * 5 + v) * n3 + qm];
+                }
+                twopoint(Ua, Ub, nv, S, F);
+                for (int v = 0; v < 5; ++v)
+                  acc[v * n3 + q] = acc[v * n3 + q] + T(2.0 * Dd) * F[v] - T(Dd) * Fv[(dir * 5 + v) * n3 + qm];
+              }
+            }
+        }
+    // surface integral
+    for (int s = 0; s < 6; ++s) {
+      int dn = s / 2;
+      bool plus = (s % 2) == 1;
+      int nb = M.nbr[e * 6 + s], ns_ = M.nside[e * 6 + s];
+      const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          // master = element owning the face as its + side; the slave takes the negated master flux
+          int em = plus ? e : nb, sm = plus ? s : ns_;
+          int es = plus ? nb : e, ss = plus ? ns_ : s;
+          T UM[5], US[5];
+          trace(M, U, 5, em, sm, a, b, UM);
+          trace(M, U, 5, es, ss, a, b, US);
+          const double* ntm = &M.fn[((size_t)em * 6 + sm) * 3 * n2];
+          double nt[3] = {ntm[0 * n2 + a + n * b], ntm[1 * n2 + a + n * b], ntm[2 * n2 + a + n * b]};
+          double sh = std::sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+          double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
+          T F[5];
+          riemann(UM, US, nh, S, F);
+          for (int v = 0; v < 5; ++v) F[v] = F[v] * T(sh);
+          if (ns) {  // BR1: mean of both viscous fluxes
+            T gM[12], gS[12], FvM[5], FvS[5];
+            trace(M, wk.G.data(), 12, em, sm, a, b, gM);
+            trace(M, wk.G.data(), 12, es, ss, a, b, gS);
+            Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);
+            viscous_flux(PM, gM, S, nt, FvM);
+            viscous_flux(PS, gS, S, nt, FvS);
+            for (int v = 0; v < 5; ++v) F[v] = F[v] - T(0.5) * (FvM[v] + FvS[v]);
+          }
+          double sgn = plus ? 1.0 : -1.0;  // outward flux of this element
+          for (int m = 0; m < n; ++m) {
+            if (lh[m] == 0.0) continue;
+            int q = line_node(n, dn, a, b, m);
+            for (int v = 0; v < 5; ++v) {
+              T pen = T(sgn) * F[v];
+              if (S.form != 0) {
+                // strong / split: minus the interior contravariant flux in the outward direction
+                pen = pen - T(sgn) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
+              }
+              acc[v * n3 + q] = acc[v * n3 + q] + T(lh[m]) * pen;
+            }
+          }
+        }
+    }
+    for (int v = 0; v < 5; ++v)
+      for (int q = 0; q < n3; ++q) Ut[((size_t)e * 5 + v) * n3 + q] = -acc[v * n3 + q] / T(M.J[(size_t)e * n3 + q]);
+  }
+}
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients
+static const double RK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double RK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+static const double RK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                               2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+template <class T> static void rk_steps(const Mesh& M, const Scheme& S, T* U, int nsteps, double dt) {
+  const size_t N = (size_t)M.K * 5 * M.n3;
+  std::vector<T> R(N, T(0.0)), Ut(N);
+  std::vector<char> all(M.K, 1);
+  for (int st = 0; st < nsteps; ++st)
+    for (int s = 0; s < 5; ++s) {
+      rhs(M, S, U, Ut.data(), all);
+      for (size_t q = 0; q < N; ++q) {
+        R[q] = T(RK_A[s]) * R[q] + T(dt) * Ut[q];
+        U[q] = U[q] + T(RK_B[s]) * R[q];
+      }
+    }
+}
+
+}  // namespace orc
+
+// ================================================================================ C interface
+using namespace orc;
+
+struct orc_handle {
+  Mesh M;
+};
+
+extern "C" {
+
+int orc_basis(int N, int type, double* x, double* w, double* D, double* Dhat, double* lm, double* lp) {
+  if (N < 1 || N > 16) return -1;
+  Basis b = make_basis(N, type);
+  int n = N + 1;
+  for (int i = 0; i < n; ++i) { x[i] = b.x[i]; w[i] = b.w[i]; lm[i] = b.lm[i]; lp[i] = b.lp[i]; }
+  for (int i = 0; i < n * n; ++i) { D[i] = b.D[i]; Dhat[i] = b.Dhat[i]; }
+  return 0;
+}
+
+orc_handle* orc_create(int K, int N, int type, const double* xgeo, const int32_t* nbr, const int8_t* nside) {
+  orc_handle* h = new orc_handle;
+  if (!build_mesh(h->M, K, N, type, xgeo, nbr, nside)) { delete h; return nullptr; }
+  return h;
+}
+
+void orc_destroy(orc_handle* h) { delete h; }
+
+// copies of the derived geometry: Ja [K][9][n3], J [K][n3], x [K][3][n3], face normals [K][6][3][n2]
+void orc_geometry(const orc_handle* h, double* Ja, double* J, double* xs, double* fn) {
+  const Mesh& M = h->M;
+  if (Ja) std::copy(M.Ja.begin(), M.Ja.end(), Ja);
+  if (J) std::copy(M.J.begin(), M.J.end(), J);
+  if (xs) std::copy(M.xs.begin(), M.xs.end(), xs);
+  if (fn) std::copy(M.fn.begin(), M.fn.end(), fn);
+}
+
+static Scheme mk(int eqn, int form, int vf, int rs, double gamma, double R, double mu, double Pr) {
+  Scheme S; S.eqn = eqn; S.form = form; S.vf = vf; S.rs = rs; S.gamma = gamma; S.R = R; S.mu = mu; S.Pr = Pr;
+  return S;
+}
+
+void orc_rhs(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu, double Pr,
+             const double* U, double* Ut) {
+  std::vector<char> all(h->M.K, 1);
+  rhs(h->M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), U, Ut, all);
+}
+
+// U_t on a subset of elements only (their neighbours' lifting is recomputed as needed);
+// Ut_sel is [nsel][5][n3] in the order of sel[]
+void orc_rhs_select(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu,
+                    double Pr, const double* U, const int32_t* sel, int nsel, double* Ut_sel) {
+  const Mesh& M = h->M;
+  std::vector<char> mask(M.K, 0);
+  for (int i = 0; i < nsel; ++i) mask[sel[i]] = 1;
+  std::vector<double> Ut((size_t)M.K * 5 * M.n3, 0.0);
+  rhs(M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), U, Ut.data(), mask);
+  for (int i = 0; i < nsel; ++i)
+    std::copy(Ut.begin() + (size_t)sel[i] * 5 * M.n3, Ut.begin() + (size_t)(sel[i] + 1) * 5 * M.n3,
+              Ut_sel + (size_t)i * 5 * M.n3);
+}
+
+// lifted gradients g[e][d*4+v][node] of W = (u,v,w,T)
+void orc_lift(const orc_handle* h, double gamma, double R, const double* U, double* G) {
+  const Mesh& M = h->M;
+  std::vector<char> all(M.K, 1);
+  Work<double> wk;
+  Scheme S = mk(1, 0, 0, 0, gamma, R, 0.0, 1.0);
+  lifting(M, S, U, all, wk);
+  std::copy(wk.G.begin(), wk.G.end(), G);
+}
+
+// tangent-linear operator: dUt = L'(U) dU (dual numbers), Ut = L(U)
+void orc_rhs_jvp(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu,
+                 double Pr, const double* U, const double* dU, double* Ut, double* dUt) {
+  const Mesh& M = h->M;
+  const size_t N = (size_t)M.K * 5 * M.n3;
+  std::vector<dual> Ud(N), Utd(N);
+  for (size_t q = 0; q < N; ++q) Ud[q] = dual(U[q], dU[q]);
+  std::vector<char> all(M.K, 1);
+  rhs(M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), Ud.data(), Utd.data(), all);
+  for (size_t q = 0; q < N; ++q) { Ut[q] = Utd[q].v; dUt[q] = Utd[q].d; }
+}
+
+// nsteps full RK steps in place on U
+void orc_rk(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu, double Pr,
+            double* U, int nsteps, double dt) {
+  rk_steps(h->M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), U, nsteps, dt);
+}
+
+// one RK stage: R = a R + dt L(U_in); U_out = U_in + b R
+void orc_rk_stage(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double Rg, double mu,
+                  double Pr, const double* Uin, double* Uout, double* R, double a, double b, double dt) {
+  const Mesh& M = h->M;
+  const size_t N = (size_t)M.K * 5 * M.n3;
+  std::vector<double> Ut(N);
+  std::vector<char> all(M.K, 1);
+  rhs(M, mk(eqn, form, vf, rs, gamma, Rg, mu, Pr), Uin, Ut.data(), all);
+  for (size_t q = 0; q < N; ++q) {
+    R[q] = a * R[q] + dt * Ut[q];
+    Uout[q] = Uin[q] + b * R[q];
+  }
+}
+
+// rollout tangent: U <- U(T), dU <- dU(T) after nsteps
+void orc_rk_jvp(const orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu, double Pr,
+                double* U, double* dU, int nsteps, double dt) {
+  const Mesh& M = h->M;
+  const size_t N = (size_t)M.K * 5 * M.n3;
+  std::vector<dual> Ud(N);
+  for (size_t q = 0; q < N; ++q) Ud[q] = dual(U[q], dU[q]);
+  rk_steps(M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), Ud.data(), nsteps, dt);
+  for (size_t q = 0; q < N; ++q) { U[q] = Ud[q].v; dU[q] = Ud[q].d; }
+}
+
+void orc_rk_coefficients(double* a, double* b, double* c) {
+  for (int s = 0; s < 5; ++s) { a[s] = RK_A[s]; b[s] = RK_B[s]; c[s] = RK_C[s]; }
+}
+
+// pointwise pieces, exposed for the algebraic pins
+void orc_twopoint(int vf, double gamma, const double* Ua, const double* Ub, const double* nv, double* F) {
+  Scheme S = mk(0, 1, vf, 0, gamma, 1.0, 0.0, 1.0);
+  twopoint(Ua, Ub, nv, S, F);
+}
+void orc_riemann(int rs, int vf, double gamma, const double* UL, const double* UR, const double* nh, double* F) {
+  Scheme S = mk(0, 1, vf, rs, gamma, 1.0, 0.0, 1.0);
+  riemann(UL, UR, nh, S, F);
+}
+void orc_roe_waves(double gamma, const double* UL, const double* UR, const double* nh, int signed_, double* Dd) {
+  Scheme S = mk(0, 1, 0, 1, gamma, 1.0, 0.0, 1.0);
+  roe_waves(UL, UR, nh, S, signed_ != 0, Dd);
+}
+void orc_euler_flux(double gamma, const double* U, const double* nv, double* F) {
+  Prim<double> P = prim(U, gamma);
+  euler_flux(U, P, nv, F);
+}
+void orc_viscous_flux(double gamma, double R, double mu, double Pr, const double* U, const double* g,
+                      const double* nv, double* F) {
+  Scheme S = mk(1, 0, 0, 0, gamma, R, mu, Pr);
+  Prim<double> P = prim(U, gamma);
+  viscous_flux(P, g, S, nv, F);
+}
+
+// volume integrals sum_e sum_q J w w w X: [rho, m1, m2, m3, E, KE, entropy S = -rho s/(gamma-1)]
+void orc_integrals(const orc_handle* h, double gamma, const double* U, double* out) {
+  const Mesh& M = h->M;
+  const int n = M.n, n3 = M.n3;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int e = 0; e < M.K; ++e)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int q = nid(n, i, j, k);
+          double wq = M.sol.w[i] * M.sol.w[j] * M.sol.w[k] * M.J[(size_t)e * n3 + q];
+          double Uq[5];
+          for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + q];
+          Prim<double> P = prim(Uq, gamma);
+          for (int v = 0; v < 5; ++v) acc[v] += wq * Uq[v];
+          acc[5] += wq * 0.5 * (Uq[1] * Uq[1] + Uq[2] * Uq[2] + Uq[3] * Uq[3]) / Uq[0];
+          double s = std::log(P.p) - gamma * std::log(P.rho);
+          acc[6] += wq * (-P.rho * s / (gamma - 1.0));
+        }
+  for (int v = 0; v < 7; ++v) out[v] = acc[v];
+}
+
+// entropy production sum J w w w (w(U) . U_t) with entropy variables of S = -rho s/(gamma-1)
+double orc_entropy_production(const orc_handle* h, double gamma, const double* U, const double* Ut) {
+  const Mesh& M = h->M;
+  const int n = M.n, n3 = M.n3;
+  double acc = 0;
+  for (int e = 0; e < M.K; ++e)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int q = nid(n, i, j, k);
+          double wq = M.sol.w[i] * M.sol.w[j] * M.sol.w[k] * M.J[(size_t)e * n3 + q];
+          double Uq[5];
+          for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + q];
+          Prim<double> P = prim(Uq, gamma);
+          double s = std::log(P.p) - gamma * std::log(P.rho);
+          double q2 = P.u[0] * P.u[0] + P.u[1] * P.u[1] + P.u[2] * P.u[2];
+          double wv[5] = {(gamma - s) / (gamma - 1.0) - 0.5 * P.rho * q2 / P.p, P.rho * P.u[0] / P.p,
+                          P.rho * P.u[1] / P.p, P.rho * P.u[2] / P.p, -P.rho / P.p};
+          for (int v = 0; v < 5; ++v) acc += wq * wv[v] * Ut[((size_t)e * 5 + v) * n3 + q];
+        }
+  return acc;
+}
+
+// time step: min of convective and viscous limits (gamma_RK = 1)
+double orc_timestep(const orc_handle* h, double gamma, double mu, double Pr, const double* U, double cfl,
+                    double dfl) {
+  const Mesh& M = h->M;
+  const int n3 = M.n3;
+  double lc = 0, lv = 0;
+  for (int e = 0; e < M.K; ++e)
+    for (int q = 0; q < n3; ++q) {
+      double Uq[5];
+      for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + q];
+      Prim<double> P = prim(Uq, gamma);
+      double c = std::sqrt(gamma * P.p / P.rho);
+      double J = M.J[(size_t)e * n3 + q];
+      double sc = 0, sv = 0;
+      for (int i = 0; i < 3; ++i) {
+        const double* Ja = &M.Ja[(size_t)e * 9 * n3];
+        double a0 = Ja[(i * 3 + 0) * n3 + q], a1 = Ja[(i * 3 + 1) * n3 + q], a2 = Ja[(i * 3 + 2) * n3 + q];
+        double nrm2 = a0 * a0 + a1 * a1 + a2 * a2;
+        sc += (std::fabs(P.u[0] * a0 + P.u[1] * a1 + P.u[2] * a2) + c * std::sqrt(nrm2)) / J;
+        sv += std::max(4.0 / 3.0, gamma / Pr) * (mu / P.rho) * nrm2 / (J * J);
+      }
+      lc = std::max(lc, sc); lv = std::max(lv, sv);
+    }
+  const int N = M.N;
+  double dt = cfl * 2.0 / ((2.0 * N + 1.0) * lc);
+  if (mu > 0 && lv > 0) dt = std::min(dt, dfl * 4.0 / ((2.0 * N + 1.0) * lv));
+  return dt;
+}
+
+}  // extern "C"
+
+extern "C" void orc_riemann_jvp(int rs, int vf, double gamma, const double* UL, const double* UR, const double* dUL,
+                                const double* dUR, const double* nh, double* F, double* dF) {
+  Scheme S = mk(0, 1, vf, rs, gamma, 1.0, 0.0, 1.0);
+  dual a[5], b[5], Fd[5];
+  for (int v = 0; v < 5; ++v) { a[v] = dual(UL[v], dUL[v]); b[v] = dual(UR[v], dUR[v]); }
+  riemann(a, b, nh, S, Fd);
+  for (int v = 0; v < 5; ++v) { F[v] = Fd[v].v; dF[v] = Fd[v].d; }
+}

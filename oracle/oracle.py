@@ -1,0 +1,251 @@
+"""ctypes wrapper of the FP64 CPU oracle (``dg_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dg_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle_dg.so")
+
+EQN = {"euler": 0, "ns": 1}
+FORM = {"weak": 0, "split": 1, "strong": 2}
+VF = {"kep": 0, "ec": 1, "central": 2}
+RS = {"llf": 0, "roe": 1, "volflux": 2, "volflux_roe": 3}
+NODES = {"lg": 0, "lgl": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain -O2, OpenMP over elements)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.run(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", SRC, "-o", tmp], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I8 = ctypes.POINTER(ctypes.c_int8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = ctypes.CDLL(LIB)
+        L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int] + [_D] * 6
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
+        sch = [ctypes.c_int] * 4 + [ctypes.c_double] * 4
+        L.orc_rhs.argtypes = [ctypes.c_void_p] + sch + [_D, _D]
+        L.orc_rhs_select.argtypes = [ctypes.c_void_p] + sch + [_D, _I32, ctypes.c_int, _D]
+        L.orc_lift.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.orc_rhs_jvp.argtypes = [ctypes.c_void_p] + sch + [_D, _D, _D, _D]
+        L.orc_rk.argtypes = [ctypes.c_void_p] + sch + [_D, ctypes.c_int, ctypes.c_double]
+        L.orc_rk_stage.argtypes = [ctypes.c_void_p] + sch + [_D, _D, _D] + [ctypes.c_double] * 3
+        L.orc_rk_jvp.argtypes = [ctypes.c_void_p] + sch + [_D, _D, ctypes.c_int, ctypes.c_double]
+        L.orc_rk_coefficients.argtypes = [_D, _D, _D]
+        L.orc_twopoint.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D, _D]
+        L.orc_riemann.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D, _D, _D]
+        L.orc_riemann_jvp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double] + [_D] * 7
+        L.orc_roe_waves.argtypes = [ctypes.c_double, _D, _D, _D, ctypes.c_int, _D]
+        L.orc_euler_flux.argtypes = [ctypes.c_double, _D, _D, _D]
+        L.orc_viscous_flux.argtypes = [ctypes.c_double] * 4 + [_D, _D, _D, _D]
+        L.orc_integrals.argtypes = [ctypes.c_void_p, ctypes.c_double, _D, _D]
+        L.orc_entropy_production.restype = ctypes.c_double
+        L.orc_entropy_production.argtypes = [ctypes.c_void_p, ctypes.c_double, _D, _D]
+        L.orc_timestep.restype = ctypes.c_double
+        L.orc_timestep.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 3 + [_D, ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def basis(N: int, nodes: str):
+    n = N + 1
+    x, w, lm, lp = (np.zeros(n) for _ in range(4))
+    D, Dh = np.zeros((n, n)), np.zeros((n, n))
+    rc = lib().orc_basis(N, NODES[nodes], _p(x), _p(w), _p(D), _p(Dh), _p(lm), _p(lp))
+    if rc:
+        raise ValueError("unsupported N")
+    return dict(x=x, w=w, D=D, Dhat=Dh, lm=lm, lp=lp)
+
+
+def rk_coefficients():
+    a, b, c = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().orc_rk_coefficients(_p(a), _p(b), _p(c))
+    return a, b, c
+
+
+class Scheme:
+    def __init__(self, eqn="euler", form="weak", volflux="central", riemann="llf", gamma=1.4, R=1.0, mu=0.0,
+                 Pr=0.72):
+        self.eqn, self.form, self.volflux, self.riemann = eqn, form, volflux, riemann
+        self.gamma, self.R, self.mu, self.Pr = gamma, R, mu, Pr
+
+    def args(self):
+        return (EQN[self.eqn], FORM[self.form], VF[self.volflux], RS[self.riemann], self.gamma, self.R, self.mu,
+                self.Pr)
+
+    @classmethod
+    def of(cls, wl):
+        return cls(wl.eqn, wl.form, wl.volflux, wl.riemann, wl.gamma, wl.R, wl.mu, wl.Pr)
+
+
+class OracleMesh:
+    """Geometry and connectivity of one mesh, built by the oracle from the sampled map."""
+
+    def __init__(self, xgeo, nbr, nside, N: int, nodes: str):
+        xgeo = _c(xgeo)
+        self.K = xgeo.shape[0]
+        self.N, self.n = N, N + 1
+        self.n3 = self.n ** 3
+        self.nodes = nodes
+        nbr = _c(nbr, np.int32)
+        nside = _c(nside, np.int8)
+        h = lib().orc_create(self.K, N, NODES[nodes], _p(xgeo), nbr.ctypes.data_as(_I32), nside.ctypes.data_as(_I8))
+        if not h:
+            raise ValueError("oracle: invalid mesh (J <= 0)")
+        self.h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.orc_destroy(self.h)
+            self.h = None
+
+    def geometry(self):
+        K, n3, n2 = self.K, self.n3, self.n ** 2
+        Ja = np.zeros((K, 9, n3)); J = np.zeros((K, n3)); xs = np.zeros((K, 3, n3)); fn = np.zeros((K, 6, 3, n2))
+        lib().orc_geometry(self.h, _p(Ja), _p(J), _p(xs), _p(fn))
+        return dict(Ja=Ja, J=J, x=xs, fn=fn)
+
+    def points(self):
+        return self.geometry()["x"]
+
+    def rhs(self, sc: Scheme, U):
+        U = _c(U)
+        Ut = np.zeros_like(U)
+        lib().orc_rhs(self.h, *sc.args(), _p(U), _p(Ut))
+        return Ut
+
+    def rhs_select(self, sc: Scheme, U, elems):
+        U = _c(U)
+        sel = _c(elems, np.int32)
+        out = np.zeros((sel.size, 5, self.n3))
+        lib().orc_rhs_select(self.h, *sc.args(), _p(U), sel.ctypes.data_as(_I32), int(sel.size), _p(out))
+        return out
+
+    def lift(self, U, gamma=1.4, R=1.0):
+        U = _c(U)
+        G = np.zeros((self.K, 12, self.n3))
+        lib().orc_lift(self.h, gamma, R, _p(U), _p(G))
+        return G
+
+    def rhs_jvp(self, sc: Scheme, U, dU):
+        U, dU = _c(U), _c(dU)
+        Ut, dUt = np.zeros_like(U), np.zeros_like(U)
+        lib().orc_rhs_jvp(self.h, *sc.args(), _p(U), _p(dU), _p(Ut), _p(dUt))
+        return Ut, dUt
+
+    def rk(self, sc: Scheme, U, nsteps: int, dt: float):
+        U = _c(U).copy()
+        lib().orc_rk(self.h, *sc.args(), _p(U), int(nsteps), float(dt))
+        return U
+
+    def rk_stage(self, sc: Scheme, U, R, a, b, dt):
+        U = _c(U)
+        R = _c(R).copy()
+        Uo = np.zeros_like(U)
+        lib().orc_rk_stage(self.h, *sc.args(), _p(U), _p(Uo), _p(R), float(a), float(b), float(dt))
+        return Uo, R
+
+    def rk_jvp(self, sc: Scheme, U, dU, nsteps: int, dt: float):
+        U, dU = _c(U).copy(), _c(dU).copy()
+        lib().orc_rk_jvp(self.h, *sc.args(), _p(U), _p(dU), int(nsteps), float(dt))
+        return U, dU
+
+    def integrals(self, U, gamma=1.4):
+        U = _c(U)
+        out = np.zeros(7)
+        lib().orc_integrals(self.h, gamma, _p(U), _p(out))
+        return out
+
+    def entropy_production(self, U, Ut, gamma=1.4):
+        U, Ut = _c(U), _c(Ut)
+        return lib().orc_entropy_production(self.h, gamma, _p(U), _p(Ut))
+
+    def timestep(self, sc: Scheme, U, cfl, dfl):
+        U = _c(U)
+        return lib().orc_timestep(self.h, sc.gamma, sc.mu, sc.Pr, _p(U), float(cfl), float(dfl))
+
+
+def twopoint(volflux, Ua, Ub, nv, gamma=1.4):
+    F = np.zeros(5)
+    lib().orc_twopoint(VF[volflux], gamma, _p(_c(Ua)), _p(_c(Ub)), _p(_c(nv)), _p(F))
+    return F
+
+
+def riemann(rs, UL, UR, nh, gamma=1.4, volflux="kep"):
+    F = np.zeros(5)
+    lib().orc_riemann(RS[rs], VF[volflux], gamma, _p(_c(UL)), _p(_c(UR)), _p(_c(nh)), _p(F))
+    return F
+
+
+def riemann_jvp(rs, UL, UR, dUL, dUR, nh, gamma=1.4, volflux="kep"):
+    F, dF = np.zeros(5), np.zeros(5)
+    lib().orc_riemann_jvp(RS[rs], VF[volflux], gamma, _p(_c(UL)), _p(_c(UR)), _p(_c(dUL)), _p(_c(dUR)),
+                          _p(_c(nh)), _p(F), _p(dF))
+    return F, dF
+
+
+def roe_waves(UL, UR, nh, signed=False, gamma=1.4):
+    D = np.zeros(5)
+    lib().orc_roe_waves(gamma, _p(_c(UL)), _p(_c(UR)), _p(_c(nh)), int(signed), _p(D))
+    return D
+
+
+def euler_flux(U, nv, gamma=1.4):
+    F = np.zeros(5)
+    lib().orc_euler_flux(gamma, _p(_c(U)), _p(_c(nv)), _p(F))
+    return F
+
+
+def viscous_flux(U, g, nv, gamma=1.4, R=1.0, mu=1e-2, Pr=0.72):
+    F = np.zeros(5)
+    lib().orc_viscous_flux(gamma, R, mu, Pr, _p(_c(U)), _p(_c(g)), _p(_c(nv)), _p(F))
+    return F
+
+
+def mesh_for(wl, K1=None, N=None, nodes=None, curved=None):
+    """Build ``(OracleMesh, U0)`` for workload ``wl`` using the oracle's own LGL nodes."""
+    from paper_1910_02858_amd import inputs
+    N = wl.N if N is None else N
+    nodes = wl.nodes if nodes is None else nodes
+    k = wl.K1 if K1 is None else K1
+    curved = wl.curved if curved is None else curved
+    lgl = basis(N, "lgl")["x"]
+    X = inputs.lattice_points(lgl, k, k, k)
+    xgeo = inputs.warp_sine(X) if curved else X
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    M = OracleMesh(xgeo, nbr, side, N, nodes)
+    U0 = inputs.initial_state(wl, M.points())
+    return M, U0, xgeo, nbr, side

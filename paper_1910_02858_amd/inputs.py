@@ -1,0 +1,265 @@
+"""Seeded, synthetic inputs shared by the GPU path, the tests and the benchmark.
+
+This module holds no arithmetic of the discretisation itself: no quadrature
+nodes, no derivative matrices, no fluxes.  It only describes *problems*:
+
+* periodic hexahedral lattices and their face connectivity,
+* analytic maps from the undeformed lattice to a curved mesh,
+* closed-form initial states (density wave, Taylor-Green vortex),
+* the parameters of the five workloads and the seeded ensemble draw.
+
+Callers pass in the 1D reference nodes at which the map is to be sampled;
+each side (oracle, library) brings its own nodes.
+
+Side numbering used everywhere (library and oracle): side ``2*d`` is the
+face ``xi_d = -1`` and side ``2*d+1`` the face ``xi_d = +1`` of direction
+``d`` in ``(0, 1, 2)``.  Elements are numbered lexicographically,
+``e = ex + Kx*(ey + Ky*ez)``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+# ----------------------------------------------------------------------------- mesh
+def periodic_lattice(kx: int, ky: int, kz: int):
+    """Face connectivity of a fully periodic ``kx*ky*kz`` lattice.
+
+    Returns ``(nbr_elem[K,6] int32, nbr_side[K,6] int8, flip[K,6] int8)``.
+    The neighbour across side ``2d`` is the previous element in direction d
+    (with wrap-around) and it meets it on its side ``2d+1``; all flips are 0.
+    """
+    K = kx * ky * kz
+    nbr = np.empty((K, 6), np.int32)
+    side = np.empty((K, 6), np.int8)
+    ez, ey, ex = np.meshgrid(np.arange(kz), np.arange(ky), np.arange(kx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+
+    def lin(a, b, c):
+        return (a % kx) + kx * ((b % ky) + ky * (c % kz))
+
+    nbr[:, 0] = lin(ex - 1, ey, ez)
+    nbr[:, 1] = lin(ex + 1, ey, ez)
+    nbr[:, 2] = lin(ex, ey - 1, ez)
+    nbr[:, 3] = lin(ex, ey + 1, ez)
+    nbr[:, 4] = lin(ex, ey, ez - 1)
+    nbr[:, 5] = lin(ex, ey, ez + 1)
+    for s in range(6):
+        side[:, s] = s ^ 1
+    flip = np.zeros((K, 6), np.int8)
+    return nbr, side, flip
+
+
+def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):
+    """Undeformed positions ``X[e][3][n^3]`` of tensor nodes in every lattice cell.
+
+    ``nodes_1d`` are reference coordinates in [-1, 1] (supplied by the caller).
+    Node index ``i + n*(j + n*k)`` with i along x.
+    """
+    r = np.asarray(nodes_1d, dtype=np.float64)
+    n = r.size
+    K = kx * ky * kz
+    hx, hy, hz = box[0] / kx, box[1] / ky, box[2] / kz
+    ez, ey, ex = np.meshgrid(np.arange(kz), np.arange(ky), np.arange(kx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    t = 0.5 * (r + 1.0)
+    # local tensor coordinates, i fastest
+    tk, tj, ti = np.meshgrid(t, t, t, indexing="ij")
+    ti, tj, tk = ti.ravel(), tj.ravel(), tk.ravel()
+    X = np.empty((K, 3, n ** 3), np.float64)
+    X[:, 0, :] = (ex[:, None] + ti[None, :]) * hx
+    X[:, 1, :] = (ey[:, None] + tj[None, :]) * hy
+    X[:, 2, :] = (ez[:, None] + tk[None, :]) * hz
+    return X
+
+
+def warp_sine(X, amp: float = 0.1):
+    """Curved map ``x_d = X_d + amp*sin(X)sin(Y)sin(Z)`` for every d.
+
+    It vanishes on the planes X,Y,Z in {0, 2*pi}, so a periodic [0,2pi]^3
+    lattice stays periodic.
+    """
+    X = np.asarray(X)
+    s = amp * np.sin(X[:, 0]) * np.sin(X[:, 1]) * np.sin(X[:, 2])
+    return X + s[:, None, :]
+
+
+# ----------------------------------------------------------------------------- states
+def prim_to_cons(rho, u, v, w, p, gamma):
+    """Conservative state (rho, rho*u, rho*v, rho*w, E) of an ideal gas."""
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E], axis=-2)
+
+
+def density_wave(x, t: float = 0.0, gamma: float = 1.4, amp: float = 0.2):
+    """Exact Euler solution rho = 1 + amp*sin(x+y+z-3t), u=(1,1,1), p=1.
+
+    ``x`` has shape ``[K,3,n3]``; returns ``U[K,5,n3]``.
+    """
+    s = x[:, 0] + x[:, 1] + x[:, 2] - 3.0 * t
+    rho = 1.0 + amp * np.sin(s)
+    one = np.ones_like(rho)
+    return prim_to_cons(rho, one, one, one, one, gamma)
+
+
+def taylor_green(x, amp: float = 1.0, mach: float = 0.1, gamma: float = 1.4, rho0: float = 1.0):
+    """Taylor-Green vortex on [0,2pi]^3 with U0 = amp, rho = rho0.
+
+    u = A sin x cos y cos z, v = -A cos x sin y cos z, w = 0,
+    p = p0 + rho0*A^2/16 (cos 2x + cos 2y)(cos 2z + 2), p0 = rho0*A^2/(gamma Ma^2).
+    """
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    A = amp
+    u = A * np.sin(X) * np.cos(Y) * np.cos(Z)
+    v = -A * np.cos(X) * np.sin(Y) * np.cos(Z)
+    w = np.zeros_like(u)
+    p0 = rho0 * A * A / (gamma * mach * mach)
+    p = p0 + rho0 * A * A / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    rho = np.full_like(u, rho0)
+    return prim_to_cons(rho, u, v, w, p, gamma)
+
+
+def isentropic_vortex(x, eps: float = 5.0, gamma: float = 1.4, center=(10.0, 10.0), vel=(1.0, 1.0), t: float = 0.0,
+                      period=(20.0, 20.0)):
+    """Shu's isentropic vortex in the x-y plane, extruded in z (exact: advected).
+
+    Free stream rho=1, p=1, (u,v)=vel.  Uses the nearest periodic image of
+    the advected centre.
+    """
+    xc = center[0] + vel[0] * t
+    yc = center[1] + vel[1] * t
+    dx = x[:, 0] - xc
+    dy = x[:, 1] - yc
+    dx = dx - period[0] * np.round(dx / period[0])
+    dy = dy - period[1] * np.round(dy / period[1])
+    r2 = dx * dx + dy * dy
+    f = np.exp(0.5 * (1.0 - r2))
+    du = -eps / (2 * math.pi) * f * dy
+    dv = eps / (2 * math.pi) * f * dx
+    dT = -(gamma - 1.0) * eps * eps / (8.0 * gamma * math.pi * math.pi) * f * f
+    T = 1.0 + dT
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    u = vel[0] + du
+    v = vel[1] + dv
+    w = np.zeros_like(u)
+    return prim_to_cons(rho, u, v, w, p, gamma)
+
+
+def constant_state(K: int, n3: int, rho=1.2, u=0.3, v=-0.2, w=0.1, p=0.9, gamma=1.4):
+    shape = (K, n3)
+    return prim_to_cons(np.full(shape, rho), np.full(shape, u), np.full(shape, v), np.full(shape, w),
+                        np.full(shape, p), gamma)
+
+
+def random_perturbation(U, seed: int, rel: float = 1e-2):
+    """``U * (1 + rel*xi)`` with xi ~ N(0,1) per entry (seeded).  Keeps rho, p > 0 for small rel."""
+    rng = np.random.default_rng(seed)
+    return U * (1.0 + rel * rng.standard_normal(U.shape))
+
+
+def random_directions(U, seed: int, count: int):
+    """``count`` directions dU = diag(scale_v) xi, xi ~ N(0,1), scale_v = max|U_v| (seeded)."""
+    rng = np.random.default_rng(seed)
+    scale = np.abs(U).max(axis=(0, 2))
+    out = []
+    for _ in range(count):
+        xi = rng.standard_normal(U.shape)
+        out.append(xi * scale[None, :, None])
+    return out
+
+
+# ----------------------------------------------------------------------------- workloads
+@dataclasses.dataclass
+class Workload:
+    name: str
+    eqn: str          # "euler" | "ns"
+    form: str         # "weak" | "strong" | "split"
+    volflux: str      # "kep" | "ec" | "central"
+    riemann: str      # "llf" | "roe" | "volflux" | "volflux_roe"
+    nodes: str        # "lg" | "lgl"
+    N: int
+    K1: int           # elements per direction
+    curved: bool
+    ic: str           # "density_wave" | "tgv"
+    steps: int
+    gamma: float = 1.4
+    R: float = 1.0
+    Re: float = 1600.0
+    Pr: float = 0.72
+    mach: float = 0.1
+    amp: float = 1.0
+    cfl: float = 0.9
+    dfl: float = 0.9
+
+    @property
+    def mu(self) -> float:
+        # rho0 = U0 = L = 1 reference scales
+        return self.amp / self.Re if self.eqn == "ns" else 0.0
+
+    @property
+    def n_elems(self) -> int:
+        return self.K1 ** 3
+
+    @property
+    def n_dof(self) -> int:
+        return self.n_elems * (self.N + 1) ** 3
+
+
+def workload(idx: int, **over) -> Workload:
+    """The five workloads: 1 Euler density wave, 2 NS TGV curved N=5, 3 NS TGV N=7 48^3,
+    4 ensemble member template, 5 adjoint case."""
+    table = {
+        1: Workload("euler_dwave_lg3_k4", "euler", "weak", "central", "llf", "lg", 3, 4, False,
+                    "density_wave", 10),
+        2: Workload("ns_tgv_kep_roe_lgl5_k16_curved", "ns", "split", "kep", "roe", "lgl", 5, 16, True, "tgv", 100),
+        3: Workload("ns_tgv_ec_roe_lgl7_k48", "ns", "split", "ec", "roe", "lgl", 7, 48, False, "tgv", 50),
+        4: Workload("ns_tgv_kep_roe_ensemble_member", "ns", "split", "kep", "roe", "lgl", 5, 8, False, "tgv", 100),
+        5: Workload("ns_tgv_kep_roe_lgl5_k12_curved_adjoint", "ns", "split", "kep", "roe", "lgl", 5, 12, True,
+                    "tgv", 50),
+    }
+    wl = dataclasses.replace(table[idx])
+    for k, v in over.items():
+        setattr(wl, k, v)
+    return wl
+
+
+def ensemble_draw(n: int = 256, seed: int = 0):
+    """Seeded ensemble: K1 ~ U{4..12}, N ~ U{3..7}, A ~ U[0.5,1.5], Ma ~ U[0.05,0.2] (in that order)."""
+    rng = np.random.default_rng(seed)
+    K1 = rng.integers(4, 13, size=n)
+    N = rng.integers(3, 8, size=n)
+    A = rng.uniform(0.5, 1.5, size=n)
+    Ma = rng.uniform(0.05, 0.2, size=n)
+    out = []
+    for i in range(n):
+        out.append(Workload(f"ens{i}", "ns", "split", "kep", "roe", "lgl", int(N[i]), int(K1[i]), False, "tgv", 100,
+                            amp=float(A[i]), mach=float(Ma[i])))
+    return out
+
+
+def build_problem(wl: Workload, geo_nodes_1d, sol_points=None):
+    """Mesh description for ``wl``: geometry sampled at ``geo_nodes_1d`` (degree-N LGL nodes of the
+    caller) plus connectivity.  ``sol_points`` (physical solution-node positions, [K,3,n3]) may be
+    given to build the initial state there; otherwise the geometry points are used."""
+    k = wl.K1
+    X = lattice_points(geo_nodes_1d, k, k, k)
+    xgeo = warp_sine(X) if wl.curved else X
+    nbr, side, flip = periodic_lattice(k, k, k)
+    pts = xgeo if sol_points is None else sol_points
+    U0 = initial_state(wl, pts)
+    return xgeo, nbr, side, flip, U0
+
+
+def initial_state(wl: Workload, pts):
+    if wl.ic == "density_wave":
+        return density_wave(pts, 0.0, wl.gamma)
+    if wl.ic == "tgv":
+        return taylor_green(pts, wl.amp, wl.mach, wl.gamma)
+    raise ValueError(wl.ic)

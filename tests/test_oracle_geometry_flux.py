@@ -1,0 +1,222 @@
+"""Pins of the oracle's geometry (Sec. 3.1, curl-form metrics) and pointwise fluxes.
+
+Closed forms (affine map, analytic Jacobian and cofactors of the sine-warped map),
+the discrete metric identities, and algebraic identities of the fluxes (consistency,
+symmetry, Roe property, Tadmor's entropy condition, the kinetic-energy structure).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1910_02858_amd import inputs
+
+GAMMA = 1.4
+
+
+def _mesh(orc, k, N, nodes, curved):
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.lattice_points(lgl, k, k, k)
+    xg = inputs.warp_sine(X) if curved else X
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    return orc.OracleMesh(xg, nbr, side, N, nodes), X
+
+
+@pytest.mark.parametrize("nodes", ["lg", "lgl"])
+def test_affine_metrics(orc, nodes):
+    k, N = 3, 4
+    M, _ = _mesh(orc, k, N, nodes, False)
+    g = M.geometry()
+    h = 2 * math.pi / k
+    ref = np.zeros((9,))
+    ref[[0, 4, 8]] = (h / 2) ** 2
+    # rounding: coordinates up to 2*pi times derivative-matrix entries up to N(N+1)/4
+    np.testing.assert_allclose(g["Ja"], np.broadcast_to(ref[None, :, None], g["Ja"].shape), atol=1e-12)
+    np.testing.assert_allclose(g["J"], (h / 2) ** 3, rtol=1e-13)
+    # outward face normals of the + sides are +e_d (h/2)^2, of the - sides -e_d (h/2)^2
+    for s in range(6):
+        d, sg = s // 2, (1 if s % 2 else -1)
+        exp = np.zeros(3)
+        exp[d] = sg * (h / 2) ** 2
+        np.testing.assert_allclose(g["fn"][:, s], np.broadcast_to(exp[None, :, None], g["fn"][:, s].shape),
+                                   atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_metric_identities_curved(orc, N):
+    """sum_i d/dxi_i (Ja^i_d) = 0 discretely on the LGL nodes (free-stream condition)."""
+    M, _ = _mesh(orc, 3, N, "lgl", True)
+    g = M.geometry()
+    D = orc.basis(N, "lgl")["D"]
+    n = N + 1
+    Ja = g["Ja"].reshape(M.K, 3, 3, n, n, n)  # [e][i][d][k][j][i]
+    div = (np.einsum("am,edkjm->edkja", D, Ja[:, 0]) + np.einsum("am,edkmi->edkai", D, Ja[:, 1])
+           + np.einsum("am,edmji->edaji", D, Ja[:, 2]))
+    scale = np.abs(Ja).max() * np.abs(D).max()
+    assert np.abs(div).max() < 1e-14 * scale * n
+
+
+def _analytic_cofactor(X, h):
+    """J and Ja = cofactor(dx/dxi) of x = X + 0.1 sin X sin Y sin Z, with X = corner + h(xi+1)/2."""
+    sx, sy, sz = np.sin(X[:, 0]), np.sin(X[:, 1]), np.sin(X[:, 2])
+    cx, cy, cz = np.cos(X[:, 0]), np.cos(X[:, 1]), np.cos(X[:, 2])
+    grad = 0.1 * np.stack([cx * sy * sz, sx * cy * sz, sx * sy * cz], axis=1)  # d s / dX_k
+    K, n3 = X.shape[0], X.shape[2]
+    A = np.zeros((K, n3, 3, 3))
+    for d in range(3):
+        for k in range(3):
+            A[:, :, d, k] = (h / 2) * ((1.0 if d == k else 0.0) + grad[:, k])
+    J = np.linalg.det(A)
+    cof = np.linalg.inv(A) * J[..., None, None]  # (dxi_i/dx_d) J -> cof[i][d] = Ja^i_d
+    Ja = np.transpose(cof, (0, 2, 3, 1)).reshape(K, 9, n3)
+    return J, Ja
+
+
+def test_curved_jacobian_and_metrics_converge(orc):
+    N = 3
+    errJ, errA = [], []
+    for k in (2, 4, 8):
+        M, X = _mesh(orc, k, N, "lgl", True)
+        g = M.geometry()
+        h = 2 * math.pi / k
+        J, Ja = _analytic_cofactor(X, h)
+        # closed form of the determinant: (h/2)^3 (1 + 0.1 (c s s + s c s + s s c))
+        sx, sy, sz = np.sin(X[:, 0]), np.sin(X[:, 1]), np.sin(X[:, 2])
+        cx, cy, cz = np.cos(X[:, 0]), np.cos(X[:, 1]), np.cos(X[:, 2])
+        Jc = (h / 2) ** 3 * (1 + 0.1 * (cx * sy * sz + sx * cy * sz + sx * sy * cz))
+        np.testing.assert_allclose(J, Jc, rtol=1e-12)
+        errJ.append(np.abs(g["J"] / Jc - 1).max())
+        errA.append(np.abs(g["Ja"] - Ja).max() / (h / 2) ** 2)
+    rJ = math.log2(errJ[1] / errJ[2])
+    rA = math.log2(errA[1] / errA[2])
+    assert rJ > N - 0.5 and rA > N - 0.5, (errJ, errA)
+    assert errJ[2] < 2e-3
+
+
+# ----------------------------------------------------------------------------- fluxes
+def _rand_state(rng, mach=0.5):
+    rho = rng.uniform(0.5, 2.0)
+    u = rng.uniform(-1, 1, 3) * mach
+    p = rng.uniform(0.5, 2.0)
+    E = p / (GAMMA - 1) + 0.5 * rho * (u @ u)
+    return np.array([rho, *(rho * u), E])
+
+
+def _unit(rng):
+    v = rng.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def _entropy_vars(U):
+    rho = U[0]
+    u = U[1:4] / rho
+    p = (GAMMA - 1) * (U[4] - 0.5 * rho * (u @ u))
+    s = math.log(p) - GAMMA * math.log(rho)
+    return np.array([(GAMMA - s) / (GAMMA - 1) - 0.5 * rho * (u @ u) / p, *(rho * u / p), -rho / p])
+
+
+@pytest.mark.parametrize("rs", ["llf", "roe", "volflux", "volflux_roe"])
+def test_riemann_consistency_antisymmetry(orc, rs):
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        UL, UR, nh = _rand_state(rng), _rand_state(rng), _unit(rng)
+        vf = "ec" if rng.random() < 0.5 else "kep"
+        F = orc.riemann(rs, UL, UL, nh, volflux=vf)
+        np.testing.assert_allclose(F, orc.euler_flux(UL, nh), atol=1e-13 * np.abs(UL).max() * 4)
+        a = orc.riemann(rs, UL, UR, nh, volflux=vf)
+        b = orc.riemann(rs, UR, UL, -nh, volflux=vf)
+        np.testing.assert_allclose(a, -b, atol=1e-13 * np.abs(a).max())
+
+
+def test_roe_property(orc):
+    """Signed Roe wave sum equals the flux jump: A_roe (UR - UL) = F(UR) - F(UL)."""
+    rng = np.random.default_rng(12)
+    for _ in range(100):
+        UL, UR, nh = _rand_state(rng, 1.5), _rand_state(rng, 1.5), _unit(rng)
+        Dd = orc.roe_waves(UL, UR, nh, signed=True)
+        dF = orc.euler_flux(UR, nh) - orc.euler_flux(UL, nh)
+        np.testing.assert_allclose(Dd, dF, atol=1e-12 * (np.abs(dF).max() + 1))
+    # with every Roe eigenvalue positive the flux is the left (upwind) flux
+    def state(rho, u, p):
+        return np.array([rho, *(rho * np.asarray(u)), p / (GAMMA - 1) + 0.5 * rho * np.dot(u, u)])
+    U = state(1.0, [4.0, 0.0, 0.0], 1.0)  # Mach ~3.4 along +x: all waves move right
+    U2 = state(1.01, [4.02, 0.01, 0.0], 1.02)
+    F = orc.riemann("roe", U, U2, np.array([1.0, 0, 0]))
+    np.testing.assert_allclose(F, orc.euler_flux(U, np.array([1.0, 0, 0])), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("spread", [1e-3, 0.3, 2.0])
+def test_ec_flux_tadmor_condition(orc, spread):
+    """(w_b - w_a) . F#(a,b;n) = rho_b u_b.n - rho_a u_a.n (both log-mean branches)."""
+    rng = np.random.default_rng(13)
+    for _ in range(100):
+        Ua = _rand_state(rng)
+        Ub = Ua * (1 + spread * rng.uniform(-0.3, 0.3, 5))
+        Ub[4] = max(Ub[4], 0.5 * (Ub[1:4] @ Ub[1:4]) / Ub[0] + 0.1)
+        nv = rng.standard_normal(3)
+        F = orc.twopoint("ec", Ua, Ub, nv)
+        lhs = (_entropy_vars(Ub) - _entropy_vars(Ua)) @ F
+        rhs = Ub[1:4] @ nv - Ua[1:4] @ nv
+        assert abs(lhs - rhs) < 1e-12 * (np.abs(F).max() * np.abs(_entropy_vars(Ua)).max() + 1)
+
+
+@pytest.mark.parametrize("vf", ["kep", "ec", "central"])
+def test_twopoint_consistency_symmetry(orc, vf):
+    rng = np.random.default_rng(14)
+    for _ in range(50):
+        Ua, Ub, nv = _rand_state(rng), _rand_state(rng), rng.standard_normal(3)
+        np.testing.assert_allclose(orc.twopoint(vf, Ua, Ua, nv), orc.euler_flux(Ua, nv), rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(orc.twopoint(vf, Ua, Ub, nv), orc.twopoint(vf, Ub, Ua, nv), rtol=1e-13,
+                                   atol=1e-14)
+        # linear in the direction vector
+        n2 = rng.standard_normal(3)
+        np.testing.assert_allclose(orc.twopoint(vf, Ua, Ub, nv + 2 * n2),
+                                   orc.twopoint(vf, Ua, Ub, nv) + 2 * orc.twopoint(vf, Ua, Ub, n2), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_kep_structure(orc):
+    """Pirozzoli: F_rho = {rho}{u.n}, F_m = {u} F_rho + {p} n, F_E = F_rho {H}."""
+    rng = np.random.default_rng(15)
+    for _ in range(50):
+        Ua, Ub, nv = _rand_state(rng), _rand_state(rng), rng.standard_normal(3)
+        F = orc.twopoint("kep", Ua, Ub, nv)
+        ua, ub = Ua[1:4] / Ua[0], Ub[1:4] / Ub[0]
+        pa = (GAMMA - 1) * (Ua[4] - 0.5 * Ua[0] * ua @ ua)
+        pb = (GAMMA - 1) * (Ub[4] - 0.5 * Ub[0] * ub @ ub)
+        um = 0.5 * (ua + ub)
+        np.testing.assert_allclose(F[0], 0.5 * (Ua[0] + Ub[0]) * (um @ nv), rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(F[1:4], F[0] * um + 0.5 * (pa + pb) * nv, rtol=1e-12, atol=1e-13)
+        Hm = 0.5 * ((Ua[4] + pa) / Ua[0] + (Ub[4] + pb) / Ub[0])
+        np.testing.assert_allclose(F[4], F[0] * Hm, rtol=1e-12, atol=1e-13)
+
+
+def test_viscous_flux_special_cases(orc):
+    """Stokes' hypothesis: a rigid rotation has no stress; a uniform expansion has none either
+    (bulk viscosity 0); a pure shear has tau = mu (grad u + grad u^T); heat flux = kappa grad T."""
+    mu, Pr, R = 0.01, 0.72, 1.0
+    kappa = mu * GAMMA * R / (GAMMA - 1) / Pr
+    U = np.array([1.0, 0.3, -0.2, 0.1, 3.0])
+    u = U[1:4] / U[0]
+    nv = np.array([0.3, -0.7, 0.2])
+    W = np.array([[0, -1.0, 0.5], [1.0, 0, -2.0], [-0.5, 2.0, 0]])  # antisymmetric du_a/dx_b
+    g = np.zeros((3, 4))
+    for b in range(3):
+        for a in range(3):
+            g[b, a] = W[a, b]
+    F = orc.viscous_flux(U, g.ravel(), nv, mu=mu, Pr=Pr, R=R)
+    np.testing.assert_allclose(F, 0.0, atol=1e-15)
+    g2 = np.zeros((3, 4))
+    for a in range(3):
+        g2[a, a] = 0.7  # du_a/dx_a, uniform expansion
+    F = orc.viscous_flux(U, g2.ravel(), nv, mu=mu, Pr=Pr, R=R)
+    np.testing.assert_allclose(F, 0.0, atol=1e-15)
+    S = np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])  # shear du/dy = dv/dx = 1
+    g3 = np.zeros((3, 4))
+    g3[1, 0] = 1.0
+    g3[0, 1] = 1.0
+    g3[:, 3] = [0.2, -0.1, 0.4]
+    F = orc.viscous_flux(U, g3.ravel(), nv, mu=mu, Pr=Pr, R=R)
+    tau = mu * 2 * S
+    np.testing.assert_allclose(F[1:4], tau @ nv, atol=1e-15)
+    np.testing.assert_allclose(F[4], (tau @ u) @ nv + kappa * (g3[:, 3] @ nv), atol=1e-15)
