@@ -1,0 +1,157 @@
+"""Benchmark: DOF updates per second of the DGSEM RK step (Navier-Stokes TGV, N=7, 48^3 elements).
+
+One step = five stages of the 2N-storage Runge-Kutta scheme, each stage = BR1 lifting
+kernel + main operator kernel with the RK update fused (split form, entropy-conserving
+two-point flux, Roe surface flux), on 56.6 M nodes x 5 variables in FP64 resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--elements 48]
+
+Prints one JSON line.  value = DOF-updates/s = nodes * steps * 5 / wall (DOF counted per
+variable, as the paper's performance index does); PID = 1/value seconds per DOF per stage.
+The roofline object is for the dominant kernel, timed with HIP events on the library's
+stream over extra profiled stages after the timed region; its algorithmic bytes are the
+compulsory HBM traffic per node (42 doubles read+write for the main kernel, 27 for the
+lifting kernel).  cpu_baseline is the FP64 oracle on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s (PID s/DOF/stage) at N=7 TGV; adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+BYTES_MAIN = 42 * 8   # U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
+BYTES_LIFT = 27 * 8   # U 5 + Ja 9 + 1/J 1 read, grad W 12 written
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    """Time the oracle's RK stage on a bounded sample of the same workload (12^3 elements, N=7)."""
+    from oracle import oracle as orc
+    from paper_1910_02858_amd import inputs
+    k = 12
+    lgl = orc.basis(wl.N, "lgl")["x"]
+    X = inputs.lattice_points(lgl, k, k, k)
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes)
+    U = inputs.initial_state(wl, M.points())
+    R = np.zeros_like(U)
+    sc = orc.Scheme.of(wl)
+    a, b, _ = orc.rk_coefficients()
+    stages = 0
+    t0 = time.perf_counter()
+    while True:
+        U, R = M.rk_stage(sc, U, R, a[stages % 5], b[stages % 5], 1e-4)
+        stages += 1
+        if time.perf_counter() - t0 > budget_s and stages >= 2:
+            break
+    wall = time.perf_counter() - t0
+    dof = M.K * M.n3
+    return {"value": dof * stages / wall, "unit": "DOF-updates/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{stages} RK stages of the same scheme on {k}^3 elements, N={wl.N} ({dof} nodes), FP64",
+            "pid_core_s": wall * orc.num_threads() / (dof * stages)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--elements", type=int, default=48, help="elements per direction")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--profile-stages", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the element decomposition across GPUs is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_02858_amd import dgsem, inputs
+
+    wl = inputs.workload(3, K1=args.elements)
+    torch.cuda.set_device(0)
+    S, U = dgsem.build_solver(wl)
+    dof = S.K * S.n3
+    dt = S.timestep(U, wl.cfl, wl.dfl)
+    a, b, _ = dgsem.rk_coefficients()
+    R = torch.zeros_like(U)
+    spare = S.empty()
+
+    def run(nsteps, U, spare):
+        cur, nxt = U, spare
+        for _ in range(nsteps):
+            for s in range(5):
+                S.rk_stage(cur, nxt, R, a[s], b[s], dt)
+                cur, nxt = nxt, cur
+        return cur, nxt
+
+    U, spare = run(args.warmup, U, spare)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, spare = run(args.steps, U, spare)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if not S.check_finite(U):
+        print("non-finite solution after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    # per-kernel durations (HIP events on the library's stream), extra stages after the timed region
+    S.profile(True)
+    cur, nxt = U, spare
+    for s in range(args.profile_stages):
+        S.rk_stage(cur, nxt, R, a[s % 5], b[s % 5], dt)
+        cur, nxt = nxt, cur
+    prof = S.profile_read()
+    S.profile(False)
+    main_ms = prof["main_ms"] / max(prof["main_launches"], 1)
+    lift_ms = prof["lift_ms"] / max(prof["lift_launches"], 1)
+    main_gbs = BYTES_MAIN * dof / (main_ms * 1e-3) / 1e9
+    lift_gbs = BYTES_LIFT * dof / (lift_ms * 1e-3) / 1e9
+
+    stages = args.steps * 5
+    value = dof * stages / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name if args.elements == 48 else f"{wl.name}_k{args.elements}",
+                   "elements": S.K, "N": wl.N, "nodes": "lgl", "dof": dof, "stages_per_step": 5,
+                   "scheme": "navier-stokes split EC volume flux, Roe surface flux, BR1", "ic": "taylor-green Ma=0.1 Re=1600"},
+        "pid_s_per_dof_stage": wall / (dof * stages),
+        "ms_per_stage": wall * 1e3 / stages,
+        "kernels_ms": {"main": main_ms, "lift": lift_ms},
+        "roofline": {"bound": "hbm", "kernel": "k_main (split volume + surface + RK update)", "achieved": main_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_dof": BYTES_MAIN},
+        "roofline_lift": {"achieved": lift_gbs, "frac": lift_gbs / HBM_PEAK_GBS,
+                          "algorithmic_bytes_per_dof": BYTES_LIFT},
+        "stage_hbm_frac": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / HBM_PEAK_GBS,
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline(wl)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["pid_core_s"] = cb["pid_core_s"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,13 @@ int dg_rk_coefficients(double *a, double *b, double *c);
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
 
+/* The setup dg_init performs, on the host only (no device memory is touched): metric terms
+ * Ja [K][9][n^3] (Ja^i_d at i*3+d), J [K][n^3], outward face normals fn [K][6][3][n^2] and the
+ * n x n matrices D and Dhat, all host arrays (any may be NULL).  All tables are computed in
+ * extended precision and rounded once to double.  For inspection and tests.  Synchronous. */
+int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, double *J, double *fn, double *D,
+                     double *Dhat);
+
 /* Change the stream later calls are ordered on. */
 int dg_set_stream(dg_handle *h, void *hip_stream);
 
@@ -130,6 +137,14 @@ int dg_node_coords(dg_handle *h, double *x_host);
 
 /* Sizes: out[0] = K, out[1] = N, out[2] = n^3, out[3] = node type. */
 int dg_info(const dg_handle *h, int64_t out[4]);
+
+/* Per-kernel timing for performance reports.  With enable != 0 every later dg_rhs /
+ * dg_rk_stage records HIP events around the lifting and the main kernel on the handle's
+ * stream and waits for them (so calls become synchronous); dg_profile also clears the
+ * counters.  dg_profile_read gives {lifting ms, lifting launches, main-kernel ms,
+ * main-kernel launches} accumulated since the last dg_profile call. */
+int dg_profile(dg_handle *h, int enable);
+int dg_profile_read(const dg_handle *h, double out[4]);
 
 void dg_destroy(dg_handle *h);
 const char *dg_status_string(int status);

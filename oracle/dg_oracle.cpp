@@ -93,13 +93,18 @@ inline dual tmax(dual a, dual b) {
 }
 
 // ------------------------------------------------------------------------------ basis
+// One-time setup (nodes, weights, D, Dhat, boundary values, metric terms, J) is evaluated in
+// extended precision (long double) and rounded once to FP64, so the tables are correctly
+// rounded up to rare ties and do not depend on the order of operations used to build them.
+typedef long double ld;
+
 // Legendre polynomial P_n(x) and its derivative by the three-term recurrence.
-static void legendre(int n, double x, double& P, double& dP) {
+static void legendre(int n, ld x, ld& P, ld& dP) {
   if (n == 0) { P = 1; dP = 0; return; }
-  double p0 = 1, p1 = x, d0 = 0, d1 = 1;
+  ld p0 = 1, p1 = x, d0 = 0, d1 = 1;
   for (int k = 1; k < n; ++k) {
-    double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
-    double d2 = d0 + (2 * k + 1) * p1;
+    ld p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    ld d2 = d0 + (2 * k + 1) * p1;
     p0 = p1; p1 = p2; d0 = d1; d1 = d2;
   }
   P = p1; dP = d1;
@@ -107,62 +112,63 @@ static void legendre(int n, double x, double& P, double& dP) {
 
 struct Basis {
   int N = 0, n = 0, type = 0;           // type 0: LG, 1: LGL
-  std::vector<double> x, w, lam;        // nodes, weights, barycentric weights
+  std::vector<double> x, w;             // nodes, weights
   std::vector<double> D, Dhat;          // [r*n+s]
   std::vector<double> lm, lp;           // l_j(-1), l_j(+1)
   std::vector<double> lhm, lhp;         // l_j(+-1)/w_j
+  std::vector<ld> xl, wl, laml, Dl, lml, lpl;  // extended-precision originals
 };
 
 // Gauss nodes: roots of P_{N+1}; Gauss-Lobatto: +-1 and the roots of P_N'.
-static void gauss_nodes(int N, int type, std::vector<double>& x, std::vector<double>& w) {
+static void gauss_nodes(int N, int type, std::vector<ld>& x, std::vector<ld>& w) {
   const int n = N + 1;
-  x.assign(n, 0.0); w.assign(n, 0.0);
-  const double pi = 3.14159265358979323846;
+  x.assign(n, 0.0L); w.assign(n, 0.0L);
+  const ld pi = 3.141592653589793238462643383279502884L;
   if (type == 0) {
     for (int j = 0; j < (n + 1) / 2; ++j) {  // lower half; the upper half by symmetry
-      double xi = -std::cos((2.0 * j + 1.0) * pi / (2.0 * N + 2.0));
+      ld xi = -std::cos((2.0L * j + 1.0L) * pi / (2.0L * N + 2.0L));
       for (int it = 0; it < 100; ++it) {
-        double P, dP; legendre(n, xi, P, dP);
-        double dx = P / dP; xi -= dx;
-        if (std::fabs(dx) < 1e-16) break;
+        ld P, dP; legendre(n, xi, P, dP);
+        ld dx = P / dP; xi -= dx;
+        if (std::fabs(dx) < 1e-19L) break;
       }
-      double P, dP; legendre(n, xi, P, dP);
-      x[j] = xi; w[j] = 2.0 / ((1.0 - xi * xi) * dP * dP);
+      ld P, dP; legendre(n, xi, P, dP);
+      x[j] = xi; w[j] = 2.0L / ((1.0L - xi * xi) * dP * dP);
     }
   } else {
     x[0] = -1; x[N] = 1;
     for (int j = 1; j < (n + 1) / 2; ++j) {  // lower half; the upper half by symmetry
       // Newton on q = P_{N+1} - P_{N-1}, whose interior roots are those of P_N'; q' = (2N+1) P_N
-      double xi = -std::cos((j + 0.25) * pi / N - 3.0 / (8.0 * N * pi * (j + 0.25)));
+      ld xi = -std::cos((j + 0.25L) * pi / N - 3.0L / (8.0L * N * pi * (j + 0.25L)));
       for (int it = 0; it < 100; ++it) {
-        double Pa, dPa, Pb, dPb, Pn, dPn;
+        ld Pa, dPa, Pb, dPb, Pn, dPn;
         legendre(N + 1, xi, Pa, dPa); legendre(N - 1, xi, Pb, dPb); legendre(N, xi, Pn, dPn);
-        double dx = (Pa - Pb) / ((2.0 * N + 1.0) * Pn); xi -= dx;
-        if (std::fabs(dx) < 1e-16) break;
+        ld dx = (Pa - Pb) / ((2.0L * N + 1.0L) * Pn); xi -= dx;
+        if (std::fabs(dx) < 1e-19L) break;
       }
       x[j] = xi;
     }
     for (int j = 0; j < (n + 1) / 2; ++j) {
-      double P, dP; legendre(N, x[j], P, dP);
-      w[j] = 2.0 / (N * (N + 1.0) * P * P);
+      ld P, dP; legendre(N, x[j], P, dP);
+      w[j] = 2.0L / (N * (N + 1.0L) * P * P);
     }
   }
   // the node set is symmetric about 0
   if (n % 2 == 1) {
-    x[N / 2] = 0.0;
-    double P, dP;
-    if (type == 0) { legendre(n, 0.0, P, dP); w[N / 2] = 2.0 / (dP * dP); }
-    else { legendre(N, 0.0, P, dP); w[N / 2] = 2.0 / (N * (N + 1.0) * P * P); }
+    x[N / 2] = 0.0L;
+    ld P, dP;
+    if (type == 0) { legendre(n, 0.0L, P, dP); w[N / 2] = 2.0L / (dP * dP); }
+    else { legendre(N, 0.0L, P, dP); w[N / 2] = 2.0L / (N * (N + 1.0L) * P * P); }
   }
   for (int j = 0; j < n / 2; ++j) { x[N - j] = -x[j]; w[N - j] = w[j]; }
 }
 
 // Lagrange polynomial l_j(t) of the node set x (barycentric form).
-static double lagrange(const std::vector<double>& x, const std::vector<double>& lam, int j, double t) {
+static ld lagrange(const std::vector<ld>& x, const std::vector<ld>& lam, int j, ld t) {
   const int n = (int)x.size();
   for (int k = 0; k < n; ++k)
-    if (t == x[k]) return (k == j) ? 1.0 : 0.0;
-  double den = 0;
+    if (t == x[k]) return (k == j) ? 1.0L : 0.0L;
+  ld den = 0;
   for (int k = 0; k < n; ++k) den += lam[k] / (t - x[k]);
   return (lam[j] / (t - x[j])) / den;
 }
@@ -170,32 +176,37 @@ static double lagrange(const std::vector<double>& x, const std::vector<double>& 
 static Basis make_basis(int N, int type) {
   Basis b; b.N = N; b.n = N + 1; b.type = type;
   const int n = b.n;
-  gauss_nodes(N, type, b.x, b.w);
-  b.lam.assign(n, 1.0);
+  gauss_nodes(N, type, b.xl, b.wl);
+  b.laml.assign(n, 1.0L);
   for (int j = 0; j < n; ++j)
     for (int k = 0; k < n; ++k)
-      if (k != j) b.lam[j] /= (b.x[j] - b.x[k]);
+      if (k != j) b.laml[j] /= (b.xl[j] - b.xl[k]);
   // D_rs = l_s'(x_r)
-  b.D.assign(n * n, 0.0);
+  b.Dl.assign(n * n, 0.0L);
   for (int r = 0; r < n; ++r) {
-    double s_sum = 0;
+    ld s_sum = 0;
     for (int s = 0; s < n; ++s) {
       if (s == r) continue;
-      double v = (b.lam[s] / b.lam[r]) / (b.x[r] - b.x[s]);
-      b.D[r * n + s] = v; s_sum += v;
+      ld v = (b.laml[s] / b.laml[r]) / (b.xl[r] - b.xl[s]);
+      b.Dl[r * n + s] = v; s_sum += v;
     }
-    b.D[r * n + r] = -s_sum;
+    b.Dl[r * n + r] = -s_sum;
   }
+  b.x.resize(n); b.w.resize(n); b.D.resize(n * n); b.Dhat.resize(n * n);
+  for (int j = 0; j < n; ++j) { b.x[j] = (double)b.xl[j]; b.w[j] = (double)b.wl[j]; }
+  for (int c = 0; c < n * n; ++c) b.D[c] = (double)b.Dl[c];
   // weak-form matrix from the volume-integral derivation: Dhat_ij = -(w_j/w_i) D_ji
-  b.Dhat.assign(n * n, 0.0);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) b.Dhat[i * n + j] = -(b.w[j] / b.w[i]) * b.D[j * n + i];
+    for (int j = 0; j < n; ++j) b.Dhat[i * n + j] = (double)(-(b.wl[j] / b.wl[i]) * b.Dl[j * n + i]);
+  b.lml.resize(n); b.lpl.resize(n);
   b.lm.resize(n); b.lp.resize(n); b.lhm.resize(n); b.lhp.resize(n);
   for (int j = 0; j < n; ++j) {
-    b.lm[j] = lagrange(b.x, b.lam, j, -1.0);
-    b.lp[j] = lagrange(b.x, b.lam, j, 1.0);
-    b.lhm[j] = b.lm[j] / b.w[j];
-    b.lhp[j] = b.lp[j] / b.w[j];
+    b.lml[j] = lagrange(b.xl, b.laml, j, -1.0L);
+    b.lpl[j] = lagrange(b.xl, b.laml, j, 1.0L);
+    b.lm[j] = (double)b.lml[j];
+    b.lp[j] = (double)b.lpl[j];
+    b.lhm[j] = (double)(b.lml[j] / b.wl[j]);
+    b.lhp[j] = (double)(b.lpl[j] / b.wl[j]);
   }
   return b;
 }
@@ -214,13 +225,6 @@ struct Mesh {
 
 static inline int nid(int n, int i, int j, int k) { return i + n * (j + n * k); }
 
-// position of face point (a,b) of side s within the element volume index space (LGL only)
-static inline void face_dirs(int s, int& dn, int& da, int& db) {
-  dn = s / 2;
-  da = (dn == 0) ? 1 : 0;
-  db = (dn == 2) ? 1 : 2;
-}
-
 // node of the line through face point (a,b) of direction dn at position m along dn
 static inline int line_node(int n, int dn, int a, int b, int m) {
   int idx[3];
@@ -229,13 +233,13 @@ static inline int line_node(int n, int dn, int a, int b, int m) {
   return nid(n, idx[0], idx[1], idx[2]);
 }
 
-// apply the 1D matrix A (rows x n) along direction dir to field f on an n^3 grid
-static void apply_dir(const std::vector<double>& A, int n, int dir, const double* f, double* out) {
+// apply the 1D matrix A (n x n) along direction dir to field f on an n^3 grid
+static void apply_dir(const std::vector<ld>& A, int n, int dir, const ld* f, ld* out) {
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
         int id[3] = {i, j, k};
-        double s = 0;
+        ld s = 0;
         for (int m = 0; m < n; ++m) {
           int jd[3] = {i, j, k};
           jd[dir] = m;
@@ -258,17 +262,26 @@ static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, cons
   M.xs.assign((size_t)K * 3 * n3, 0.0);
   M.fn.assign((size_t)K * 6 * 3 * n2, 0.0);
   // interpolation matrix LGL -> solution nodes
-  std::vector<double> V(n * n);
+  std::vector<ld> V(n * n);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) V[i * n + j] = lagrange(M.lgl.x, M.lgl.lam, j, M.sol.x[i]);
+    for (int j = 0; j < n; ++j) V[i * n + j] = lagrange(M.lgl.xl, M.lgl.laml, j, M.sol.xl[i]);
   bool ok = true;
 #pragma omp parallel for schedule(static) reduction(&& : ok)
   for (int e = 0; e < K; ++e) {
-    std::vector<double> dx(9 * n3), Vf(3 * n3), tmp(n3), tmp2(n3), JaL(9 * n3);
-    const double* xe = xgeo + (size_t)e * 3 * n3;
+    std::vector<ld> xe(3 * n3), dx(9 * n3), Vf(3 * n3), tmp(n3), tmp2(n3), JaL(9 * n3), Jas(9 * n3), xse(3 * n3);
+    // coordinates relative to the element's centroid: the curl form is unchanged by a
+    // translation (the curl of a gradient vanishes, also for the tensor-product D), and the
+    // shift keeps the products x_l grad x_m small, so the subtraction in the curl loses
+    // no precision
+    ld cen[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+      for (int q = 0; q < n3; ++q) cen[d] += (ld)xgeo[((size_t)e * 3 + d) * n3 + q];
+      cen[d] /= n3;
+      for (int q = 0; q < n3; ++q) xe[d * n3 + q] = (ld)xgeo[((size_t)e * 3 + d) * n3 + q] - cen[d];
+    }
     // dx[(d*3+k)] = d x_d / d xi_k on LGL nodes
     for (int d = 0; d < 3; ++d)
-      for (int k = 0; k < 3; ++k) apply_dir(M.lgl.D, n, k, xe + d * n3, &dx[(d * 3 + k) * n3]);
+      for (int k = 0; k < 3; ++k) apply_dir(M.lgl.Dl, n, k, &xe[d * n3], &dx[(d * 3 + k) * n3]);
     // curl form: Ja^i_nn = -(curl_xi (x_l grad_xi x_m))_i, (nn,m,l) cyclic
     for (int nn = 0; nn < 3; ++nn) {
       int m = (nn + 1) % 3, l = (nn + 2) % 3;
@@ -276,55 +289,54 @@ static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, cons
         for (int q = 0; q < n3; ++q) Vf[k * n3 + q] = xe[l * n3 + q] * dx[(m * 3 + k) * n3 + q];
       for (int i = 0; i < 3; ++i) {
         int a = (i + 1) % 3, b = (i + 2) % 3;
-        apply_dir(M.lgl.D, n, a, &Vf[b * n3], tmp.data());
-        apply_dir(M.lgl.D, n, b, &Vf[a * n3], tmp2.data());
+        apply_dir(M.lgl.Dl, n, a, &Vf[b * n3], tmp.data());
+        apply_dir(M.lgl.Dl, n, b, &Vf[a * n3], tmp2.data());
         for (int q = 0; q < n3; ++q) JaL[(i * 3 + nn) * n3 + q] = -(tmp[q] - tmp2[q]);
       }
     }
-    double* Jae = &M.Ja[(size_t)e * 9 * n3];
-    double* xse = &M.xs[(size_t)e * 3 * n3];
     if (type == 1) {
-      std::copy(JaL.begin(), JaL.end(), Jae);
-      std::copy(xe, xe + 3 * n3, xse);
+      Jas = JaL;
+      xse = xe;
     } else {
       for (int c = 0; c < 9; ++c) {
         apply_dir(V, n, 0, &JaL[c * n3], tmp.data());
         apply_dir(V, n, 1, tmp.data(), tmp2.data());
-        apply_dir(V, n, 2, tmp2.data(), Jae + c * n3);
+        apply_dir(V, n, 2, tmp2.data(), &Jas[c * n3]);
       }
       for (int d = 0; d < 3; ++d) {
-        apply_dir(V, n, 0, xe + d * n3, tmp.data());
+        apply_dir(V, n, 0, &xe[d * n3], tmp.data());
         apply_dir(V, n, 1, tmp.data(), tmp2.data());
-        apply_dir(V, n, 2, tmp2.data(), xse + d * n3);
+        apply_dir(V, n, 2, tmp2.data(), &xse[d * n3]);
       }
     }
-    // J = det(dx/dxi) at solution nodes from the solution-node D
-    std::vector<double> g(9 * n3);
+    for (int q = 0; q < 9 * n3; ++q) M.Ja[(size_t)e * 9 * n3 + q] = (double)Jas[q];
     for (int d = 0; d < 3; ++d)
-      for (int k = 0; k < 3; ++k) apply_dir(M.sol.D, n, k, xse + d * n3, &g[(d * 3 + k) * n3]);
+      for (int q = 0; q < n3; ++q) M.xs[((size_t)e * 3 + d) * n3 + q] = (double)(xse[d * n3 + q] + cen[d]);
+    // J = det(dx/dxi) at solution nodes from the solution-node D
+    std::vector<ld> g(9 * n3);
+    for (int d = 0; d < 3; ++d)
+      for (int k = 0; k < 3; ++k) apply_dir(M.sol.Dl, n, k, &xse[d * n3], &g[(d * 3 + k) * n3]);
     for (int q = 0; q < n3; ++q) {
-      double a[9];
+      ld a[9];
       for (int c = 0; c < 9; ++c) a[c] = g[c * n3 + q];
-      double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
-                   a[2] * (a[3] * a[7] - a[4] * a[6]);
-      M.J[(size_t)e * n3 + q] = det;
+      ld det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+               a[2] * (a[3] * a[7] - a[4] * a[6]);
+      M.J[(size_t)e * n3 + q] = (double)det;
       if (!(det > 0)) ok = false;
     }
-  }
-  if (!ok) return false;
-  // master (+xi side) normals: Ja^dn evaluated on the face
-  for (int e = 0; e < K; ++e)
+    // master (+xi side) normals: Ja^dn evaluated on the face
     for (int s = 1; s < 6; s += 2) {
       int dn = s / 2;
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a)
           for (int d = 0; d < 3; ++d) {
-            double v = 0;
-            for (int m = 0; m < n; ++m)
-              v += M.sol.lp[m] * M.Ja[((size_t)e * 9 + dn * 3 + d) * n3 + line_node(n, dn, a, b, m)];
-            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = v;
+            ld v = 0;
+            for (int m = 0; m < n; ++m) v += M.sol.lpl[m] * Jas[(dn * 3 + d) * n3 + line_node(n, dn, a, b, m)];
+            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = (double)v;
           }
     }
+  }
+  if (!ok) return false;
   // slave (-xi side): negated normal of the neighbour's matching + side
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; s += 2) {
@@ -1003,3 +1015,10 @@ extern "C" void orc_riemann_jvp(int rs, int vf, double gamma, const double* UL, 
   riemann(a, b, nh, S, Fd);
   for (int v = 0; v < 5; ++v) { F[v] = Fd[v].v; dF[v] = Fd[v].d; }
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+extern "C" int orc_num_threads() { return omp_get_max_threads(); }
+#else
+extern "C" int orc_num_threads() { return 1; }
+#endif

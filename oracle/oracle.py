@@ -66,6 +66,7 @@ def lib():
         L.orc_integrals.argtypes = [ctypes.c_void_p, ctypes.c_double, _D, _D]
         L.orc_entropy_production.restype = ctypes.c_double
         L.orc_entropy_production.argtypes = [ctypes.c_void_p, ctypes.c_double, _D, _D]
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_timestep.restype = ctypes.c_double
         L.orc_timestep.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 3 + [_D, ctypes.c_double, ctypes.c_double]
         _lib = L
@@ -88,6 +89,10 @@ def basis(N: int, nodes: str):
     if rc:
         raise ValueError("unsupported N")
     return dict(x=x, w=w, D=D, Dhat=Dh, lm=lm, lp=lp)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def rk_coefficients():

@@ -1,0 +1,651 @@
+// Host side of libdgsem: argument checks, the one-time geometry setup of dg_init, and the
+// C entry points that launch the HIP kernels.  Nothing here computes the operator itself.
+//
+// Setup (Krais et al., FLEXI, Sec. 3.1):
+//   * nodes and weights: roots of P_{N+1} (LG) or +-1 and roots of P_N' (LGL), by Newton;
+//   * D_rs = l_s'(x_r) in barycentric form; Dhat_ij = -(w_j/w_i) D_ji, the matrix the volume
+//     integral's derivation produces; l(+-1) and lhat(+-1) = l(+-1)/w;
+//   * metric terms in curl form (eq. contravariantBasisVectorsCurl), evaluated on the degree-N
+//     LGL sample of the mapping and interpolated exactly to LG nodes when those are used;
+//   * J = det of the mapping Jacobian from the differentiation matrix at the solution nodes;
+//   * face normals: Ja^d on the +xi_d face of the element that owns the face (the master,
+//     Sec. 5.1), negated for the neighbour that sees the face as its -xi_d side.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+using dg::NMAX;
+
+namespace {
+
+const char *status_name(int s) {
+  switch (s) {
+    case DG_OK: return "DG_OK";
+    case DG_ERR_ARG: return "DG_ERR_ARG: invalid argument";
+    case DG_ERR_MESH: return "DG_ERR_MESH: invalid mesh";
+    case DG_ERR_UNSUPPORTED: return "DG_ERR_UNSUPPORTED: not supported by this build";
+    case DG_ERR_HIP: return "DG_ERR_HIP: HIP runtime error";
+    case DG_ERR_NONFINITE: return "DG_ERR_NONFINITE: non-finite value";
+    case DG_ERR_OOM: return "DG_ERR_OOM: device allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int fail(dg_handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------- 1D basis
+// All one-time tables are computed in long double and rounded once to double, so they are
+// correctly rounded (up to rare ties) whatever the order of operations used here.
+typedef long double xf;
+
+// P_n and P_n' at x via the three-term recurrence
+void legendre_pd(int n, xf x, xf &P, xf &dP) {
+  xf pm = 1.0L, pc = x;
+  if (n == 0) { P = 1.0L; dP = 0.0L; return; }
+  for (int k = 2; k <= n; ++k) {
+    const xf pn = ((2.0L * k - 1.0L) * x * pc - (k - 1.0L) * pm) / k;
+    pm = pc; pc = pn;
+  }
+  P = pc;
+  // P_n' = n (P_{n-1} - x P_n) / (1 - x^2), valid off +-1
+  dP = n * (pm - x * pc) / (1.0L - x * x);
+}
+
+void nodes_weights(int N, int type, std::vector<xf> &x, std::vector<xf> &w) {
+  const int n = N + 1;
+  x.assign(n, 0.0L);
+  w.assign(n, 0.0L);
+  const xf pi = 3.14159265358979323846264338327950288L;
+  if (type == DG_NODES_LG) {
+    for (int j = 0; j < n / 2; ++j) {
+      // root j of P_n counted from +1, Tricomi-type initial guess
+      xf r = std::cos(pi * (4.0L * j + 3.0L) / (4.0L * n + 2.0L));
+      for (int it = 0; it < 60; ++it) {
+        xf P, dP;
+        legendre_pd(n, r, P, dP);
+        const xf dr = P / dP;
+        r -= dr;
+        if (std::fabs(dr) <= 1e-20L) break;
+      }
+      xf P, dP;
+      legendre_pd(n, r, P, dP);
+      x[N - j] = r;
+      x[j] = -r;
+      w[j] = w[N - j] = 2.0L / ((1.0L - r * r) * dP * dP);
+    }
+    if (n % 2) {
+      xf P, dP;
+      legendre_pd(n, 0.0L, P, dP);
+      x[N / 2] = 0.0L;
+      w[N / 2] = 2.0L / (dP * dP);
+    }
+  } else {
+    x[0] = -1.0L;
+    x[N] = 1.0L;
+    for (int j = 1; j < (n + 1) / 2; ++j) {
+      // interior roots of P_N': Newton with P_N'' = (2x P_N' - N(N+1) P_N)/(1-x^2)
+      xf r = std::cos(pi * j / N) * (1.0L - 0.05L / (N * N));
+      for (int it = 0; it < 80; ++it) {
+        xf P, dP;
+        legendre_pd(N, r, P, dP);
+        const xf d2P = (2.0L * r * dP - N * (N + 1.0L) * P) / (1.0L - r * r);
+        const xf dr = dP / d2P;
+        r -= dr;
+        if (std::fabs(dr) <= 1e-20L) break;
+      }
+      x[N - j] = r;
+      x[j] = -r;
+    }
+    if (n % 2) x[N / 2] = 0.0L;
+    for (int j = 0; j < n; ++j) {
+      xf pm = 1.0L, pc = x[j];
+      for (int k = 2; k <= N; ++k) {
+        const xf pn = ((2.0L * k - 1.0L) * x[j] * pc - (k - 1.0L) * pm) / k;
+        pm = pc; pc = pn;
+      }
+      w[j] = 2.0L / (N * (N + 1.0L) * pc * pc);
+    }
+  }
+}
+
+struct Basis1D {
+  int n = 0;
+  std::vector<xf> x, w, bw, D, Dh, lm, lp;
+};
+
+xf lag_eval(const std::vector<xf> &x, const std::vector<xf> &bw, int j, xf t) {
+  const int n = (int)x.size();
+  for (int k = 0; k < n; ++k)
+    if (t == x[k]) return k == j ? 1.0L : 0.0L;
+  xf num = 0.0L, den = 0.0L;
+  for (int k = 0; k < n; ++k) {
+    const xf c = bw[k] / (t - x[k]);
+    den += c;
+    if (k == j) num = c;
+  }
+  return num / den;
+}
+
+Basis1D make_basis(int N, int type) {
+  Basis1D B;
+  const int n = N + 1;
+  B.n = n;
+  nodes_weights(N, type, B.x, B.w);
+  B.bw.assign(n, 1.0L);
+  for (int j = 0; j < n; ++j) {
+    xf p = 1.0L;
+    for (int k = 0; k < n; ++k)
+      if (k != j) p *= (B.x[j] - B.x[k]);
+    B.bw[j] = 1.0L / p;
+  }
+  B.D.assign(n * n, 0.0L);
+  for (int r = 0; r < n; ++r) {
+    xf diag = 0.0L;
+    for (int s = 0; s < n; ++s)
+      if (s != r) {
+        B.D[r * n + s] = (B.bw[s] / B.bw[r]) / (B.x[r] - B.x[s]);
+        diag -= B.D[r * n + s];
+      }
+    B.D[r * n + r] = diag;
+  }
+  B.Dh.assign(n * n, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) B.Dh[i * n + j] = -(B.w[j] / B.w[i]) * B.D[j * n + i];
+  B.lm.resize(n);
+  B.lp.resize(n);
+  for (int j = 0; j < n; ++j) {
+    B.lm[j] = lag_eval(B.x, B.bw, j, -1.0L);
+    B.lp[j] = lag_eval(B.x, B.bw, j, 1.0L);
+  }
+  return B;
+}
+
+// ---------------------------------------------------------------- geometry
+// y[i,j,k] = sum_m A[idx_dir, m] x[.. m ..] for an n x n matrix A along direction dir
+void tensor_apply(const xf *A, int n, int dir, const xf *x, xf *y) {
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        xf s = 0.0L;
+        const int row = dir == 0 ? i : (dir == 1 ? j : k);
+        for (int m = 0; m < n; ++m) {
+          const int ii = dir == 0 ? m : i, jj = dir == 1 ? m : j, kk = dir == 2 ? m : k;
+          s += A[row * n + m] * x[ii + n * (jj + n * kk)];
+        }
+        y[i + n * (j + n * k)] = s;
+      }
+}
+
+struct HostGeo {
+  std::vector<double> Ja, J, sJ, xs, fn;
+};
+
+int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nbr, HostGeo &G, std::string &msg) {
+  const int n = N + 1, n2 = n * n, n3 = n2 * n;
+  const Basis1D L = make_basis(N, DG_NODES_LGL);
+  const Basis1D S = (type == DG_NODES_LGL) ? L : make_basis(N, type);
+  std::vector<xf> V(n * n);  // LGL -> solution nodes
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = lag_eval(L.x, L.bw, j, S.x[i]);
+  G.Ja.assign((size_t)K * 9 * n3, 0.0);
+  G.J.assign((size_t)K * n3, 0.0);
+  G.sJ.assign((size_t)K * n3, 0.0);
+  G.xs.assign((size_t)K * 3 * n3, 0.0);
+  G.fn.assign((size_t)K * 6 * 3 * n2, 0.0);
+  std::vector<xf> X(3 * n3), dx(9 * n3), prod(3 * n3), c1(n3), c2(n3), JaL(9 * n3), Jas(9 * n3), t1(n3), t2(n3),
+      xs(3 * n3), jac(9 * n3);
+  for (int e = 0; e < K; ++e) {
+    // work relative to the element centroid; the curl form is translation invariant and the
+    // shift removes the cancellation between the two products of each curl component
+    xf c0[3];
+    for (int d = 0; d < 3; ++d) {
+      xf acc = 0.0L;
+      for (int q = 0; q < n3; ++q) acc += xgeo[((size_t)e * 3 + d) * n3 + q];
+      c0[d] = acc / n3;
+      for (int q = 0; q < n3; ++q) X[d * n3 + q] = xgeo[((size_t)e * 3 + d) * n3 + q] - c0[d];
+    }
+    // dx[m*3+k] = d x_m / d xi_k on the LGL sample
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 3; ++k) tensor_apply(L.D.data(), n, k, &X[m * n3], &dx[(m * 3 + k) * n3]);
+    // curl form, component nn with (nn, m, l) cyclic:
+    //   Ja^i_nn = -[curl_xi (x_l grad_xi x_m)]_i
+    for (int nn = 0; nn < 3; ++nn) {
+      const int m = (nn + 1) % 3, l = (nn + 2) % 3;
+      for (int k = 0; k < 3; ++k)
+        for (int q = 0; q < n3; ++q) prod[k * n3 + q] = X[l * n3 + q] * dx[(m * 3 + k) * n3 + q];
+      for (int i = 0; i < 3; ++i) {
+        const int a = (i + 1) % 3, b = (i + 2) % 3;
+        tensor_apply(L.D.data(), n, a, &prod[b * n3], c1.data());
+        tensor_apply(L.D.data(), n, b, &prod[a * n3], c2.data());
+        for (int q = 0; q < n3; ++q) JaL[(i * 3 + nn) * n3 + q] = c2[q] - c1[q];
+      }
+    }
+    if (type == DG_NODES_LGL) {
+      Jas = JaL;
+      xs = X;
+    } else {
+      for (int c = 0; c < 9; ++c) {
+        tensor_apply(V.data(), n, 0, &JaL[c * n3], t1.data());
+        tensor_apply(V.data(), n, 1, t1.data(), t2.data());
+        tensor_apply(V.data(), n, 2, t2.data(), &Jas[c * n3]);
+      }
+      for (int c = 0; c < 3; ++c) {
+        tensor_apply(V.data(), n, 0, &X[c * n3], t1.data());
+        tensor_apply(V.data(), n, 1, t1.data(), t2.data());
+        tensor_apply(V.data(), n, 2, t2.data(), &xs[c * n3]);
+      }
+    }
+    for (int q = 0; q < 9 * n3; ++q) G.Ja[(size_t)e * 9 * n3 + q] = (double)Jas[q];
+    for (int d = 0; d < 3; ++d)
+      for (int q = 0; q < n3; ++q) G.xs[((size_t)e * 3 + d) * n3 + q] = (double)(xs[d * n3 + q] + c0[d]);
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 3; ++k) tensor_apply(S.D.data(), n, k, &xs[m * n3], &jac[(m * 3 + k) * n3]);
+    for (int q = 0; q < n3; ++q) {
+      const xf a00 = jac[0 * n3 + q], a01 = jac[1 * n3 + q], a02 = jac[2 * n3 + q];
+      const xf a10 = jac[3 * n3 + q], a11 = jac[4 * n3 + q], a12 = jac[5 * n3 + q];
+      const xf a20 = jac[6 * n3 + q], a21 = jac[7 * n3 + q], a22 = jac[8 * n3 + q];
+      const xf det = a00 * (a11 * a22 - a12 * a21) + a01 * (a12 * a20 - a10 * a22) + a02 * (a10 * a21 - a11 * a20);
+      if (!(det > 0.0L) || !std::isfinite((double)det)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "element %d node %d: Jacobian %.3Le is not positive", e, q, det);
+        msg = buf;
+        return DG_ERR_MESH;
+      }
+      G.J[(size_t)e * n3 + q] = (double)det;
+      G.sJ[(size_t)e * n3 + q] = (double)(1.0L / det);
+    }
+    // masters: the +xi_d side of every element
+    for (int d = 0; d < 3; ++d) {
+      const int s = 2 * d + 1;
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a)
+          for (int c = 0; c < 3; ++c) {
+            xf v = 0.0L;
+            for (int m = 0; m < n; ++m) {
+              const int q = d == 0 ? (m + n * (a + n * b)) : (d == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
+              v += S.lp[m] * Jas[(d * 3 + c) * n3 + q];
+            }
+            G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + a + n * b] = (double)v;
+          }
+    }
+  }
+  // slaves: negated normal of the master's matching side
+  for (int e = 0; e < K; ++e)
+    for (int d = 0; d < 3; ++d) {
+      const int s = 2 * d, nb = nbr[e * 6 + s];
+      for (int c = 0; c < 3; ++c)
+        for (int p = 0; p < n2; ++p)
+          G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + p] = -G.fn[(((size_t)nb * 6 + s + 1) * 3 + c) * n2 + p];
+    }
+  return DG_OK;
+}
+
+int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
+  if (!mesh || !mesh->xgeo || !mesh->nbr_elem || !mesh->nbr_side) return DG_ERR_ARG;
+  if (N < 1 || N > NMAX) return DG_ERR_UNSUPPORTED;
+  if (mesh->n_geo != N) return DG_ERR_UNSUPPORTED;
+  if (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) return DG_ERR_ARG;
+  if (mesh->n_elems < 1) return DG_ERR_ARG;
+  const int K = mesh->n_elems;
+  // connectivity: every side has a reciprocal neighbour on the opposite side, flip 0
+  for (int e = 0; e < K; ++e)
+    for (int s = 0; s < 6; ++s) {
+      const int nb = mesh->nbr_elem[e * 6 + s];
+      if (nb < 0 || nb >= K) return DG_ERR_UNSUPPORTED;  // boundaries are not supported
+      if (mesh->nbr_side[e * 6 + s] != (s ^ 1)) return DG_ERR_UNSUPPORTED;
+      if (mesh->flip && mesh->flip[e * 6 + s] != 0) return DG_ERR_UNSUPPORTED;
+      if (mesh->nbr_elem[nb * 6 + (s ^ 1)] != e) return DG_ERR_MESH;
+    }
+  return DG_OK;
+}
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+template <class T> int dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return DG_OK;
+  if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return DG_ERR_OOM;
+  }
+  return DG_OK;
+}
+
+int lift_dispatch(dg_handle *h, const double *U) {
+  const dg::Geo g = h->geo();
+  const bool lgl = h->node_type == DG_NODES_LGL;
+  switch (h->N) {
+#define DG_CASE(NN) \
+  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, U, h->d_G, h->stream);
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return DG_ERR_UNSUPPORTED;
+  }
+}
+
+int main_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode) {
+  const dg::Geo g = h->geo();
+  const bool lgl = h->node_type == DG_NODES_LGL;
+  switch (h->N) {
+#define DG_CASE(NN) \
+  case NN: \
+    return dg::launch_main<NN>(g, h->ph, lgl, h->sc.eqn, h->sc.form, U, h->d_G, out, R, a, b, dt, mode, h->stream);
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return DG_ERR_UNSUPPORTED;
+  }
+}
+
+// lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on
+int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode) {
+  const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
+  if (h->prof) (void)hipEventRecord(h->ev[0], h->stream);
+  if (ns) {
+    int rc = lift_dispatch(h, U);
+    if (rc) return rc;
+  }
+  if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
+  int rc = main_dispatch(h, U, out, R, a, b, dt, mode);
+  if (rc) return rc;
+  if (h->prof) {
+    (void)hipEventRecord(h->ev[2], h->stream);
+    if (hipEventSynchronize(h->ev[2]) != hipSuccess) return DG_ERR_HIP;
+    float m0 = 0.f, m1 = 0.f;
+    (void)hipEventElapsedTime(&m0, h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&m1, h->ev[1], h->ev[2]);
+    if (ns) { h->prof_ms[0] += m0; h->prof_ms[1] += 1; }
+    h->prof_ms[2] += m1; h->prof_ms[3] += 1;
+  }
+  return DG_OK;
+}
+
+int reduce_dispatch(dg_handle *h, int what, const double *U) {
+  const dg::Geo g = h->geo();
+  int rc;
+  switch (h->N) {
+#define DG_CASE(NN) \
+  case NN: rc = dg::launch_reduce<NN>(g, h->ph, what, U, 0.0, h->d_partial, h->stream); break;
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return DG_ERR_UNSUPPORTED;
+  }
+  if (rc) return rc;
+  return dg::launch_final_reduce(what, h->d_partial, h->K, h->d_red, h->stream);
+}
+
+int fetch_red(dg_handle *h, double *out8) {
+  if (hipMemcpyAsync(out8, h->d_red, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    return fail(h, DG_ERR_HIP, "copy of a reduction result failed");
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, DG_ERR_HIP, "stream synchronisation failed");
+  return DG_OK;
+}
+
+int check_solution_ptr(dg_handle *h, const void *p, const char *name) {
+  if (!p) return fail(h, DG_ERR_ARG, std::string(name) + " is NULL");
+  if (!aligned8(p)) return fail(h, DG_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+  return DG_OK;
+}
+
+bool overlap(const void *a, const void *b, size_t bytes) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dg_status_string(int status) { return status_name(status); }
+
+const char *dg_last_error(const dg_handle *h) { return h ? h->err.c_str() : "no handle"; }
+
+int dg_nodes(int N, int node_type, double *x, double *w) {
+  if (N < 1 || N > NMAX || (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) || !x || !w) return DG_ERR_ARG;
+  std::vector<xf> xx, ww;
+  nodes_weights(N, node_type, xx, ww);
+  for (int i = 0; i <= N; ++i) { x[i] = (double)xx[i]; w[i] = (double)ww[i]; }
+  return DG_OK;
+}
+
+int dg_rk_coefficients(double *a, double *b, double *c) {
+  if (!a || !b || !c) return DG_ERR_ARG;
+  // Carpenter & Kennedy (1994), five-stage fourth-order 2N-storage scheme
+  static const double A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                              -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+  static const double B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                              1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                              2277821191437.0 / 14882151754819.0};
+  static const double C[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                              2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+  for (int s = 0; s < 5; ++s) { a[s] = A[s]; b[s] = B[s]; c[s] = C[s]; }
+  return DG_OK;
+}
+
+int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void *stream, dg_handle **out) {
+  if (!out) return DG_ERR_ARG;
+  *out = nullptr;
+  if (!mesh || !sc) return DG_ERR_ARG;
+  if (sc->eqn != DG_EULER && sc->eqn != DG_NAVIER_STOKES) return DG_ERR_ARG;
+  if (sc->form < DG_FORM_WEAK || sc->form > DG_FORM_STRONG) return DG_ERR_ARG;
+  if (sc->volflux < DG_VF_KEP || sc->volflux > DG_VF_CENTRAL) return DG_ERR_ARG;
+  if (sc->riemann < DG_RS_LLF || sc->riemann > DG_RS_VOLFLUX_ROE) return DG_ERR_ARG;
+  if (!(sc->gamma > 1.0) || !(sc->R > 0.0) || !(sc->Pr > 0.0) || !(sc->mu >= 0.0)) return DG_ERR_ARG;
+  int vrc = validate_mesh(mesh, N, node_type);
+  if (vrc) return vrc;
+  if (sc->form != DG_FORM_WEAK && node_type != DG_NODES_LGL) return DG_ERR_UNSUPPORTED;
+  const int K = mesh->n_elems;
+  dg_handle *h = new (std::nothrow) dg_handle;
+  if (!h) return DG_ERR_OOM;
+  h->K = K; h->N = N; h->n = N + 1; h->n2 = h->n * h->n; h->n3 = h->n2 * h->n; h->node_type = node_type;
+  h->sc = *sc;
+  h->stream = (hipStream_t)stream;
+  h->ph.gamma = sc->gamma; h->ph.R = sc->R; h->ph.mu = sc->mu; h->ph.Pr = sc->Pr;
+  h->ph.kappa = sc->mu * sc->gamma * sc->R / (sc->gamma - 1.0) / sc->Pr;
+  h->ph.vf = sc->volflux; h->ph.rs = sc->riemann;
+  const int n = h->n, n2 = h->n2, n3 = h->n3;
+  // 1D tables
+  const Basis1D B = make_basis(N, node_type);
+  std::memset(&h->tab, 0, sizeof(h->tab));
+  for (int c = 0; c < n * n; ++c) { h->tab.D[c] = (double)B.D[c]; h->tab.Dh[c] = (double)B.Dh[c]; }
+  for (int j = 0; j < n; ++j) {
+    h->tab.lm[j] = (double)B.lm[j]; h->tab.lp[j] = (double)B.lp[j];
+    h->tab.lhm[j] = (double)(B.lm[j] / B.w[j]); h->tab.lhp[j] = (double)(B.lp[j] / B.w[j]);
+    h->tab.w[j] = (double)B.w[j];
+  }
+  HostGeo G;
+  std::string msg;
+  int rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, G, msg);
+  if (rc) { delete h; return rc; }
+  const std::vector<double> &sJ = G.sJ;
+  h->x_nodes.swap(G.xs);
+  const bool ns = sc->eqn == DG_NAVIER_STOKES;
+  rc = dev_alloc(&h->d_Ja, (size_t)K * 9 * n3);
+  if (!rc) rc = dev_alloc(&h->d_sJ, (size_t)K * n3);
+  if (!rc) rc = dev_alloc(&h->d_fn, (size_t)K * 18 * n2);
+  if (!rc) rc = dev_alloc(&h->d_nbr, (size_t)K * 6);
+  if (!rc) rc = dev_alloc(&h->d_tab, 1);
+  if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
+  if (!rc) rc = dev_alloc(&h->d_partial, (size_t)K * 8);
+  if (!rc) rc = dev_alloc(&h->d_red, 8);
+  if (rc) { dg_destroy(h); return rc; }
+  bool ok = hipMemcpy(h->d_Ja, G.Ja.data(), G.Ja.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(h->d_sJ, sJ.data(), sJ.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(h->d_fn, G.fn.data(), G.fn.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(h->d_nbr, mesh->nbr_elem, (size_t)K * 6 * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(h->d_tab, &h->tab, sizeof(dg::Tab), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) { dg_destroy(h); return DG_ERR_HIP; }
+  *out = h;
+  return DG_OK;
+}
+
+int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, double *J, double *fn, double *D,
+                     double *Dhat) {
+  int rc = validate_mesh(mesh, N, node_type);
+  if (rc) return rc;
+  const int K = mesh->n_elems, n = N + 1;
+  HostGeo G;
+  std::string msg;
+  rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, G, msg);
+  if (rc) return rc;
+  if (Ja) std::memcpy(Ja, G.Ja.data(), G.Ja.size() * sizeof(double));
+  if (J) std::memcpy(J, G.J.data(), G.J.size() * sizeof(double));
+  if (fn) std::memcpy(fn, G.fn.data(), G.fn.size() * sizeof(double));
+  const Basis1D B = make_basis(N, node_type);
+  for (int c = 0; c < n * n; ++c) {
+    if (D) D[c] = (double)B.D[c];
+    if (Dhat) Dhat[c] = (double)B.Dh[c];
+  }
+  return DG_OK;
+}
+
+int dg_set_stream(dg_handle *h, void *stream) {
+  if (!h) return DG_ERR_ARG;
+  h->stream = (hipStream_t)stream;
+  return DG_OK;
+}
+
+int dg_info(const dg_handle *h, int64_t out[4]) {
+  if (!h || !out) return DG_ERR_ARG;
+  out[0] = h->K; out[1] = h->N; out[2] = h->n3; out[3] = h->node_type;
+  return DG_OK;
+}
+
+int dg_rhs(dg_handle *h, const double *U, double *Ut) {
+  if (!h) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U, "U");
+  if (!rc) rc = check_solution_ptr(h, Ut, "Ut");
+  if (rc) return rc;
+  const size_t bytes = (size_t)h->K * 5 * h->n3 * sizeof(double);
+  if (overlap(U, Ut, bytes)) return fail(h, DG_ERR_ARG, "U and Ut overlap");
+  rc = rhs_dispatch(h, U, Ut, nullptr, 0.0, 0.0, 0.0, 0);
+  if (rc) return fail(h, rc, "launch of the operator failed");
+  return DG_OK;
+}
+
+int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt) {
+  if (!h) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U_in, "U_in");
+  if (!rc) rc = check_solution_ptr(h, U_out, "U_out");
+  if (!rc) rc = check_solution_ptr(h, R, "R");
+  if (rc) return rc;
+  const size_t bytes = (size_t)h->K * 5 * h->n3 * sizeof(double);
+  if (overlap(U_in, U_out, bytes) || overlap(U_in, R, bytes) || overlap(U_out, R, bytes))
+    return fail(h, DG_ERR_ARG, "U_in, U_out and R must be three distinct buffers");
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite coefficient");
+  rc = rhs_dispatch(h, U_in, U_out, R, a, b, dt, 1);
+  if (rc) return fail(h, rc, "launch of the operator failed");
+  return DG_OK;
+}
+
+int dg_timestep(dg_handle *h, const double *U, double cfl, double dfl, double *dt_out) {
+  if (!h || !dt_out) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U, "U");
+  if (rc) return rc;
+  if (!(cfl > 0.0) || !(dfl > 0.0)) return fail(h, DG_ERR_ARG, "CFL numbers must be positive");
+  rc = reduce_dispatch(h, dg::RED_TIMESTEP, U);
+  if (rc) return fail(h, rc, "launch of the time-step reduction failed");
+  double r[8];
+  rc = fetch_red(h, r);
+  if (rc) return rc;
+  if (!std::isfinite(r[0]) || !(r[0] > 0.0)) return fail(h, DG_ERR_NONFINITE, "invalid signal speed");
+  double dt = cfl * 2.0 / ((2.0 * h->N + 1.0) * r[0]);
+  if (h->sc.eqn == DG_NAVIER_STOKES && h->sc.mu > 0.0 && r[1] > 0.0)
+    dt = std::min(dt, dfl * 4.0 / ((2.0 * h->N + 1.0) * r[1]));
+  *dt_out = dt;
+  return DG_OK;
+}
+
+int dg_integrals(dg_handle *h, const double *U, double out[8]) {
+  if (!h || !out) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U, "U");
+  if (rc) return rc;
+  rc = reduce_dispatch(h, dg::RED_INTEGRALS, U);
+  if (rc) return fail(h, rc, "launch of the integral reduction failed");
+  return fetch_red(h, out);
+}
+
+int dg_check_finite(dg_handle *h, const double *U) {
+  if (!h) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U, "U");
+  if (rc) return rc;
+  rc = reduce_dispatch(h, dg::RED_FINITE, U);
+  if (rc) return fail(h, rc, "launch of the finiteness check failed");
+  double r[8];
+  rc = fetch_red(h, r);
+  if (rc) return rc;
+  if (r[0] != 0.0) return fail(h, DG_ERR_NONFINITE, "solution holds NaN or Inf");
+  return DG_OK;
+}
+
+int dg_node_coords(dg_handle *h, double *x_host) {
+  if (!h || !x_host) return DG_ERR_ARG;
+  std::memcpy(x_host, h->x_nodes.data(), h->x_nodes.size() * sizeof(double));
+  return DG_OK;
+}
+
+int dg_profile(dg_handle *h, int enable) {
+  if (!h) return DG_ERR_ARG;
+  if (enable && !h->ev[0]) {
+    for (int i = 0; i < 3; ++i)
+      if (hipEventCreate(&h->ev[i]) != hipSuccess) return fail(h, DG_ERR_HIP, "hipEventCreate failed");
+  }
+  h->prof = enable != 0;
+  for (int i = 0; i < 4; ++i) h->prof_ms[i] = 0.0;
+  return DG_OK;
+}
+
+int dg_profile_read(const dg_handle *h, double out[4]) {
+  if (!h || !out) return DG_ERR_ARG;
+  for (int i = 0; i < 4; ++i) out[i] = h->prof_ms[i];
+  return DG_OK;
+}
+
+void dg_destroy(dg_handle *h) {
+  if (!h) return;
+  for (int i = 0; i < 3; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
+  (void)hipFree(h->d_tab);
+  (void)hipFree(h->d_G); (void)hipFree(h->d_Gbar); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
+  delete h;
+}
+
+int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_bar) {
+  if (!h) return DG_ERR_ARG;
+  (void)U; (void)Ut_bar; (void)U_bar;
+  return fail(h, DG_ERR_UNSUPPORTED, "vector-Jacobian product not built");
+}
+
+int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt) {
+  if (!h) return DG_ERR_ARG;
+  (void)U_in; (void)U_bar; (void)R_bar; (void)a; (void)b; (void)dt;
+  return fail(h, DG_ERR_UNSUPPORTED, "vector-Jacobian product not built");
+}
+
+int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {
+  (void)members; (void)n_members;
+  if (out) *out = nullptr;
+  return DG_ERR_UNSUPPORTED;
+}
+
+int dg_batch_rk_stage(dg_batch *b, const double *const *U_in, double *const *U_out, double *const *R, const double *a,
+                      const double *b_coef, const double *dt) {
+  (void)b; (void)U_in; (void)U_out; (void)R; (void)a; (void)b_coef; (void)dt;
+  return DG_ERR_UNSUPPORTED;
+}
+
+void dg_batch_destroy(dg_batch *b) { (void)b; }
+
+}  // extern "C"

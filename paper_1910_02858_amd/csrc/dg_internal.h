@@ -1,0 +1,85 @@
+// Internal declarations shared by the host setup (dg_host.cpp) and the HIP kernels
+// (dg_kernels.hip) of libdgsem.  Not part of the public ABI (include/dgsem.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dgsem.h"
+
+namespace dg {
+
+constexpr int NMAX = 8;  // highest supported polynomial degree
+
+// 1D operators of one node set, packed for the handle's degree (n = N+1):
+// D[r*n+s] = l_s'(x_r); Dh[i*n+j] = -(w_j/w_i) D[j*n+i]; l(+-1); lhat(+-1) = l(+-1)/w.
+struct Tab {
+  double D[(NMAX + 1) * (NMAX + 1)];
+  double Dh[(NMAX + 1) * (NMAX + 1)];
+  double lm[NMAX + 1], lp[NMAX + 1], lhm[NMAX + 1], lhp[NMAX + 1], w[NMAX + 1];
+};
+
+// Device-resident geometry of one mesh.
+struct Geo {
+  const double *Ja;   // [K][9][n3]: Ja^i_d at (i*3+d)
+  const double *sJ;   // [K][n3]: 1/J
+  const double *fn;   // [K][6][3][n2]: outward scaled normal of each side (the master's, negated on slaves)
+  const int32_t *nbr; // [K][6]
+  const Tab *tab;
+  int K;
+};
+
+struct Phys {
+  double gamma, R, mu, Pr, kappa;  // kappa = mu cp / Pr
+  int vf, rs;
+};
+
+// Kernel launch entry points, one explicit instantiation per degree.
+template <int N>
+int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double *G, hipStream_t st);
+template <int N>
+int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const double *U, const double *G,
+                double *out, double *R, double a, double b, double dt, int mode, hipStream_t st);
+template <int N>
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
+               const double *Ubar_t, double *Ubar, double scale, int accumulate, hipStream_t st);
+template <int N>
+int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double cfl_unused, double *partial,
+                  hipStream_t st);
+
+// what codes for launch_reduce
+enum { RED_TIMESTEP = 0, RED_INTEGRALS = 1, RED_FINITE = 2 };
+
+int launch_final_reduce(int what, const double *partial, int K, double *out, hipStream_t st);
+int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n, hipStream_t st);
+
+}  // namespace dg
+
+struct dg_handle {
+  int K = 0, N = 0, n = 0, n2 = 0, n3 = 0, node_type = 0;
+  dg_scheme sc{};
+  dg::Phys ph{};
+  hipStream_t stream = nullptr;
+  // device memory owned by the handle
+  double *d_Ja = nullptr, *d_sJ = nullptr, *d_fn = nullptr;
+  int32_t *d_nbr = nullptr;
+  dg::Tab *d_tab = nullptr;
+  double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
+  double *d_Gbar = nullptr;     // adjoint of the gradients (allocated on first VJP)
+  double *d_partial = nullptr;  // [K][8] per-element partial reductions
+  double *d_red = nullptr;      // [8] reduction result
+  dg::Tab tab{};
+  // optional per-kernel timing with HIP events (dg_profile)
+  bool prof = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  double prof_ms[4] = {0, 0, 0, 0};  // lift ms, lift launches, main ms, main launches
+  std::vector<double> x_nodes;  // solution-node coordinates (host), [K][3][n3]
+  std::string err;
+  dg::Geo geo() const {
+    dg::Geo g;
+    g.Ja = d_Ja; g.sJ = d_sJ; g.fn = d_fn; g.nbr = d_nbr; g.tab = d_tab; g.K = K;
+    return g;
+  }
+};

@@ -1,0 +1,685 @@
+// HIP kernels of the DGSEM operator for gfx950 (one workgroup per element).
+//
+// Paper map (Krais et al., FLEXI):
+//   k_lift  ... BR1 lifting of W = (u,v,w,T): Sec. 3.1, eq. discreteGradient, U* = mean of traces
+//   k_main  ... volume integral (weak eq. semiDiscrete / strong eq. semiDiscreteStrong / split
+//               flux differencing eq. semiDiscreteSplit), numerical surface flux (Riemann + BR1
+//               viscous mean), surface integral, -1/J scaling, and optionally the 2N-storage
+//               Runge-Kutta update of Sec. 4.4 fused into the epilogue.
+//   k_reduce .. per-element partial sums for the time step (eqs. CFLCondition, DFLCondition),
+//               quadrature integrals and the finiteness check, then one final pass.
+//
+// Layout: U[e][v][k][j][i] (i fastest), Ja[e][i*3+d][node], 1/J[e][node],
+// outward normals fn[e][side][d][a + n*b].  Each workgroup stages its element's state in
+// LDS; neighbour face values are read straight from global memory (for LGL nodes they are
+// volume nodes of the neighbour's face layer; for LG nodes they are interpolated on the fly).
+// Both elements sharing a face evaluate the same numerical flux with the master's normal and
+// the master's state as the left argument, so the two contributions cancel to rounding.
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+template <int N> struct Sz {
+  static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int NT = ((n3 + 63) / 64) * 64;  // threads per workgroup (one node each)
+};
+
+// node of the line through face point (a,b) of direction dn at position m along dn
+template <int n> __device__ __forceinline__ int line_node(int dn, int a, int b, int m) {
+  return dn == 0 ? (m + n * (a + n * b)) : (dn == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
+}
+
+// ----------------------------------------------------------------------------- physics
+struct Pr5 {
+  double rho, u, v, w, p;
+};
+
+__device__ __forceinline__ Pr5 to_prim(const double *U, double gm1) {
+  Pr5 P;
+  P.rho = U[0];
+  const double ir = 1.0 / U[0];
+  P.u = U[1] * ir; P.v = U[2] * ir; P.w = U[3] * ir;
+  P.p = gm1 * (U[4] - 0.5 * (U[1] * P.u + U[2] * P.v + U[3] * P.w));
+  return P;
+}
+
+// Euler flux along the (unnormalised) vector nv
+__device__ __forceinline__ void flux_c(const double *U, const Pr5 &P, const double *nv, double *F) {
+  const double un = P.u * nv[0] + P.v * nv[1] + P.w * nv[2];
+  F[0] = U[0] * un;
+  F[1] = U[1] * un + P.p * nv[0];
+  F[2] = U[2] * un + P.p * nv[1];
+  F[3] = U[3] * un + P.p * nv[2];
+  F[4] = (U[4] + P.p) * un;
+}
+
+// viscous flux along nv; g[d*4+c] = dW_c/dx_d with W = (u, v, w, T)
+__device__ __forceinline__ void flux_v(const Pr5 &P, const double *g, const Phys &ph, const double *nv, double *F) {
+  const double mu = ph.mu;
+  const double div = g[0] + g[5] + g[10];
+  // tau[a][b] = mu (du_a/dx_b + du_b/dx_a) - 2/3 mu div delta_ab ; du_a/dx_b = g[b*4+a]
+  const double t00 = mu * (2.0 * g[0] - (2.0 / 3.0) * div);
+  const double t11 = mu * (2.0 * g[5] - (2.0 / 3.0) * div);
+  const double t22 = mu * (2.0 * g[10] - (2.0 / 3.0) * div);
+  const double t01 = mu * (g[4] + g[1]);
+  const double t02 = mu * (g[8] + g[2]);
+  const double t12 = mu * (g[9] + g[6]);
+  F[0] = 0.0;
+  F[1] = t00 * nv[0] + t01 * nv[1] + t02 * nv[2];
+  F[2] = t01 * nv[0] + t11 * nv[1] + t12 * nv[2];
+  F[3] = t02 * nv[0] + t12 * nv[1] + t22 * nv[2];
+  // energy: (tau . u)_d + kappa dT/dx_d, contracted with nv
+  F[4] = F[1] * P.u + F[2] * P.v + F[3] * P.w + ph.kappa * (g[3] * nv[0] + g[7] * nv[1] + g[11] * nv[2]);
+}
+
+__device__ __forceinline__ double logmean(double a, double b) {
+  const double s = a + b;
+  const double d = a - b;
+  const double f = d / s;
+  const double u = f * f;
+  if (u < 1e-4) return s / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
+  return d / (log(a) - log(b));
+}
+
+// two-point flux along nv: vf 0 KEP (Pirozzoli), 1 EC (Chandrashekar), 2 central
+__device__ __forceinline__ void flux_2pt(int vf, const double *Ua, const Pr5 &A, const double *Ub, const Pr5 &B,
+                                         const double *nv, double gm1, double *F) {
+  if (vf == 2) {
+    double Fa[5], Fb[5];
+    flux_c(Ua, A, nv, Fa);
+    flux_c(Ub, B, nv, Fb);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (Fa[v] + Fb[v]);
+    return;
+  }
+  const double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
+  const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
+  if (vf == 0) {
+    const double rhom = 0.5 * (A.rho + B.rho);
+    const double pm = 0.5 * (A.p + B.p);
+    const double Hm = 0.5 * ((Ua[4] + A.p) / A.rho + (Ub[4] + B.p) / B.rho);
+    const double f0 = rhom * umn;
+    F[0] = f0;
+    F[1] = f0 * um + pm * nv[0];
+    F[2] = f0 * vm + pm * nv[1];
+    F[3] = f0 * wm + pm * nv[2];
+    F[4] = f0 * Hm;
+    return;
+  }
+  const double ba = 0.5 * A.rho / A.p, bb = 0.5 * B.rho / B.p;
+  const double rholn = logmean(A.rho, B.rho);
+  const double betaln = logmean(ba, bb);
+  const double phat = 0.25 * (A.rho + B.rho) / (0.5 * (ba + bb));
+  const double q2m = 0.5 * ((A.u * A.u + A.v * A.v + A.w * A.w) + (B.u * B.u + B.v * B.v + B.w * B.w));
+  const double f0 = rholn * umn;
+  F[0] = f0;
+  F[1] = f0 * um + phat * nv[0];
+  F[2] = f0 * vm + phat * nv[1];
+  F[3] = f0 * wm + phat * nv[2];
+  F[4] = f0 * (0.5 / (gm1 * betaln) - 0.5 * q2m) + um * F[1] + vm * F[2] + wm * F[3];
+}
+
+// Roe dissipation sum |lambda_k| alpha_k r_k, written without a rotated frame:
+// shear waves act on the tangential velocity jump du - (du.n) n.
+__device__ __forceinline__ void roe_diss(const double *UL, const Pr5 &L, const double *UR, const Pr5 &R,
+                                         const double *nh, double gm1, double *D) {
+  const double sL = sqrt(L.rho), sR = sqrt(R.rho);
+  const double is = 1.0 / (sL + sR);
+  const double u = (sL * L.u + sR * R.u) * is;
+  const double v = (sL * L.v + sR * R.v) * is;
+  const double w = (sL * L.w + sR * R.w) * is;
+  const double HL = (UL[4] + L.p) / L.rho, HR = (UR[4] + R.p) / R.rho;
+  const double H = (sL * HL + sR * HR) * is;
+  const double q2 = u * u + v * v + w * w;
+  const double c2 = gm1 * (H - 0.5 * q2);
+  const double c = sqrt(c2);
+  const double rt = sL * sR;
+  const double un = u * nh[0] + v * nh[1] + w * nh[2];
+  const double dr = R.rho - L.rho, dp = R.p - L.p;
+  const double du = R.u - L.u, dv = R.v - L.v, dw = R.w - L.w;
+  const double dun = du * nh[0] + dv * nh[1] + dw * nh[2];
+  const double ic2 = 1.0 / c2;
+  const double a1 = 0.5 * (dp - rt * c * dun) * ic2;
+  const double a5 = 0.5 * (dp + rt * c * dun) * ic2;
+  const double a2 = dr - dp * ic2;
+  const double l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
+  const double tu = du - dun * nh[0], tv = dv - dun * nh[1], tw = dw - dun * nh[2];
+  const double s1 = l1 * a1, s5 = l5 * a5, s2 = l2 * a2, ss = l2 * rt;
+  D[0] = s1 + s2 + s5;
+  D[1] = s1 * (u - c * nh[0]) + s2 * u + ss * tu + s5 * (u + c * nh[0]);
+  D[2] = s1 * (v - c * nh[1]) + s2 * v + ss * tv + s5 * (v + c * nh[1]);
+  D[3] = s1 * (w - c * nh[2]) + s2 * w + ss * tw + s5 * (w + c * nh[2]);
+  D[4] = s1 * (H - un * c) + s2 * 0.5 * q2 + ss * (u * tu + v * tv + w * tw) + s5 * (H + un * c);
+}
+
+// convective numerical flux f*(UL, UR, nh), nh a unit normal
+__device__ __forceinline__ void riemann(const Phys &ph, const double *UL, const double *UR, const double *nh,
+                                        double *F) {
+  const double gm1 = ph.gamma - 1.0;
+  const Pr5 L = to_prim(UL, gm1), R = to_prim(UR, gm1);
+  if (ph.rs >= 2) {
+    flux_2pt(ph.vf, UL, L, UR, R, nh, gm1, F);
+    if (ph.rs == 3) {
+      double D[5];
+      roe_diss(UL, L, UR, R, nh, gm1, D);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * D[v];
+    }
+    return;
+  }
+  double FL[5], FR[5];
+  flux_c(UL, L, nh, FL);
+  flux_c(UR, R, nh, FR);
+  if (ph.rs == 0) {
+    const double cL = sqrt(ph.gamma * L.p / L.rho), cR = sqrt(ph.gamma * R.p / R.rho);
+    const double unL = L.u * nh[0] + L.v * nh[1] + L.w * nh[2];
+    const double unR = R.u * nh[0] + R.v * nh[1] + R.w * nh[2];
+    const double lam = fmax(fabs(unL) + cL, fabs(unR) + cR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
+    return;
+  }
+  double D[5];
+  roe_diss(UL, L, UR, R, nh, gm1, D);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
+__device__ __forceinline__ void grad_prim_to_W(const double *U, double gm1, double Rg, double *W) {
+  const Pr5 P = to_prim(U, gm1);
+  W[0] = P.u; W[1] = P.v; W[2] = P.w; W[3] = P.p / (P.rho * Rg);
+}
+
+// ----------------------------------------------------------------------------- lifting
+template <int N, bool LGL>
+__global__ void __launch_bounds__(Sz<N>::NT) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+                                                    double *__restrict__ G) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  __shared__ double sW[4 * n3];
+  __shared__ double sJa[3 * n3];
+  __shared__ double sWs[6 * 4 * n2];
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const double gm1 = ph.gamma - 1.0;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += NT) sDh[c] = tb->Dh[c];
+  if (t < n) {
+    sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
+    slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
+  }
+  const double *Ue = U + (size_t)e * 5 * n3;
+  if (t < n3) {
+    double Uq[5], W[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + t];
+    grad_prim_to_W(Uq, gm1, ph.R, W);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sW[v * n3 + t] = W[v];
+  }
+  __syncthreads();
+  // W* = mean of the two traces on every face point of the element
+  for (int p = t; p < 6 * n2; p += NT) {
+    const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const bool plus = s & 1;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const double *Un = U + (size_t)nb * 5 * n3;
+    double WL[4], WR[4];
+    if (LGL) {
+      const int q = line_node<n>(dn, a, b, plus ? N : 0);
+      const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) WL[v] = sW[v * n3 + q];
+      double Uq[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
+      grad_prim_to_W(Uq, gm1, ph.R, WR);
+    } else {
+      const double *lo = sl + (plus ? n : 0), *ln = sl + (plus ? 0 : n);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { WL[v] = 0.0; WR[v] = 0.0; }
+      for (int m = 0; m < n; ++m) {
+        const int q = line_node<n>(dn, a, b, m);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) WL[v] += lo[m] * sW[v * n3 + q];
+        double Uq[5], W[4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + q];
+        grad_prim_to_W(Uq, gm1, ph.R, W);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) WR[v] += ln[m] * W[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sWs[(s * 4 + v) * n2 + ab] = 0.5 * (WL[v] + WR[v]);
+  }
+  double acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+  const int i = t % n, j = (t / n) % n, k = t / n2;
+  for (int dir = 0; dir < 3; ++dir) {
+    __syncthreads();
+    const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3;
+    for (int c = t; c < 3 * n3; c += NT) sJa[c] = Jd[c];
+    __syncthreads();
+    if (t < n3) {
+      const int id = dir == 0 ? i : (dir == 1 ? j : k);
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      for (int m = 0; m < n; ++m) {
+        const int qm = base + m * str;
+        const double Dh = sDh[id * n + m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double c1 = Dh * sJa[d * n3 + qm];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sW[v * n3 + qm];
+        }
+      }
+    }
+  }
+  if (t < n3) {
+    // surface: lhat(+-1) [W* nt_d] on each side
+    for (int s = 0; s < 6; ++s) {
+      const int dn = s >> 1;
+      const bool plus = s & 1;
+      const int id = dn == 0 ? i : (dn == 1 ? j : k);
+      const double lh = slh[(plus ? n : 0) + id];
+      if (LGL && lh == 0.0) continue;
+      const int a = dn == 0 ? j : i, b = dn == 2 ? j : k;
+      const int ab = a + n * b;
+      const double *nt = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double c1 = lh * nt[d * n2];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sWs[(s * 4 + v) * n2 + ab];
+      }
+    }
+    const double sj = g.sJ[(size_t)e * n3 + t];
+    double *Ge = G + (size_t)e * 12 * n3;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c] * sj;
+  }
+}
+
+// ----------------------------------------------------------------------------- operator
+// FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.
+template <int N, bool LGL, bool NS, int FORM, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double *__restrict__ U,
+                                                    const double *__restrict__ G, double *__restrict__ out,
+                                                    double *__restrict__ R, double ca, double cb, double dt) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  constexpr int NX = (FORM == 1) ? 8 : 5;
+  __shared__ double sU[5 * n3];
+  __shared__ double sX[NX * n3];
+  __shared__ double sF[6 * 5 * n2];
+  __shared__ double sD[n * n], sl[2 * n], slh[2 * n];
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const double gm1 = ph.gamma - 1.0;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += NT) sD[c] = (FORM == 0) ? tb->Dh[c] : tb->D[c];
+  if (t < n) {
+    sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
+    slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
+  }
+  const double *Ue = U + (size_t)e * 5 * n3;
+  const double *Ge = G + (size_t)e * 12 * n3;
+  double Uo[5], go[12];
+  if (t < n3) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Uo[v] = Ue[v * n3 + t];
+      sU[v * n3 + t] = Uo[v];
+    }
+    if (NS) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+    }
+  }
+  __syncthreads();
+  // numerical surface flux on the six faces, stored outward for this element
+  for (int p = t; p < 6 * n2; p += NT) {
+    const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const bool plus = s & 1;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const double *Un = U + (size_t)nb * 5 * n3;
+    const double *Gn = G + (size_t)nb * 12 * n3;
+    double Uw[5], Ux[5], gw[12], gx[12];  // w: this element's trace, x: neighbour's trace
+    if (LGL) {
+      const int q = line_node<n>(dn, a, b, plus ? N : 0);
+      const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = Un[v * n3 + qn]; }
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = Gn[c * n3 + qn]; }
+      }
+    } else {
+      const double *lo = sl + (plus ? n : 0), *ln = sl + (plus ? 0 : n);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { Uw[v] = 0.0; Ux[v] = 0.0; }
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { gw[c] = 0.0; gx[c] = 0.0; }
+      }
+      for (int m = 0; m < n; ++m) {
+        const int q = line_node<n>(dn, a, b, m);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) { Uw[v] += lo[m] * sU[v * n3 + q]; Ux[v] += ln[m] * Un[v * n3 + q]; }
+        if (NS) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) { gw[c] += lo[m] * Ge[c * n3 + q]; gx[c] += ln[m] * Gn[c * n3 + q]; }
+        }
+      }
+    }
+    // master = the element owning the face as its + side; its normal and state go first
+    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    const double sg = plus ? 1.0 : -1.0;
+    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
+    double F[5];
+    riemann(ph, UM, US, nh, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] *= sh;
+    if (NS) {
+      const double *gM = plus ? gw : gx, *gS = plus ? gx : gw;
+      double FvM[5], FvS[5];
+      const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
+      flux_v(PM, gM, ph, nt, FvM);
+      flux_v(PS, gS, ph, nt, FvS);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (FvM[v] + FvS[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sF[(s * 5 + v) * n2 + ab] = sg * F[v];
+  }
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int i = t % n, j = (t / n) % n, k = t / n2;
+  Pr5 Po;
+  if (t < n3) Po = to_prim(Uo, gm1);
+  for (int dir = 0; dir < 3; ++dir) {
+    double Fint[5], nv[3];
+    __syncthreads();
+    if (t < n3) {
+      const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3 + t;
+      nv[0] = Jd[0]; nv[1] = Jd[n3]; nv[2] = Jd[2 * n3];
+      double Fc[5], Fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      flux_c(Uo, Po, nv, Fc);
+      if (NS) flux_v(Po, go, ph, nv, Fv);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fint[v] = Fc[v] - Fv[v];
+      if (FORM == 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sX[d * n3 + t] = nv[d];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sX[(3 + v) * n3 + t] = Fv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sX[v * n3 + t] = Fint[v];
+      }
+    }
+    __syncthreads();
+    if (t < n3) {
+      const int id = dir == 0 ? i : (dir == 1 ? j : k);
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      for (int m = 0; m < n; ++m) {
+        const int qm = base + m * str;
+        const double Dm = sD[id * n + m];
+        if (FORM == 1) {
+          double Ub[5], F[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Ub[v] = sU[v * n3 + qm];
+          const Pr5 Pb = to_prim(Ub, gm1);
+          const double nm[3] = {0.5 * (nv[0] + sX[qm]), 0.5 * (nv[1] + sX[n3 + qm]), 0.5 * (nv[2] + sX[2 * n3 + qm])};
+          flux_2pt(ph.vf, Uo, Po, Ub, Pb, nm, gm1, F);
+          const double D2 = 2.0 * Dm;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] += D2 * F[v] - Dm * sX[(3 + v) * n3 + qm];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] += Dm * sX[v * n3 + qm];
+        }
+      }
+      // surface integral of the two faces of this direction
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int s = 2 * dir + sd;
+        const double lh = slh[(sd ? n : 0) + id];
+        if (LGL && lh == 0.0) continue;
+        const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
+        const int ab = a + n * b;
+        const double sg = sd ? 1.0 : -1.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          double pen = sF[(s * 5 + v) * n2 + ab];
+          if (FORM != 0) pen -= sg * Fint[v];
+          acc[v] += lh * pen;
+        }
+      }
+    }
+  }
+  if (t < n3) {
+    const double sj = g.sJ[(size_t)e * n3 + t];
+    if (MODE == 0) {
+      double *Oe = out + (size_t)e * 5 * n3;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Oe[v * n3 + t] = -acc[v] * sj;
+    } else {
+      double *Oe = out + (size_t)e * 5 * n3;
+      double *Re = R + (size_t)e * 5 * n3;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double ut = -acc[v] * sj;
+        const double r = ca * Re[v * n3 + t] + dt * ut;
+        Re[v * n3 + t] = r;
+        Oe[v * n3 + t] = Uo[v] + cb * r;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- reductions
+// partial[e][0..7]: timestep -> {max sum lambda_c, max sum lambda_v};
+// integrals -> {rho, m1, m2, m3, E, KE, entropy, min J}; finite -> {count of non-finite}
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_reduce(Geo g, Phys ph, int what, const double *__restrict__ U,
+                                                      double *__restrict__ partial) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  __shared__ double red[8][NT];
+  const int e = blockIdx.x, t = threadIdx.x;
+  const double gm1 = ph.gamma - 1.0;
+  double val[8];
+  const bool isMin[8] = {false, false, false, false, false, false, false, true};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) val[c] = 0.0;
+  if (what == RED_INTEGRALS) val[7] = 1e300;
+  if (t < n3) {
+    double Uq[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + t];
+    if (what == RED_FINITE) {
+      double bad = 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) bad += isfinite(Uq[v]) ? 0.0 : 1.0;
+      val[0] = bad;
+    } else {
+      const Pr5 P = to_prim(Uq, gm1);
+      const double sj = g.sJ[(size_t)e * n3 + t];
+      if (what == RED_TIMESTEP) {
+        const double c = sqrt(ph.gamma * P.p / P.rho);
+        double sc = 0.0, sv = 0.0;
+        for (int dir = 0; dir < 3; ++dir) {
+          const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3 + t;
+          const double a0 = Jd[0], a1 = Jd[n3], a2 = Jd[2 * n3];
+          const double nn = a0 * a0 + a1 * a1 + a2 * a2;
+          sc += (fabs(P.u * a0 + P.v * a1 + P.w * a2) + c * sqrt(nn)) * sj;
+          sv += fmax(4.0 / 3.0, ph.gamma / ph.Pr) * (ph.mu / P.rho) * nn * sj * sj;
+        }
+        val[0] = sc; val[1] = sv;
+      } else {
+        const int i = t % n, j = (t / n) % n, k = t / n2;
+        const double wq = g.tab->w[i] * g.tab->w[j] * g.tab->w[k] / sj;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) val[v] = wq * Uq[v];
+        val[5] = wq * 0.5 * (Uq[1] * P.u + Uq[2] * P.v + Uq[3] * P.w);
+        const double s = log(P.p) - ph.gamma * log(P.rho);
+        val[6] = wq * (-P.rho * s / gm1);
+        val[7] = 1.0 / sj;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) red[c][t] = val[c];
+  __syncthreads();
+  // fold the block onto its largest power-of-two prefix, then halve
+  constexpr int P = (NT & (NT - 1)) == 0 ? NT : (NT >= 512 ? 512 : 256);
+  for (int off = P; off > 0; off >>= 1) {
+    const int lim = (off == P) ? NT - P : off;
+    if (off < P || P < NT) {
+      if (t < lim) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const double x = red[c][t], y = red[c][t + off];
+          if (what == RED_TIMESTEP) red[c][t] = fmax(x, y);
+          else if (what == RED_INTEGRALS && isMin[c]) red[c][t] = fmin(x, y);
+          else red[c][t] = x + y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < 8) partial[(size_t)e * 8 + t] = red[t][0];
+}
+
+// ----------------------------------------------------------------------------- launchers
+#define DG_CHECK_LAUNCH()                                   \
+  do {                                                      \
+    hipError_t _e = hipGetLastError();                      \
+    if (_e != hipSuccess) return DG_ERR_HIP;                \
+  } while (0)
+
+template <int N, bool LGL, bool NS, int FORM>
+static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
+                         double a, double b, double dt, int mode, hipStream_t st) {
+  dim3 grid(g.K), block(Sz<N>::NT);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N, bool LGL, bool NS>
+static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, const double *G, double *out,
+                       double *R, double a, double b, double dt, int mode, hipStream_t st) {
+  if (form == DG_FORM_WEAK) return launch_main_t<N, LGL, NS, 0>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  if (!LGL) return DG_ERR_UNSUPPORTED;
+  if (form == DG_FORM_SPLIT) return launch_main_t<N, true, NS, 1>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  return launch_main_t<N, true, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
+}
+
+template <int N>
+int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double *G, hipStream_t st) {
+  dim3 grid(g.K), block(Sz<N>::NT);
+  if (lgl) hipLaunchKernelGGL((k_lift<N, true>), grid, block, 0, st, g, ph, U, G);
+  else hipLaunchKernelGGL((k_lift<N, false>), grid, block, 0, st, g, ph, U, G);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const double *U, const double *G,
+                double *out, double *R, double a, double b, double dt, int mode, hipStream_t st) {
+  const bool ns = (eqn == DG_NAVIER_STOKES);
+  if (lgl) {
+    if (ns) return launch_form<N, true, true>(g, ph, form, U, G, out, R, a, b, dt, mode, st);
+    return launch_form<N, true, false>(g, ph, form, U, G, out, R, a, b, dt, mode, st);
+  }
+  if (ns) return launch_form<N, false, true>(g, ph, form, U, G, out, R, a, b, dt, mode, st);
+  return launch_form<N, false, false>(g, ph, form, U, G, out, R, a, b, dt, mode, st);
+}
+
+template <int N>
+int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double, double *partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_reduce<N>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, what, U, partial);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+#ifndef DG_ONLY_N
+// one workgroup folds the per-element partials in a fixed order
+__global__ void __launch_bounds__(256) k_final_reduce(int what, const double *__restrict__ partial, int K,
+                                                      double *__restrict__ out) {
+  __shared__ double red[8][256];
+  const int t = threadIdx.x;
+  double val[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) val[c] = (what == RED_INTEGRALS && c == 7) ? 1e300 : 0.0;
+  for (int e = t; e < K; e += 256) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double x = partial[(size_t)e * 8 + c];
+      if (what == RED_TIMESTEP) val[c] = fmax(val[c], x);
+      else if (what == RED_INTEGRALS && c == 7) val[c] = fmin(val[c], x);
+      else val[c] += x;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) red[c][t] = val[c];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double x = red[c][t], y = red[c][t + off];
+        if (what == RED_TIMESTEP) red[c][t] = fmax(x, y);
+        else if (what == RED_INTEGRALS && c == 7) red[c][t] = fmin(x, y);
+        else red[c][t] = x + y;
+      }
+    }
+    __syncthreads();
+  }
+  if (t < 8) out[t] = red[t][0];
+}
+
+__global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, double alpha, double beta, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) y[i] = alpha * y[i] + beta * x[i];
+}
+
+int launch_final_reduce(int what, const double *partial, int K, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(256), 0, st, what, partial, K, out);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)blocks), dim3(256), 0, st, y, x, alpha, beta, n);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+#endif
+
+#ifdef DG_ONLY_N
+template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, const double *, double *, hipStream_t);
+template int launch_main<DG_ONLY_N>(const Geo &, const Phys &, bool, int, int, const double *, const double *,
+                                    double *, double *, double, double, double, int, hipStream_t);
+template int launch_reduce<DG_ONLY_N>(const Geo &, const Phys &, int, const double *, double, double *, hipStream_t);
+#endif
+
+}  // namespace dg

@@ -1,0 +1,272 @@
+"""Python binding of libdgsem (include/dgsem.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the operator runs in the
+library's HIP kernels.  Importing this module does not load the library; the first use
+does, and raises if ``libdgsem.so`` has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgsem.so")
+
+DG_OK = 0
+STATUS = {0: "DG_OK", -1: "DG_ERR_ARG", -2: "DG_ERR_MESH", -3: "DG_ERR_UNSUPPORTED", -4: "DG_ERR_HIP",
+          -5: "DG_ERR_NONFINITE", -6: "DG_ERR_OOM"}
+NODES = {"lg": 0, "lgl": 1}
+EQN = {"euler": 0, "ns": 1}
+FORM = {"weak": 0, "split": 1, "strong": 2}
+VF = {"kep": 0, "ec": 1, "central": 2}
+RS = {"llf": 0, "roe": 1, "volflux": 2, "volflux_roe": 3}
+
+EXPORTS = [
+    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
+    "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
+    "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
+    "dg_profile_read", "dg_host_geometry",
+]
+
+
+class DGError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_elems", ctypes.c_int32), ("n_geo", ctypes.c_int32), ("xgeo", ctypes.POINTER(ctypes.c_double)),
+                ("nbr_elem", ctypes.POINTER(ctypes.c_int32)), ("nbr_side", ctypes.POINTER(ctypes.c_int8)),
+                ("flip", ctypes.POINTER(ctypes.c_int8))]
+
+
+class _Scheme(ctypes.Structure):
+    _fields_ = [("eqn", ctypes.c_int32), ("form", ctypes.c_int32), ("volflux", ctypes.c_int32),
+                ("riemann", ctypes.c_int32), ("gamma", ctypes.c_double), ("R", ctypes.c_double),
+                ("mu", ctypes.c_double), ("Pr", ctypes.c_double)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load libdgsem.so (raises if it is missing: the GPU path has no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1910_02858_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.dg_nodes.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.dg_rk_coefficients.argtypes = [_D, _D, _D]
+        L.dg_init.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Scheme), _VP,
+                              ctypes.POINTER(_VP)]
+        L.dg_set_stream.argtypes = [_VP, _VP]
+        L.dg_rhs.argtypes = [_VP, _VP, _VP]
+        L.dg_rk_stage.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.dg_rhs_vjp.argtypes = [_VP, _VP, _VP, _VP]
+        L.dg_rk_stage_vjp.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.dg_timestep.argtypes = [_VP, _VP, ctypes.c_double, ctypes.c_double, _D]
+        L.dg_integrals.argtypes = [_VP, _VP, _D]
+        L.dg_check_finite.argtypes = [_VP, _VP]
+        L.dg_node_coords.argtypes = [_VP, _D]
+        L.dg_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64)]
+        L.dg_destroy.argtypes = [_VP]
+        L.dg_destroy.restype = None
+        L.dg_status_string.restype = ctypes.c_char_p
+        L.dg_status_string.argtypes = [ctypes.c_int]
+        L.dg_last_error.restype = ctypes.c_char_p
+        L.dg_last_error.argtypes = [_VP]
+        L.dg_host_geometry.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_int] + [_D] * 5
+        L.dg_profile.argtypes = [_VP, ctypes.c_int]
+        L.dg_profile_read.argtypes = [_VP, _D]
+        L.dg_batch_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
+        L.dg_batch_rk_stage.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, _D, _D]
+        L.dg_batch_destroy.argtypes = [_VP]
+        L.dg_batch_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def nodes(N: int, node_type: str):
+    x, w = np.zeros(N + 1), np.zeros(N + 1)
+    rc = lib().dg_nodes(N, NODES[node_type], _ptr(x), _ptr(w))
+    if rc:
+        raise DGError(rc, "dg_nodes")
+    return x, w
+
+
+def rk_coefficients():
+    a, b, c = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().dg_rk_coefficients(_ptr(a), _ptr(b), _ptr(c))
+    return a, b, c
+
+
+def host_geometry(xgeo, nbr, nside, N: int, node_type: str):
+    """dg_init's geometry and 1D tables computed on the host only (no device needed)."""
+    xgeo = np.ascontiguousarray(xgeo, np.float64)
+    nbr = np.ascontiguousarray(nbr, np.int32)
+    nside = np.ascontiguousarray(nside, np.int8)
+    K, n = xgeo.shape[0], N + 1
+    m = _Mesh(K, N, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+              nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), None)
+    Ja, J, fn = np.zeros((K, 9, n ** 3)), np.zeros((K, n ** 3)), np.zeros((K, 6, 3, n * n))
+    D, Dh = np.zeros((n, n)), np.zeros((n, n))
+    rc = lib().dg_host_geometry(ctypes.byref(m), N, NODES[node_type], _ptr(Ja), _ptr(J), _ptr(fn), _ptr(D), _ptr(Dh))
+    if rc:
+        raise DGError(rc, "dg_host_geometry")
+    return dict(Ja=Ja, J=J, fn=fn, D=D, Dhat=Dh)
+
+
+def _dptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("solution arrays must be contiguous float64 CUDA tensors")
+    return t.data_ptr()
+
+
+class DGSolver:
+    """One mesh + scheme on the GPU (a ``dg_handle``)."""
+
+    def __init__(self, xgeo, nbr, nside, N: int, nodes_: str, eqn="ns", form="split", volflux="kep",
+                 riemann="roe", gamma=1.4, R=1.0, mu=0.0, Pr=0.72, flip=None, stream=None):
+        import torch
+        self.torch = torch
+        xgeo = np.ascontiguousarray(xgeo, np.float64)
+        nbr = np.ascontiguousarray(nbr, np.int32)
+        nside = np.ascontiguousarray(nside, np.int8)
+        K = xgeo.shape[0]
+        if xgeo.shape != (K, 3, (N + 1) ** 3) or nbr.shape != (K, 6) or nside.shape != (K, 6):
+            raise ValueError("mesh arrays have inconsistent shapes")
+        flip_arr = None if flip is None else np.ascontiguousarray(flip, np.int8)
+        m = _Mesh(K, N, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                  nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                  None if flip_arr is None else flip_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+        sc = _Scheme(EQN[eqn], FORM[form], VF[volflux], RS[riemann], gamma, R, mu, Pr)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        h = _VP()
+        rc = lib().dg_init(ctypes.byref(m), N, NODES[nodes_], ctypes.byref(sc), _VP(st.cuda_stream), ctypes.byref(h))
+        if rc:
+            raise DGError(rc, "dg_init")
+        self.h = h
+        self.K, self.N, self.n3 = K, N, (N + 1) ** 3
+        self.shape = (K, 5, self.n3)
+        self.eqn, self.form, self.volflux, self.riemann = eqn, form, volflux, riemann
+        self.gamma, self.mu = gamma, mu
+        self._stream = st
+
+    @classmethod
+    def from_workload(cls, wl, xgeo, nbr, nside, **kw):
+        return cls(xgeo, nbr, nside, wl.N, wl.nodes, wl.eqn, wl.form, wl.volflux, wl.riemann, wl.gamma, wl.R, wl.mu,
+                   wl.Pr, **kw)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.dg_destroy(h)
+            self.h = None
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().dg_last_error(self.h)
+            raise DGError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _sync_stream(self):
+        st = self.torch.cuda.current_stream()
+        if st is not self._stream:
+            self._check(lib().dg_set_stream(self.h, _VP(st.cuda_stream)), "dg_set_stream")
+            self._stream = st
+
+    def empty(self):
+        return self.torch.empty(self.shape, dtype=self.torch.float64, device="cuda")
+
+    def rhs(self, U, out=None):
+        self._sync_stream()
+        out = self.empty() if out is None else out
+        self._check(lib().dg_rhs(self.h, _VP(_dptr(U)), _VP(_dptr(out))), "dg_rhs")
+        return out
+
+    def rk_stage(self, U_in, U_out, R, a, b, dt):
+        self._sync_stream()
+        self._check(lib().dg_rk_stage(self.h, _VP(_dptr(U_in)), _VP(_dptr(U_out)), _VP(_dptr(R)), float(a), float(b),
+                                      float(dt)), "dg_rk_stage")
+
+    def rhs_vjp(self, U, Ut_bar, out=None):
+        self._sync_stream()
+        out = self.empty() if out is None else out
+        self._check(lib().dg_rhs_vjp(self.h, _VP(_dptr(U)), _VP(_dptr(Ut_bar)), _VP(_dptr(out))), "dg_rhs_vjp")
+        return out
+
+    def rk_stage_vjp(self, U_in, U_bar, R_bar, a, b, dt):
+        self._sync_stream()
+        self._check(lib().dg_rk_stage_vjp(self.h, _VP(_dptr(U_in)), _VP(_dptr(U_bar)), _VP(_dptr(R_bar)), float(a),
+                                          float(b), float(dt)), "dg_rk_stage_vjp")
+
+    def timestep(self, U, cfl=0.9, dfl=0.9) -> float:
+        self._sync_stream()
+        out = ctypes.c_double()
+        self._check(lib().dg_timestep(self.h, _VP(_dptr(U)), float(cfl), float(dfl), ctypes.byref(out)), "dg_timestep")
+        return out.value
+
+    def integrals(self, U):
+        self._sync_stream()
+        out = np.zeros(8)
+        self._check(lib().dg_integrals(self.h, _VP(_dptr(U)), _ptr(out)), "dg_integrals")
+        return out
+
+    def check_finite(self, U) -> bool:
+        self._sync_stream()
+        rc = lib().dg_check_finite(self.h, _VP(_dptr(U)))
+        if rc == -5:
+            return False
+        self._check(rc, "dg_check_finite")
+        return True
+
+    def profile(self, enable: bool):
+        self._check(lib().dg_profile(self.h, int(enable)), "dg_profile")
+
+    def profile_read(self):
+        out = np.zeros(4)
+        self._check(lib().dg_profile_read(self.h, _ptr(out)), "dg_profile_read")
+        return {"lift_ms": out[0], "lift_launches": int(out[1]), "main_ms": out[2], "main_launches": int(out[3])}
+
+    def node_coords(self):
+        x = np.zeros((self.K, 3, self.n3))
+        self._check(lib().dg_node_coords(self.h, _ptr(x)), "dg_node_coords")
+        return x
+
+    def steps(self, U, nsteps: int, dt: float, R=None, spare=None):
+        """Advance ``nsteps`` full RK steps (5 stages each) with ping-pong buffers; returns the new U."""
+        a, b, _ = rk_coefficients()
+        R = self.torch.zeros_like(U) if R is None else R
+        cur = U
+        nxt = self.empty() if spare is None else spare
+        for _ in range(nsteps):
+            for s in range(5):
+                self.rk_stage(cur, nxt, R, a[s], b[s], dt)
+                cur, nxt = nxt, cur
+        return cur
+
+
+def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[bool] = None):
+    """Mesh, solver and initial state of workload ``wl`` using the library's own LGL nodes."""
+    from . import inputs
+    import torch
+    k = wl.K1 if K1 is None else K1
+    cv = wl.curved if curved is None else curved
+    lgl, _ = nodes(wl.N, "lgl")
+    X = inputs.lattice_points(lgl, k, k, k)
+    xgeo = inputs.warp_sine(X) if cv else X
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    S = DGSolver.from_workload(wl, xgeo, nbr, side, stream=stream)
+    U0 = inputs.initial_state(wl, S.node_coords())
+    return S, torch.from_numpy(np.ascontiguousarray(U0)).cuda()
