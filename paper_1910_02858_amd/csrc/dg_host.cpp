@@ -17,7 +17,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <cstdlib>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dg_internal.h"
@@ -203,9 +205,18 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
   G.sJ.assign((size_t)K * n3, 0.0);
   G.xs.assign((size_t)K * 3 * n3, 0.0);
   G.fn.assign((size_t)K * 6 * 3 * n2, 0.0);
+  // elements are independent: split them over host threads
+  unsigned nthr = std::thread::hardware_concurrency();
+  if (const char *env = std::getenv("OMP_NUM_THREADS")) nthr = (unsigned)std::max(1, std::atoi(env));
+  nthr = std::max(1u, std::min(nthr, 32u));
+  if ((size_t)K < 4 * (size_t)nthr) nthr = 1;
+  std::vector<int> bad(nthr, -1), badq(nthr, 0);
+  std::vector<double> badv(nthr, 0.0);
+  auto work = [&](unsigned tid) {
   std::vector<xf> X(3 * n3), dx(9 * n3), prod(3 * n3), c1(n3), c2(n3), JaL(9 * n3), Jas(9 * n3), t1(n3), t2(n3),
       xs(3 * n3), jac(9 * n3);
-  for (int e = 0; e < K; ++e) {
+  const int e0 = (int)((size_t)K * tid / nthr), e1 = (int)((size_t)K * (tid + 1) / nthr);
+  for (int e = e0; e < e1; ++e) {
     // work relative to the element centroid; the curl form is translation invariant and the
     // shift removes the cancellation between the two products of each curl component
     xf c0[3];
@@ -257,10 +268,8 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
       const xf a20 = jac[6 * n3 + q], a21 = jac[7 * n3 + q], a22 = jac[8 * n3 + q];
       const xf det = a00 * (a11 * a22 - a12 * a21) + a01 * (a12 * a20 - a10 * a22) + a02 * (a10 * a21 - a11 * a20);
       if (!(det > 0.0L) || !std::isfinite((double)det)) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "element %d node %d: Jacobian %.3Le is not positive", e, q, det);
-        msg = buf;
-        return DG_ERR_MESH;
+        if (bad[tid] < 0) { bad[tid] = e; badq[tid] = q; badv[tid] = (double)det; }
+        return;
       }
       G.J[(size_t)e * n3 + q] = (double)det;
       G.sJ[(size_t)e * n3 + q] = (double)(1.0L / det);
@@ -280,6 +289,21 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
           }
     }
   }
+  };
+  if (nthr == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nthr; ++t) pool.emplace_back(work, t);
+    for (auto &th : pool) th.join();
+  }
+  for (unsigned t = 0; t < nthr; ++t)
+    if (bad[t] >= 0) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "element %d node %d: Jacobian %.3e is not positive", bad[t], badq[t], badv[t]);
+      msg = buf;
+      return DG_ERR_MESH;
+    }
   // slaves: negated normal of the master's matching side
   for (int e = 0; e < K; ++e)
     for (int d = 0; d < 3; ++d) {
