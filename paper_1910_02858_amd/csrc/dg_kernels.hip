@@ -488,6 +488,322 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   }
 }
 
+// ----------------------------------------------------------------------------- split form, LGL
+// Reciprocal from v_rcp_f64 refined by two Newton steps (error well below one ulp of the
+// quantities it feeds); used for the two-point fluxes, where IEEE division dominated.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// logarithmic mean (a-b)/(ln a - ln b) and its reciprocal, from one shared reciprocal of
+// a+b; a 4-term series when ((a-b)/(a+b))^2 < 1e-4, the logarithms otherwise
+__device__ __forceinline__ double lnmean(double a, double b) {
+  const double s = a + b, d = a - b;
+  const double f = d * frcp(s);
+  const double u = f * f;
+  if (u < 1e-4) return s * frcp(2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
+  return d / (log(a) - log(b));
+}
+__device__ __forceinline__ double inv_lnmean(double a, double b) {
+  const double s = a + b, d = a - b;
+  const double is = frcp(s);
+  const double f = d * is;
+  const double u = f * f;
+  if (u < 1e-4) return (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)))) * is;
+  return (log(a) - log(b)) / d;
+}
+
+// per-node state of the two-point fluxes: rho, u, v, w, beta = rho/(2p) (EC) or p (KEP, central)
+struct PS {
+  double r, u, v, w, b;
+};
+
+// two-point flux along nv between states A and B (VF 0 KEP, 1 EC, 2 central)
+template <int VF>
+__device__ __forceinline__ void pair_flux(const PS &A, const PS &B, const double *nv, double gm1, double *F) {
+  const double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
+  if (VF == 1) {
+    const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
+    const double rln = lnmean(A.r, B.r);
+    const double sb = A.b + B.b;
+    const double isb = frcp(sb);
+    const double db = A.b - B.b;
+    const double fb = db * isb;
+    const double ub = fb * fb;
+    const double iblm = (ub < 1e-4) ? (2.0 + ub * (2.0 / 3.0 + ub * (2.0 / 5.0 + ub * (2.0 / 7.0)))) * isb
+                                    : (log(A.b) - log(B.b)) / db;
+    const double phat = 0.5 * (A.r + B.r) * isb;  // {rho} / (2 {beta})
+    const double q2m = 0.5 * ((A.u * A.u + A.v * A.v + A.w * A.w) + (B.u * B.u + B.v * B.v + B.w * B.w));
+    const double f0 = rln * umn;
+    F[0] = f0;
+    F[1] = f0 * um + phat * nv[0];
+    F[2] = f0 * vm + phat * nv[1];
+    F[3] = f0 * wm + phat * nv[2];
+    F[4] = f0 * (0.5 / gm1 * iblm - 0.5 * q2m) + um * F[1] + vm * F[2] + wm * F[3];
+  } else if (VF == 0) {
+    // kinetic-energy preserving: {rho}{u.n}, {u} F_rho + {p} n, F_rho {H}, H = (E+p)/rho
+    const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
+    const double pm = 0.5 * (A.b + B.b);
+    const double g1 = 1.0 / gm1 + 1.0;  // gamma/(gamma-1)
+    const double Ha = g1 * A.b / A.r + 0.5 * (A.u * A.u + A.v * A.v + A.w * A.w);
+    const double Hb = g1 * B.b / B.r + 0.5 * (B.u * B.u + B.v * B.v + B.w * B.w);
+    const double f0 = 0.5 * (A.r + B.r) * umn;
+    F[0] = f0;
+    F[1] = f0 * um + pm * nv[0];
+    F[2] = f0 * vm + pm * nv[1];
+    F[3] = f0 * wm + pm * nv[2];
+    F[4] = f0 * 0.5 * (Ha + Hb);
+  } else {
+    // mean of the two Euler fluxes
+    const double una = A.u * nv[0] + A.v * nv[1] + A.w * nv[2];
+    const double unb = B.u * nv[0] + B.v * nv[1] + B.w * nv[2];
+    const double g1 = 1.0 / gm1 + 1.0;
+    const double Ha = g1 * A.b / A.r + 0.5 * (A.u * A.u + A.v * A.v + A.w * A.w);
+    const double Hb = g1 * B.b / B.r + 0.5 * (B.u * B.u + B.v * B.v + B.w * B.w);
+    F[0] = 0.5 * (A.r * una + B.r * unb);
+    F[1] = 0.5 * (A.r * A.u * una + B.r * B.u * unb + (A.b + B.b) * nv[0]);
+    F[2] = 0.5 * (A.r * A.v * una + B.r * B.v * unb + (A.b + B.b) * nv[1]);
+    F[3] = 0.5 * (A.r * A.w * una + B.r * B.w * unb + (A.b + B.b) * nv[2]);
+    F[4] = 0.5 * (A.r * Ha * una + B.r * Hb * unb);
+  }
+}
+
+// element handled by workgroup b: the launch hands each XCD (workgroups are dealt to the
+// 8 XCDs round-robin) one contiguous range of elements, so face neighbours along the first
+// two lattice directions are usually read from the same L2
+__device__ __forceinline__ int xcd_element(int b, int K) {
+  const int per = (K + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Split-form operator on LGL nodes (eq. semiDiscreteSplit): every unordered pair of nodes on a
+// line is evaluated once; the pair's contribution to the other node goes through an LDS
+// accumulator.  Viscous part in strong form, surface penalty f* s - F_int.N, -1/J, optional RK.
+template <int N, bool NS, int VF, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) k_split(Geo g, Phys ph, const double *__restrict__ U,
+                                                     const double *__restrict__ G, double *__restrict__ out,
+                                                     double *__restrict__ R, double ca, double cb, double dt) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  constexpr int NP = (5 * n3 > 30 * n2) ? 5 * n3 : 30 * n2;  // partner accumulator / face fluxes
+  __shared__ double sS[5 * n3];   // rho, u, v, w, beta|p
+  __shared__ double sJ[3 * n3];   // Ja^dir_d of the current direction
+  __shared__ double sV[4 * n3];   // contravariant viscous flux of the current direction (momentum, energy)
+  __shared__ double sP[NP];
+  __shared__ double sD[n * n], slh[2 * n];
+  const int e = xcd_element(blockIdx.x, g.K);
+  if (e >= g.K) return;
+  const int t = threadIdx.x;
+  const bool act = t < n3;
+  const double gm1 = ph.gamma - 1.0;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += NT) sD[c] = tb->D[c];
+  if (t < n) { slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t]; }
+  const double *Ue = U + (size_t)e * 5 * n3;
+  const double *Ge = G + (size_t)e * 12 * n3;
+  const double *Jae = g.Ja + (size_t)e * 9 * n3;
+  // numerical surface flux on the six faces, stored outward for this element
+  for (int q = t; q < 6 * n2; q += NT) {
+    const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const bool plus = s & 1;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const double *Un = U + (size_t)nb * 5 * n3;
+    const double *Gn = G + (size_t)nb * 12 * n3;
+    const int qo = line_node<n>(dn, a, b, plus ? N : 0);
+    const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+    double Uw[5], Ux[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = Un[v * n3 + qn]; }
+    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    const double sg = plus ? 1.0 : -1.0;
+    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
+    double F[5];
+    riemann(ph, UM, US, nh, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] *= sh;
+    if (NS) {
+      double gw[12], gx[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + qo]; gx[c] = Gn[c * n3 + qn]; }
+      const double *gM = plus ? gw : gx, *gS = plus ? gx : gw;
+      double FvM[5], FvS[5];
+      const Pr5 PM = to_prim(UM, gm1), PS_ = to_prim(US, gm1);
+      flux_v(PM, gM, ph, nt, FvM);
+      flux_v(PS_, gS, ph, nt, FvS);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (FvM[v] + FvS[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = sg * F[v];
+  }
+  __syncthreads();
+  double Uo[5];
+  PS o;
+  double p = 0.0;
+  double FvD[3][4];  // contravariant viscous flux per direction (components 1..4)
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
+    const Pr5 P = to_prim(Uo, gm1);
+    p = P.p;
+    o.r = P.rho; o.u = P.u; o.v = P.v; o.w = P.w;
+    o.b = (VF == 1) ? 0.5 * P.rho / P.p : P.p;
+    sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w; sS[4 * n3 + t] = o.b;
+    if (NS) {
+      double go[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double nv[3] = {Jae[(d * 3) * n3 + t], Jae[(d * 3 + 1) * n3 + t], Jae[(d * 3 + 2) * n3 + t]};
+        double F[5];
+        flux_v(P, go, ph, nv, F);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) FvD[d][c] = F[1 + c];
+      }
+    }
+  }
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int id3[3] = {t % n, (t / n) % n, t / n2};
+  if (act) {
+    // surface penalty [f* s - F_int . N_out] lhat(+-1) on the faces through this node
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      const int id = id3[dir];
+      if (id != 0 && id != N) continue;
+      const int sd = (id == N) ? 1 : 0;
+      const int s = 2 * dir + sd;
+      const double lh = slh[(sd ? n : 0) + id];
+      const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+      const int ab = a + n * b;
+      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      const Pr5 P = {o.r, o.u, o.v, o.w, p};
+      double Fc[5];
+      flux_c(Uo, P, nv, Fc);
+      const double sg = sd ? 1.0 : -1.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double fint = Fc[v];
+        if (NS && v > 0) fint -= FvD[dir][v - 1];
+        acc[v] += lh * (sP[(s * 5 + v) * n2 + ab] - sg * fint);
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sP[v * n3 + t] = 0.0;
+  }
+  for (int dir = 0; dir < 3; ++dir) {
+    double nvo[3];
+    if (act) {
+      nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
+      sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sV[c * n3 + t] = FvD[dir][c];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int id = id3[dir];
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      // pairs (id, id+s mod n), s = 1 .. (n-1)/2: each unordered pair once, both nodes updated
+#pragma unroll 1
+      for (int sft = 1; sft <= (n - 1) / 2; ++sft) {
+        int jp = id + sft;
+        if (jp >= n) jp -= n;
+        const int qp = base + jp * str;
+        PS bq;
+        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
+        const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]), 0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+        double F[5];
+        pair_flux<VF>(o, bq, nm, gm1, F);
+        const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
+        const double Dij2 = 2.0 * Dij, Dji2 = 2.0 * Dji;
+        acc[0] += Dij2 * F[0];
+        atomicAdd(&sP[qp], Dji2 * F[0]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double own = Dij2 * F[1 + c], oth = Dji2 * F[1 + c];
+          if (NS) {
+            own -= Dij * sV[c * n3 + qp];
+            oth -= Dji * FvD[dir][c];
+          }
+          acc[1 + c] += own;
+          atomicAdd(&sP[(1 + c) * n3 + qp], oth);
+        }
+      }
+      if ((n & 1) == 0) {
+        // s = n/2 pairs each other twice: each side takes only its own share
+        int jp = id + n / 2;
+        if (jp >= n) jp -= n;
+        const int qp = base + jp * str;
+        PS bq;
+        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
+        const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]), 0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+        double F[5];
+        pair_flux<VF>(o, bq, nm, gm1, F);
+        const double Dij = sD[id * n + jp];
+        acc[0] += 2.0 * Dij * F[0];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double own = 2.0 * Dij * F[1 + c];
+          if (NS) own -= Dij * sV[c * n3 + qp];
+          acc[1 + c] += own;
+        }
+      }
+      // diagonal: F#(U,U) = F(U) . Ja (non-zero D_ii only on the end nodes of LGL lines)
+      const double Dii = sD[id * n + id];
+      if (Dii != 0.0) {
+        const Pr5 P = {o.r, o.u, o.v, o.w, p};
+        double Fc[5];
+        flux_c(Uo, P, nvo, Fc);
+        acc[0] += 2.0 * Dii * Fc[0];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double own = 2.0 * Dii * Fc[1 + c];
+          if (NS) own -= Dii * FvD[dir][c];
+          acc[1 + c] += own;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        acc[v] += sP[v * n3 + t];
+        sP[v * n3 + t] = 0.0;
+      }
+    }
+  }
+  if (act) {
+    const double sj = g.sJ[(size_t)e * n3 + t];
+    double *Oe = out + (size_t)e * 5 * n3;
+    if (MODE == 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Oe[v * n3 + t] = -acc[v] * sj;
+    } else {
+      double *Re = R + (size_t)e * 5 * n3;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double r = ca * Re[v * n3 + t] + dt * (-acc[v] * sj);
+        Re[v * n3 + t] = r;
+        Oe[v * n3 + t] = Uo[v] + cb * r;
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------- reductions
 // partial[e][0..7]: timestep -> {max sum lambda_c, max sum lambda_v};
 // integrals -> {rho, m1, m2, m3, E, KE, entropy, min J}; finite -> {count of non-finite}
@@ -581,12 +897,28 @@ static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const do
   return DG_OK;
 }
 
+template <int N, bool NS, int VF>
+static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
+                          double a, double b, double dt, int mode, hipStream_t st) {
+  dim3 grid(8 * ((g.K + 7) / 8)), block(Sz<N>::NT);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_split<N, NS, VF, 0>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else
+    hipLaunchKernelGGL((k_split<N, NS, VF, 1>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
 template <int N, bool LGL, bool NS>
 static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, const double *G, double *out,
                        double *R, double a, double b, double dt, int mode, hipStream_t st) {
   if (form == DG_FORM_WEAK) return launch_main_t<N, LGL, NS, 0>(g, ph, U, G, out, R, a, b, dt, mode, st);
   if (!LGL) return DG_ERR_UNSUPPORTED;
-  if (form == DG_FORM_SPLIT) return launch_main_t<N, true, NS, 1>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  if (form == DG_FORM_SPLIT) {
+    if (ph.vf == DG_VF_EC) return launch_split_t<N, NS, 1>(g, ph, U, G, out, R, a, b, dt, mode, st);
+    if (ph.vf == DG_VF_KEP) return launch_split_t<N, NS, 0>(g, ph, U, G, out, R, a, b, dt, mode, st);
+    return launch_split_t<N, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  }
   return launch_main_t<N, true, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
 }
 
