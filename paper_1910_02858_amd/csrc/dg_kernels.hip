@@ -19,6 +19,12 @@
 
 #include "dg_internal.h"
 
+// minimum waves per SIMD requested for the split-form kernel: 4 fits two 512-thread
+// workgroups per CU at N=7 (128 VGPRs), measured faster than 2-3 waves despite a small spill
+#ifndef DG_SPLIT_MINB
+#define DG_SPLIT_MINB 4
+#endif
+
 namespace dg {
 
 template <int N> struct Sz {
@@ -190,6 +196,14 @@ __device__ __forceinline__ void riemann(const Phys &ph, const double *UL, const 
 __device__ __forceinline__ void grad_prim_to_W(const double *U, double gm1, double Rg, double *W) {
   const Pr5 P = to_prim(U, gm1);
   W[0] = P.u; W[1] = P.v; W[2] = P.w; W[3] = P.p / (P.rho * Rg);
+}
+
+// element handled by workgroup b: the launch hands each XCD (workgroups are dealt to the
+// 8 XCDs round-robin) one contiguous range of elements, so face neighbours along the first
+// two lattice directions are usually read from the same L2
+__device__ __forceinline__ int xcd_element(int b, int K) {
+  const int per = (K + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
 }
 
 // ----------------------------------------------------------------------------- lifting
@@ -572,19 +586,11 @@ __device__ __forceinline__ void pair_flux(const PS &A, const PS &B, const double
   }
 }
 
-// element handled by workgroup b: the launch hands each XCD (workgroups are dealt to the
-// 8 XCDs round-robin) one contiguous range of elements, so face neighbours along the first
-// two lattice directions are usually read from the same L2
-__device__ __forceinline__ int xcd_element(int b, int K) {
-  const int per = (K + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
 // Split-form operator on LGL nodes (eq. semiDiscreteSplit): every unordered pair of nodes on a
 // line is evaluated once; the pair's contribution to the other node goes through an LDS
 // accumulator.  Viscous part in strong form, surface penalty f* s - F_int.N, -1/J, optional RK.
 template <int N, bool NS, int VF, int MODE>
-__global__ void __launch_bounds__(Sz<N>::NT) k_split(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
   using S = Sz<N>;
