@@ -132,6 +132,10 @@ int dg_integrals(dg_handle *h, const double *U, double out[8]);
 /* DG_ERR_NONFINITE if any entry of U is NaN or Inf, DG_OK otherwise.  Synchronous. */
 int dg_check_finite(dg_handle *h, const double *U);
 
+/* Quadrature weight of every node, J w_i w_j w_k (the diagonal mass matrix of Sec. 3.1,
+ * eq. discTemp), written to the DEVICE array out [K][n^3]. */
+int dg_mass_weights(dg_handle *h, double *out);
+
 /* Physical coordinates of the solution nodes, HOST out [K][3][n^3].  Synchronous. */
 int dg_node_coords(dg_handle *h, double *x_host);
 

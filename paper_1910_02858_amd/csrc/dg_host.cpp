@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <cstddef>
 #include <cstdlib>
 #include <string>
 #include <thread>
@@ -613,6 +614,16 @@ int dg_check_finite(dg_handle *h, const double *U) {
   return DG_OK;
 }
 
+int dg_mass_weights(dg_handle *h, double *out) {
+  if (!h) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, out, "out");
+  if (rc) return rc;
+  const double *w = reinterpret_cast<const double *>(reinterpret_cast<const char *>(h->d_tab) + offsetof(dg::Tab, w));
+  rc = dg::launch_mass(h->d_sJ, w, h->n, (size_t)h->K * h->n3, out, h->stream);
+  if (rc) return fail(h, rc, "launch of the mass-weight kernel failed");
+  return DG_OK;
+}
+
 int dg_node_coords(dg_handle *h, double *x_host) {
   if (!h || !x_host) return DG_ERR_ARG;
   std::memcpy(x_host, h->x_nodes.data(), h->x_nodes.size() * sizeof(double));
@@ -646,16 +657,68 @@ void dg_destroy(dg_handle *h) {
   delete h;
 }
 
+namespace {
+int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, double scale, int accumulate) {
+  if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
+    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
+  if (h->sc.volflux == DG_VF_EC)
+    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the KEP and central volume fluxes");
+  const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
+  if (ns && !h->d_Gbar) {
+    int rc = dev_alloc(&h->d_Gbar, (size_t)h->K * 12 * h->n3);
+    if (rc) return fail(h, rc, "allocation of the gradient adjoint failed");
+  }
+  if (ns) {
+    int rc = lift_dispatch(h, U);  // forward lifting at U (the reverse needs G)
+    if (rc) return fail(h, rc, "launch of the lifting kernel failed");
+  }
+  const dg::Geo g = h->geo();
+  int rc;
+  switch (h->N) {
+#define DG_CASE(NN) \
+  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, h->d_G, h->d_Gbar, Utb, Ub, scale, accumulate, h->stream); break;
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: rc = DG_ERR_UNSUPPORTED;
+  }
+  if (rc) return fail(h, rc, rc == DG_ERR_UNSUPPORTED ? "vector-Jacobian product not built for this degree"
+                                                      : "launch of the vector-Jacobian kernels failed");
+  return DG_OK;
+}
+}  // namespace
+
 int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_bar) {
   if (!h) return DG_ERR_ARG;
-  (void)U; (void)Ut_bar; (void)U_bar;
-  return fail(h, DG_ERR_UNSUPPORTED, "vector-Jacobian product not built");
+  int rc = check_solution_ptr(h, U, "U");
+  if (!rc) rc = check_solution_ptr(h, Ut_bar, "Ut_bar");
+  if (!rc) rc = check_solution_ptr(h, U_bar, "U_bar");
+  if (rc) return rc;
+  const size_t bytes = (size_t)h->K * 5 * h->n3 * sizeof(double);
+  if (overlap(U, U_bar, bytes) || overlap(Ut_bar, U_bar, bytes))
+    return fail(h, DG_ERR_ARG, "U_bar must not overlap U or Ut_bar");
+  return vjp_dispatch(h, U, Ut_bar, U_bar, 1.0, 0);
 }
 
 int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt) {
   if (!h) return DG_ERR_ARG;
-  (void)U_in; (void)U_bar; (void)R_bar; (void)a; (void)b; (void)dt;
-  return fail(h, DG_ERR_UNSUPPORTED, "vector-Jacobian product not built");
+  int rc = check_solution_ptr(h, U_in, "U_in");
+  if (!rc) rc = check_solution_ptr(h, U_bar, "U_bar");
+  if (!rc) rc = check_solution_ptr(h, R_bar, "R_bar");
+  if (rc) return rc;
+  const size_t n = (size_t)h->K * 5 * h->n3, bytes = n * sizeof(double);
+  if (overlap(U_in, U_bar, bytes) || overlap(U_in, R_bar, bytes) || overlap(U_bar, R_bar, bytes))
+    return fail(h, DG_ERR_ARG, "U_in, U_bar and R_bar must be three distinct buffers");
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite coefficient");
+  // R_bar <- R_bar + b U_bar
+  rc = dg::launch_axpby(R_bar, U_bar, 1.0, b, n, h->stream);
+  if (rc) return fail(h, rc, "launch failed");
+  // U_bar <- U_bar + dt (dL/dU)^T R_bar
+  rc = vjp_dispatch(h, U_in, R_bar, U_bar, dt, 1);
+  if (rc) return rc;
+  // R_bar <- a R_bar
+  rc = dg::launch_axpby(R_bar, R_bar, a, 0.0, n, h->stream);
+  if (rc) return fail(h, rc, "launch failed");
+  return DG_OK;
 }
 
 int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {

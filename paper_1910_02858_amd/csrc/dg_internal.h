@@ -54,6 +54,7 @@ enum { RED_TIMESTEP = 0, RED_INTEGRALS = 1, RED_FINITE = 2 };
 
 int launch_final_reduce(int what, const double *partial, int K, double *out, hipStream_t st);
 int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n, hipStream_t st);
+int launch_mass(const double *sJ, const double *w, int n, size_t total, double *out, hipStream_t st);
 
 }  // namespace dg
 

@@ -703,11 +703,6 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       }
     }
   }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sP[v * n3 + t] = 0.0;
-  }
   for (int dir = 0; dir < 3; ++dir) {
     double nvo[3];
     if (act) {
@@ -719,37 +714,48 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       }
     }
     __syncthreads();
-    if (act) {
-      const int id = id3[dir];
+    {
+      const int id = act ? id3[dir] : 0;
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
       const int base = t - id * str;
       // pairs (id, id+s mod n), s = 1 .. (n-1)/2: each unordered pair once, both nodes updated
 #pragma unroll 1
       for (int sft = 1; sft <= (n - 1) / 2; ++sft) {
-        int jp = id + sft;
-        if (jp >= n) jp -= n;
-        const int qp = base + jp * str;
-        PS bq;
-        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
-        const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]), 0.5 * (nvo[2] + sJ[2 * n3 + qp])};
-        double F[5];
-        pair_flux<VF>(o, bq, nm, gm1, F);
-        const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
-        const double Dij2 = 2.0 * Dij, Dji2 = 2.0 * Dji;
-        acc[0] += Dij2 * F[0];
-        atomicAdd(&sP[qp], Dji2 * F[0]);
+        // barriers stay in uniform control flow: only the work is guarded
+        if (act) {
+          int jp = id + sft;
+          if (jp >= n) jp -= n;
+          const int qp = base + jp * str;
+          PS bq;
+          bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
+          const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]),
+                                0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+          double F[5];
+          pair_flux<VF>(o, bq, nm, gm1, F);
+          const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
+          const double Dij2 = 2.0 * Dij, Dji2 = 2.0 * Dji;
+          acc[0] += Dij2 * F[0];
+          sP[qp] = Dji2 * F[0];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double own = Dij2 * F[1 + c], oth = Dji2 * F[1 + c];
-          if (NS) {
-            own -= Dij * sV[c * n3 + qp];
-            oth -= Dji * FvD[dir][c];
+          for (int c = 0; c < 4; ++c) {
+            double own = Dij2 * F[1 + c], oth = Dji2 * F[1 + c];
+            if (NS) {
+              own -= Dij * sV[c * n3 + qp];
+              oth -= Dji * FvD[dir][c];
+            }
+            acc[1 + c] += own;
+            sP[(1 + c) * n3 + qp] = oth;
           }
-          acc[1 + c] += own;
-          atomicAdd(&sP[(1 + c) * n3 + qp], oth);
         }
+        // every node receives exactly one partner share per round: collect it in a fixed order
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] += sP[v * n3 + t];
+        }
+        __syncthreads();
       }
-      if ((n & 1) == 0) {
+      if (act && (n & 1) == 0) {
         // s = n/2 pairs each other twice: each side takes only its own share
         int jp = id + n / 2;
         if (jp >= n) jp -= n;
@@ -769,7 +775,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
         }
       }
       // diagonal: F#(U,U) = F(U) . Ja (non-zero D_ii only on the end nodes of LGL lines)
-      const double Dii = sD[id * n + id];
+      const double Dii = act ? sD[id * n + id] : 0.0;
       if (Dii != 0.0) {
         const Pr5 P = {o.r, o.u, o.v, o.w, p};
         double Fc[5];
@@ -783,14 +789,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
         }
       }
     }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        acc[v] += sP[v * n3 + t];
-        sP[v * n3 + t] = 0.0;
-      }
-    }
+    __syncthreads();  // sJ / sV / sS reads of this direction are done before the next one is staged
   }
   if (act) {
     const double sj = g.sJ[(size_t)e * n3 + t];
@@ -992,6 +991,19 @@ __global__ void __launch_bounds__(256) k_final_reduce(int what, const double *__
   if (t < 8) out[t] = red[t][0];
 }
 
+// quadrature weight of every node: J w_i w_j w_k
+__global__ void k_mass(const double *__restrict__ sJ, const double *__restrict__ w, int n, size_t total,
+                       double *__restrict__ out) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int n3 = n * n * n;
+  for (; q < total; q += stride) {
+    const int node = (int)(q % n3);
+    const int i = node % n, j = (node / n) % n, k = node / (n * n);
+    out[q] = w[i] * w[j] * w[k] / sJ[q];
+  }
+}
+
 __global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, double alpha, double beta, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1000,6 +1012,14 @@ __global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, do
 
 int launch_final_reduce(int what, const double *partial, int K, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(256), 0, st, what, partial, K, out);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+int launch_mass(const double *sJ, const double *w, int n, size_t total, double *out, hipStream_t st) {
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_mass, dim3((unsigned)blocks), dim3(256), 0, st, sJ, w, n, total, out);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }

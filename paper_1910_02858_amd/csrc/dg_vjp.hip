@@ -1,0 +1,368 @@
+// Vector-Jacobian product of the split-form DGSEM operator on LGL nodes (one workgroup per
+// element), for Ubar = (dL/dU)^T Utbar.
+//
+// The forward operator (Krais et al., FLEXI, Sec. 3.3 eq. semiDiscreteSplit with BR1 lifting,
+// Sec. 3.1 eq. discreteGradient) is
+//   U_t = -(1/J) acc,  acc_q = sum_dir [ sum_m 2 D_im F#(U_q, U_m) - sum_m D_im Fv_m ]
+//                            + sum_faces lhat (F_face - sg F_int,q),
+//   G = lift(W(U)),    W = (u, v, w, T).
+// With Abar = -(1/J) Utbar (the adjoint of acc) the reverse is:
+//   * each unordered pair {q, p} on a line: Fbar = 2 D_qp Abar_q + 2 D_pq Abar_p, then the
+//     two-point flux's transposed Jacobian in both arguments (the partner's share goes through
+//     LDS atomics);
+//   * viscous volume term: Fvbar_p = -sum_q D_qp Abar_q, then the viscous flux's transposed
+//     Jacobian in U and in G;
+//   * each face point: the flux enters both elements, so Fbar = lhat (Abar_master - Abar_slave),
+//     and every element adds only the derivative with respect to its own trace (the neighbour's
+//     Abar is read from global memory, nothing is written into another element);
+//   * the lifting transposed: Wbar from own Gbar (volume, own faces) and from the neighbours'
+//     Gbar on shared faces, then W's Jacobian.
+#include <hip/hip_runtime.h>
+
+#include "dg_flux.h"
+#include "dg_internal.h"
+
+namespace dg {
+
+template <int N> struct VSz {
+  static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int NT = ((n3 + 63) / 64) * 64;
+};
+
+template <int n> __device__ __forceinline__ int vline_node(int dn, int a, int b, int m) {
+  return dn == 0 ? (m + n * (a + n * b)) : (dn == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
+}
+
+// ---------------------------------------------------------------------------------- main
+template <int N, bool NS>
+__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
+                                                         const double *__restrict__ G,
+                                                         const double *__restrict__ Utb, double *__restrict__ Ub,
+                                                         double *__restrict__ Gb, double scale, int accumulate) {
+  using S = VSz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  constexpr int NG = NS ? 12 : 1;
+  __shared__ double sQ[5 * n3];    // primitive state
+  __shared__ double sA[5 * n3];    // Abar = -(1/J) Utbar
+  __shared__ double sJ[3 * n3];    // Ja^dir of the current direction
+  __shared__ double sPA[5 * n3];   // primitive adjoints added by other threads
+  __shared__ double sCB[5 * n3];   // conservative adjoints added by face threads
+  __shared__ double sGb[NG * n3];  // gradient adjoints added by face threads
+  __shared__ double sD[n * n];
+  const int e = blockIdx.x, t = threadIdx.x;
+  const bool act = t < n3;
+  const double gamma = ph.gamma, gm1 = gamma - 1.0, g1 = gamma / gm1;
+  const int vf = ph.vf;
+  for (int c = t; c < n * n; c += NT) sD[c] = g.tab->D[c];
+  const double lh = g.tab->lhp[N];  // lhat at a face node (the same value at both ends)
+  const double *Ue = U + (size_t)e * 5 * n3;
+  const double *Ge = G + (size_t)e * 12 * n3;
+  const double *Jae = g.Ja + (size_t)e * 9 * n3;
+  const double *sJe = g.sJ + (size_t)e * n3;
+  dgf::P q;
+  if (act) {
+    double Uq[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + t];
+    q = dgf::prim(Uq, gm1);
+    sQ[t] = q.r; sQ[n3 + t] = q.u; sQ[2 * n3 + t] = q.v; sQ[3 * n3 + t] = q.w; sQ[4 * n3 + t] = q.p;
+    const double sj = sJe[t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      sA[v * n3 + t] = -sj * Utb[((size_t)e * 5 + v) * n3 + t];
+      sPA[v * n3 + t] = 0.0;
+      sCB[v * n3 + t] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NG; ++c) sGb[c * n3 + t] = 0.0;
+  }
+  __syncthreads();
+  // ---- faces: Fbar = lhat (Abar_master - Abar_slave); own-trace derivative only.  One
+  // direction at a time: its two faces touch disjoint nodes, so plain adds are race-free and
+  // every node sums its face terms in a fixed order.
+  for (int dn = 0; dn < 3; ++dn) {
+  for (int p = t; p < 2 * n2; p += NT) {
+    const int s = 2 * dn + p / n2, ab = p % n2, a = ab % n, b = ab / n;
+    const bool plus = s & 1;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
+    const int qn = vline_node<n>(dn, a, b, plus ? 0 : N);
+    double Uw[5], Ux[5], Aw[5], Ax[5];
+    const double sjn = g.sJ[(size_t)nb * n3 + qn];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Uw[v] = Ue[v * n3 + qo];
+      Ux[v] = U[((size_t)nb * 5 + v) * n3 + qn];
+      Aw[v] = sA[v * n3 + qo];
+      Ax[v] = -sjn * Utb[((size_t)nb * 5 + v) * n3 + qn];
+    }
+    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    const double sg = plus ? 1.0 : -1.0;
+    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    double Fb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fb[v] = lh * (plus ? (Aw[v] - Ax[v]) : (Ax[v] - Aw[v]));
+    const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
+    const dgf::P PM = dgf::prim(UM, gm1), PS = dgf::prim(US, gm1);
+    double Fbs[5], bM[5] = {0, 0, 0, 0, 0}, bS[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fbs[v] = Fb[v] * sh;
+    dgf::riemann_adj(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, bM, bS);
+    const double *bo = plus ? bM : bS;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sCB[v * n3 + qo] += bo[v];
+    if (NS) {
+      // F contains -1/2 Fv(U_own, G_own) . nt
+      double go[12], gbo[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) { go[c] = Ge[c * n3 + qo]; gbo[c] = 0.0; }
+      double Fvb[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
+      dgf::PA pa = dgf::zero_pa();
+      const dgf::P Po = plus ? PM : PS;
+      dgf::visc_flux_adj(Po, go, ph.mu, ph.kappa, nt, Fvb, pa, gbo);
+      sPA[0 * n3 + qo] += pa.r;
+      sPA[1 * n3 + qo] += pa.u;
+      sPA[2 * n3 + qo] += pa.v;
+      sPA[3 * n3 + qo] += pa.w;
+      sPA[4 * n3 + qo] += pa.p;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sGb[c * n3 + qo] += gbo[c];
+    }
+  }
+  __syncthreads();
+  }
+  // ---- face contributions into registers; sPA is reused for the pair exchange below
+  dgf::PA pa = dgf::zero_pa();
+  double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (act) {
+    pa.r = sPA[t]; pa.u = sPA[n3 + t]; pa.v = sPA[2 * n3 + t]; pa.w = sPA[3 * n3 + t]; pa.p = sPA[4 * n3 + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) cb[v] = sCB[v * n3 + t];
+  }
+  // ---- interior flux F_int = Fc . Ja - Fv on the faces through this node
+  double fvb[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) fvb[d][c] = 0.0;
+  const int id3[3] = {t % n, (t / n) % n, t / n2};
+  if (act) {
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      const int id = id3[dir];
+      if (id != 0 && id != N) continue;
+      const double sg = (id == N) ? 1.0 : -1.0;
+      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      double Fib[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fib[v] = -lh * sg * sA[v * n3 + t];
+      dgf::euler_flux_adj(q, nv, g1, Fib, pa);
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fvb[dir][c] -= Fib[1 + c];
+      }
+    }
+  }
+  // ---- volume: pairs, diagonal and viscous transpose, direction by direction
+  for (int dir = 0; dir < 3; ++dir) {
+    double nvo[3] = {0.0, 0.0, 0.0};
+    __syncthreads();
+    if (act) {
+      nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
+      sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
+    }
+    __syncthreads();
+    {
+      const int id = act ? id3[dir] : 0;
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      double Ao[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ao[v] = act ? sA[v * n3 + t] : 0.0;
+#pragma unroll 1
+      for (int sft = 1; sft <= n / 2; ++sft) {
+        if (act) {
+          const bool half = (2 * sft == n);  // the pair at distance n/2 is met from both ends
+          int jp = id + sft;
+          if (jp >= n) jp -= n;
+          const int qp = base + jp * str;
+          dgf::P r;
+          r.r = sQ[qp]; r.u = sQ[n3 + qp]; r.v = sQ[2 * n3 + qp]; r.w = sQ[3 * n3 + qp]; r.p = sQ[4 * n3 + qp];
+          const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]),
+                                0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+          const double Dij2 = 2.0 * sD[id * n + jp], Dji2 = 2.0 * sD[jp * n + id];
+          double Fb[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Fb[v] = Dij2 * Ao[v] + (half ? 0.0 : Dji2 * sA[v * n3 + qp]);
+          dgf::PA pr = dgf::zero_pa();
+          dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
+          // every node receives exactly one partner share per round
+          sPA[qp] = pr.r; sPA[n3 + qp] = pr.u; sPA[2 * n3 + qp] = pr.v; sPA[3 * n3 + qp] = pr.w;
+          sPA[4 * n3 + qp] = pr.p;
+        }
+        __syncthreads();
+        if (act) {
+          pa.r += sPA[t]; pa.u += sPA[n3 + t]; pa.v += sPA[2 * n3 + t]; pa.w += sPA[3 * n3 + t];
+          pa.p += sPA[4 * n3 + t];
+        }
+        __syncthreads();
+      }
+      if (!act) continue;
+      const double Dii = sD[id * n + id];
+      if (Dii != 0.0) {
+        double Fb[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fb[v] = 2.0 * Dii * Ao[v];
+        dgf::euler_flux_adj(q, nvo, g1, Fb, pa);
+      }
+      if (NS) {
+        // acc_m -= sum_i D_mi Fv_i  =>  Fvbar_i -= sum_m D_mi Abar_m
+        for (int m = 0; m < n; ++m) {
+          const int qm = base + m * str;
+          const double Dmi = sD[m * n + id];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) fvb[dir][c] -= Dmi * sA[(1 + c) * n3 + qm];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    double gbo[NG];
+#pragma unroll
+    for (int c = 0; c < NG; ++c) gbo[c] = 0.0;
+    if (NS) {
+      double go[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+        const double Fvb[5] = {0.0, fvb[dir][0], fvb[dir][1], fvb[dir][2], fvb[dir][3]};
+        dgf::visc_flux_adj(q, go, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
+      }
+    }
+    dgf::cons_adj(q, gm1, pa, cb);
+    double *Ube = Ub + (size_t)e * 5 * n3;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = (accumulate ? Ube[v * n3 + t] : 0.0) + scale * cb[v];
+    if (NS) {
+      double *Gbe = Gb + (size_t)e * 12 * n3;
+#pragma unroll
+      for (int c = 0; c < NG; ++c) Gbe[c * n3 + t] = scale * (gbo[c] + sGb[c * n3 + t]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------- lifting
+// Ubar += (dW/dU)^T Wbar, Wbar = transpose of G = (1/J)[sum Dhat Ja W + lhat nt (W + W_nb)/2]
+template <int N>
+__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_lift(Geo g, Phys ph, const double *__restrict__ U,
+                                                         const double *__restrict__ Gb, double *__restrict__ Ub) {
+  using S = VSz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  __shared__ double sH[12 * n3];  // (1/J) Gbar
+  __shared__ double sDh[n * n];
+  const int e = blockIdx.x, t = threadIdx.x;
+  const bool act = t < n3;
+  const double gm1 = ph.gamma - 1.0;
+  for (int c = t; c < n * n; c += NT) sDh[c] = g.tab->Dh[c];
+  const double lh = g.tab->lhp[N];
+  if (act) {
+    const double sj = g.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sH[c * n3 + t] = sj * Gb[((size_t)e * 12 + c) * n3 + t];
+  }
+  __syncthreads();
+  if (!act) return;
+  const int id3[3] = {t % n, (t / n) % n, t / n2};
+  const double *Jae = g.Ja + (size_t)e * 9 * n3;
+  double Wb[4] = {0.0, 0.0, 0.0, 0.0};
+  // volume: W_v(p) enters G_{d,v}(q_i) with Dhat[i][ip] Ja^dir_d(p)
+  for (int dir = 0; dir < 3; ++dir) {
+    const int id = id3[dir];
+    const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+    const int base = t - id * str;
+    const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+    double hs[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) hs[c] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const int qi = base + i * str;
+      const double Dh = sDh[i * n + id];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) hs[c] += Dh * sH[c * n3 + qi];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wb[v] += nv[d] * hs[d * 4 + v];
+  }
+  // faces: own lifting and the neighbour's lifting both use W*/2 of this trace
+  for (int dir = 0; dir < 3; ++dir) {
+    const int id = id3[dir];
+    if (id != 0 && id != N) continue;
+    const int sd = (id == N) ? 1 : 0;
+    const int s = 2 * dir + sd;
+    const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+    const int ab = a + n * b;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const int qn = vline_node<n>(dir, a, b, sd ? 0 : N);
+    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    const double *fnn = g.fn + ((size_t)nb * 6 + (s ^ 1)) * 3 * n2 + ab;
+    const double sjn = g.sJ[(size_t)nb * n3 + qn];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double own = fnp[d * n2] * sH[(d * 4 + v) * n3 + t];
+        const double nbr = fnn[d * n2] * sjn * Gb[((size_t)nb * 12 + d * 4 + v) * n3 + qn];
+        Wb[v] += 0.5 * lh * (own + nbr);
+      }
+  }
+  double Uq[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + t];
+  const dgf::P q = dgf::prim(Uq, gm1);
+  dgf::PA pa = dgf::zero_pa();
+  dgf::lift_vars_adj(q, ph.R, Wb, pa);
+  double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  dgf::cons_adj(q, gm1, pa, cb);
+  double *Ube = Ub + (size_t)e * 5 * n3;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Ube[v * n3 + t] += cb[v];
+}
+
+// ---------------------------------------------------------------------------------- launcher
+template <int N>
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
+               const double *Ubar_t, double *Ubar, double scale, int accumulate, hipStream_t st) {
+  if (form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
+  if constexpr (N > 7) {
+    return DG_ERR_UNSUPPORTED;  // the reverse kernel's LDS staging exceeds 160 KB beyond N = 7
+  } else {
+  dim3 grid(g.K), block(VSz<N>::NT);
+  if (eqn == DG_NAVIER_STOKES) {
+    hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale, accumulate);
+    if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
+    hipLaunchKernelGGL((k_vjp_lift<N>), grid, block, 0, st, g, ph, U, Gbar, Ubar);
+  } else {
+    hipLaunchKernelGGL((k_vjp_main<N, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale,
+                       accumulate);
+  }
+  if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
+  return DG_OK;
+  }
+}
+
+#ifdef DG_ONLY_N
+template int launch_vjp<DG_ONLY_N>(const Geo &, const Phys &, int, int, const double *, const double *, double *,
+                                   const double *, double *, double, int, hipStream_t);
+#endif
+
+}  // namespace dg

@@ -1,0 +1,167 @@
+// Host self-check of the reverse flux products in dg_flux.h: for random states and random
+// output adjoints, the transposed-Jacobian product must equal the central finite difference of
+// <adjoint, flux> along every input coordinate.  Prints one line per function with the largest
+// relative mismatch and returns non-zero if any exceeds the tolerance.
+#define DGFN inline
+#include "dg_flux.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+
+using namespace dgf;
+
+static std::mt19937_64 rng(7);
+static double urand(double a, double b) { return std::uniform_real_distribution<double>(a, b)(rng); }
+
+static P rand_prim(double mach) {
+  P q;
+  q.r = urand(0.6, 1.6);
+  q.p = urand(0.6, 1.6);
+  q.u = urand(-1, 1) * mach; q.v = urand(-1, 1) * mach; q.w = urand(-1, 1) * mach;
+  return q;
+}
+static void to_cons(const P &q, double gamma, double *U) {
+  U[0] = q.r; U[1] = q.r * q.u; U[2] = q.r * q.v; U[3] = q.r * q.w;
+  U[4] = q.p / (gamma - 1) + 0.5 * q.r * (q.u * q.u + q.v * q.v + q.w * q.w);
+}
+static double *comp(P &q, int j) { return j == 0 ? &q.r : j == 1 ? &q.u : j == 2 ? &q.v : j == 3 ? &q.w : &q.p; }
+static double comp(const PA &a, int j) { return j == 0 ? a.r : j == 1 ? a.u : j == 2 ? a.v : j == 3 ? a.w : a.p; }
+
+static int failures = 0;
+static void report(const char *name, double err, double tol) {
+  std::printf("%-28s max rel err %.3e %s\n", name, err, err <= tol ? "ok" : "FAIL");
+  if (!(err <= tol)) ++failures;
+}
+
+template <class F> static double fd_dir(F f, double h) { return (f(h) - f(-h)) / (2 * h); }
+
+int main() {
+  const double gamma = 1.4, gm1 = gamma - 1, g1 = gamma / gm1, tol = 2e-7;
+  double worst;
+  // Euler flux
+  worst = 0;
+  for (int it = 0; it < 200; ++it) {
+    P q = rand_prim(0.8);
+    double nv[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)}, Fb[5];
+    for (double &x : Fb) x = urand(-1, 1);
+    PA a = zero_pa();
+    euler_flux_adj(q, nv, g1, Fb, a);
+    for (int j = 0; j < 5; ++j) {
+      auto f = [&](double h) { P t = q; *comp(t, j) += h; double F[5]; euler_flux(t, nv, g1, F);
+                               double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
+      double fd = fd_dir(f, 1e-6), an = comp(a, j);
+      worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
+    }
+  }
+  report("euler_flux_adj", worst, tol);
+  // two-point fluxes
+  for (int vf : {0, 2}) {
+    worst = 0;
+    for (int it = 0; it < 200; ++it) {
+      P A = rand_prim(0.8), B = rand_prim(0.8);
+      double nv[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)}, Fb[5];
+      for (double &x : Fb) x = urand(-1, 1);
+      PA aA = zero_pa(), aB = zero_pa();
+      pair_flux_adj(vf, A, B, nv, g1, Fb, aA, aB);
+      for (int side = 0; side < 2; ++side)
+        for (int j = 0; j < 5; ++j) {
+          auto f = [&](double h) { P a = A, b = B; *comp(side ? b : a, j) += h; double F[5];
+                                   pair_flux(vf, a, b, nv, g1, F);
+                                   double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
+          double fd = fd_dir(f, 1e-6), an = comp(side ? aB : aA, j);
+          worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
+        }
+    }
+    report(vf == 0 ? "kep_flux_adj" : "central_flux_adj", worst, tol);
+  }
+  // Roe dissipation
+  worst = 0;
+  for (int it = 0; it < 300; ++it) {
+    P L = rand_prim(0.5), R = rand_prim(0.5);  // away from sonic points, where |u_n -+ c| has kinks
+    double nh[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)};
+    double nn = std::sqrt(nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2]);
+    for (double &x : nh) x /= nn;
+    double Db[5];
+    for (double &x : Db) x = urand(-1, 1);
+    PA aL = zero_pa(), aR = zero_pa();
+    roe_diss_adj(L, R, nh, gm1, g1, Db, aL, aR);
+    for (int side = 0; side < 2; ++side)
+      for (int j = 0; j < 5; ++j) {
+        auto f = [&](double h) { P a = L, b = R; *comp(side ? b : a, j) += h; double D[5];
+                                 roe_diss(a, b, nh, gm1, g1, D);
+                                 double s = 0; for (int v = 0; v < 5; ++v) s += Db[v] * D[v]; return s; };
+        double fd = fd_dir(f, 1e-5), an = comp(side ? aR : aL, j);
+        worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
+      }
+  }
+  report("roe_diss_adj", worst, tol);
+  // full Riemann solvers in conservative variables
+  for (int rs : {0, 1, 3}) {
+    worst = 0;
+    for (int it = 0; it < 200; ++it) {
+      P L = rand_prim(0.5), R = rand_prim(0.5);
+      double UL[5], UR[5];
+      to_cons(L, gamma, UL); to_cons(R, gamma, UR);
+      double nh[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)};
+      double nn = std::sqrt(nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2]);
+      for (double &x : nh) x /= nn;
+      double Fb[5];
+      for (double &x : Fb) x = urand(-1, 1);
+      double ULb[5] = {0, 0, 0, 0, 0}, URb[5] = {0, 0, 0, 0, 0};
+      riemann_adj(rs, 0, L, R, UL, UR, nh, gamma, Fb, ULb, URb);
+      for (int side = 0; side < 2; ++side)
+        for (int j = 0; j < 5; ++j) {
+          auto f = [&](double h) { double a[5], b[5]; for (int v = 0; v < 5; ++v) { a[v] = UL[v]; b[v] = UR[v]; }
+                                   (side ? b : a)[j] += h;
+                                   P pa = prim(a, gm1), pb = prim(b, gm1); double F[5];
+                                   riemann(rs, 0, pa, pb, a, b, nh, gamma, F);
+                                   double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
+          double fd = fd_dir(f, 1e-5), an = (side ? URb : ULb)[j];
+          worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
+        }
+    }
+    report(rs == 0 ? "riemann_adj llf" : rs == 1 ? "riemann_adj roe" : "riemann_adj kep+roe", worst, tol);
+  }
+  // viscous flux (state and gradient) and lifted variables
+  worst = 0;
+  for (int it = 0; it < 200; ++it) {
+    P q = rand_prim(0.8);
+    double g[12], nv[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)}, Fb[5];
+    for (double &x : g) x = urand(-1, 1);
+    for (double &x : Fb) x = urand(-1, 1);
+    const double mu = 0.013, kappa = 0.021;
+    PA a = zero_pa();
+    double gb[12] = {0};
+    visc_flux_adj(q, g, mu, kappa, nv, Fb, a, gb);
+    for (int j = 0; j < 5 + 12; ++j) {
+      auto f = [&](double h) { P t = q; double gg[12]; for (int c = 0; c < 12; ++c) gg[c] = g[c];
+                               if (j < 5) *comp(t, j) += h; else gg[j - 5] += h;
+                               double F[5]; visc_flux(t, gg, mu, kappa, nv, F);
+                               double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
+      double fd = fd_dir(f, 1e-6), an = j < 5 ? comp(a, j) : gb[j - 5];
+      worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
+    }
+  }
+  report("visc_flux_adj", worst, tol);
+  // primitive -> conservative adjoint map
+  worst = 0;
+  for (int it = 0; it < 200; ++it) {
+    P q = rand_prim(0.8);
+    double U[5];
+    to_cons(q, gamma, U);
+    PA a;
+    a.r = urand(-1, 1); a.u = urand(-1, 1); a.v = urand(-1, 1); a.w = urand(-1, 1); a.p = urand(-1, 1);
+    double Ub[5] = {0, 0, 0, 0, 0};
+    cons_adj(q, gm1, a, Ub);
+    for (int j = 0; j < 5; ++j) {
+      auto f = [&](double h) { double V[5]; for (int v = 0; v < 5; ++v) V[v] = U[v]; V[j] += h;
+                               P t = prim(V, gm1);
+                               return a.r * t.r + a.u * t.u + a.v * t.v + a.w * t.w + a.p * t.p; };
+      double fd = fd_dir(f, 1e-6);
+      worst = std::max(worst, std::fabs(fd - Ub[j]) / (std::fabs(Ub[j]) + 1e-3));
+    }
+  }
+  report("cons_adj", worst, tol);
+  return failures ? 1 : 0;
+}

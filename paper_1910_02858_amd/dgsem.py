@@ -28,7 +28,7 @@ EXPORTS = [
     "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
-    "dg_profile_read", "dg_host_geometry",
+    "dg_profile_read", "dg_host_geometry", "dg_mass_weights",
 ]
 
 
@@ -75,6 +75,7 @@ def lib():
         L.dg_integrals.argtypes = [_VP, _VP, _D]
         L.dg_check_finite.argtypes = [_VP, _VP]
         L.dg_node_coords.argtypes = [_VP, _D]
+        L.dg_mass_weights.argtypes = [_VP, _VP]
         L.dg_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64)]
         L.dg_destroy.argtypes = [_VP]
         L.dg_destroy.restype = None
@@ -239,6 +240,13 @@ class DGSolver:
         self._check(lib().dg_profile_read(self.h, _ptr(out)), "dg_profile_read")
         return {"lift_ms": out[0], "lift_launches": int(out[1]), "main_ms": out[2], "main_launches": int(out[3])}
 
+    def mass_weights(self):
+        """J w_i w_j w_k per node as a [K, n^3] device tensor."""
+        self._sync_stream()
+        out = self.torch.empty((self.K, self.n3), dtype=self.torch.float64, device="cuda")
+        self._check(lib().dg_mass_weights(self.h, _VP(out.data_ptr())), "dg_mass_weights")
+        return out
+
     def node_coords(self):
         x = np.zeros((self.K, 3, self.n3))
         self._check(lib().dg_node_coords(self.h, _ptr(x)), "dg_node_coords")
@@ -270,3 +278,73 @@ def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[boo
     S = DGSolver.from_workload(wl, xgeo, nbr, side, stream=stream)
     U0 = inputs.initial_state(wl, S.node_coords())
     return S, torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+
+
+# ----------------------------------------------------------------------------- differentiation
+def _rollout_forward(S, U0, nsteps, dt, keep_stage_inputs=False):
+    """nsteps RK steps from U0 (not modified).  Returns U_T and, if asked, the input of every stage."""
+    a, b, _ = rk_coefficients()
+    R = S.torch.zeros_like(U0)
+    cur = U0.clone()
+    nxt = S.empty()
+    inputs = []
+    for _ in range(nsteps):
+        for s in range(5):
+            if keep_stage_inputs:
+                inputs.append(cur.clone())
+            S.rk_stage(cur, nxt, R, a[s], b[s], dt)
+            cur, nxt = nxt, cur
+    return cur, inputs
+
+
+def _rollout_backward(S, stage_inputs, Ubar, dt):
+    """Reverse of the stages whose inputs are given (in forward order); Ubar is updated in place.
+    The RK register's adjoint starts at zero: a_1 = 0 makes R start from zero at every step."""
+    a, b, _ = rk_coefficients()
+    Rbar = S.torch.zeros_like(Ubar)
+    for idx in range(len(stage_inputs) - 1, -1, -1):
+        s = idx % 5
+        S.rk_stage_vjp(stage_inputs[idx], Ubar, Rbar, a[s], b[s], dt)
+    return Ubar
+
+
+def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
+    """U(T) after nsteps RK steps as a differentiable function of U0 (torch.autograd)."""
+    import torch
+
+    class _Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, U):
+            a, b, _ = rk_coefficients()
+            ckpts = []
+            R = torch.zeros_like(U)
+            cur = U.detach().clone()
+            nxt = S.empty()
+            for step in range(nsteps):
+                if step % ckpt_every == 0:
+                    ckpts.append(cur.clone())
+                for s in range(5):
+                    S.rk_stage(cur, nxt, R, a[s], b[s], dt)
+                    cur, nxt = nxt, cur
+            ctx.ckpts = ckpts
+            return cur
+
+        @staticmethod
+        def backward(ctx, gUT):
+            Ubar = gUT.detach().contiguous().clone()
+            nseg = len(ctx.ckpts)
+            for seg in range(nseg - 1, -1, -1):
+                first = seg * ckpt_every
+                steps = min(ckpt_every, nsteps - first)
+                _, inputs = _rollout_forward(S, ctx.ckpts[seg], steps, dt, keep_stage_inputs=True)
+                _rollout_backward(S, inputs, Ubar, dt)
+                del inputs
+            return Ubar
+
+    return _Rollout.apply(U0)
+
+
+def kinetic_energy(U, wJ):
+    """sum over nodes of J w_i w_j w_k |m|^2 / (2 rho), a differentiable torch scalar."""
+    m2 = (U[:, 1:4] ** 2).sum(dim=1)
+    return (wJ * 0.5 * m2 / U[:, 0]).sum()
