@@ -60,6 +60,31 @@ def cpu_baseline(wl, budget_s: float = 12.0):
             "pid_core_s": wall * orc.num_threads() / (dof * stages)}
 
 
+def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2):
+    """Wall time of the gradient (checkpoint recomputation + reverse stages) over the wall time
+    of the forward rollout that stores the checkpoints: 12^3 curved hexes, N=5, split KEP + Roe +
+    BR1, Taylor-Green vortex, 50 RK steps, checkpoint every 10 steps, objective = kinetic energy."""
+    wl = inputs.workload(5)
+    S, U0 = dgsem.build_solver(wl)
+    dt = S.timestep(U0, wl.cfl, wl.dfl)
+    wJ = S.mass_weights()
+    best_f, best_b = float("inf"), float("inf")
+    for _ in range(repeats + 1):  # the first round warms up
+        U = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UT = dgsem.rollout(S, U, wl.steps, dt, ckpt_every=10)
+        ke = dgsem.kinetic_energy(UT, wJ)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (g,) = torch.autograd.grad(ke, U)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
+    return {"value": best_b / best_f, "forward_ms": best_f * 1e3, "backward_ms": best_b * 1e3,
+            "workload": wl.name, "dof": S.K * S.n3, "steps": wl.steps, "checkpoint_every": 10}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +93,7 @@ def main():
     ap.add_argument("--elements", type=int, default=48, help="elements per direction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--profile-stages", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -156,6 +182,10 @@ def main():
         "stage_hbm_frac": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / HBM_PEAK_GBS,
         "adjoint_forward_ratio": None,
     }
+    if not args.no_adjoint:
+        adj = adjoint_ratio(dgsem, inputs, torch)
+        out["adjoint_forward_ratio"] = adj["value"]
+        out["adjoint"] = adj
     if not args.no_cpu:
         cb = cpu_baseline(wl)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
