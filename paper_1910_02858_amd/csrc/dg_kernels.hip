@@ -24,6 +24,10 @@
 #ifndef DG_SPLIT_MINB
 #define DG_SPLIT_MINB 4
 #endif
+// minimum waves per SIMD for the lifting kernel: 6 fits three 512-thread workgroups per CU
+#ifndef DG_LIFT_MINB
+#define DG_LIFT_MINB 6
+#endif
 
 namespace dg {
 
@@ -38,6 +42,15 @@ template <int n> __device__ __forceinline__ int line_node(int dn, int a, int b, 
 }
 
 // ----------------------------------------------------------------------------- physics
+// Reciprocal from v_rcp_f64 refined by two Newton steps (error well below one ulp of the
+// quantities it feeds); used for the two-point fluxes, where IEEE division dominated.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 struct Pr5 {
   double rho, u, v, w, p;
 };
@@ -45,7 +58,7 @@ struct Pr5 {
 __device__ __forceinline__ Pr5 to_prim(const double *U, double gm1) {
   Pr5 P;
   P.rho = U[0];
-  const double ir = 1.0 / U[0];
+  const double ir = frcp(U[0]);
   P.u = U[1] * ir; P.v = U[2] * ir; P.w = U[3] * ir;
   P.p = gm1 * (U[4] - 0.5 * (U[1] * P.u + U[2] * P.v + U[3] * P.w));
   return P;
@@ -208,8 +221,8 @@ __device__ __forceinline__ int xcd_element(int b, int K) {
 
 // ----------------------------------------------------------------------------- lifting
 template <int N, bool LGL>
-__global__ void __launch_bounds__(Sz<N>::NT) k_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                    double *__restrict__ G) {
+__global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+                                                                  double *__restrict__ G) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   __shared__ double sW[4 * n3];
@@ -293,9 +306,25 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_lift(Geo g, Phys ph, const double
           for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sW[v * n3 + qm];
         }
       }
+      if (LGL && (id == 0 || id == N)) {
+        // surface on the face of this direction through the node: on LGL nodes the outward
+        // normal times s-hat is +-Ja^dir at the node itself
+        const bool plus = id == N;
+        const int s = 2 * dir + (plus ? 1 : 0);
+        const double lh = slh[(plus ? n : 0) + id];
+        const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
+        const int ab = a + n * b;
+        const double sl_ = plus ? lh : -lh;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double c1 = sl_ * sJa[d * n3 + t];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sWs[(s * 4 + v) * n2 + ab];
+        }
+      }
     }
   }
-  if (t < n3) {
+  if (!LGL && t < n3) {
     // surface: lhat(+-1) [W* nt_d] on each side
     for (int s = 0; s < 6; ++s) {
       const int dn = s >> 1;
@@ -313,6 +342,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_lift(Geo g, Phys ph, const double
         for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sWs[(s * 4 + v) * n2 + ab];
       }
     }
+  }
+  if (t < n3) {
     const double sj = g.sJ[(size_t)e * n3 + t];
     double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
@@ -503,100 +534,107 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 }
 
 // ----------------------------------------------------------------------------- split form, LGL
-// Reciprocal from v_rcp_f64 refined by two Newton steps (error well below one ulp of the
-// quantities it feeds); used for the two-point fluxes, where IEEE division dominated.
-__device__ __forceinline__ double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+// one Newton step: for ratios that only enter through a correction of relative size < 1e-4
+__device__ __forceinline__ double frcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-// logarithmic mean (a-b)/(ln a - ln b) and its reciprocal, from one shared reciprocal of
-// a+b; a 4-term series when ((a-b)/(a+b))^2 < 1e-4, the logarithms otherwise
-__device__ __forceinline__ double lnmean(double a, double b) {
-  const double s = a + b, d = a - b;
-  const double f = d * frcp(s);
-  const double u = f * f;
-  if (u < 1e-4) return s * frcp(2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
-  return d / (log(a) - log(b));
-}
-__device__ __forceinline__ double inv_lnmean(double a, double b) {
-  const double s = a + b, d = a - b;
-  const double is = frcp(s);
-  const double f = d * is;
-  const double u = f * f;
-  if (u < 1e-4) return (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)))) * is;
-  return (log(a) - log(b)) / d;
-}
-
-// per-node state of the two-point fluxes: rho, u, v, w, beta = rho/(2p) (EC) or p (KEP, central)
+// per-node state of the two-point fluxes: rho, u, v, w, and
+//   EC:  b = beta = rho/(2p), q = |u|^2
+//   KEP, central: b = p, q = H = (E+p)/rho
 struct PS {
-  double r, u, v, w, b;
+  double r, u, v, w, b, q;
 };
 
-// two-point flux along nv between states A and B (VF 0 KEP, 1 EC, 2 central)
+// Coefficients of f/artanh(f) = 1 + C1 u + C2 u^2 + C3 u^3 + O(u^4), u = f^2 (inverse of the
+// series artanh(f)/f = 1 + u/3 + u^2/5 + u^3/7 + ...); the truncation error is below 3e-18
+// relative for u < 1e-4.
+#define DG_LM_C1 (-1.0 / 3.0)
+#define DG_LM_C2 (-4.0 / 45.0)
+#define DG_LM_C3 (-44.0 / 945.0)
+
+// Twice the two-point flux of the pair (A, B) contracted with the mean metric, given the
+// metric sum nS = Ja(A) + Ja(B) (eq. semiDiscreteSplit: the volume term is 2 D_ij F#(i,j)).
+// VF 0: kinetic-energy preserving (Pirozzoli); 1: entropy conserving (Chandrashekar) with the
+// logarithmic means f (a+b)/(2 artanh f), f = (a-b)/(a+b), by series for f^2 < 1e-4 and by
+// logarithms otherwise; 2: mean of the two Euler fluxes.  kg = 1/(gamma-1).
 template <int VF>
-__device__ __forceinline__ void pair_flux(const PS &A, const PS &B, const double *nv, double gm1, double *F) {
-  const double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
-  if (VF == 1) {
-    const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
-    const double rln = lnmean(A.r, B.r);
-    const double sb = A.b + B.b;
-    const double isb = frcp(sb);
-    const double db = A.b - B.b;
-    const double fb = db * isb;
-    const double ub = fb * fb;
-    const double iblm = (ub < 1e-4) ? (2.0 + ub * (2.0 / 3.0 + ub * (2.0 / 5.0 + ub * (2.0 / 7.0)))) * isb
-                                    : (log(A.b) - log(B.b)) / db;
-    const double phat = 0.5 * (A.r + B.r) * isb;  // {rho} / (2 {beta})
-    const double q2m = 0.5 * ((A.u * A.u + A.v * A.v + A.w * A.w) + (B.u * B.u + B.v * B.v + B.w * B.w));
-    const double f0 = rln * umn;
-    F[0] = f0;
-    F[1] = f0 * um + phat * nv[0];
-    F[2] = f0 * vm + phat * nv[1];
-    F[3] = f0 * wm + phat * nv[2];
-    F[4] = f0 * (0.5 / gm1 * iblm - 0.5 * q2m) + um * F[1] + vm * F[2] + wm * F[3];
-  } else if (VF == 0) {
-    // kinetic-energy preserving: {rho}{u.n}, {u} F_rho + {p} n, F_rho {H}, H = (E+p)/rho
-    const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
-    const double pm = 0.5 * (A.b + B.b);
-    const double g1 = 1.0 / gm1 + 1.0;  // gamma/(gamma-1)
-    const double Ha = g1 * A.b / A.r + 0.5 * (A.u * A.u + A.v * A.v + A.w * A.w);
-    const double Hb = g1 * B.b / B.r + 0.5 * (B.u * B.u + B.v * B.v + B.w * B.w);
-    const double f0 = 0.5 * (A.r + B.r) * umn;
-    F[0] = f0;
-    F[1] = f0 * um + pm * nv[0];
-    F[2] = f0 * vm + pm * nv[1];
-    F[3] = f0 * wm + pm * nv[2];
-    F[4] = f0 * 0.5 * (Ha + Hb);
-  } else {
-    // mean of the two Euler fluxes
-    const double una = A.u * nv[0] + A.v * nv[1] + A.w * nv[2];
-    const double unb = B.u * nv[0] + B.v * nv[1] + B.w * nv[2];
-    const double g1 = 1.0 / gm1 + 1.0;
-    const double Ha = g1 * A.b / A.r + 0.5 * (A.u * A.u + A.v * A.v + A.w * A.w);
-    const double Hb = g1 * B.b / B.r + 0.5 * (B.u * B.u + B.v * B.v + B.w * B.w);
-    F[0] = 0.5 * (A.r * una + B.r * unb);
-    F[1] = 0.5 * (A.r * A.u * una + B.r * B.u * unb + (A.b + B.b) * nv[0]);
-    F[2] = 0.5 * (A.r * A.v * una + B.r * B.v * unb + (A.b + B.b) * nv[1]);
-    F[3] = 0.5 * (A.r * A.w * una + B.r * B.w * unb + (A.b + B.b) * nv[2]);
-    F[4] = 0.5 * (A.r * Ha * una + B.r * Hb * unb);
+__device__ __forceinline__ void pair2(const PS &A, const PS &B, const double *nS, double kg, double *F) {
+  const double su = A.u + B.u, sv = A.v + B.v, sw = A.w + B.w;
+  if (VF == 2) {
+    const double una = A.u * nS[0] + A.v * nS[1] + A.w * nS[2];
+    const double unb = B.u * nS[0] + B.v * nS[1] + B.w * nS[2];
+    const double ma = 0.5 * A.r * una, mb = 0.5 * B.r * unb, ps = 0.5 * (A.b + B.b);
+    F[0] = ma + mb;
+    F[1] = fma(ma, A.u, fma(mb, B.u, ps * nS[0]));
+    F[2] = fma(ma, A.v, fma(mb, B.v, ps * nS[1]));
+    F[3] = fma(ma, A.w, fma(mb, B.w, ps * nS[2]));
+    F[4] = fma(ma, A.q, mb * B.q);
+    return;
   }
+  const double un = su * nS[0] + sv * nS[1] + sw * nS[2];  // 4 {u}.{Ja}
+  const double sr = A.r + B.r;
+  double f0, pp, e4;
+  if (VF == 0) {
+    // {rho}{u.Ja}, {u} F_rho + {p}{Ja}, F_rho {H}
+    f0 = 0.25 * sr * un;
+    pp = 0.5 * (A.b + B.b);
+    e4 = 0.5 * (A.q + B.q);
+  } else {
+    const double dr = A.r - B.r;
+    const double fr = dr * frcp1(sr);
+    const double ur = fr * fr;
+    double rl;  // rho^ln / 2
+    if (ur < 1e-4)
+      rl = 0.25 * sr * fma(ur, fma(ur, fma(ur, DG_LM_C3, DG_LM_C2), DG_LM_C1), 1.0);
+    else
+      rl = 0.5 * dr / (log(A.r) - log(B.r));
+    const double sb = A.b + B.b, db = A.b - B.b;
+    const double rb = frcp(sb);
+    const double fb = db * rb, ub = fb * fb;
+    double eb;  // 1 / (2 (gamma-1) beta^ln)
+    if (ub < 1e-4)
+      eb = kg * rb * fma(ub, fma(ub, fma(ub, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
+    else
+      eb = 0.5 * kg * (log(A.b) - log(B.b)) / db;
+    f0 = rl * un;                // 2 rho^ln {u}.{Ja}
+    pp = 0.5 * sr * rb;          // {rho} / (2 {beta})
+    e4 = eb - 0.25 * (A.q + B.q);
+  }
+  const double hg = 0.5 * f0;
+  F[0] = f0;
+  F[1] = fma(hg, su, pp * nS[0]);
+  F[2] = fma(hg, sv, pp * nS[1]);
+  F[3] = fma(hg, sw, pp * nS[2]);
+  if (VF == 0)
+    F[4] = f0 * e4;
+  else
+    F[4] = fma(0.5, su * F[1] + sv * F[2] + sw * F[3], f0 * e4);
+}
+
+// orders this wave's LDS accesses before and after the call (LDS executes one wave's
+// instructions in order, so lanes of one wave need no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Split-form operator on LGL nodes (eq. semiDiscreteSplit): every unordered pair of nodes on a
 // line is evaluated once; the pair's contribution to the other node goes through an LDS
 // accumulator.  Viscous part in strong form, surface penalty f* s - F_int.N, -1/J, optional RK.
+// With n = 8 nodes per line (N = 7) a 64-lane wave holds one k-plane, so the lines of the first
+// two directions lie inside one wave and their exchange rounds need no workgroup barrier.
 template <int N, bool NS, int VF, int MODE>
 __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  constexpr bool WAVE_LINES = (n == 8);
   constexpr int NP = (5 * n3 > 30 * n2) ? 5 * n3 : 30 * n2;  // partner accumulator / face fluxes
-  __shared__ double sS[5 * n3];   // rho, u, v, w, beta|p
+  __shared__ double sS[6 * n3];   // PS per node
   __shared__ double sJ[3 * n3];   // Ja^dir_d of the current direction
   __shared__ double sV[4 * n3];   // contravariant viscous flux of the current direction (momentum, energy)
   __shared__ double sP[NP];
@@ -605,7 +643,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   if (e >= g.K) return;
   const int t = threadIdx.x;
   const bool act = t < n3;
-  const double gm1 = ph.gamma - 1.0;
+  const double gm1 = ph.gamma - 1.0, kg = 1.0 / gm1;
   const Tab *tb = g.tab;
   for (int c = t; c < n * n; c += NT) sD[c] = tb->D[c];
   if (t < n) { slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t]; }
@@ -654,33 +692,26 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   double Uo[5];
   PS o;
   double p = 0.0;
-  double FvD[3][4];  // contravariant viscous flux per direction (components 1..4)
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
     const Pr5 P = to_prim(Uo, gm1);
     p = P.p;
     o.r = P.rho; o.u = P.u; o.v = P.v; o.w = P.w;
-    o.b = (VF == 1) ? 0.5 * P.rho / P.p : P.p;
-    sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w; sS[4 * n3 + t] = o.b;
-    if (NS) {
-      double go[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double nv[3] = {Jae[(d * 3) * n3 + t], Jae[(d * 3 + 1) * n3 + t], Jae[(d * 3 + 2) * n3 + t]};
-        double F[5];
-        flux_v(P, go, ph, nv, F);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) FvD[d][c] = F[1 + c];
-      }
+    if (VF == 1) {
+      o.b = 0.5 * P.rho / P.p;
+      o.q = P.u * P.u + P.v * P.v + P.w * P.w;
+    } else {
+      o.b = P.p;
+      o.q = (Uo[4] + P.p) / P.rho;
     }
+    sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w; sS[4 * n3 + t] = o.b;
+    sS[5 * n3 + t] = o.q;
   }
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int id3[3] = {t % n, (t / n) % n, t / n2};
   if (act) {
-    // surface penalty [f* s - F_int . N_out] lhat(+-1) on the faces through this node
+    // surface integral, numerical-flux part: lhat(+-1) f* s on the faces through this node
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
       const int id = id3[dir];
@@ -690,30 +721,32 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       const double lh = slh[(sd ? n : 0) + id];
       const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
       const int ab = a + n * b;
-      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
-      const Pr5 P = {o.r, o.u, o.v, o.w, p};
-      double Fc[5];
-      flux_c(Uo, P, nv, Fc);
-      const double sg = sd ? 1.0 : -1.0;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        double fint = Fc[v];
-        if (NS && v > 0) fint -= FvD[dir][v - 1];
-        acc[v] += lh * (sP[(s * 5 + v) * n2 + ab] - sg * fint);
-      }
+      for (int v = 0; v < 5; ++v) acc[v] += lh * sP[(s * 5 + v) * n2 + ab];
     }
   }
+#pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
-    double nvo[3];
+    // exchange rounds of this direction stay inside one wave
+    const bool wl = WAVE_LINES && dir < 2;
+    double nvo[3], fv[4] = {0.0, 0.0, 0.0, 0.0};
     if (act) {
       nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
       sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
       if (NS) {
+        // contravariant viscous flux of this direction (momentum, energy)
+        double go[12];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sV[c * n3 + t] = FvD[dir][c];
+        for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+        const Pr5 P = {o.r, o.u, o.v, o.w, p};
+        double F[5];
+        flux_v(P, go, ph, nvo, F);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { fv[c] = F[1 + c]; sV[c * n3 + t] = fv[c]; }
       }
     }
-    __syncthreads();
+    // the first direction also separates the face-flux reads above from the partner shares
+    if (wl && dir > 0) wave_sync(); else __syncthreads();
     {
       const int id = act ? id3[dir] : 0;
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
@@ -727,33 +760,32 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
           if (jp >= n) jp -= n;
           const int qp = base + jp * str;
           PS bq;
-          bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
-          const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]),
-                                0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+          bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp];
+          bq.b = sS[4 * n3 + qp]; bq.q = sS[5 * n3 + qp];
+          const double nS[3] = {nvo[0] + sJ[qp], nvo[1] + sJ[n3 + qp], nvo[2] + sJ[2 * n3 + qp]};
           double F[5];
-          pair_flux<VF>(o, bq, nm, gm1, F);
+          pair2<VF>(o, bq, nS, kg, F);
           const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
-          const double Dij2 = 2.0 * Dij, Dji2 = 2.0 * Dji;
-          acc[0] += Dij2 * F[0];
-          sP[qp] = Dji2 * F[0];
+          acc[0] = fma(Dij, F[0], acc[0]);
+          sP[qp] = Dji * F[0];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            double own = Dij2 * F[1 + c], oth = Dji2 * F[1 + c];
+            double fo = F[1 + c], fp = F[1 + c];
             if (NS) {
-              own -= Dij * sV[c * n3 + qp];
-              oth -= Dji * FvD[dir][c];
+              fo -= sV[c * n3 + qp];
+              fp -= fv[c];
             }
-            acc[1 + c] += own;
-            sP[(1 + c) * n3 + qp] = oth;
+            acc[1 + c] = fma(Dij, fo, acc[1 + c]);
+            sP[(1 + c) * n3 + qp] = Dji * fp;
           }
         }
         // every node receives exactly one partner share per round: collect it in a fixed order
-        __syncthreads();
+        if (wl) wave_sync(); else __syncthreads();
         if (act) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) acc[v] += sP[v * n3 + t];
         }
-        __syncthreads();
+        if (wl) wave_sync(); else __syncthreads();
       }
       if (act && (n & 1) == 0) {
         // s = n/2 pairs each other twice: each side takes only its own share
@@ -761,35 +793,43 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
         if (jp >= n) jp -= n;
         const int qp = base + jp * str;
         PS bq;
-        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp]; bq.b = sS[4 * n3 + qp];
-        const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]), 0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp];
+        bq.b = sS[4 * n3 + qp]; bq.q = sS[5 * n3 + qp];
+        const double nS[3] = {nvo[0] + sJ[qp], nvo[1] + sJ[n3 + qp], nvo[2] + sJ[2 * n3 + qp]};
         double F[5];
-        pair_flux<VF>(o, bq, nm, gm1, F);
+        pair2<VF>(o, bq, nS, kg, F);
         const double Dij = sD[id * n + jp];
-        acc[0] += 2.0 * Dij * F[0];
+        acc[0] = fma(Dij, F[0], acc[0]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          double own = 2.0 * Dij * F[1 + c];
-          if (NS) own -= Dij * sV[c * n3 + qp];
-          acc[1 + c] += own;
+          double fo = F[1 + c];
+          if (NS) fo -= sV[c * n3 + qp];
+          acc[1 + c] = fma(Dij, fo, acc[1 + c]);
         }
       }
-      // diagonal: F#(U,U) = F(U) . Ja (non-zero D_ii only on the end nodes of LGL lines)
-      const double Dii = act ? sD[id * n + id] : 0.0;
-      if (Dii != 0.0) {
+      if (act && (id == 0 || id == N)) {
+        // end nodes of the line: diagonal F#(U,U) = F(U).Ja (D_ii is non-zero only there on LGL
+        // lines) and the interior-flux part - F_int . N_out lhat(+-1) of the surface integral
         const Pr5 P = {o.r, o.u, o.v, o.w, p};
         double Fc[5];
         flux_c(Uo, P, nvo, Fc);
-        acc[0] += 2.0 * Dii * Fc[0];
+        const double Dii = sD[id * n + id];
+        const bool plus = id == N;
+        const double lh = slh[(plus ? n : 0) + id];
+        const double sl_ = plus ? -lh : lh;
+        acc[0] += 2.0 * Dii * Fc[0] + sl_ * Fc[0];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           double own = 2.0 * Dii * Fc[1 + c];
-          if (NS) own -= Dii * FvD[dir][c];
-          acc[1 + c] += own;
+          if (NS) own -= Dii * fv[c];
+          acc[1 + c] += own + sl_ * (Fc[1 + c] - fv[c]);
         }
       }
     }
-    __syncthreads();  // sJ / sV / sS reads of this direction are done before the next one is staged
+    // sJ / sV reads of this direction are done before the next one is staged
+    if (dir < 2) {
+      if (WAVE_LINES) wave_sync(); else __syncthreads();
+    }
   }
   if (act) {
     const double sj = g.sJ[(size_t)e * n3 + t];
