@@ -49,6 +49,34 @@ template <int N>
 int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double cfl_unused, double *partial,
                   hipStream_t st);
 
+// One ensemble member as the batched kernels see it (entry of a device-resident table).
+struct Member {
+  Geo g;
+  Phys ph;
+  const double *U;  // stage input
+  double *G;        // the member's lifted-gradient scratch
+  double *out;      // stage output
+  double *R;        // 2N-storage register
+  double a, b, dt;  // stage coefficients: R = a R + dt L(U); out = U + b R
+};
+
+// All members of one degree N: m[0..count), element prefix sums first[0..count] (device),
+// total = first[count]; tab = the 1D tables of degree N (identical for every member).
+struct BatchView {
+  const Member *m;
+  const int *first;
+  int count, total;
+  const Tab *tab;
+};
+
+// elements per workgroup the batched kernels are built for (1, 2, 4 up to this bound)
+__host__ __device__ constexpr int batch_max_epb(int N) { return N <= 3 ? 4 : (N <= 5 ? 2 : 1); }
+
+template <int N>
+int launch_batch_lift(const BatchView &bv, int epb, hipStream_t st);
+template <int N>
+int launch_batch_split(const BatchView &bv, bool ns, int vf, int epb, hipStream_t st);
+
 // what codes for launch_reduce
 enum { RED_TIMESTEP = 0, RED_INTEGRALS = 1, RED_FINITE = 2 };
 

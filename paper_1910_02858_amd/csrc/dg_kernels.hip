@@ -220,26 +220,35 @@ __device__ __forceinline__ int xcd_element(int b, int K) {
 }
 
 // ----------------------------------------------------------------------------- lifting
-template <int N, bool LGL>
-__global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                                  double *__restrict__ G) {
-  using S = Sz<N>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  __shared__ double sW[4 * n3];
-  __shared__ double sJa[3 * n3];
-  __shared__ double sWs[6 * 4 * n2];
-  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
-  const int e = blockIdx.x;
-  const int t = threadIdx.x;
-  const double gm1 = ph.gamma - 1.0;
-  const Tab *tb = g.tab;
-  for (int c = t; c < n * n; c += NT) sDh[c] = tb->Dh[c];
+// LDS sizes (doubles) of one element in the lifting kernel
+template <int N> struct LiftLds {
+  static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int W = 4 * n3, JA = 3 * n3, WS = 24 * n2;
+};
+
+// 1D tables of the lifting kernel into LDS (by the first threads of the workgroup)
+template <int N>
+__device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, double *sDh, double *sl, double *slh) {
+  constexpr int n = N + 1;
+  for (int c = t; c < n * n; c += nthreads) sDh[c] = tb->Dh[c];
   if (t < n) {
     sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
     slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
   }
+}
+
+// BR1 lifting of element e by the NT threads t of one slot.  valid = false keeps the slot's
+// threads in step with the workgroup barriers without touching memory.
+template <int N, bool LGL>
+__device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
+                                          const double *__restrict__ U, double *__restrict__ G, double *sW,
+                                          double *sJa, double *sWs, const double *sDh, const double *sl,
+                                          const double *slh) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  const double gm1 = ph.gamma - 1.0;
   const double *Ue = U + (size_t)e * 5 * n3;
-  if (t < n3) {
+  if (valid && t < n3) {
     double Uq[5], W[4];
 #pragma unroll
     for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + t];
@@ -249,7 +258,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
   }
   __syncthreads();
   // W* = mean of the two traces on every face point of the element
-  for (int p = t; p < 6 * n2; p += NT) {
+  for (int p = valid ? t : 6 * n2; p < 6 * n2; p += NT) {
     const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
@@ -290,9 +299,10 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
   for (int dir = 0; dir < 3; ++dir) {
     __syncthreads();
     const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3;
-    for (int c = t; c < 3 * n3; c += NT) sJa[c] = Jd[c];
+    if (valid)
+      for (int c = t; c < 3 * n3; c += NT) sJa[c] = Jd[c];
     __syncthreads();
-    if (t < n3) {
+    if (valid && t < n3) {
       const int id = dir == 0 ? i : (dir == 1 ? j : k);
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
       const int base = t - id * str;
@@ -324,7 +334,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
       }
     }
   }
-  if (!LGL && t < n3) {
+  if (!LGL && valid && t < n3) {
     // surface: lhat(+-1) [W* nt_d] on each side
     for (int s = 0; s < 6; ++s) {
       const int dn = s >> 1;
@@ -343,12 +353,23 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
       }
     }
   }
-  if (t < n3) {
+  if (valid && t < n3) {
     const double sj = g.sJ[(size_t)e * n3 + t];
     double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
     for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c] * sj;
   }
+}
+
+template <int N, bool LGL>
+__global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+                                                                  double *__restrict__ G) {
+  using L = LiftLds<N>;
+  constexpr int n = L::n;
+  __shared__ double sW[L::W], sJa[L::JA], sWs[L::WS];
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
+  lift_body<N, LGL>(g, ph, blockIdx.x, true, threadIdx.x, U, G, sW, sJa, sWs, sDh, sl, slh);
 }
 
 // ----------------------------------------------------------------------------- operator
@@ -613,6 +634,23 @@ __device__ __forceinline__ void pair2(const PS &A, const PS &B, const double *nS
     F[4] = fma(0.5, su * F[1] + sv * F[2] + sw * F[3], f0 * e4);
 }
 
+// partner state from the LDS copy (rho, u, v, w, beta|H); the sixth field is derived:
+// |u|^2 for EC, p = ((gamma-1)/gamma) rho (H - |u|^2/2) for KEP and central (gg = (gamma-1)/gamma)
+template <int VF>
+__device__ __forceinline__ PS load_ps(const double *sS, int n3, int q, double gg) {
+  PS s;
+  s.r = sS[q]; s.u = sS[n3 + q]; s.v = sS[2 * n3 + q]; s.w = sS[3 * n3 + q];
+  const double q2 = s.u * s.u + s.v * s.v + s.w * s.w;
+  if (VF == 1) {
+    s.b = sS[4 * n3 + q];
+    s.q = q2;
+  } else {
+    s.q = sS[4 * n3 + q];
+    s.b = gg * s.r * (s.q - 0.5 * q2);
+  }
+  return s;
+}
+
 // orders this wave's LDS accesses before and after the call (LDS executes one wave's
 // instructions in order, so lanes of one wave need no workgroup barrier)
 __device__ __forceinline__ void wave_sync() {
@@ -621,37 +659,51 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Split-form operator on LGL nodes (eq. semiDiscreteSplit): every unordered pair of nodes on a
-// line is evaluated once; the pair's contribution to the other node goes through an LDS
-// accumulator.  Viscous part in strong form, surface penalty f* s - F_int.N, -1/J, optional RK.
-// With n = 8 nodes per line (N = 7) a 64-lane wave holds one k-plane, so the lines of the first
-// two directions lie inside one wave and their exchange rounds need no workgroup barrier.
+// LDS sizes (doubles) of one element in the split-form kernel.  Region A first holds the
+// contravariant viscous fluxes of the three directions (12 per node), then the two-point state
+// (5 per node) and the metric terms Ja^i_d (9 per node); region P first holds the six faces'
+// numerical fluxes, then the partner shares of the exchange rounds.
+template <int N> struct SplitLds {
+  static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int A = 14 * n3;
+  static constexpr int P = (5 * n3 > 30 * n2) ? 5 * n3 : 30 * n2;
+};
+
+template <int N>
+__device__ __forceinline__ void split_tables(const Tab *tb, int t, int nthreads, double *sD, double *slh) {
+  constexpr int n = N + 1;
+  for (int c = t; c < n * n; c += nthreads) sD[c] = tb->D[c];
+  if (t < n) { slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t]; }
+}
+
+// exchange rounds of direction dir stay inside one 64-lane wave: lines of the first two
+// directions when n divides 64 and n^2 divides 64 (n = 2, 4, 8); every line when the whole
+// element fits one wave
+template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
+  return (n * n * n <= 64) || (dir < 2 && (n == 2 || n == 4 || n == 8));
+}
+
+// Split-form operator on LGL nodes (eq. semiDiscreteSplit) for element e by the NT threads t of
+// one slot: every unordered pair of nodes on a line is evaluated once; the pair's contribution
+// to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
+// penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
+// order their exchange rounds with a wave fence instead of a workgroup barrier.
 template <int N, bool NS, int VF, int MODE>
-__global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
-                                                     const double *__restrict__ G, double *__restrict__ out,
-                                                     double *__restrict__ R, double ca, double cb, double dt) {
+__device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
+                                           const double *__restrict__ U, const double *__restrict__ G,
+                                           double *__restrict__ out, double *__restrict__ R, double ca, double cb,
+                                           double dt, double *sA, double *sP, const double *sD, const double *slh) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  constexpr bool WAVE_LINES = (n == 8);
-  constexpr int NP = (5 * n3 > 30 * n2) ? 5 * n3 : 30 * n2;  // partner accumulator / face fluxes
-  __shared__ double sS[6 * n3];   // PS per node
-  __shared__ double sJ[3 * n3];   // Ja^dir_d of the current direction
-  __shared__ double sV[4 * n3];   // contravariant viscous flux of the current direction (momentum, energy)
-  __shared__ double sP[NP];
-  __shared__ double sD[n * n], slh[2 * n];
-  const int e = xcd_element(blockIdx.x, g.K);
-  if (e >= g.K) return;
-  const int t = threadIdx.x;
-  const bool act = t < n3;
-  const double gm1 = ph.gamma - 1.0, kg = 1.0 / gm1;
-  const Tab *tb = g.tab;
-  for (int c = t; c < n * n; c += NT) sD[c] = tb->D[c];
-  if (t < n) { slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t]; }
+  const bool act = valid && t < n3;
+  const double gm1 = ph.gamma - 1.0, kg = 1.0 / gm1, gg = gm1 / ph.gamma;
   const double *Ue = U + (size_t)e * 5 * n3;
   const double *Ge = G + (size_t)e * 12 * n3;
   const double *Jae = g.Ja + (size_t)e * 9 * n3;
+  double *sS = sA;           // rho, u, v, w, beta (EC) or H (KEP, central) per node
+  double *sJ = sA + 5 * n3;  // Ja^i_d at (i*3+d)*n3 + node
   // numerical surface flux on the six faces, stored outward for this element
-  for (int q = t; q < 6 * n2; q += NT) {
+  for (int q = valid ? t : 6 * n2; q < 6 * n2; q += NT) {
     const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
@@ -705,8 +757,6 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       o.b = P.p;
       o.q = (Uo[4] + P.p) / P.rho;
     }
-    sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w; sS[4 * n3 + t] = o.b;
-    sS[5 * n3 + t] = o.q;
   }
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int id3[3] = {t % n, (t / n) % n, t / n2};
@@ -725,110 +775,135 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       for (int v = 0; v < 5; ++v) acc[v] += lh * sP[(s * 5 + v) * n2 + ab];
     }
   }
+  double ja[9];
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = Jae[c * n3 + t];
+  }
+  if (NS) {
+    // viscous part in strong form: -sum_a D_ia Fv^dir_a along each line, and -Fv.N_out lhat(+-1)
+    // on the faces through the node.  The contravariant viscous fluxes of all three directions
+    // are staged once in region A.
+    double *sF = sA;
+    if (act) {
+      double go[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+      const double mu = ph.mu, div = go[0] + go[5] + go[10];
+      const double t00 = mu * (2.0 * go[0] - (2.0 / 3.0) * div);
+      const double t11 = mu * (2.0 * go[5] - (2.0 / 3.0) * div);
+      const double t22 = mu * (2.0 * go[10] - (2.0 / 3.0) * div);
+      const double t01 = mu * (go[4] + go[1]);
+      const double t02 = mu * (go[8] + go[2]);
+      const double t12 = mu * (go[9] + go[6]);
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const double *nv = ja + 3 * dir;
+        double fv[4];
+        fv[0] = t00 * nv[0] + t01 * nv[1] + t02 * nv[2];
+        fv[1] = t01 * nv[0] + t11 * nv[1] + t12 * nv[2];
+        fv[2] = t02 * nv[0] + t12 * nv[1] + t22 * nv[2];
+        fv[3] = fv[0] * o.u + fv[1] * o.v + fv[2] * o.w +
+                ph.kappa * (go[3] * nv[0] + go[7] * nv[1] + go[11] * nv[2]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sF[(dir * 4 + c) * n3 + t] = fv[c];
+        const int id = id3[dir];
+        if (id == 0 || id == N) {
+          const bool plus = id == N;
+          const double lh = slh[(plus ? n : 0) + id];
+          const double sl_ = plus ? -lh : lh;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[1 + c] -= sl_ * fv[c];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const int id = id3[dir];
+        const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+        const int base = t - id * str;
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+          const double D = sD[id * n + m];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[1 + c] -= D * sF[(dir * 4 + c) * n3 + base + m * str];
+        }
+      }
+    }
+    __syncthreads();  // region A is reused below
+  }
+  if (act) {
+    sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w;
+    sS[4 * n3 + t] = (VF == 1) ? o.b : o.q;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sJ[c * n3 + t] = ja[c];
+  }
+  // the first direction's barrier also separates the face-flux reads above from the partner
+  // shares and publishes the staged state of every node
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
-    // exchange rounds of this direction stay inside one wave
-    const bool wl = WAVE_LINES && dir < 2;
-    double nvo[3], fv[4] = {0.0, 0.0, 0.0, 0.0};
-    if (act) {
-      nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
-      sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
-      if (NS) {
-        // contravariant viscous flux of this direction (momentum, energy)
-        double go[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
-        const Pr5 P = {o.r, o.u, o.v, o.w, p};
-        double F[5];
-        flux_v(P, go, ph, nvo, F);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) { fv[c] = F[1 + c]; sV[c * n3 + t] = fv[c]; }
-      }
-    }
-    // the first direction also separates the face-flux reads above from the partner shares
-    if (wl && dir > 0) wave_sync(); else __syncthreads();
-    {
-      const int id = act ? id3[dir] : 0;
-      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
-      const int base = t - id * str;
-      // pairs (id, id+s mod n), s = 1 .. (n-1)/2: each unordered pair once, both nodes updated
+    const bool wl = wave_local<n>(dir);
+    if (dir > 0 && wl) wave_sync(); else __syncthreads();
+    const double *sJd = sJ + 3 * dir * n3;
+    double nvo[3] = {0.0, 0.0, 0.0};
+    if (act) { nvo[0] = sJd[t]; nvo[1] = sJd[n3 + t]; nvo[2] = sJd[2 * n3 + t]; }
+    const int id = act ? id3[dir] : 0;
+    const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+    const int base = t - id * str;
+    // pairs (id, id+s mod n), s = 1 .. (n-1)/2: each unordered pair once, both nodes updated
 #pragma unroll 1
-      for (int sft = 1; sft <= (n - 1) / 2; ++sft) {
-        // barriers stay in uniform control flow: only the work is guarded
-        if (act) {
-          int jp = id + sft;
-          if (jp >= n) jp -= n;
-          const int qp = base + jp * str;
-          PS bq;
-          bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp];
-          bq.b = sS[4 * n3 + qp]; bq.q = sS[5 * n3 + qp];
-          const double nS[3] = {nvo[0] + sJ[qp], nvo[1] + sJ[n3 + qp], nvo[2] + sJ[2 * n3 + qp]};
-          double F[5];
-          pair2<VF>(o, bq, nS, kg, F);
-          const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
-          acc[0] = fma(Dij, F[0], acc[0]);
-          sP[qp] = Dji * F[0];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            double fo = F[1 + c], fp = F[1 + c];
-            if (NS) {
-              fo -= sV[c * n3 + qp];
-              fp -= fv[c];
-            }
-            acc[1 + c] = fma(Dij, fo, acc[1 + c]);
-            sP[(1 + c) * n3 + qp] = Dji * fp;
-          }
-        }
-        // every node receives exactly one partner share per round: collect it in a fixed order
-        if (wl) wave_sync(); else __syncthreads();
-        if (act) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v] += sP[v * n3 + t];
-        }
-        if (wl) wave_sync(); else __syncthreads();
-      }
-      if (act && (n & 1) == 0) {
-        // s = n/2 pairs each other twice: each side takes only its own share
-        int jp = id + n / 2;
+    for (int sft = 1; sft <= (n - 1) / 2; ++sft) {
+      // barriers stay in uniform control flow: only the work is guarded
+      if (act) {
+        int jp = id + sft;
         if (jp >= n) jp -= n;
         const int qp = base + jp * str;
-        PS bq;
-        bq.r = sS[qp]; bq.u = sS[n3 + qp]; bq.v = sS[2 * n3 + qp]; bq.w = sS[3 * n3 + qp];
-        bq.b = sS[4 * n3 + qp]; bq.q = sS[5 * n3 + qp];
-        const double nS[3] = {nvo[0] + sJ[qp], nvo[1] + sJ[n3 + qp], nvo[2] + sJ[2 * n3 + qp]};
+        const PS bq = load_ps<VF>(sS, n3, qp, gg);
+        const double nS[3] = {nvo[0] + sJd[qp], nvo[1] + sJd[n3 + qp], nvo[2] + sJd[2 * n3 + qp]};
         double F[5];
         pair2<VF>(o, bq, nS, kg, F);
-        const double Dij = sD[id * n + jp];
-        acc[0] = fma(Dij, F[0], acc[0]);
+        const double Dij = sD[id * n + jp], Dji = sD[jp * n + id];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double fo = F[1 + c];
-          if (NS) fo -= sV[c * n3 + qp];
-          acc[1 + c] = fma(Dij, fo, acc[1 + c]);
+        for (int v = 0; v < 5; ++v) {
+          acc[v] = fma(Dij, F[v], acc[v]);
+          sP[v * n3 + qp] = Dji * F[v];
         }
       }
-      if (act && (id == 0 || id == N)) {
-        // end nodes of the line: diagonal F#(U,U) = F(U).Ja (D_ii is non-zero only there on LGL
-        // lines) and the interior-flux part - F_int . N_out lhat(+-1) of the surface integral
-        const Pr5 P = {o.r, o.u, o.v, o.w, p};
-        double Fc[5];
-        flux_c(Uo, P, nvo, Fc);
-        const double Dii = sD[id * n + id];
-        const bool plus = id == N;
-        const double lh = slh[(plus ? n : 0) + id];
-        const double sl_ = plus ? -lh : lh;
-        acc[0] += 2.0 * Dii * Fc[0] + sl_ * Fc[0];
+      // every node receives exactly one partner share per round: collect it in a fixed order
+      if (wl) wave_sync(); else __syncthreads();
+      if (act) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double own = 2.0 * Dii * Fc[1 + c];
-          if (NS) own -= Dii * fv[c];
-          acc[1 + c] += own + sl_ * (Fc[1 + c] - fv[c]);
-        }
+        for (int v = 0; v < 5; ++v) acc[v] += sP[v * n3 + t];
       }
+      if (wl) wave_sync(); else __syncthreads();
     }
-    // sJ / sV reads of this direction are done before the next one is staged
-    if (dir < 2) {
-      if (WAVE_LINES) wave_sync(); else __syncthreads();
+    if (act && (n & 1) == 0) {
+      // s = n/2 pairs each other twice: each side takes only its own share
+      int jp = id + n / 2;
+      if (jp >= n) jp -= n;
+      const int qp = base + jp * str;
+      const PS bq = load_ps<VF>(sS, n3, qp, gg);
+      const double nS[3] = {nvo[0] + sJd[qp], nvo[1] + sJd[n3 + qp], nvo[2] + sJd[2 * n3 + qp]};
+      double F[5];
+      pair2<VF>(o, bq, nS, kg, F);
+      const double Dij = sD[id * n + jp];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] = fma(Dij, F[v], acc[v]);
+    }
+    if (act && (id == 0 || id == N)) {
+      // end nodes of the line: diagonal F#(U,U) = F(U).Ja (D_ii is non-zero only there on LGL
+      // lines) and the interior convective part - F_int . N_out lhat(+-1) of the surface integral
+      const Pr5 P = {o.r, o.u, o.v, o.w, p};
+      double Fc[5];
+      flux_c(Uo, P, nvo, Fc);
+      const double Dii = sD[id * n + id];
+      const bool plus = id == N;
+      const double lh = slh[(plus ? n : 0) + id];
+      const double cd = 2.0 * Dii + (plus ? -lh : lh);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] += cd * Fc[v];
     }
   }
   if (act) {
@@ -847,6 +922,74 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
       }
     }
   }
+}
+
+template <int N, bool NS, int VF, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
+                                                     const double *__restrict__ G, double *__restrict__ out,
+                                                     double *__restrict__ R, double ca, double cb, double dt) {
+  using L = SplitLds<N>;
+  constexpr int n = L::n;
+  __shared__ double sA[L::A], sP[L::P];
+  __shared__ double sD[n * n], slh[2 * n];
+  split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
+  const int e = xcd_element(blockIdx.x, g.K);
+  if (e >= g.K) return;
+  split_body<N, NS, VF, MODE>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
+}
+
+// ----------------------------------------------------------------------------- ensemble batch
+// Workgroups of the batched kernels walk the concatenated element list of all members of one
+// degree; EPB elements share a workgroup (one slot of Sz<N>::NT threads each, wave aligned).
+// Each slot finds its member by bisection of the element prefix sums.
+__device__ __forceinline__ int member_of(const int *first, int count, int item) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int N, int EPB>
+__global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchView bv) {
+  using L = LiftLds<N>;
+  constexpr int n = L::n, NT = Sz<N>::NT;
+  __shared__ double sW[EPB * L::W], sJa[EPB * L::JA], sWs[EPB * L::WS];
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  lift_tables<N>(bv.tab, threadIdx.x, NT * EPB, sDh, sl, slh);
+  const int nblk = (bv.total + EPB - 1) / EPB;
+  const int blk = xcd_element(blockIdx.x, nblk);
+  if (blk >= nblk) return;
+  const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
+  const int t = threadIdx.x - slot * NT;
+  const int item = blk * EPB + slot;
+  const bool valid = item < bv.total;
+  const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
+  const Member &M = bv.m[mi];
+  lift_body<N, true>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, sW + slot * L::W,
+                     sJa + slot * L::JA, sWs + slot * L::WS, sDh, sl, slh);
+}
+
+template <int N, bool NS, int VF, int EPB>
+__global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_SPLIT_MINB) k_split_b(BatchView bv) {
+  using L = SplitLds<N>;
+  constexpr int n = L::n, NT = Sz<N>::NT;
+  __shared__ double sA[EPB * L::A], sP[EPB * L::P];
+  __shared__ double sD[n * n], slh[2 * n];
+  split_tables<N>(bv.tab, threadIdx.x, NT * EPB, sD, slh);
+  const int nblk = (bv.total + EPB - 1) / EPB;
+  const int blk = xcd_element(blockIdx.x, nblk);
+  if (blk >= nblk) return;
+  const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
+  const int t = threadIdx.x - slot * NT;
+  const int item = blk * EPB + slot;
+  const bool valid = item < bv.total;
+  const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
+  const Member &M = bv.m[mi];
+  split_body<N, NS, VF, 1>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, M.out, M.R, M.a, M.b,
+                           M.dt, sA + slot * L::A, sP + slot * L::P, sD, slh);
 }
 
 // ----------------------------------------------------------------------------- reductions
@@ -988,6 +1131,53 @@ int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const
   return launch_form<N, false, false>(g, ph, form, U, G, out, R, a, b, dt, mode, st);
 }
 
+template <int N, int EPB>
+static int launch_batch_lift_t(const BatchView &bv, hipStream_t st) {
+  const int nblk = (bv.total + EPB - 1) / EPB;
+  hipLaunchKernelGGL((k_lift_b<N, EPB>), dim3(8 * ((nblk + 7) / 8)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N, bool NS, int VF, int EPB>
+static int launch_batch_split_t(const BatchView &bv, hipStream_t st) {
+  const int nblk = (bv.total + EPB - 1) / EPB;
+  hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB>), dim3(8 * ((nblk + 7) / 8)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N, bool NS, int EPB>
+static int launch_batch_split_vf(const BatchView &bv, int vf, hipStream_t st) {
+  if (vf == DG_VF_EC) return launch_batch_split_t<N, NS, 1, EPB>(bv, st);
+  if (vf == DG_VF_KEP) return launch_batch_split_t<N, NS, 0, EPB>(bv, st);
+  return launch_batch_split_t<N, NS, 2, EPB>(bv, st);
+}
+
+template <int N>
+int launch_batch_lift(const BatchView &bv, int epb, hipStream_t st) {
+  if (bv.total <= 0) return DG_OK;
+  if (epb == 1) return launch_batch_lift_t<N, 1>(bv, st);
+  if constexpr (batch_max_epb(N) >= 2)
+    if (epb == 2) return launch_batch_lift_t<N, 2>(bv, st);
+  if constexpr (batch_max_epb(N) >= 4)
+    if (epb == 4) return launch_batch_lift_t<N, 4>(bv, st);
+  return DG_ERR_UNSUPPORTED;
+}
+
+template <int N>
+int launch_batch_split(const BatchView &bv, bool ns, int vf, int epb, hipStream_t st) {
+  if (bv.total <= 0) return DG_OK;
+  if (epb == 1) return ns ? launch_batch_split_vf<N, true, 1>(bv, vf, st) : launch_batch_split_vf<N, false, 1>(bv, vf, st);
+  if constexpr (batch_max_epb(N) >= 2)
+    if (epb == 2)
+      return ns ? launch_batch_split_vf<N, true, 2>(bv, vf, st) : launch_batch_split_vf<N, false, 2>(bv, vf, st);
+  if constexpr (batch_max_epb(N) >= 4)
+    if (epb == 4)
+      return ns ? launch_batch_split_vf<N, true, 4>(bv, vf, st) : launch_batch_split_vf<N, false, 4>(bv, vf, st);
+  return DG_ERR_UNSUPPORTED;
+}
+
 template <int N>
 int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double, double *partial, hipStream_t st) {
   hipLaunchKernelGGL((k_reduce<N>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, what, U, partial);
@@ -1078,6 +1268,8 @@ template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, const doubl
 template int launch_main<DG_ONLY_N>(const Geo &, const Phys &, bool, int, int, const double *, const double *,
                                     double *, double *, double, double, double, int, hipStream_t);
 template int launch_reduce<DG_ONLY_N>(const Geo &, const Phys &, int, const double *, double, double *, hipStream_t);
+template int launch_batch_lift<DG_ONLY_N>(const BatchView &, int, hipStream_t);
+template int launch_batch_split<DG_ONLY_N>(const BatchView &, bool, int, int, hipStream_t);
 #endif
 
 }  // namespace dg
