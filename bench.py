@@ -85,6 +85,56 @@ def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2):
             "workload": wl.name, "dof": S.K * S.n3, "steps": wl.steps, "checkpoint_every": 10}
 
 
+def ensemble_bench(dgsem, inputs, torch, steps: int = 10, n_members: int = 256):
+    """Seeded ensemble of uneven members (K1 ~ U{4..12}, N ~ U{3..7}, amplitude and Mach drawn per
+    member; split KEP + Roe + BR1, TGV): DOF updates per second of whole RK steps for
+    (a) the batched step replayed as one HIP graph, (b) the batched stages launched eagerly and
+    (c) every member advanced with its own one-mesh launches, all on the same GPU."""
+    wls = inputs.ensemble_draw(n_members, 0)
+    sols, U0s = [], []
+    for wl in wls:
+        S, U = dgsem.build_solver(wl)
+        sols.append(S)
+        U0s.append(U)
+    dts = [S.timestep(U, wl.cfl, wl.dfl) for S, U, wl in zip(sols, U0s, wls)]
+    dof = sum(S.K * S.n3 for S in sols)
+    B = dgsem.Batch(sols)
+    tiles = B.tune(U0s, repeats=3)
+    cur = [U.clone() for U in U0s]
+    nxt = [S.empty() for S in sols]
+    Rs = [torch.zeros_like(U) for U in U0s]
+
+    def batched(nsteps, graph):
+        nonlocal cur, nxt
+        for _ in range(nsteps):
+            B.step(cur, nxt, Rs, dts, graph=graph)
+            cur, nxt = nxt, cur
+
+    def unbatched(nsteps):
+        nonlocal cur, nxt
+        a, b, _ = dgsem.rk_coefficients()
+        for _ in range(nsteps):
+            for s in range(5):
+                for S, u, o, R, dt in zip(sols, cur, nxt, Rs, dts):
+                    S.rk_stage(u, o, R, a[s], b[s], dt)
+                cur, nxt = nxt, cur
+
+    out = {"members": len(sols), "dof": dof, "steps": steps, "tiles": [list(t) for t in tiles]}
+    for name, fn in (("batched_graph", lambda k: batched(k, True)), ("batched_eager", lambda k: batched(k, False)),
+                     ("per_member_launches", unbatched)):
+        fn(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = dof * 5 * steps / wall
+    if not all(S.check_finite(u) for S, u in zip(sols, cur)):
+        raise RuntimeError("non-finite ensemble state")
+    out["speedup_vs_per_member"] = out["batched_graph"] / out["per_member_launches"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +144,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--profile-stages", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -186,6 +237,8 @@ def main():
         adj = adjoint_ratio(dgsem, inputs, torch)
         out["adjoint_forward_ratio"] = adj["value"]
         out["adjoint"] = adj
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_bench(dgsem, inputs, torch)
     if not args.no_cpu:
         cb = cpu_baseline(wl)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

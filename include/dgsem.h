@@ -154,13 +154,46 @@ void dg_destroy(dg_handle *h);
 const char *dg_status_string(int status);
 const char *dg_last_error(const dg_handle *h);
 
-/* ---- batched ensembles: many independent handles advanced by one launch per stage ----
- * The members keep their own meshes, degrees and schemes (LGL split/strong forms);
- * dg_batch_rk_stage applies dg_rk_stage to every member with its own a[i], b[i], dt[i]
- * using one persistent kernel launch per kernel phase on the stream of members[0]. */
+/* ---- batched ensembles ------------------------------------------------------------------
+ * Not in the paper: advances many independent handles together so that small meshes fill the
+ * GPU.  Every member keeps its own mesh, degree N, viscosity (mu, Pr) and time step; all members
+ * share the equations, the volume flux and the Riemann solver, and use the split form on LGL
+ * nodes.  A stage launches, for each degree present, one lifting kernel (Navier-Stokes) and one
+ * operator kernel over the concatenated elements of all members of that degree, on the stream
+ * of members[0] (read at every call).  Members are referenced, not copied: they must outlive
+ * the batch, and their gradient scratch is used by the batch's kernels.  Arrays passed below
+ * have one entry per member, in the order given to dg_batch_create.
+ *
+ * dg_batch_create  -> DG_ERR_UNSUPPORTED if a member is not split/LGL or the schemes differ;
+ *                     DG_ERR_ARG for NULL entries or a member listed twice.
+ * dg_batch_rk_stage: for every member i, dg_rk_stage(member i, U_in[i], U_out[i], R[i], a[i],
+ *                     b_coef[i], dt[i]) (same semantics: a = 0 does not read R; the three
+ *                     buffers must be distinct).  Asynchronous.  Descriptor tables of the
+ *                     distinct argument sets seen are uploaded once (first use of a set is
+ *                     synchronous) and cached (at most 64).
+ * dg_batch_step    : one full step of the five-stage scheme of dg_rk_coefficients for every
+ *                     member: reads U[i], leaves the new state in U_out[i]; U[i] (overwritten
+ *                     with the fourth stage) and R[i] are working storage.  use_graph != 0
+ *                     captures the five stages into a HIP graph on first use of an argument set
+ *                     and replays it afterwards (ordered after the caller's queued work on the
+ *                     members[0] stream, and later work on that stream after it).
+ * dg_batch_tune    : times every elements-per-workgroup choice (1, 2, 4 as built for the
+ *                     degree) of both kernels of every degree on the states U (read only;
+ *                     repeats launches per choice, scratch outputs allocated and freed here) and
+ *                     keeps the fastest.  Synchronous.  Without it every choice is 1.
+ * dg_batch_set_tile: fixes the choices of degree N by hand.
+ * dg_batch_info    : writes N, members, elements, elements per workgroup of the lifting and of
+ *                     the operator kernel for each degree present (5 ints each, up to cap ints)
+ *                     and returns the number of degrees. */
 int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out);
 int dg_batch_rk_stage(dg_batch *b, const double *const *U_in, double *const *U_out, double *const *R,
                       const double *a, const double *b_coef, const double *dt);
+int dg_batch_step(dg_batch *b, double *const *U, double *const *U_out, double *const *R, const double *dt,
+                  int use_graph);
+int dg_batch_tune(dg_batch *b, const double *const *U, int repeats);
+int dg_batch_set_tile(dg_batch *b, int N, int epb_lift, int epb_main);
+int dg_batch_info(const dg_batch *b, int *out, int cap);
+const char *dg_batch_last_error(const dg_batch *b);
 void dg_batch_destroy(dg_batch *b);
 
 #ifdef __cplusplus

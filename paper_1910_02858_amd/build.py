@@ -27,6 +27,13 @@ COMMON = [
 ]
 
 
+HOST_SOURCES = ("dg_host.cpp", "dg_batch.cpp")
+
+
+def _host_obj(src: str) -> str:
+    return "host_" + src.split(".")[0] + ".o"
+
+
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,12 +45,9 @@ def kernel_units():
     units = [("dg_kernels.hip", [], "k_common.o")]
     for n in range(1, NMAX + 1):
         units.append(("dg_kernels.hip", [f"-DDG_ONLY_N={n}"], f"k_n{n}.o"))
-    for extra in ("dg_vjp.hip", "dg_batch.hip"):
-        if os.path.exists(os.path.join(CSRC, extra)):
-            base = extra.split(".")[0]
-            units.append((extra, [], f"{base}_common.o"))
-            for n in range(1, NMAX + 1):
-                units.append((extra, [f"-DDG_ONLY_N={n}"], f"{base}_n{n}.o"))
+    units.append(("dg_vjp.hip", [], "dg_vjp_common.o"))
+    for n in range(1, NMAX + 1):
+        units.append(("dg_vjp.hip", [f"-DDG_ONLY_N={n}"], f"dg_vjp_n{n}.o"))
     return units
 
 
@@ -54,14 +58,15 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     cmds = []
     for src, defs, obj in units:
         cmds.append([HIPCC, *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)])
-    cmds.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, "dg_host.cpp"), "-o", os.path.join(BUILD, "host.o")])
+    for src in HOST_SOURCES:
+        cmds.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, _host_obj(src))])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_run, c) for c in cmds]
         for f in futs:
             r = f.result()
             if verbose and (r.stderr.strip()):
                 print(r.stderr)
-    objs = [os.path.join(BUILD, o) for _, _, o in units] + [os.path.join(BUILD, "host.o")]
+    objs = [os.path.join(BUILD, o) for _, _, o in units] + [os.path.join(BUILD, _host_obj(s)) for s in HOST_SOURCES]
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, OUT)

@@ -721,18 +721,6 @@ int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_b
   return DG_OK;
 }
 
-int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {
-  (void)members; (void)n_members;
-  if (out) *out = nullptr;
-  return DG_ERR_UNSUPPORTED;
-}
 
-int dg_batch_rk_stage(dg_batch *b, const double *const *U_in, double *const *U_out, double *const *R, const double *a,
-                      const double *b_coef, const double *dt) {
-  (void)b; (void)U_in; (void)U_out; (void)R; (void)a; (void)b_coef; (void)dt;
-  return DG_ERR_UNSUPPORTED;
-}
-
-void dg_batch_destroy(dg_batch *b) { (void)b; }
 
 }  // extern "C"

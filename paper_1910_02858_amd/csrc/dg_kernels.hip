@@ -546,7 +546,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double ut = -acc[v] * sj;
-        const double r = ca * Re[v * n3 + t] + dt * ut;
+        // a = 0 (first stage) does not read R, so R may hold anything on entry
+        const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * ut;
         Re[v * n3 + t] = r;
         Oe[v * n3 + t] = Uo[v] + cb * r;
       }
@@ -916,7 +917,8 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       double *Re = R + (size_t)e * 5 * n3;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const double r = ca * Re[v * n3 + t] + dt * (-acc[v] * sj);
+        // a = 0 (first stage) does not read R, so R may hold anything on entry
+        const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * (-acc[v] * sj);
         Re[v * n3 + t] = r;
         Oe[v * n3 + t] = Uo[v] + cb * r;
       }

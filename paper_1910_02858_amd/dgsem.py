@@ -28,7 +28,8 @@ EXPORTS = [
     "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
-    "dg_profile_read", "dg_host_geometry", "dg_mass_weights",
+    "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
+    "dg_batch_info", "dg_batch_last_error",
 ]
 
 
@@ -90,6 +91,12 @@ def lib():
         L.dg_batch_rk_stage.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, _D, _D]
         L.dg_batch_destroy.argtypes = [_VP]
         L.dg_batch_destroy.restype = None
+        L.dg_batch_step.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, ctypes.c_int]
+        L.dg_batch_tune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.c_int]
+        L.dg_batch_set_tile.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.dg_batch_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        L.dg_batch_last_error.restype = ctypes.c_char_p
+        L.dg_batch_last_error.argtypes = [_VP]
         _lib = L
     return _lib
 
@@ -263,6 +270,83 @@ class DGSolver:
                 self.rk_stage(cur, nxt, R, a[s], b[s], dt)
                 cur, nxt = nxt, cur
         return cur
+
+
+class Batch:
+    """Several solvers advanced together (``dg_batch``): one lifting and one operator launch per
+    degree present and stage, optionally one HIP graph per RK step.  All solvers must use the
+    split form on LGL nodes with the same equations, volume flux and Riemann solver."""
+
+    def __init__(self, solvers):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        self.n = n
+        hs = (_VP * n)(*[S.h for S in self.solvers])
+        b = _VP()
+        rc = lib().dg_batch_create(hs, n, ctypes.byref(b))
+        if rc:
+            raise DGError(rc, "dg_batch_create")
+        self.b = b
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value and _lib is not None:
+            _lib.dg_batch_destroy(b)
+            self.b = None
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().dg_batch_last_error(self.b)
+            raise DGError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _ptrs(self, ts):
+        if len(ts) != self.n:
+            raise ValueError(f"expected {self.n} tensors, got {len(ts)}")
+        for S, t in zip(self.solvers, ts):
+            if tuple(t.shape) != S.shape:
+                raise ValueError("tensor shape does not match its solver")
+        return (_VP * self.n)(*[_dptr(t) for t in ts])
+
+    def _dbl(self, x):
+        v = np.ascontiguousarray(np.broadcast_to(np.asarray(x, np.float64), (self.n,)))
+        return v, _ptr(v)
+
+    def _sync_stream(self):
+        self.solvers[0]._sync_stream()
+
+    def rk_stage(self, U_in, U_out, R, a, b, dt):
+        """For every member i: R_i = a_i R_i + dt_i L_i(U_in_i); U_out_i = U_in_i + b_i R_i."""
+        self._sync_stream()
+        av, ap = self._dbl(a)
+        bv, bp = self._dbl(b)
+        dv, dp = self._dbl(dt)
+        self._check(lib().dg_batch_rk_stage(self.b, self._ptrs(U_in), self._ptrs(U_out), self._ptrs(R), ap, bp, dp),
+                    "dg_batch_rk_stage")
+
+    def step(self, U, U_out, R, dt, graph: bool = True):
+        """One full RK step of every member: U_out_i = step(U_i); U_i and R_i are working storage."""
+        self._sync_stream()
+        dv, dp = self._dbl(dt)
+        self._check(lib().dg_batch_step(self.b, self._ptrs(U), self._ptrs(U_out), self._ptrs(R), dp, int(graph)),
+                    "dg_batch_step")
+
+    def tune(self, U, repeats: int = 3):
+        self._sync_stream()
+        self._check(lib().dg_batch_tune(self.b, self._ptrs(U), repeats), "dg_batch_tune")
+        return self.info()
+
+    def set_tile(self, N: int, epb_lift: int, epb_main: int):
+        self._check(lib().dg_batch_set_tile(self.b, N, epb_lift, epb_main), "dg_batch_set_tile")
+
+    def info(self):
+        """[(N, members, elements, elements per workgroup of lifting, of operator)] per degree."""
+        buf = (ctypes.c_int * (5 * 8))()
+        ng = lib().dg_batch_info(self.b, buf, 5 * 8)
+        if ng < 0:
+            raise DGError(ng, "dg_batch_info")
+        return [tuple(buf[5 * i:5 * i + 5]) for i in range(ng)]
 
 
 def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[bool] = None):

@@ -1,0 +1,190 @@
+"""Batched ensembles (dg_batch_*): members of different degrees, sizes and viscosities advanced
+together must give, member by member, exactly the bits of the one-mesh entry points (the
+kernels share the per-element code, and the order of every floating-point operation is the
+same); the graph-replayed step must equal the eager step on every replay; every tile choice of
+the tuner must give the same bits; one member is also checked against the oracle after several
+batched steps (1e-10, the RK parity bar).
+"""
+import numpy as np
+import pytest
+
+from paper_1910_02858_amd import inputs
+from gpu_common import norm_err, problem, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    from paper_1910_02858_amd import dgsem
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+# (N, K1, curved, amplitude, Mach): every degree 1..8 at least once, two members of degree 3
+MEMBERS = [(3, 3, False, 0.7, 0.12), (5, 2, True, 1.3, 0.08), (7, 2, False, 1.0, 0.1), (4, 3, False, 0.9, 0.15),
+           (3, 2, True, 1.4, 0.06), (6, 2, False, 0.6, 0.18), (1, 3, False, 1.1, 0.1), (2, 2, True, 0.8, 0.2),
+           (8, 1, False, 1.2, 0.1)]
+
+
+def make_members(dg, volflux="kep", eqn="ns", seed=0):
+    import torch
+    sols, U0s = [], []
+    for j, (N, K1, cv, A, Ma) in enumerate(MEMBERS):
+        wl = inputs.workload(4, N=N, K1=K1, curved=cv, amp=A, mach=Ma, volflux=volflux, eqn=eqn)
+        S, U = dg.build_solver(wl)
+        U = torch.from_numpy(inputs.random_perturbation(U.cpu().numpy(), seed + j, 1e-2)).cuda()
+        sols.append(S)
+        U0s.append(U)
+    return sols, U0s
+
+
+def rand_like(U, seed):
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    return torch.randn(U.shape, generator=g, dtype=torch.float64).cuda()
+
+
+@pytest.mark.parametrize("volflux,eqn", [("kep", "ns"), ("ec", "ns"), ("kep", "euler")])
+def test_batched_stage_equals_member_stages(dg, volflux, eqn):
+    import torch
+    sols, U0s = make_members(dg, volflux, eqn)
+    B = dg.Batch(sols)
+    dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    a, b, _ = dg.rk_coefficients()
+    R0 = [rand_like(U, 10 + i) * 1e-3 for i, U in enumerate(U0s)]
+    ref = []
+    for S, U, R, dt in zip(sols, U0s, R0, dts):
+        out, Rr = S.empty(), R.clone()
+        S.rk_stage(U, out, Rr, a[2], b[2], dt)
+        ref.append((out, Rr))
+    degrees = sorted({m[0] for m in MEMBERS})
+    for tile in (1, 2, 4):
+        # every degree at this many elements per workgroup, or its largest built choice
+        for N in degrees:
+            mx = 4 if N <= 3 else (2 if N <= 5 else 1)
+            t = min(tile, mx)
+            B.set_tile(N, t, t)
+        outs = [S.empty() for S in sols]
+        Rs = [R.clone() for R in R0]
+        B.rk_stage(U0s, outs, Rs, a[2], b[2], dts)
+        torch.cuda.synchronize()
+        for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
+            assert torch.equal(o, ro), f"member {i} (N={MEMBERS[i][0]}) U_out differs at tile {tile}"
+            assert torch.equal(Rb, rR), f"member {i} R differs at tile {tile}"
+
+
+def test_first_stage_ignores_R(dg):
+    import torch
+    sols, U0s = make_members(dg)
+    B = dg.Batch(sols)
+    dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    a, b, _ = dg.rk_coefficients()
+    assert a[0] == 0.0
+    outs1 = [S.empty() for S in sols]
+    outs2 = [S.empty() for S in sols]
+    R1 = [torch.full_like(U, float("nan")) for U in U0s]
+    R2 = [torch.zeros_like(U) for U in U0s]
+    B.rk_stage(U0s, outs1, R1, a[0], b[0], dts)
+    B.rk_stage(U0s, outs2, R2, a[0], b[0], dts)
+    torch.cuda.synchronize()
+    for o1, o2, r1, r2 in zip(outs1, outs2, R1, R2):
+        assert torch.equal(o1, o2) and torch.equal(r1, r2)
+
+
+def test_graph_step_equals_eager_and_member_steps(dg):
+    import torch
+    sols, U0s = make_members(dg)
+    B = dg.Batch(sols)
+    dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    # member by member, one-mesh entry points
+    ref = []
+    for S, U, dt in zip(sols, U0s, dts):
+        ref.append(S.steps(U.clone(), 1, dt))
+    # batched, eager
+    Ue = [U.clone() for U in U0s]
+    Oe = [S.empty() for S in sols]
+    Re = [torch.zeros_like(U) for U in U0s]
+    B.step(Ue, Oe, Re, dts, graph=False)
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(Oe, ref)):
+        assert torch.equal(o, r), f"eager batched step differs for member {i}"
+    # batched, graph: three replays on the same buffers with eager work between them
+    Ug = [S.empty() for S in sols]
+    Og = [S.empty() for S in sols]
+    Rg = [S.empty() for S in sols]
+    for rep in range(3):
+        for u, U in zip(Ug, U0s):
+            u.copy_(U)
+        for r in Rg:
+            r.fill_(float("nan"))  # the first stage must not read R
+        B.step(Ug, Og, Rg, dts, graph=True)
+        junk = [S.rhs(U) for S, U in zip(sols, U0s)]  # unrelated work on the same stream
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(Og, ref)):
+            assert torch.equal(o, r), f"graph replay {rep} differs for member {i}"
+        del junk
+
+
+def test_tuned_tiles_and_oracle_parity(dg, orc):
+    import torch
+    sols, U0s = make_members(dg)
+    B = dg.Batch(sols)
+    info = B.tune(U0s, repeats=2)
+    degrees = sorted({m[0] for m in MEMBERS})
+    assert [t[0] for t in info] == degrees
+    for N, count, elems, el, em in info:
+        mx = 4 if N <= 3 else (2 if N <= 5 else 1)
+        assert el in (1, 2, 4) and em in (1, 2, 4) and el <= mx and em <= mx
+        assert count == sum(1 for m in MEMBERS if m[0] == N)
+        assert elems == sum(m[1] ** 3 for m in MEMBERS if m[0] == N)
+    dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    steps = 4
+    cur = [U.clone() for U in U0s]
+    nxt = [S.empty() for S in sols]
+    Rs = [S.empty() for S in sols]
+    for _ in range(steps):
+        B.step(cur, nxt, Rs, dts, graph=True)
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    # member 1: N=5 curved; the oracle integrates the same initial state on its own mesh
+    j = 1
+    N, K1, cv, A, Ma = MEMBERS[j]
+    wl = inputs.workload(4, N=N, K1=K1, curved=cv, amp=A, mach=Ma)
+    M, xgeo, nbr, side, _ = problem(orc, wl, perturb=0)
+    Uo = M.rk(orc.Scheme.of(wl), U0s[j].cpu().numpy(), steps, dts[j])
+    err = norm_err(cur[j].cpu().numpy(), Uo)
+    print(f"batched member N={N} after {steps} steps: normwise error {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_batch_argument_errors(dg):
+    import torch
+    sols, U0s = make_members(dg)
+    wl = inputs.workload(4, N=3, K1=2, volflux="ec")
+    S_ec, _ = dg.build_solver(wl)
+    with pytest.raises(dg.DGError) as ei:
+        dg.Batch([sols[0], S_ec])
+    assert ei.value.code == -3
+    wlw = inputs.workload(1, N=3, K1=2)
+    S_weak, _ = dg.build_solver(wlw)
+    with pytest.raises(dg.DGError) as ei:
+        dg.Batch([S_weak])
+    assert ei.value.code == -3
+    with pytest.raises(dg.DGError) as ei:
+        dg.Batch([sols[0], sols[0]])
+    assert ei.value.code == -1
+    B = dg.Batch(sols[:2])
+    outs = [S.empty() for S in sols[:2]]
+    Rs = [torch.zeros_like(U) for U in U0s[:2]]
+    with pytest.raises(dg.DGError) as ei:
+        B.rk_stage(U0s[:2], [U0s[0], outs[1]], Rs, 0.0, 0.1, 1e-3)
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError) as ei:
+        B.rk_stage(U0s[:2], outs, Rs, 0.0, 0.1, float("nan"))
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError) as ei:
+        B.set_tile(7, 2, 1)
+    assert ei.value.code == -1

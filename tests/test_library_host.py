@@ -113,6 +113,16 @@ def test_null_arguments(dg):
     assert L.dg_rhs(None, None, None) == -1
     assert L.dg_rk_stage(None, None, None, None, 0.0, 0.0, 0.0) == -1
     assert L.dg_nodes(0, 1, None, None) == -1
+    b = ctypes.c_void_p()
+    assert L.dg_batch_create(None, 0, ctypes.byref(b)) == -1 and not b.value
+    assert L.dg_batch_create(None, 1, None) == -1
+    assert L.dg_batch_rk_stage(None, None, None, None, None, None, None) == -1
+    assert L.dg_batch_step(None, None, None, None, None, 1) == -1
+    assert L.dg_batch_tune(None, None, 1) == -1
+    assert L.dg_batch_set_tile(None, 3, 1, 1) == -1
+    assert L.dg_batch_info(None, None, 0) == -1
+    assert L.dg_batch_last_error(None) == b"no batch"
+    L.dg_batch_destroy(None)
 
 
 @pytest.mark.parametrize("N", [3, 5, 7])
