@@ -33,6 +33,39 @@ BYTES_MAIN = 42 * 8   # U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5
 BYTES_LIFT = 27 * 8   # U 5 + Ja 9 + 1/J 1 read, grad W 12 written
 
 
+# HBM traffic of the split kernel from committed counter summaries: FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch) of one rocprofv3 --pmc pass each, scaled by the factors a 1 GiB
+# device-to-device copy gives on the same box; valid only while the kernel sources still hash
+# to the value recorded with the counters.
+COUNTERS = os.path.join(ROOT, "profiles", "k_split_ns_ec_n7_k48_counters.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_02858_amd", "csrc", f) for f in ("dg_kernels.hip", "dg_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """(bytes per launch, source hash matches) from the committed counter summary, or (None, False)."""
+    try:
+        kv = {}
+        with open(COUNTERS) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        fetch = float(kv["FETCH_SIZE_KiB"]) * float(kv["fetch_scale"])
+        write = float(kv["WRITE_SIZE_KiB"]) * float(kv["write_scale"])
+        return (fetch + write) * 1024.0, kv.get("kernel_source_sha256") == kernel_source_hash()
+    except (OSError, KeyError, ValueError):
+        return None, False
+
+
 def cpu_baseline(wl, budget_s: float = 12.0):
     """Time the oracle's RK stage on a bounded sample of the same workload (12^3 elements, N=7)."""
     from oracle import oracle as orc
@@ -206,6 +239,8 @@ def main():
 
     stages = args.steps * 5
     value = dof * stages / wall
+    tbytes, tvalid = counter_traffic()
+    traffic_gbs = tbytes / (main_ms * 1e-3) / 1e9 if (tbytes is not None and tvalid and args.elements == 48) else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -226,7 +261,8 @@ def main():
         "ms_per_stage": wall * 1e3 / stages,
         "kernels_ms": {"main": main_ms, "lift": lift_ms},
         "roofline": {"bound": "hbm", "kernel": "k_main (split volume + surface + RK update)", "achieved": main_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
+                     "traffic_bytes_per_launch": tbytes if traffic_gbs is not None else None,
                      "algorithmic_bytes_per_dof": BYTES_MAIN},
         "roofline_lift": {"achieved": lift_gbs, "frac": lift_gbs / HBM_PEAK_GBS,
                           "algorithmic_bytes_per_dof": BYTES_LIFT},

@@ -111,8 +111,10 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for LGL split/strong forms; derivative of |x| at 0 and of max at a tie are
- * the mean of the one-sided derivatives.  Device arrays [K][5][n^3], pairwise distinct. */
+ * Supported for the split form on LGL nodes with the KEP or central volume flux
+ * (DG_ERR_UNSUPPORTED otherwise) and N <= 7; the derivative of |x| at 0 and of max at a tie
+ * is the mean of the one-sided derivatives.  Device arrays [K][5][n^3], pairwise distinct.
+ * Not in the paper: the reverse of its operator, for gradients of objectives of U. */
 int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_bar);
 
 /* Reverse of dg_rk_stage at the stage input U_in.  On entry U_bar, R_bar hold the
@@ -120,6 +122,22 @@ int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_ba
  * (U_in, R before the stage):
  *   R_bar <- R_bar + b*U_bar;  U_bar <- U_bar + dt*(dL/dU)(U_in)^T R_bar;  R_bar <- a*R_bar. */
 int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt);
+
+/* dg_rk_stage that also keeps the lifted gradients of U_in in G_out (Navier-Stokes: device
+ * [K][12][n^3], caller-owned, distinct from the solution buffers; ignored for Euler), so that a
+ * reverse sweep over recomputed stages need not lift again. */
+int dg_rk_stage_keep(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt,
+                     double *G_out);
+
+/* Reverse of one full step of the five-stage scheme of dg_rk_coefficients with time step dt.
+ * stage_U[s] (s = 0..4) is the input of stage s; stage_G[s] its gradients from
+ * dg_rk_stage_keep, or NULL (the array or an entry) to recompute them.  On entry U_bar and R_bar
+ * hold the adjoints of the step's output state and R; on return those of its input state and
+ * of R before the step (zero, as the first stage does not read R).  Same result as the five
+ * dg_rk_stage_vjp calls in reverse order, with the register updates of neighbouring stages
+ * merged. */
+int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *const *stage_G, double *U_bar,
+                   double *R_bar, double dt);
 
 /* Largest stable step (eqs. CFLCondition and DFLCondition with gamma_RK = 1, evaluated per
  * reference direction from the metric terms).  Synchronous; result in *dt_out (host). */

@@ -50,6 +50,17 @@ DGFN void cons_adj(const P &q, double gm1, const PA &a, double *Ub) {
   Ub[4] += a.p * gm1;
 }
 
+// a conservative adjoint Ub expressed as a primitive adjoint: a += (dU/dP)^T Ub, so that
+// cons_adj maps it back to Ub (U = (rho, rho u, rho v, rho w, p/(gamma-1) + rho |u|^2/2))
+DGFN void prim_adj_of_cons(const P &q, double gm1, const double *Ub, PA &a) {
+  const double q2 = q.u * q.u + q.v * q.v + q.w * q.w;
+  a.r += Ub[0] + q.u * Ub[1] + q.v * Ub[2] + q.w * Ub[3] + 0.5 * q2 * Ub[4];
+  a.u += q.r * (Ub[1] + q.u * Ub[4]);
+  a.v += q.r * (Ub[2] + q.v * Ub[4]);
+  a.w += q.r * (Ub[3] + q.w * Ub[4]);
+  a.p += Ub[4] / gm1;
+}
+
 // total enthalpy H = g1 p / rho + |u|^2 / 2 with g1 = gamma / (gamma - 1)
 DGFN double enthalpy(const P &q, double g1) { return g1 * q.p / q.r + 0.5 * (q.u * q.u + q.v * q.v + q.w * q.w); }
 

@@ -348,41 +348,46 @@ template <class T> int dev_alloc(T **p, size_t count) {
   return DG_OK;
 }
 
-int lift_dispatch(dg_handle *h, const double *U) {
+// lifted gradients of U into G (the handle's scratch unless the caller keeps them)
+int lift_dispatch(dg_handle *h, const double *U, double *G) {
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, U, h->d_G, h->stream);
+  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, U, G, h->stream);
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return DG_ERR_UNSUPPORTED;
   }
 }
 
-int main_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode) {
+int main_dispatch(dg_handle *h, const double *U, const double *G, double *out, double *R, double a, double b,
+                  double dt, int mode) {
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
   switch (h->N) {
 #define DG_CASE(NN) \
   case NN: \
-    return dg::launch_main<NN>(g, h->ph, lgl, h->sc.eqn, h->sc.form, U, h->d_G, out, R, a, b, dt, mode, h->stream);
+    return dg::launch_main<NN>(g, h->ph, lgl, h->sc.eqn, h->sc.form, U, G, out, R, a, b, dt, mode, h->stream);
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return DG_ERR_UNSUPPORTED;
   }
 }
 
-// lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on
-int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode) {
+// lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on;
+// the gradients go to G (the handle's scratch by default)
+int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode,
+                 double *G = nullptr) {
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
+  if (!G) G = h->d_G;
   if (h->prof) (void)hipEventRecord(h->ev[0], h->stream);
   if (ns) {
-    int rc = lift_dispatch(h, U);
+    int rc = lift_dispatch(h, U, G);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
-  int rc = main_dispatch(h, U, out, R, a, b, dt, mode);
+  int rc = main_dispatch(h, U, G, out, R, a, b, dt, mode);
   if (rc) return rc;
   if (h->prof) {
     (void)hipEventRecord(h->ev[2], h->stream);
@@ -426,6 +431,12 @@ int check_solution_ptr(dg_handle *h, const void *p, const char *name) {
 bool overlap(const void *a, const void *b, size_t bytes) {
   const char *x = (const char *)a, *y = (const char *)b;
   return x < y + bytes && y < x + bytes;
+}
+
+// [a, a + abytes) and [b, b + bbytes) intersect
+bool overlap2(const void *a, size_t abytes, const void *b, size_t bbytes) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bbytes && y < x + abytes;
 }
 
 }  // namespace
@@ -658,7 +669,10 @@ void dg_destroy(dg_handle *h) {
 }
 
 namespace {
-int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, double scale, int accumulate) {
+// Ub (+)= scale (dL/dU)(U)^T Utb; Gin = lifted gradients of U if the caller kept them, else
+// they are recomputed into the handle's scratch
+int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, double scale, int accumulate,
+                 const double *Gin = nullptr) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
   if (h->sc.volflux == DG_VF_EC)
@@ -668,15 +682,16 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
     int rc = dev_alloc(&h->d_Gbar, (size_t)h->K * 12 * h->n3);
     if (rc) return fail(h, rc, "allocation of the gradient adjoint failed");
   }
-  if (ns) {
-    int rc = lift_dispatch(h, U);  // forward lifting at U (the reverse needs G)
+  if (ns && !Gin) {
+    int rc = lift_dispatch(h, U, h->d_G);  // forward lifting at U (the reverse needs G)
     if (rc) return fail(h, rc, "launch of the lifting kernel failed");
+    Gin = h->d_G;
   }
   const dg::Geo g = h->geo();
   int rc;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, h->d_G, h->d_Gbar, Utb, Ub, scale, accumulate, h->stream); break;
+  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Gbar, Utb, Ub, scale, accumulate, h->stream); break;
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: rc = DG_ERR_UNSUPPORTED;
@@ -717,6 +732,57 @@ int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_b
   if (rc) return rc;
   // R_bar <- a R_bar
   rc = dg::launch_axpby(R_bar, R_bar, a, 0.0, n, h->stream);
+  if (rc) return fail(h, rc, "launch failed");
+  return DG_OK;
+}
+
+int dg_rk_stage_keep(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt,
+                     double *G_out) {
+  if (!h) return DG_ERR_ARG;
+  int rc = check_solution_ptr(h, U_in, "U_in");
+  if (!rc) rc = check_solution_ptr(h, U_out, "U_out");
+  if (!rc) rc = check_solution_ptr(h, R, "R");
+  if (rc) return rc;
+  const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
+  if (ns && (!G_out || !aligned8(G_out))) return fail(h, DG_ERR_ARG, "G_out is NULL or not 8-byte aligned");
+  const size_t bytes = (size_t)h->K * 5 * h->n3 * sizeof(double), gbytes = (size_t)h->K * 12 * h->n3 * sizeof(double);
+  if (overlap(U_in, U_out, bytes) || overlap(U_in, R, bytes) || overlap(U_out, R, bytes))
+    return fail(h, DG_ERR_ARG, "U_in, U_out and R must be three distinct buffers");
+  if (ns && (overlap2(G_out, gbytes, U_in, bytes) || overlap2(G_out, gbytes, U_out, bytes) ||
+             overlap2(G_out, gbytes, R, bytes)))
+    return fail(h, DG_ERR_ARG, "G_out overlaps a solution buffer");
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite coefficient");
+  rc = rhs_dispatch(h, U_in, U_out, R, a, b, dt, 1, ns ? G_out : nullptr);
+  if (rc) return fail(h, rc, "launch of the operator failed");
+  return DG_OK;
+}
+
+int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *const *stage_G, double *U_bar,
+                   double *R_bar, double dt) {
+  if (!h) return DG_ERR_ARG;
+  if (!stage_U) return fail(h, DG_ERR_ARG, "stage_U is NULL");
+  int rc = check_solution_ptr(h, U_bar, "U_bar");
+  if (!rc) rc = check_solution_ptr(h, R_bar, "R_bar");
+  for (int s = 0; s < 5 && !rc; ++s) rc = check_solution_ptr(h, stage_U[s], "stage_U[s]");
+  if (rc) return rc;
+  const size_t n = (size_t)h->K * 5 * h->n3, bytes = n * sizeof(double);
+  if (overlap(U_bar, R_bar, bytes)) return fail(h, DG_ERR_ARG, "U_bar and R_bar overlap");
+  for (int s = 0; s < 5; ++s)
+    if (overlap(stage_U[s], U_bar, bytes) || overlap(stage_U[s], R_bar, bytes))
+      return fail(h, DG_ERR_ARG, "a stage input overlaps U_bar or R_bar");
+  if (!std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite time step");
+  double A[5], B[5], C[5];
+  dg_rk_coefficients(A, B, C);
+  for (int s = 4; s >= 0; --s) {
+    // R_bar <- a_{s+1} R_bar + b_s U_bar: the register update of stage s+1's reverse fused with
+    // the entry of stage s's reverse
+    rc = dg::launch_axpby(R_bar, U_bar, s == 4 ? 1.0 : A[s + 1], B[s], n, h->stream);
+    if (rc) return fail(h, rc, "launch failed");
+    const double *Gs = (stage_G && stage_G[s]) ? stage_G[s] : nullptr;
+    rc = vjp_dispatch(h, stage_U[s], R_bar, U_bar, dt, 1, Gs);
+    if (rc) return rc;
+  }
+  rc = dg::launch_axpby(R_bar, R_bar, A[0], 0.0, n, h->stream);
   if (rc) return fail(h, rc, "launch failed");
   return DG_OK;
 }

@@ -369,7 +369,9 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
   __shared__ double sW[L::W], sJa[L::JA], sWs[L::WS];
   __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
   lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
-  lift_body<N, LGL>(g, ph, blockIdx.x, true, threadIdx.x, U, G, sW, sJa, sWs, sDh, sl, slh);
+  const int e = xcd_element(blockIdx.x, g.K);
+  if (e >= g.K) return;
+  lift_body<N, LGL>(g, ph, e, true, threadIdx.x, U, G, sW, sJa, sWs, sDh, sl, slh);
 }
 
 // ----------------------------------------------------------------------------- operator
@@ -1114,7 +1116,7 @@ static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, 
 
 template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double *G, hipStream_t st) {
-  dim3 grid(g.K), block(Sz<N>::NT);
+  dim3 grid(8 * ((g.K + 7) / 8)), block(Sz<N>::NT);
   if (lgl) hipLaunchKernelGGL((k_lift<N, true>), grid, block, 0, st, g, ph, U, G);
   else hipLaunchKernelGGL((k_lift<N, false>), grid, block, 0, st, g, ph, U, G);
   DG_CHECK_LAUNCH();
@@ -1236,7 +1238,8 @@ __global__ void k_mass(const double *__restrict__ sJ, const double *__restrict__
   }
 }
 
-__global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, double alpha, double beta, size_t n) {
+// y = alpha y + beta x; x may be y
+__global__ void k_axpby(double *y, const double *x, double alpha, double beta, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) y[i] = alpha * y[i] + beta * x[i];

@@ -22,6 +22,11 @@
 #include "dg_flux.h"
 #include "dg_internal.h"
 
+// minimum waves per SIMD of the operator's vector-Jacobian kernel (caps its registers)
+#ifndef DG_VJP_MINB
+#define DG_VJP_MINB 2
+#endif
+
 namespace dg {
 
 template <int N> struct VSz {
@@ -35,20 +40,21 @@ template <int n> __device__ __forceinline__ int vline_node(int dn, int a, int b,
 
 // ---------------------------------------------------------------------------------- main
 template <int N, bool NS>
-__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
                                                          const double *__restrict__ G,
                                                          const double *__restrict__ Utb, double *__restrict__ Ub,
                                                          double *__restrict__ Gb, double scale, int accumulate) {
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  constexpr int NG = NS ? 12 : 1;
-  __shared__ double sQ[5 * n3];    // primitive state
-  __shared__ double sA[5 * n3];    // Abar = -(1/J) Utbar
-  __shared__ double sJ[3 * n3];    // Ja^dir of the current direction
-  __shared__ double sPA[5 * n3];   // primitive adjoints added by other threads
-  __shared__ double sCB[5 * n3];   // conservative adjoints added by face threads
-  __shared__ double sGb[NG * n3];  // gradient adjoints added by face threads
+  constexpr int NF = NS ? 17 : 5;  // results per face point: primitive adjoint, gradient adjoint
+  constexpr int NX = (NF * 6 * n2 > 8 * n3) ? NF * 6 * n2 : 8 * n3;
+  __shared__ double sQ[5 * n3];  // primitive state
+  __shared__ double sA[5 * n3];  // Abar = -(1/J) Utbar
+  // region X: first the face-point results, then Ja^dir of the current direction (3 per node)
+  // and the partner shares of the pair rounds (5 per node)
+  __shared__ double sX[NX];
   __shared__ double sD[n * n];
+  double *sF = sX, *sJ = sX, *sPA = sX + 3 * n3;
   const int e = blockIdx.x, t = threadIdx.x;
   const bool act = t < n3;
   const double gamma = ph.gamma, gm1 = gamma - 1.0, g1 = gamma / gm1;
@@ -68,21 +74,14 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const d
     sQ[t] = q.r; sQ[n3 + t] = q.u; sQ[2 * n3 + t] = q.v; sQ[3 * n3 + t] = q.w; sQ[4 * n3 + t] = q.p;
     const double sj = sJe[t];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      sA[v * n3 + t] = -sj * Utb[((size_t)e * 5 + v) * n3 + t];
-      sPA[v * n3 + t] = 0.0;
-      sCB[v * n3 + t] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < NG; ++c) sGb[c * n3 + t] = 0.0;
+    for (int v = 0; v < 5; ++v) sA[v * n3 + t] = -sj * Utb[((size_t)e * 5 + v) * n3 + t];
   }
   __syncthreads();
-  // ---- faces: Fbar = lhat (Abar_master - Abar_slave); own-trace derivative only.  One
-  // direction at a time: its two faces touch disjoint nodes, so plain adds are race-free and
-  // every node sums its face terms in a fixed order.
-  for (int dn = 0; dn < 3; ++dn) {
-  for (int p = t; p < 2 * n2; p += NT) {
-    const int s = 2 * dn + p / n2, ab = p % n2, a = ab % n, b = ab / n;
+  // ---- faces: Fbar = lhat (Abar_master - Abar_slave); own-trace derivative only.  All six
+  // faces at once, one face point per thread; the results wait in LDS per face point and every
+  // node collects its (up to three) face terms in direction order.
+  for (int p = t; p < 6 * n2; p += NT) {
+    const int s = p / n2, ab = p % n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
@@ -112,8 +111,11 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const d
     for (int v = 0; v < 5; ++v) Fbs[v] = Fb[v] * sh;
     dgf::riemann_adj(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, bM, bS);
     const double *bo = plus ? bM : bS;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sCB[v * n3 + qo] += bo[v];
+    const dgf::P Po = plus ? PM : PS;
+    // the conservative adjoint of the own trace, carried as a primitive adjoint (the final
+    // (dP/dU)^T map returns it unchanged)
+    dgf::PA pc = dgf::zero_pa();
+    dgf::prim_adj_of_cons(Po, gm1, bo, pc);
     if (NS) {
       // F contains -1/2 Fv(U_own, G_own) . nt
       double go[12], gbo[12];
@@ -122,35 +124,40 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const d
       double Fvb[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
-      dgf::PA pa = dgf::zero_pa();
-      const dgf::P Po = plus ? PM : PS;
-      dgf::visc_flux_adj(Po, go, ph.mu, ph.kappa, nt, Fvb, pa, gbo);
-      sPA[0 * n3 + qo] += pa.r;
-      sPA[1 * n3 + qo] += pa.u;
-      sPA[2 * n3 + qo] += pa.v;
-      sPA[3 * n3 + qo] += pa.w;
-      sPA[4 * n3 + qo] += pa.p;
+      dgf::visc_flux_adj(Po, go, ph.mu, ph.kappa, nt, Fvb, pc, gbo);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sGb[c * n3 + qo] += gbo[c];
+      for (int c = 0; c < 12; ++c) sF[(5 + c) * 6 * n2 + p] = gbo[c];
     }
+    sF[0 * 6 * n2 + p] = pc.r;
+    sF[1 * 6 * n2 + p] = pc.u;
+    sF[2 * 6 * n2 + p] = pc.v;
+    sF[3 * 6 * n2 + p] = pc.w;
+    sF[4 * 6 * n2 + p] = pc.p;
   }
   __syncthreads();
-  }
-  // ---- face contributions into registers; sPA is reused for the pair exchange below
   dgf::PA pa = dgf::zero_pa();
-  double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (act) {
-    pa.r = sPA[t]; pa.u = sPA[n3 + t]; pa.v = sPA[2 * n3 + t]; pa.w = sPA[3 * n3 + t]; pa.p = sPA[4 * n3 + t];
+  double gbf[12];  // gradient adjoint of the face terms at this node
 #pragma unroll
-    for (int v = 0; v < 5; ++v) cb[v] = sCB[v * n3 + t];
-  }
-  // ---- interior flux F_int = Fc . Ja - Fv on the faces through this node
-  double fvb[3][4];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) fvb[d][c] = 0.0;
+  for (int c = 0; c < 12; ++c) gbf[c] = 0.0;
   const int id3[3] = {t % n, (t / n) % n, t / n2};
+  if (act) {
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      const int id = id3[dir];
+      if (id != 0 && id != N) continue;
+      const int s = 2 * dir + (id == N ? 1 : 0);
+      const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+      const int p = s * n2 + a + n * b;
+      pa.r += sF[p]; pa.u += sF[6 * n2 + p]; pa.v += sF[2 * 6 * n2 + p]; pa.w += sF[3 * 6 * n2 + p];
+      pa.p += sF[4 * 6 * n2 + p];
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gbf[c] += sF[(5 + c) * 6 * n2 + p];
+      }
+    }
+  }
+  double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // ---- interior convective flux F_int = Fc . Ja on the faces through this node
   if (act) {
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
@@ -162,11 +169,39 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const d
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fib[v] = -lh * sg * sA[v * n3 + t];
       dgf::euler_flux_adj(q, nv, g1, Fib, pa);
-      if (NS) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fvb[dir][c] -= Fib[1 + c];
-      }
     }
+  }
+  // ---- viscous part, all directions before the pair rounds: acc_m -= sum_i D_mi Fv_i gives
+  // Fvbar_i = -sum_m D_mi Abar_m; the interior face term -F_int contributes +lhat sg Abar_i.
+  // The gradient adjoint of this node is final afterwards.
+  if (NS && act) {
+    double go[12], gbo[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) { go[c] = Ge[c * n3 + t]; gbo[c] = gbf[c]; }
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      const int id = id3[dir];
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      double fvb[4] = {0.0, 0.0, 0.0, 0.0};
+      if (id == 0 || id == N) {
+        const double sg = (id == N) ? 1.0 : -1.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fvb[c] -= -lh * sg * sA[(1 + c) * n3 + t];
+      }
+      for (int m = 0; m < n; ++m) {
+        const int qm = base + m * str;
+        const double Dmi = sD[m * n + id];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fvb[c] -= Dmi * sA[(1 + c) * n3 + qm];
+      }
+      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      const double Fvb[5] = {0.0, fvb[0], fvb[1], fvb[2], fvb[3]};
+      dgf::visc_flux_adj(q, go, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
+    }
+    double *Gbe = Gb + (size_t)e * 12 * n3;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) Gbe[c * n3 + t] = scale * gbo[c];
   }
   // ---- volume: pairs, diagonal and viscous transpose, direction by direction
   for (int dir = 0; dir < 3; ++dir) {
@@ -220,42 +255,13 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_main(Geo g, Phys ph, const d
         for (int v = 0; v < 5; ++v) Fb[v] = 2.0 * Dii * Ao[v];
         dgf::euler_flux_adj(q, nvo, g1, Fb, pa);
       }
-      if (NS) {
-        // acc_m -= sum_i D_mi Fv_i  =>  Fvbar_i -= sum_m D_mi Abar_m
-        for (int m = 0; m < n; ++m) {
-          const int qm = base + m * str;
-          const double Dmi = sD[m * n + id];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) fvb[dir][c] -= Dmi * sA[(1 + c) * n3 + qm];
-        }
-      }
     }
   }
-  __syncthreads();
   if (act) {
-    double gbo[NG];
-#pragma unroll
-    for (int c = 0; c < NG; ++c) gbo[c] = 0.0;
-    if (NS) {
-      double go[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
-#pragma unroll
-      for (int dir = 0; dir < 3; ++dir) {
-        const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
-        const double Fvb[5] = {0.0, fvb[dir][0], fvb[dir][1], fvb[dir][2], fvb[dir][3]};
-        dgf::visc_flux_adj(q, go, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
-      }
-    }
     dgf::cons_adj(q, gm1, pa, cb);
     double *Ube = Ub + (size_t)e * 5 * n3;
 #pragma unroll
     for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = (accumulate ? Ube[v * n3 + t] : 0.0) + scale * cb[v];
-    if (NS) {
-      double *Gbe = Gb + (size_t)e * 12 * n3;
-#pragma unroll
-      for (int c = 0; c < NG; ++c) Gbe[c * n3 + t] = scale * (gbo[c] + sGb[c * n3 + t]);
-    }
   }
 }
 

@@ -163,5 +163,17 @@ int main() {
     }
   }
   report("cons_adj", worst, tol);
+  // conservative adjoint carried through primitive space and back
+  worst = 0;
+  for (int it = 0; it < 200; ++it) {
+    P q = rand_prim(0.8);
+    double Ub[5], back[5] = {0, 0, 0, 0, 0};
+    for (double &x : Ub) x = urand(-1, 1);
+    PA a = zero_pa();
+    prim_adj_of_cons(q, gm1, Ub, a);
+    cons_adj(q, gm1, a, back);
+    for (int j = 0; j < 5; ++j) worst = std::max(worst, std::fabs(back[j] - Ub[j]) / (std::fabs(Ub[j]) + 1e-3));
+  }
+  report("prim_adj_of_cons round trip", worst, 1e-13);
   return failures ? 1 : 0;
 }

@@ -29,7 +29,7 @@ EXPORTS = [
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
-    "dg_batch_info", "dg_batch_last_error",
+    "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp",
 ]
 
 
@@ -72,6 +72,8 @@ def lib():
         L.dg_rk_stage.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.dg_rhs_vjp.argtypes = [_VP, _VP, _VP, _VP]
         L.dg_rk_stage_vjp.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.dg_rk_stage_keep.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, _VP]
+        L.dg_rk_step_vjp.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP, ctypes.c_double]
         L.dg_timestep.argtypes = [_VP, _VP, ctypes.c_double, ctypes.c_double, _D]
         L.dg_integrals.argtypes = [_VP, _VP, _D]
         L.dg_check_finite.argtypes = [_VP, _VP]
@@ -218,6 +220,25 @@ class DGSolver:
         self._sync_stream()
         self._check(lib().dg_rk_stage_vjp(self.h, _VP(_dptr(U_in)), _VP(_dptr(U_bar)), _VP(_dptr(R_bar)), float(a),
                                           float(b), float(dt)), "dg_rk_stage_vjp")
+
+    def empty_grad(self):
+        """device buffer for the lifted gradients of one state, [K][12][n^3]"""
+        return self.torch.empty((self.K, 12, self.n3), dtype=self.torch.float64, device="cuda")
+
+    def rk_stage_keep(self, U_in, U_out, R, a, b, dt, G_out):
+        """rk_stage that keeps the lifted gradients of U_in in G_out (Navier-Stokes)."""
+        self._sync_stream()
+        gp = _VP(_dptr(G_out)) if G_out is not None else _VP()
+        self._check(lib().dg_rk_stage_keep(self.h, _VP(_dptr(U_in)), _VP(_dptr(U_out)), _VP(_dptr(R)), a, b, dt,
+                                           gp), "dg_rk_stage_keep")
+
+    def rk_step_vjp(self, stage_U, stage_G, U_bar, R_bar, dt):
+        """Reverse of one five-stage step given its stage inputs (and kept gradients or None)."""
+        self._sync_stream()
+        su = (_VP * 5)(*[_dptr(u) for u in stage_U])
+        sg = None if stage_G is None else (_VP * 5)(*[(_dptr(g) if g is not None else None) for g in stage_G])
+        self._check(lib().dg_rk_step_vjp(self.h, su, sg, _VP(_dptr(U_bar)), _VP(_dptr(R_bar)), dt),
+                    "dg_rk_step_vjp")
 
     def timestep(self, U, cfl=0.9, dfl=0.9) -> float:
         self._sync_stream()
@@ -415,14 +436,25 @@ def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
 
         @staticmethod
         def backward(ctx, gUT):
+            a, b, _ = rk_coefficients()
             Ubar = gUT.detach().contiguous().clone()
+            Rbar = torch.zeros_like(Ubar)
             nseg = len(ctx.ckpts)
+            ns = S.eqn == "ns"
+            # buffers of one segment, reused: the input of every stage and its lifted gradients
+            nst = 5 * min(ckpt_every, nsteps)
+            bufs = [S.empty() for _ in range(nst + 1)]
+            grads = [S.empty_grad() for _ in range(nst)] if ns else [None] * nst
+            R = torch.empty_like(Ubar)
             for seg in range(nseg - 1, -1, -1):
                 first = seg * ckpt_every
                 steps = min(ckpt_every, nsteps - first)
-                _, inputs = _rollout_forward(S, ctx.ckpts[seg], steps, dt, keep_stage_inputs=True)
-                _rollout_backward(S, inputs, Ubar, dt)
-                del inputs
+                bufs[0].copy_(ctx.ckpts[seg])
+                for idx in range(5 * steps):  # recompute; the first stage does not read R
+                    s = idx % 5
+                    S.rk_stage_keep(bufs[idx], bufs[idx + 1], R, a[s], b[s], dt, grads[idx])
+                for st in range(steps - 1, -1, -1):
+                    S.rk_step_vjp(bufs[5 * st:5 * st + 5], grads[5 * st:5 * st + 5], Ubar, Rbar, dt)
             return Ubar
 
     return _Rollout.apply(U0)

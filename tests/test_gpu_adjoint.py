@@ -138,3 +138,39 @@ def test_kinetic_energy_gradient_vs_central_differences(dg, orc):
         worst = max(worst, rel)
     print(f"worst relative gap gradient vs central differences over 20 directions: {worst:.2e}")
     assert worst <= 1e-6
+
+
+def test_step_vjp_matches_stage_vjps(dg):
+    """dg_rk_step_vjp (register updates of neighbouring stages merged, kept or recomputed
+    gradients) against five dg_rk_stage_vjp calls; dg_rk_stage_keep against dg_rk_stage."""
+    import torch
+    wl = inputs.workload(5, K1=3)
+    S, U0 = dg.build_solver(wl)
+    U0 = to_gpu(inputs.random_perturbation(U0.cpu().numpy(), 4, 1e-3))
+    dt = S.timestep(U0, 0.9, 0.9)
+    a, b, _ = dg.rk_coefficients()
+    bufs = [U0.clone()] + [S.empty() for _ in range(5)]
+    plain = [U0.clone()] + [S.empty() for _ in range(5)]
+    G = [S.empty_grad() for _ in range(5)]
+    R, R2 = torch.zeros_like(U0), torch.zeros_like(U0)
+    for s in range(5):
+        S.rk_stage_keep(bufs[s], bufs[s + 1], R, a[s], b[s], dt, G[s])
+        S.rk_stage(plain[s], plain[s + 1], R2, a[s], b[s], dt)
+    torch.cuda.synchronize()
+    assert torch.equal(bufs[5], plain[5]) and torch.equal(R, R2)
+    rng = np.random.default_rng(8)
+    w = to_gpu(rng.standard_normal(U0.shape))
+    rb = to_gpu(rng.standard_normal(U0.shape))
+    Ub1, Rb1 = w.clone(), rb.clone()
+    for s in range(4, -1, -1):
+        S.rk_stage_vjp(bufs[s], Ub1, Rb1, a[s], b[s], dt)
+    Ub2, Rb2 = w.clone(), rb.clone()
+    S.rk_step_vjp(bufs[:5], G, Ub2, Rb2, dt)
+    Ub3, Rb3 = w.clone(), rb.clone()
+    S.rk_step_vjp(bufs[:5], None, Ub3, Rb3, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(Ub2, Ub3) and torch.equal(Rb2, Rb3)
+    rel = float((Ub1 - Ub2).abs().max() / Ub1.abs().max())
+    print(f"step VJP vs five stage VJPs: max relative difference {rel:.2e}")
+    assert rel <= 1e-13
+    assert float(Rb1.abs().max()) == 0.0 and float(Rb2.abs().max()) == 0.0
