@@ -206,6 +206,12 @@ __device__ __forceinline__ void riemann(const Phys &ph, const double *UL, const 
   for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
 }
 
+// numerical flux of the split-form kernel: as riemann(), with the two-point variants (rs 2, 3)
+// evaluated by the volume flux VF of the kernel (pair2, defined below)
+template <int VF>
+__device__ __forceinline__ void riemann_vf(const Phys &ph, const double *UL, const double *UR, const double *nh,
+                                           double *F);
+
 __device__ __forceinline__ void grad_prim_to_W(const double *U, double gm1, double Rg, double *W) {
   const Pr5 P = to_prim(U, gm1);
   W[0] = P.u; W[1] = P.v; W[2] = P.w; W[3] = P.p / (P.rho * Rg);
@@ -654,6 +660,38 @@ __device__ __forceinline__ PS load_ps(const double *sS, int n3, int q, double gg
   return s;
 }
 
+template <int VF>
+__device__ __forceinline__ void riemann_vf(const Phys &ph, const double *UL, const double *UR, const double *nh,
+                                           double *F) {
+  if (ph.rs < 2) {
+    riemann(ph, UL, UR, nh, F);
+    return;
+  }
+  const double gm1 = ph.gamma - 1.0;
+  const Pr5 L = to_prim(UL, gm1), R = to_prim(UR, gm1);
+  PS a, b;
+  a.r = L.rho; a.u = L.u; a.v = L.v; a.w = L.w;
+  b.r = R.rho; b.u = R.u; b.v = R.v; b.w = R.w;
+  if (VF == 1) {
+    a.b = 0.5 * L.rho / L.p; a.q = L.u * L.u + L.v * L.v + L.w * L.w;
+    b.b = 0.5 * R.rho / R.p; b.q = R.u * R.u + R.v * R.v + R.w * R.w;
+  } else {
+    a.b = L.p; a.q = (UL[4] + L.p) / L.rho;
+    b.b = R.p; b.q = (UR[4] + R.p) / R.rho;
+  }
+  // pair2 along the metric sum nh + nh returns twice the flux along nh
+  const double n2[3] = {2.0 * nh[0], 2.0 * nh[1], 2.0 * nh[2]};
+  pair2<VF>(a, b, n2, 1.0 / gm1, F);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] *= 0.5;
+  if (ph.rs == 3) {
+    double D[5];
+    roe_diss(UL, L, UR, R, nh, gm1, D);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] -= 0.5 * D[v];
+  }
+}
+
 // orders this wave's LDS accesses before and after the call (LDS executes one wave's
 // instructions in order, so lanes of one wave need no workgroup barrier)
 __device__ __forceinline__ void wave_sync() {
@@ -725,7 +763,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
     const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
     double F[5];
-    riemann(ph, UM, US, nh, F);
+    riemann_vf<VF>(ph, UM, US, nh, F);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
     if (NS) {
