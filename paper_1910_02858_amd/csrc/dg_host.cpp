@@ -672,7 +672,7 @@ namespace {
 // Ub (+)= scale (dL/dU)(U)^T Utb; Gin = lifted gradients of U if the caller kept them, else
 // they are recomputed into the handle's scratch
 int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, double scale, int accumulate,
-                 const double *Gin = nullptr) {
+                 const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
   if (h->sc.volflux == DG_VF_EC)
@@ -691,13 +691,18 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
   int rc;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Gbar, Utb, Ub, scale, accumulate, h->stream); break;
+  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Gbar, Utb, Ub, scale, accumulate, \
+                                   ns ? Rb : nullptr, ra, rb, h->stream); break;
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: rc = DG_ERR_UNSUPPORTED;
   }
   if (rc) return fail(h, rc, rc == DG_ERR_UNSUPPORTED ? "vector-Jacobian product not built for this degree"
                                                       : "launch of the vector-Jacobian kernels failed");
+  if (Rb && !ns) {
+    rc = dg::launch_axpby(Rb, Ub, ra, rb, (size_t)h->K * 5 * h->n3, h->stream);
+    if (rc) return fail(h, rc, "launch failed");
+  }
   return DG_OK;
 }
 }  // namespace
@@ -773,17 +778,16 @@ int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *con
   if (!std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite time step");
   double A[5], B[5], C[5];
   dg_rk_coefficients(A, B, C);
+  // R_bar <- R_bar + b_4 U_bar enters the last stage's reverse; after the reverse of stage s the
+  // register update R_bar <- a_s R_bar is merged with the entry of stage s-1,
+  // R_bar <- a_s R_bar + b_{s-1} U_bar, and done by the reverse kernels themselves
+  rc = dg::launch_axpby(R_bar, U_bar, 1.0, B[4], n, h->stream);
+  if (rc) return fail(h, rc, "launch failed");
   for (int s = 4; s >= 0; --s) {
-    // R_bar <- a_{s+1} R_bar + b_s U_bar: the register update of stage s+1's reverse fused with
-    // the entry of stage s's reverse
-    rc = dg::launch_axpby(R_bar, U_bar, s == 4 ? 1.0 : A[s + 1], B[s], n, h->stream);
-    if (rc) return fail(h, rc, "launch failed");
     const double *Gs = (stage_G && stage_G[s]) ? stage_G[s] : nullptr;
-    rc = vjp_dispatch(h, stage_U[s], R_bar, U_bar, dt, 1, Gs);
+    rc = vjp_dispatch(h, stage_U[s], R_bar, U_bar, dt, 1, Gs, R_bar, A[s], s > 0 ? B[s - 1] : 0.0);
     if (rc) return rc;
   }
-  rc = dg::launch_axpby(R_bar, R_bar, A[0], 0.0, n, h->stream);
-  if (rc) return fail(h, rc, "launch failed");
   return DG_OK;
 }
 

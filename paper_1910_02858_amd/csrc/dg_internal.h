@@ -42,9 +42,12 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double 
 template <int N>
 int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const double *U, const double *G,
                 double *out, double *R, double a, double b, double dt, int mode, hipStream_t st);
+// Ubar (+)= scale (dL/dU)^T Ubar_t; for Navier-Stokes with Rb != NULL the lifting-transpose kernel
+// then also sets Rb = ra Rb + rb Ubar (Euler: the caller updates Rb)
 template <int N>
 int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
-               const double *Ubar_t, double *Ubar, double scale, int accumulate, hipStream_t st);
+               const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
+               hipStream_t st);
 template <int N>
 int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double cfl_unused, double *partial,
                   hipStream_t st);

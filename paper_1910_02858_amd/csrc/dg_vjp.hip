@@ -267,9 +267,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
 
 // ---------------------------------------------------------------------------------- lifting
 // Ubar += (dW/dU)^T Wbar, Wbar = transpose of G = (1/J)[sum Dhat Ja W + lhat nt (W + W_nb)/2]
+// With upd != 0 the register of the 2N scheme is updated from the final U_bar of each own node,
+// Rb = ra Rb + rb Ubar (the element reads no Rb, so this is race-free).
 template <int N>
 __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                         const double *__restrict__ Gb, double *__restrict__ Ub) {
+                                                         const double *__restrict__ Gb, double *__restrict__ Ub,
+                                                         double *__restrict__ Rb, double ra, double rb, int upd) {
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   __shared__ double sH[12 * n3];  // (1/J) Gbar
@@ -309,27 +312,26 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_lift(Geo g, Phys ph, const d
 #pragma unroll
       for (int v = 0; v < 4; ++v) Wb[v] += nv[d] * hs[d * 4 + v];
   }
-  // faces: own lifting and the neighbour's lifting both use W*/2 of this trace
+  // faces: own lifting and the neighbour's lifting both use W*/2 of this trace.  As in the forward
+  // lifting on LGL nodes, the outward normal times s-hat is +-Ja^dir at the face node (the
+  // neighbour's outward normal is the opposite one)
   for (int dir = 0; dir < 3; ++dir) {
     const int id = id3[dir];
     if (id != 0 && id != N) continue;
     const int sd = (id == N) ? 1 : 0;
     const int s = 2 * dir + sd;
     const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
-    const int ab = a + n * b;
     const int nb = g.nbr[(size_t)e * 6 + s];
     const int qn = vline_node<n>(dir, a, b, sd ? 0 : N);
-    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
-    const double *fnn = g.fn + ((size_t)nb * 6 + (s ^ 1)) * 3 * n2 + ab;
     const double sjn = g.sJ[(size_t)nb * n3 + qn];
+    const double c0 = (sd ? 0.5 : -0.5) * lh;
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+      const double nd = c0 * Jae[(dir * 3 + d) * n3 + t];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double own = fnp[d * n2] * sH[(d * 4 + v) * n3 + t];
-        const double nbr = fnn[d * n2] * sjn * Gb[((size_t)nb * 12 + d * 4 + v) * n3 + qn];
-        Wb[v] += 0.5 * lh * (own + nbr);
-      }
+      for (int v = 0; v < 4; ++v)
+        Wb[v] += nd * (sH[(d * 4 + v) * n3 + t] - sjn * Gb[((size_t)nb * 12 + d * 4 + v) * n3 + qn]);
+    }
   }
   double Uq[5];
 #pragma unroll
@@ -341,13 +343,21 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_lift(Geo g, Phys ph, const d
   dgf::cons_adj(q, gm1, pa, cb);
   double *Ube = Ub + (size_t)e * 5 * n3;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) Ube[v * n3 + t] += cb[v];
+  for (int v = 0; v < 5; ++v) {
+    const double u = Ube[v * n3 + t] + cb[v];
+    Ube[v * n3 + t] = u;
+    if (upd) {
+      double *r = Rb + ((size_t)e * 5 + v) * n3 + t;
+      *r = ra * *r + rb * u;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------- launcher
 template <int N>
 int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
-               const double *Ubar_t, double *Ubar, double scale, int accumulate, hipStream_t st) {
+               const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
+               hipStream_t st) {
   if (form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
   if constexpr (N > 7) {
     return DG_ERR_UNSUPPORTED;  // the reverse kernel's LDS staging exceeds 160 KB beyond N = 7
@@ -356,7 +366,7 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
   if (eqn == DG_NAVIER_STOKES) {
     hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale, accumulate);
     if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
-    hipLaunchKernelGGL((k_vjp_lift<N>), grid, block, 0, st, g, ph, U, Gbar, Ubar);
+    hipLaunchKernelGGL((k_vjp_lift<N>), grid, block, 0, st, g, ph, U, Gbar, Ubar, Rb, ra, rb, Rb ? 1 : 0);
   } else {
     hipLaunchKernelGGL((k_vjp_main<N, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale,
                        accumulate);
@@ -368,7 +378,7 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
 
 #ifdef DG_ONLY_N
 template int launch_vjp<DG_ONLY_N>(const Geo &, const Phys &, int, int, const double *, const double *, double *,
-                                   const double *, double *, double, int, hipStream_t);
+                                   const double *, double *, double, int, double *, double, double, hipStream_t);
 #endif
 
 }  // namespace dg
