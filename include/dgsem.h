@@ -123,15 +123,17 @@ int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_ba
  *   R_bar <- R_bar + b*U_bar;  U_bar <- U_bar + dt*(dL/dU)(U_in)^T R_bar;  R_bar <- a*R_bar. */
 int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt);
 
-/* dg_rk_stage that also keeps the lifted gradients of U_in in G_out (Navier-Stokes: device
- * [K][12][n^3], caller-owned, distinct from the solution buffers; ignored for Euler), so that a
- * reverse sweep over recomputed stages need not lift again. */
+/* dg_rk_stage that also keeps the lifting output of U_in in G_out (Navier-Stokes: device
+ * [K][12][n^3], caller-owned, distinct from the solution buffers; ignored for Euler): for the split
+ * form the contravariant viscous fluxes (F^v . Ja^dir), dir*4 + (momentum x, y, z, energy), for the
+ * other forms the gradients of (u, v, w, T), d*4 + c.  A reverse sweep over recomputed stages
+ * then need not lift again. */
 int dg_rk_stage_keep(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt,
                      double *G_out);
 
 /* Reverse of one full step of the five-stage scheme of dg_rk_coefficients with time step dt.
- * stage_U[s] (s = 0..4) is the input of stage s; stage_G[s] its gradients from
- * dg_rk_stage_keep, or NULL (the array or an entry) to recompute them.  On entry U_bar and R_bar
+ * stage_U[s] (s = 0..4) is the input of stage s; stage_G[s] its lifting output from
+ * dg_rk_stage_keep, or NULL (the array or an entry) to recompute it.  On entry U_bar and R_bar
  * hold the adjoints of the step's output state and R; on return those of its input state and
  * of R before the step (zero, as the first stage does not read R).  Same result as the five
  * dg_rk_stage_vjp calls in reverse order, with the register updates of neighbouring stages

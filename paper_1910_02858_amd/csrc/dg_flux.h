@@ -380,14 +380,13 @@ DGFN void visc_flux(const P &q, const double *g, double mu, double kappa, const 
   F[4] = F[1] * q.u + F[2] * q.v + F[3] * q.w + kappa * (g[3] * nv[0] + g[7] * nv[1] + g[11] * nv[2]);
 }
 
-// reverse of visc_flux: a (velocity part) and gb[12] accumulated; F[0] has no dependence
-DGFN void visc_flux_adj(const P &q, const double *g, double mu, double kappa, const double *nv, const double *Fb,
-                        PA &a, double *gb) {
-  double Fv[5];
-  visc_flux(q, g, mu, kappa, nv, Fv);
-  a.u += Fb[4] * Fv[1];
-  a.v += Fb[4] * Fv[2];
-  a.w += Fb[4] * Fv[3];
+// reverse of visc_flux given its momentum part tn = tau . nv (the flux is linear in the gradients
+// and depends on the state only through u in tau . u): a (velocity part) and gb[12] accumulated
+DGFN void visc_flux_adj_tn(const P &q, const double *tn, double mu, double kappa, const double *nv, const double *Fb,
+                           PA &a, double *gb) {
+  a.u += Fb[4] * tn[0];
+  a.v += Fb[4] * tn[1];
+  a.w += Fb[4] * tn[2];
   const double bm[3] = {Fb[1] + Fb[4] * q.u, Fb[2] + Fb[4] * q.v, Fb[3] + Fb[4] * q.w};
   // tau_ab adjoint = bm_a nv_b ; tau_ab = mu (du_a/dx_b + du_b/dx_a) - 2/3 mu div delta_ab
   double tb[3][3];
@@ -402,6 +401,14 @@ DGFN void visc_flux_adj(const P &q, const double *g, double mu, double kappa, co
       gb[d * 4 + c] += v;
     }
   for (int d = 0; d < 3; ++d) gb[d * 4 + 3] += Fb[4] * kappa * nv[d];
+}
+
+// reverse of visc_flux: a (velocity part) and gb[12] accumulated; F[0] has no dependence
+DGFN void visc_flux_adj(const P &q, const double *g, double mu, double kappa, const double *nv, const double *Fb,
+                        PA &a, double *gb) {
+  double Fv[5];
+  visc_flux(q, g, mu, kappa, nv, Fv);
+  visc_flux_adj_tn(q, Fv + 1, mu, kappa, nv, Fb, a, gb);
 }
 
 // lifted variables W = (u, v, w, T = p / (rho R)): adjoint into primitive adjoint

@@ -348,13 +348,13 @@ template <class T> int dev_alloc(T **p, size_t count) {
   return DG_OK;
 }
 
-// lifted gradients of U into G (the handle's scratch unless the caller keeps them)
-int lift_dispatch(dg_handle *h, const double *U, double *G) {
+// lifting of U: out 0 gradients into G, 1 contravariant viscous fluxes into Fv, 2 both
+int lift_dispatch(dg_handle *h, const double *U, int out, double *G, double *Fv) {
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, U, G, h->stream);
+  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, out, U, G, Fv, h->stream);
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return DG_ERR_UNSUPPORTED;
@@ -375,19 +375,22 @@ int main_dispatch(dg_handle *h, const double *U, const double *G, double *out, d
   }
 }
 
-// lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on;
-// the gradients go to G (the handle's scratch by default)
+// lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on.  The
+// split form takes the contravariant viscous fluxes, the other forms the gradients, in the
+// handle's scratch or, if Gkeep != NULL, in Gkeep (kept for a later reverse sweep).
 int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode,
-                 double *G = nullptr) {
+                 double *Gkeep = nullptr) {
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
-  if (!G) G = h->d_G;
+  const bool split = h->sc.form == DG_FORM_SPLIT;
   if (h->prof) (void)hipEventRecord(h->ev[0], h->stream);
   if (ns) {
-    int rc = lift_dispatch(h, U, G);
+    double *dst = Gkeep ? Gkeep : h->d_G;
+    const int rc = split ? lift_dispatch(h, U, 1, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
-  int rc = main_dispatch(h, U, G, out, R, a, b, dt, mode);
+  const double *Gin = (ns && Gkeep) ? Gkeep : h->d_G;
+  int rc = main_dispatch(h, U, Gin, out, R, a, b, dt, mode);
   if (rc) return rc;
   if (h->prof) {
     (void)hipEventRecord(h->ev[2], h->stream);
@@ -683,7 +686,7 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
     if (rc) return fail(h, rc, "allocation of the gradient adjoint failed");
   }
   if (ns && !Gin) {
-    int rc = lift_dispatch(h, U, h->d_G);  // forward lifting at U (the reverse needs G)
+    int rc = lift_dispatch(h, U, 1, nullptr, h->d_G);  // forward lifting at U (the reverse needs Fv)
     if (rc) return fail(h, rc, "launch of the lifting kernel failed");
     Gin = h->d_G;
   }

@@ -37,8 +37,11 @@ struct Phys {
 };
 
 // Kernel launch entry points, one explicit instantiation per degree.
+// lifting: out 0 writes G (gradients), 1 writes Fv (contravariant viscous fluxes, LGL only),
+// 2 writes both
 template <int N>
-int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double *G, hipStream_t st);
+int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
+                hipStream_t st);
 template <int N>
 int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const double *U, const double *G,
                 double *out, double *R, double a, double b, double dt, int mode, hipStream_t st);
@@ -57,7 +60,7 @@ struct Member {
   Geo g;
   Phys ph;
   const double *U;  // stage input
-  double *G;        // the member's lifted-gradient scratch
+  double *G;        // the member's scratch: contravariant viscous fluxes from the lifting
   double *out;      // stage output
   double *R;        // 2N-storage register
   double a, b, dt;  // stage coefficients: R = a R + dt L(U); out = U + b R

@@ -245,11 +245,16 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 
 // BR1 lifting of element e by the NT threads t of one slot.  valid = false keeps the slot's
 // threads in step with the workgroup barriers without touching memory.
-template <int N, bool LGL>
+// OUT: LIFT_G writes the gradients G[e][d*4+c][node] = dW_c/dx_d (weak and strong forms);
+// LIFT_FV writes instead the contravariant viscous fluxes Fv[e][dir*4+c][node] =
+// (F^v . Ja^dir)_{1+c} (momentum, energy) that the split-form kernels and their reverse consume.
+enum { LIFT_G = 0, LIFT_FV = 1 };
+
+template <int N, bool LGL, int OUT>
 __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
-                                          const double *__restrict__ U, double *__restrict__ G, double *sW,
-                                          double *sJa, double *sWs, const double *sDh, const double *sl,
-                                          const double *slh) {
+                                          const double *__restrict__ U, double *__restrict__ G,
+                                          double *__restrict__ Fv, double *sW, double *sJa, double *sWs,
+                                          const double *sDh, const double *sl, const double *slh) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   const double gm1 = ph.gamma - 1.0;
@@ -302,12 +307,18 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = 0.0;
   const int i = t % n, j = (t / n) % n, k = t / n2;
+  double jo[9];  // this node's metric terms, kept for the viscous fluxes (LIFT_FV)
+#pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
     __syncthreads();
     const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3;
     if (valid)
       for (int c = t; c < 3 * n3; c += NT) sJa[c] = Jd[c];
     __syncthreads();
+    if (OUT == LIFT_FV && valid && t < n3) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) jo[dir * 3 + d] = sJa[d * n3 + t];
+    }
     if (valid && t < n3) {
       const int id = dir == 0 ? i : (dir == 1 ? j : k);
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
@@ -361,15 +372,52 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   }
   if (valid && t < n3) {
     const double sj = g.sJ[(size_t)e * n3 + t];
-    double *Ge = G + (size_t)e * 12 * n3;
+    {
+      // the gradients are rounded once, whatever is computed from them (so the three output
+      // variants give the same bits)
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c] * sj;
+      for (int c = 0; c < 12; ++c) acc[c] *= sj;
+    }
+    if (OUT == LIFT_G) {
+      double *Ge = G + (size_t)e * 12 * n3;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
+    }
+    if (OUT == LIFT_FV) {
+      // Newtonian stress with Stokes' hypothesis and Fourier heat flux, contracted with Ja^dir.
+      // Every rounding step is spelled out (explicit fma, no contraction), so every kernel that
+      // runs this lifting produces the same fluxes bit for bit.
+#pragma clang fp contract(off)
+      const double mu = ph.mu, div = (acc[0] + acc[5]) + acc[10];
+      const double t00 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[0]);
+      const double t11 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[5]);
+      const double t22 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[10]);
+      const double t01 = mu * (acc[4] + acc[1]);
+      const double t02 = mu * (acc[8] + acc[2]);
+      const double t12 = mu * (acc[9] + acc[6]);
+      const double u = sW[t], v = sW[n3 + t], w = sW[2 * n3 + t];
+      double *Fe = Fv + (size_t)e * 12 * n3;
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const double *nv = jo + 3 * dir;
+        const double f0 = fma(t02, nv[2], fma(t01, nv[1], t00 * nv[0]));
+        const double f1 = fma(t12, nv[2], fma(t11, nv[1], t01 * nv[0]));
+        const double f2 = fma(t22, nv[2], fma(t12, nv[1], t02 * nv[0]));
+        const double q = fma(acc[11], nv[2], fma(acc[7], nv[1], acc[3] * nv[0]));
+        const double f3 = fma(ph.kappa, q, fma(f2, w, fma(f1, v, f0 * u)));
+        Fe[(dir * 4) * n3 + t] = f0;
+        Fe[(dir * 4 + 1) * n3 + t] = f1;
+        Fe[(dir * 4 + 2) * n3 + t] = f2;
+        Fe[(dir * 4 + 3) * n3 + t] = f3;
+      }
+    }
   }
 }
 
-template <int N, bool LGL>
+template <int N, bool LGL, int OUT>
 __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                                  double *__restrict__ G) {
+                                                                  double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
   __shared__ double sW[L::W], sJa[L::JA], sWs[L::WS];
@@ -377,7 +425,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
   lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  lift_body<N, LGL>(g, ph, e, true, threadIdx.x, U, G, sW, sJa, sWs, sDh, sl, slh);
+  lift_body<N, LGL, OUT>(g, ph, e, true, threadIdx.x, U, G, Fv, sW, sJa, sWs, sDh, sl, slh);
 }
 
 // ----------------------------------------------------------------------------- operator
@@ -767,16 +815,11 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
     if (NS) {
-      double gw[12], gx[12];
+      // BR1 mean of the viscous fluxes along the master normal: on both sides the contravariant
+      // flux of the face's direction (Ja^dn is continuous across a conforming face)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + qo]; gx[c] = Gn[c * n3 + qn]; }
-      const double *gM = plus ? gw : gx, *gS = plus ? gx : gw;
-      double FvM[5], FvS[5];
-      const Pr5 PM = to_prim(UM, gm1), PS_ = to_prim(US, gm1);
-      flux_v(PM, gM, ph, nt, FvM);
-      flux_v(PS_, gS, ph, nt, FvS);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (FvM[v] + FvS[v]);
+      for (int c = 0; c < 4; ++c)
+        F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + Gn[(dn * 4 + c) * n3 + qn]);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = sg * F[v];
@@ -824,30 +867,17 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   if (NS) {
     // viscous part in strong form: -sum_a D_ia Fv^dir_a along each line, and -Fv.N_out lhat(+-1)
     // on the faces through the node.  The contravariant viscous fluxes of all three directions
-    // are staged once in region A.
+    // (from the lifting kernel) are staged once in region A.
     double *sF = sA;
     if (act) {
-      double go[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
-      const double mu = ph.mu, div = go[0] + go[5] + go[10];
-      const double t00 = mu * (2.0 * go[0] - (2.0 / 3.0) * div);
-      const double t11 = mu * (2.0 * go[5] - (2.0 / 3.0) * div);
-      const double t22 = mu * (2.0 * go[10] - (2.0 / 3.0) * div);
-      const double t01 = mu * (go[4] + go[1]);
-      const double t02 = mu * (go[8] + go[2]);
-      const double t12 = mu * (go[9] + go[6]);
 #pragma unroll
       for (int dir = 0; dir < 3; ++dir) {
-        const double *nv = ja + 3 * dir;
         double fv[4];
-        fv[0] = t00 * nv[0] + t01 * nv[1] + t02 * nv[2];
-        fv[1] = t01 * nv[0] + t11 * nv[1] + t12 * nv[2];
-        fv[2] = t02 * nv[0] + t12 * nv[1] + t22 * nv[2];
-        fv[3] = fv[0] * o.u + fv[1] * o.v + fv[2] * o.w +
-                ph.kappa * (go[3] * nv[0] + go[7] * nv[1] + go[11] * nv[2]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sF[(dir * 4 + c) * n3 + t] = fv[c];
+        for (int c = 0; c < 4; ++c) {
+          fv[c] = Ge[(dir * 4 + c) * n3 + t];
+          sF[(dir * 4 + c) * n3 + t] = fv[c];
+        }
         const int id = id3[dir];
         if (id == 0 || id == N) {
           const bool plus = id == N;
@@ -1010,8 +1040,8 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
   const bool valid = item < bv.total;
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
-  lift_body<N, true>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, sW + slot * L::W,
-                     sJa + slot * L::JA, sWs + slot * L::WS, sDh, sl, slh);
+  lift_body<N, true, LIFT_FV>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
+                              sW + slot * L::W, sJa + slot * L::JA, sWs + slot * L::WS, sDh, sl, slh);
 }
 
 template <int N, bool NS, int VF, int EPB>
@@ -1153,10 +1183,17 @@ static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, 
 }
 
 template <int N>
-int launch_lift(const Geo &g, const Phys &ph, bool lgl, const double *U, double *G, hipStream_t st) {
+int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
+                hipStream_t st) {
   dim3 grid(8 * ((g.K + 7) / 8)), block(Sz<N>::NT);
-  if (lgl) hipLaunchKernelGGL((k_lift<N, true>), grid, block, 0, st, g, ph, U, G);
-  else hipLaunchKernelGGL((k_lift<N, false>), grid, block, 0, st, g, ph, U, G);
+  if (!lgl) {
+    if (out != LIFT_G) return DG_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_lift<N, false, LIFT_G>), grid, block, 0, st, g, ph, U, G, Fv);
+  } else if (out == LIFT_G) {
+    hipLaunchKernelGGL((k_lift<N, true, LIFT_G>), grid, block, 0, st, g, ph, U, G, Fv);
+  } else {
+    hipLaunchKernelGGL((k_lift<N, true, LIFT_FV>), grid, block, 0, st, g, ph, U, G, Fv);
+  }
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -1307,7 +1344,8 @@ int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n
 #endif
 
 #ifdef DG_ONLY_N
-template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, const double *, double *, hipStream_t);
+template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, int, const double *, double *, double *,
+                                    hipStream_t);
 template int launch_main<DG_ONLY_N>(const Geo &, const Phys &, bool, int, int, const double *, const double *,
                                     double *, double *, double, double, double, int, hipStream_t);
 template int launch_reduce<DG_ONLY_N>(const Geo &, const Phys &, int, const double *, double, double *, hipStream_t);

@@ -6,6 +6,8 @@
 //   U_t = -(1/J) acc,  acc_q = sum_dir [ sum_m 2 D_im F#(U_q, U_m) - sum_m D_im Fv_m ]
 //                            + sum_faces lhat (F_face - sg F_int,q),
 //   G = lift(W(U)),    W = (u, v, w, T).
+// G holds the contravariant viscous fluxes Fv^dir of the lifting (LIFT_FV): the viscous flux is
+// linear in the gradients, so its derivative in U needs only tau . Ja^dir, their momentum part.
 // With Abar = -(1/J) Utbar (the adjoint of acc) the reverse is:
 //   * each unordered pair {q, p} on a line: Fbar = 2 D_qp Abar_q + 2 D_pq Abar_p, then the
 //     two-point flux's transposed Jacobian in both arguments (the partner's share goes through
@@ -117,14 +119,16 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     dgf::PA pc = dgf::zero_pa();
     dgf::prim_adj_of_cons(Po, gm1, bo, pc);
     if (NS) {
-      // F contains -1/2 Fv(U_own, G_own) . nt
-      double go[12], gbo[12];
+      // F contains -1/2 Fv(U_own, G_own) . nt; its momentum part along the face's direction is
+      // the contravariant viscous flux of that direction from the lifting (G holds those)
+      double gbo[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) { go[c] = Ge[c * n3 + qo]; gbo[c] = 0.0; }
+      for (int c = 0; c < 12; ++c) gbo[c] = 0.0;
+      const double tn[3] = {Ge[(dn * 4) * n3 + qo], Ge[(dn * 4 + 1) * n3 + qo], Ge[(dn * 4 + 2) * n3 + qo]};
       double Fvb[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
-      dgf::visc_flux_adj(Po, go, ph.mu, ph.kappa, nt, Fvb, pc, gbo);
+      dgf::visc_flux_adj_tn(Po, tn, ph.mu, ph.kappa, nt, Fvb, pc, gbo);
 #pragma unroll
       for (int c = 0; c < 12; ++c) sF[(5 + c) * 6 * n2 + p] = gbo[c];
     }
@@ -175,9 +179,9 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // Fvbar_i = -sum_m D_mi Abar_m; the interior face term -F_int contributes +lhat sg Abar_i.
   // The gradient adjoint of this node is final afterwards.
   if (NS && act) {
-    double go[12], gbo[12];
+    double gbo[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) { go[c] = Ge[c * n3 + t]; gbo[c] = gbf[c]; }
+    for (int c = 0; c < 12; ++c) gbo[c] = gbf[c];
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
       const int id = id3[dir];
@@ -197,7 +201,8 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       }
       const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
       const double Fvb[5] = {0.0, fvb[0], fvb[1], fvb[2], fvb[3]};
-      dgf::visc_flux_adj(q, go, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
+      const double tn[3] = {Ge[(dir * 4) * n3 + t], Ge[(dir * 4 + 1) * n3 + t], Ge[(dir * 4 + 2) * n3 + t]};
+      dgf::visc_flux_adj_tn(q, tn, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
     }
     double *Gbe = Gb + (size_t)e * 12 * n3;
 #pragma unroll
