@@ -803,9 +803,10 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     double Uw[5], Ux[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = Un[v * n3 + qn]; }
-    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    // normal along +xi_dn scaled by s-hat: Ja^dn at the face node, the master's on the master
+    // side and (up to rounding, the metric terms being continuous across the face) on the slave
     const double sg = plus ? 1.0 : -1.0;
-    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    const double nt[3] = {Jae[(dn * 3) * n3 + qo], Jae[(dn * 3 + 1) * n3 + qo], Jae[(dn * 3 + 2) * n3 + qo]};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
