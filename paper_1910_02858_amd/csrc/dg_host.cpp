@@ -667,7 +667,7 @@ void dg_destroy(dg_handle *h) {
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_tab);
-  (void)hipFree(h->d_G); (void)hipFree(h->d_Gbar); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
+  (void)hipFree(h->d_G); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
   delete h;
 }
 
@@ -681,9 +681,9 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
   if (h->sc.volflux == DG_VF_EC)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the KEP and central volume fluxes");
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
-  if (ns && !h->d_Gbar) {
-    int rc = dev_alloc(&h->d_Gbar, (size_t)h->K * 12 * h->n3);
-    if (rc) return fail(h, rc, "allocation of the gradient adjoint failed");
+  if (ns && !h->d_Pf) {
+    int rc = dev_alloc(&h->d_Pf, (size_t)h->K * 24 * h->n * h->n);
+    if (rc) return fail(h, rc, "allocation of the lifting's face adjoint failed");
   }
   if (ns && !Gin) {
     int rc = lift_dispatch(h, U, 1, nullptr, h->d_G);  // forward lifting at U (the reverse needs Fv)
@@ -694,7 +694,7 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
   int rc;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Gbar, Utb, Ub, scale, accumulate, \
+  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Pf, Utb, Ub, scale, accumulate, \
                                    ns ? Rb : nullptr, ra, rb, h->stream); break;
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE

@@ -37,18 +37,18 @@ struct Phys {
 };
 
 // Kernel launch entry points, one explicit instantiation per degree.
-// lifting: out 0 writes G (gradients), 1 writes Fv (contravariant viscous fluxes, LGL only),
-// 2 writes both
+// lifting: out 0 writes G (gradients), 1 writes Fv (contravariant viscous fluxes, LGL only)
 template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st);
 template <int N>
 int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const double *U, const double *G,
                 double *out, double *R, double a, double b, double dt, int mode, hipStream_t st);
-// Ubar (+)= scale (dL/dU)^T Ubar_t; for Navier-Stokes with Rb != NULL the lifting-transpose kernel
-// then also sets Rb = ra Rb + rb Ubar (Euler: the caller updates Rb)
+// Ubar (+)= scale (dL/dU)^T Ubar_t; Pf: face terms of the transposed lifting, [K][6][4][n^2]
+// (Navier-Stokes); for Navier-Stokes with Rb != NULL the second reverse kernel then also sets
+// Rb = ra Rb + rb Ubar (Euler: the caller updates Rb)
 template <int N>
-int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Pf,
                const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
                hipStream_t st);
 template <int N>
@@ -102,7 +102,7 @@ struct dg_handle {
   int32_t *d_nbr = nullptr;
   dg::Tab *d_tab = nullptr;
   double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
-  double *d_Gbar = nullptr;     // adjoint of the gradients (allocated on first VJP)
+  double *d_Pf = nullptr;       // face terms of the transposed lifting [K][6][4][n^2] (first VJP)
   double *d_partial = nullptr;  // [K][8] per-element partial reductions
   double *d_red = nullptr;      // [8] reduction result
   dg::Tab tab{};

@@ -323,6 +323,8 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       const int id = dir == 0 ? i : (dir == 1 ? j : k);
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
       const int base = t - id * str;
+      // not unrolled: with all of a line's loads in flight the kernel exceeds its register budget
+#pragma unroll 1
       for (int m = 0; m < n; ++m) {
         const int qm = base + m * str;
         const double Dh = sDh[id * n + m];

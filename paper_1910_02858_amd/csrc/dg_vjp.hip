@@ -8,6 +8,7 @@
 //   G = lift(W(U)),    W = (u, v, w, T).
 // G holds the contravariant viscous fluxes Fv^dir of the lifting (LIFT_FV): the viscous flux is
 // linear in the gradients, so its derivative in U needs only tau . Ja^dir, their momentum part.
+// Face normals are Ja^dir at the face node of the element itself, as in the forward kernels.
 // With Abar = -(1/J) Utbar (the adjoint of acc) the reverse is:
 //   * each unordered pair {q, p} on a line: Fbar = 2 D_qp Abar_q + 2 D_pq Abar_p, then the
 //     two-point flux's transposed Jacobian in both arguments (the partner's share goes through
@@ -17,8 +18,12 @@
 //   * each face point: the flux enters both elements, so Fbar = lhat (Abar_master - Abar_slave),
 //     and every element adds only the derivative with respect to its own trace (the neighbour's
 //     Abar is read from global memory, nothing is written into another element);
-//   * the lifting transposed: Wbar from own Gbar (volume, own faces) and from the neighbours'
-//     Gbar on shared faces, then W's Jacobian.
+//   * the lifting transposed: with H = (1/J) Gbar, Wbar = sum_dir Ja^dir . (Dhat^T H) along the
+//     lines plus, on each face point, c0 Ja^dn . H (c0 = +-lhat/2) — a term that enters the
+//     element's own Wbar and, the face state being the mean of both traces, the neighbour's
+//     Wbar at the matching point.  The first kernel does the element's own part and leaves the
+//     face terms in a face array; the second adds the neighbours' face terms and W's Jacobian
+//     on the face nodes and performs the register update of the 2N scheme.
 #include <hip/hip_runtime.h>
 
 #include "dg_flux.h"
@@ -45,23 +50,25 @@ template <int N, bool NS>
 __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
                                                          const double *__restrict__ G,
                                                          const double *__restrict__ Utb, double *__restrict__ Ub,
-                                                         double *__restrict__ Gb, double scale, int accumulate) {
+                                                         double *__restrict__ Pf, double scale, int accumulate) {
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   constexpr int NF = NS ? 17 : 5;  // results per face point: primitive adjoint, gradient adjoint
   constexpr int NX = (NF * 6 * n2 > 8 * n3) ? NF * 6 * n2 : 8 * n3;
   __shared__ double sQ[5 * n3];  // primitive state
   __shared__ double sA[5 * n3];  // Abar = -(1/J) Utbar
-  // region X: first the face-point results, then Ja^dir of the current direction (3 per node)
-  // and the partner shares of the pair rounds (5 per node)
+  // region X: first the face-point results, then H = (1/J) Gbar (12 per node, Navier-Stokes),
+  // then Ja^dir of the current direction (3 per node) and the partner shares of the pair
+  // rounds (5 per node)
+  static_assert(!NS || NX >= 12 * n3, "region X holds H");
   __shared__ double sX[NX];
-  __shared__ double sD[n * n];
-  double *sF = sX, *sJ = sX, *sPA = sX + 3 * n3;
+  __shared__ double sD[n * n], sDh[n * n];
+  double *sF = sX, *sH = sX, *sJ = sX, *sPA = sX + 3 * n3;
   const int e = blockIdx.x, t = threadIdx.x;
   const bool act = t < n3;
   const double gamma = ph.gamma, gm1 = gamma - 1.0, g1 = gamma / gm1;
   const int vf = ph.vf;
-  for (int c = t; c < n * n; c += NT) sD[c] = g.tab->D[c];
+  for (int c = t; c < n * n; c += NT) { sD[c] = g.tab->D[c]; sDh[c] = g.tab->Dh[c]; }
   const double lh = g.tab->lhp[N];  // lhat at a face node (the same value at both ends)
   const double *Ue = U + (size_t)e * 5 * n3;
   const double *Ge = G + (size_t)e * 12 * n3;
@@ -97,9 +104,8 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       Aw[v] = sA[v * n3 + qo];
       Ax[v] = -sjn * Utb[((size_t)nb * 5 + v) * n3 + qn];
     }
-    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
-    const double sg = plus ? 1.0 : -1.0;
-    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    // normal along +xi_dn scaled by s-hat: this element's Ja^dn at the face node
+    const double nt[3] = {Jae[(dn * 3) * n3 + qo], Jae[(dn * 3 + 1) * n3 + qo], Jae[(dn * 3 + 2) * n3 + qo]};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
@@ -178,6 +184,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // ---- viscous part, all directions before the pair rounds: acc_m -= sum_i D_mi Fv_i gives
   // Fvbar_i = -sum_m D_mi Abar_m; the interior face term -F_int contributes +lhat sg Abar_i.
   // The gradient adjoint of this node is final afterwards.
+  double hq[12];  // H = (1/J) scale Gbar of this node
   if (NS && act) {
     double gbo[12];
 #pragma unroll
@@ -204,9 +211,58 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       const double tn[3] = {Ge[(dir * 4) * n3 + t], Ge[(dir * 4 + 1) * n3 + t], Ge[(dir * 4 + 2) * n3 + t]};
       dgf::visc_flux_adj_tn(q, tn, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
     }
-    double *Gbe = Gb + (size_t)e * 12 * n3;
+    const double sj = sJe[t];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) Gbe[c * n3 + t] = scale * gbo[c];
+    for (int c = 0; c < 12; ++c) hq[c] = sj * (scale * gbo[c]);
+  }
+  // ---- lifting transposed, own part (volume and own face terms); the face terms also go to
+  // the face array for the neighbours
+  dgf::PA pl = dgf::zero_pa();
+  if (NS) {
+    __syncthreads();  // every node has collected its face results from region X
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sH[c * n3 + t] = hq[c];
+    }
+    __syncthreads();
+    if (act) {
+      double Wb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const int id = id3[dir];
+        const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+        const int base = t - id * str;
+        const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+        double hs[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) hs[c] = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < n; ++i) {
+          const int qi = base + i * str;
+          const double Dh = sDh[i * n + id];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) hs[c] += Dh * sH[c * n3 + qi];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Wb[v] += nv[d] * hs[d * 4 + v];
+        if (id == 0 || id == N) {
+          const int sd = (id == N) ? 1 : 0;
+          const int s = 2 * dir + sd;
+          const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+          const double c0 = (sd ? 0.5 : -0.5) * lh;
+          double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double f = c0 * (nv[0] * hq[v] + nv[1] * hq[4 + v] + nv[2] * hq[8 + v]);
+            Wb[v] += f;
+            pf[v * n2] = f;
+          }
+        }
+      }
+      dgf::lift_vars_adj(q, ph.R, Wb, pl);
+    }
   }
   // ---- volume: pairs, diagonal and viscous transpose, direction by direction
   for (int dir = 0; dir < 3; ++dir) {
@@ -263,104 +319,75 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     }
   }
   if (act) {
-    dgf::cons_adj(q, gm1, pa, cb);
+    dgf::PA pt;
+    pt.r = fma(scale, pa.r, pl.r); pt.u = fma(scale, pa.u, pl.u); pt.v = fma(scale, pa.v, pl.v);
+    pt.w = fma(scale, pa.w, pl.w); pt.p = fma(scale, pa.p, pl.p);
+    dgf::cons_adj(q, gm1, pt, cb);
     double *Ube = Ub + (size_t)e * 5 * n3;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = (accumulate ? Ube[v * n3 + t] : 0.0) + scale * cb[v];
+    for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = (accumulate ? Ube[v * n3 + t] : 0.0) + cb[v];
   }
 }
 
-// ---------------------------------------------------------------------------------- lifting
-// Ubar += (dW/dU)^T Wbar, Wbar = transpose of G = (1/J)[sum Dhat Ja W + lhat nt (W + W_nb)/2]
-// With upd != 0 the register of the 2N scheme is updated from the final U_bar of each own node,
-// Rb = ra Rb + rb Ubar (the element reads no Rb, so this is race-free).
+// ---------------------------------------------------------------------------------- faces
+// Completes Ubar on the face nodes with the neighbours' face terms of the transposed lifting
+// (Wbar, then W's Jacobian at the node's state).  With upd != 0 the register of the 2N scheme
+// is updated from the final Ubar of every node, Rb = ra Rb + rb Ubar (each node is read and
+// written by its own thread only).
 template <int N>
-__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                         const double *__restrict__ Gb, double *__restrict__ Ub,
+__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const double *__restrict__ U,
+                                                         const double *__restrict__ Pf, double *__restrict__ Ub,
                                                          double *__restrict__ Rb, double ra, double rb, int upd) {
   using S = VSz<N>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  __shared__ double sH[12 * n3];  // (1/J) Gbar
-  __shared__ double sDh[n * n];
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
   const int e = blockIdx.x, t = threadIdx.x;
-  const bool act = t < n3;
-  const double gm1 = ph.gamma - 1.0;
-  for (int c = t; c < n * n; c += NT) sDh[c] = g.tab->Dh[c];
-  const double lh = g.tab->lhp[N];
-  if (act) {
-    const double sj = g.sJ[(size_t)e * n3 + t];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) sH[c * n3 + t] = sj * Gb[((size_t)e * 12 + c) * n3 + t];
-  }
-  __syncthreads();
-  if (!act) return;
+  if (t >= n3) return;
   const int id3[3] = {t % n, (t / n) % n, t / n2};
-  const double *Jae = g.Ja + (size_t)e * 9 * n3;
   double Wb[4] = {0.0, 0.0, 0.0, 0.0};
-  // volume: W_v(p) enters G_{d,v}(q_i) with Dhat[i][ip] Ja^dir_d(p)
-  for (int dir = 0; dir < 3; ++dir) {
-    const int id = id3[dir];
-    const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
-    const int base = t - id * str;
-    const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
-    double hs[12];
+  bool face = false;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) hs[c] = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const int qi = base + i * str;
-      const double Dh = sDh[i * n + id];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) hs[c] += Dh * sH[c * n3 + qi];
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Wb[v] += nv[d] * hs[d * 4 + v];
-  }
-  // faces: own lifting and the neighbour's lifting both use W*/2 of this trace.  As in the forward
-  // lifting on LGL nodes, the outward normal times s-hat is +-Ja^dir at the face node (the
-  // neighbour's outward normal is the opposite one)
   for (int dir = 0; dir < 3; ++dir) {
     const int id = id3[dir];
     if (id != 0 && id != N) continue;
-    const int sd = (id == N) ? 1 : 0;
-    const int s = 2 * dir + sd;
+    const int s = 2 * dir + (id == N ? 1 : 0);
     const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const int qn = vline_node<n>(dir, a, b, sd ? 0 : N);
-    const double sjn = g.sJ[(size_t)nb * n3 + qn];
-    const double c0 = (sd ? 0.5 : -0.5) * lh;
+    // the neighbour's side facing this one is s ^ 1; conforming faces share the point index
+    const double *pf = Pf + ((size_t)nb * 6 + (s ^ 1)) * 4 * n2 + a + n * b;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double nd = c0 * Jae[(dir * 3 + d) * n3 + t];
+    for (int v = 0; v < 4; ++v) Wb[v] += pf[v * n2];
+    face = true;
+  }
+  if (!face && !upd) return;
+  double *Ube = Ub + (size_t)e * 5 * n3 + t;
+  double u[5];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Wb[v] += nd * (sH[(d * 4 + v) * n3 + t] - sjn * Gb[((size_t)nb * 12 + d * 4 + v) * n3 + qn]);
+  for (int v = 0; v < 5; ++v) u[v] = Ube[v * n3];
+  if (face) {
+    double Uq[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + t];
+    const dgf::P q = dgf::prim(Uq, ph.gamma - 1.0);
+    dgf::PA pa = dgf::zero_pa();
+    dgf::lift_vars_adj(q, ph.R, Wb, pa);
+    double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    dgf::cons_adj(q, ph.gamma - 1.0, pa, cb);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] += cb[v];
+      Ube[v * n3] = u[v];
     }
   }
-  double Uq[5];
+  if (upd) {
+    double *r = Rb + (size_t)e * 5 * n3 + t;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + t];
-  const dgf::P q = dgf::prim(Uq, gm1);
-  dgf::PA pa = dgf::zero_pa();
-  dgf::lift_vars_adj(q, ph.R, Wb, pa);
-  double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  dgf::cons_adj(q, gm1, pa, cb);
-  double *Ube = Ub + (size_t)e * 5 * n3;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double u = Ube[v * n3 + t] + cb[v];
-    Ube[v * n3 + t] = u;
-    if (upd) {
-      double *r = Rb + ((size_t)e * 5 + v) * n3 + t;
-      *r = ra * *r + rb * u;
-    }
+    for (int v = 0; v < 5; ++v) r[v * n3] = ra * r[v * n3] + rb * u[v];
   }
 }
 
 // ---------------------------------------------------------------------------------- launcher
 template <int N>
-int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Gbar,
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Pf,
                const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
                hipStream_t st) {
   if (form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
@@ -369,11 +396,11 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
   } else {
   dim3 grid(g.K), block(VSz<N>::NT);
   if (eqn == DG_NAVIER_STOKES) {
-    hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale, accumulate);
+    hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale, accumulate);
     if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
-    hipLaunchKernelGGL((k_vjp_lift<N>), grid, block, 0, st, g, ph, U, Gbar, Ubar, Rb, ra, rb, Rb ? 1 : 0);
+    hipLaunchKernelGGL((k_vjp_face<N>), grid, block, 0, st, g, ph, U, Pf, Ubar, Rb, ra, rb, Rb ? 1 : 0);
   } else {
-    hipLaunchKernelGGL((k_vjp_main<N, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Gbar, scale,
+    hipLaunchKernelGGL((k_vjp_main<N, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
                        accumulate);
   }
   if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;

@@ -441,20 +441,28 @@ def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
             Rbar = torch.zeros_like(Ubar)
             nseg = len(ctx.ckpts)
             ns = S.eqn == "ns"
-            # buffers of one segment, reused: the input of every stage and its lifted gradients
+            # buffers of one segment, reused: the input of every stage after the first and the
+            # lifting output of every stage but the last
             nst = 5 * min(ckpt_every, nsteps)
-            bufs = [S.empty() for _ in range(nst + 1)]
-            grads = [S.empty_grad() for _ in range(nst)] if ns else [None] * nst
+            bufs = [None] + [S.empty() for _ in range(nst - 1)]
+            grads = [S.empty_grad() for _ in range(nst - 1)] + [None] if ns else [None] * nst
             R = torch.empty_like(Ubar)
             for seg in range(nseg - 1, -1, -1):
                 first = seg * ckpt_every
                 steps = min(ckpt_every, nsteps - first)
-                bufs[0].copy_(ctx.ckpts[seg])
-                for idx in range(5 * steps):  # recompute; the first stage does not read R
+                bufs[0] = ctx.ckpts[seg]
+                # recompute up to the input of the segment's last stage (its output is the next
+                # checkpoint; the reverse lifts that stage's input itself); the first stage does
+                # not read R
+                for idx in range(5 * steps - 1):
                     s = idx % 5
                     S.rk_stage_keep(bufs[idx], bufs[idx + 1], R, a[s], b[s], dt, grads[idx])
                 for st in range(steps - 1, -1, -1):
-                    S.rk_step_vjp(bufs[5 * st:5 * st + 5], grads[5 * st:5 * st + 5], Ubar, Rbar, dt)
+                    gs = grads[5 * st:5 * st + 5]
+                    if st == steps - 1:
+                        gs = gs[:4] + [None]
+                    S.rk_step_vjp(bufs[5 * st:5 * st + 5], gs, Ubar, Rbar, dt)
+            bufs[0] = None
             return Ubar
 
     return _Rollout.apply(U0)

@@ -76,6 +76,25 @@ def test_vjp_dot_product_cfg5_operator(dg, orc):
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("N", [1, 3, 4, 6, 7])
+def test_vjp_dot_product_degrees(dg, orc, N):
+    """<J^T w, v> = <w, J v> for every degree the reverse kernels are built for, on a curved
+    ragged 3x2x2 lattice (Navier-Stokes, KEP + Roe + BR1), J v from the oracle's tangent."""
+    wl = inputs.workload(5, N=N, K1=2)
+    M, xgeo, nbr, side, U0 = problem(orc, wl, kxyz=(3, 2, 2), curved=True, perturb=1e-2, seed=N)
+    sc = orc.Scheme.of(wl)
+    S = gpu_solver(dg, wl, xgeo, nbr, side)
+    rng = np.random.default_rng(20 + N)
+    for v in inputs.random_directions(U0, 30 + N, 2):
+        w = rng.standard_normal(U0.shape)
+        _, Jv = M.rhs_jvp(sc, U0, v)
+        JTw = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy()
+        lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
+        scale = float(np.sum(np.abs(JTw * v)))
+        print(f"N={N}: <J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
 def test_rollout_dot_product(dg, orc):
     wl = inputs.workload(5, K1=4)
     M, xgeo, nbr, side, U0 = problem(orc, wl, perturb=1e-3)
