@@ -141,6 +141,14 @@ int dg_rk_stage_keep(dg_handle *h, const double *U_in, double *U_out, double *R,
 int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *const *stage_G, double *U_bar,
                    double *R_bar, double dt);
 
+/* Reverse of nsteps >= 1 consecutive steps: stage_U[5*k + s] (and stage_G[5*k + s], or NULL)
+ * belong to stage s of the k-th step, in forward order; the steps are reversed from the last.
+ * Same result, bit for bit, as nsteps dg_rk_step_vjp calls from the last step to the first
+ * (the register update between two steps is merged into the reverse kernels, since a_1 = 0
+ * leaves R_bar zero after every reversed step).  On return R_bar is zero. */
+int dg_rk_steps_vjp(dg_handle *h, int nsteps, const double *const *stage_U, const double *const *stage_G,
+                    double *U_bar, double *R_bar, double dt);
+
 /* Largest stable step (eqs. CFLCondition and DFLCondition with gamma_RK = 1, evaluated per
  * reference direction from the metric terms).  Synchronous; result in *dt_out (host). */
 int dg_timestep(dg_handle *h, const double *U, double cfl, double dfl, double *dt_out);

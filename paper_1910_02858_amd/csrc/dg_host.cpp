@@ -765,33 +765,44 @@ int dg_rk_stage_keep(dg_handle *h, const double *U_in, double *U_out, double *R,
   return DG_OK;
 }
 
-int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *const *stage_G, double *U_bar,
-                   double *R_bar, double dt) {
+int dg_rk_steps_vjp(dg_handle *h, int nsteps, const double *const *stage_U, const double *const *stage_G,
+                    double *U_bar, double *R_bar, double dt) {
   if (!h) return DG_ERR_ARG;
+  if (nsteps < 1) return fail(h, DG_ERR_ARG, "nsteps must be positive");
   if (!stage_U) return fail(h, DG_ERR_ARG, "stage_U is NULL");
   int rc = check_solution_ptr(h, U_bar, "U_bar");
   if (!rc) rc = check_solution_ptr(h, R_bar, "R_bar");
-  for (int s = 0; s < 5 && !rc; ++s) rc = check_solution_ptr(h, stage_U[s], "stage_U[s]");
+  for (int s = 0; s < 5 * nsteps && !rc; ++s) rc = check_solution_ptr(h, stage_U[s], "stage_U[s]");
   if (rc) return rc;
   const size_t n = (size_t)h->K * 5 * h->n3, bytes = n * sizeof(double);
   if (overlap(U_bar, R_bar, bytes)) return fail(h, DG_ERR_ARG, "U_bar and R_bar overlap");
-  for (int s = 0; s < 5; ++s)
+  for (int s = 0; s < 5 * nsteps; ++s)
     if (overlap(stage_U[s], U_bar, bytes) || overlap(stage_U[s], R_bar, bytes))
       return fail(h, DG_ERR_ARG, "a stage input overlaps U_bar or R_bar");
   if (!std::isfinite(dt)) return fail(h, DG_ERR_ARG, "non-finite time step");
   double A[5], B[5], C[5];
   dg_rk_coefficients(A, B, C);
   // R_bar <- R_bar + b_4 U_bar enters the last stage's reverse; after the reverse of stage s the
-  // register update R_bar <- a_s R_bar is merged with the entry of stage s-1,
-  // R_bar <- a_s R_bar + b_{s-1} U_bar, and done by the reverse kernels themselves
+  // register update R_bar <- a_s R_bar is merged with the entry of the stage reversed next,
+  // R_bar <- a_s R_bar + b_{s-1} U_bar (b_4 across a step boundary, nothing after the last),
+  // and done by the reverse kernels themselves
   rc = dg::launch_axpby(R_bar, U_bar, 1.0, B[4], n, h->stream);
   if (rc) return fail(h, rc, "launch failed");
-  for (int s = 4; s >= 0; --s) {
-    const double *Gs = (stage_G && stage_G[s]) ? stage_G[s] : nullptr;
-    rc = vjp_dispatch(h, stage_U[s], R_bar, U_bar, dt, 1, Gs, R_bar, A[s], s > 0 ? B[s - 1] : 0.0);
-    if (rc) return rc;
+  for (int st = nsteps - 1; st >= 0; --st) {
+    for (int s = 4; s >= 0; --s) {
+      const int k = 5 * st + s;
+      const double *Gs = (stage_G && stage_G[k]) ? stage_G[k] : nullptr;
+      const double rb = s > 0 ? B[s - 1] : (st > 0 ? B[4] : 0.0);
+      rc = vjp_dispatch(h, stage_U[k], R_bar, U_bar, dt, 1, Gs, R_bar, A[s], rb);
+      if (rc) return rc;
+    }
   }
   return DG_OK;
+}
+
+int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *const *stage_G, double *U_bar,
+                   double *R_bar, double dt) {
+  return dg_rk_steps_vjp(h, 1, stage_U, stage_G, U_bar, R_bar, dt);
 }
 
 

@@ -78,6 +78,16 @@ struct BatchView {
 // elements per workgroup the batched kernels are built for (1, 2, 4 up to this bound)
 __host__ __device__ constexpr int batch_max_epb(int N) { return N <= 3 ? 4 : (N <= 5 ? 2 : 1); }
 
+// element handled by workgroup b of a grid of 8 ceil(K/8) workgroups: the launch hands each XCD
+// (workgroups are dealt to the 8 XCDs round-robin) one contiguous range of elements, so face
+// neighbours along the first two lattice directions are usually read from the same L2; values
+// >= K are past the end
+__host__ __device__ inline int xcd_element(int b, int K) {
+  const int per = (K + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+__host__ __device__ inline int xcd_grid(int K) { return 8 * ((K + 7) / 8); }
+
 template <int N>
 int launch_batch_lift(const BatchView &bv, int epb, hipStream_t st);
 template <int N>

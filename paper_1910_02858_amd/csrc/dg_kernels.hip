@@ -217,14 +217,6 @@ __device__ __forceinline__ void grad_prim_to_W(const double *U, double gm1, doub
   W[0] = P.u; W[1] = P.v; W[2] = P.w; W[3] = P.p / (P.rho * Rg);
 }
 
-// element handled by workgroup b: the launch hands each XCD (workgroups are dealt to the
-// 8 XCDs round-robin) one contiguous range of elements, so face neighbours along the first
-// two lattice directions are usually read from the same L2
-__device__ __forceinline__ int xcd_element(int b, int K) {
-  const int per = (K + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
 // ----------------------------------------------------------------------------- lifting
 // LDS sizes (doubles) of one element in the lifting kernel
 template <int N> struct LiftLds {
@@ -1163,7 +1155,7 @@ static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const do
 template <int N, bool NS, int VF>
 static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
                           double a, double b, double dt, int mode, hipStream_t st) {
-  dim3 grid(8 * ((g.K + 7) / 8)), block(Sz<N>::NT);
+  dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
   if (mode == 0)
     hipLaunchKernelGGL((k_split<N, NS, VF, 0>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   else
@@ -1188,7 +1180,7 @@ static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, 
 template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st) {
-  dim3 grid(8 * ((g.K + 7) / 8)), block(Sz<N>::NT);
+  dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
   if (!lgl) {
     if (out != LIFT_G) return DG_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_lift<N, false, LIFT_G>), grid, block, 0, st, g, ph, U, G, Fv);
@@ -1216,7 +1208,7 @@ int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const
 template <int N, int EPB>
 static int launch_batch_lift_t(const BatchView &bv, hipStream_t st) {
   const int nblk = (bv.total + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_lift_b<N, EPB>), dim3(8 * ((nblk + 7) / 8)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  hipLaunchKernelGGL((k_lift_b<N, EPB>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -1224,7 +1216,7 @@ static int launch_batch_lift_t(const BatchView &bv, hipStream_t st) {
 template <int N, bool NS, int VF, int EPB>
 static int launch_batch_split_t(const BatchView &bv, hipStream_t st) {
   const int nblk = (bv.total + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB>), dim3(8 * ((nblk + 7) / 8)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }

@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   __shared__ double sX[NX];
   __shared__ double sD[n * n], sDh[n * n];
   double *sF = sX, *sH = sX, *sJ = sX, *sPA = sX + 3 * n3;
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int e = xcd_element(blockIdx.x, g.K), t = threadIdx.x;
+  if (e >= g.K) return;
   const bool act = t < n3;
   const double gamma = ph.gamma, gm1 = gamma - 1.0, g1 = gamma / gm1;
   const int vf = ph.vf;
@@ -340,8 +341,8 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
                                                          double *__restrict__ Rb, double ra, double rb, int upd) {
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
-  const int e = blockIdx.x, t = threadIdx.x;
-  if (t >= n3) return;
+  const int e = xcd_element(blockIdx.x, g.K), t = threadIdx.x;
+  if (e >= g.K || t >= n3) return;
   const int id3[3] = {t % n, (t / n) % n, t / n2};
   double Wb[4] = {0.0, 0.0, 0.0, 0.0};
   bool face = false;
@@ -394,7 +395,7 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
   if constexpr (N > 7) {
     return DG_ERR_UNSUPPORTED;  // the reverse kernel's LDS staging exceeds 160 KB beyond N = 7
   } else {
-  dim3 grid(g.K), block(VSz<N>::NT);
+  dim3 grid(xcd_grid(g.K)), block(VSz<N>::NT);
   if (eqn == DG_NAVIER_STOKES) {
     hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale, accumulate);
     if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;

@@ -29,7 +29,7 @@ EXPORTS = [
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
-    "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp",
+    "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
 ]
 
 
@@ -74,6 +74,8 @@ def lib():
         L.dg_rk_stage_vjp.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.dg_rk_stage_keep.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, _VP]
         L.dg_rk_step_vjp.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP, ctypes.c_double]
+        L.dg_rk_steps_vjp.argtypes = [_VP, ctypes.c_int, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP,
+                                      ctypes.c_double]
         L.dg_timestep.argtypes = [_VP, _VP, ctypes.c_double, ctypes.c_double, _D]
         L.dg_integrals.argtypes = [_VP, _VP, _D]
         L.dg_check_finite.argtypes = [_VP, _VP]
@@ -172,7 +174,7 @@ class DGSolver:
         self.shape = (K, 5, self.n3)
         self.eqn, self.form, self.volflux, self.riemann = eqn, form, volflux, riemann
         self.gamma, self.mu = gamma, mu
-        self._stream = st
+        self._stream = st.cuda_stream
 
     @classmethod
     def from_workload(cls, wl, xgeo, nbr, nside, **kw):
@@ -191,9 +193,9 @@ class DGSolver:
             raise DGError(rc, f"{what}: {msg.decode() if msg else ''}")
 
     def _sync_stream(self):
-        st = self.torch.cuda.current_stream()
-        if st is not self._stream:
-            self._check(lib().dg_set_stream(self.h, _VP(st.cuda_stream)), "dg_set_stream")
+        st = self.torch.cuda.current_stream().cuda_stream
+        if st != self._stream:
+            self._check(lib().dg_set_stream(self.h, _VP(st)), "dg_set_stream")
             self._stream = st
 
     def empty(self):
@@ -239,6 +241,18 @@ class DGSolver:
         sg = None if stage_G is None else (_VP * 5)(*[(_dptr(g) if g is not None else None) for g in stage_G])
         self._check(lib().dg_rk_step_vjp(self.h, su, sg, _VP(_dptr(U_bar)), _VP(_dptr(R_bar)), dt),
                     "dg_rk_step_vjp")
+
+    def rk_steps_vjp(self, stage_U, stage_G, U_bar, R_bar, dt):
+        """Reverse of len(stage_U) // 5 consecutive steps given their stage inputs in forward
+        order (and kept lifting outputs, or None entries)."""
+        self._sync_stream()
+        k = len(stage_U)
+        if k == 0 or k % 5:
+            raise ValueError("stage_U must hold five stage inputs per step")
+        su = (_VP * k)(*[_dptr(u) for u in stage_U])
+        sg = None if stage_G is None else (_VP * k)(*[(_dptr(g) if g is not None else None) for g in stage_G])
+        self._check(lib().dg_rk_steps_vjp(self.h, k // 5, su, sg, _VP(_dptr(U_bar)), _VP(_dptr(R_bar)), dt),
+                    "dg_rk_steps_vjp")
 
     def timestep(self, U, cfl=0.9, dfl=0.9) -> float:
         self._sync_stream()
@@ -457,11 +471,7 @@ def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
                 for idx in range(5 * steps - 1):
                     s = idx % 5
                     S.rk_stage_keep(bufs[idx], bufs[idx + 1], R, a[s], b[s], dt, grads[idx])
-                for st in range(steps - 1, -1, -1):
-                    gs = grads[5 * st:5 * st + 5]
-                    if st == steps - 1:
-                        gs = gs[:4] + [None]
-                    S.rk_step_vjp(bufs[5 * st:5 * st + 5], gs, Ubar, Rbar, dt)
+                S.rk_steps_vjp(bufs[:5 * steps], grads[:5 * steps - 1] + [None], Ubar, Rbar, dt)
             bufs[0] = None
             return Ubar
 

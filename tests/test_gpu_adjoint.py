@@ -192,4 +192,34 @@ def test_step_vjp_matches_stage_vjps(dg):
     rel = float((Ub1 - Ub2).abs().max() / Ub1.abs().max())
     print(f"step VJP vs five stage VJPs: max relative difference {rel:.2e}")
     assert rel <= 1e-13
+
+
+def test_steps_vjp_equals_repeated_step_vjp(dg):
+    """dg_rk_steps_vjp over three steps (register updates merged across step boundaries, some
+    lifting outputs kept, some recomputed) equals three dg_rk_step_vjp calls bit for bit."""
+    import torch
+    wl = inputs.workload(5, K1=3)
+    S, U0 = dg.build_solver(wl)
+    U0 = to_gpu(inputs.random_perturbation(U0.cpu().numpy(), 6, 1e-3))
+    dt = S.timestep(U0, 0.9, 0.9)
+    a, b, _ = dg.rk_coefficients()
+    nst = 15
+    bufs = [U0.clone()] + [S.empty() for _ in range(nst)]
+    G = [S.empty_grad() if k % 4 else None for k in range(nst)]
+    R = torch.zeros_like(U0)
+    for k in range(nst):
+        if G[k] is None:
+            S.rk_stage(bufs[k], bufs[k + 1], R, a[k % 5], b[k % 5], dt)
+        else:
+            S.rk_stage_keep(bufs[k], bufs[k + 1], R, a[k % 5], b[k % 5], dt, G[k])
+    rng = np.random.default_rng(9)
+    w = to_gpu(rng.standard_normal(U0.shape))
+    Ub1, Rb1 = w.clone(), torch.zeros_like(w)
+    for st in range(2, -1, -1):
+        S.rk_step_vjp(bufs[5 * st:5 * st + 5], G[5 * st:5 * st + 5], Ub1, Rb1, dt)
+    Ub2, Rb2 = w.clone(), torch.zeros_like(w)
+    S.rk_steps_vjp(bufs[:nst], G, Ub2, Rb2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(Ub1, Ub2) and torch.equal(Rb1, Rb2)
+    assert float(Rb2.abs().max()) == 0.0
     assert float(Rb1.abs().max()) == 0.0 and float(Rb2.abs().max()) == 0.0

@@ -112,6 +112,9 @@ def test_null_arguments(dg):
     assert L.dg_init(None, 3, 1, None, None, ctypes.byref(h)) == -1
     assert L.dg_rhs(None, None, None) == -1
     assert L.dg_rk_stage(None, None, None, None, 0.0, 0.0, 0.0) == -1
+    assert L.dg_rk_step_vjp(None, None, None, None, None, 0.0) == -1
+    assert L.dg_rk_steps_vjp(None, 2, None, None, None, None, 0.0) == -1
+    assert L.dg_rk_stage_keep(None, None, None, None, 0.0, 0.0, 0.0, None) == -1
     assert L.dg_nodes(0, 1, None, None) == -1
     b = ctypes.c_void_p()
     assert L.dg_batch_create(None, 0, ctypes.byref(b)) == -1 and not b.value
