@@ -251,6 +251,14 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   const double gm1 = ph.gamma - 1.0;
   const double *Ue = U + (size_t)e * 5 * n3;
+  // the metric terms of the next direction are loaded one phase ahead (at most 3 per thread)
+  constexpr int JPT = (3 * n3 + NT - 1) / NT;
+  double jn[JPT];
+  {
+    const double *Jd = g.Ja + (size_t)e * 9 * n3;
+#pragma unroll
+    for (int r = 0; r < JPT; ++r) jn[r] = (valid && t + r * NT < 3 * n3) ? Jd[t + r * NT] : 0.0;
+  }
   if (valid && t < n3) {
     double Uq[5], W[4];
 #pragma unroll
@@ -303,9 +311,14 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
     __syncthreads();
-    const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3;
-    if (valid)
-      for (int c = t; c < 3 * n3; c += NT) sJa[c] = Jd[c];
+#pragma unroll
+    for (int r = 0; r < JPT; ++r)
+      if (valid && t + r * NT < 3 * n3) sJa[t + r * NT] = jn[r];
+    if (dir < 2) {
+      const double *Jd = g.Ja + ((size_t)e * 9 + (dir + 1) * 3) * n3;
+#pragma unroll
+      for (int r = 0; r < JPT; ++r) jn[r] = (valid && t + r * NT < 3 * n3) ? Jd[t + r * NT] : 0.0;
+    }
     __syncthreads();
     if (OUT == LIFT_FV && valid && t < n3) {
 #pragma unroll
@@ -785,6 +798,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   const double *Jae = g.Ja + (size_t)e * 9 * n3;
   double *sS = sA;           // rho, u, v, w, beta (EC) or H (KEP, central) per node
   double *sJ = sA + 5 * n3;  // Ja^i_d at (i*3+d)*n3 + node
+  double *sF = sA;           // first: the contravariant viscous fluxes of the three directions
+  if (NS && act) {
+    // staged before the face phase, so that their loads overlap with the neighbours' face reads
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sF[c * n3 + t] = Ge[c * n3 + t];
+  }
   // numerical surface flux on the six faces, stored outward for this element
   for (int q = valid ? t : 6 * n2; q < 6 * n2; q += NT) {
     const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
@@ -863,16 +882,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     // viscous part in strong form: -sum_a D_ia Fv^dir_a along each line, and -Fv.N_out lhat(+-1)
     // on the faces through the node.  The contravariant viscous fluxes of all three directions
     // (from the lifting kernel) are staged once in region A.
-    double *sF = sA;
     if (act) {
 #pragma unroll
       for (int dir = 0; dir < 3; ++dir) {
         double fv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          fv[c] = Ge[(dir * 4 + c) * n3 + t];
-          sF[(dir * 4 + c) * n3 + t] = fv[c];
-        }
+        for (int c = 0; c < 4; ++c) fv[c] = sF[(dir * 4 + c) * n3 + t];
         const int id = id3[dir];
         if (id == 0 || id == N) {
           const bool plus = id == N;
@@ -883,7 +898,6 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
         }
       }
     }
-    __syncthreads();
     if (act) {
 #pragma unroll
       for (int dir = 0; dir < 3; ++dir) {
