@@ -61,8 +61,14 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // then Ja^dir of the current direction (3 per node) and the partner shares of the pair
   // rounds (5 per node)
   static_assert(!NS || NX >= 12 * n3, "region X holds H");
+  // where the LDS allows it, all metric terms (9 per node) and the momentum part of the kept
+  // viscous fluxes (9 per node) are staged once at the start, so that no later phase waits on a
+  // global load after a barrier
+  constexpr int NST = 9 + (NS ? 9 : 0);
+  constexpr bool STAGE = (10 + NST) * n3 + NX + 2 * n * n <= 160 * 1024 / 8;
   __shared__ double sX[NX];
   __shared__ double sD[n * n], sDh[n * n];
+  __shared__ double sM[STAGE ? NST * n3 : 1];  // Ja^i_d at (i*3+d)*n3, then Fv^dir_c at (9+dir*3+c)*n3
   double *sF = sX, *sH = sX, *sJ = sX, *sPA = sX + 3 * n3;
   const int e = xcd_element(blockIdx.x, g.K), t = threadIdx.x;
   if (e >= g.K) return;
@@ -75,6 +81,25 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   const double *Ge = G + (size_t)e * 12 * n3;
   const double *Jae = g.Ja + (size_t)e * 9 * n3;
   const double *sJe = g.sJ + (size_t)e * n3;
+  // this element's metric term Ja^dir_d and momentum viscous flux Fv^dir_c at a node
+  auto JA = [&](int dir, int d, int node) -> double {
+    if constexpr (STAGE) return sM[(dir * 3 + d) * n3 + node];
+    else return Jae[(dir * 3 + d) * n3 + node];
+  };
+  auto FV = [&](int dir, int c, int node) -> double {
+    if constexpr (STAGE) return sM[(9 + dir * 3 + c) * n3 + node];
+    else return Ge[(dir * 4 + c) * n3 + node];
+  };
+  if (STAGE && act) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sM[c * n3 + t] = Jae[c * n3 + t];
+    if (NS) {
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sM[(9 + dir * 3 + c) * n3 + t] = Ge[(dir * 4 + c) * n3 + t];
+    }
+  }
   dgf::P q;
   if (act) {
     double Uq[5];
@@ -106,7 +131,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       Ax[v] = -sjn * Utb[((size_t)nb * 5 + v) * n3 + qn];
     }
     // normal along +xi_dn scaled by s-hat: this element's Ja^dn at the face node
-    const double nt[3] = {Jae[(dn * 3) * n3 + qo], Jae[(dn * 3 + 1) * n3 + qo], Jae[(dn * 3 + 2) * n3 + qo]};
+    const double nt[3] = {JA(dn, 0, qo), JA(dn, 1, qo), JA(dn, 2, qo)};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
@@ -131,7 +156,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       double gbo[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) gbo[c] = 0.0;
-      const double tn[3] = {Ge[(dn * 4) * n3 + qo], Ge[(dn * 4 + 1) * n3 + qo], Ge[(dn * 4 + 2) * n3 + qo]};
+      const double tn[3] = {FV(dn, 0, qo), FV(dn, 1, qo), FV(dn, 2, qo)};
       double Fvb[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
@@ -175,7 +200,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       const int id = id3[dir];
       if (id != 0 && id != N) continue;
       const double sg = (id == N) ? 1.0 : -1.0;
-      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      const double nv[3] = {JA(dir, 0, t), JA(dir, 1, t), JA(dir, 2, t)};
       double Fib[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fib[v] = -lh * sg * sA[v * n3 + t];
@@ -207,9 +232,9 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
 #pragma unroll
         for (int c = 0; c < 4; ++c) fvb[c] -= Dmi * sA[(1 + c) * n3 + qm];
       }
-      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      const double nv[3] = {JA(dir, 0, t), JA(dir, 1, t), JA(dir, 2, t)};
       const double Fvb[5] = {0.0, fvb[0], fvb[1], fvb[2], fvb[3]};
-      const double tn[3] = {Ge[(dir * 4) * n3 + t], Ge[(dir * 4 + 1) * n3 + t], Ge[(dir * 4 + 2) * n3 + t]};
+      const double tn[3] = {FV(dir, 0, t), FV(dir, 1, t), FV(dir, 2, t)};
       dgf::visc_flux_adj_tn(q, tn, ph.mu, ph.kappa, nv, Fvb, pa, gbo);
     }
     const double sj = sJe[t];
@@ -233,7 +258,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
         const int id = id3[dir];
         const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
         const int base = t - id * str;
-        const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+        const double nv[3] = {JA(dir, 0, t), JA(dir, 1, t), JA(dir, 2, t)};
         double hs[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) hs[c] = 0.0;
@@ -268,12 +293,21 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // ---- volume: pairs, diagonal and viscous transpose, direction by direction
   for (int dir = 0; dir < 3; ++dir) {
     double nvo[3] = {0.0, 0.0, 0.0};
-    __syncthreads();
-    if (act) {
-      nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
-      sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
+    const double *sJd = sJ;
+    if constexpr (STAGE) {
+      // the metric terms are in LDS already; every exchange round ends with a barrier, so
+      // only the first direction needs one (after the last reads of region X)
+      if (dir == 0) __syncthreads();
+      sJd = sM + dir * 3 * n3;
+      if (act) { nvo[0] = sJd[t]; nvo[1] = sJd[n3 + t]; nvo[2] = sJd[2 * n3 + t]; }
+    } else {
+      __syncthreads();
+      if (act) {
+        nvo[0] = Jae[(dir * 3) * n3 + t]; nvo[1] = Jae[(dir * 3 + 1) * n3 + t]; nvo[2] = Jae[(dir * 3 + 2) * n3 + t];
+        sJ[t] = nvo[0]; sJ[n3 + t] = nvo[1]; sJ[2 * n3 + t] = nvo[2];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     {
       const int id = act ? id3[dir] : 0;
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
@@ -290,8 +324,8 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
           const int qp = base + jp * str;
           dgf::P r;
           r.r = sQ[qp]; r.u = sQ[n3 + qp]; r.v = sQ[2 * n3 + qp]; r.w = sQ[3 * n3 + qp]; r.p = sQ[4 * n3 + qp];
-          const double nm[3] = {0.5 * (nvo[0] + sJ[qp]), 0.5 * (nvo[1] + sJ[n3 + qp]),
-                                0.5 * (nvo[2] + sJ[2 * n3 + qp])};
+          const double nm[3] = {0.5 * (nvo[0] + sJd[qp]), 0.5 * (nvo[1] + sJd[n3 + qp]),
+                                0.5 * (nvo[2] + sJd[2 * n3 + qp])};
           const double Dij2 = 2.0 * sD[id * n + jp], Dji2 = 2.0 * sD[jp * n + id];
           double Fb[5];
 #pragma unroll
