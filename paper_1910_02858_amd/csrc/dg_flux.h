@@ -120,12 +120,15 @@ DGFN void kep_flux(const P &A, const P &B, const double *nv, double g1, double *
   F[4] = f0 * 0.5 * (enthalpy(A, g1) + enthalpy(B, g1));
 }
 
-DGFN void kep_flux_adj(const P &A, const P &B, const double *nv, double g1, const double *Fb, PA &aA, PA &aB) {
+// reverse of kep_flux with the two total enthalpies given: the adjoints of the enthalpies are
+// accumulated into hA, hB (enthalpy_adj maps them to the states)
+DGFN void kep_flux_adj_h(const P &A, const P &B, double HA, double HB, const double *nv, const double *Fb, PA &aA,
+                         PA &aB, double &hA, double &hB) {
   const double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
   const double umn = um * nv[0] + vm * nv[1] + wm * nv[2];
   const double rm = 0.5 * (A.r + B.r);
   const double f0 = rm * umn;
-  const double Hm = 0.5 * (enthalpy(A, g1) + enthalpy(B, g1));
+  const double Hm = 0.5 * (HA + HB);
   const double g0 = Fb[0] + Fb[1] * um + Fb[2] * vm + Fb[3] * wm + Fb[4] * Hm;  // adjoint of f0
   const double bu = Fb[1] * f0 + g0 * rm * nv[0];
   const double bv = Fb[2] * f0 + g0 * rm * nv[1];
@@ -135,8 +138,15 @@ DGFN void kep_flux_adj(const P &A, const P &B, const double *nv, double g1, cons
   const double bH = Fb[4] * f0;
   aA.r += 0.5 * br; aA.u += 0.5 * bu; aA.v += 0.5 * bv; aA.w += 0.5 * bw; aA.p += 0.5 * bp;
   aB.r += 0.5 * br; aB.u += 0.5 * bu; aB.v += 0.5 * bv; aB.w += 0.5 * bw; aB.p += 0.5 * bp;
-  enthalpy_adj(A, g1, 0.5 * bH, aA);
-  enthalpy_adj(B, g1, 0.5 * bH, aB);
+  hA += 0.5 * bH;
+  hB += 0.5 * bH;
+}
+
+DGFN void kep_flux_adj(const P &A, const P &B, const double *nv, double g1, const double *Fb, PA &aA, PA &aB) {
+  double hA = 0.0, hB = 0.0;
+  kep_flux_adj_h(A, B, enthalpy(A, g1), enthalpy(B, g1), nv, Fb, aA, aB, hA, hB);
+  enthalpy_adj(A, g1, hA, aA);
+  enthalpy_adj(B, g1, hB, aB);
 }
 
 // mean of the two Euler fluxes
@@ -315,11 +325,11 @@ DGFN void riemann(int rs, int vf, const P &L, const P &R, const double *UL, cons
   for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
 }
 
-// reverse of riemann: conservative adjoints of both states (accumulated)
-DGFN void riemann_adj(int rs, int vf, const P &L, const P &R, const double *UL, const double *UR, const double *nh,
-                      double gamma, const double *Fb, double *ULb, double *URb) {
+// reverse of riemann: primitive adjoints of both states (accumulated into aL, aR); the LLF
+// jump term, linear in the conservative states, enters through (dU/dP)^T
+DGFN void riemann_adj_prim(int rs, int vf, const P &L, const P &R, const double *UL, const double *UR,
+                           const double *nh, double gamma, const double *Fb, PA &aL, PA &aR) {
   const double gm1 = gamma - 1.0, g1 = gamma / gm1;
-  PA aL = zero_pa(), aR = zero_pa();
   if (rs >= 2) {
     pair_flux_adj(vf, L, R, nh, g1, Fb, aL, aR);
     if (rs == 3) {
@@ -337,12 +347,14 @@ DGFN void riemann_adj(int rs, int vf, const P &L, const P &R, const double *UL, 
       const double unL = L.u * nh[0] + L.v * nh[1] + L.w * nh[2], unR = R.u * nh[0] + R.v * nh[1] + R.w * nh[2];
       const double xL = fabs(unL) + cL, xR = fabs(unR) + cR;
       const double lam = fmax(xL, xR);
-      double blam = 0.0;
+      double blam = 0.0, jL[5], jR[5];
       for (int v = 0; v < 5; ++v) {
         blam -= 0.5 * Fb[v] * (UR[v] - UL[v]);
-        ULb[v] += 0.5 * lam * Fb[v];
-        URb[v] -= 0.5 * lam * Fb[v];
+        jL[v] = 0.5 * lam * Fb[v];
+        jR[v] = -0.5 * lam * Fb[v];
       }
+      prim_adj_of_cons(L, gm1, jL, aL);
+      prim_adj_of_cons(R, gm1, jR, aR);
       double wL, wR;
       if (fabs(xL - xR) <= 1e-12 * fmax(fabs(xL), fabs(xR))) { wL = 0.5; wR = 0.5; }
       else if (xL > xR) { wL = 1.0; wR = 0.0; }
@@ -359,8 +371,15 @@ DGFN void riemann_adj(int rs, int vf, const P &L, const P &R, const double *UL, 
       roe_diss_adj(L, R, nh, gm1, g1, Dbar, aL, aR);
     }
   }
-  cons_adj(L, gm1, aL, ULb);
-  cons_adj(R, gm1, aR, URb);
+}
+
+// reverse of riemann: conservative adjoints of both states (accumulated)
+DGFN void riemann_adj(int rs, int vf, const P &L, const P &R, const double *UL, const double *UR, const double *nh,
+                      double gamma, const double *Fb, double *ULb, double *URb) {
+  PA aL = zero_pa(), aR = zero_pa();
+  riemann_adj_prim(rs, vf, L, R, UL, UR, nh, gamma, Fb, aL, aR);
+  cons_adj(L, gamma - 1.0, aL, ULb);
+  cons_adj(R, gamma - 1.0, aR, URb);
 }
 
 // viscous flux along nv (components 0..4, component 0 is zero); g[d*4+c] = dW_c/dx_d with

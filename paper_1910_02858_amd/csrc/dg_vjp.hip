@@ -54,18 +54,19 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   constexpr int NF = NS ? 17 : 5;  // results per face point: primitive adjoint, gradient adjoint
-  constexpr int NX = (NF * 6 * n2 > 8 * n3) ? NF * 6 * n2 : 8 * n3;
-  __shared__ double sQ[5 * n3];  // primitive state
+  constexpr int NX = (NF * 6 * n2 > (NS ? 12 : 9) * n3) ? NF * 6 * n2 : (NS ? 12 : 9) * n3;
+  __shared__ double sQ[6 * n3];  // primitive state and total enthalpy
   __shared__ double sA[5 * n3];  // Abar = -(1/J) Utbar
   // region X: first the face-point results, then H = (1/J) Gbar (12 per node, Navier-Stokes),
   // then Ja^dir of the current direction (3 per node) and the partner shares of the pair
-  // rounds (5 per node)
+  // rounds (6 per node: primitive adjoint and enthalpy adjoint)
   static_assert(!NS || NX >= 12 * n3, "region X holds H");
+  static_assert(NX >= 9 * n3, "region X holds Ja^dir and the partner shares");
   // where the LDS allows it, all metric terms (9 per node) and the momentum part of the kept
   // viscous fluxes (9 per node) are staged once at the start, so that no later phase waits on a
   // global load after a barrier
   constexpr int NST = 9 + (NS ? 9 : 0);
-  constexpr bool STAGE = (10 + NST) * n3 + NX + 2 * n * n <= 160 * 1024 / 8;
+  constexpr bool STAGE = (11 + NST) * n3 + NX + 2 * n * n <= 160 * 1024 / 8;
   __shared__ double sX[NX];
   __shared__ double sD[n * n], sDh[n * n];
   __shared__ double sM[STAGE ? NST * n3 : 1];  // Ja^i_d at (i*3+d)*n3, then Fv^dir_c at (9+dir*3+c)*n3
@@ -107,6 +108,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + t];
     q = dgf::prim(Uq, gm1);
     sQ[t] = q.r; sQ[n3 + t] = q.u; sQ[2 * n3 + t] = q.v; sQ[3 * n3 + t] = q.w; sQ[4 * n3 + t] = q.p;
+    sQ[5 * n3 + t] = dgf::enthalpy(q, g1);
     const double sj = sJe[t];
 #pragma unroll
     for (int v = 0; v < 5; ++v) sA[v * n3 + t] = -sj * Utb[((size_t)e * 5 + v) * n3 + t];
@@ -140,16 +142,14 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     for (int v = 0; v < 5; ++v) Fb[v] = lh * (plus ? (Aw[v] - Ax[v]) : (Ax[v] - Aw[v]));
     const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
     const dgf::P PM = dgf::prim(UM, gm1), PS = dgf::prim(US, gm1);
-    double Fbs[5], bM[5] = {0, 0, 0, 0, 0}, bS[5] = {0, 0, 0, 0, 0};
+    double Fbs[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fbs[v] = Fb[v] * sh;
-    dgf::riemann_adj(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, bM, bS);
-    const double *bo = plus ? bM : bS;
+    // the primitive adjoint of the own trace (the final (dP/dU)^T map of the node applies to it)
+    dgf::PA aM = dgf::zero_pa(), aS = dgf::zero_pa();
+    dgf::riemann_adj_prim(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, aM, aS);
+    dgf::PA pc = plus ? aM : aS;
     const dgf::P Po = plus ? PM : PS;
-    // the conservative adjoint of the own trace, carried as a primitive adjoint (the final
-    // (dP/dU)^T map returns it unchanged)
-    dgf::PA pc = dgf::zero_pa();
-    dgf::prim_adj_of_cons(Po, gm1, bo, pc);
     if (NS) {
       // F contains -1/2 Fv(U_own, G_own) . nt; its momentum part along the face's direction is
       // the contravariant viscous flux of that direction from the lifting (G holds those)
@@ -290,7 +290,10 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       dgf::lift_vars_adj(q, ph.R, Wb, pl);
     }
   }
-  // ---- volume: pairs, diagonal and viscous transpose, direction by direction
+  // ---- volume: pairs, diagonal and viscous transpose, direction by direction.  With the KEP flux
+  // the adjoint of this node's total enthalpy is summed over all pairs and mapped once at the end.
+  const double Hq = act ? sQ[5 * n3 + t] : 0.0;
+  double hq_b = 0.0;
   for (int dir = 0; dir < 3; ++dir) {
     double nvo[3] = {0.0, 0.0, 0.0};
     const double *sJd = sJ;
@@ -324,6 +327,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
           const int qp = base + jp * str;
           dgf::P r;
           r.r = sQ[qp]; r.u = sQ[n3 + qp]; r.v = sQ[2 * n3 + qp]; r.w = sQ[3 * n3 + qp]; r.p = sQ[4 * n3 + qp];
+          const double Hr = sQ[5 * n3 + qp];
           const double nm[3] = {0.5 * (nvo[0] + sJd[qp]), 0.5 * (nvo[1] + sJd[n3 + qp]),
                                 0.5 * (nvo[2] + sJd[2 * n3 + qp])};
           const double Dij2 = 2.0 * sD[id * n + jp], Dji2 = 2.0 * sD[jp * n + id];
@@ -331,15 +335,17 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
 #pragma unroll
           for (int v = 0; v < 5; ++v) Fb[v] = Dij2 * Ao[v] + (half ? 0.0 : Dji2 * sA[v * n3 + qp]);
           dgf::PA pr = dgf::zero_pa();
-          dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
+          double hr_b = 0.0;
+          if (vf == 0) dgf::kep_flux_adj_h(q, r, Hq, Hr, nm, Fb, pa, pr, hq_b, hr_b);
+          else dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
           // every node receives exactly one partner share per round
           sPA[qp] = pr.r; sPA[n3 + qp] = pr.u; sPA[2 * n3 + qp] = pr.v; sPA[3 * n3 + qp] = pr.w;
-          sPA[4 * n3 + qp] = pr.p;
+          sPA[4 * n3 + qp] = pr.p; sPA[5 * n3 + qp] = hr_b;
         }
         __syncthreads();
         if (act) {
           pa.r += sPA[t]; pa.u += sPA[n3 + t]; pa.v += sPA[2 * n3 + t]; pa.w += sPA[3 * n3 + t];
-          pa.p += sPA[4 * n3 + t];
+          pa.p += sPA[4 * n3 + t]; hq_b += sPA[5 * n3 + t];
         }
         __syncthreads();
       }
@@ -354,6 +360,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     }
   }
   if (act) {
+    dgf::enthalpy_adj(q, g1, hq_b, pa);
     dgf::PA pt;
     pt.r = fma(scale, pa.r, pl.r); pt.u = fma(scale, pa.u, pl.u); pt.v = fma(scale, pa.v, pl.v);
     pt.w = fma(scale, pa.w, pl.w); pt.p = fma(scale, pa.p, pl.p);
