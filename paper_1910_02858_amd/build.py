@@ -24,6 +24,10 @@ COMMON = [
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # a*b+c is fused where one source expression says so, never across statements: every kernel
+    # that instantiates the same per-element code then rounds alike, whatever the surrounding
+    # code (the one-mesh, batched and gradient-keeping entry points agree bit for bit)
+    "-ffp-contract=on",
 ]
 
 

@@ -259,6 +259,17 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
     for (int r = 0; r < JPT; ++r) jn[r] = (valid && t + r * NT < 3 * n3) ? Jd[t + r * NT] : 0.0;
   }
+  // on LGL nodes with one face point per thread, the neighbour's trace is loaded before the
+  // first barrier
+  constexpr bool PF = LGL && 6 * n2 <= NT;
+  double Unp[5];
+  if (PF && valid && t < 6 * n2) {
+    const int s = t / n2, ab = t - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const int nb = g.nbr[(size_t)e * 6 + s];
+    const int qn = line_node<n>(dn, a, b, (s & 1) ? 0 : N);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Unp[v] = U[((size_t)nb * 5 + v) * n3 + qn];
+  }
   if (valid && t < n3) {
     double Uq[5], W[4];
 #pragma unroll
@@ -282,7 +293,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       for (int v = 0; v < 4; ++v) WL[v] = sW[v * n3 + q];
       double Uq[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
+      for (int v = 0; v < 5; ++v) Uq[v] = PF ? Unp[v] : Un[v * n3 + qn];
       grad_prim_to_W(Uq, gm1, ph.R, WR);
     } else {
       const double *lo = sl + (plus ? n : 0), *ln = sl + (plus ? 0 : n);
