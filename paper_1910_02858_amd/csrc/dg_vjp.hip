@@ -12,7 +12,7 @@
 // With Abar = -(1/J) Utbar (the adjoint of acc) the reverse is:
 //   * each unordered pair {q, p} on a line: Fbar = 2 D_qp Abar_q + 2 D_pq Abar_p, then the
 //     two-point flux's transposed Jacobian in both arguments (the partner's share goes through
-//     LDS atomics);
+//     LDS, one share per node and round, collected in a fixed order);
 //   * viscous volume term: Fvbar_p = -sum_q D_qp Abar_q, then the viscous flux's transposed
 //     Jacobian in U and in G;
 //   * each face point: the flux enters both elements, so Fbar = lhat (Abar_master - Abar_slave),
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // ---- viscous part, all directions before the pair rounds: acc_m -= sum_i D_mi Fv_i gives
   // Fvbar_i = -sum_m D_mi Abar_m; the interior face term -F_int contributes +lhat sg Abar_i.
   // The gradient adjoint of this node is final afterwards.
-  double hq[12];  // H = (1/J) scale Gbar of this node
+  double hg[12];  // H = (1/J) scale Gbar of this node
   if (NS && act) {
     double gbo[12];
 #pragma unroll
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     }
     const double sj = sJe[t];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) hq[c] = sj * (scale * gbo[c]);
+    for (int c = 0; c < 12; ++c) hg[c] = sj * (scale * gbo[c]);
   }
   // ---- lifting transposed, own part (volume and own face terms); the face terms also go to
   // the face array for the neighbours
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     __syncthreads();  // every node has collected its face results from region X
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sH[c * n3 + t] = hq[c];
+      for (int c = 0; c < 12; ++c) sH[c * n3 + t] = hg[c];
     }
     __syncthreads();
     if (act) {
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
           double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double f = c0 * (nv[0] * hq[v] + nv[1] * hq[4 + v] + nv[2] * hq[8 + v]);
+            const double f = c0 * (nv[0] * hg[v] + nv[1] * hg[4 + v] + nv[2] * hg[8 + v]);
             Wb[v] += f;
             pf[v * n2] = f;
           }
@@ -290,10 +290,10 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       dgf::lift_vars_adj(q, ph.R, Wb, pl);
     }
   }
-  // ---- volume: pairs, diagonal and viscous transpose, direction by direction.  With the KEP flux
-  // the adjoint of this node's total enthalpy is summed over all pairs and mapped once at the end.
-  const double Hq = act ? sQ[5 * n3 + t] : 0.0;
-  double hq_b = 0.0;
+  // ---- volume: pairs and diagonal, direction by direction.  With the KEP flux the adjoint of
+  // this node's total enthalpy is summed over all pairs and mapped once at the end.
+  const double Ht = act ? sQ[5 * n3 + t] : 0.0;
+  double Htb = 0.0;
   for (int dir = 0; dir < 3; ++dir) {
     double nvo[3] = {0.0, 0.0, 0.0};
     const double *sJd = sJ;
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
           const int qp = base + jp * str;
           dgf::P r;
           r.r = sQ[qp]; r.u = sQ[n3 + qp]; r.v = sQ[2 * n3 + qp]; r.w = sQ[3 * n3 + qp]; r.p = sQ[4 * n3 + qp];
-          const double Hr = sQ[5 * n3 + qp];
+          const double Hr = sQ[5 * n3 + qp];  // the partner's total enthalpy
           const double nm[3] = {0.5 * (nvo[0] + sJd[qp]), 0.5 * (nvo[1] + sJd[n3 + qp]),
                                 0.5 * (nvo[2] + sJd[2 * n3 + qp])};
           const double Dij2 = 2.0 * sD[id * n + jp], Dji2 = 2.0 * sD[jp * n + id];
@@ -335,17 +335,17 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
 #pragma unroll
           for (int v = 0; v < 5; ++v) Fb[v] = Dij2 * Ao[v] + (half ? 0.0 : Dji2 * sA[v * n3 + qp]);
           dgf::PA pr = dgf::zero_pa();
-          double hr_b = 0.0;
-          if (vf == 0) dgf::kep_flux_adj_h(q, r, Hq, Hr, nm, Fb, pa, pr, hq_b, hr_b);
+          double Hrb = 0.0;
+          if (vf == 0) dgf::kep_flux_adj_h(q, r, Ht, Hr, nm, Fb, pa, pr, Htb, Hrb);
           else dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
           // every node receives exactly one partner share per round
           sPA[qp] = pr.r; sPA[n3 + qp] = pr.u; sPA[2 * n3 + qp] = pr.v; sPA[3 * n3 + qp] = pr.w;
-          sPA[4 * n3 + qp] = pr.p; sPA[5 * n3 + qp] = hr_b;
+          sPA[4 * n3 + qp] = pr.p; sPA[5 * n3 + qp] = Hrb;
         }
         __syncthreads();
         if (act) {
           pa.r += sPA[t]; pa.u += sPA[n3 + t]; pa.v += sPA[2 * n3 + t]; pa.w += sPA[3 * n3 + t];
-          pa.p += sPA[4 * n3 + t]; hq_b += sPA[5 * n3 + t];
+          pa.p += sPA[4 * n3 + t]; Htb += sPA[5 * n3 + t];
         }
         __syncthreads();
       }
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     }
   }
   if (act) {
-    dgf::enthalpy_adj(q, g1, hq_b, pa);
+    dgf::enthalpy_adj(q, g1, Htb, pa);
     dgf::PA pt;
     pt.r = fma(scale, pa.r, pl.r); pt.u = fma(scale, pa.u, pl.u); pt.v = fma(scale, pa.v, pl.v);
     pt.w = fma(scale, pa.w, pl.w); pt.p = fma(scale, pa.p, pl.p);
