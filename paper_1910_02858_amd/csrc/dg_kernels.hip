@@ -795,7 +795,7 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
-template <int N, bool NS, int VF, int MODE>
+template <int N, bool NS, int VF, int MODE, bool EARLY = false>
 __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
@@ -814,6 +814,13 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     // staged before the face phase, so that their loads overlap with the neighbours' face reads
 #pragma unroll
     for (int c = 0; c < 12; ++c) sF[c * n3 + t] = Ge[c * n3 + t];
+  }
+  // the one-mesh kernel loads the node's own state before the face phase (the batched one has
+  // no registers to spare for it)
+  double Uo[5];
+  if (EARLY && act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
   }
   // numerical surface flux on the six faces, stored outward for this element
   for (int q = valid ? t : 6 * n2; q < 6 * n2; q += NT) {
@@ -850,12 +857,13 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = sg * F[v];
   }
   __syncthreads();
-  double Uo[5];
   PS o;
   double p = 0.0;
   if (act) {
+    if (!EARLY) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
+      for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
+    }
     const Pr5 P = to_prim(Uo, gm1);
     p = P.p;
     o.r = P.rho; o.u = P.u; o.v = P.v; o.w = P.w;
@@ -1027,7 +1035,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  split_body<N, NS, VF, MODE>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
+  split_body<N, NS, VF, MODE, true>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
 }
 
 // ----------------------------------------------------------------------------- ensemble batch
