@@ -941,8 +941,18 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   }
   // the first direction's barrier also separates the face-flux reads above from the partner
   // shares and publishes the staged state of every node
+  double Rq[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, sjq = 0.0;
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
+    if (EARLY && dir == 2 && act) {
+      // the epilogue's loads are issued before the last direction's rounds
+      sjq = g.sJ[(size_t)e * n3 + t];
+      if (MODE == 1 && ca != 0.0) {
+        const double *Re = R + (size_t)e * 5 * n3;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Rq[v] = Re[v * n3 + t];
+      }
+    }
     const bool wl = wave_local<n>(dir);
     if (dir > 0 && wl) wave_sync(); else __syncthreads();
     const double *sJd = sJ + 3 * dir * n3;
@@ -1006,7 +1016,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     }
   }
   if (act) {
-    const double sj = g.sJ[(size_t)e * n3 + t];
+    const double sj = EARLY ? sjq : g.sJ[(size_t)e * n3 + t];
     double *Oe = out + (size_t)e * 5 * n3;
     if (MODE == 0) {
 #pragma unroll
@@ -1016,7 +1026,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         // a = 0 (first stage) does not read R, so R may hold anything on entry
-        const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * (-acc[v] * sj);
+        const double r = (ca != 0.0 ? ca * (EARLY ? Rq[v] : Re[v * n3 + t]) : 0.0) + dt * (-acc[v] * sj);
         Re[v * n3 + t] = r;
         Oe[v * n3 + t] = Uo[v] + cb * r;
       }

@@ -294,6 +294,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // this node's total enthalpy is summed over all pairs and mapped once at the end.
   const double Ht = act ? sQ[5 * n3 + t] : 0.0;
   double Htb = 0.0;
+  // the epilogue's loads are issued before the rounds
+  double *Ube = Ub + (size_t)e * 5 * n3;
+  double ub0[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (act && accumulate) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ub0[v] = Ube[v * n3 + t];
+  }
   for (int dir = 0; dir < 3; ++dir) {
     double nvo[3] = {0.0, 0.0, 0.0};
     const double *sJd = sJ;
@@ -365,9 +372,8 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     pt.r = fma(scale, pa.r, pl.r); pt.u = fma(scale, pa.u, pl.u); pt.v = fma(scale, pa.v, pl.v);
     pt.w = fma(scale, pa.w, pl.w); pt.p = fma(scale, pa.p, pl.p);
     dgf::cons_adj(q, gm1, pt, cb);
-    double *Ube = Ub + (size_t)e * 5 * n3;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = (accumulate ? Ube[v * n3 + t] : 0.0) + cb[v];
+    for (int v = 0; v < 5; ++v) Ube[v * n3 + t] = ub0[v] + cb[v];
   }
 }
 
