@@ -16,8 +16,8 @@
 
 namespace dgf {
 
-struct P {  // primitive state
-  double r, u, v, w, p;
+struct P {  // primitive state; ir = 1/r is kept so that no function divides by the density
+  double r, u, v, w, p, ir;
 };
 struct PA {  // adjoint of a primitive state
   double r, u, v, w, p;
@@ -27,6 +27,7 @@ DGFN P prim(const double *U, double gm1) {
   P q;
   q.r = U[0];
   const double ir = 1.0 / U[0];
+  q.ir = ir;
   q.u = U[1] * ir; q.v = U[2] * ir; q.w = U[3] * ir;
   q.p = gm1 * (U[4] - 0.5 * (U[1] * q.u + U[2] * q.v + U[3] * q.w));
   return q;
@@ -41,7 +42,7 @@ DGFN PA zero_pa() {
 // conservative adjoint += (d prim / d U)^T a, for U = (rho, m, E), u = m/rho,
 // p = (gamma-1)(E - |m|^2/(2 rho))
 DGFN void cons_adj(const P &q, double gm1, const PA &a, double *Ub) {
-  const double ir = 1.0 / q.r;
+  const double ir = q.ir;
   const double q2 = q.u * q.u + q.v * q.v + q.w * q.w;
   Ub[0] += a.r - (a.u * q.u + a.v * q.v + a.w * q.w) * ir + a.p * gm1 * 0.5 * q2;
   Ub[1] += a.u * ir - a.p * gm1 * q.u;
@@ -62,21 +63,22 @@ DGFN void prim_adj_of_cons(const P &q, double gm1, const double *Ub, PA &a) {
 }
 
 // total enthalpy H = g1 p / rho + |u|^2 / 2 with g1 = gamma / (gamma - 1)
-DGFN double enthalpy(const P &q, double g1) { return g1 * q.p / q.r + 0.5 * (q.u * q.u + q.v * q.v + q.w * q.w); }
+DGFN double enthalpy(const P &q, double g1) { return g1 * q.p * q.ir + 0.5 * (q.u * q.u + q.v * q.v + q.w * q.w); }
 
 DGFN void enthalpy_adj(const P &q, double g1, double Hb, PA &a) {
-  a.p += Hb * g1 / q.r;
-  a.r -= Hb * g1 * q.p / (q.r * q.r);
+  const double k = Hb * g1 * q.ir;
+  a.p += k;
+  a.r -= k * q.p * q.ir;
   a.u += Hb * q.u; a.v += Hb * q.v; a.w += Hb * q.w;
 }
 
-DGFN double sound_speed(const P &q, double gamma) { return sqrt(gamma * q.p / q.r); }
+DGFN double sound_speed(const P &q, double gamma) { return sqrt(gamma * q.p * q.ir); }
 
 DGFN void sound_speed_adj(const P &q, double gamma, double c, double cb, PA &a) {
   // c = sqrt(gamma p / rho)
-  const double k = cb * 0.5 / c * gamma;
-  a.p += k / q.r;
-  a.r -= k * q.p / (q.r * q.r);
+  const double k = cb * 0.5 / c * gamma * q.ir;
+  a.p += k;
+  a.r -= k * q.p * q.ir;
 }
 
 DGFN double kink_sign(double x, double scale) {
@@ -261,7 +263,7 @@ DGFN void roe_diss_adj(const P &L, const P &R, const double *nh, double gm1, dou
   bc += 0.5 * (ba5 - ba1) * rt * dun * ic2;
   bdun += 0.5 * (ba5 - ba1) * rt * c * ic2;
   const double bic2 = ba1 * 0.5 * (dp - rt * c * dun) + ba5 * 0.5 * (dp + rt * c * dun) - ba2 * dp;
-  double bc2 = -bic2 * ic2 * ic2 + bc * 0.5 / c;
+  double bc2 = -bic2 * ic2 * ic2 + bc * 0.5 * c * ic2;  // 1/c = c / c^2
   // un = u . n
   for (int k = 0; k < 3; ++k) bu[k] += bun * nh[k];
   // c2 = gm1 (H - q2/2)
@@ -286,8 +288,8 @@ DGFN void roe_diss_adj(const P &L, const P &R, const double *nh, double gm1, dou
   }
   bsL -= bis * is * is;
   bsR -= bis * is * is;
-  aL.r += bsL * 0.5 / sL - bdr;
-  aR.r += bsR * 0.5 / sR + bdr;
+  aL.r += bsL * 0.5 * sL * L.ir - bdr;  // 1/sqrt(rho) = sqrt(rho) / rho
+  aR.r += bsR * 0.5 * sR * R.ir + bdr;
   aL.p -= bdp;
   aR.p += bdp;
   aL.u += buL[0]; aL.v += buL[1]; aL.w += buL[2];
@@ -433,8 +435,9 @@ DGFN void visc_flux_adj(const P &q, const double *g, double mu, double kappa, co
 // lifted variables W = (u, v, w, T = p / (rho R)): adjoint into primitive adjoint
 DGFN void lift_vars_adj(const P &q, double Rg, const double *Wb, PA &a) {
   a.u += Wb[0]; a.v += Wb[1]; a.w += Wb[2];
-  a.p += Wb[3] / (q.r * Rg);
-  a.r -= Wb[3] * q.p / (q.r * q.r * Rg);
+  const double k = Wb[3] * q.ir / Rg;
+  a.p += k;
+  a.r -= k * q.p * q.ir;
 }
 
 }  // namespace dgf

@@ -343,8 +343,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
           for (int v = 0; v < 5; ++v) Fb[v] = Dij2 * Ao[v] + (half ? 0.0 : Dji2 * sA[v * n3 + qp]);
           dgf::PA pr = dgf::zero_pa();
           double Hrb = 0.0;
-          if (vf == 0) dgf::kep_flux_adj_h(q, r, Ht, Hr, nm, Fb, pa, pr, Htb, Hrb);
-          else dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
+          if (vf == 0) {
+            dgf::kep_flux_adj_h(q, r, Ht, Hr, nm, Fb, pa, pr, Htb, Hrb);
+          } else {
+            r.ir = 1.0 / r.r;  // the central flux's enthalpies need it
+            dgf::pair_flux_adj(vf, q, r, nm, g1, Fb, pa, pr);
+          }
           // every node receives exactly one partner share per round
           sPA[qp] = pr.r; sPA[n3 + qp] = pr.u; sPA[2 * n3 + qp] = pr.v; sPA[3 * n3 + qp] = pr.w;
           sPA[4 * n3 + qp] = pr.p; sPA[5 * n3 + qp] = Hrb;

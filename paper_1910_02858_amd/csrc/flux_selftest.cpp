@@ -19,6 +19,7 @@ static P rand_prim(double mach) {
   q.r = urand(0.6, 1.6);
   q.p = urand(0.6, 1.6);
   q.u = urand(-1, 1) * mach; q.v = urand(-1, 1) * mach; q.w = urand(-1, 1) * mach;
+  q.ir = 1.0 / q.r;
   return q;
 }
 static void to_cons(const P &q, double gamma, double *U) {
@@ -27,6 +28,12 @@ static void to_cons(const P &q, double gamma, double *U) {
 }
 static double *comp(P &q, int j) { return j == 0 ? &q.r : j == 1 ? &q.u : j == 2 ? &q.v : j == 3 ? &q.w : &q.p; }
 static double comp(const PA &a, int j) { return j == 0 ? a.r : j == 1 ? a.u : j == 2 ? a.v : j == 3 ? a.w : a.p; }
+// q with component j moved by h (the cached reciprocal density follows)
+static P moved(P q, int j, double h) {
+  *comp(q, j) += h;
+  q.ir = 1.0 / q.r;
+  return q;
+}
 
 static int failures = 0;
 static void report(const char *name, double err, double tol) {
@@ -48,7 +55,7 @@ int main() {
     PA a = zero_pa();
     euler_flux_adj(q, nv, g1, Fb, a);
     for (int j = 0; j < 5; ++j) {
-      auto f = [&](double h) { P t = q; *comp(t, j) += h; double F[5]; euler_flux(t, nv, g1, F);
+      auto f = [&](double h) { P t = moved(q, j, h); double F[5]; euler_flux(t, nv, g1, F);
                                double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
       double fd = fd_dir(f, 1e-6), an = comp(a, j);
       worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
@@ -66,7 +73,7 @@ int main() {
       pair_flux_adj(vf, A, B, nv, g1, Fb, aA, aB);
       for (int side = 0; side < 2; ++side)
         for (int j = 0; j < 5; ++j) {
-          auto f = [&](double h) { P a = A, b = B; *comp(side ? b : a, j) += h; double F[5];
+          auto f = [&](double h) { P a = side ? A : moved(A, j, h), b = side ? moved(B, j, h) : B; double F[5];
                                    pair_flux(vf, a, b, nv, g1, F);
                                    double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
           double fd = fd_dir(f, 1e-6), an = comp(side ? aB : aA, j);
@@ -88,7 +95,7 @@ int main() {
     roe_diss_adj(L, R, nh, gm1, g1, Db, aL, aR);
     for (int side = 0; side < 2; ++side)
       for (int j = 0; j < 5; ++j) {
-        auto f = [&](double h) { P a = L, b = R; *comp(side ? b : a, j) += h; double D[5];
+        auto f = [&](double h) { P a = side ? L : moved(L, j, h), b = side ? moved(R, j, h) : R; double D[5];
                                  roe_diss(a, b, nh, gm1, g1, D);
                                  double s = 0; for (int v = 0; v < 5; ++v) s += Db[v] * D[v]; return s; };
         double fd = fd_dir(f, 1e-5), an = comp(side ? aR : aL, j);
@@ -136,7 +143,7 @@ int main() {
     visc_flux_adj(q, g, mu, kappa, nv, Fb, a, gb);
     for (int j = 0; j < 5 + 12; ++j) {
       auto f = [&](double h) { P t = q; double gg[12]; for (int c = 0; c < 12; ++c) gg[c] = g[c];
-                               if (j < 5) *comp(t, j) += h; else gg[j - 5] += h;
+                               if (j < 5) t = moved(t, j, h); else gg[j - 5] += h;
                                double F[5]; visc_flux(t, gg, mu, kappa, nv, F);
                                double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
       double fd = fd_dir(f, 1e-6), an = j < 5 ? comp(a, j) : gb[j - 5];
