@@ -54,13 +54,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   using S = VSz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   constexpr int NF = NS ? 17 : 5;  // results per face point: primitive adjoint, gradient adjoint
-  constexpr int NX = (NF * 6 * n2 > (NS ? 12 : 9) * n3) ? NF * 6 * n2 : (NS ? 12 : 9) * n3;
+  constexpr int NX = (NF * 6 * n2 > 9 * n3) ? NF * 6 * n2 : 9 * n3;
   __shared__ double sQ[6 * n3];  // primitive state and total enthalpy
   __shared__ double sA[5 * n3];  // Abar = -(1/J) Utbar
-  // region X: first the face-point results, then H = (1/J) Gbar (12 per node, Navier-Stokes),
+  // region X: first the face-point results, then H = (1/J) Gbar (9 per node, Navier-Stokes),
   // then Ja^dir of the current direction (3 per node) and the partner shares of the pair
   // rounds (6 per node: primitive adjoint and enthalpy adjoint)
-  static_assert(!NS || NX >= 12 * n3, "region X holds H");
+  static_assert(!NS || NX >= 9 * n3, "region X holds H");
   static_assert(NX >= 9 * n3, "region X holds Ja^dir and the partner shares");
   // where the LDS allows it, all metric terms (9 per node) and the momentum part of the kept
   // viscous fluxes (9 per node) are staged once at the start, so that no later phase waits on a
@@ -242,13 +242,16 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     for (int c = 0; c < 12; ++c) hg[c] = sj * (scale * gbo[c]);
   }
   // ---- lifting transposed, own part (volume and own face terms); the face terms also go to
-  // the face array for the neighbours
+  // the face array for the neighbours.  The velocity block of H is symmetric, H_dc = H_cd (every
+  // viscous transpose adds mu (T_cd + T_dc) - 2/3 mu tr(T) delta_cd), so region X holds its six
+  // distinct entries (00, 11, 22, 01, 02, 12) and the three temperature entries, 9 per node.
   dgf::PA pl = dgf::zero_pa();
   if (NS) {
     __syncthreads();  // every node has collected its face results from region X
     if (act) {
+      const double h9[9] = {hg[0], hg[5], hg[10], hg[1], hg[2], hg[6], hg[3], hg[7], hg[11]};
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sH[c * n3 + t] = hg[c];
+      for (int c = 0; c < 9; ++c) sH[c * n3 + t] = h9[c];
     }
     __syncthreads();
     if (act) {
@@ -259,20 +262,20 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
         const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
         const int base = t - id * str;
         const double nv[3] = {JA(dir, 0, t), JA(dir, 1, t), JA(dir, 2, t)};
-        double hs[12];
+        double hs[9];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) hs[c] = 0.0;
+        for (int c = 0; c < 9; ++c) hs[c] = 0.0;
 #pragma unroll 1
         for (int i = 0; i < n; ++i) {
           const int qi = base + i * str;
           const double Dh = sDh[i * n + id];
 #pragma unroll
-          for (int c = 0; c < 12; ++c) hs[c] += Dh * sH[c * n3 + qi];
+          for (int c = 0; c < 9; ++c) hs[c] += Dh * sH[c * n3 + qi];
         }
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Wb[v] += nv[d] * hs[d * 4 + v];
+        Wb[0] += nv[0] * hs[0] + nv[1] * hs[3] + nv[2] * hs[4];
+        Wb[1] += nv[0] * hs[3] + nv[1] * hs[1] + nv[2] * hs[5];
+        Wb[2] += nv[0] * hs[4] + nv[1] * hs[5] + nv[2] * hs[2];
+        Wb[3] += nv[0] * hs[6] + nv[1] * hs[7] + nv[2] * hs[8];
         if (id == 0 || id == N) {
           const int sd = (id == N) ? 1 : 0;
           const int s = 2 * dir + sd;
