@@ -237,6 +237,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # bandwidth of a plain device-to-device copy on the same GPU (context for the fractions)
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     stages = args.steps * 5
     value = dof * stages / wall
     tbytes, tvalid = counter_traffic()
@@ -267,6 +280,8 @@ def main():
         "roofline_lift": {"achieved": lift_gbs, "frac": lift_gbs / HBM_PEAK_GBS,
                           "algorithmic_bytes_per_dof": BYTES_LIFT},
         "stage_hbm_frac": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / HBM_PEAK_GBS,
+        "copy_gbs": copy_gbs,
+        "stage_frac_of_copy": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / copy_gbs,
         "adjoint_forward_ratio": None,
     }
     if not args.no_adjoint:
