@@ -428,51 +428,72 @@ def _rollout_backward(S, stage_inputs, Ubar, dt):
 
 
 def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
-    """U(T) after nsteps RK steps as a differentiable function of U0 (torch.autograd)."""
+    """U(T) after nsteps RK steps as a differentiable function of U0 (torch.autograd).
+
+    The forward pass stores the state at the start of every ckpt_every-step segment and keeps
+    the stage inputs and lifting outputs of the last segment; the backward reverses the last
+    segment from those and every earlier one after recomputing it from its checkpoint."""
     import torch
+    if nsteps < 1 or ckpt_every < 1:
+        raise ValueError("nsteps and ckpt_every must be positive")
 
     class _Rollout(torch.autograd.Function):
         @staticmethod
         def forward(ctx, U):
             a, b, _ = rk_coefficients()
+            ns = S.eqn == "ns"
+            nseg = (nsteps + ckpt_every - 1) // ckpt_every
+            last = (nseg - 1) * ckpt_every  # first step of the last segment
             ckpts = []
             R = torch.zeros_like(U)
             cur = U.detach().clone()
             nxt = S.empty()
-            for step in range(nsteps):
+            for step in range(last):
                 if step % ckpt_every == 0:
                     ckpts.append(cur.clone())
                 for s in range(5):
                     S.rk_stage(cur, nxt, R, a[s], b[s], dt)
                     cur, nxt = nxt, cur
+            # the last segment keeps every stage input and lifting output: the backward starts
+            # there and need not recompute it
+            k = 5 * (nsteps - last)
+            bufs = [cur] + [S.empty() for _ in range(k - 1)]
+            grads = [S.empty_grad() for _ in range(k)] if ns else [None] * k
+            out = S.empty()
+            for idx in range(k):
+                s = idx % 5
+                S.rk_stage_keep(bufs[idx], bufs[idx + 1] if idx + 1 < k else out, R, a[s], b[s], dt, grads[idx])
             ctx.ckpts = ckpts
-            return cur
+            ctx.tail = (bufs, grads)
+            return out
 
         @staticmethod
         def backward(ctx, gUT):
             a, b, _ = rk_coefficients()
             Ubar = gUT.detach().contiguous().clone()
             Rbar = torch.zeros_like(Ubar)
-            nseg = len(ctx.ckpts)
             ns = S.eqn == "ns"
-            # buffers of one segment, reused: the input of every stage after the first and the
-            # lifting output of every stage but the last
-            nst = 5 * min(ckpt_every, nsteps)
-            bufs = [None] + [S.empty() for _ in range(nst - 1)]
-            grads = [S.empty_grad() for _ in range(nst - 1)] + [None] if ns else [None] * nst
-            R = torch.empty_like(Ubar)
+            bufs, grads = ctx.tail
+            S.rk_steps_vjp(bufs, grads, Ubar, Rbar, dt)
+            ctx.tail = None
+            del bufs, grads
+            nseg = len(ctx.ckpts)  # the segments before the last
+            if nseg:
+                # buffers of one segment, reused: the input of every stage after the first and
+                # the lifting output of every stage but the last
+                nst = 5 * ckpt_every
+                bufs = [None] + [S.empty() for _ in range(nst - 1)]
+                grads = [S.empty_grad() for _ in range(nst - 1)] + [None] if ns else [None] * nst
+                R = torch.empty_like(Ubar)
             for seg in range(nseg - 1, -1, -1):
-                first = seg * ckpt_every
-                steps = min(ckpt_every, nsteps - first)
                 bufs[0] = ctx.ckpts[seg]
                 # recompute up to the input of the segment's last stage (its output is the next
                 # checkpoint; the reverse lifts that stage's input itself); the first stage does
                 # not read R
-                for idx in range(5 * steps - 1):
+                for idx in range(nst - 1):
                     s = idx % 5
                     S.rk_stage_keep(bufs[idx], bufs[idx + 1], R, a[s], b[s], dt, grads[idx])
-                S.rk_steps_vjp(bufs[:5 * steps], grads[:5 * steps - 1] + [None], Ubar, Rbar, dt)
-            bufs[0] = None
+                S.rk_steps_vjp(bufs, grads, Ubar, Rbar, dt)
             return Ubar
 
     return _Rollout.apply(U0)
