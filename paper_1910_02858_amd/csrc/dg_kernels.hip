@@ -795,7 +795,7 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
-template <int N, bool NS, int VF, int MODE, bool EARLY = false>
+template <int N, bool NS, int VF, int MODE>
 __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
@@ -815,10 +815,9 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
     for (int c = 0; c < 12; ++c) sF[c * n3 + t] = Ge[c * n3 + t];
   }
-  // the one-mesh kernel loads the node's own state before the face phase (the batched one has
-  // no registers to spare for it)
+  // the node's own state is loaded before the face phase, so that its latency overlaps with it
   double Uo[5];
-  if (EARLY && act) {
+  if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
   }
@@ -860,10 +859,6 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   PS o;
   double p = 0.0;
   if (act) {
-    if (!EARLY) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
-    }
     const Pr5 P = to_prim(Uo, gm1);
     p = P.p;
     o.r = P.rho; o.u = P.u; o.v = P.v; o.w = P.w;
@@ -944,7 +939,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   double Rq[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, sjq = 0.0;
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
-    if (EARLY && dir == 2 && act) {
+    if (dir == 2 && act) {
       // the epilogue's loads are issued before the last direction's rounds
       sjq = g.sJ[(size_t)e * n3 + t];
       if (MODE == 1 && ca != 0.0) {
@@ -1016,7 +1011,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     }
   }
   if (act) {
-    const double sj = EARLY ? sjq : g.sJ[(size_t)e * n3 + t];
+    const double sj = sjq;
     double *Oe = out + (size_t)e * 5 * n3;
     if (MODE == 0) {
 #pragma unroll
@@ -1026,7 +1021,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         // a = 0 (first stage) does not read R, so R may hold anything on entry
-        const double r = (ca != 0.0 ? ca * (EARLY ? Rq[v] : Re[v * n3 + t]) : 0.0) + dt * (-acc[v] * sj);
+        const double r = (ca != 0.0 ? ca * Rq[v] : 0.0) + dt * (-acc[v] * sj);
         Re[v * n3 + t] = r;
         Oe[v * n3 + t] = Uo[v] + cb * r;
       }
@@ -1045,7 +1040,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  split_body<N, NS, VF, MODE, true>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
+  split_body<N, NS, VF, MODE>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
 }
 
 // ----------------------------------------------------------------------------- ensemble batch
