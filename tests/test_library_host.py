@@ -145,3 +145,12 @@ def test_host_geometry_matches_oracle(dg, orc, N, nodes, curved):
     eps = np.finfo(float).eps
     for key, ref in (("D", b["D"]), ("Dhat", b["Dhat"]), ("Ja", g["Ja"]), ("J", g["J"]), ("fn", g["fn"])):
         assert np.abs(h[key] - ref).max() <= 1.0 * eps * np.abs(ref).max(), key
+
+
+def test_rollout_rejects_empty_schedules():
+    """Argument checks of the checkpointed rollout run before anything touches the GPU."""
+    from paper_1910_02858_amd import dgsem
+    with pytest.raises(ValueError):
+        dgsem.rollout(None, None, 0, 0.1)
+    with pytest.raises(ValueError):
+        dgsem.rollout(None, None, 5, 0.1, ckpt_every=0)
