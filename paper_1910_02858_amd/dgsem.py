@@ -306,6 +306,14 @@ class DGSolver:
                 cur, nxt = nxt, cur
         return cur
 
+    def step(self, U, R, dt: float):
+        """One RK step from U with register R; U is overwritten with the new state (a buffer of
+        the solver's shape is used in between)."""
+        out = self.steps(U, 1, dt, R=R)
+        if out is not U:
+            U.copy_(out)
+        return U
+
 
 class Batch:
     """Several solvers advanced together (``dg_batch``): one lifting and one operator launch per
@@ -500,6 +508,7 @@ def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
 
 
 def kinetic_energy(U, wJ):
-    """sum over nodes of J w_i w_j w_k |m|^2 / (2 rho), a differentiable torch scalar."""
+    """sum over nodes of J w_i w_j w_k |m|^2 / (2 rho), a differentiable torch scalar (wJ from
+    DGSolver.mass_weights())."""
     m2 = (U[:, 1:4] ** 2).sum(dim=1)
     return (wJ * 0.5 * m2 / U[:, 0]).sum()

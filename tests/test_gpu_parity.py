@@ -96,6 +96,21 @@ def test_rk_stage_semantics(dg, orc):
     assert np.array_equal(Ug.cpu().numpy(), U0)
 
 
+def test_step_in_place_equals_steps(dg, orc):
+    """DGSolver.step (one RK step, result written back into U) gives the bits of steps(U, 1)."""
+    import torch
+    wl = inputs.workload(2, K1=2, N=3)
+    M, xgeo, nbr, side, U0 = problem(orc, wl)
+    S = gpu_solver(dg, wl, xgeo, nbr, side)
+    dt = S.timestep(to_gpu(U0), 0.9, 0.9)
+    ref = S.steps(to_gpu(U0), 1, dt)
+    U = to_gpu(U0)
+    R = torch.zeros_like(U)
+    out = S.step(U, R, dt)
+    torch.cuda.synchronize()
+    assert out is U and torch.equal(U, ref)
+
+
 def test_full_size_cfg3_sampled(dg, orc):
     """48^3 elements, N=7: one operator evaluation and one fused RK stage at full size, in the launch
     configuration the benchmark times, checked on sampled elements (including the periodic wrap)."""
