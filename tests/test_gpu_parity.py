@@ -111,6 +111,25 @@ def test_step_in_place_equals_steps(dg, orc):
     assert out is U and torch.equal(U, ref)
 
 
+def test_resume_from_saved_state_is_bitwise(dg, orc, tmp_path):
+    """The state at a step boundary is the whole restart information (a_1 = 0: the register
+    does not carry across steps): 3 steps, save U to a file, reload, 3 more steps equals 6
+    uninterrupted steps bit for bit."""
+    import torch
+    wl = inputs.workload(2, K1=2, N=4)
+    M, xgeo, nbr, side, U0 = problem(orc, wl)
+    S = gpu_solver(dg, wl, xgeo, nbr, side)
+    dt = S.timestep(to_gpu(U0), 0.9, 0.9)
+    ref = S.steps(to_gpu(U0), 6, dt).cpu().numpy()
+    half = S.steps(to_gpu(U0), 3, dt).cpu().numpy()
+    f = tmp_path / "state.npy"
+    np.save(f, half)
+    S2 = gpu_solver(dg, wl, xgeo, nbr, side)
+    R = torch.full(half.shape, float("nan"), dtype=torch.float64, device="cuda")  # not carried over
+    got = S2.steps(to_gpu(np.load(f)), 3, dt, R=R).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
 def test_full_size_cfg3_sampled(dg, orc):
     """48^3 elements, N=7: one operator evaluation and one fused RK stage at full size, in the launch
     configuration the benchmark times, checked on sampled elements (including the periodic wrap)."""
