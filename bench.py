@@ -237,18 +237,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # bandwidth of a plain device-to-device copy on the same GPU (context for the fractions)
-    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
+    # bandwidth of a plain device-to-device copy on the same GPU (context for the fractions); not
+    # in counter passes, whose only copies are the 1 GiB calibration copies above
+    copy_gbs = None
+    if not args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
         dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
 
     stages = args.steps * 5
     value = dof * stages / wall
@@ -281,7 +284,8 @@ def main():
                           "algorithmic_bytes_per_dof": BYTES_LIFT},
         "stage_hbm_frac": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / HBM_PEAK_GBS,
         "copy_gbs": copy_gbs,
-        "stage_frac_of_copy": (BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / copy_gbs,
+        "stage_frac_of_copy": ((BYTES_MAIN + BYTES_LIFT) * dof * stages / wall / 1e9 / copy_gbs
+                               if copy_gbs else None),
         "adjoint_forward_ratio": None,
     }
     if not args.no_adjoint:
