@@ -143,9 +143,13 @@ int dg_rk_step_vjp(dg_handle *h, const double *const *stage_U, const double *con
 
 /* Reverse of nsteps >= 1 consecutive steps: stage_U[5*k + s] (and stage_G[5*k + s], or NULL)
  * belong to stage s of the k-th step, in forward order; the steps are reversed from the last.
- * Same result, bit for bit, as nsteps dg_rk_step_vjp calls from the last step to the first
- * (the register update between two steps is merged into the reverse kernels, since a_1 = 0
- * leaves R_bar zero after every reversed step).  On return R_bar is zero. */
+ * On entry U_bar and R_bar hold the adjoints of the last step's output state and R; on return
+ * U_bar holds the adjoint of the first step's input state and R_bar is zero.  Same result, bit
+ * for bit, as nsteps dg_rk_step_vjp calls from the last step to the first (the register update
+ * between two steps is merged into the reverse kernels, since a_1 = 0 leaves R_bar zero after
+ * every reversed step).  DG_ERR_ARG for nsteps < 1, NULL or overlapping arrays or a non-finite
+ * dt; the reverse kernels support what dg_rhs_vjp supports (DG_ERR_UNSUPPORTED otherwise).
+ * Not in the paper: the reverse of its time integration. */
 int dg_rk_steps_vjp(dg_handle *h, int nsteps, const double *const *stage_U, const double *const *stage_G,
                     double *U_bar, double *R_bar, double dt);
 
