@@ -71,6 +71,16 @@ def _mesh(dg, N, k=2):
     return X, nbr, side, flip
 
 
+def test_init_rejects_empty_mesh(dg):
+    """No elements: DG_ERR_ARG from dg_init and dg_host_geometry, before any device call."""
+    X, nbr, side, _ = _mesh(dg, 3)
+    rc, h = _init(dg, X[:0].copy(), nbr[:0].copy(), side[:0].copy(), 3)
+    assert rc == -1 and not h.value
+    with pytest.raises(dg.DGError) as ei:
+        dg.host_geometry(X[:0], nbr[:0], side[:0], 3, "lgl")
+    assert ei.value.code == -1
+
+
 def test_init_rejects_inverted_element(dg):
     X, nbr, side, _ = _mesh(dg, 3)
     X[1, 0] = X[1, 0, ::-1].copy()  # mirror one element in x: J < 0
