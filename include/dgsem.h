@@ -111,9 +111,10 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for the split form on LGL nodes with the KEP or central volume flux
- * (DG_ERR_UNSUPPORTED otherwise) and N <= 7; the derivative of |x| at 0 and of max at a tie
- * is the mean of the one-sided derivatives.  Device arrays [K][5][n^3], pairwise distinct.
+ * Supported for the split form on LGL nodes (KEP, EC or central volume flux; DG_ERR_UNSUPPORTED
+ * otherwise) and N <= 7; the derivative of |x| at 0 and of max at a tie is the mean of the
+ * one-sided derivatives, the log means of the EC flux are differentiated with the forward's
+ * branch threshold (series below ((a-b)/(a+b))^2 = 1e-4, logarithms above).  Device arrays [K][5][n^3], pairwise distinct.
  * Not in the paper: the reverse of its operator, for gradients of objectives of U. */
 int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_bar);
 

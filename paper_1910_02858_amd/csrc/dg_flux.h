@@ -166,14 +166,99 @@ DGFN void central_flux_adj(const P &A, const P &B, const double *nv, double g1, 
   euler_flux_adj(B, nv, g1, h, aB);
 }
 
-// two-point flux of kind vf (0 KEP, 2 central)
+// logarithmic mean (a - b)/(ln a - ln b) of two positive numbers and its partial derivatives;
+// for u = ((a - b)/(a + b))^2 below 1e-4 from the series of artanh(f)/f = 1 + u/3 + u^2/5 + u^3/7
+// (f = (a - b)/(a + b)), where the difference of logarithms loses its accuracy
+DGFN void logmean_d(double a, double b, double &L, double &La, double &Lb) {
+  const double s = a + b, d = a - b, is = 1.0 / s, f = d * is, u = f * f;
+  if (u < 1e-4) {
+    const double h = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
+    const double hu = 1.0 / 3.0 + u * (2.0 / 5.0 + u * (3.0 / 7.0));  // dh/du
+    const double ih = 1.0 / h;
+    L = 0.5 * s * ih;
+    // L = s / (2 h(u)); du/da = 4 b d / s^3, du/db = -4 a d / s^3
+    const double c = 2.0 * s * hu * ih * ih * d * is * is * is;
+    La = 0.5 * ih - c * b;
+    Lb = 0.5 * ih + c * a;
+  } else {
+    const double il = 1.0 / (log(a) - log(b));
+    L = d * il;
+    La = (1.0 - L / a) * il;
+    Lb = (L / b - 1.0) * il;
+  }
+}
+
+// entropy-conserving two-point flux (Chandrashekar) along nv, with beta = rho / (2 p):
+// F_rho = rho^ln {u}.n, F_m = F_rho {u} + {rho}/(2 {beta}) n,
+// F_E = F_rho (1 / (2 (gamma-1) beta^ln) - {|u|^2}/2) + {u}.F_m   (g1 = gamma / (gamma-1))
+DGFN void ec_flux(const P &A, const P &B, const double *nv, double g1, double *F) {
+  const double kg = g1 - 1.0;  // 1 / (gamma - 1)
+  const double ba = 0.5 * A.r / A.p, bb = 0.5 * B.r / B.p;
+  double rl, bl, t0, t1;
+  logmean_d(A.r, B.r, rl, t0, t1);
+  logmean_d(ba, bb, bl, t0, t1);
+  const double um[3] = {0.5 * (A.u + B.u), 0.5 * (A.v + B.v), 0.5 * (A.w + B.w)};
+  const double umn = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+  const double ph = 0.5 * (A.r + B.r) / (ba + bb);
+  const double q2m = 0.5 * ((A.u * A.u + A.v * A.v + A.w * A.w) + (B.u * B.u + B.v * B.v + B.w * B.w));
+  F[0] = rl * umn;
+  for (int k = 0; k < 3; ++k) F[1 + k] = F[0] * um[k] + ph * nv[k];
+  F[4] = F[0] * (0.5 * kg / bl - 0.5 * q2m) + um[0] * F[1] + um[1] * F[2] + um[2] * F[3];
+}
+
+DGFN void ec_flux_adj(const P &A, const P &B, const double *nv, double g1, const double *Fb, PA &aA, PA &aB) {
+  const double kg = g1 - 1.0;
+  const double ipA = 1.0 / A.p, ipB = 1.0 / B.p;
+  const double ba = 0.5 * A.r * ipA, bb = 0.5 * B.r * ipB;
+  double rl, rla, rlb, bl, bla, blb;
+  logmean_d(A.r, B.r, rl, rla, rlb);
+  logmean_d(ba, bb, bl, bla, blb);
+  const double um[3] = {0.5 * (A.u + B.u), 0.5 * (A.v + B.v), 0.5 * (A.w + B.w)};
+  const double umn = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+  const double rm = 0.5 * (A.r + B.r), ibm = 2.0 / (ba + bb);  // 1 / {beta}
+  const double ph = 0.5 * rm * ibm;
+  const double ibl = 1.0 / bl;
+  const double q2m = 0.5 * ((A.u * A.u + A.v * A.v + A.w * A.w) + (B.u * B.u + B.v * B.v + B.w * B.w));
+  const double F0 = rl * umn;
+  const double e = 0.5 * kg * ibl - 0.5 * q2m;
+  // reverse sweep
+  double bum[3], bF0 = Fb[0] + Fb[4] * e, bph = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double Fm = F0 * um[k] + ph * nv[k];
+    const double bFm = Fb[1 + k] + Fb[4] * um[k];  // F_m enters F_E through {u}.F_m
+    bum[k] = Fb[4] * Fm + bFm * F0;
+    bF0 += bFm * um[k];
+    bph += bFm * nv[k];
+  }
+  const double be = Fb[4] * F0;
+  const double brl = bF0 * umn, bumn = bF0 * rl;
+  for (int k = 0; k < 3; ++k) bum[k] += bumn * nv[k];
+  const double bbl = -be * 0.5 * kg * ibl * ibl;
+  const double bq2m = -0.5 * be;
+  const double brm = 0.5 * bph * ibm;
+  const double bbm = -0.5 * bph * rm * ibm * ibm;
+  // densities: {rho} and rho^ln
+  aA.r += 0.5 * brm + brl * rla;
+  aB.r += 0.5 * brm + brl * rlb;
+  // beta = rho / (2 p): {beta} and beta^ln
+  const double bba = 0.5 * bbm + bbl * bla, bbb = 0.5 * bbm + bbl * blb;
+  aA.r += bba * 0.5 * ipA; aA.p -= bba * ba * ipA;
+  aB.r += bbb * 0.5 * ipB; aB.p -= bbb * bb * ipB;
+  // velocities: {u} and {|u|^2}
+  aA.u += 0.5 * bum[0] + bq2m * A.u; aA.v += 0.5 * bum[1] + bq2m * A.v; aA.w += 0.5 * bum[2] + bq2m * A.w;
+  aB.u += 0.5 * bum[0] + bq2m * B.u; aB.v += 0.5 * bum[1] + bq2m * B.v; aB.w += 0.5 * bum[2] + bq2m * B.w;
+}
+
+// two-point flux of kind vf (0 KEP, 1 EC, 2 central)
 DGFN void pair_flux(int vf, const P &A, const P &B, const double *nv, double g1, double *F) {
   if (vf == 0) kep_flux(A, B, nv, g1, F);
+  else if (vf == 1) ec_flux(A, B, nv, g1, F);
   else central_flux(A, B, nv, g1, F);
 }
 DGFN void pair_flux_adj(int vf, const P &A, const P &B, const double *nv, double g1, const double *Fb, PA &aA,
                         PA &aB) {
   if (vf == 0) kep_flux_adj(A, B, nv, g1, Fb, aA, aB);
+  else if (vf == 1) ec_flux_adj(A, B, nv, g1, Fb, aA, aB);
   else central_flux_adj(A, B, nv, g1, Fb, aA, aB);
 }
 

@@ -42,6 +42,10 @@ static void report(const char *name, double err, double tol) {
 }
 
 template <class F> static double fd_dir(F f, double h) { return (f(h) - f(-h)) / (2 * h); }
+// fourth-order central difference (the log means of states far apart have large third derivatives)
+template <class F> static double fd4_dir(F f, double h) {
+  return (8.0 * (f(h) - f(-h)) - (f(2 * h) - f(-2 * h))) / (12 * h);
+}
 
 int main() {
   const double gamma = 1.4, gm1 = gamma - 1, g1 = gamma / gm1, tol = 2e-7;
@@ -62,25 +66,44 @@ int main() {
     }
   }
   report("euler_flux_adj", worst, tol);
-  // two-point fluxes
-  for (int vf : {0, 2}) {
+  // logarithmic mean: value against the logarithms away from a = b, derivatives against central
+  // differences on both branches
+  worst = 0;
+  for (int it = 0; it < 400; ++it) {
+    const double a = urand(0.3, 3.0), b = it % 2 ? a * (1.0 + urand(-1e-3, 1e-3)) : urand(0.3, 3.0);
+    double L, La, Lb;
+    logmean_d(a, b, L, La, Lb);
+    if (std::fabs(a - b) > 0.05 * a) worst = std::max(worst, std::fabs(L - (a - b) / (std::log(a) - std::log(b))) / L);
+    auto fa = [&](double h) { double l, x, y; logmean_d(a + h, b, l, x, y); return l; };
+    auto fb = [&](double h) { double l, x, y; logmean_d(a, b + h, l, x, y); return l; };
+    worst = std::max(worst, std::fabs(fd_dir(fa, 1e-7) - La) / std::fabs(La));
+    worst = std::max(worst, std::fabs(fd_dir(fb, 1e-7) - Lb) / std::fabs(Lb));
+  }
+  report("logmean_d", worst, tol);
+  // two-point fluxes (EC also with nearly equal states, the series branch of the log means)
+  for (int vf : {0, 1, 2, 3}) {
     worst = 0;
     for (int it = 0; it < 200; ++it) {
       P A = rand_prim(0.8), B = rand_prim(0.8);
+      if (vf == 3) {
+        B = A;
+        B.r *= 1.0 + urand(-2e-3, 2e-3); B.p *= 1.0 + urand(-2e-3, 2e-3); B.ir = 1.0 / B.r;
+      }
       double nv[3] = {urand(-1, 1), urand(-1, 1), urand(-1, 1)}, Fb[5];
       for (double &x : Fb) x = urand(-1, 1);
       PA aA = zero_pa(), aB = zero_pa();
-      pair_flux_adj(vf, A, B, nv, g1, Fb, aA, aB);
+      pair_flux_adj(vf == 3 ? 1 : vf, A, B, nv, g1, Fb, aA, aB);
       for (int side = 0; side < 2; ++side)
         for (int j = 0; j < 5; ++j) {
           auto f = [&](double h) { P a = side ? A : moved(A, j, h), b = side ? moved(B, j, h) : B; double F[5];
-                                   pair_flux(vf, a, b, nv, g1, F);
+                                   pair_flux(vf == 3 ? 1 : vf, a, b, nv, g1, F);
                                    double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
-          double fd = fd_dir(f, 1e-6), an = comp(side ? aB : aA, j);
+          double fd = fd4_dir(f, 1e-4), an = comp(side ? aB : aA, j);
           worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
         }
     }
-    report(vf == 0 ? "kep_flux_adj" : "central_flux_adj", worst, tol);
+    report(vf == 0 ? "kep_flux_adj" : vf == 1 ? "ec_flux_adj" : vf == 2 ? "central_flux_adj" : "ec_flux_adj near-equal",
+           worst, tol);
   }
   // Roe dissipation
   worst = 0;
@@ -103,8 +126,9 @@ int main() {
       }
   }
   report("roe_diss_adj", worst, tol);
-  // full Riemann solvers in conservative variables
-  for (int rs : {0, 1, 3}) {
+  // full Riemann solvers in conservative variables (case 4: EC two-point flux + Roe dissipation)
+  for (int rc : {0, 1, 3, 4}) {
+    const int rs = rc == 4 ? 3 : rc, vf = rc == 4 ? 1 : 0;
     worst = 0;
     for (int it = 0; it < 200; ++it) {
       P L = rand_prim(0.5), R = rand_prim(0.5);
@@ -116,19 +140,20 @@ int main() {
       double Fb[5];
       for (double &x : Fb) x = urand(-1, 1);
       double ULb[5] = {0, 0, 0, 0, 0}, URb[5] = {0, 0, 0, 0, 0};
-      riemann_adj(rs, 0, L, R, UL, UR, nh, gamma, Fb, ULb, URb);
+      riemann_adj(rs, vf, L, R, UL, UR, nh, gamma, Fb, ULb, URb);
       for (int side = 0; side < 2; ++side)
         for (int j = 0; j < 5; ++j) {
           auto f = [&](double h) { double a[5], b[5]; for (int v = 0; v < 5; ++v) { a[v] = UL[v]; b[v] = UR[v]; }
                                    (side ? b : a)[j] += h;
                                    P pa = prim(a, gm1), pb = prim(b, gm1); double F[5];
-                                   riemann(rs, 0, pa, pb, a, b, nh, gamma, F);
+                                   riemann(rs, vf, pa, pb, a, b, nh, gamma, F);
                                    double s = 0; for (int v = 0; v < 5; ++v) s += Fb[v] * F[v]; return s; };
           double fd = fd_dir(f, 1e-5), an = (side ? URb : ULb)[j];
           worst = std::max(worst, std::fabs(fd - an) / (std::fabs(an) + 1e-3));
         }
     }
-    report(rs == 0 ? "riemann_adj llf" : rs == 1 ? "riemann_adj roe" : "riemann_adj kep+roe", worst, tol);
+    report(rc == 0 ? "riemann_adj llf" : rc == 1 ? "riemann_adj roe" : rc == 3 ? "riemann_adj kep+roe" : "riemann_adj ec+roe",
+           worst, tol);
   }
   // viscous flux (state and gradient) and lifted variables
   worst = 0;

@@ -32,6 +32,8 @@ TINY = [
     ("ns_kep_roe", dict(eqn="ns", volflux="kep", riemann="roe")),
     ("ns_central_llf", dict(eqn="ns", volflux="central", riemann="llf")),
     ("euler_kep_volflux_roe", dict(eqn="euler", volflux="kep", riemann="volflux_roe")),
+    ("ns_ec_roe", dict(eqn="ns", volflux="ec", riemann="roe")),
+    ("euler_ec_volflux", dict(eqn="euler", volflux="ec", riemann="volflux")),
 ]
 
 
@@ -76,11 +78,11 @@ def test_vjp_dot_product_cfg5_operator(dg, orc):
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("N", [1, 3, 4, 6, 7])
-def test_vjp_dot_product_degrees(dg, orc, N):
+@pytest.mark.parametrize("N,vf", [(1, "kep"), (3, "kep"), (4, "kep"), (6, "kep"), (7, "kep"), (3, "ec"), (7, "ec")])
+def test_vjp_dot_product_degrees(dg, orc, N, vf):
     """<J^T w, v> = <w, J v> for every degree the reverse kernels are built for, on a curved
-    ragged 3x2x2 lattice (Navier-Stokes, KEP + Roe + BR1), J v from the oracle's tangent."""
-    wl = inputs.workload(5, N=N, K1=2)
+    ragged 3x2x2 lattice (Navier-Stokes, KEP or EC + Roe + BR1), J v from the oracle's tangent."""
+    wl = inputs.workload(5, N=N, K1=2, volflux=vf)
     M, xgeo, nbr, side, U0 = problem(orc, wl, kxyz=(3, 2, 2), curved=True, perturb=1e-2, seed=N)
     sc = orc.Scheme.of(wl)
     S = gpu_solver(dg, wl, xgeo, nbr, side)
@@ -91,7 +93,7 @@ def test_vjp_dot_product_degrees(dg, orc, N):
         JTw = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy()
         lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
         scale = float(np.sum(np.abs(JTw * v)))
-        print(f"N={N}: <J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        print(f"N={N} {vf}: <J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
         assert abs(lhs - rhs) <= 1e-12 * scale
 
 
