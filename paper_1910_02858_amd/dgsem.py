@@ -450,6 +450,9 @@ def rollout(S, U0, nsteps: int, dt: float, ckpt_every: int = 10):
         def forward(ctx, U):
             a, b, _ = rk_coefficients()
             ns = S.eqn == "ns"
+            if not ctx.needs_input_grad[0]:  # nothing to differentiate: a plain rollout
+                ctx.ckpts, ctx.tail = [], None
+                return S.steps(U.detach().clone(), nsteps, dt)
             nseg = (nsteps + ckpt_every - 1) // ckpt_every
             last = (nseg - 1) * ckpt_every  # first step of the last segment
             ckpts = []

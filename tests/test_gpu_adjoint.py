@@ -149,6 +149,7 @@ def test_rollout_gradient_equals_stage_by_stage_reverse(dg, eqn, ck):
     (g,) = torch.autograd.grad(UT, U, grad_outputs=w)
     UT2, stage_inputs = dg._rollout_forward(S, U0, steps, dt, keep_stage_inputs=True)
     assert torch.equal(UT.detach(), UT2)
+    assert torch.equal(dg.rollout(S, U0, steps, dt, ckpt_every=ck), UT2)  # no gradient wanted
     g2 = dg._rollout_backward(S, stage_inputs, w.clone(), dt)
     rel = float((g - g2).abs().max() / g2.abs().max())
     print(f"{eqn}: checkpointed vs stage-by-stage reverse, max relative difference {rel:.2e}")
