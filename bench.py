@@ -90,7 +90,42 @@ def cpu_baseline(wl, budget_s: float = 12.0):
     dof = M.K * M.n3
     return {"value": dof * stages / wall, "unit": "DOF-updates/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": f"{stages} RK stages of the same scheme on {k}^3 elements, N={wl.N} ({dof} nodes), FP64",
-            "pid_core_s": wall * orc.num_threads() / (dof * stages)}
+            "pid_core_s": wall * orc.num_threads() / (dof * stages), "pid_1thread_s": cpu_pid_one_thread()}
+
+
+_ONE_THREAD = r"""
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as orc
+from paper_1910_02858_amd import inputs
+wl = inputs.workload(3, K1=4)
+lgl = orc.basis(wl.N, "lgl")["x"]
+X = inputs.lattice_points(lgl, 4, 4, 4)
+nbr, side, _ = inputs.periodic_lattice(4, 4, 4)
+M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes)
+U = inputs.initial_state(wl, M.points())
+R = np.zeros_like(U)
+sc = orc.Scheme.of(wl)
+a, b, _ = orc.rk_coefficients()
+t0 = time.perf_counter()
+for s in range(10):
+    U, R = M.rk_stage(sc, U, R, a[s % 5], b[s % 5], 1e-4)
+print((time.perf_counter() - t0) / (M.K * M.n3 * 10))
+"""
+
+
+def cpu_pid_one_thread():
+    """The oracle's seconds per DOF and stage on one host thread (4^3 elements, N=7, 10 stages),
+    in a child process started with OMP_NUM_THREADS=1; None if that fails."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", _ONE_THREAD, os.path.dirname(os.path.abspath(__file__))],
+                             env=env, capture_output=True, text=True, timeout=120)
+        return float(out.stdout.strip().splitlines()[-1]) if out.returncode == 0 else None
+    except (OSError, ValueError, IndexError, subprocess.SubprocessError):
+        return None
 
 
 def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2):
@@ -274,6 +309,7 @@ def main():
                    "elements": S.K, "N": wl.N, "nodes": "lgl", "dof": dof, "stages_per_step": 5,
                    "scheme": "navier-stokes split EC volume flux, Roe surface flux, BR1", "ic": "taylor-green Ma=0.1 Re=1600"},
         "pid_s_per_dof_stage": wall / (dof * stages),
+        "pid_cu_s": wall * 256 / (dof * stages),  # per compute unit, context beside per-core CPU PIDs
         "ms_per_stage": wall * 1e3 / stages,
         "kernels_ms": {"main": main_ms, "lift": lift_ms},
         "roofline": {"bound": "hbm", "kernel": "k_main (split volume + surface + RK update)", "achieved": main_gbs,
@@ -298,6 +334,7 @@ def main():
         cb = cpu_baseline(wl)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["pid_core_s"] = cb["pid_core_s"]
+        out["cpu_baseline"]["pid_1thread_s"] = cb["pid_1thread_s"]
     print(json.dumps(out))
 
 
