@@ -2,10 +2,14 @@
 against central finite differences.
 
 * dg_rhs_vjp element by element: the oracle's Jacobian is assembled column by column from its
-  dual-number tangent on a tiny mesh, and J^T w must match the GPU product.
+  dual-number tangent on a tiny mesh, and J^T w must match the GPU product (KEP, EC and central
+  two-point fluxes, LLF, Roe and two-point surface fluxes, Euler and Navier-Stokes).
 * dot-product tests <J^T w, v> = <w, J v> for one operator evaluation at the 12^3 N=5 curved
-  workload, and for RK rollouts (GPU reverse sweep vs oracle tangent rollout).
-* the checkpointed rollout gradient equals the store-everything gradient bit for bit.
+  workload and at every degree the reverse kernels are built for, and for RK rollouts (GPU
+  reverse sweep vs oracle tangent rollout).
+* the checkpointed rollout gradient equals the store-everything gradient bit for bit, and the
+  stage-by-stage reverse to rounding; the reverse of several steps in one call equals repeated
+  single steps bit for bit.
 * gradient of the kinetic energy after 50 RK steps (12^3 curved hexes, N=5, checkpoint every 10)
   against central differences (eps = 1e-6) in 20 seeded random directions.
 Kink convention: d|x|/dx = 0 and a tie in max splits evenly, also within 1e-12 relative.
