@@ -217,7 +217,7 @@ def main():
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the element decomposition across GPUs is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 

@@ -37,7 +37,7 @@ typedef enum {
   DG_OK = 0,
   DG_ERR_ARG = -1,         /* null/misaligned pointer, bad size, aliasing, bad enum value */
   DG_ERR_MESH = -2,        /* J <= 0 somewhere, or inconsistent connectivity               */
-  DG_ERR_UNSUPPORTED = -3, /* valid request outside what this build implements            */
+  DG_ERR_UNSUPPORTED = -3, /* valid request outside what the library implements           */
   DG_ERR_HIP = -4,         /* a HIP runtime call failed                                    */
   DG_ERR_NONFINITE = -5,   /* NaN or Inf found by dg_check_finite                          */
   DG_ERR_OOM = -6          /* device allocation failed                                     */

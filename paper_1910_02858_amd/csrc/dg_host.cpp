@@ -34,7 +34,7 @@ const char *status_name(int s) {
     case DG_OK: return "DG_OK";
     case DG_ERR_ARG: return "DG_ERR_ARG: invalid argument";
     case DG_ERR_MESH: return "DG_ERR_MESH: invalid mesh";
-    case DG_ERR_UNSUPPORTED: return "DG_ERR_UNSUPPORTED: not supported by this build";
+    case DG_ERR_UNSUPPORTED: return "DG_ERR_UNSUPPORTED: valid request the library does not implement";
     case DG_ERR_HIP: return "DG_ERR_HIP: HIP runtime error";
     case DG_ERR_NONFINITE: return "DG_ERR_NONFINITE: non-finite value";
     case DG_ERR_OOM: return "DG_ERR_OOM: device allocation failed";

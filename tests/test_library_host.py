@@ -90,7 +90,7 @@ def test_init_rejects_inverted_element(dg):
 
 def test_init_rejects_unsupported(dg):
     X, nbr, side, flip = _mesh(dg, 3)
-    rc, h = _init(dg, X, nbr, side, 9)            # N beyond the build
+    rc, h = _init(dg, X, nbr, side, 9)            # N beyond the largest supported degree
     assert rc in (-3, -1) and not h.value
     rc, h = _init(dg, X, nbr, side, 3, nodes="lg", form="split")  # split needs LGL
     assert rc == -3
