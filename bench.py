@@ -312,7 +312,7 @@ def main():
         "pid_cu_s": wall * 256 / (dof * stages),  # per compute unit, context beside per-core CPU PIDs
         "ms_per_stage": wall * 1e3 / stages,
         "kernels_ms": {"main": main_ms, "lift": lift_ms},
-        "roofline": {"bound": "hbm", "kernel": "k_main (split volume + surface + RK update)", "achieved": main_gbs,
+        "roofline": {"bound": "hbm", "kernel": "k_split (face fluxes + split volume integral + surface integral + RK update)", "achieved": main_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
                      "traffic_bytes_per_launch": tbytes if traffic_gbs is not None else None,
                      "algorithmic_bytes_per_dof": BYTES_MAIN},
