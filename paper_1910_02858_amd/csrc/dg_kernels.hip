@@ -251,9 +251,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   const double gm1 = ph.gamma - 1.0;
   const double *Ue = U + (size_t)e * 5 * n3;
-  // the metric terms of the next direction are loaded one phase ahead (at most 3 per thread)
+  // the metric terms of the next direction (at most 3 per thread) and, in the last direction, the
+  // node's 1/J are loaded one phase ahead
   constexpr int JPT = (3 * n3 + NT - 1) / NT;
-  double jn[JPT];
+  double jn[JPT], sjn = 0.0;
   {
     const double *Jd = g.Ja + (size_t)e * 9 * n3;
 #pragma unroll
@@ -330,6 +331,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
       for (int r = 0; r < JPT; ++r) jn[r] = (valid && t + r * NT < 3 * n3) ? Jd[t + r * NT] : 0.0;
     }
+    if (dir == 2 && valid && t < n3) sjn = g.sJ[(size_t)e * n3 + t];  // for the epilogue
     __syncthreads();
     if (OUT == LIFT_FV && valid && t < n3) {
 #pragma unroll
@@ -389,7 +391,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
   }
   if (valid && t < n3) {
-    const double sj = g.sJ[(size_t)e * n3 + t];
+    const double sj = sjn;
     {
       // the gradients are rounded once, whatever is computed from them (so the three output
       // variants give the same bits)
