@@ -24,9 +24,14 @@
 //   * the split form carries the same -1/J scaling as the weak form.
 //   * geometry: mapping sampled at degree-N LGL nodes, curl form on LGL nodes, exact
 //     interpolation to LG nodes; J = det of the D-derived mapping Jacobian.
-//   * face normals and surface elements are taken from the master (the element that
-//     owns the face as its +xi side); the slave uses the negated master normal and
-//     the negated master flux.
+//   * face normals and surface elements are taken from the master; the slave uses the
+//     negated master normal and the negated master flux.  The master of a face is the
+//     +xi side where a +xi side meets a -xi side (always so on a structured lattice);
+//     where two sides of equal parity meet, the element with the smaller index (the
+//     smaller side within one element).
+//   * conforming faces may meet in any of the eight orientations of a square: the
+//     neighbour's face point matching face point (a,b) is found by an optional swap of
+//     (a,b) followed by optional reversals of the first and of the second index.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
@@ -217,6 +222,7 @@ struct Mesh {
   Basis sol, lgl;
   std::vector<int32_t> nbr;        // [e][6]
   std::vector<int8_t> nside;       // [e][6]
+  std::vector<int8_t> flip;        // [e][6] orientation code of the face map to the neighbour
   std::vector<double> Ja;          // [e][i*3+d][node]: Ja^i_d
   std::vector<double> J;           // [e][node]
   std::vector<double> xs;          // [e][3][node] solution-node positions
@@ -231,6 +237,24 @@ static inline int line_node(int n, int dn, int a, int b, int m) {
   int da = (dn == 0) ? 1 : 0, db = (dn == 2) ? 1 : 2;
   idx[dn] = m; idx[da] = a; idx[db] = b;
   return nid(n, idx[0], idx[1], idx[2]);
+}
+
+// face point (a2,b2) of the neighbour across side s of element e that coincides with this
+// element's face point (a,b).  Orientation code o: bit 2 swaps (a,b), then bit 0 reverses
+// the first and bit 1 the second index.
+static void mate(const Mesh& M, int e, int s, int a, int b, int& a2, int& b2) {
+  const int o = M.flip[e * 6 + s];
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  a2 = (o & 1) ? M.N - p : p;
+  b2 = (o & 2) ? M.N - q : q;
+}
+
+// whether side s of element e is the master of its face
+static bool is_master(const Mesh& M, int e, int s) {
+  const int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
+  const bool plus = (s % 2) == 1, nplus = (ns % 2) == 1;
+  if (plus != nplus) return plus;
+  return e < nb || (e == nb && s < ns);
 }
 
 // apply the 1D matrix A (n x n) along direction dir to field f on an n^3 grid
@@ -250,13 +274,17 @@ static void apply_dir(const std::vector<ld>& A, int n, int dir, const ld* f, ld*
 }
 
 static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, const int32_t* nbr,
-                       const int8_t* nside) {
+                       const int8_t* nside, const int8_t* flip) {
   M.K = K; M.N = N; M.n = N + 1; M.n2 = M.n * M.n; M.n3 = M.n2 * M.n; M.type = type;
   const int n = M.n, n2 = M.n2, n3 = M.n3;
   M.sol = make_basis(N, type);
   M.lgl = make_basis(N, 1);
   M.nbr.assign(nbr, nbr + 6 * (size_t)K);
   M.nside.assign(nside, nside + 6 * (size_t)K);
+  if (flip)
+    M.flip.assign(flip, flip + 6 * (size_t)K);
+  else
+    M.flip.assign(6 * (size_t)K, 0);
   M.Ja.assign((size_t)K * 9 * n3, 0.0);
   M.J.assign((size_t)K * n3, 0.0);
   M.xs.assign((size_t)K * 3 * n3, 0.0);
@@ -324,26 +352,34 @@ static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, cons
       M.J[(size_t)e * n3 + q] = (double)det;
       if (!(det > 0)) ok = false;
     }
-    // master (+xi side) normals: Ja^dn evaluated on the face
-    for (int s = 1; s < 6; s += 2) {
+    // outward normal of every side from the element's own metric: +-Ja^dn evaluated on the
+    // face (the slaves' are replaced below)
+    for (int s = 0; s < 6; ++s) {
       int dn = s / 2;
+      bool plus = (s % 2) == 1;
+      const std::vector<ld>& l = plus ? M.sol.lpl : M.sol.lml;
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a)
           for (int d = 0; d < 3; ++d) {
             ld v = 0;
-            for (int m = 0; m < n; ++m) v += M.sol.lpl[m] * Jas[(dn * 3 + d) * n3 + line_node(n, dn, a, b, m)];
-            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = (double)v;
+            for (int m = 0; m < n; ++m) v += l[m] * Jas[(dn * 3 + d) * n3 + line_node(n, dn, a, b, m)];
+            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = (double)(plus ? v : -v);
           }
     }
   }
   if (!ok) return false;
-  // slave (-xi side): negated normal of the neighbour's matching + side
+  // slaves: negated normal of the master at the matching face point
   for (int e = 0; e < K; ++e)
-    for (int s = 0; s < 6; s += 2) {
+    for (int s = 0; s < 6; ++s) {
+      if (is_master(M, e, s)) continue;
       int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
-      for (int d = 0; d < 3; ++d)
-        for (int p = 0; p < n2; ++p)
-          M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + p] = -M.fn[(((size_t)nb * 6 + ns) * 3 + d) * n2 + p];
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          int a2, b2;
+          mate(M, e, s, a, b, a2, b2);
+          for (int d = 0; d < 3; ++d)
+            M.fn[(((size_t)e * 6 + s) * 3 + d) * n2 + a + n * b] = -M.fn[(((size_t)nb * 6 + ns) * 3 + d) * n2 + a2 + n * b2];
+        }
     }
   return true;
 }
@@ -623,8 +659,10 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
           T WL[4], WR[4];
+          int a2, b2;
+          mate(M, e, s, a, b, a2, b2);
           trace(M, wk.W.data(), 4, e, s, a, b, WL);
-          trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a, b, WR);
+          trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a2, b2, WR);
           const double* nt = &M.fn[((size_t)e * 6 + s) * 3 * n2];
           for (int m = 0; m < n; ++m) {
             if (lh[m] == 0.0) continue;
@@ -721,16 +759,19 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
       bool plus = (s % 2) == 1;
       int nb = M.nbr[e * 6 + s], ns_ = M.nside[e * 6 + s];
       const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
+      const bool mst = is_master(M, e, s);
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
-          // master = element owning the face as its + side; the slave takes the negated master flux
-          int em = plus ? e : nb, sm = plus ? s : ns_;
-          int es = plus ? nb : e, ss = plus ? ns_ : s;
+          // the master's flux along the master's normal; the slave takes it negated
+          int a2, b2;
+          mate(M, e, s, a, b, a2, b2);
+          int em = mst ? e : nb, sm = mst ? s : ns_, am = mst ? a : a2, bm = mst ? b : b2;
+          int es = mst ? nb : e, ss = mst ? ns_ : s, as = mst ? a2 : a, bs = mst ? b2 : b;
           T UM[5], US[5];
-          trace(M, U, 5, em, sm, a, b, UM);
-          trace(M, U, 5, es, ss, a, b, US);
+          trace(M, U, 5, em, sm, am, bm, UM);
+          trace(M, U, 5, es, ss, as, bs, US);
           const double* ntm = &M.fn[((size_t)em * 6 + sm) * 3 * n2];
-          double nt[3] = {ntm[0 * n2 + a + n * b], ntm[1 * n2 + a + n * b], ntm[2 * n2 + a + n * b]};
+          double nt[3] = {ntm[0 * n2 + am + n * bm], ntm[1 * n2 + am + n * bm], ntm[2 * n2 + am + n * bm]};
           double sh = std::sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
           double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
           T F[5];
@@ -738,14 +779,15 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           for (int v = 0; v < 5; ++v) F[v] = F[v] * T(sh);
           if (ns) {  // BR1: mean of both viscous fluxes
             T gM[12], gS[12], FvM[5], FvS[5];
-            trace(M, wk.G.data(), 12, em, sm, a, b, gM);
-            trace(M, wk.G.data(), 12, es, ss, a, b, gS);
+            trace(M, wk.G.data(), 12, em, sm, am, bm, gM);
+            trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
             Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);
             viscous_flux(PM, gM, S, nt, FvM);
             viscous_flux(PS, gS, S, nt, FvS);
             for (int v = 0; v < 5; ++v) F[v] = F[v] - T(0.5) * (FvM[v] + FvS[v]);
           }
-          double sgn = plus ? 1.0 : -1.0;  // outward flux of this element
+          double sgn = mst ? 1.0 : -1.0;   // outward flux of this element
+          double sgo = plus ? 1.0 : -1.0;  // outward sense of xi_dn on this side
           for (int m = 0; m < n; ++m) {
             if (lh[m] == 0.0) continue;
             int q = line_node(n, dn, a, b, m);
@@ -753,7 +795,7 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
               T pen = T(sgn) * F[v];
               if (S.form != 0) {
                 // strong / split: minus the interior contravariant flux in the outward direction
-                pen = pen - T(sgn) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
+                pen = pen - T(sgo) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
               }
               acc[v * n3 + q] = acc[v * n3 + q] + T(lh[m]) * pen;
             }
@@ -808,9 +850,10 @@ int orc_basis(int N, int type, double* x, double* w, double* D, double* Dhat, do
   return 0;
 }
 
-orc_handle* orc_create(int K, int N, int type, const double* xgeo, const int32_t* nbr, const int8_t* nside) {
+orc_handle* orc_create(int K, int N, int type, const double* xgeo, const int32_t* nbr, const int8_t* nside,
+                       const int8_t* flip) {
   orc_handle* h = new orc_handle;
-  if (!build_mesh(h->M, K, N, type, xgeo, nbr, nside)) { delete h; return nullptr; }
+  if (!build_mesh(h->M, K, N, type, xgeo, nbr, nside, flip)) { delete h; return nullptr; }
   return h;
 }
 

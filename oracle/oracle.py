@@ -45,7 +45,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int] + [_D] * 6
         L.orc_create.restype = ctypes.c_void_p
-        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8]
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8, _I8]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
         sch = [ctypes.c_int] * 4 + [ctypes.c_double] * 4
@@ -117,9 +117,13 @@ class Scheme:
 
 
 class OracleMesh:
-    """Geometry and connectivity of one mesh, built by the oracle from the sampled map."""
+    """Geometry and connectivity of one mesh, built by the oracle from the sampled map.
 
-    def __init__(self, xgeo, nbr, nside, N: int, nodes: str):
+    ``flip[K,6]`` (optional, all 0 when omitted) holds each side's orientation code: the
+    neighbour's face point matching face point (a, b) is reached by swapping (a, b) if bit 2
+    is set, then reversing the first index if bit 0 and the second if bit 1 is set."""
+
+    def __init__(self, xgeo, nbr, nside, N: int, nodes: str, flip=None):
         xgeo = _c(xgeo)
         self.K = xgeo.shape[0]
         self.N, self.n = N, N + 1
@@ -127,7 +131,9 @@ class OracleMesh:
         self.nodes = nodes
         nbr = _c(nbr, np.int32)
         nside = _c(nside, np.int8)
-        h = lib().orc_create(self.K, N, NODES[nodes], _p(xgeo), nbr.ctypes.data_as(_I32), nside.ctypes.data_as(_I8))
+        self._flip = None if flip is None else _c(flip, np.int8)
+        fl = None if self._flip is None else self._flip.ctypes.data_as(_I8)
+        h = lib().orc_create(self.K, N, NODES[nodes], _p(xgeo), nbr.ctypes.data_as(_I32), nside.ctypes.data_as(_I8), fl)
         if not h:
             raise ValueError("oracle: invalid mesh (J <= 0)")
         self.h = ctypes.c_void_p(h)

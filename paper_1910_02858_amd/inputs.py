@@ -3,7 +3,8 @@
 This module holds no arithmetic of the discretisation itself: no quadrature
 nodes, no derivative matrices, no fluxes.  It only describes *problems*:
 
-* periodic hexahedral lattices and their face connectivity,
+* periodic hexahedral lattices and their face connectivity, also with the reference
+  axes of elements rotated (faces that meet on other sides and in other orientations),
 * analytic maps from the undeformed lattice to a curved mesh,
 * closed-form initial states (density wave, Taylor-Green vortex),
 * the parameters of the five workloads and the seeded ensemble draw.
@@ -19,6 +20,7 @@ face ``xi_d = -1`` and side ``2*d+1`` the face ``xi_d = +1`` of direction
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import math
 from typing import Optional
 
@@ -54,6 +56,120 @@ def periodic_lattice(kx: int, ky: int, kz: int):
         side[:, s] = s ^ 1
     flip = np.zeros((K, 6), np.int8)
     return nbr, side, flip
+
+
+def face_orientation_map(code: int, a, b, N: int):
+    """Neighbour face point matching face point ``(a, b)`` under orientation ``code``.
+
+    Face points of side ``s`` (direction ``d = s // 2``) are indexed by the two tangential
+    node indices in increasing direction order.  ``code`` in 0..7: bit 2 swaps ``(a, b)``,
+    then bit 0 reverses the first index and bit 1 the second (``x -> N - x``).
+    """
+    p, q = (b, a) if code & 4 else (a, b)
+    return (N - p if code & 1 else p), (N - q if code & 2 else q)
+
+
+def cube_rotations():
+    """The 24 proper rotations of the reference cube ``[-1, 1]^3`` as ``(perm, sign)``:
+    new axis ``d`` runs along old axis ``perm[d]``, reversed where ``sign[d] < 0``."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inv = sum(1 for x in range(3) for y in range(x + 1, 3) if perm[x] > perm[y])
+        for sg in itertools.product((1, -1), repeat=3):
+            if (-1) ** inv * sg[0] * sg[1] * sg[2] == 1:
+                out.append((perm, sg))
+    return out
+
+
+def rotation_node_map(r: int, N: int):
+    """``old[q']``: the node (index ``i + n*(j + n*k)``) of the unrotated element that the
+    rotated element's node ``q'`` is, for rotation ``r`` of :func:`cube_rotations`."""
+    perm, sg = cube_rotations()[r]
+    n = N + 1
+    old = np.empty(n ** 3, np.int64)
+    for q in range(n ** 3):
+        new = (q % n, (q // n) % n, q // (n * n))
+        o = [0, 0, 0]
+        for d in range(3):
+            o[perm[d]] = new[d] if sg[d] > 0 else N - new[d]
+        old[q] = o[0] + n * (o[1] + n * o[2])
+    return old
+
+
+def _rotated_face_table():
+    """For rotations ``(re, rn)`` of two face neighbours of a structured lattice and side
+    ``s'`` of the rotated element ``e``: the old side of ``e`` behind ``s'`` and the rotated
+    neighbour's side and orientation code.  Derived by following every face point (N = 2)."""
+    N, n = 2, 3
+    rots = cube_rotations()
+    old_side = np.empty((24, 6), np.int64)
+    tab = np.empty((24, 6, 24, 2), np.int64)
+    for re, (pe, se) in enumerate(rots):
+        for s2 in range(6):
+            d2, p2 = s2 // 2, s2 % 2
+            da, db = (1, 2) if d2 == 0 else ((0, 2) if d2 == 1 else (0, 1))
+            S = 2 * pe[d2] + (p2 ^ (1 if se[d2] < 0 else 0))
+            old_side[re, s2] = S
+            for rn, (pn, sn) in enumerate(rots):
+                found = None
+                for o in range(8):
+                    ok, side_n = True, None
+                    for a in range(n):
+                        for b in range(n):
+                            new = [0, 0, 0]
+                            new[d2], new[da], new[db] = (N if p2 else 0), a, b
+                            old = [0, 0, 0]
+                            for d in range(3):
+                                old[pe[d]] = new[d] if se[d] > 0 else N - new[d]
+                            D = S // 2
+                            old[D] = N - old[D]            # the neighbour's node across the face
+                            nn = [0, 0, 0]
+                            for d in range(3):
+                                nn[d] = old[pn[d]] if sn[d] > 0 else N - old[pn[d]]
+                            dn = [d for d in range(3) if pn[d] == D][0]
+                            sd = 2 * dn + (1 if nn[dn] == N else 0)
+                            ta, tb = (1, 2) if dn == 0 else ((0, 2) if dn == 1 else (0, 1))
+                            if side_n is None:
+                                side_n = sd
+                            if sd != side_n or face_orientation_map(o, a, b, N) != (nn[ta], nn[tb]):
+                                ok = False
+                                break
+                        if not ok:
+                            break
+                    if ok:
+                        found = (side_n, o)
+                        break
+                assert found is not None
+                tab[re, s2, rn] = found
+    return old_side, tab
+
+
+_FACE_TABLE = None
+
+
+def rotate_elements(X, nbr, side, flip, N: int, rot):
+    """Relabel the reference axes of every element of a structured periodic lattice.
+
+    ``rot[e]`` indexes :func:`cube_rotations`.  The physical mesh is unchanged; each element's
+    nodes are renumbered, so neighbouring faces meet on other sides and in other orientations.
+    Returns ``(X', nbr', side', flip', node_map)`` with ``X'[e][:, q'] = X[e][:, node_map[e][q']]``
+    (a state field is carried over the same way).
+    """
+    global _FACE_TABLE
+    nbr, side, flip = np.asarray(nbr), np.asarray(side), np.asarray(flip)
+    K = nbr.shape[0]
+    assert np.all(side == np.arange(6)[None, :] ^ 1) and not np.any(flip), "expects a structured lattice"
+    if _FACE_TABLE is None:
+        _FACE_TABLE = _rotated_face_table()
+    old_side, tab = _FACE_TABLE
+    rot = np.asarray(rot, np.int64)
+    maps = np.stack([rotation_node_map(r, N) for r in range(24)])
+    node_map = maps[rot]
+    Xr = np.take_along_axis(np.asarray(X), node_map[:, None, :], axis=2)
+    S = old_side[rot]                                   # [K][6] old side behind each new side
+    nb = np.take_along_axis(nbr, S, axis=1).astype(np.int32)
+    t = tab[rot[:, None], np.arange(6)[None, :], rot[nb]]
+    return (np.ascontiguousarray(Xr), nb, t[..., 0].astype(np.int8), t[..., 1].astype(np.int8), node_map)
 
 
 def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):
