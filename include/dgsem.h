@@ -62,10 +62,23 @@ typedef struct {
   int32_t n_geo;           /* polynomial degree of the geometry; must equal N               */
   const double *xgeo;      /* HOST [K][3][(n_geo+1)^3] physical coordinates at the LGL nodes
                               of degree n_geo (node i + n*(j + n*k))                         */
-  const int32_t *nbr_elem; /* HOST [K][6] element across each side                          */
-  const int8_t *nbr_side;  /* HOST [K][6] side of that neighbour (must be the opposite side) */
-  const int8_t *flip;      /* HOST [K][6] orientation; NULL or all 0 (only 0 supported)      */
+  const int32_t *nbr_elem; /* HOST [K][6] element across each side (every side has one)     */
+  const int8_t *nbr_side;  /* HOST [K][6] side of that neighbour the face lies on, 0..5       */
+  const int8_t *flip;      /* HOST [K][6] orientation code 0..7 of each face, NULL = all 0    */
 } dg_mesh;
+/* Faces of conforming meshes (Sec. 5.1: each face has a master and a slave side).  Side 2d is
+ * the face xi_d = -1 and side 2d+1 the face xi_d = +1 of direction d.  Face point (a,b) of a
+ * side is the node at the face's position along d whose indices along the other two
+ * directions, in increasing direction order, are a and b.  flip[e][s] = o maps face point (a,b)
+ * of side s of element e to the neighbour's matching face point: swap (a,b) if o & 4, then
+ * reverse the first index (x -> N - x) if o & 1 and the second if o & 2.  The neighbour must
+ * name e back, on side s, with the inverse code (o itself, or o with bits 0 and 1 exchanged
+ * when o & 4), and the matched face points must coincide up to one translation per face (a
+ * periodic shift): otherwise DG_ERR_MESH.  The master of a face is the +xi side where a +xi
+ * side meets a -xi side, else the element with the smaller index (the smaller side within one
+ * element); normals and surface elements are the master's.  A mesh whose every face meets the
+ * opposite side with code 0 is structured; the vector-Jacobian products are built for
+ * structured meshes only. */
 
 typedef struct {
   int32_t eqn, form, volflux, riemann; /* enums above                                      */
@@ -85,7 +98,8 @@ int dg_rk_coefficients(double *a, double *b, double *c);
 /* Build the operator for a mesh (Sec. 3.1: metric terms in curl form, eq.
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
- * Supported: 1 <= N <= 8, periodic/conforming meshes with flip 0.  hip_stream is a
+ * Supported: 1 <= N <= 8, closed conforming meshes (no boundary sides; faces on any side and
+ * in any orientation, see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
@@ -111,8 +125,8 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for the split form on LGL nodes (KEP, EC or central volume flux; DG_ERR_UNSUPPORTED
- * otherwise) and N <= 7; the derivative of |x| at 0 and of max at a tie is the mean of the
+ * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on structured
+ * meshes and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
  * one-sided derivatives, the log means of the EC flux are differentiated with the forward's
  * branch threshold (series below ((a-b)/(a+b))^2 = 1e-4, logarithms above).  Device arrays [K][5][n^3], pairwise distinct.
  * Not in the paper: the reverse of its operator, for gradients of objectives of U. */

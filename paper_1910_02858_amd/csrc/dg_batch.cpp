@@ -103,6 +103,9 @@ dg::BatchView view(const dg_batch *b, const Group &g, const dg::Member *table) {
   v.count = (int)g.idx.size();
   v.total = g.total;
   v.tab = b->mem[g.idx[0]]->d_tab;
+  v.general = 0;
+  for (int i : g.idx)
+    if (b->mem[i]->d_fc) v.general = 1;
   return v;
 }
 
@@ -117,7 +120,7 @@ std::vector<dg::Member> describe(const dg_batch *b, const double *const *U_in, d
       // field by field into zeroed storage, so padding bytes are defined for the content hash
       dg::Member d;
       std::memset(&d, 0, sizeof(d));
-      d.g.Ja = h->d_Ja; d.g.sJ = h->d_sJ; d.g.fn = h->d_fn; d.g.nbr = h->d_nbr; d.g.tab = h->d_tab; d.g.K = h->K;
+      d.g.Ja = h->d_Ja; d.g.sJ = h->d_sJ; d.g.fn = h->d_fn; d.g.nbr = h->d_nbr; d.g.fc = h->d_fc; d.g.tab = h->d_tab; d.g.K = h->K;
       d.ph.gamma = h->ph.gamma; d.ph.R = h->ph.R; d.ph.mu = h->ph.mu; d.ph.Pr = h->ph.Pr;
       d.ph.kappa = h->ph.kappa; d.ph.vf = h->ph.vf; d.ph.rs = h->ph.rs;
       d.U = U_in[i];

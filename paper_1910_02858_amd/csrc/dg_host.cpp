@@ -194,7 +194,30 @@ struct HostGeo {
   std::vector<double> Ja, J, sJ, xs, fn;
 };
 
-int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nbr, HostGeo &G, std::string &msg) {
+// Face conventions of conforming meshes.  Face point (a,b) of side s (direction d = s/2) is the
+// volume node at position 0 (s even) or N (s odd) along d, with a and b the node indices along
+// the other two directions in increasing order.  The orientation code o maps it to the
+// neighbour's face point: swap (a,b) if o & 4, then reverse the first index if o & 1 and the
+// second if o & 2.
+inline void face_mate(int o, int N, int a, int b, int &a2, int &b2) {
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  a2 = (o & 1) ? N - p : p;
+  b2 = (o & 2) ? N - q : q;
+}
+inline int orientation_inverse(int o) { return (o & 4) ? (4 | ((o & 1) << 1) | ((o >> 1) & 1)) : o; }
+inline int face_point_node(int n, int s, int a, int b) {
+  const int d = s >> 1, m = (s & 1) ? n - 1 : 0;
+  return d == 0 ? m + n * (a + n * b) : (d == 1 ? a + n * (m + n * b) : a + n * (b + n * m));
+}
+// master of a face: the +xi side where a +xi side meets a -xi side, else the element with the
+// smaller index (the smaller side within one element)
+inline bool face_master(int e, int s, int nb, int ns) {
+  if ((s & 1) != (ns & 1)) return (s & 1) != 0;
+  return e < nb || (e == nb && s < ns);
+}
+
+int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nbr, const int8_t *nside,
+                   const int8_t *flip, HostGeo &G, std::string &msg) {
   const int n = N + 1, n2 = n * n, n3 = n2 * n;
   const Basis1D L = make_basis(N, DG_NODES_LGL);
   const Basis1D S = (type == DG_NODES_LGL) ? L : make_basis(N, type);
@@ -275,18 +298,20 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
       G.J[(size_t)e * n3 + q] = (double)det;
       G.sJ[(size_t)e * n3 + q] = (double)(1.0L / det);
     }
-    // masters: the +xi_d side of every element
-    for (int d = 0; d < 3; ++d) {
-      const int s = 2 * d + 1;
+    // outward normal of every master side from the element's own metric: +-Ja^d at the face
+    for (int s = 0; s < 6; ++s) {
+      const int d = s >> 1;
+      if (!face_master(e, s, nbr[e * 6 + s], nside[e * 6 + s])) continue;
+      const std::vector<xf> &l = (s & 1) ? S.lp : S.lm;
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a)
           for (int c = 0; c < 3; ++c) {
             xf v = 0.0L;
             for (int m = 0; m < n; ++m) {
               const int q = d == 0 ? (m + n * (a + n * b)) : (d == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
-              v += S.lp[m] * Jas[(d * 3 + c) * n3 + q];
+              v += l[m] * Jas[(d * 3 + c) * n3 + q];
             }
-            G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + a + n * b] = (double)v;
+            G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + a + n * b] = (double)((s & 1) ? v : -v);
           }
     }
   }
@@ -305,15 +330,37 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
       msg = buf;
       return DG_ERR_MESH;
     }
-  // slaves: negated normal of the master's matching side
+  // slaves: negated normal of the master at the matching face point
   for (int e = 0; e < K; ++e)
-    for (int d = 0; d < 3; ++d) {
-      const int s = 2 * d, nb = nbr[e * 6 + s];
-      for (int c = 0; c < 3; ++c)
-        for (int p = 0; p < n2; ++p)
-          G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + p] = -G.fn[(((size_t)nb * 6 + s + 1) * 3 + c) * n2 + p];
+    for (int s = 0; s < 6; ++s) {
+      const int nb = nbr[e * 6 + s], ns = nside[e * 6 + s], o = flip ? flip[e * 6 + s] : 0;
+      if (face_master(e, s, nb, ns)) continue;
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          int a2, b2;
+          face_mate(o, N, a, b, a2, b2);
+          for (int c = 0; c < 3; ++c)
+            G.fn[(((size_t)e * 6 + s) * 3 + c) * n2 + a + n * b] = -G.fn[(((size_t)nb * 6 + ns) * 3 + c) * n2 + a2 + n * b2];
+        }
     }
   return DG_OK;
+}
+
+// face codes for the kernels (see dg::Geo::fc); empty on a structured mesh
+std::vector<uint8_t> face_codes(const dg_mesh *mesh) {
+  const int K = mesh->n_elems;
+  bool structured = true;
+  for (int q = 0; q < 6 * K && structured; ++q)
+    structured = mesh->nbr_side[q] == ((q % 6) ^ 1) && (!mesh->flip || mesh->flip[q] == 0);
+  std::vector<uint8_t> fc;
+  if (structured) return fc;
+  fc.resize((size_t)6 * K);
+  for (int e = 0; e < K; ++e)
+    for (int s = 0; s < 6; ++s) {
+      const int q = e * 6 + s, ns = mesh->nbr_side[q], o = mesh->flip ? mesh->flip[q] : 0;
+      fc[q] = (uint8_t)(ns | (o << 3) | (face_master(e, s, mesh->nbr_elem[q], ns) ? 64 : 0));
+    }
+  return fc;
 }
 
 int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
@@ -323,15 +370,45 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) return DG_ERR_ARG;
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
-  // connectivity: every side has a reciprocal neighbour on the opposite side, flip 0
+  // connectivity: every side has a neighbour that names it back, on the side and with the
+  // inverse orientation it names; boundaries (no neighbour) are not supported
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
-      const int nb = mesh->nbr_elem[e * 6 + s];
-      if (nb < 0 || nb >= K) return DG_ERR_UNSUPPORTED;  // boundaries are not supported
-      if (mesh->nbr_side[e * 6 + s] != (s ^ 1)) return DG_ERR_UNSUPPORTED;
-      if (mesh->flip && mesh->flip[e * 6 + s] != 0) return DG_ERR_UNSUPPORTED;
-      if (mesh->nbr_elem[nb * 6 + (s ^ 1)] != e) return DG_ERR_MESH;
+      const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
+      const int o = mesh->flip ? mesh->flip[q] : 0;
+      if (nb < 0 || nb >= K) return DG_ERR_UNSUPPORTED;
+      if (ns < 0 || ns > 5 || o < 0 || o > 7 || (nb == e && ns == s)) return DG_ERR_MESH;
+      const int qn = nb * 6 + ns;
+      if (mesh->nbr_elem[qn] != e || mesh->nbr_side[qn] != s) return DG_ERR_MESH;
+      if ((mesh->flip ? mesh->flip[qn] : 0) != orientation_inverse(o)) return DG_ERR_MESH;
     }
+  // the matched face points coincide up to one translation per face (a periodic shift)
+  const int n = N + 1, n3 = n * n * n;
+  for (int e = 0; e < K; ++e) {
+    const double *xe = mesh->xgeo + (size_t)e * 3 * n3;
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      double lo = xe[d * n3], hi = lo;
+      for (int q = 0; q < n3; ++q) { lo = std::min(lo, xe[d * n3 + q]); hi = std::max(hi, xe[d * n3 + q]); }
+      ext = std::max(ext, hi - lo);
+    }
+    for (int s = 0; s < 6; ++s) {
+      const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q], o = mesh->flip ? mesh->flip[q] : 0;
+      const double *xn = mesh->xgeo + (size_t)nb * 3 * n3;
+      double shift[3];
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          int a2, b2;
+          face_mate(o, N, a, b, a2, b2);
+          const int qe = face_point_node(n, s, a, b), qn = face_point_node(n, ns, a2, b2);
+          for (int d = 0; d < 3; ++d) {
+            const double dx = xe[d * n3 + qe] - xn[d * n3 + qn];
+            if (a == 0 && b == 0) shift[d] = dx;
+            else if (!(std::fabs(dx - shift[d]) <= 1e-9 * ext)) return DG_ERR_MESH;
+          }
+        }
+    }
+  }
   return DG_OK;
 }
 
@@ -505,8 +582,9 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   }
   HostGeo G;
   std::string msg;
-  int rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, G, msg);
+  int rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
   if (rc) { delete h; return rc; }
+  const std::vector<uint8_t> fc = face_codes(mesh);
   const std::vector<double> &sJ = G.sJ;
   h->x_nodes.swap(G.xs);
   const bool ns = sc->eqn == DG_NAVIER_STOKES;
@@ -514,6 +592,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc) rc = dev_alloc(&h->d_sJ, (size_t)K * n3);
   if (!rc) rc = dev_alloc(&h->d_fn, (size_t)K * 18 * n2);
   if (!rc) rc = dev_alloc(&h->d_nbr, (size_t)K * 6);
+  if (!rc && !fc.empty()) rc = dev_alloc(&h->d_fc, fc.size());
   if (!rc) rc = dev_alloc(&h->d_tab, 1);
   if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
   if (!rc) rc = dev_alloc(&h->d_partial, (size_t)K * 8);
@@ -523,6 +602,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   ok = ok && hipMemcpy(h->d_sJ, sJ.data(), sJ.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(h->d_fn, G.fn.data(), G.fn.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(h->d_nbr, mesh->nbr_elem, (size_t)K * 6 * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+  if (!fc.empty()) ok = ok && hipMemcpy(h->d_fc, fc.data(), fc.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(h->d_tab, &h->tab, sizeof(dg::Tab), hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) { dg_destroy(h); return DG_ERR_HIP; }
   *out = h;
@@ -536,7 +616,7 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
   const int K = mesh->n_elems, n = N + 1;
   HostGeo G;
   std::string msg;
-  rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, G, msg);
+  rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
   if (rc) return rc;
   if (Ja) std::memcpy(Ja, G.Ja.data(), G.Ja.size() * sizeof(double));
   if (J) std::memcpy(J, G.J.data(), G.J.size() * sizeof(double));
@@ -666,7 +746,7 @@ void dg_destroy(dg_handle *h) {
   for (int i = 0; i < 3; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
-  (void)hipFree(h->d_tab);
+  (void)hipFree(h->d_fc); (void)hipFree(h->d_tab);
   (void)hipFree(h->d_G); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
   delete h;
 }
@@ -678,6 +758,10 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
+  if (h->d_fc)
+    return fail(h, DG_ERR_UNSUPPORTED,
+                "the vector-Jacobian product is built for structured meshes (every face on the opposite side, "
+                "orientation 0)");
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
   if (ns && !h->d_Pf) {
     int rc = dev_alloc(&h->d_Pf, (size_t)h->K * 24 * h->n * h->n);

@@ -27,6 +27,11 @@ struct Geo {
   const double *sJ;   // [K][n3]: 1/J
   const double *fn;   // [K][6][3][n2]: outward scaled normal of each side (the master's, negated on slaves)
   const int32_t *nbr; // [K][6]
+  // [K][6] face code of each side, NULL on a structured mesh (every neighbour across side s
+  // meets it on side s^1 in the same orientation): bits 0-2 the neighbour's side, bits 3-5
+  // the orientation (bit 3+2 swaps the face indices (a,b), then bit 3+0 reverses the first and
+  // bit 3+1 the second), bit 6 set where this side is the face's master
+  const uint8_t *fc;
   const Tab *tab;
   int K;
 };
@@ -73,6 +78,7 @@ struct BatchView {
   const int *first;
   int count, total;
   const Tab *tab;
+  int general;  // some member's mesh has face codes (Geo::fc): launch the kernels that read them
 };
 
 // elements per workgroup the batched kernels are built for (1, 2, 4 up to this bound)
@@ -110,6 +116,7 @@ struct dg_handle {
   // device memory owned by the handle
   double *d_Ja = nullptr, *d_sJ = nullptr, *d_fn = nullptr;
   int32_t *d_nbr = nullptr;
+  uint8_t *d_fc = nullptr;      // face codes [K][6], only on meshes that are not structured
   dg::Tab *d_tab = nullptr;
   double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
   double *d_Pf = nullptr;       // face terms of the transposed lifting [K][6][4][n^2] (first VJP)
@@ -124,7 +131,7 @@ struct dg_handle {
   std::string err;
   dg::Geo geo() const {
     dg::Geo g;
-    g.Ja = d_Ja; g.sJ = d_sJ; g.fn = d_fn; g.nbr = d_nbr; g.tab = d_tab; g.K = K;
+    g.Ja = d_Ja; g.sJ = d_sJ; g.fn = d_fn; g.nbr = d_nbr; g.fc = d_fc; g.tab = d_tab; g.K = K;
     return g;
   }
 };

@@ -41,6 +41,33 @@ template <int n> __device__ __forceinline__ int line_node(int dn, int a, int b, 
   return dn == 0 ? (m + n * (a + n * b)) : (dn == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
 }
 
+// The neighbour's face point matching face point (a,b) of side s of element e: its direction,
+// indices along the other two directions, whether it lies on the neighbour's +xi side, and
+// whether side s is the master of the face.  On a structured mesh (no face codes) the neighbour
+// meets side s on side s^1 at the same (a,b) and the +xi side is the master.  GEN selects the
+// face-code lookup at compile time, so kernels built for structured meshes carry none of it; a
+// GEN kernel still treats a mesh without face codes as structured (a batched launch can mix
+// both kinds of members).
+struct NbFace {
+  int dn, a, b;
+  bool plus, master;
+};
+template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo &g, int e, int s, int a, int b) {
+  NbFace f;
+  if (!GEN || !g.fc) {
+    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = s & 1;
+    return f;
+  }
+  const int c = g.fc[(size_t)e * 6 + s], ns = c & 7, o = (c >> 3) & 7;
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  f.dn = ns >> 1;
+  f.a = (o & 1) ? n - 1 - p : p;
+  f.b = (o & 2) ? n - 1 - q : q;
+  f.plus = ns & 1;
+  f.master = (c >> 6) & 1;
+  return f;
+}
+
 // ----------------------------------------------------------------------------- physics
 // Reciprocal from v_rcp_f64 refined by two Newton steps (error well below one ulp of the
 // quantities it feeds); used for the two-point fluxes, where IEEE division dominated.
@@ -242,7 +269,7 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // (F^v . Ja^dir)_{1+c} (momentum, energy) that the split-form kernels and their reverse consume.
 enum { LIFT_G = 0, LIFT_FV = 1 };
 
-template <int N, bool LGL, int OUT>
+template <int N, bool LGL, int OUT, bool GEN>
 __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                           const double *__restrict__ U, double *__restrict__ G,
                                           double *__restrict__ Fv, double *sW, double *sJa, double *sWs,
@@ -265,9 +292,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   constexpr bool PF = LGL && 6 * n2 <= NT;
   double Unp[5];
   if (PF && valid && t < 6 * n2) {
-    const int s = t / n2, ab = t - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const int s = t / n2, ab = t - s * n2, a = ab % n, b = ab / n;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const int qn = line_node<n>(dn, a, b, (s & 1) ? 0 : N);
+    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(s >> 1, a, b, (s & 1) ? 0 : N);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Unp[v] = U[((size_t)nb * 5 + v) * n3 + qn];
   }
@@ -286,10 +314,11 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
     const double *Un = U + (size_t)nb * 5 * n3;
+    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     double WL[4], WR[4];
     if (LGL) {
       const int q = line_node<n>(dn, a, b, plus ? N : 0);
-      const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+      const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
       for (int v = 0; v < 4; ++v) WL[v] = sW[v * n3 + q];
       double Uq[5];
@@ -297,16 +326,16 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       for (int v = 0; v < 5; ++v) Uq[v] = PF ? Unp[v] : Un[v * n3 + qn];
       grad_prim_to_W(Uq, gm1, ph.R, WR);
     } else {
-      const double *lo = sl + (plus ? n : 0), *ln = sl + (plus ? 0 : n);
+      const double *lo = sl + (plus ? n : 0), *ln = GEN ? sl + (f.plus ? n : 0) : sl + (plus ? 0 : n);
 #pragma unroll
       for (int v = 0; v < 4; ++v) { WL[v] = 0.0; WR[v] = 0.0; }
       for (int m = 0; m < n; ++m) {
-        const int q = line_node<n>(dn, a, b, m);
+        const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
 #pragma unroll
         for (int v = 0; v < 4; ++v) WL[v] += lo[m] * sW[v * n3 + q];
         double Uq[5], W[4];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + q];
+        for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
         grad_prim_to_W(Uq, gm1, ph.R, W);
 #pragma unroll
         for (int v = 0; v < 4; ++v) WR[v] += ln[m] * W[v];
@@ -435,7 +464,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   }
 }
 
-template <int N, bool LGL, int OUT>
+template <int N, bool LGL, int OUT, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
@@ -445,12 +474,12 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
   lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  lift_body<N, LGL, OUT>(g, ph, e, true, threadIdx.x, U, G, Fv, sW, sJa, sWs, sDh, sl, slh);
+  lift_body<N, LGL, OUT, GEN>(g, ph, e, true, threadIdx.x, U, G, Fv, sW, sJa, sWs, sDh, sl, slh);
 }
 
 // ----------------------------------------------------------------------------- operator
-// FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.
-template <int N, bool LGL, bool NS, int FORM, int MODE>
+// FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
+template <int N, bool LGL, bool NS, int FORM, int MODE, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double *__restrict__ U,
                                                     const double *__restrict__ G, double *__restrict__ out,
                                                     double *__restrict__ R, double ca, double cb, double dt) {
@@ -492,10 +521,11 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const int nb = g.nbr[(size_t)e * 6 + s];
     const double *Un = U + (size_t)nb * 5 * n3;
     const double *Gn = G + (size_t)nb * 12 * n3;
+    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     double Uw[5], Ux[5], gw[12], gx[12];  // w: this element's trace, x: neighbour's trace
     if (LGL) {
       const int q = line_node<n>(dn, a, b, plus ? N : 0);
-      const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+      const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
       for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = Un[v * n3 + qn]; }
       if (NS) {
@@ -503,7 +533,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
         for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = Gn[c * n3 + qn]; }
       }
     } else {
-      const double *lo = sl + (plus ? n : 0), *ln = sl + (plus ? 0 : n);
+      const double *lo = sl + (plus ? n : 0), *ln = GEN ? sl + (f.plus ? n : 0) : sl + (plus ? 0 : n);
 #pragma unroll
       for (int v = 0; v < 5; ++v) { Uw[v] = 0.0; Ux[v] = 0.0; }
       if (NS) {
@@ -511,29 +541,31 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
         for (int c = 0; c < 12; ++c) { gw[c] = 0.0; gx[c] = 0.0; }
       }
       for (int m = 0; m < n; ++m) {
-        const int q = line_node<n>(dn, a, b, m);
+        const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) { Uw[v] += lo[m] * sU[v * n3 + q]; Ux[v] += ln[m] * Un[v * n3 + q]; }
+        for (int v = 0; v < 5; ++v) { Uw[v] += lo[m] * sU[v * n3 + q]; Ux[v] += ln[m] * Un[v * n3 + qn]; }
         if (NS) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) { gw[c] += lo[m] * Ge[c * n3 + q]; gx[c] += ln[m] * Gn[c * n3 + q]; }
+          for (int c = 0; c < 12; ++c) { gw[c] += lo[m] * Ge[c * n3 + q]; gx[c] += ln[m] * Gn[c * n3 + qn]; }
         }
       }
     }
-    // master = the element owning the face as its + side; its normal and state go first
+    // the master's normal and state go first (fn holds the outward normal, the master's
+    // negated on the slave side)
     const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
-    const double sg = plus ? 1.0 : -1.0;
+    const bool mst = GEN ? f.master : plus;
+    const double sg = mst ? 1.0 : -1.0;
     const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
+    const double *UM = mst ? Uw : Ux, *US = mst ? Ux : Uw;
     double F[5];
     riemann(ph, UM, US, nh, F);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
     if (NS) {
-      const double *gM = plus ? gw : gx, *gS = plus ? gx : gw;
+      const double *gM = mst ? gw : gx, *gS = mst ? gx : gw;
       double FvM[5], FvS[5];
       const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
       flux_v(PM, gM, ph, nt, FvM);
@@ -797,7 +829,7 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
-template <int N, bool NS, int VF, int MODE>
+template <int N, bool NS, int VF, int MODE, bool GEN>
 __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
@@ -830,8 +862,9 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const int nb = g.nbr[(size_t)e * 6 + s];
     const double *Un = U + (size_t)nb * 5 * n3;
     const double *Gn = G + (size_t)nb * 12 * n3;
+    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     const int qo = line_node<n>(dn, a, b, plus ? N : 0);
-    const int qn = line_node<n>(dn, a, b, plus ? 0 : N);
+    const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
     double Uw[5], Ux[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = Un[v * n3 + qn]; }
@@ -848,11 +881,20 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
     if (NS) {
-      // BR1 mean of the viscous fluxes along the master normal: on both sides the contravariant
-      // flux of the face's direction (Ja^dn is continuous across a conforming face)
+      // BR1 mean of the viscous fluxes along this side's +xi_dn normal Ja^dn: on both sides the
+      // contravariant flux of the face's direction (the normal metric of a conforming face is
+      // continuous: the neighbour's Ja of its face direction is +-Ja^dn, + where one side is a
+      // +xi side and the other a -xi side)
+      if (GEN) {
+        const double sn = (f.plus != plus) ? 1.0 : -1.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + Gn[(dn * 4 + c) * n3 + qn]);
+        for (int c = 0; c < 4; ++c)
+          F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + sn * Gn[(f.dn * 4 + c) * n3 + qn]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + Gn[(dn * 4 + c) * n3 + qn]);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = sg * F[v];
@@ -1031,7 +1073,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   }
 }
 
-template <int N, bool NS, int VF, int MODE>
+template <int N, bool NS, int VF, int MODE, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
@@ -1042,7 +1084,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  split_body<N, NS, VF, MODE>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
+  split_body<N, NS, VF, MODE, GEN>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
 }
 
 // ----------------------------------------------------------------------------- ensemble batch
@@ -1059,7 +1101,7 @@ __device__ __forceinline__ int member_of(const int *first, int count, int item) 
   return lo;
 }
 
-template <int N, int EPB>
+template <int N, int EPB, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchView bv) {
   using L = LiftLds<N>;
   constexpr int n = L::n, NT = Sz<N>::NT;
@@ -1075,11 +1117,11 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
   const bool valid = item < bv.total;
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
-  lift_body<N, true, LIFT_FV>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
+  lift_body<N, true, LIFT_FV, GEN>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
                               sW + slot * L::W, sJa + slot * L::JA, sWs + slot * L::WS, sDh, sl, slh);
 }
 
-template <int N, bool NS, int VF, int EPB>
+template <int N, bool NS, int VF, int EPB, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_SPLIT_MINB) k_split_b(BatchView bv) {
   using L = SplitLds<N>;
   constexpr int n = L::n, NT = Sz<N>::NT;
@@ -1095,7 +1137,7 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_SPLIT_MINB) k_split_b(Batc
   const bool valid = item < bv.total;
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
-  split_body<N, NS, VF, 1>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, M.out, M.R, M.a, M.b,
+  split_body<N, NS, VF, 1, GEN>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, M.out, M.R, M.a, M.b,
                            M.dt, sA + slot * L::A, sP + slot * L::P, sD, slh);
 }
 
@@ -1184,10 +1226,15 @@ template <int N, bool LGL, bool NS, int FORM>
 static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
                          double a, double b, double dt, int mode, hipStream_t st) {
   dim3 grid(g.K), block(Sz<N>::NT);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  const bool gen = g.fc != nullptr;
+  if (mode == 0 && !gen)
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else if (!gen)
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   else
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -1196,10 +1243,15 @@ template <int N, bool NS, int VF>
 static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
                           double a, double b, double dt, int mode, hipStream_t st) {
   dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_split<N, NS, VF, 0>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  const bool gen = g.fc != nullptr;
+  if (mode == 0 && !gen)
+    hipLaunchKernelGGL((k_split<N, NS, VF, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_split<N, NS, VF, 0, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  else if (!gen)
+    hipLaunchKernelGGL((k_split<N, NS, VF, 1, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   else
-    hipLaunchKernelGGL((k_split<N, NS, VF, 1>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+    hipLaunchKernelGGL((k_split<N, NS, VF, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -1221,13 +1273,17 @@ template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st) {
   dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
+  const bool gen = g.fc != nullptr;
   if (!lgl) {
     if (out != LIFT_G) return DG_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_lift<N, false, LIFT_G>), grid, block, 0, st, g, ph, U, G, Fv);
+    if (gen) hipLaunchKernelGGL((k_lift<N, false, LIFT_G, true>), grid, block, 0, st, g, ph, U, G, Fv);
+    else hipLaunchKernelGGL((k_lift<N, false, LIFT_G, false>), grid, block, 0, st, g, ph, U, G, Fv);
   } else if (out == LIFT_G) {
-    hipLaunchKernelGGL((k_lift<N, true, LIFT_G>), grid, block, 0, st, g, ph, U, G, Fv);
+    if (gen) hipLaunchKernelGGL((k_lift<N, true, LIFT_G, true>), grid, block, 0, st, g, ph, U, G, Fv);
+    else hipLaunchKernelGGL((k_lift<N, true, LIFT_G, false>), grid, block, 0, st, g, ph, U, G, Fv);
   } else {
-    hipLaunchKernelGGL((k_lift<N, true, LIFT_FV>), grid, block, 0, st, g, ph, U, G, Fv);
+    if (gen) hipLaunchKernelGGL((k_lift<N, true, LIFT_FV, true>), grid, block, 0, st, g, ph, U, G, Fv);
+    else hipLaunchKernelGGL((k_lift<N, true, LIFT_FV, false>), grid, block, 0, st, g, ph, U, G, Fv);
   }
   DG_CHECK_LAUNCH();
   return DG_OK;
@@ -1248,7 +1304,10 @@ int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const
 template <int N, int EPB>
 static int launch_batch_lift_t(const BatchView &bv, hipStream_t st) {
   const int nblk = (bv.total + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_lift_b<N, EPB>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  if (bv.general)
+    hipLaunchKernelGGL((k_lift_b<N, EPB, true>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  else
+    hipLaunchKernelGGL((k_lift_b<N, EPB, false>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -1256,7 +1315,10 @@ static int launch_batch_lift_t(const BatchView &bv, hipStream_t st) {
 template <int N, bool NS, int VF, int EPB>
 static int launch_batch_split_t(const BatchView &bv, hipStream_t st) {
   const int nblk = (bv.total + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  if (bv.general)
+    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, true>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+  else
+    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, false>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }

@@ -123,14 +123,16 @@ def rk_coefficients():
     return a, b, c
 
 
-def host_geometry(xgeo, nbr, nside, N: int, node_type: str):
+def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None):
     """dg_init's geometry and 1D tables computed on the host only (no device needed)."""
     xgeo = np.ascontiguousarray(xgeo, np.float64)
     nbr = np.ascontiguousarray(nbr, np.int32)
     nside = np.ascontiguousarray(nside, np.int8)
+    flip = None if flip is None else np.ascontiguousarray(flip, np.int8)
     K, n = xgeo.shape[0], N + 1
     m = _Mesh(K, N, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-              nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), None)
+              nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+              None if flip is None else flip.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
     Ja, J, fn = np.zeros((K, 9, n ** 3)), np.zeros((K, n ** 3)), np.zeros((K, 6, 3, n * n))
     D, Dh = np.zeros((n, n)), np.zeros((n, n))
     rc = lib().dg_host_geometry(ctypes.byref(m), N, NODES[node_type], _ptr(Ja), _ptr(J), _ptr(fn), _ptr(D), _ptr(Dh))
@@ -392,8 +394,12 @@ class Batch:
         return [tuple(buf[5 * i:5 * i + 5]) for i in range(ng)]
 
 
-def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[bool] = None):
-    """Mesh, solver and initial state of workload ``wl`` using the library's own LGL nodes."""
+def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[bool] = None,
+                 rotate_seed: Optional[int] = None):
+    """Mesh, solver and initial state of workload ``wl`` using the library's own LGL nodes.
+
+    With ``rotate_seed`` every element's reference axes are rotated by a seeded proper rotation
+    of the cube (same physical mesh; faces meet on other sides and in all orientations)."""
     from . import inputs
     import torch
     k = wl.K1 if K1 is None else K1
@@ -401,8 +407,14 @@ def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[boo
     lgl, _ = nodes(wl.N, "lgl")
     X = inputs.lattice_points(lgl, k, k, k)
     xgeo = inputs.warp_sine(X) if cv else X
-    nbr, side, _ = inputs.periodic_lattice(k, k, k)
-    S = DGSolver.from_workload(wl, xgeo, nbr, side, stream=stream)
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    if rotate_seed is not None:
+        rot = np.random.default_rng(rotate_seed).integers(0, 24, k ** 3)
+        xgeo, nbr, side, flip, _ = inputs.rotate_elements(xgeo, nbr, side, flip, wl.N, rot)
+        del X
+        S = DGSolver.from_workload(wl, xgeo, nbr, side, flip=flip, stream=stream)
+    else:
+        S = DGSolver.from_workload(wl, xgeo, nbr, side, stream=stream)
     U0 = inputs.initial_state(wl, S.node_coords())
     return S, torch.from_numpy(np.ascontiguousarray(U0)).cuda()
 

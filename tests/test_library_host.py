@@ -94,14 +94,56 @@ def test_init_rejects_unsupported(dg):
     assert rc in (-3, -1) and not h.value
     rc, h = _init(dg, X, nbr, side, 3, nodes="lg", form="split")  # split needs LGL
     assert rc == -3
+    nb = nbr.copy()
+    nb[0, 1] = -1                                  # a boundary side
+    rc, h = _init(dg, X, nb, side, 3)
+    assert rc == -3
+
+
+def test_init_rejects_inconsistent_faces(dg):
+    """Sides, orientation codes and coordinates of the two sides of a face must agree."""
+    X, nbr, side, flip = _mesh(dg, 3)
     bad = side.copy()
-    bad[0, 1] = 3                                  # neighbour side not the opposite one
+    bad[0, 1] = 3                                  # the neighbour does not name this side back
     rc, h = _init(dg, X, nbr, bad, 3)
-    assert rc == -3
+    assert rc == -2 and not h.value
     fl = flip.copy()
-    fl[0, 0] = 1                                   # rotated faces are not supported
+    fl[0, 0] = 1                                   # neighbour's code is not the inverse
     rc, h = _init(dg, X, nbr, side, 3, flip=fl)
-    assert rc == -3
+    assert rc == -2
+    fl = flip.copy()
+    fl[0, 0] = 8                                   # no such orientation
+    rc, h = _init(dg, X, nbr, side, 3, flip=fl)
+    assert rc == -2
+    fl = flip.copy()
+    nb, ns = nbr[0, 0], side[0, 0]
+    fl[0, 0] = fl[nb, ns] = 3                      # reciprocal codes, but the points do not match
+    with pytest.raises(dg.DGError) as ei:
+        dg.host_geometry(X, nbr, side, 3, "lgl", flip=fl)
+    assert ei.value.code == -2
+
+
+def _rotated(dg, N, k=3, seed=4, curved=True):
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.lattice_points(lgl, k, k, k)
+    X = inputs.warp_sine(X) if curved else X
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    rot = np.random.default_rng(seed).integers(0, 24, k ** 3)
+    return inputs.rotate_elements(X, nbr, side, flip, N, rot)
+
+
+@pytest.mark.parametrize("N", [2, 5])
+@pytest.mark.parametrize("nodes", ["lg", "lgl"])
+def test_host_geometry_rotated_matches_oracle(dg, orc, N, nodes):
+    """On a mesh whose faces meet on any side and in any orientation, dg_init's tables
+    (including the master normals carried to the slaves) agree with the oracle's."""
+    Xr, nbr, side, flip, _ = _rotated(dg, N)
+    M = orc.OracleMesh(Xr, nbr, side, N, nodes, flip=flip)
+    g = M.geometry()
+    h = dg.host_geometry(Xr, nbr, side, N, nodes, flip=flip)
+    eps = np.finfo(float).eps
+    for key in ("Ja", "J", "fn"):
+        assert np.abs(h[key] - g[key]).max() <= 1.0 * eps * np.abs(g[key]).max(), key
 
 
 def test_init_rejects_broken_connectivity(dg):
