@@ -32,6 +32,10 @@
 //   * conforming faces may meet in any of the eight orientations of a square: the
 //     neighbour's face point matching face point (a,b) is found by an optional swap of
 //     (a,b) followed by optional reversals of the first and of the second index.
+//   * a side without neighbour (neighbour index < 0) is a symmetry plane (slip wall): its
+//     outer state is the mirror image of the inner one across the face (velocity reflected),
+//     its outer gradient the mirror image of the inner gradient (velocity components and
+//     derivative direction reflected); the side is its own master.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
@@ -249,9 +253,10 @@ static void mate(const Mesh& M, int e, int s, int a, int b, int& a2, int& b2) {
   b2 = (o & 2) ? M.N - q : q;
 }
 
-// whether side s of element e is the master of its face
+// whether side s of element e is the master of its face (a boundary side always is)
 static bool is_master(const Mesh& M, int e, int s) {
   const int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
+  if (nb < 0) return true;
   const bool plus = (s % 2) == 1, nplus = (ns % 2) == 1;
   if (plus != nplus) return plus;
   return e < nb || (e == nb && s < ns);
@@ -603,6 +608,53 @@ static void trace(const Mesh& M, const T* X, int nv, int e, int s, int a, int b,
   }
 }
 
+// ------------------------------------------------------------------ symmetry planes
+// unit vector along the scaled normal nt (stored [d][p], stride n2) at face point p
+static void unit_normal(const double* nt, int n2, int p, double* nh) {
+  double a = nt[p], b = nt[n2 + p], c = nt[2 * n2 + p];
+  double l = std::sqrt(a * a + b * b + c * c);
+  nh[0] = a / l; nh[1] = b / l; nh[2] = c / l;
+}
+
+// reflection P = I - 2 nh nh^T applied to a 3-vector
+template <class T> static void reflect(const T* x, const double* nh, T* y) {
+  T xn = x[0] * nh[0] + x[1] * nh[1] + x[2] * nh[2];
+  for (int d = 0; d < 3; ++d) y[d] = x[d] - T(2.0 * nh[d]) * xn;
+}
+
+// mirror image of a conservative state: density and energy unchanged, momentum reflected
+template <class T> static void mirror_state(const T* U, const double* nh, T* G) {
+  G[0] = U[0];
+  reflect(U + 1, nh, G + 1);
+  G[4] = U[4];
+}
+
+// mirror image of W = (u, v, w, T)
+template <class T> static void mirror_W(const T* W, const double* nh, T* G) {
+  reflect(W, nh, G);
+  G[3] = W[3];
+}
+
+// mirror image of the gradients g[d*4+v] = dW_v/dx_d: h = P g P for the velocity block,
+// h = P g for the temperature column
+template <class T> static void mirror_grad(const T* g, const double* nh, T* h) {
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = (i == j ? 1.0 : 0.0) - 2.0 * nh[i] * nh[j];
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 4; ++v) {
+      T acc = T(0.0);
+      for (int d2 = 0; d2 < 3; ++d2) {
+        if (v == 3) {
+          acc = acc + T(P[d][d2]) * g[d2 * 4 + 3];
+        } else {
+          for (int v2 = 0; v2 < 3; ++v2) acc = acc + T(P[d][d2] * P[v][v2]) * g[d2 * 4 + v2];
+        }
+      }
+      h[d * 4 + v] = acc;
+    }
+}
+
 // BR1 lifting of W = (u,v,w,T) for the elements with need[e] != 0
 template <class T>
 static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vector<char>& need, Work<T>& wk) {
@@ -614,7 +666,8 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
   for (int e = 0; e < K; ++e)
     if (need[e]) {
       needW[e] = 1;
-      for (int s = 0; s < 6; ++s) needW[M.nbr[e * 6 + s]] = 1;
+      for (int s = 0; s < 6; ++s)
+        if (M.nbr[e * 6 + s] >= 0) needW[M.nbr[e * 6 + s]] = 1;
     }
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < K; ++e) {
@@ -661,9 +714,15 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
           T WL[4], WR[4];
           int a2, b2;
           mate(M, e, s, a, b, a2, b2);
-          trace(M, wk.W.data(), 4, e, s, a, b, WL);
-          trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a2, b2, WR);
           const double* nt = &M.fn[((size_t)e * 6 + s) * 3 * n2];
+          trace(M, wk.W.data(), 4, e, s, a, b, WL);
+          if (nb >= 0) {
+            trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a2, b2, WR);
+          } else {
+            double nh[3];
+            unit_normal(nt, n2, a + n * b, nh);
+            mirror_W(WL, nh, WR);
+          }
           for (int m = 0; m < n; ++m) {
             if (lh[m] == 0.0) continue;
             int q = line_node(n, dn, a, b, m);
@@ -690,7 +749,8 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
     for (int e = 0; e < K; ++e)
       if (out_mask[e]) {
         need[e] = 1;
-        for (int s = 0; s < 6; ++s) need[M.nbr[e * 6 + s]] = 1;
+        for (int s = 0; s < 6; ++s)
+          if (M.nbr[e * 6 + s] >= 0) need[M.nbr[e * 6 + s]] = 1;
       }
     lifting(M, S, U, need, wk);
   }
@@ -767,20 +827,26 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           mate(M, e, s, a, b, a2, b2);
           int em = mst ? e : nb, sm = mst ? s : ns_, am = mst ? a : a2, bm = mst ? b : b2;
           int es = mst ? nb : e, ss = mst ? ns_ : s, as = mst ? a2 : a, bs = mst ? b2 : b;
-          T UM[5], US[5];
-          trace(M, U, 5, em, sm, am, bm, UM);
-          trace(M, U, 5, es, ss, as, bs, US);
           const double* ntm = &M.fn[((size_t)em * 6 + sm) * 3 * n2];
           double nt[3] = {ntm[0 * n2 + am + n * bm], ntm[1 * n2 + am + n * bm], ntm[2 * n2 + am + n * bm]};
           double sh = std::sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
           double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
+          T UM[5], US[5];
+          trace(M, U, 5, em, sm, am, bm, UM);
+          if (nb >= 0)
+            trace(M, U, 5, es, ss, as, bs, US);
+          else
+            mirror_state(UM, nh, US);
           T F[5];
           riemann(UM, US, nh, S, F);
           for (int v = 0; v < 5; ++v) F[v] = F[v] * T(sh);
           if (ns) {  // BR1: mean of both viscous fluxes
             T gM[12], gS[12], FvM[5], FvS[5];
             trace(M, wk.G.data(), 12, em, sm, am, bm, gM);
-            trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
+            if (nb >= 0)
+              trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
+            else
+              mirror_grad(gM, nh, gS);
             Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);
             viscous_flux(PM, gM, S, nt, FvM);
             viscous_flux(PS, gS, S, nt, FvS);

@@ -58,6 +58,23 @@ def periodic_lattice(kx: int, ky: int, kz: int):
     return nbr, side, flip
 
 
+def box_lattice(kx: int, ky: int, kz: int):
+    """Face connectivity of a ``kx*ky*kz`` lattice whose six outer faces are symmetry planes.
+
+    Same numbering as :func:`periodic_lattice`; a side on the outer boundary has neighbour
+    ``-1`` and boundary kind 0 (symmetry plane) in ``nbr_side``.
+    """
+    nbr, side, flip = periodic_lattice(kx, ky, kz)
+    ez, ey, ex = np.meshgrid(np.arange(kz), np.arange(ky), np.arange(kx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    for s, (c, k, lo) in enumerate([(ex, kx, True), (ex, kx, False), (ey, ky, True), (ey, ky, False),
+                                    (ez, kz, True), (ez, kz, False)]):
+        at = (c == 0) if lo else (c == k - 1)
+        nbr[at, s] = -1
+        side[at, s] = 0
+    return nbr, side, flip
+
+
 def face_orientation_map(code: int, a, b, N: int):
     """Neighbour face point matching face point ``(a, b)`` under orientation ``code``.
 
