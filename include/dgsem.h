@@ -56,15 +56,22 @@ enum { DG_VF_KEP = 0, DG_VF_EC = 1, DG_VF_CENTRAL = 2 };
 /* convective surface flux (Sec. 2.2.3 names LLF and Roe; Sec. 3.3 allows the volume's
  * two-point flux, optionally with Roe-type dissipation) */
 enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
+/* kind of a boundary side (nbr_elem = -1; the kind goes in nbr_side): a symmetry plane or slip
+ * wall, whose outer state and gradient are the mirror images of the inner ones across the face
+ * (velocity and, for the gradient, also the derivative direction reflected; Sec. 2 lists slip
+ * walls among the boundary conditions) */
+enum { DG_BC_SYMMETRY = 0 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
   int32_t n_geo;           /* polynomial degree of the geometry; must equal N               */
   const double *xgeo;      /* HOST [K][3][(n_geo+1)^3] physical coordinates at the LGL nodes
                               of degree n_geo (node i + n*(j + n*k))                         */
-  const int32_t *nbr_elem; /* HOST [K][6] element across each side (every side has one)     */
-  const int8_t *nbr_side;  /* HOST [K][6] side of that neighbour the face lies on, 0..5       */
-  const int8_t *flip;      /* HOST [K][6] orientation code 0..7 of each face, NULL = all 0    */
+  const int32_t *nbr_elem; /* HOST [K][6] element across each side, -1 on a boundary side     */
+  const int8_t *nbr_side;  /* HOST [K][6] side of that neighbour the face lies on, 0..5; on a
+                              boundary side the boundary kind (DG_BC_SYMMETRY)                 */
+  const int8_t *flip;      /* HOST [K][6] orientation code 0..7 of each face, NULL = all 0
+                              (0 on boundary sides)                                            */
 } dg_mesh;
 /* Faces of conforming meshes (Sec. 5.1: each face has a master and a slave side).  Side 2d is
  * the face xi_d = -1 and side 2d+1 the face xi_d = +1 of direction d.  Face point (a,b) of a
@@ -76,9 +83,11 @@ typedef struct {
  * when o & 4), and the matched face points must coincide up to one translation per face (a
  * periodic shift): otherwise DG_ERR_MESH.  The master of a face is the +xi side where a +xi
  * side meets a -xi side, else the element with the smaller index (the smaller side within one
- * element); normals and surface elements are the master's.  A mesh whose every face meets the
- * opposite side with code 0 is structured; the vector-Jacobian products are built for
- * structured meshes only. */
+ * element); normals and surface elements are the master's; a boundary side is its own master.
+ * A mesh without boundary sides whose every face meets the opposite side with code 0 is
+ * structured; the vector-Jacobian products are built for structured meshes only.  Errors:
+ * a boundary kind other than DG_BC_SYMMETRY is DG_ERR_UNSUPPORTED; a neighbour index out of
+ * range (other than -1) is DG_ERR_MESH. */
 
 typedef struct {
   int32_t eqn, form, volflux, riemann; /* enums above                                      */
@@ -98,8 +107,8 @@ int dg_rk_coefficients(double *a, double *b, double *c);
 /* Build the operator for a mesh (Sec. 3.1: metric terms in curl form, eq.
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
- * Supported: 1 <= N <= 8, closed conforming meshes (no boundary sides; faces on any side and
- * in any orientation, see dg_mesh).  hip_stream is a
+ * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
+ * symmetry-plane boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);

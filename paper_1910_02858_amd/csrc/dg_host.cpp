@@ -209,9 +209,10 @@ inline int face_point_node(int n, int s, int a, int b) {
   const int d = s >> 1, m = (s & 1) ? n - 1 : 0;
   return d == 0 ? m + n * (a + n * b) : (d == 1 ? a + n * (m + n * b) : a + n * (b + n * m));
 }
-// master of a face: the +xi side where a +xi side meets a -xi side, else the element with the
-// smaller index (the smaller side within one element)
+// master of a face: a boundary side (no neighbour) itself, the +xi side where a +xi side meets
+// a -xi side, else the element with the smaller index (the smaller side within one element)
 inline bool face_master(int e, int s, int nb, int ns) {
+  if (nb < 0) return true;
   if ((s & 1) != (ns & 1)) return (s & 1) != 0;
   return e < nb || (e == nb && s < ns);
 }
@@ -351,14 +352,17 @@ std::vector<uint8_t> face_codes(const dg_mesh *mesh) {
   const int K = mesh->n_elems;
   bool structured = true;
   for (int q = 0; q < 6 * K && structured; ++q)
-    structured = mesh->nbr_side[q] == ((q % 6) ^ 1) && (!mesh->flip || mesh->flip[q] == 0);
+    structured = mesh->nbr_elem[q] >= 0 && mesh->nbr_side[q] == ((q % 6) ^ 1) && (!mesh->flip || mesh->flip[q] == 0);
   std::vector<uint8_t> fc;
   if (structured) return fc;
   fc.resize((size_t)6 * K);
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, ns = mesh->nbr_side[q], o = mesh->flip ? mesh->flip[q] : 0;
-      fc[q] = (uint8_t)(ns | (o << 3) | (face_master(e, s, mesh->nbr_elem[q], ns) ? 64 : 0));
+      if (mesh->nbr_elem[q] < 0)
+        fc[q] = (uint8_t)(128 | 64 | ns);  // boundary of kind ns, its own master
+      else
+        fc[q] = (uint8_t)(ns | (o << 3) | (face_master(e, s, mesh->nbr_elem[q], ns) ? 64 : 0));
     }
   return fc;
 }
@@ -370,13 +374,19 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) return DG_ERR_ARG;
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
-  // connectivity: every side has a neighbour that names it back, on the side and with the
-  // inverse orientation it names; boundaries (no neighbour) are not supported
+  // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side: only
+  // DG_BC_SYMMETRY, orientation 0) or has a neighbour that names it back, on the side and with
+  // the inverse orientation it names
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
       const int o = mesh->flip ? mesh->flip[q] : 0;
-      if (nb < 0 || nb >= K) return DG_ERR_UNSUPPORTED;
+      if (nb == -1) {
+        if (ns != DG_BC_SYMMETRY) return DG_ERR_UNSUPPORTED;
+        if (o != 0) return DG_ERR_MESH;
+        continue;
+      }
+      if (nb < 0 || nb >= K) return DG_ERR_MESH;
       if (ns < 0 || ns > 5 || o < 0 || o > 7 || (nb == e && ns == s)) return DG_ERR_MESH;
       const int qn = nb * 6 + ns;
       if (mesh->nbr_elem[qn] != e || mesh->nbr_side[qn] != s) return DG_ERR_MESH;
@@ -394,6 +404,7 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
     }
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q], o = mesh->flip ? mesh->flip[q] : 0;
+      if (nb < 0) continue;
       const double *xn = mesh->xgeo + (size_t)nb * 3 * n3;
       double shift[3];
       for (int b = 0; b < n; ++b)

@@ -48,17 +48,25 @@ template <int n> __device__ __forceinline__ int line_node(int dn, int a, int b, 
 // face-code lookup at compile time, so kernels built for structured meshes carry none of it; a
 // GEN kernel still treats a mesh without face codes as structured (a batched launch can mix
 // both kinds of members).
+// A boundary side (bnd) has no neighbour: its outer state is built from the inner one and the
+// other fields hold in-range placeholders that no load may use.
 struct NbFace {
   int dn, a, b;
-  bool plus, master;
+  bool plus, master, bnd;
 };
 template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo &g, int e, int s, int a, int b) {
   NbFace f;
+  f.bnd = false;
   if (!GEN || !g.fc) {
     f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = s & 1;
     return f;
   }
-  const int c = g.fc[(size_t)e * 6 + s], ns = c & 7, o = (c >> 3) & 7;
+  const int c = g.fc[(size_t)e * 6 + s];
+  if (c & 128) {
+    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = true; f.bnd = true;
+    return f;
+  }
+  const int ns = c & 7, o = (c >> 3) & 7;
   const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
   f.dn = ns >> 1;
   f.a = (o & 1) ? n - 1 - p : p;
@@ -66,6 +74,31 @@ template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo 
   f.plus = ns & 1;
   f.master = (c >> 6) & 1;
   return f;
+}
+
+// Symmetry-plane (slip-wall) boundary: the outer side is the mirror image of the inner one across
+// the plane with unit normal nh.  mirror3 reflects a 3-vector; mirror_grad reflects gradients
+// g[d*4+v] = dW_v/dx_d of W = (u, v, w, T) in the derivative direction and, for the velocity
+// block, also in the component.
+__device__ __forceinline__ void mirror3(double *x, const double *nh) {
+  const double xn = 2.0 * (x[0] * nh[0] + x[1] * nh[1] + x[2] * nh[2]);
+  x[0] -= xn * nh[0];
+  x[1] -= xn * nh[1];
+  x[2] -= xn * nh[2];
+}
+__device__ __forceinline__ void mirror_grad(double *g, const double *nh) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double c[3] = {g[v], g[4 + v], g[8 + v]};
+    mirror3(c, nh);
+    g[v] = c[0]; g[4 + v] = c[1]; g[8 + v] = c[2];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) mirror3(g + 4 * d, nh);
+}
+__device__ __forceinline__ void unit3(const double *x, double *nh) {
+  const double il = 1.0 / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  nh[0] = x[0] * il; nh[1] = x[1] * il; nh[2] = x[2] * il;
 }
 
 // ----------------------------------------------------------------------------- physics
@@ -296,8 +329,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     const int nb = g.nbr[(size_t)e * 6 + s];
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(s >> 1, a, b, (s & 1) ? 0 : N);
+    if (!(GEN && f.bnd)) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Unp[v] = U[((size_t)nb * 5 + v) * n3 + qn];
+      for (int v = 0; v < 5; ++v) Unp[v] = U[((size_t)nb * 5 + v) * n3 + qn];
+    }
   }
   if (valid && t < n3) {
     double Uq[5], W[4];
@@ -313,18 +348,20 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const double *Un = U + (size_t)nb * 5 * n3;
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const double *Un = U + (size_t)(GEN && f.bnd ? e : nb) * 5 * n3;
     double WL[4], WR[4];
     if (LGL) {
       const int q = line_node<n>(dn, a, b, plus ? N : 0);
       const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
       for (int v = 0; v < 4; ++v) WL[v] = sW[v * n3 + q];
-      double Uq[5];
+      if (!(GEN && f.bnd)) {
+        double Uq[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Uq[v] = PF ? Unp[v] : Un[v * n3 + qn];
-      grad_prim_to_W(Uq, gm1, ph.R, WR);
+        for (int v = 0; v < 5; ++v) Uq[v] = PF ? Unp[v] : Un[v * n3 + qn];
+        grad_prim_to_W(Uq, gm1, ph.R, WR);
+      }
     } else {
       const double *lo = sl + (plus ? n : 0), *ln = GEN ? sl + (f.plus ? n : 0) : sl + (plus ? 0 : n);
 #pragma unroll
@@ -333,13 +370,25 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
 #pragma unroll
         for (int v = 0; v < 4; ++v) WL[v] += lo[m] * sW[v * n3 + q];
-        double Uq[5], W[4];
+        if (!(GEN && f.bnd)) {
+          double Uq[5], W[4];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
-        grad_prim_to_W(Uq, gm1, ph.R, W);
+          for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
+          grad_prim_to_W(Uq, gm1, ph.R, W);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) WR[v] += ln[m] * W[v];
+          for (int v = 0; v < 4; ++v) WR[v] += ln[m] * W[v];
+        }
       }
+    }
+    if (GEN && f.bnd) {
+      // symmetry plane: the outer W is the inner one with the velocity reflected
+      const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+      const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
+      double nh[3];
+      unit3(nt, nh);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) WR[v] = WL[v];
+      mirror3(WR, nh);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) sWs[(s * 4 + v) * n2 + ab] = 0.5 * (WL[v] + WR[v]);
@@ -519,18 +568,19 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const double *Un = U + (size_t)nb * 5 * n3;
-    const double *Gn = G + (size_t)nb * 12 * n3;
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const bool bnd = GEN && f.bnd;
+    const double *Un = U + (size_t)(bnd ? e : nb) * 5 * n3;
+    const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     double Uw[5], Ux[5], gw[12], gx[12];  // w: this element's trace, x: neighbour's trace
     if (LGL) {
       const int q = line_node<n>(dn, a, b, plus ? N : 0);
       const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = Un[v * n3 + qn]; }
+      for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = bnd ? 0.0 : Un[v * n3 + qn]; }
       if (NS) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = Gn[c * n3 + qn]; }
+        for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = bnd ? 0.0 : Gn[c * n3 + qn]; }
       }
     } else {
       const double *lo = sl + (plus ? n : 0), *ln = GEN ? sl + (f.plus ? n : 0) : sl + (plus ? 0 : n);
@@ -543,10 +593,18 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       for (int m = 0; m < n; ++m) {
         const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) { Uw[v] += lo[m] * sU[v * n3 + q]; Ux[v] += ln[m] * Un[v * n3 + qn]; }
+        for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
         if (NS) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) { gw[c] += lo[m] * Ge[c * n3 + q]; gx[c] += ln[m] * Gn[c * n3 + qn]; }
+          for (int c = 0; c < 12; ++c) gw[c] += lo[m] * Ge[c * n3 + q];
+        }
+        if (!bnd) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Ux[v] += ln[m] * Un[v * n3 + qn];
+          if (NS) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) gx[c] += ln[m] * Gn[c * n3 + qn];
+          }
         }
       }
     }
@@ -559,6 +617,17 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    if (bnd) {
+      // symmetry plane: mirror image of the inner state and gradients
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ux[v] = Uw[v];
+      mirror3(Ux + 1, nh);
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gx[c] = gw[c];
+        mirror_grad(gx, nh);
+      }
+    }
     const double *UM = mst ? Uw : Ux, *US = mst ? Ux : Uw;
     double F[5];
     riemann(ph, UM, US, nh, F);
@@ -860,14 +929,15 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const double *Un = U + (size_t)nb * 5 * n3;
-    const double *Gn = G + (size_t)nb * 12 * n3;
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const bool bnd = GEN && f.bnd;
+    const double *Un = U + (size_t)(bnd ? e : nb) * 5 * n3;
+    const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     const int qo = line_node<n>(dn, a, b, plus ? N : 0);
     const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
     double Uw[5], Ux[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = Un[v * n3 + qn]; }
+    for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = bnd ? Uw[v] : Un[v * n3 + qn]; }
     // normal along +xi_dn scaled by s-hat: Ja^dn at the face node, the master's on the master
     // side and (up to rounding, the metric terms being continuous across the face) on the slave
     const double sg = plus ? 1.0 : -1.0;
@@ -875,6 +945,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    if (bnd) mirror3(Ux + 1, nh);  // symmetry plane: mirror image of the inner state
     const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
     double F[5];
     riemann_vf<VF>(ph, UM, US, nh, F);
@@ -885,7 +956,14 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       // contravariant flux of the face's direction (the normal metric of a conforming face is
       // continuous: the neighbour's Ja of its face direction is +-Ja^dn, + where one side is a
       // +xi side and the other a -xi side)
-      if (GEN) {
+      if (bnd) {
+        // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
+        // mean keeps the normal part of the momentum flux
+        const double gm = Ge[(dn * 4) * n3 + qo] * nh[0] + Ge[(dn * 4 + 1) * n3 + qo] * nh[1] +
+                          Ge[(dn * 4 + 2) * n3 + qo] * nh[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[1 + c] -= gm * nh[c];
+      } else if (GEN) {
         const double sn = (f.plus != plus) ? 1.0 : -1.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)

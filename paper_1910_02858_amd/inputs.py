@@ -165,7 +165,8 @@ _FACE_TABLE = None
 
 
 def rotate_elements(X, nbr, side, flip, N: int, rot):
-    """Relabel the reference axes of every element of a structured periodic lattice.
+    """Relabel the reference axes of every element of a lattice (periodic, or with boundary
+    sides as from :func:`box_lattice`, which stay boundary sides of the same kind).
 
     ``rot[e]`` indexes :func:`cube_rotations`.  The physical mesh is unchanged; each element's
     nodes are renumbered, so neighbouring faces meet on other sides and in other orientations.
@@ -175,7 +176,8 @@ def rotate_elements(X, nbr, side, flip, N: int, rot):
     global _FACE_TABLE
     nbr, side, flip = np.asarray(nbr), np.asarray(side), np.asarray(flip)
     K = nbr.shape[0]
-    assert np.all(side == np.arange(6)[None, :] ^ 1) and not np.any(flip), "expects a structured lattice"
+    inner = nbr >= 0
+    assert np.all((side == np.arange(6)[None, :] ^ 1) | ~inner) and not np.any(flip), "expects a lattice"
     if _FACE_TABLE is None:
         _FACE_TABLE = _rotated_face_table()
     old_side, tab = _FACE_TABLE
@@ -185,8 +187,11 @@ def rotate_elements(X, nbr, side, flip, N: int, rot):
     Xr = np.take_along_axis(np.asarray(X), node_map[:, None, :], axis=2)
     S = old_side[rot]                                   # [K][6] old side behind each new side
     nb = np.take_along_axis(nbr, S, axis=1).astype(np.int32)
-    t = tab[rot[:, None], np.arange(6)[None, :], rot[nb]]
-    return (np.ascontiguousarray(Xr), nb, t[..., 0].astype(np.int8), t[..., 1].astype(np.int8), node_map)
+    bnd = nb < 0
+    t = tab[rot[:, None], np.arange(6)[None, :], rot[np.where(bnd, 0, nb)]]
+    side_r = np.where(bnd, np.take_along_axis(side, S, axis=1), t[..., 0]).astype(np.int8)
+    flip_r = np.where(bnd, 0, t[..., 1]).astype(np.int8)
+    return (np.ascontiguousarray(Xr), nb, side_r, flip_r, node_map)
 
 
 def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):

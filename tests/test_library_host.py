@@ -94,9 +94,9 @@ def test_init_rejects_unsupported(dg):
     assert rc in (-3, -1) and not h.value
     rc, h = _init(dg, X, nbr, side, 3, nodes="lg", form="split")  # split needs LGL
     assert rc == -3
-    nb = nbr.copy()
-    nb[0, 1] = -1                                  # a boundary side
-    rc, h = _init(dg, X, nb, side, 3)
+    nb, sd = nbr.copy(), side.copy()
+    nb[0, 1], sd[0, 1] = -1, 1                     # a boundary of a kind that does not exist
+    rc, h = _init(dg, X, nb, sd, 3)
     assert rc == -3
 
 
@@ -134,6 +134,23 @@ def _rotated(dg, N, k=3, seed=4, curved=True):
 
 @pytest.mark.parametrize("N", [2, 5])
 @pytest.mark.parametrize("nodes", ["lg", "lgl"])
+def test_host_geometry_box_matches_oracle(dg, orc, N, nodes):
+    """A curved box whose outer faces are symmetry planes, element axes rotated: tables agree."""
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.warp_sine(inputs.lattice_points(lgl, 3, 3, 3, box=(np.pi,) * 3))
+    nbr, side, flip = inputs.box_lattice(3, 3, 3)
+    rot = np.random.default_rng(9).integers(0, 24, 27)
+    Xr, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, N, rot)
+    M = orc.OracleMesh(Xr, nbr, side, N, nodes, flip=flip)
+    g = M.geometry()
+    h = dg.host_geometry(Xr, nbr, side, N, nodes, flip=flip)
+    eps = np.finfo(float).eps
+    for key in ("Ja", "J", "fn"):
+        assert np.abs(h[key] - g[key]).max() <= 1.0 * eps * np.abs(g[key]).max(), key
+
+
+@pytest.mark.parametrize("N", [2, 5])
+@pytest.mark.parametrize("nodes", ["lg", "lgl"])
 def test_host_geometry_rotated_matches_oracle(dg, orc, N, nodes):
     """On a mesh whose faces meet on any side and in any orientation, dg_init's tables
     (including the master normals carried to the slaves) agree with the oracle's."""
@@ -155,7 +172,11 @@ def test_init_rejects_broken_connectivity(dg):
     nb = nbr.copy()
     nb[0, 1] = 99  # out of range
     rc, h = _init(dg, X, nb, side, 3)
-    assert rc == -3
+    assert rc == -2
+    nb, sd = nbr.copy(), side.copy()
+    nb[0, 1], sd[0, 1] = -1, 0  # a symmetry plane whose neighbour still names this side
+    rc, h = _init(dg, X, nb, sd, 3)
+    assert rc == -2
 
 
 def test_null_arguments(dg):

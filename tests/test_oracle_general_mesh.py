@@ -179,3 +179,25 @@ def test_symmetry_planes_conserve_mass_and_energy(orc, eqn, form, vf, rs, nodes)
     U0 = inputs.constant_state(M.K, M.n3, u=0.0, v=0.0, w=0.0)
     h = math.pi / m
     assert np.abs(M.rhs(sc, U0)).max() < 1e-12 * np.abs(U0).max() * 2 * (N + 1) ** 2 / h
+
+
+def test_rotated_box_with_symmetry_planes_equals_periodic_octant(orc):
+    """Both extensions together: the octant with six symmetry planes and every element's axes
+    rotated (boundary sides move to other sides too) still equals the periodic result."""
+    N, m = 3, 2
+    lgl = orc.basis(N, "lgl")["x"]
+    Xf = inputs.lattice_points(lgl, 2 * m, 2 * m, 2 * m)
+    nbr, side, _ = inputs.periodic_lattice(2 * m, 2 * m, 2 * m)
+    Mf = orc.OracleMesh(Xf, nbr, side, N, "lgl")
+    Xo = inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3)
+    nbo, sdo, flo = inputs.box_lattice(m, m, m)
+    rot = np.random.default_rng(2).integers(0, 24, m ** 3)
+    Xr, nbr_r, side_r, flip_r, nm = inputs.rotate_elements(Xo, nbo, sdo, flo, N, rot)
+    assert np.any((nbr_r < 0) & (np.arange(6)[None, :] % 2 == 1)) and np.any((nbr_r < 0) & (np.arange(6)[None, :] % 2 == 0))
+    Mr = orc.OracleMesh(Xr, nbr_r, side_r, N, "lgl", flip=flip_r)
+    octant = [e for e in range(Mf.K) if e % (2 * m) < m and (e // (2 * m)) % (2 * m) < m and e // (4 * m * m) < m]
+    U = inputs.taylor_green(Mf.points(), 1.0, 0.3)
+    sc = orc.Scheme("ns", "split", "kep", "roe", mu=1e-2)
+    ref = carry(Mf.rhs(sc, U)[octant], nm)
+    got = Mr.rhs(sc, carry(U[octant], nm))
+    assert np.all(np.abs(got - ref).max(axis=(0, 2)) <= 1e-12 * np.abs(ref).max(axis=(0, 2)))
