@@ -596,6 +596,8 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   int rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
   if (rc) { delete h; return rc; }
   const std::vector<uint8_t> fc = face_codes(mesh);
+  for (int q = 0; q < 6 * K; ++q)
+    if (mesh->nbr_elem[q] < 0) h->has_boundary = true;
   const std::vector<double> &sJ = G.sJ;
   h->x_nodes.swap(G.xs);
   const bool ns = sc->eqn == DG_NAVIER_STOKES;
@@ -769,10 +771,8 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
-  if (h->d_fc)
-    return fail(h, DG_ERR_UNSUPPORTED,
-                "the vector-Jacobian product is built for structured meshes (every face on the opposite side, "
-                "orientation 0)");
+  if (h->has_boundary)
+    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for meshes without boundary sides");
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
   if (ns && !h->d_Pf) {
     int rc = dev_alloc(&h->d_Pf, (size_t)h->K * 24 * h->n * h->n);

@@ -94,6 +94,41 @@ __host__ __device__ inline int xcd_element(int b, int K) {
 }
 __host__ __device__ inline int xcd_grid(int K) { return 8 * ((K + 7) / 8); }
 
+// The neighbour's face point matching face point (a,b) of side s of element e: its direction,
+// indices along the other two directions, whether it lies on the neighbour's +xi side, and
+// whether side s is the master of the face.  On a structured mesh (no face codes) the neighbour
+// meets side s on side s^1 at the same (a,b) and the +xi side is the master.  GEN selects the
+// face-code lookup at compile time, so kernels built for structured meshes carry none of it; a
+// GEN kernel still treats a mesh without face codes as structured (a batched launch can mix
+// both kinds of members).
+// A boundary side (bnd) has no neighbour: its outer state is built from the inner one and the
+// other fields hold in-range placeholders that no load may use.
+struct NbFace {
+  int dn, a, b;
+  bool plus, master, bnd;
+};
+template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo &g, int e, int s, int a, int b) {
+  NbFace f;
+  f.bnd = false;
+  if (!GEN || !g.fc) {
+    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = s & 1;
+    return f;
+  }
+  const int c = g.fc[(size_t)e * 6 + s];
+  if (c & 128) {
+    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = true; f.bnd = true;
+    return f;
+  }
+  const int ns = c & 7, o = (c >> 3) & 7;
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  f.dn = ns >> 1;
+  f.a = (o & 1) ? n - 1 - p : p;
+  f.b = (o & 2) ? n - 1 - q : q;
+  f.plus = ns & 1;
+  f.master = (c >> 6) & 1;
+  return f;
+}
+
 template <int N>
 int launch_batch_lift(const BatchView &bv, int epb, hipStream_t st);
 template <int N>
@@ -117,6 +152,7 @@ struct dg_handle {
   double *d_Ja = nullptr, *d_sJ = nullptr, *d_fn = nullptr;
   int32_t *d_nbr = nullptr;
   uint8_t *d_fc = nullptr;      // face codes [K][6], only on meshes that are not structured
+  bool has_boundary = false;    // some side has no neighbour (symmetry plane)
   dg::Tab *d_tab = nullptr;
   double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
   double *d_Pf = nullptr;       // face terms of the transposed lifting [K][6][4][n^2] (first VJP)

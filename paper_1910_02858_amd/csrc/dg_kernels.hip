@@ -41,41 +41,6 @@ template <int n> __device__ __forceinline__ int line_node(int dn, int a, int b, 
   return dn == 0 ? (m + n * (a + n * b)) : (dn == 1 ? (a + n * (m + n * b)) : (a + n * (b + n * m)));
 }
 
-// The neighbour's face point matching face point (a,b) of side s of element e: its direction,
-// indices along the other two directions, whether it lies on the neighbour's +xi side, and
-// whether side s is the master of the face.  On a structured mesh (no face codes) the neighbour
-// meets side s on side s^1 at the same (a,b) and the +xi side is the master.  GEN selects the
-// face-code lookup at compile time, so kernels built for structured meshes carry none of it; a
-// GEN kernel still treats a mesh without face codes as structured (a batched launch can mix
-// both kinds of members).
-// A boundary side (bnd) has no neighbour: its outer state is built from the inner one and the
-// other fields hold in-range placeholders that no load may use.
-struct NbFace {
-  int dn, a, b;
-  bool plus, master, bnd;
-};
-template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo &g, int e, int s, int a, int b) {
-  NbFace f;
-  f.bnd = false;
-  if (!GEN || !g.fc) {
-    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = s & 1;
-    return f;
-  }
-  const int c = g.fc[(size_t)e * 6 + s];
-  if (c & 128) {
-    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = true; f.bnd = true;
-    return f;
-  }
-  const int ns = c & 7, o = (c >> 3) & 7;
-  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
-  f.dn = ns >> 1;
-  f.a = (o & 1) ? n - 1 - p : p;
-  f.b = (o & 2) ? n - 1 - q : q;
-  f.plus = ns & 1;
-  f.master = (c >> 6) & 1;
-  return f;
-}
-
 // Symmetry-plane (slip-wall) boundary: the outer side is the mirror image of the inner one across
 // the plane with unit normal nh.  mirror3 reflects a 3-vector; mirror_grad reflects gradients
 // g[d*4+v] = dW_v/dx_d of W = (u, v, w, T) in the derivative direction and, for the velocity

@@ -46,7 +46,12 @@ template <int n> __device__ __forceinline__ int vline_node(int dn, int a, int b,
 }
 
 // ---------------------------------------------------------------------------------- main
-template <int N, bool NS>
+// GEN: the mesh has face codes (faces on any side, in any orientation; no boundary sides), and
+// every neighbour value is read at the neighbour's matching face point.  The face terms
+// themselves need no change: with the two copies of a face flux related by the antisymmetry of
+// the surface flux (same-parity sides) or equal (opposite parities), the own-trace derivative of
+// both copies is lhat (Abar_own - Abar_nb) times the outward sign of this side in every case.
+template <int N, bool NS, bool GEN>
 __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
                                                          const double *__restrict__ G,
                                                          const double *__restrict__ Utb, double *__restrict__ Ub,
@@ -122,7 +127,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
-    const int qn = vline_node<n>(dn, a, b, plus ? 0 : N);
+    int qn;
+    if constexpr (GEN) {
+      const NbFace f = nbr_face<n, true>(g, e, s, a, b);
+      qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
+    } else {
+      qn = vline_node<n>(dn, a, b, plus ? 0 : N);
+    }
     double Uw[5], Ux[5], Aw[5], Ax[5];
     const double sjn = g.sJ[(size_t)nb * n3 + qn];
 #pragma unroll
@@ -389,7 +400,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
 // (Wbar, then W's Jacobian at the node's state).  With upd != 0 the register of the 2N scheme
 // is updated from the final Ubar of every node, Rb = ra Rb + rb Ubar (each node is read and
 // written by its own thread only).
-template <int N>
+template <int N, bool GEN>
 __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const double *__restrict__ U,
                                                          const double *__restrict__ Pf, double *__restrict__ Ub,
                                                          double *__restrict__ Rb, double ra, double rb, int upd) {
@@ -407,8 +418,14 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
     const int s = 2 * dir + (id == N ? 1 : 0);
     const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
     const int nb = g.nbr[(size_t)e * 6 + s];
-    // the neighbour's side facing this one is s ^ 1; conforming faces share the point index
-    const double *pf = Pf + ((size_t)nb * 6 + (s ^ 1)) * 4 * n2 + a + n * b;
+    // the neighbour's term at its matching face point (structured: side s ^ 1, same index)
+    const double *pf;
+    if constexpr (GEN) {
+      const NbFace f = nbr_face<n, true>(g, e, s, a, b);
+      pf = Pf + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
+    } else {
+      pf = Pf + ((size_t)nb * 6 + (s ^ 1)) * 4 * n2 + a + n * b;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) Wb[v] += pf[v * n2];
     face = true;
@@ -450,13 +467,26 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
     return DG_ERR_UNSUPPORTED;  // the reverse kernel's LDS staging exceeds 160 KB beyond N = 7
   } else {
   dim3 grid(xcd_grid(g.K)), block(VSz<N>::NT);
+  const bool gen = g.fc != nullptr;
   if (eqn == DG_NAVIER_STOKES) {
-    hipLaunchKernelGGL((k_vjp_main<N, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale, accumulate);
+    if (gen)
+      hipLaunchKernelGGL((k_vjp_main<N, true, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
+                         accumulate);
+    else
+      hipLaunchKernelGGL((k_vjp_main<N, true, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
+                         accumulate);
     if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
-    hipLaunchKernelGGL((k_vjp_face<N>), grid, block, 0, st, g, ph, U, Pf, Ubar, Rb, ra, rb, Rb ? 1 : 0);
+    if (gen)
+      hipLaunchKernelGGL((k_vjp_face<N, true>), grid, block, 0, st, g, ph, U, Pf, Ubar, Rb, ra, rb, Rb ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_vjp_face<N, false>), grid, block, 0, st, g, ph, U, Pf, Ubar, Rb, ra, rb, Rb ? 1 : 0);
   } else {
-    hipLaunchKernelGGL((k_vjp_main<N, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
-                       accumulate);
+    if (gen)
+      hipLaunchKernelGGL((k_vjp_main<N, false, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
+                         accumulate);
+    else
+      hipLaunchKernelGGL((k_vjp_main<N, false, false>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
+                         accumulate);
   }
   if (hipGetLastError() != hipSuccess) return DG_ERR_HIP;
   return DG_OK;

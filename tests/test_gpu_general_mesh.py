@@ -6,8 +6,11 @@ include/dgsem.h).  The library's operator and RK stages are compared with the or
 same rotated mesh (bar: 1e-12 per operator evaluation, 1e-10 after RK steps), with its own
 result on the unrotated lattice carried node for node (the operator does not depend on the
 labelling of the reference axes: 1e-12), and a batched ensemble with a rotated member must
-reproduce that member's one-mesh stage bit for bit.  The vector-Jacobian products are built for
-structured meshes and must refuse a rotated one.
+reproduce that member's one-mesh stage bit for bit.  The vector-Jacobian products on the rotated
+mesh: J^T w against the oracle's assembled tangent Jacobian element by element (1e-12), dot-
+product tests <J^T w, v> = <w, J v> with the oracle's tangent for one operator evaluation
+(1e-12) and an RK rollout (1e-10), and against the library's own lattice result carried over;
+they must refuse a mesh with boundary sides.
 
 Symmetry-plane boundaries: a curved box [0, pi]^3 whose six outer faces are symmetry planes
 (with and without rotated element axes) against the oracle on the same mesh (1e-12, 1e-10 after
@@ -130,10 +133,87 @@ def test_batch_with_rotated_member(dg, orc):
         assert torch.equal(Rb, rR), f"member {i} R differs"
 
 
-def test_vjp_refuses_rotated_mesh(dg, orc):
-    wl = inputs.workload(5, K1=2)
-    _, (Xr, nbr, side, flip), _, _, U = rotated_problem(orc, wl, 2)
+VJP_TINY = [
+    ("ns_kep_roe", dict(eqn="ns", volflux="kep", riemann="roe")),
+    ("ns_ec_volflux_roe", dict(eqn="ns", volflux="ec", riemann="volflux_roe")),
+    ("euler_central_llf", dict(eqn="euler", volflux="central", riemann="llf")),
+]
+
+
+@pytest.mark.parametrize("name,kw", VJP_TINY, ids=[t[0] for t in VJP_TINY])
+def test_vjp_rotated_elementwise_against_oracle_jacobian(dg, orc, name, kw):
+    print(f"case {name}", flush=True)
+    wl = inputs.workload(2, N=2, mach=0.3, **kw)
+    M, (Xr, nbr, side, flip), _, _, U0 = rotated_problem(orc, wl, 2, seed=13, perturb=2e-2)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
     S = dg.DGSolver.from_workload(wl, Xr, nbr, side, flip=flip)
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name}: max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("N,vf", [(5, "kep"), (7, "ec"), (3, "kep")])
+def test_vjp_rotated_dot_product_and_invariance(dg, orc, N, vf):
+    print(f"case N={N} {vf}", flush=True)
+    wl = inputs.workload(5, N=N, volflux=vf)
+    M, (Xr, nbr_r, side_r, flip_r), (X, nbr, side), nm, Ur = rotated_problem(orc, wl, 3, seed=N, perturb=1e-2)
+    sc = orc.Scheme.of(wl)
+    Sr = dg.DGSolver.from_workload(wl, Xr, nbr_r, side_r, flip=flip_r)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side)
+    inv = np.argsort(nm, axis=1)
+    rng = np.random.default_rng(40 + N)
+    for v in inputs.random_directions(Ur, 50 + N, 2):
+        w = rng.standard_normal(Ur.shape)
+        _, Jv = M.rhs_jvp(sc, Ur, v)
+        JTw = Sr.rhs_vjp(to_gpu(Ur), to_gpu(w)).cpu().numpy()
+        lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
+        scale = float(np.sum(np.abs(JTw * v)))
+        print(f"<J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * scale
+        # the same product on the lattice labelling, carried over
+        U = np.take_along_axis(Ur, inv[:, None, :], axis=2)
+        wl_ = np.take_along_axis(w, inv[:, None, :], axis=2)
+        ref = np.take_along_axis(S.rhs_vjp(to_gpu(U), to_gpu(wl_)).cpu().numpy(), nm[:, None, :], axis=2)
+        err = rel_err(JTw, ref)
+        print(f"against the lattice, per variable {err}")
+        assert np.all(err <= 1e-12), err
+
+
+def test_rollout_dot_product_rotated(dg, orc):
+    wl = inputs.workload(5)
+    M, (Xr, nbr, side, flip), _, _, U0 = rotated_problem(orc, wl, 3, seed=21, perturb=1e-3)
+    sc = orc.Scheme.of(wl)
+    S = dg.DGSolver.from_workload(wl, Xr, nbr, side, flip=flip)
+    dt = M.timestep(sc, U0, 0.9, 0.9)
+    steps = 4
+    v = inputs.random_directions(U0, 4, 1)[0]
+    _, vT = M.rk_jvp(sc, U0, v, steps, dt)
+    w = np.random.default_rng(5).standard_normal(U0.shape)
+    _, stage_inputs = dg._rollout_forward(S, to_gpu(U0), steps, dt, keep_stage_inputs=True)
+    Ubar = dg._rollout_backward(S, stage_inputs, to_gpu(w), dt).cpu().numpy()
+    lhs, rhs = float(np.sum(Ubar * v)), float(np.sum(w * vT))
+    scale = float(np.sum(np.abs(Ubar * v)))
+    print(f"<Ubar_0, v_0> = {lhs:.15e}  <w, v_T> = {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-10 * scale
+
+
+def test_vjp_refuses_boundaries(dg, orc):
+    wl = inputs.workload(5)
+    _, (X, nbr, side, flip), U = box_problem(orc, wl, 2)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
     Ug = to_gpu(U)
     with pytest.raises(dg.DGError) as ei:
         S.rhs_vjp(Ug, Ug.clone())
