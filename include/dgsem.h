@@ -85,7 +85,7 @@ typedef struct {
  * side meets a -xi side, else the element with the smaller index (the smaller side within one
  * element); normals and surface elements are the master's; a boundary side is its own master.
  * A mesh without boundary sides whose every face meets the opposite side with code 0 is
- * structured; the vector-Jacobian products are built for meshes without boundary sides.  Errors:
+ * structured.  Errors:
  * a boundary kind other than DG_BC_SYMMETRY is DG_ERR_UNSUPPORTED; a neighbour index out of
  * range (other than -1) is DG_ERR_MESH. */
 
@@ -134,8 +134,8 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on meshes without
- * boundary sides and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
+ * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on every mesh
+ * dg_init accepts and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
  * one-sided derivatives, the log means of the EC flux are differentiated with the forward's
  * branch threshold (series below ((a-b)/(a+b))^2 = 1e-4, logarithms above).  Device arrays [K][5][n^3], pairwise distinct.
  * Not in the paper: the reverse of its operator, for gradients of objectives of U. */

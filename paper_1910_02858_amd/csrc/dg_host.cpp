@@ -771,8 +771,6 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
-  if (h->has_boundary)
-    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for meshes without boundary sides");
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
   if (ns && !h->d_Pf) {
     int rc = dev_alloc(&h->d_Pf, (size_t)h->K * 24 * h->n * h->n);

@@ -46,11 +46,14 @@ template <int n> __device__ __forceinline__ int vline_node(int dn, int a, int b,
 }
 
 // ---------------------------------------------------------------------------------- main
-// GEN: the mesh has face codes (faces on any side, in any orientation; no boundary sides), and
+// GEN: the mesh has face codes (faces on any side, in any orientation, symmetry planes), and
 // every neighbour value is read at the neighbour's matching face point.  The face terms
 // themselves need no change: with the two copies of a face flux related by the antisymmetry of
 // the surface flux (same-parity sides) or equal (opposite parities), the own-trace derivative of
 // both copies is lhat (Abar_own - Abar_nb) times the outward sign of this side in every case.
+// A symmetry plane has one copy (Abar_nb = 0) whose outer state is the mirrored own trace: the
+// outer argument's adjoint comes back mirrored, and the viscous term keeps only the normal part
+// of the own momentum flux.
 template <int N, bool NS, bool GEN>
 __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phys ph, const double *__restrict__ U,
                                                          const double *__restrict__ G,
@@ -125,14 +128,17 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   for (int p = t; p < 6 * n2; p += NT) {
     const int s = p / n2, ab = p % n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
-    const int nb = g.nbr[(size_t)e * 6 + s];
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
-    int qn;
+    int qn, nb;
+    bool bnd = false;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
+      bnd = f.bnd;
+      nb = bnd ? e : g.nbr[(size_t)e * 6 + s];  // a boundary side reads nothing of a neighbour
     } else {
       qn = vline_node<n>(dn, a, b, plus ? 0 : N);
+      nb = g.nbr[(size_t)e * 6 + s];
     }
     double Uw[5], Ux[5], Aw[5], Ax[5];
     const double sjn = g.sJ[(size_t)nb * n3 + qn];
@@ -141,13 +147,19 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       Uw[v] = Ue[v * n3 + qo];
       Ux[v] = U[((size_t)nb * 5 + v) * n3 + qn];
       Aw[v] = sA[v * n3 + qo];
-      Ax[v] = -sjn * Utb[((size_t)nb * 5 + v) * n3 + qn];
+      Ax[v] = bnd ? 0.0 : -sjn * Utb[((size_t)nb * 5 + v) * n3 + qn];
     }
     // normal along +xi_dn scaled by s-hat: this element's Ja^dn at the face node
     const double nt[3] = {JA(dn, 0, qo), JA(dn, 1, qo), JA(dn, 2, qo)};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    if (bnd) {
+      // symmetry plane: the outer state is the mirrored own trace
+      const double mn = 2.0 * (Uw[1] * nh[0] + Uw[2] * nh[1] + Uw[3] * nh[2]);
+      Ux[0] = Uw[0]; Ux[4] = Uw[4];
+      Ux[1] = Uw[1] - mn * nh[0]; Ux[2] = Uw[2] - mn * nh[1]; Ux[3] = Uw[3] - mn * nh[2];
+    }
     double Fb[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fb[v] = lh * (plus ? (Aw[v] - Ax[v]) : (Ax[v] - Aw[v]));
@@ -161,6 +173,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     dgf::riemann_adj_prim(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, aM, aS);
     dgf::PA pc = plus ? aM : aS;
     const dgf::P Po = plus ? PM : PS;
+    if (bnd) {
+      // the outer argument is the mirror image of the own trace: its adjoint comes back mirrored
+      const dgf::PA ao = plus ? aS : aM;
+      const double an = 2.0 * (ao.u * nh[0] + ao.v * nh[1] + ao.w * nh[2]);
+      pc.r += ao.r; pc.p += ao.p;
+      pc.u += ao.u - an * nh[0]; pc.v += ao.v - an * nh[1]; pc.w += ao.w - an * nh[2];
+    }
     if (NS) {
       // F contains -1/2 Fv(U_own, G_own) . nt; its momentum part along the face's direction is
       // the contravariant viscous flux of that direction from the lifting (G holds those)
@@ -171,6 +190,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       double Fvb[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
+      if (bnd) {
+        // symmetry plane: the term is -(g.nh) nh of the own momentum flux g, no energy part
+        const double fn_ = Fb[1] * nh[0] + Fb[2] * nh[1] + Fb[3] * nh[2];
+        Fvb[0] = 0.0; Fvb[4] = 0.0;
+        Fvb[1] = -fn_ * nh[0]; Fvb[2] = -fn_ * nh[1]; Fvb[3] = -fn_ * nh[2];
+      }
       dgf::visc_flux_adj_tn(Po, tn, ph.mu, ph.kappa, nt, Fvb, pc, gbo);
 #pragma unroll
       for (int c = 0; c < 12; ++c) sF[(5 + c) * 6 * n2 + p] = gbo[c];
@@ -417,17 +442,33 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
     if (id != 0 && id != N) continue;
     const int s = 2 * dir + (id == N ? 1 : 0);
     const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
-    const int nb = g.nbr[(size_t)e * 6 + s];
     // the neighbour's term at its matching face point (structured: side s ^ 1, same index)
-    const double *pf;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
-      pf = Pf + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
-    } else {
-      pf = Pf + ((size_t)nb * 6 + (s ^ 1)) * 4 * n2 + a + n * b;
-    }
+      if (f.bnd) {
+        // symmetry plane: the outer W is the mirrored own W, so the element's own face term
+        // comes back with its velocity part mirrored
+        const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
+        const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + a + n * b;
+        const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
+        const double il = 1.0 / sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        const double nh[3] = {nt[0] * il, nt[1] * il, nt[2] * il};
+        const double w0 = pf[0], w1 = pf[n2], w2 = pf[2 * n2];
+        const double wn = 2.0 * (w0 * nh[0] + w1 * nh[1] + w2 * nh[2]);
+        Wb[0] += w0 - wn * nh[0]; Wb[1] += w1 - wn * nh[1]; Wb[2] += w2 - wn * nh[2];
+        Wb[3] += pf[3 * n2];
+      } else {
+        const int nb = g.nbr[(size_t)e * 6 + s];
+        const double *pf = Pf + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Wb[v] += pf[v * n2];
+        for (int v = 0; v < 4; ++v) Wb[v] += pf[v * n2];
+      }
+    } else {
+      const int nb = g.nbr[(size_t)e * 6 + s];
+      const double *pf = Pf + ((size_t)nb * 6 + (s ^ 1)) * 4 * n2 + a + n * b;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wb[v] += pf[v * n2];
+    }
     face = true;
   }
   if (!face && !upd) return;

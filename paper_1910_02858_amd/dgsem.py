@@ -395,21 +395,28 @@ class Batch:
 
 
 def build_solver(wl, K1: Optional[int] = None, stream=None, curved: Optional[bool] = None,
-                 rotate_seed: Optional[int] = None):
+                 rotate_seed: Optional[int] = None, symmetry_box: bool = False):
     """Mesh, solver and initial state of workload ``wl`` using the library's own LGL nodes.
 
     With ``rotate_seed`` every element's reference axes are rotated by a seeded proper rotation
-    of the cube (same physical mesh; faces meet on other sides and in all orientations)."""
+    of the cube (same physical mesh; faces meet on other sides and in all orientations).  With
+    ``symmetry_box`` the mesh covers [0, pi]^3 (the Taylor-Green vortex's symmetry octant) and its
+    six outer faces are symmetry planes instead of periodic."""
     from . import inputs
     import torch
     k = wl.K1 if K1 is None else K1
     cv = wl.curved if curved is None else curved
     lgl, _ = nodes(wl.N, "lgl")
-    X = inputs.lattice_points(lgl, k, k, k)
+    if symmetry_box:
+        X = inputs.lattice_points(lgl, k, k, k, box=(np.pi, np.pi, np.pi))
+        nbr, side, flip = inputs.box_lattice(k, k, k)
+    else:
+        X = inputs.lattice_points(lgl, k, k, k)
+        nbr, side, flip = inputs.periodic_lattice(k, k, k)
     xgeo = inputs.warp_sine(X) if cv else X
-    nbr, side, flip = inputs.periodic_lattice(k, k, k)
-    if rotate_seed is not None:
-        rot = np.random.default_rng(rotate_seed).integers(0, 24, k ** 3)
+    if rotate_seed is not None or symmetry_box:
+        rot = (np.random.default_rng(rotate_seed).integers(0, 24, k ** 3) if rotate_seed is not None
+               else np.zeros(k ** 3, np.int64))
         xgeo, nbr, side, flip, _ = inputs.rotate_elements(xgeo, nbr, side, flip, wl.N, rot)
         del X
         S = DGSolver.from_workload(wl, xgeo, nbr, side, flip=flip, stream=stream)

@@ -10,7 +10,7 @@ reproduce that member's one-mesh stage bit for bit.  The vector-Jacobian product
 mesh: J^T w against the oracle's assembled tangent Jacobian element by element (1e-12), dot-
 product tests <J^T w, v> = <w, J v> with the oracle's tangent for one operator evaluation
 (1e-12) and an RK rollout (1e-10), and against the library's own lattice result carried over;
-they must refuse a mesh with boundary sides.
+the same element-wise, dot-product and rollout checks on boxes with symmetry planes.
 
 Symmetry-plane boundaries: a curved box [0, pi]^3 whose six outer faces are symmetry planes
 (with and without rotated element axes) against the oracle on the same mesh (1e-12, 1e-10 after
@@ -210,14 +210,66 @@ def test_rollout_dot_product_rotated(dg, orc):
     assert abs(lhs - rhs) <= 1e-10 * scale
 
 
-def test_vjp_refuses_boundaries(dg, orc):
-    wl = inputs.workload(5)
-    _, (X, nbr, side, flip), U = box_problem(orc, wl, 2)
+@pytest.mark.parametrize("name,kw,seed", [(t[0], t[1], s) for t in VJP_TINY for s in (None, 8)],
+                         ids=[f"{t[0]}_{'rotated' if s else 'lattice'}" for t in VJP_TINY for s in (None, 8)])
+def test_vjp_box_elementwise_against_oracle_jacobian(dg, orc, name, kw, seed):
+    """Symmetry planes on every outer face of a 2x2x2 curved box (also with rotated axes)."""
+    print(f"case {name} {seed}", flush=True)
+    wl = inputs.workload(2, N=2, mach=0.3, **kw)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 2, seed=seed, perturb=2e-2)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
     S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
-    Ug = to_gpu(U)
-    with pytest.raises(dg.DGError) as ei:
-        S.rhs_vjp(Ug, Ug.clone())
-    assert ei.value.code == -3
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name}: max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("N,vf", [(5, "kep"), (7, "ec")])
+def test_vjp_box_dot_product(dg, orc, N, vf):
+    wl = inputs.workload(5, N=N, volflux=vf)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, 3, seed=N, perturb=1e-2)
+    sc = orc.Scheme.of(wl)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    rng = np.random.default_rng(60 + N)
+    for v in inputs.random_directions(U, 70 + N, 2):
+        w = rng.standard_normal(U.shape)
+        _, Jv = M.rhs_jvp(sc, U, v)
+        JTw = S.rhs_vjp(to_gpu(U), to_gpu(w)).cpu().numpy()
+        lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
+        scale = float(np.sum(np.abs(JTw * v)))
+        print(f"N={N} {vf}: <J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def test_rollout_dot_product_box(dg, orc):
+    wl = inputs.workload(5)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 3, seed=9, perturb=1e-3)
+    sc = orc.Scheme.of(wl)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    dt = M.timestep(sc, U0, 0.9, 0.9)
+    steps = 4
+    v = inputs.random_directions(U0, 6, 1)[0]
+    _, vT = M.rk_jvp(sc, U0, v, steps, dt)
+    w = np.random.default_rng(7).standard_normal(U0.shape)
+    _, stage_inputs = dg._rollout_forward(S, to_gpu(U0), steps, dt, keep_stage_inputs=True)
+    Ubar = dg._rollout_backward(S, stage_inputs, to_gpu(w), dt).cpu().numpy()
+    lhs, rhs = float(np.sum(Ubar * v)), float(np.sum(w * vT))
+    scale = float(np.sum(np.abs(Ubar * v)))
+    print(f"<Ubar_0, v_0> = {lhs:.15e}  <w, v_T> = {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-10 * scale
 
 
 def box_problem(orc, wl, m, seed=None, curved=True, perturb=1e-2):
