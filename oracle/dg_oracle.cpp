@@ -32,10 +32,12 @@
 //   * conforming faces may meet in any of the eight orientations of a square: the
 //     neighbour's face point matching face point (a,b) is found by an optional swap of
 //     (a,b) followed by optional reversals of the first and of the second index.
-//   * a side without neighbour (neighbour index < 0) is a symmetry plane (slip wall): its
-//     outer state is the mirror image of the inner one across the face (velocity reflected),
-//     its outer gradient the mirror image of the inner gradient (velocity components and
-//     derivative direction reflected); the side is its own master.
+//   * a side without neighbour (neighbour index < 0) is a boundary of the kind stored in its
+//     neighbour-side entry, and its own master.  Kind 0, symmetry plane (slip wall): the outer
+//     state is the mirror image of the inner one across the face (velocity reflected), the
+//     outer gradient the mirror image of the inner gradient (velocity components and
+//     derivative direction reflected).  Kind 1, given state: the outer state is a fixed
+//     state U_b of the mesh, and the outer viscous flux equals the inner one.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
@@ -227,6 +229,7 @@ struct Mesh {
   std::vector<int32_t> nbr;        // [e][6]
   std::vector<int8_t> nside;       // [e][6]
   std::vector<int8_t> flip;        // [e][6] orientation code of the face map to the neighbour
+  double ub[5] = {0, 0, 0, 0, 0};  // outer state of boundary sides of kind 1
   std::vector<double> Ja;          // [e][i*3+d][node]: Ja^i_d
   std::vector<double> J;           // [e][node]
   std::vector<double> xs;          // [e][3][node] solution-node positions
@@ -718,6 +721,12 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
           trace(M, wk.W.data(), 4, e, s, a, b, WL);
           if (nb >= 0) {
             trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a2, b2, WR);
+          } else if (M.nside[e * 6 + s] == 1) {
+            T Ub[5];
+            for (int v = 0; v < 5; ++v) Ub[v] = T(M.ub[v]);
+            Prim<T> Pb = prim(Ub, S.gamma);
+            for (int d = 0; d < 3; ++d) WR[d] = Pb.u[d];
+            WR[3] = Pb.p / (Pb.rho * T(S.R));
           } else {
             double nh[3];
             unit_normal(nt, n2, a + n * b, nh);
@@ -833,8 +842,11 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
           T UM[5], US[5];
           trace(M, U, 5, em, sm, am, bm, UM);
+          const bool given = nb < 0 && ns_ == 1;  // boundary with a given outer state
           if (nb >= 0)
             trace(M, U, 5, es, ss, as, bs, US);
+          else if (given)
+            for (int v = 0; v < 5; ++v) US[v] = T(M.ub[v]);
           else
             mirror_state(UM, nh, US);
           T F[5];
@@ -845,11 +857,14 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
             trace(M, wk.G.data(), 12, em, sm, am, bm, gM);
             if (nb >= 0)
               trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
-            else
+            else if (!given)
               mirror_grad(gM, nh, gS);
             Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);
             viscous_flux(PM, gM, S, nt, FvM);
-            viscous_flux(PS, gS, S, nt, FvS);
+            if (given)
+              for (int v = 0; v < 5; ++v) FvS[v] = FvM[v];  // outer viscous flux = inner
+            else
+              viscous_flux(PS, gS, S, nt, FvS);
             for (int v = 0; v < 5; ++v) F[v] = F[v] - T(0.5) * (FvM[v] + FvS[v]);
           }
           double sgn = mst ? 1.0 : -1.0;   // outward flux of this element
@@ -924,6 +939,11 @@ orc_handle* orc_create(int K, int N, int type, const double* xgeo, const int32_t
 }
 
 void orc_destroy(orc_handle* h) { delete h; }
+
+// outer state of boundary sides of kind 1 (given state)
+void orc_set_boundary_state(orc_handle* h, const double* ub) {
+  for (int v = 0; v < 5; ++v) h->M.ub[v] = ub[v];
+}
 
 // copies of the derived geometry: Ja [K][9][n3], J [K][n3], x [K][3][n3], face normals [K][6][3][n2]
 void orc_geometry(const orc_handle* h, double* Ja, double* J, double* xs, double* fn) {

@@ -47,6 +47,7 @@ def lib():
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8, _I8]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_set_boundary_state.argtypes = [ctypes.c_void_p, _D]
         L.orc_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
         sch = [ctypes.c_int] * 4 + [ctypes.c_double] * 4
         L.orc_rhs.argtypes = [ctypes.c_void_p] + sch + [_D, _D]
@@ -137,6 +138,11 @@ class OracleMesh:
         if not h:
             raise ValueError("oracle: invalid mesh (J <= 0)")
         self.h = ctypes.c_void_p(h)
+
+    def set_boundary_state(self, ub):
+        """Outer state (rho, m1, m2, m3, E) of boundary sides of kind 1 (given state)."""
+        ub = _c(ub)
+        lib().orc_set_boundary_state(self.h, _p(ub))
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:

@@ -58,11 +58,11 @@ def periodic_lattice(kx: int, ky: int, kz: int):
     return nbr, side, flip
 
 
-def box_lattice(kx: int, ky: int, kz: int):
-    """Face connectivity of a ``kx*ky*kz`` lattice whose six outer faces are symmetry planes.
+def box_lattice(kx: int, ky: int, kz: int, kind: int = 0):
+    """Face connectivity of a ``kx*ky*kz`` lattice whose six outer faces are boundaries.
 
     Same numbering as :func:`periodic_lattice`; a side on the outer boundary has neighbour
-    ``-1`` and boundary kind 0 (symmetry plane) in ``nbr_side``.
+    ``-1`` and the boundary kind in ``nbr_side`` (0 symmetry plane, 1 given outer state).
     """
     nbr, side, flip = periodic_lattice(kx, ky, kz)
     ez, ey, ex = np.meshgrid(np.arange(kz), np.arange(ky), np.arange(kx), indexing="ij")
@@ -71,7 +71,7 @@ def box_lattice(kx: int, ky: int, kz: int):
                                     (ez, kz, True), (ez, kz, False)]):
         at = (c == 0) if lo else (c == k - 1)
         nbr[at, s] = -1
-        side[at, s] = 0
+        side[at, s] = kind
     return nbr, side, flip
 
 

@@ -16,6 +16,12 @@ alone with six symmetry planes; with the mirrored outer state the mass and energ
 a symmetry plane vanish, so mass and energy are conserved for any state; a fluid at rest stays
 at rest.  (Mutants of the boundary -- outer state not reflected, outer gradient not reflected --
 each fail one of these: the conservation check catches both, the octant check the second.)
+
+Given-state boundaries: a uniform flow equal to the given state is preserved on a curved box
+(every scheme, Euler and Navier-Stokes); for the Euler equations a periodic lattice whose outer
+shell of elements holds exactly the given state reproduces, on its inner elements, the box of
+those elements with given-state boundaries.  The viscous outer flux of a given-state side (equal
+to the inner one) is a reading with no such pin beyond the uniform flow: parity only.
 """
 import math
 
@@ -200,4 +206,45 @@ def test_rotated_box_with_symmetry_planes_equals_periodic_octant(orc):
     sc = orc.Scheme("ns", "split", "kep", "roe", mu=1e-2)
     ref = carry(Mf.rhs(sc, U)[octant], nm)
     got = Mr.rhs(sc, carry(U[octant], nm))
+    assert np.all(np.abs(got - ref).max(axis=(0, 2)) <= 1e-12 * np.abs(ref).max(axis=(0, 2)))
+
+
+@pytest.mark.parametrize("eqn,form,vf,rs,nodes", OCTANT_SCHEMES)
+def test_given_state_preserves_uniform_flow(orc, eqn, form, vf, rs, nodes):
+    N, m = 4, 3
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3))
+    nbo, sdo, _ = inputs.box_lattice(m, m, m, kind=1)
+    M = orc.OracleMesh(X, nbo, sdo, N, nodes)
+    U0 = inputs.constant_state(M.K, M.n3)          # moving: u = (0.3, -0.2, 0.1)
+    M.set_boundary_state(U0[0, :, 0])
+    sc = orc.Scheme(eqn, form, vf, rs, mu=1e-2)
+    h = math.pi / m
+    assert np.abs(M.rhs(sc, U0)).max() < 1e-12 * np.abs(U0).max() * 2 * (N + 1) ** 2 / h
+
+
+@pytest.mark.parametrize("form,vf,rs,nodes", [("split", "ec", "roe", "lgl"), ("split", "kep", "volflux_roe", "lgl"),
+                                              ("weak", "central", "llf", "lg"), ("strong", "central", "roe", "lgl")])
+def test_given_state_equals_constant_shell(orc, form, vf, rs, nodes):
+    """Euler: inner 3^3 elements of a periodic 5^3 lattice whose outer shell holds the given
+    state exactly against the 3^3 box with given-state boundaries."""
+    N, k = 3, 5
+    lgl = orc.basis(N, "lgl")["x"]
+    h = 2 * math.pi / k
+    Xf = inputs.warp_sine(inputs.lattice_points(lgl, k, k, k), 0.05)
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    Mf = orc.OracleMesh(Xf, nbr, side, N, nodes)
+    e3 = np.arange(k ** 3)
+    ex, ey, ez = e3 % k, (e3 // k) % k, e3 // (k * k)
+    inner = (ex > 0) & (ex < k - 1) & (ey > 0) & (ey < k - 1) & (ez > 0) & (ez < k - 1)
+    ub = inputs.constant_state(1, 1)[0, :, 0]
+    U = np.empty((k ** 3, 5, Mf.n3))
+    U[:] = ub[None, :, None]
+    U[inner] = inputs.random_perturbation(inputs.taylor_green(Mf.points()[inner], 1.0, 0.3), 3, 1e-2)
+    nbo, sdo, _ = inputs.box_lattice(k - 2, k - 2, k - 2, kind=1)
+    Mb = orc.OracleMesh(Xf[inner], nbo, sdo, N, nodes)
+    Mb.set_boundary_state(ub)
+    sc = orc.Scheme("euler", form, vf, rs)
+    ref = Mf.rhs(sc, U)[inner]
+    got = Mb.rhs(sc, U[inner])
     assert np.all(np.abs(got - ref).max(axis=(0, 2)) <= 1e-12 * np.abs(ref).max(axis=(0, 2)))
