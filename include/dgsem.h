@@ -56,11 +56,13 @@ enum { DG_VF_KEP = 0, DG_VF_EC = 1, DG_VF_CENTRAL = 2 };
 /* convective surface flux (Sec. 2.2.3 names LLF and Roe; Sec. 3.3 allows the volume's
  * two-point flux, optionally with Roe-type dissipation) */
 enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
-/* kind of a boundary side (nbr_elem = -1; the kind goes in nbr_side): a symmetry plane or slip
- * wall, whose outer state and gradient are the mirror images of the inner ones across the face
- * (velocity and, for the gradient, also the derivative direction reflected; Sec. 2 lists slip
- * walls among the boundary conditions) */
-enum { DG_BC_SYMMETRY = 0 };
+/* kind of a boundary side (nbr_elem = -1; the kind goes in nbr_side).  DG_BC_SYMMETRY: a
+ * symmetry plane or slip wall, whose outer state and gradient are the mirror images of the inner
+ * ones across the face (velocity and, for the gradient, also the derivative direction reflected;
+ * Sec. 2 lists slip walls among the boundary conditions).  DG_BC_STATE: a given outer state U_b
+ * (far field, inflow; set with dg_set_boundary_state), whose outer viscous flux is taken equal
+ * to the inner one. */
+enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
@@ -86,7 +88,7 @@ typedef struct {
  * element); normals and surface elements are the master's; a boundary side is its own master.
  * A mesh without boundary sides whose every face meets the opposite side with code 0 is
  * structured.  Errors:
- * a boundary kind other than DG_BC_SYMMETRY is DG_ERR_UNSUPPORTED; a neighbour index out of
+ * a boundary kind other than DG_BC_SYMMETRY or DG_BC_STATE is DG_ERR_UNSUPPORTED; a neighbour index out of
  * range (other than -1) is DG_ERR_MESH. */
 
 typedef struct {
@@ -108,7 +110,7 @@ int dg_rk_coefficients(double *a, double *b, double *c);
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
  * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
- * symmetry-plane boundaries; see dg_mesh).  hip_stream is a
+ * symmetry-plane and given-state boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
@@ -122,6 +124,13 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
 
 /* Change the stream later calls are ordered on. */
 int dg_set_stream(dg_handle *h, void *hip_stream);
+
+/* Outer state U_b = (rho, rho u, rho v, rho w, E) of the DG_BC_STATE sides (host array of 5).
+ * Must be called before the first operator, stage or vector-Jacobian call on a mesh that has
+ * such sides (those return DG_ERR_ARG until then) and before the handle joins a batch; may be
+ * called again to change the state.  DG_ERR_ARG if rho or the pressure is not positive or a
+ * value is not finite.  Synchronous (host only). */
+int dg_set_boundary_state(dg_handle *h, const double ub[5]);
 
 /* U_t = L(U) (eq. semiDiscrete / semiDiscreteStrong / semiDiscreteSplit, BR1 lifting for
  * Navier-Stokes).  U, Ut: device [K][5][n^3]; Ut is overwritten; U and Ut must differ. */

@@ -374,15 +374,15 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) return DG_ERR_ARG;
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
-  // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side: only
-  // DG_BC_SYMMETRY, orientation 0) or has a neighbour that names it back, on the side and with
+  // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side:
+  // DG_BC_SYMMETRY or DG_BC_STATE, orientation 0) or has a neighbour that names it back, on the side and with
   // the inverse orientation it names
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
       const int o = mesh->flip ? mesh->flip[q] : 0;
       if (nb == -1) {
-        if (ns != DG_BC_SYMMETRY) return DG_ERR_UNSUPPORTED;
+        if (ns != DG_BC_SYMMETRY && ns != DG_BC_STATE) return DG_ERR_UNSUPPORTED;
         if (o != 0) return DG_ERR_MESH;
         continue;
       }
@@ -437,7 +437,15 @@ template <class T> int dev_alloc(T **p, size_t count) {
 }
 
 // lifting of U: out 0 gradients into G, 1 contravariant viscous fluxes into Fv, 2 both
+// the kernels read the given outer state of DG_BC_STATE sides from the handle's physics
+int state_ready(dg_handle *h) {
+  if (h->needs_state && !h->state_set)
+    return fail(h, DG_ERR_ARG, "the mesh has given-state boundary sides: call dg_set_boundary_state first");
+  return DG_OK;
+}
+
 int lift_dispatch(dg_handle *h, const double *U, int out, double *G, double *Fv) {
+  if (int rc = state_ready(h)) return rc;
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
   switch (h->N) {
@@ -451,6 +459,7 @@ int lift_dispatch(dg_handle *h, const double *U, int out, double *G, double *Fv)
 
 int main_dispatch(dg_handle *h, const double *U, const double *G, double *out, double *R, double a, double b,
                   double dt, int mode) {
+  if (int rc = state_ready(h)) return rc;
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
   switch (h->N) {
@@ -597,7 +606,10 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (rc) { delete h; return rc; }
   const std::vector<uint8_t> fc = face_codes(mesh);
   for (int q = 0; q < 6 * K; ++q)
-    if (mesh->nbr_elem[q] < 0) h->has_boundary = true;
+    if (mesh->nbr_elem[q] < 0) {
+      h->has_boundary = true;
+      if (mesh->nbr_side[q] == DG_BC_STATE) h->needs_state = true;
+    }
   const std::vector<double> &sJ = G.sJ;
   h->x_nodes.swap(G.xs);
   const bool ns = sc->eqn == DG_NAVIER_STOKES;
@@ -645,6 +657,17 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
 int dg_set_stream(dg_handle *h, void *stream) {
   if (!h) return DG_ERR_ARG;
   h->stream = (hipStream_t)stream;
+  return DG_OK;
+}
+
+int dg_set_boundary_state(dg_handle *h, const double ub[5]) {
+  if (!h || !ub) return DG_ERR_ARG;
+  for (int v = 0; v < 5; ++v)
+    if (!std::isfinite(ub[v])) return fail(h, DG_ERR_ARG, "boundary state is not finite");
+  const double p = (h->sc.gamma - 1.0) * (ub[4] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2] + ub[3] * ub[3]) / ub[0]);
+  if (!(ub[0] > 0.0) || !(p > 0.0)) return fail(h, DG_ERR_ARG, "boundary state needs positive density and pressure");
+  for (int v = 0; v < 5; ++v) h->ph.ub[v] = ub[v];
+  h->state_set = true;
   return DG_OK;
 }
 
@@ -771,6 +794,7 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
+  if (int rc = state_ready(h)) return rc;
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
   if (ns && !h->d_Pf) {
     int rc = dev_alloc(&h->d_Pf, (size_t)h->K * 24 * h->n * h->n);

@@ -39,6 +39,7 @@ struct Geo {
 struct Phys {
   double gamma, R, mu, Pr, kappa;  // kappa = mu cp / Pr
   int vf, rs;
+  double ub[5];                    // outer state of given-state boundary sides (conservative)
 };
 
 // Kernel launch entry points, one explicit instantiation per degree.
@@ -106,17 +107,19 @@ __host__ __device__ inline int xcd_grid(int K) { return 8 * ((K + 7) / 8); }
 struct NbFace {
   int dn, a, b;
   bool plus, master, bnd;
+  int kind;  // boundary kind (DG_BC_SYMMETRY, DG_BC_STATE) of a boundary side
 };
 template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo &g, int e, int s, int a, int b) {
   NbFace f;
   f.bnd = false;
+  f.kind = 0;
   if (!GEN || !g.fc) {
     f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = s & 1;
     return f;
   }
   const int c = g.fc[(size_t)e * 6 + s];
   if (c & 128) {
-    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = true; f.bnd = true;
+    f.dn = s >> 1; f.a = a; f.b = b; f.plus = !(s & 1); f.master = true; f.bnd = true; f.kind = c & 7;
     return f;
   }
   const int ns = c & 7, o = (c >> 3) & 7;
@@ -152,7 +155,9 @@ struct dg_handle {
   double *d_Ja = nullptr, *d_sJ = nullptr, *d_fn = nullptr;
   int32_t *d_nbr = nullptr;
   uint8_t *d_fc = nullptr;      // face codes [K][6], only on meshes that are not structured
-  bool has_boundary = false;    // some side has no neighbour (symmetry plane)
+  bool has_boundary = false;    // some side has no neighbour
+  bool needs_state = false;     // some boundary side takes the given outer state
+  bool state_set = false;       // dg_set_boundary_state has been called
   dg::Tab *d_tab = nullptr;
   double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
   double *d_Pf = nullptr;       // face terms of the transposed lifting [K][6][4][n^2] (first VJP)

@@ -345,7 +345,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         }
       }
     }
-    if (GEN && f.bnd) {
+    if (GEN && f.bnd && f.kind == DG_BC_STATE) {
+      // given outer state
+      grad_prim_to_W(ph.ub, gm1, ph.R, WR);
+    } else if (GEN && f.bnd) {
       // symmetry plane: the outer W is the inner one with the velocity reflected
       const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
       const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
@@ -582,7 +585,12 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    if (bnd) {
+    const bool given = bnd && f.kind == DG_BC_STATE;
+    if (given) {
+      // given outer state; its viscous flux is taken equal to the inner one below
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+    } else if (bnd) {
       // symmetry plane: mirror image of the inner state and gradients
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = Uw[v];
@@ -603,7 +611,12 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       double FvM[5], FvS[5];
       const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
       flux_v(PM, gM, ph, nt, FvM);
-      flux_v(PS, gS, ph, nt, FvS);
+      if (given) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) FvS[v] = FvM[v];
+      } else {
+        flux_v(PS, gS, ph, nt, FvS);
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (FvM[v] + FvS[v]);
     }
@@ -910,7 +923,13 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    if (bnd) mirror3(Ux + 1, nh);  // symmetry plane: mirror image of the inner state
+    const bool given = bnd && f.kind == DG_BC_STATE;
+    if (given) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state
+    } else if (bnd) {
+      mirror3(Ux + 1, nh);  // symmetry plane: mirror image of the inner state
+    }
     const double *UM = plus ? Uw : Ux, *US = plus ? Ux : Uw;
     double F[5];
     riemann_vf<VF>(ph, UM, US, nh, F);
@@ -921,7 +940,11 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       // contravariant flux of the face's direction (the normal metric of a conforming face is
       // continuous: the neighbour's Ja of its face direction is +-Ja^dn, + where one side is a
       // +xi side and the other a -xi side)
-      if (bnd) {
+      if (given) {
+        // given outer state: the outer viscous flux equals the inner one
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
+      } else if (bnd) {
         // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
         // mean keeps the normal part of the momentum flux
         const double gm = Ge[(dn * 4) * n3 + qo] * nh[0] + Ge[(dn * 4 + 1) * n3 + qo] * nh[1] +

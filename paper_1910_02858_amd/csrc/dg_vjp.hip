@@ -130,11 +130,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const bool plus = s & 1;
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
     int qn, nb;
-    bool bnd = false;
+    bool bnd = false, given = false;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
       bnd = f.bnd;
+      given = bnd && f.kind == DG_BC_STATE;
       nb = bnd ? e : g.nbr[(size_t)e * 6 + s];  // a boundary side reads nothing of a neighbour
     } else {
       qn = vline_node<n>(dn, a, b, plus ? 0 : N);
@@ -154,7 +155,10 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    if (bnd) {
+    if (given) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state, independent of U
+    } else if (bnd) {
       // symmetry plane: the outer state is the mirrored own trace
       const double mn = 2.0 * (Uw[1] * nh[0] + Uw[2] * nh[1] + Uw[3] * nh[2]);
       Ux[0] = Uw[0]; Ux[4] = Uw[4];
@@ -173,7 +177,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     dgf::riemann_adj_prim(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, aM, aS);
     dgf::PA pc = plus ? aM : aS;
     const dgf::P Po = plus ? PM : PS;
-    if (bnd) {
+    if (bnd && !given) {
       // the outer argument is the mirror image of the own trace: its adjoint comes back mirrored
       const dgf::PA ao = plus ? aS : aM;
       const double an = 2.0 * (ao.u * nh[0] + ao.v * nh[1] + ao.w * nh[2]);
@@ -190,7 +194,11 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
       double Fvb[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fvb[v] = -0.5 * Fb[v];
-      if (bnd) {
+      if (given) {
+        // given outer state: the term is -g, the whole own flux
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fvb[v] = -Fb[v];
+      } else if (bnd) {
         // symmetry plane: the term is -(g.nh) nh of the own momentum flux g, no energy part
         const double fn_ = Fb[1] * nh[0] + Fb[2] * nh[1] + Fb[3] * nh[2];
         Fvb[0] = 0.0; Fvb[4] = 0.0;
@@ -445,7 +453,9 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
     // the neighbour's term at its matching face point (structured: side s ^ 1, same index)
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
-      if (f.bnd) {
+      if (f.bnd && f.kind == DG_BC_STATE) {
+        // given outer state: W* depends on this element's W only through its own half
+      } else if (f.bnd) {
         // symmetry plane: the outer W is the mirrored own W, so the element's own face term
         // comes back with its velocity part mirrored
         const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;

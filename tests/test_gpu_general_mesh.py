@@ -12,6 +12,11 @@ product tests <J^T w, v> = <w, J v> with the oracle's tangent for one operator e
 (1e-12) and an RK rollout (1e-10), and against the library's own lattice result carried over;
 the same element-wise, dot-product and rollout checks on boxes with symmetry planes.
 
+Given-state boundaries: boxes whose outer faces take a given state (also with rotated axes)
+against the oracle (1e-12), a uniform flow equal to that state at rest in time, the operator
+refusing to run before the state is set, J^T w against the oracle's assembled Jacobian, and a
+batch with such a member bitwise equal to the one-mesh stage.
+
 Symmetry-plane boundaries: a curved box [0, pi]^3 whose six outer faces are symmetry planes
 (with and without rotated element axes) against the oracle on the same mesh (1e-12, 1e-10 after
 RK steps), the Taylor-Green octant against the library's own periodic result (1e-12), and a
@@ -272,19 +277,31 @@ def test_rollout_dot_product_box(dg, orc):
     assert abs(lhs - rhs) <= 1e-10 * scale
 
 
-def box_problem(orc, wl, m, seed=None, curved=True, perturb=1e-2):
+UB = np.array([1.1, 0.3, -0.2, 0.15, 60.0])  # given outer state (rho, m, E): Mach ~ 0.05
+
+
+def box_problem(orc, wl, m, seed=None, curved=True, perturb=1e-2, kind=0):
     lgl = orc.basis(wl.N, "lgl")["x"]
     X = inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3)
     X = inputs.warp_sine(X) if curved else X
-    nbr, side, flip = inputs.box_lattice(m, m, m)
+    nbr, side, flip = inputs.box_lattice(m, m, m, kind=kind)
     if seed is not None:
         rot = np.random.default_rng(seed).integers(0, 24, m ** 3)
         X, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, wl.N, rot)
     M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes, flip=flip)
+    if kind == 1:
+        M.set_boundary_state(UB)
     U = inputs.initial_state(wl, M.points() + 0.3)
     if perturb:
         U = inputs.random_perturbation(U, 4, perturb)
     return M, (X, nbr, side, flip), U
+
+
+def box_solver(dg, wl, X, nbr, side, flip, kind=0):
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    if kind == 1:
+        S.set_boundary_state(UB)
+    return S
 
 
 BOX_CASES = [
@@ -366,6 +383,108 @@ def test_batch_with_box_member(dg, orc):
     outs = [S.empty() for S in sols]
     Rs = [R.clone() for R in R0]
     B.rk_stage(Us, outs, Rs, a[3], b[3], dts)
+    torch.cuda.synchronize()
+    for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
+        assert torch.equal(o, ro), f"member {i} U_out differs"
+        assert torch.equal(Rb, rR), f"member {i} R differs"
+
+
+STATE_CASES = [
+    ("ns_split_kep_roe_lgl5", inputs.workload(2, N=5), 3, None),
+    ("ns_split_ec_roe_lgl7_rotated", inputs.workload(3), 2, 1),
+    ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 2),
+    ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+    ("euler_split_ec_volflux_roe_lgl3", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 4),
+]
+
+
+@pytest.mark.parametrize("name,wl,m,seed", STATE_CASES, ids=[c[0] for c in STATE_CASES])
+def test_rhs_parity_given_state_box(dg, orc, name, wl, m, seed):
+    print(f"case {name}", flush=True)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, m, seed, kind=1)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=1)
+    ref = M.rhs(orc.Scheme.of(wl), U)
+    got = S.rhs(to_gpu(U)).cpu().numpy()
+    ne, per = check_rhs(got, ref)
+    print(f"normwise {ne:.2e} per-variable {per}")
+
+
+def test_given_state_uniform_flow_and_unset_state(dg, orc):
+    wl = inputs.workload(3, N=4)
+    M, (X, nbr, side, flip), _ = box_problem(orc, wl, 3, seed=3, kind=1)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    U = to_gpu(np.broadcast_to(UB[None, :, None], (M.K, 5, M.n3)).copy())
+    with pytest.raises(dg.DGError) as ei:
+        S.rhs(U)
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError):
+        S.set_boundary_state(np.array([1.0, 0.0, 0.0, 0.0, -1.0]))  # negative pressure
+    S.set_boundary_state(UB)
+    Ut = S.rhs(U).cpu().numpy()
+    scale = np.abs(UB).max() * 2 * (wl.N + 1) ** 2 / (math.pi / 3)
+    print(f"max |U_t| {np.abs(Ut).max():.2e} of the flux scale {scale:.2e}")
+    assert np.abs(Ut).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("seed", [None, 8], ids=["lattice", "rotated"])
+def test_vjp_given_state_elementwise_against_oracle_jacobian(dg, orc, seed):
+    wl = inputs.workload(2, N=2, mach=0.3)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 2, seed=seed, perturb=2e-2, kind=1)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=1)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+def test_vjp_given_state_dot_product(dg, orc):
+    wl = inputs.workload(5, N=5)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, 3, seed=5, perturb=1e-2, kind=1)
+    sc = orc.Scheme.of(wl)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=1)
+    rng = np.random.default_rng(81)
+    for v in inputs.random_directions(U, 82, 2):
+        w = rng.standard_normal(U.shape)
+        _, Jv = M.rhs_jvp(sc, U, v)
+        JTw = S.rhs_vjp(to_gpu(U), to_gpu(w)).cpu().numpy()
+        lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
+        scale = float(np.sum(np.abs(JTw * v)))
+        print(f"<J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def test_batch_with_given_state_member(dg, orc):
+    import torch
+    wl = inputs.workload(2, N=4)
+    _, (X, nbr, side, flip), Ub = box_problem(orc, wl, 3, seed=6, kind=1)
+    _, (X0, nbr0, side0, flip0), U0 = box_problem(orc, wl, 3, seed=7, kind=0)
+    sols = [box_solver(dg, wl, X, nbr, side, flip, kind=1), box_solver(dg, wl, X0, nbr0, side0, flip0, kind=0)]
+    Us = [to_gpu(Ub), to_gpu(U0)]
+    a, b, _ = dg.rk_coefficients()
+    dts = [S.timestep(U) for S, U in zip(sols, Us)]
+    R0 = [torch.full_like(U, 1e-4) for U in Us]
+    ref = []
+    for S, U, R, dt in zip(sols, Us, R0, dts):
+        out, Rr = S.empty(), R.clone()
+        S.rk_stage(U, out, Rr, a[2], b[2], dt)
+        ref.append((out, Rr))
+    B = dg.Batch(sols)
+    outs = [S.empty() for S in sols]
+    Rs = [R.clone() for R in R0]
+    B.rk_stage(Us, outs, Rs, a[2], b[2], dts)
     torch.cuda.synchronize()
     for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
         assert torch.equal(o, ro), f"member {i} U_out differs"

@@ -95,7 +95,7 @@ def test_init_rejects_unsupported(dg):
     rc, h = _init(dg, X, nbr, side, 3, nodes="lg", form="split")  # split needs LGL
     assert rc == -3
     nb, sd = nbr.copy(), side.copy()
-    nb[0, 1], sd[0, 1] = -1, 1                     # a boundary of a kind that does not exist
+    nb[0, 1], sd[0, 1] = -1, 5                     # a boundary of a kind that does not exist
     rc, h = _init(dg, X, nb, sd, 3)
     assert rc == -3
 
@@ -188,6 +188,7 @@ def test_null_arguments(dg):
     assert L.dg_rk_step_vjp(None, None, None, None, None, 0.0) == -1
     assert L.dg_rk_steps_vjp(None, 2, None, None, None, None, 0.0) == -1
     assert L.dg_rk_stage_keep(None, None, None, None, 0.0, 0.0, 0.0, None) == -1
+    assert L.dg_set_boundary_state(None, None) == -1
     assert L.dg_nodes(0, 1, None, None) == -1
     b = ctypes.c_void_p()
     assert L.dg_batch_create(None, 0, ctypes.byref(b)) == -1 and not b.value
