@@ -230,7 +230,10 @@ const char *dg_last_error(const dg_handle *h);
  * have one entry per member, in the order given to dg_batch_create.
  *
  * dg_batch_create  -> DG_ERR_UNSUPPORTED if a member is not split/LGL or the schemes differ;
- *                     DG_ERR_ARG for NULL entries or a member listed twice.
+ *                     DG_ERR_ARG for NULL entries, a member listed twice, or a member with
+ *                     given-state boundary sides whose state is not set.  Members may have
+ *                     any mesh dg_init accepts; a later dg_set_boundary_state on a member is
+ *                     seen by the next batched call.
  * dg_batch_rk_stage: for every member i, dg_rk_stage(member i, U_in[i], U_out[i], R[i], a[i],
  *                     b_coef[i], dt[i]) (same semantics: a = 0 does not read R; the three
  *                     buffers must be distinct).  Asynchronous.  Descriptor tables of the
