@@ -37,7 +37,10 @@
 //     state is the mirror image of the inner one across the face (velocity reflected), the
 //     outer gradient the mirror image of the inner gradient (velocity components and
 //     derivative direction reflected).  Kind 1, given state: the outer state is a fixed
-//     state U_b of the mesh, and the outer viscous flux equals the inner one.
+//     state U_b of the mesh, and the outer viscous flux equals the inner one.  Kind 2, no-slip
+//     adiabatic wall: the outer state has the velocity reversed (density and energy kept), the
+//     outer gradient keeps the velocity gradient and mirrors the temperature gradient, so that
+//     the BR1 means give zero velocity, no work and no heat flux at the wall.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
@@ -640,6 +643,21 @@ template <class T> static void mirror_W(const T* W, const double* nh, T* G) {
 
 // mirror image of the gradients g[d*4+v] = dW_v/dx_d: h = P g P for the velocity block,
 // h = P g for the temperature column
+// no-slip adiabatic wall: outer state with the velocity reversed
+template <class T> static void wall_state(const T* U, T* G) {
+  G[0] = U[0];
+  for (int d = 0; d < 3; ++d) G[1 + d] = -U[1 + d];
+  G[4] = U[4];
+}
+
+// no-slip adiabatic wall: outer gradients, velocity gradient kept, temperature gradient mirrored
+template <class T> static void wall_grad(const T* g, const double* nh, T* h) {
+  for (int c = 0; c < 12; ++c) h[c] = g[c];
+  T gt[3] = {g[3], g[7], g[11]}, m[3];
+  reflect(gt, nh, m);
+  for (int d = 0; d < 3; ++d) h[d * 4 + 3] = m[d];
+}
+
 template <class T> static void mirror_grad(const T* g, const double* nh, T* h) {
   double P[3][3];
   for (int i = 0; i < 3; ++i)
@@ -721,6 +739,9 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
           trace(M, wk.W.data(), 4, e, s, a, b, WL);
           if (nb >= 0) {
             trace(M, wk.W.data(), 4, nb, M.nside[e * 6 + s], a2, b2, WR);
+          } else if (M.nside[e * 6 + s] == 2) {
+            for (int d = 0; d < 3; ++d) WR[d] = -WL[d];  // no-slip wall: velocity reversed
+            WR[3] = WL[3];
           } else if (M.nside[e * 6 + s] == 1) {
             T Ub[5];
             for (int v = 0; v < 5; ++v) Ub[v] = T(M.ub[v]);
@@ -843,8 +864,11 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           T UM[5], US[5];
           trace(M, U, 5, em, sm, am, bm, UM);
           const bool given = nb < 0 && ns_ == 1;  // boundary with a given outer state
+          const bool wall = nb < 0 && ns_ == 2;   // no-slip adiabatic wall
           if (nb >= 0)
             trace(M, U, 5, es, ss, as, bs, US);
+          else if (wall)
+            wall_state(UM, US);
           else if (given)
             for (int v = 0; v < 5; ++v) US[v] = T(M.ub[v]);
           else
@@ -857,6 +881,8 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
             trace(M, wk.G.data(), 12, em, sm, am, bm, gM);
             if (nb >= 0)
               trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
+            else if (wall)
+              wall_grad(gM, nh, gS);
             else if (!given)
               mirror_grad(gM, nh, gS);
             Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);

@@ -22,6 +22,11 @@ Given-state boundaries: a uniform flow equal to the given state is preserved on 
 shell of elements holds exactly the given state reproduces, on its inner elements, the box of
 those elements with given-state boundaries.  The viscous outer flux of a given-state side (equal
 to the inner one) is a reading with no such pin beyond the uniform flow: parity only.
+
+No-slip adiabatic walls: a fluid at rest stays at rest on a curved box, and for arbitrary states
+no mass and no energy cross a wall (the outer state reverses the velocity, so the mass flux and
+the wall's work vanish; the mirrored temperature gradient cancels the normal heat flux), while
+momentum changes.
 """
 import math
 
@@ -248,3 +253,26 @@ def test_given_state_equals_constant_shell(orc, form, vf, rs, nodes):
     ref = Mf.rhs(sc, U)[inner]
     got = Mb.rhs(sc, U[inner])
     assert np.all(np.abs(got - ref).max(axis=(0, 2)) <= 1e-12 * np.abs(ref).max(axis=(0, 2)))
+
+
+@pytest.mark.parametrize("eqn,form,vf,rs,nodes", OCTANT_SCHEMES)
+def test_no_slip_walls_rest_and_conservation(orc, eqn, form, vf, rs, nodes):
+    N, m = 4, 3
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3))
+    nbo, sdo, _ = inputs.box_lattice(m, m, m, kind=2)
+    rot = np.random.default_rng(12).integers(0, 24, m ** 3)
+    X, nbo, sdo, flo, _ = inputs.rotate_elements(X, nbo, sdo, np.zeros_like(sdo), N, rot)
+    M = orc.OracleMesh(X, nbo, sdo, N, nodes, flip=flo)
+    sc = orc.Scheme(eqn, form, vf, rs, mu=1e-2)
+    U0 = inputs.constant_state(M.K, M.n3, u=0.0, v=0.0, w=0.0)
+    h = math.pi / m
+    assert np.abs(M.rhs(sc, U0)).max() < 1e-12 * np.abs(U0).max() * 2 * (N + 1) ** 2 / h
+    U = inputs.random_perturbation(inputs.taylor_green(M.points() + 0.3, 1.0, 0.3), 5, 1e-2)
+    Ut = M.rhs(sc, U)
+    w = orc.basis(N, nodes)["w"]
+    wq = np.einsum("k,j,i->kji", w, w, w).ravel()[None, :] * M.geometry()["J"]
+    tot = np.einsum("eq,evq->v", wq, Ut)
+    scale = np.einsum("eq,evq->v", wq, np.abs(Ut))
+    assert np.all(np.abs(tot[[0, 4]]) < 1e-13 * scale[[0, 4]])
+    assert np.abs(tot[1:4]).max() > 1e-6 * scale[1:4].max()
