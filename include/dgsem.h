@@ -61,8 +61,10 @@ enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
  * ones across the face (velocity and, for the gradient, also the derivative direction reflected;
  * Sec. 2 lists slip walls among the boundary conditions).  DG_BC_STATE: a given outer state U_b
  * (far field, inflow; set with dg_set_boundary_state), whose outer viscous flux is taken equal
- * to the inner one. */
-enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1 };
+ * to the inner one.  DG_BC_WALL: a no-slip adiabatic wall (Sec. 2): outer state with the
+ * velocity reversed, outer gradient with the velocity gradient kept and the temperature
+ * gradient mirrored, so the surface means give zero velocity, no work and no heat flux. */
+enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
@@ -88,7 +90,7 @@ typedef struct {
  * element); normals and surface elements are the master's; a boundary side is its own master.
  * A mesh without boundary sides whose every face meets the opposite side with code 0 is
  * structured.  Errors:
- * a boundary kind other than DG_BC_SYMMETRY or DG_BC_STATE is DG_ERR_UNSUPPORTED; a neighbour index out of
+ * a boundary kind other than DG_BC_SYMMETRY, DG_BC_STATE or DG_BC_WALL is DG_ERR_UNSUPPORTED; a neighbour index out of
  * range (other than -1) is DG_ERR_MESH. */
 
 typedef struct {
@@ -110,7 +112,7 @@ int dg_rk_coefficients(double *a, double *b, double *c);
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
  * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
- * symmetry-plane and given-state boundaries; see dg_mesh).  hip_stream is a
+ * symmetry-plane, given-state and no-slip wall boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);

@@ -375,14 +375,14 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
   // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side:
-  // DG_BC_SYMMETRY or DG_BC_STATE, orientation 0) or has a neighbour that names it back, on the side and with
+  // DG_BC_SYMMETRY, DG_BC_STATE or DG_BC_WALL, orientation 0) or has a neighbour that names it back, on the side and with
   // the inverse orientation it names
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
       const int o = mesh->flip ? mesh->flip[q] : 0;
       if (nb == -1) {
-        if (ns != DG_BC_SYMMETRY && ns != DG_BC_STATE) return DG_ERR_UNSUPPORTED;
+        if (ns != DG_BC_SYMMETRY && ns != DG_BC_STATE && ns != DG_BC_WALL) return DG_ERR_UNSUPPORTED;
         if (o != 0) return DG_ERR_MESH;
         continue;
       }

@@ -348,6 +348,11 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     if (GEN && f.bnd && f.kind == DG_BC_STATE) {
       // given outer state
       grad_prim_to_W(ph.ub, gm1, ph.R, WR);
+    } else if (GEN && f.bnd && f.kind == DG_BC_WALL) {
+      // no-slip wall: velocity reversed, temperature kept
+#pragma unroll
+      for (int v = 0; v < 3; ++v) WR[v] = -WL[v];
+      WR[3] = WL[3];
     } else if (GEN && f.bnd) {
       // symmetry plane: the outer W is the inner one with the velocity reflected
       const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
@@ -590,6 +595,16 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       // given outer state; its viscous flux is taken equal to the inner one below
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+    } else if (bnd && f.kind == DG_BC_WALL) {
+      // no-slip wall: velocity reversed; velocity gradient kept, temperature gradient mirrored
+      Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gx[c] = gw[c];
+        double tg[3] = {gw[3], gw[7], gw[11]};
+        mirror3(tg, nh);
+        gx[3] = tg[0]; gx[7] = tg[1]; gx[11] = tg[2];
+      }
     } else if (bnd) {
       // symmetry plane: mirror image of the inner state and gradients
 #pragma unroll
@@ -924,9 +939,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
     const bool given = bnd && f.kind == DG_BC_STATE;
+    const bool wall = bnd && f.kind == DG_BC_WALL;
     if (given) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state
+    } else if (wall) {
+      Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3];  // no-slip wall: velocity reversed
     } else if (bnd) {
       mirror3(Ux + 1, nh);  // symmetry plane: mirror image of the inner state
     }
@@ -944,6 +962,11 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
         // given outer state: the outer viscous flux equals the inner one
 #pragma unroll
         for (int c = 0; c < 4; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
+      } else if (wall) {
+        // no-slip wall: the outer momentum flux equals the inner one, the outer energy flux is
+        // its negative (reversed velocity, mirrored heat flux), so the mean keeps the momentum
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
       } else if (bnd) {
         // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
         // mean keeps the normal part of the momentum flux

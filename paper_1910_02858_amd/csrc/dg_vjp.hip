@@ -130,12 +130,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const bool plus = s & 1;
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
     int qn, nb;
-    bool bnd = false, given = false;
+    bool bnd = false, given = false, wall = false;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
       bnd = f.bnd;
       given = bnd && f.kind == DG_BC_STATE;
+      wall = bnd && f.kind == DG_BC_WALL;
       nb = bnd ? e : g.nbr[(size_t)e * 6 + s];  // a boundary side reads nothing of a neighbour
     } else {
       qn = vline_node<n>(dn, a, b, plus ? 0 : N);
@@ -158,6 +159,9 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     if (given) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state, independent of U
+    } else if (wall) {
+      // no-slip wall: the outer state is the own trace with the velocity reversed
+      Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
     } else if (bnd) {
       // symmetry plane: the outer state is the mirrored own trace
       const double mn = 2.0 * (Uw[1] * nh[0] + Uw[2] * nh[1] + Uw[3] * nh[2]);
@@ -177,7 +181,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     dgf::riemann_adj_prim(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, aM, aS);
     dgf::PA pc = plus ? aM : aS;
     const dgf::P Po = plus ? PM : PS;
-    if (bnd && !given) {
+    if (wall) {
+      // the outer argument is the own trace with the velocity reversed
+      const dgf::PA ao = plus ? aS : aM;
+      pc.r += ao.r; pc.p += ao.p;
+      pc.u -= ao.u; pc.v -= ao.v; pc.w -= ao.w;
+    } else if (bnd && !given) {
       // the outer argument is the mirror image of the own trace: its adjoint comes back mirrored
       const dgf::PA ao = plus ? aS : aM;
       const double an = 2.0 * (ao.u * nh[0] + ao.v * nh[1] + ao.w * nh[2]);
@@ -198,6 +207,10 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
         // given outer state: the term is -g, the whole own flux
 #pragma unroll
         for (int v = 0; v < 5; ++v) Fvb[v] = -Fb[v];
+      } else if (wall) {
+        // no-slip wall: the term is -g for the momentum, nothing for the energy
+        Fvb[0] = 0.0; Fvb[4] = 0.0;
+        Fvb[1] = -Fb[1]; Fvb[2] = -Fb[2]; Fvb[3] = -Fb[3];
       } else if (bnd) {
         // symmetry plane: the term is -(g.nh) nh of the own momentum flux g, no energy part
         const double fn_ = Fb[1] * nh[0] + Fb[2] * nh[1] + Fb[3] * nh[2];
@@ -455,6 +468,11 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       if (f.bnd && f.kind == DG_BC_STATE) {
         // given outer state: W* depends on this element's W only through its own half
+      } else if (f.bnd && f.kind == DG_BC_WALL) {
+        // no-slip wall: the outer W is the own W with the velocity reversed
+        const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
+        Wb[0] -= pf[0]; Wb[1] -= pf[n2]; Wb[2] -= pf[2 * n2];
+        Wb[3] += pf[3 * n2];
       } else if (f.bnd) {
         // symmetry plane: the outer W is the mirrored own W, so the element's own face term
         // comes back with its velocity part mirrored

@@ -21,6 +21,11 @@ Symmetry-plane boundaries: a curved box [0, pi]^3 whose six outer faces are symm
 (with and without rotated element axes) against the oracle on the same mesh (1e-12, 1e-10 after
 RK steps), the Taylor-Green octant against the library's own periodic result (1e-12), and a
 batch with a boxed member bitwise equal to the one-mesh stages.
+
+No-slip adiabatic walls: boxes with walls on every outer face (also with rotated axes) against
+the oracle (1e-12), a fluid at rest staying at rest, 20 RK steps (1e-10), J^T w against the
+assembled Jacobian and dot products, and a batch with a walled member bitwise equal to the
+one-mesh stage.
 """
 import math
 
@@ -485,6 +490,102 @@ def test_batch_with_given_state_member(dg, orc):
     outs = [S.empty() for S in sols]
     Rs = [R.clone() for R in R0]
     B.rk_stage(Us, outs, Rs, a[2], b[2], dts)
+    torch.cuda.synchronize()
+    for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
+        assert torch.equal(o, ro), f"member {i} U_out differs"
+        assert torch.equal(Rb, rR), f"member {i} R differs"
+
+
+WALL_CASES = [
+    ("ns_split_kep_roe_lgl5_rotated", inputs.workload(2, N=5), 3, 11),
+    ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
+    ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 12),
+    ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+    ("euler_split_ec_volflux_roe_lgl3_rotated", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 13),
+]
+
+
+@pytest.mark.parametrize("name,wl,m,seed", WALL_CASES, ids=[c[0] for c in WALL_CASES])
+def test_rhs_parity_wall_box(dg, orc, name, wl, m, seed):
+    print(f"case {name}", flush=True)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, m, seed, kind=2)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=2)
+    ref = M.rhs(orc.Scheme.of(wl), U)
+    got = S.rhs(to_gpu(U)).cpu().numpy()
+    ne, per = check_rhs(got, ref)
+    print(f"normwise {ne:.2e} per-variable {per}")
+
+
+def test_wall_fluid_at_rest_and_rk_parity(dg, orc):
+    wl = inputs.workload(2, N=4)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, 3, seed=14, perturb=0, kind=2)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=2)
+    U0 = inputs.constant_state(M.K, M.n3, u=0.0, v=0.0, w=0.0)
+    Ut = S.rhs(to_gpu(U0)).cpu().numpy()
+    assert np.abs(Ut).max() < 1e-12 * np.abs(U0).max() * 2 * (wl.N + 1) ** 2 / (math.pi / 3)
+    sc = orc.Scheme.of(wl)
+    dt = M.timestep(sc, U, wl.cfl, wl.dfl)
+    ref = M.rk(sc, U, 20, dt)
+    got = S.steps(to_gpu(U), 20, dt).cpu().numpy()
+    err = rel_err(got, ref)
+    print(f"per-variable after 20 steps {err}")
+    assert np.all(err <= 1e-10), err
+
+
+@pytest.mark.parametrize("seed", [None, 8], ids=["lattice", "rotated"])
+def test_vjp_wall_elementwise_against_oracle_jacobian(dg, orc, seed):
+    wl = inputs.workload(2, N=2, mach=0.3)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 2, seed=seed, perturb=2e-2, kind=2)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=2)
+    rng = np.random.default_rng(6)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+def test_vjp_wall_dot_product_and_batch(dg, orc):
+    import torch
+    wl = inputs.workload(5, N=5)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, 3, seed=15, perturb=1e-2, kind=2)
+    sc = orc.Scheme.of(wl)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=2)
+    rng = np.random.default_rng(91)
+    for v in inputs.random_directions(U, 92, 2):
+        w = rng.standard_normal(U.shape)
+        _, Jv = M.rhs_jvp(sc, U, v)
+        JTw = S.rhs_vjp(to_gpu(U), to_gpu(w)).cpu().numpy()
+        lhs, rhs = float(np.sum(JTw * v)), float(np.sum(w * Jv))
+        scale = float(np.sum(np.abs(JTw * v)))
+        print(f"<J^T w, v> = {lhs:.15e}  <w, J v> = {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * scale
+    _, (X2, nbr2, side2, flip2), U2 = box_problem(orc, wl, 3, seed=16, kind=0)
+    sols = [S, box_solver(dg, wl, X2, nbr2, side2, flip2, kind=0)]
+    Us = [to_gpu(U), to_gpu(U2)]
+    a, b, _ = dg.rk_coefficients()
+    dts = [Si.timestep(Ui) for Si, Ui in zip(sols, Us)]
+    R0 = [torch.full_like(Ui, 1e-4) for Ui in Us]
+    ref = []
+    for Si, Ui, R, dt in zip(sols, Us, R0, dts):
+        out, Rr = Si.empty(), R.clone()
+        Si.rk_stage(Ui, out, Rr, a[4], b[4], dt)
+        ref.append((out, Rr))
+    B = dg.Batch(sols)
+    outs = [Si.empty() for Si in sols]
+    Rs = [R.clone() for R in R0]
+    B.rk_stage(Us, outs, Rs, a[4], b[4], dts)
     torch.cuda.synchronize()
     for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
         assert torch.equal(o, ro), f"member {i} U_out differs"
