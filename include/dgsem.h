@@ -117,6 +117,19 @@ int dg_rk_coefficients(double *a, double *b, double *c);
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
 
+/* Mesh preprocessing (Sec. 5.1: the element-to-side connectivity and face orientations a mesh
+ * file carries): derives nbr_elem, nbr_side and flip of a conforming hexahedral mesh from its
+ * element coordinates alone, in the conventions of dg_mesh.  xgeo is as in dg_mesh (HOST
+ * [K][3][(n_geo+1)^3]).  Two faces match when each corner of one lies within tol of a corner of
+ * the other (tol <= 0: 1e-8 of the smallest element extent); along every direction d with
+ * period[d] > 0 (period may be NULL) coordinates are compared modulo period[d], which joins the
+ * opposite faces of a periodic box.  Faces without a match become boundary sides (nbr_elem -1,
+ * nbr_side = bc_kind, flip 0).  Outputs are HOST [K][6] arrays owned by the caller.  Host only,
+ * synchronous; DG_ERR_ARG for NULL or non-finite input or an unknown bc_kind.  dg_init
+ * validates the result like any other connectivity. */
+int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
+                    int32_t *nbr_elem, int8_t *nbr_side, int8_t *flip);
+
 /* The setup dg_init performs, on the host only (no device memory is touched): metric terms
  * Ja [K][9][n^3] (Ja^i_d at i*3+d), J [K][n^3], outward face normals fn [K][6][3][n^2] and the
  * n x n matrices D and Dhat, all host arrays (any may be NULL).  All tables are computed in

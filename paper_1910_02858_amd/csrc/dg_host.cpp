@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "dg_internal.h"
@@ -657,6 +658,97 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
 int dg_set_stream(dg_handle *h, void *stream) {
   if (!h) return DG_ERR_ARG;
   h->stream = (hipStream_t)stream;
+  return DG_OK;
+}
+
+int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
+                    int32_t *nbr, int8_t *side, int8_t *flip) {
+  if (n_elems < 1 || n_geo < 1 || n_geo > NMAX || !xgeo || !nbr || !side || !flip) return DG_ERR_ARG;
+  if (bc_kind != DG_BC_SYMMETRY && bc_kind != DG_BC_STATE && bc_kind != DG_BC_WALL) return DG_ERR_ARG;
+  const int K = n_elems, N = n_geo, n = N + 1, n3 = n * n * n;
+  double L[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < 3 && period; ++d) {
+    if (!(period[d] >= 0.0) || !std::isfinite(period[d])) return DG_ERR_ARG;
+    L[d] = period[d];
+  }
+  // corners of every face, in face-point order (0,0), (N,0), (0,N), (N,N), shifted so that the
+  // face centroid lies in [0, L_d) along every periodic direction d
+  const int F = 6 * K;
+  std::vector<double> corner((size_t)F * 12), cen((size_t)F * 3);
+  double hmin = INFINITY;
+  for (int e = 0; e < K; ++e) {
+    const double *x = xgeo + (size_t)e * 3 * n3;
+    for (int d = 0; d < 3; ++d) {
+      double lo = x[d * n3], hi = lo;
+      for (int q = 0; q < n3; ++q) { lo = std::min(lo, x[d * n3 + q]); hi = std::max(hi, x[d * n3 + q]); }
+      if (!std::isfinite(lo) || !std::isfinite(hi)) return DG_ERR_ARG;
+      hmin = std::min(hmin, hi - lo);
+    }
+  }
+  if (!(tol > 0.0)) tol = 1e-8 * hmin;
+  for (int e = 0; e < K; ++e) {
+    const double *x = xgeo + (size_t)e * 3 * n3;
+    for (int s = 0; s < 6; ++s) {
+      const int f = e * 6 + s;
+      double c[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < 4; ++k) {
+        const int q = face_point_node(n, s, (k & 1) ? N : 0, (k & 2) ? N : 0);
+        for (int d = 0; d < 3; ++d) {
+          corner[(size_t)f * 12 + k * 3 + d] = x[d * n3 + q];
+          c[d] += 0.25 * x[d * n3 + q];
+        }
+      }
+      for (int d = 0; d < 3; ++d) {
+        double sh = 0.0;
+        if (L[d] > 0.0) sh = std::floor((c[d] + tol) / L[d]) * L[d];
+        for (int k = 0; k < 4; ++k) corner[(size_t)f * 12 + k * 3 + d] -= sh;
+        cen[(size_t)f * 3 + d] = c[d] - sh;
+      }
+    }
+  }
+  // faces binned by centroid on a grid of spacing 4 tol; a partner is searched in the 27 cells
+  // around a face's cell
+  const double hc = 4.0 * tol;
+  auto cell = [&](int f, int d) { return (long long)std::floor(cen[(size_t)f * 3 + d] / hc); };
+  auto key = [](long long i, long long j, long long k) {
+    return (uint64_t)(i * 73856093LL) ^ (uint64_t)(j * 19349663LL) ^ (uint64_t)(k * 83492791LL);
+  };
+  std::unordered_multimap<uint64_t, int> bins;
+  bins.reserve((size_t)F * 2);
+  for (int f = 0; f < F; ++f) bins.emplace(key(cell(f, 0), cell(f, 1), cell(f, 2)), f);
+  auto close = [&](int f, int k, int g, int l) {
+    for (int d = 0; d < 3; ++d)
+      if (!(std::fabs(corner[(size_t)f * 12 + k * 3 + d] - corner[(size_t)g * 12 + l * 3 + d]) <= tol)) return false;
+    return true;
+  };
+  for (int f = 0; f < F; ++f) {
+    int partner = -1, code = -1;
+    const long long ci = cell(f, 0), cj = cell(f, 1), ck = cell(f, 2);
+    for (int di = -1; di <= 1 && partner < 0; ++di)
+      for (int dj = -1; dj <= 1 && partner < 0; ++dj)
+        for (int dk = -1; dk <= 1 && partner < 0; ++dk) {
+          auto range = bins.equal_range(key(ci + di, cj + dj, ck + dk));
+          for (auto it = range.first; it != range.second && partner < 0; ++it) {
+            const int g = it->second;
+            if (g == f) continue;
+            // the orientation code whose face map sends every corner of f onto a corner of g
+            for (int o = 0; o < 8 && partner < 0; ++o) {
+              bool ok = true;
+              for (int k = 0; k < 4 && ok; ++k) {
+                int a2, b2;
+                face_mate(o, N, (k & 1) ? N : 0, (k & 2) ? N : 0, a2, b2);
+                ok = close(f, k, g, (a2 ? 1 : 0) + (b2 ? 2 : 0));
+              }
+              if (ok) { partner = g; code = o; }
+            }
+          }
+        }
+    if (partner < 0) {
+      nbr[f] = -1; side[f] = (int8_t)bc_kind; flip[f] = 0;
+    } else {
+      nbr[f] = partner / 6; side[f] = (int8_t)(partner % 6); flip[f] = (int8_t)code;
+    }
+  }
   return DG_OK;
 }
 

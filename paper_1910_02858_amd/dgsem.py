@@ -25,7 +25,7 @@ VF = {"kep": 0, "ec": 1, "central": 2}
 RS = {"llf": 0, "roe": 1, "volflux": 2, "volflux_roe": 3}
 
 EXPORTS = [
-    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
+    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_mesh_connect", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
@@ -69,6 +69,10 @@ def lib():
                               ctypes.POINTER(_VP)]
         L.dg_set_stream.argtypes = [_VP, _VP]
         L.dg_set_boundary_state.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
+        L.dg_mesh_connect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8),
+                                      ctypes.POINTER(ctypes.c_int8)]
         L.dg_rhs.argtypes = [_VP, _VP, _VP]
         L.dg_rk_stage.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.dg_rhs_vjp.argtypes = [_VP, _VP, _VP, _VP]
@@ -122,6 +126,25 @@ def rk_coefficients():
     a, b, c = np.zeros(5), np.zeros(5), np.zeros(5)
     lib().dg_rk_coefficients(_ptr(a), _ptr(b), _ptr(c))
     return a, b, c
+
+
+def mesh_connect(xgeo, N: int, period=None, tol: float = 0.0, bc_kind: int = 0):
+    """Connectivity (nbr_elem, nbr_side, flip) of a conforming hex mesh from its element
+    coordinates ``xgeo[K][3][(N+1)^3]`` (``dg_mesh_connect``); ``period`` joins the opposite faces
+    of a periodic box along the directions with a positive entry."""
+    xgeo = np.ascontiguousarray(xgeo, np.float64)
+    K = xgeo.shape[0]
+    nbr = np.zeros((K, 6), np.int32)
+    side = np.zeros((K, 6), np.int8)
+    flip = np.zeros((K, 6), np.int8)
+    per = None if period is None else np.ascontiguousarray(period, np.float64)
+    rc = lib().dg_mesh_connect(K, N, _ptr(xgeo), None if per is None else _ptr(per), tol, bc_kind,
+                               nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               side.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                               flip.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    if rc:
+        raise DGError(rc, "dg_mesh_connect")
+    return nbr, side, flip
 
 
 def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None):

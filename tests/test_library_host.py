@@ -27,7 +27,7 @@ def dg():
 def test_exports_match_header(dg):
     hdr = open(os.path.join(ROOT, "include", "dgsem.h")).read()
     declared = set(re.findall(r"\b(dg_[a-z_]+)\s*\(", hdr))
-    declared = {d for d in declared if not d.startswith("dg_mesh") and not d.startswith("dg_scheme")}
+    declared = {d for d in declared if d not in ("dg_mesh", "dg_scheme")}
     L = ctypes.CDLL(dg.LIB_PATH)
     missing = [d for d in sorted(declared) if not hasattr(L, d)]
     assert not missing, missing
@@ -228,3 +228,47 @@ def test_rollout_rejects_empty_schedules():
         dgsem.rollout(None, None, 0, 0.1)
     with pytest.raises(ValueError):
         dgsem.rollout(None, None, 5, 0.1, ckpt_every=0)
+
+
+@pytest.mark.parametrize("k,curved,seed", [(3, True, None), (3, True, 5), (2, False, 7), (1, False, 3)])
+def test_mesh_connect_periodic(dg, k, curved, seed):
+    """dg_mesh_connect rebuilds the connectivity of periodic lattices, also with every element's
+    axes rotated (any side, any of the eight orientations), from the coordinates alone."""
+    N = 3
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.lattice_points(lgl, k, k, k)
+    X = inputs.warp_sine(X) if curved else X
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    if seed is not None:
+        rot = np.random.default_rng(seed).integers(0, 24, k ** 3)
+        X, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, N, rot)
+    got = dg.mesh_connect(X, N, period=(2 * np.pi,) * 3)
+    for a, b in zip(got, (nbr, side, flip)):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_mesh_connect_box(dg, kind):
+    """Without periods the outer faces of a box become boundary sides of the requested kind."""
+    N, m = 2, 3
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.warp_sine(inputs.lattice_points(lgl, m, m, m, box=(np.pi,) * 3))
+    nbr, side, flip = inputs.box_lattice(m, m, m, kind=kind)
+    rot = np.random.default_rng(kind).integers(0, 24, m ** 3)
+    X, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, N, rot)
+    got = dg.mesh_connect(X, N, bc_kind=kind)
+    for a, b in zip(got, (nbr, side, flip)):
+        np.testing.assert_array_equal(a, b)
+    dg.host_geometry(X, *got[:2], N, "lgl", flip=got[2])  # accepted by dg_init's validation
+
+
+def test_mesh_connect_arguments(dg):
+    X = inputs.lattice_points(np.array([-1.0, 1.0]), 1, 1, 1)
+    with pytest.raises(dg.DGError):
+        dg.mesh_connect(X, 1, bc_kind=7)
+    with pytest.raises(dg.DGError):
+        dg.mesh_connect(X, 1, period=(-1.0, 0.0, 0.0))
+    nbr, side, flip = dg.mesh_connect(X, 1)                      # one element, no periods
+    assert np.all(nbr == -1) and np.all(side == 0) and np.all(flip == 0)
+    nbr, side, flip = dg.mesh_connect(X, 1, period=(2 * np.pi,) * 3)
+    assert np.all(nbr == 0) and np.array_equal(side[0], [1, 0, 3, 2, 5, 4])
