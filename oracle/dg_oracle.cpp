@@ -41,6 +41,10 @@
 //     adiabatic wall: the outer state has the velocity reversed (density and energy kept), the
 //     outer gradient keeps the velocity gradient and mirrors the temperature gradient, so that
 //     the BR1 means give zero velocity, no work and no heat flux at the wall.
+//   * parity unpinned: the outer viscous flux of a given-state side (taken equal to the inner
+//     one) and the tangential part of the surface flux at a no-slip wall (the Riemann
+//     solver's dissipation of the reversed tangential velocity) are readings no closed form
+//     fixes; the tests pin what they imply (uniform flow, rest, conservation), not their values.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
