@@ -247,6 +247,58 @@ def general_mesh_bench(dgsem, inputs, torch, wl, steps: int, structured_value: f
             "vs_structured": value / structured_value, "setup_s": setup_s}
 
 
+def order_bench(dgsem, inputs, torch, wl, steps: int, lexicographic_value: float):
+    """Element order study on the headline lattice: the elements numbered at random, and the same
+    mesh renumbered along the Hilbert curve of its element centroids (dg_mesh_sfc_order).  DOF
+    updates per second of whole RK steps and per-kernel durations of each, against the
+    lexicographic numbering of the headline run."""
+    import numpy as np
+    lgl, _ = dgsem.nodes(wl.N, "lgl")
+    k = wl.K1
+    X = inputs.lattice_points(lgl, k, k, k)
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    rnd = np.random.default_rng(0).permutation(k ** 3)
+    out = {}
+    for name, order in (("random", rnd), ("hilbert", None)):
+        if order is None:
+            order = rnd[dgsem.mesh_sfc_order(X[rnd], wl.N)]
+        Xo, nbo, sdo, flo = inputs.renumber_elements(X, nbr, side, flip, order)
+        S = dgsem.DGSolver.from_workload(wl, Xo, nbo, sdo, flip=flo)
+        del Xo
+        U = torch.from_numpy(np.ascontiguousarray(inputs.initial_state(wl, S.node_coords()))).cuda()
+        dof = S.K * S.n3
+        dt = S.timestep(U, wl.cfl, wl.dfl)
+        a, b, _ = dgsem.rk_coefficients()
+        R = torch.zeros_like(U)
+        cur, nxt = U, S.empty()
+        for st in range(steps + 1):
+            if st == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            for s_ in range(5):
+                S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+                cur, nxt = nxt, cur
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if not S.check_finite(cur):
+            raise RuntimeError("non-finite state in the element order study")
+        S.profile(True)
+        for s_ in range(5):
+            S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+            cur, nxt = nxt, cur
+        prof = S.profile_read()
+        S.profile(False)
+        value = dof * 5 * steps / wall
+        out[name] = {"value": value, "ms_per_stage": wall * 1e3 / (5 * steps),
+                     "kernels_ms": {"main": prof["main_ms"] / max(prof["main_launches"], 1),
+                                    "lift": prof["lift_ms"] / max(prof["lift_launches"], 1)},
+                     "vs_lexicographic": value / lexicographic_value}
+        del S, U, R, cur, nxt
+        torch.cuda.empty_cache()
+    out["steps"] = steps
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +311,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-general", action="store_true",
                     help="skip the measurement on the same mesh with rotated element axes")
+    ap.add_argument("--order-study", action="store_true",
+                    help="also time the lattice with random and with Hilbert-curve element numbering")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -376,12 +430,19 @@ def main():
         out["adjoint"] = adj
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(dgsem, inputs, torch)
+    freed = False
     if not args.no_general:
         del S, U, R, spare, cur, nxt
+        freed = True
         torch.cuda.empty_cache()
         out["general_mesh"] = general_mesh_bench(dgsem, inputs, torch, wl, 5, value)
         if not args.no_adjoint:
             out["general_mesh"]["adjoint"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, general=True)
+    if args.order_study:
+        if not freed:
+            del S, U, R, spare, cur, nxt
+        torch.cuda.empty_cache()
+        out["element_order"] = order_bench(dgsem, inputs, torch, wl, 5, value)
     if not args.no_cpu:
         cb = cpu_baseline(wl)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -130,6 +130,14 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, 
 int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
                     int32_t *nbr_elem, int8_t *nbr_side, int8_t *flip);
 
+/* Element order along a space-filling curve (Sec. 5.2: elements are stored in the order of a
+ * space-filling curve, so that neighbours are near in memory and in the launch order): order[i]
+ * is the element (index into xgeo, HOST [K][3][(n_geo+1)^3]) at position i of the 3-D Hilbert
+ * curve through the element centroids.  Renumbering a mesh by it is the caller's (the
+ * connectivity arrays refer to element indices).  Host only, synchronous; DG_ERR_ARG for NULL
+ * or non-finite input. */
+int dg_mesh_sfc_order(int n_elems, int n_geo, const double *xgeo, int32_t *order);
+
 /* The setup dg_init performs, on the host only (no device memory is touched): metric terms
  * Ja [K][9][n^3] (Ja^i_d at i*3+d), J [K][n^3], outward face normals fn [K][6][3][n^2] and the
  * n x n matrices D and Dhat, all host arrays (any may be NULL).  All tables are computed in

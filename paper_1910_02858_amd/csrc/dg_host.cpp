@@ -752,6 +752,68 @@ int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double per
   return DG_OK;
 }
 
+// position of integer point (x0, x1, x2) (each < 2^B) along a 3-D Hilbert curve: Skilling's
+// transform of the coordinates to the curve's transposed index (J. Skilling, "Programming the
+// Hilbert curve", AIP Conf. Proc. 707, 2004), then the index bits interleaved
+static uint64_t hilbert_index(uint32_t x[3], int B) {
+  // inverse undo of excess work
+  for (uint32_t Q = 1u << (B - 1); Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (x[i] & Q) {
+        x[0] ^= P;  // invert the low bits of the first coordinate
+      } else {
+        const uint32_t t = (x[0] ^ x[i]) & P;  // exchange the low bits of x[0] and x[i]
+        x[0] ^= t;
+        x[i] ^= t;
+      }
+    }
+  }
+  // Gray encode
+  for (int i = 1; i < 3; ++i) x[i] ^= x[i - 1];
+  uint32_t t = 0;
+  for (uint32_t Q = 1u << (B - 1); Q > 1; Q >>= 1)
+    if (x[2] & Q) t ^= Q - 1;
+  for (int i = 0; i < 3; ++i) x[i] ^= t;
+  // interleave: the most significant bit of x[0] first
+  uint64_t h = 0;
+  for (int b = B - 1; b >= 0; --b)
+    for (int i = 0; i < 3; ++i) h = (h << 1) | ((x[i] >> b) & 1u);
+  return h;
+}
+
+int dg_mesh_sfc_order(int n_elems, int n_geo, const double *xgeo, int32_t *order) {
+  if (n_elems < 1 || n_geo < 1 || n_geo > NMAX || !xgeo || !order) return DG_ERR_ARG;
+  const int K = n_elems, n = n_geo + 1, n3 = n * n * n;
+  std::vector<double> c((size_t)K * 3);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int e = 0; e < K; ++e)
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int q = 0; q < n3; ++q) acc += xgeo[((size_t)e * 3 + d) * n3 + q];
+      acc /= n3;
+      if (!std::isfinite(acc)) return DG_ERR_ARG;
+      c[(size_t)e * 3 + d] = acc;
+      lo[d] = std::min(lo[d], acc);
+      hi[d] = std::max(hi[d], acc);
+    }
+  // centroids mapped onto a 2^21 grid per axis (one scale for all axes keeps the curve's cells
+  // cubic), then sorted by their Hilbert index; ties keep the input order
+  const int B = 21;
+  const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+  const double sc = ((double)((1u << B) - 1)) / ext;
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)K);
+  for (int e = 0; e < K; ++e) {
+    uint32_t x[3];
+    for (int d = 0; d < 3; ++d)
+      x[d] = (uint32_t)std::min<double>((double)((1u << B) - 1), std::floor((c[(size_t)e * 3 + d] - lo[d]) * sc + 0.5));
+    key[e] = {hilbert_index(x, B), (int32_t)e};
+  }
+  std::stable_sort(key.begin(), key.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+  for (int i = 0; i < K; ++i) order[i] = key[i].second;
+  return DG_OK;
+}
+
 int dg_set_boundary_state(dg_handle *h, const double ub[5]) {
   if (!h || !ub) return DG_ERR_ARG;
   for (int v = 0; v < 5; ++v)

@@ -25,7 +25,7 @@ VF = {"kep": 0, "ec": 1, "central": 2}
 RS = {"llf": 0, "roe": 1, "volflux": 2, "volflux_roe": 3}
 
 EXPORTS = [
-    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_mesh_connect", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
+    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_mesh_connect", "dg_mesh_sfc_order", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
@@ -69,6 +69,8 @@ def lib():
                               ctypes.POINTER(_VP)]
         L.dg_set_stream.argtypes = [_VP, _VP]
         L.dg_set_boundary_state.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
+        L.dg_mesh_sfc_order.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32)]
         L.dg_mesh_connect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8),
@@ -145,6 +147,17 @@ def mesh_connect(xgeo, N: int, period=None, tol: float = 0.0, bc_kind: int = 0):
     if rc:
         raise DGError(rc, "dg_mesh_connect")
     return nbr, side, flip
+
+
+def mesh_sfc_order(xgeo, N: int):
+    """Element order along the Hilbert curve through the element centroids (``dg_mesh_sfc_order``):
+    ``order[i]`` is the element at position ``i``."""
+    xgeo = np.ascontiguousarray(xgeo, np.float64)
+    order = np.zeros(xgeo.shape[0], np.int32)
+    rc = lib().dg_mesh_sfc_order(xgeo.shape[0], N, _ptr(xgeo), order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc:
+        raise DGError(rc, "dg_mesh_sfc_order")
+    return order
 
 
 def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None):

@@ -194,6 +194,19 @@ def rotate_elements(X, nbr, side, flip, N: int, rot):
     return (np.ascontiguousarray(Xr), nb, side_r, flip_r, node_map)
 
 
+def renumber_elements(X, nbr, side, flip, order):
+    """The same mesh with element ``order[i]`` stored as element ``i`` (connectivity remapped;
+    boundary sides, neighbour sides and orientations unchanged).  A state field is carried with
+    ``U[order]``."""
+    order = np.asarray(order, np.int64)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.size)
+    nbr = np.asarray(nbr)[order]
+    nbr = np.where(nbr < 0, nbr, inv[np.maximum(nbr, 0)]).astype(np.int32)
+    return (np.ascontiguousarray(np.asarray(X)[order]), nbr, np.ascontiguousarray(np.asarray(side)[order]),
+            np.ascontiguousarray(np.asarray(flip)[order]))
+
+
 def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):
     """Undeformed positions ``X[e][3][n^3]`` of tensor nodes in every lattice cell.
 

@@ -22,6 +22,9 @@ Symmetry-plane boundaries: a curved box [0, pi]^3 whose six outer faces are symm
 RK steps), the Taylor-Green octant against the library's own periodic result (1e-12), and a
 batch with a boxed member bitwise equal to the one-mesh stages.
 
+Element renumbering (a shuffled lattice and its space-filling-curve order): the operator is the
+same bit for bit, element for element.
+
 No-slip adiabatic walls: boxes with walls on every outer face (also with rotated axes) against
 the oracle (1e-12), a fluid at rest staying at rest, 20 RK steps (1e-10), J^T w against the
 assembled Jacobian and dot products, and a batch with a walled member bitwise equal to the
@@ -590,3 +593,23 @@ def test_vjp_wall_dot_product_and_batch(dg, orc):
     for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
         assert torch.equal(o, ro), f"member {i} U_out differs"
         assert torch.equal(Rb, rR), f"member {i} R differs"
+
+
+@pytest.mark.parametrize("name,wl", [("ns_split_ec_roe_lgl7", inputs.workload(3)),
+                                     ("ns_weak_lg3_llf", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=3))],
+                         ids=["ns_split_ec_roe_lgl7", "ns_weak_lg3_llf"])
+def test_element_renumbering_is_bitwise(dg, orc, name, wl):
+    """Shuffled element numbering, and its Hilbert-curve order: U_t is the same bits per element
+    (every element's arithmetic is unchanged, only the launch order and the addresses move)."""
+    k = 3
+    lgl = orc.basis(wl.N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, k, k, k))
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes)
+    U = inputs.random_perturbation(inputs.initial_state(wl, M.points()), 2, 1e-2)
+    ref = dg.DGSolver.from_workload(wl, X, nbr, side).rhs(to_gpu(U)).cpu().numpy()
+    rnd = np.random.default_rng(3).permutation(k ** 3)
+    for order in (rnd, rnd[dg.mesh_sfc_order(X[rnd], wl.N)]):
+        Xo, nbo, sdo, flo = inputs.renumber_elements(X, nbr, side, flip, order)
+        got = dg.DGSolver.from_workload(wl, Xo, nbo, sdo, flip=flo).rhs(to_gpu(U[order])).cpu().numpy()
+        assert np.array_equal(got, ref[order])

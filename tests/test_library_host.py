@@ -272,3 +272,37 @@ def test_mesh_connect_arguments(dg):
     assert np.all(nbr == -1) and np.all(side == 0) and np.all(flip == 0)
     nbr, side, flip = dg.mesh_connect(X, 1, period=(2 * np.pi,) * 3)
     assert np.all(nbr == 0) and np.array_equal(side[0], [1, 0, 3, 2, 5, 4])
+
+
+def test_sfc_order_is_a_hilbert_curve(dg):
+    """On a 2^3-cells-per-direction lattice a Hilbert curve steps from every element to a face
+    neighbour; the order does not depend on how the elements were numbered before."""
+    k = 8
+    lgl, _ = dg.nodes(3, "lgl")
+    X = inputs.lattice_points(lgl, k, k, k)
+    order = dg.mesh_sfc_order(X, 3)
+    assert np.array_equal(np.sort(order), np.arange(k ** 3))
+    c = X.mean(axis=2)
+    step = np.linalg.norm(np.diff(c[order], axis=0), axis=1) / (2 * np.pi / k)
+    np.testing.assert_allclose(step, 1.0, rtol=1e-12)
+    shuffle = np.random.default_rng(0).permutation(k ** 3)
+    assert np.array_equal(shuffle[dg.mesh_sfc_order(X[shuffle], 3)], order)
+    with pytest.raises(dg.DGError):
+        dg.mesh_sfc_order(X * np.nan, 3)
+
+
+def test_renumbered_mesh_connectivity(dg):
+    """Renumbering along the curve keeps a valid mesh: the connectivity rebuilt from the
+    renumbered coordinates equals the renumbered connectivity, and dg_init's checks pass."""
+    N, k = 2, 4
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.warp_sine(inputs.lattice_points(lgl, k, k, k))
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    rnd = np.random.default_rng(1).permutation(k ** 3)
+    X, nbr, side, flip = inputs.renumber_elements(X, nbr, side, flip, rnd)
+    order = dg.mesh_sfc_order(X, N)
+    Xs, nbs, sds, fls = inputs.renumber_elements(X, nbr, side, flip, order)
+    got = dg.mesh_connect(Xs, N, period=(2 * np.pi,) * 3)
+    for a, b in zip(got, (nbs, sds, fls)):
+        np.testing.assert_array_equal(a, b)
+    dg.host_geometry(Xs, nbs, sds, N, "lgl", flip=fls)
