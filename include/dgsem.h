@@ -130,7 +130,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, 
 int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
                     int32_t *nbr_elem, int8_t *nbr_side, int8_t *flip);
 
-/* Element order along a space-filling curve (Sec. 5.2: elements are stored in the order of a
+/* Element order along a space-filling curve (Sec. 2.1.1 and 5.2: elements are stored in the order of a
  * space-filling curve, so that neighbours are near in memory and in the launch order): order[i]
  * is the element (index into xgeo, HOST [K][3][(n_geo+1)^3]) at position i of the 3-D Hilbert
  * curve through the element centroids.  Renumbering a mesh by it is the caller's (the
