@@ -40,7 +40,11 @@
 //     state U_b of the mesh, and the outer viscous flux equals the inner one.  Kind 2, no-slip
 //     adiabatic wall: the outer state has the velocity reversed (density and energy kept), the
 //     outer gradient keeps the velocity gradient and mirrors the temperature gradient, so that
-//     the BR1 means give zero velocity, no work and no heat flux at the wall.
+//     the BR1 means give zero velocity, no work and no heat flux at the wall.  Kind 3,
+//     no-slip isothermal wall at temperature T_w: the same outer state, outer W with the
+//     velocity reversed and temperature 2 T_w - T (so the mean is (0, T_w)), outer gradient
+//     equal to the inner one, so the BR1 means give zero velocity, no work, and the inner heat
+//     flux through the wall.
 //   * parity unpinned: the outer viscous flux of a given-state side (taken equal to the inner
 //     one) and the tangential part of the surface flux at a no-slip wall (the Riemann
 //     solver's dissipation of the reversed tangential velocity) are readings no closed form
@@ -237,6 +241,7 @@ struct Mesh {
   std::vector<int8_t> nside;       // [e][6]
   std::vector<int8_t> flip;        // [e][6] orientation code of the face map to the neighbour
   double ub[5] = {0, 0, 0, 0, 0};  // outer state of boundary sides of kind 1
+  double tw = 0;                   // wall temperature of boundary sides of kind 3
   std::vector<double> Ja;          // [e][i*3+d][node]: Ja^i_d
   std::vector<double> J;           // [e][node]
   std::vector<double> xs;          // [e][3][node] solution-node positions
@@ -746,6 +751,9 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
           } else if (M.nside[e * 6 + s] == 2) {
             for (int d = 0; d < 3; ++d) WR[d] = -WL[d];  // no-slip wall: velocity reversed
             WR[3] = WL[3];
+          } else if (M.nside[e * 6 + s] == 3) {
+            for (int d = 0; d < 3; ++d) WR[d] = -WL[d];  // isothermal wall: mean (0, T_w)
+            WR[3] = T(2.0 * M.tw) - WL[3];
           } else if (M.nside[e * 6 + s] == 1) {
             T Ub[5];
             for (int v = 0; v < 5; ++v) Ub[v] = T(M.ub[v]);
@@ -868,7 +876,8 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           T UM[5], US[5];
           trace(M, U, 5, em, sm, am, bm, UM);
           const bool given = nb < 0 && ns_ == 1;  // boundary with a given outer state
-          const bool wall = nb < 0 && ns_ == 2;   // no-slip adiabatic wall
+          const bool wall = nb < 0 && (ns_ == 2 || ns_ == 3);  // no-slip wall
+          const bool iso = nb < 0 && ns_ == 3;                 // ... isothermal
           if (nb >= 0)
             trace(M, U, 5, es, ss, as, bs, US);
           else if (wall)
@@ -885,6 +894,8 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
             trace(M, wk.G.data(), 12, em, sm, am, bm, gM);
             if (nb >= 0)
               trace(M, wk.G.data(), 12, es, ss, as, bs, gS);
+            else if (iso)
+              for (int c = 0; c < 12; ++c) gS[c] = gM[c];
             else if (wall)
               wall_grad(gM, nh, gS);
             else if (!given)
@@ -974,6 +985,9 @@ void orc_destroy(orc_handle* h) { delete h; }
 void orc_set_boundary_state(orc_handle* h, const double* ub) {
   for (int v = 0; v < 5; ++v) h->M.ub[v] = ub[v];
 }
+
+// wall temperature of boundary sides of kind 3 (isothermal wall)
+void orc_set_wall_temperature(orc_handle* h, double tw) { h->M.tw = tw; }
 
 // copies of the derived geometry: Ja [K][9][n3], J [K][n3], x [K][3][n3], face normals [K][6][3][n2]
 void orc_geometry(const orc_handle* h, double* Ja, double* J, double* xs, double* fn) {

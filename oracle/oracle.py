@@ -48,6 +48,7 @@ def lib():
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8, _I8]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_set_boundary_state.argtypes = [ctypes.c_void_p, _D]
+        L.orc_set_wall_temperature.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
         sch = [ctypes.c_int] * 4 + [ctypes.c_double] * 4
         L.orc_rhs.argtypes = [ctypes.c_void_p] + sch + [_D, _D]
@@ -143,6 +144,10 @@ class OracleMesh:
         """Outer state (rho, m1, m2, m3, E) of boundary sides of kind 1 (given state)."""
         ub = _c(ub)
         lib().orc_set_boundary_state(self.h, _p(ub))
+
+    def set_wall_temperature(self, tw: float):
+        """Wall temperature of boundary sides of kind 3 (isothermal wall)."""
+        lib().orc_set_wall_temperature(self.h, float(tw))
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:

@@ -27,6 +27,10 @@ No-slip adiabatic walls: a fluid at rest stays at rest on a curved box, and for 
 no mass and no energy cross a wall (the outer state reverses the velocity, so the mass flux and
 the wall's work vanish; the mirrored temperature gradient cancels the normal heat flux), while
 momentum changes.
+
+Isothermal walls: a fluid at rest at the wall temperature stays at rest; mass is conserved for
+arbitrary states; a fluid at rest hotter than the walls loses energy and a colder one gains it
+(the rate itself is parity unpinned).
 """
 import math
 
@@ -276,3 +280,33 @@ def test_no_slip_walls_rest_and_conservation(orc, eqn, form, vf, rs, nodes):
     scale = np.einsum("eq,evq->v", wq, np.abs(Ut))
     assert np.all(np.abs(tot[[0, 4]]) < 1e-13 * scale[[0, 4]])
     assert np.abs(tot[1:4]).max() > 1e-6 * scale[1:4].max()
+
+
+@pytest.mark.parametrize("eqn,form,vf,rs,nodes", [t for t in OCTANT_SCHEMES if t[0] == "ns"])
+def test_isothermal_walls(orc, eqn, form, vf, rs, nodes):
+    N, m = 4, 3
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3))
+    nbo, sdo, _ = inputs.box_lattice(m, m, m, kind=3)
+    rot = np.random.default_rng(13).integers(0, 24, m ** 3)
+    X, nbo, sdo, flo, _ = inputs.rotate_elements(X, nbo, sdo, np.zeros_like(sdo), N, rot)
+    M = orc.OracleMesh(X, nbo, sdo, N, nodes, flip=flo)
+    sc = orc.Scheme(eqn, form, vf, rs, mu=1e-2)
+    w = orc.basis(N, nodes)["w"]
+    wq = np.einsum("k,j,i->kji", w, w, w).ravel()[None, :] * M.geometry()["J"]
+    h = math.pi / m
+    rho, p = 1.2, 0.9
+    Tw = p / (rho * sc.R)
+    U0 = inputs.constant_state(M.K, M.n3, rho=rho, u=0.0, v=0.0, w=0.0, p=p)
+    M.set_wall_temperature(Tw)
+    assert np.abs(M.rhs(sc, U0)).max() < 1e-12 * np.abs(U0).max() * 2 * (N + 1) ** 2 / h
+    for fac, sign in ((0.8, -1.0), (1.25, 1.0)):       # walls colder / hotter than the fluid
+        M.set_wall_temperature(fac * Tw)
+        dE = float(np.sum(wq * M.rhs(sc, U0)[:, 4]))
+        assert sign * dE > 0.0
+    M.set_wall_temperature(0.9 * Tw)
+    U = inputs.random_perturbation(inputs.taylor_green(M.points() + 0.3, 1.0, 0.3), 5, 1e-2)
+    Ut = M.rhs(sc, U)
+    tot = np.einsum("eq,evq->v", wq, Ut)
+    scale = np.einsum("eq,evq->v", wq, np.abs(Ut))
+    assert abs(tot[0]) < 1e-13 * scale[0]
