@@ -63,8 +63,11 @@ enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
  * (far field, inflow; set with dg_set_boundary_state), whose outer viscous flux is taken equal
  * to the inner one.  DG_BC_WALL: a no-slip adiabatic wall (Sec. 2): outer state with the
  * velocity reversed, outer gradient with the velocity gradient kept and the temperature
- * gradient mirrored, so the surface means give zero velocity, no work and no heat flux. */
-enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2 };
+ * gradient mirrored, so the surface means give zero velocity, no work and no heat flux.
+ * DG_BC_WALL_ISOTHERMAL: a no-slip wall at temperature T_w (set with dg_set_wall_temperature):
+ * the same outer state, outer (u, v, w, T) = (-u, -v, -w, 2 T_w - T), outer gradient equal to
+ * the inner one, so the means give zero velocity, T_w, no work, and the inner heat flux. */
+enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2, DG_BC_WALL_ISOTHERMAL = 3 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
@@ -90,7 +93,7 @@ typedef struct {
  * element); normals and surface elements are the master's; a boundary side is its own master.
  * A mesh without boundary sides whose every face meets the opposite side with code 0 is
  * structured.  Errors:
- * a boundary kind other than DG_BC_SYMMETRY, DG_BC_STATE or DG_BC_WALL is DG_ERR_UNSUPPORTED; a neighbour index out of
+ * an unknown boundary kind is DG_ERR_UNSUPPORTED; a neighbour index out of
  * range (other than -1) is DG_ERR_MESH. */
 
 typedef struct {
@@ -112,7 +115,7 @@ int dg_rk_coefficients(double *a, double *b, double *c);
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
  * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
- * symmetry-plane, given-state and no-slip wall boundaries; see dg_mesh).  hip_stream is a
+ * symmetry-plane, given-state, adiabatic and isothermal wall boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
@@ -154,6 +157,11 @@ int dg_set_stream(dg_handle *h, void *hip_stream);
  * called again to change the state.  DG_ERR_ARG if rho or the pressure is not positive or a
  * value is not finite.  Synchronous (host only). */
 int dg_set_boundary_state(dg_handle *h, const double ub[5]);
+
+/* Wall temperature T_w (> 0, finite; else DG_ERR_ARG) of the DG_BC_WALL_ISOTHERMAL sides.  The
+ * same rules as for dg_set_boundary_state: required before launching calls on a mesh with such
+ * sides, may be changed later.  Synchronous (host only). */
+int dg_set_wall_temperature(dg_handle *h, double T_w);
 
 /* U_t = L(U) (eq. semiDiscrete / semiDiscreteStrong / semiDiscreteSplit, BR1 lifting for
  * Navier-Stokes).  U, Ut: device [K][5][n^3]; Ut is overwritten; U and Ut must differ. */

@@ -353,6 +353,11 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
       for (int v = 0; v < 3; ++v) WR[v] = -WL[v];
       WR[3] = WL[3];
+    } else if (GEN && f.bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
+      // isothermal wall: velocity reversed, mean temperature T_w
+#pragma unroll
+      for (int v = 0; v < 3; ++v) WR[v] = -WL[v];
+      WR[3] = 2.0 * ph.tw - WL[3];
     } else if (GEN && f.bnd) {
       // symmetry plane: the outer W is the inner one with the velocity reflected
       const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
@@ -595,6 +600,13 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       // given outer state; its viscous flux is taken equal to the inner one below
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+    } else if (bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
+      // isothermal wall: velocity reversed; outer gradient equal to the inner one
+      Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
+      if (NS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gx[c] = gw[c];
+      }
     } else if (bnd && f.kind == DG_BC_WALL) {
       // no-slip wall: velocity reversed; velocity gradient kept, temperature gradient mirrored
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
@@ -939,7 +951,8 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
     const bool given = bnd && f.kind == DG_BC_STATE;
-    const bool wall = bnd && f.kind == DG_BC_WALL;
+    const bool iso = bnd && f.kind == DG_BC_WALL_ISOTHERMAL;
+    const bool wall = bnd && (f.kind == DG_BC_WALL || iso);
     if (given) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state
@@ -964,9 +977,19 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
         for (int c = 0; c < 4; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
       } else if (wall) {
         // no-slip wall: the outer momentum flux equals the inner one, the outer energy flux is
-        // its negative (reversed velocity, mirrored heat flux), so the mean keeps the momentum
+        // its negative (reversed velocity, mirrored heat flux), so the mean keeps the momentum;
+        // at an isothermal wall the outer gradient is the inner one, so the mean energy flux is
+        // the inner heat flux: the inner energy flux minus the work (tau Ja^dn) . u
+        double g3[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
+        for (int c = 0; c < 3; ++c) {
+          g3[c] = Ge[(dn * 4 + c) * n3 + qo];
+          F[1 + c] -= g3[c];
+        }
+        if (iso) {
+          const double ir = 1.0 / Uw[0];
+          F[4] -= Ge[(dn * 4 + 3) * n3 + qo] - (g3[0] * Uw[1] + g3[1] * Uw[2] + g3[2] * Uw[3]) * ir;
+        }
       } else if (bnd) {
         // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
         // mean keeps the normal part of the momentum flux

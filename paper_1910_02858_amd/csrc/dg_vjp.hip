@@ -130,13 +130,14 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const bool plus = s & 1;
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
     int qn, nb;
-    bool bnd = false, given = false, wall = false;
+    bool bnd = false, given = false, wall = false, iso = false;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
       bnd = f.bnd;
       given = bnd && f.kind == DG_BC_STATE;
-      wall = bnd && f.kind == DG_BC_WALL;
+      iso = bnd && f.kind == DG_BC_WALL_ISOTHERMAL;
+      wall = bnd && (f.kind == DG_BC_WALL || iso);
       nb = bnd ? e : g.nbr[(size_t)e * 6 + s];  // a boundary side reads nothing of a neighbour
     } else {
       qn = vline_node<n>(dn, a, b, plus ? 0 : N);
@@ -207,6 +208,12 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
         // given outer state: the term is -g, the whole own flux
 #pragma unroll
         for (int v = 0; v < 5; ++v) Fvb[v] = -Fb[v];
+      } else if (iso) {
+        // isothermal wall: the terms are -g_m for the momentum and -(g_E - g_m . u) for the
+        // energy, with u this node's velocity
+        Fvb[0] = 0.0; Fvb[4] = -Fb[4];
+        Fvb[1] = -Fb[1] + Fb[4] * Po.u; Fvb[2] = -Fb[2] + Fb[4] * Po.v; Fvb[3] = -Fb[3] + Fb[4] * Po.w;
+        pc.u += Fb[4] * tn[0]; pc.v += Fb[4] * tn[1]; pc.w += Fb[4] * tn[2];
       } else if (wall) {
         // no-slip wall: the term is -g for the momentum, nothing for the energy
         Fvb[0] = 0.0; Fvb[4] = 0.0;
@@ -473,6 +480,11 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
         const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
         Wb[0] -= pf[0]; Wb[1] -= pf[n2]; Wb[2] -= pf[2 * n2];
         Wb[3] += pf[3 * n2];
+      } else if (f.bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
+        // isothermal wall: the outer W is (-u, -v, -w, 2 T_w - T)
+        const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
+        Wb[0] -= pf[0]; Wb[1] -= pf[n2]; Wb[2] -= pf[2 * n2];
+        Wb[3] -= pf[3 * n2];
       } else if (f.bnd) {
         // symmetry plane: the outer W is the mirrored own W, so the element's own face term
         // comes back with its velocity part mirrored

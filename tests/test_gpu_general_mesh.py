@@ -25,6 +25,10 @@ batch with a boxed member bitwise equal to the one-mesh stages.
 Element renumbering (a shuffled lattice and its space-filling-curve order): the operator is the
 same bit for bit, element for element.
 
+Isothermal walls: boxes against the oracle (1e-12), a fluid at rest at the wall temperature at
+rest, the operator refusing to run before the temperature is set, J^T w against the assembled
+Jacobian and a mixed batch bitwise equal to the one-mesh stage.
+
 No-slip adiabatic walls: boxes with walls on every outer face (also with rotated axes) against
 the oracle (1e-12), a fluid at rest staying at rest, 20 RK steps (1e-10), J^T w against the
 assembled Jacobian and dot products, and a batch with a walled member bitwise equal to the
@@ -299,16 +303,23 @@ def box_problem(orc, wl, m, seed=None, curved=True, perturb=1e-2, kind=0):
     M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes, flip=flip)
     if kind == 1:
         M.set_boundary_state(UB)
+    if kind == 3:
+        M.set_wall_temperature(TW)
     U = inputs.initial_state(wl, M.points() + 0.3)
     if perturb:
         U = inputs.random_perturbation(U, 4, perturb)
     return M, (X, nbr, side, flip), U
 
 
+TW = 65.0  # wall temperature of isothermal walls (below the vortex's, about 71 at Mach 0.1)
+
+
 def box_solver(dg, wl, X, nbr, side, flip, kind=0):
     S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
     if kind == 1:
         S.set_boundary_state(UB)
+    if kind == 3:
+        S.set_wall_temperature(TW)
     return S
 
 
@@ -613,3 +624,87 @@ def test_element_renumbering_is_bitwise(dg, orc, name, wl):
         Xo, nbo, sdo, flo = inputs.renumber_elements(X, nbr, side, flip, order)
         got = dg.DGSolver.from_workload(wl, Xo, nbo, sdo, flip=flo).rhs(to_gpu(U[order])).cpu().numpy()
         assert np.array_equal(got, ref[order])
+
+
+ISO_CASES = [
+    ("ns_split_kep_roe_lgl5_rotated", inputs.workload(2, N=5), 3, 21),
+    ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
+    ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 22),
+    ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+]
+
+
+@pytest.mark.parametrize("name,wl,m,seed", ISO_CASES, ids=[c[0] for c in ISO_CASES])
+def test_rhs_parity_isothermal_box(dg, orc, name, wl, m, seed):
+    print(f"case {name}", flush=True)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, m, seed, kind=3)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=3)
+    ref = M.rhs(orc.Scheme.of(wl), U)
+    got = S.rhs(to_gpu(U)).cpu().numpy()
+    ne, per = check_rhs(got, ref)
+    print(f"normwise {ne:.2e} per-variable {per}")
+
+
+def test_isothermal_rest_and_unset_temperature(dg, orc):
+    wl = inputs.workload(2, N=4)
+    M, (X, nbr, side, flip), _ = box_problem(orc, wl, 3, seed=23, kind=3)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    rho, p = 1.2, 0.9
+    U0 = inputs.constant_state(M.K, M.n3, rho=rho, u=0.0, v=0.0, w=0.0, p=p)
+    with pytest.raises(dg.DGError) as ei:
+        S.rhs(to_gpu(U0))
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError):
+        S.set_wall_temperature(-1.0)
+    S.set_wall_temperature(p / (rho * wl.R))
+    Ut = S.rhs(to_gpu(U0)).cpu().numpy()
+    assert np.abs(Ut).max() < 1e-12 * np.abs(U0).max() * 2 * (wl.N + 1) ** 2 / (math.pi / 3)
+
+
+@pytest.mark.parametrize("seed", [None, 8], ids=["lattice", "rotated"])
+def test_vjp_isothermal_elementwise_against_oracle_jacobian(dg, orc, seed):
+    wl = inputs.workload(2, N=2, mach=0.3)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 2, seed=seed, perturb=2e-2, kind=3)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=3)
+    rng = np.random.default_rng(7)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+def test_batch_with_isothermal_member(dg, orc):
+    import torch
+    wl = inputs.workload(2, N=4)
+    _, (X, nbr, side, flip), Ui = box_problem(orc, wl, 3, seed=24, kind=3)
+    _, (X2, nbr2, side2, flip2), U2 = box_problem(orc, wl, 3, seed=25, kind=2)
+    sols = [box_solver(dg, wl, X, nbr, side, flip, kind=3), box_solver(dg, wl, X2, nbr2, side2, flip2, kind=2)]
+    Us = [to_gpu(Ui), to_gpu(U2)]
+    a, b, _ = dg.rk_coefficients()
+    dts = [Si.timestep(Ui_) for Si, Ui_ in zip(sols, Us)]
+    R0 = [torch.full_like(U, 1e-4) for U in Us]
+    ref = []
+    for Si, Ui_, R, dt in zip(sols, Us, R0, dts):
+        out, Rr = Si.empty(), R.clone()
+        Si.rk_stage(Ui_, out, Rr, a[1], b[1], dt)
+        ref.append((out, Rr))
+    B = dg.Batch(sols)
+    outs = [Si.empty() for Si in sols]
+    Rs = [R.clone() for R in R0]
+    B.rk_stage(Us, outs, Rs, a[1], b[1], dts)
+    torch.cuda.synchronize()
+    for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
+        assert torch.equal(o, ro), f"member {i} U_out differs"
+        assert torch.equal(Rb, rR), f"member {i} R differs"

@@ -189,6 +189,7 @@ def test_null_arguments(dg):
     assert L.dg_rk_steps_vjp(None, 2, None, None, None, None, 0.0) == -1
     assert L.dg_rk_stage_keep(None, None, None, None, 0.0, 0.0, 0.0, None) == -1
     assert L.dg_set_boundary_state(None, None) == -1
+    assert L.dg_set_wall_temperature(None, 1.0) == -1
     assert L.dg_nodes(0, 1, None, None) == -1
     b = ctypes.c_void_p()
     assert L.dg_batch_create(None, 0, ctypes.byref(b)) == -1 and not b.value
@@ -247,7 +248,7 @@ def test_mesh_connect_periodic(dg, k, curved, seed):
         np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_mesh_connect_box(dg, kind):
     """Without periods the outer faces of a box become boundary sides of the requested kind."""
     N, m = 2, 3
