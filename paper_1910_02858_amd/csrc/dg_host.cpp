@@ -690,6 +690,7 @@ int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double per
     }
   }
   if (!(tol > 0.0)) tol = 1e-8 * hmin;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return DG_ERR_ARG;  // degenerate elements
   for (int e = 0; e < K; ++e) {
     const double *x = xgeo + (size_t)e * 3 * n3;
     for (int s = 0; s < 6; ++s) {

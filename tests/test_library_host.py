@@ -269,6 +269,8 @@ def test_mesh_connect_arguments(dg):
         dg.mesh_connect(X, 1, bc_kind=7)
     with pytest.raises(dg.DGError):
         dg.mesh_connect(X, 1, period=(-1.0, 0.0, 0.0))
+    with pytest.raises(dg.DGError):
+        dg.mesh_connect(np.zeros_like(X), 1)                     # degenerate element
     nbr, side, flip = dg.mesh_connect(X, 1)                      # one element, no periods
     assert np.all(nbr == -1) and np.all(side == 0) and np.all(flip == 0)
     nbr, side, flip = dg.mesh_connect(X, 1, period=(2 * np.pi,) * 3)
