@@ -128,13 +128,13 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, 
  * period[d] > 0 (period may be NULL) coordinates are compared modulo period[d], which joins the
  * opposite faces of a periodic box.  Faces without a match become boundary sides (nbr_elem -1,
  * nbr_side = bc_kind, flip 0).  Outputs are HOST [K][6] arrays owned by the caller.  Host only,
- * synchronous; DG_ERR_ARG for NULL or non-finite input or an unknown bc_kind.  dg_init
- * validates the result like any other connectivity. */
+ * synchronous; DG_ERR_ARG for NULL or non-finite input, degenerate (flat) elements, a negative
+ * period or an unknown bc_kind.  dg_init validates the result like any other connectivity. */
 int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
                     int32_t *nbr_elem, int8_t *nbr_side, int8_t *flip);
 
-/* Element order along a space-filling curve (Sec. 2.1.1 and 5.2: elements are stored in the order of a
- * space-filling curve, so that neighbours are near in memory and in the launch order): order[i]
+/* Element order along a space-filling curve (Secs. 2.1.1 and 5.2: elements are stored in the
+ * order of a space-filling curve, so neighbours are near in memory and in the launch order): order[i]
  * is the element (index into xgeo, HOST [K][3][(n_geo+1)^3]) at position i of the 3-D Hilbert
  * curve through the element centroids.  Renumbering a mesh by it is the caller's (the
  * connectivity arrays refer to element indices).  Host only, synchronous; DG_ERR_ARG for NULL
