@@ -44,7 +44,9 @@
 //     no-slip isothermal wall at temperature T_w: the same outer state, outer W with the
 //     velocity reversed and temperature 2 T_w - T (so the mean is (0, T_w)), outer gradient
 //     equal to the inner one, so the BR1 means give zero velocity, no work, and the inner heat
-//     flux through the wall.
+//     flux through the wall.  Kind 4, subsonic pressure outflow at p_out: the outer state has
+//     the inner density and velocity and the pressure p_out; the outer viscous flux equals the
+//     inner one (as for a given state).
 //   * parity unpinned: the outer viscous flux of a given-state side (taken equal to the inner
 //     one) and the tangential part of the surface flux at a no-slip wall (the Riemann
 //     solver's dissipation of the reversed tangential velocity) are readings no closed form
@@ -242,6 +244,7 @@ struct Mesh {
   std::vector<int8_t> flip;        // [e][6] orientation code of the face map to the neighbour
   double ub[5] = {0, 0, 0, 0, 0};  // outer state of boundary sides of kind 1
   double tw = 0;                   // wall temperature of boundary sides of kind 3
+  double pout = 0;                 // outflow pressure of boundary sides of kind 4
   std::vector<double> Ja;          // [e][i*3+d][node]: Ja^i_d
   std::vector<double> J;           // [e][node]
   std::vector<double> xs;          // [e][3][node] solution-node positions
@@ -652,6 +655,17 @@ template <class T> static void mirror_W(const T* W, const double* nh, T* G) {
 
 // mirror image of the gradients g[d*4+v] = dW_v/dx_d: h = P g P for the velocity block,
 // h = P g for the temperature column
+// pressure outflow: the inner density and velocity with the pressure p_out
+template <class T> static void outflow_state(const T* U, double pout, double gamma, T* G) {
+  G[0] = U[0];
+  T k = T(0.0);
+  for (int d = 0; d < 3; ++d) {
+    G[1 + d] = U[1 + d];
+    k = k + U[1 + d] * U[1 + d];
+  }
+  G[4] = T(pout / (gamma - 1.0)) + T(0.5) * k / U[0];
+}
+
 // no-slip adiabatic wall: outer state with the velocity reversed
 template <class T> static void wall_state(const T* U, T* G) {
   G[0] = U[0];
@@ -751,6 +765,13 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
           } else if (M.nside[e * 6 + s] == 2) {
             for (int d = 0; d < 3; ++d) WR[d] = -WL[d];  // no-slip wall: velocity reversed
             WR[3] = WL[3];
+          } else if (M.nside[e * 6 + s] == 4) {
+            T Ul[5], Ur[5];
+            trace(M, U, 5, e, s, a, b, Ul);
+            outflow_state(Ul, M.pout, S.gamma, Ur);
+            Prim<T> Pr = prim(Ur, S.gamma);
+            for (int d = 0; d < 3; ++d) WR[d] = Pr.u[d];
+            WR[3] = Pr.p / (Pr.rho * T(S.R));
           } else if (M.nside[e * 6 + s] == 3) {
             for (int d = 0; d < 3; ++d) WR[d] = -WL[d];  // isothermal wall: mean (0, T_w)
             WR[3] = T(2.0 * M.tw) - WL[3];
@@ -875,13 +896,16 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
           T UM[5], US[5];
           trace(M, U, 5, em, sm, am, bm, UM);
-          const bool given = nb < 0 && ns_ == 1;  // boundary with a given outer state
+          const bool given = nb < 0 && (ns_ == 1 || ns_ == 4);  // outer viscous flux = inner
+          const bool outflow = nb < 0 && ns_ == 4;
           const bool wall = nb < 0 && (ns_ == 2 || ns_ == 3);  // no-slip wall
           const bool iso = nb < 0 && ns_ == 3;                 // ... isothermal
           if (nb >= 0)
             trace(M, U, 5, es, ss, as, bs, US);
           else if (wall)
             wall_state(UM, US);
+          else if (outflow)
+            outflow_state(UM, M.pout, S.gamma, US);
           else if (given)
             for (int v = 0; v < 5; ++v) US[v] = T(M.ub[v]);
           else
@@ -988,6 +1012,9 @@ void orc_set_boundary_state(orc_handle* h, const double* ub) {
 
 // wall temperature of boundary sides of kind 3 (isothermal wall)
 void orc_set_wall_temperature(orc_handle* h, double tw) { h->M.tw = tw; }
+
+// pressure of boundary sides of kind 4 (pressure outflow)
+void orc_set_outflow_pressure(orc_handle* h, double p) { h->M.pout = p; }
 
 // copies of the derived geometry: Ja [K][9][n3], J [K][n3], x [K][3][n3], face normals [K][6][3][n2]
 void orc_geometry(const orc_handle* h, double* Ja, double* J, double* xs, double* fn) {

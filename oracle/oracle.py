@@ -49,6 +49,7 @@ def lib():
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_set_boundary_state.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_wall_temperature.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_set_outflow_pressure.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
         sch = [ctypes.c_int] * 4 + [ctypes.c_double] * 4
         L.orc_rhs.argtypes = [ctypes.c_void_p] + sch + [_D, _D]
@@ -144,6 +145,10 @@ class OracleMesh:
         """Outer state (rho, m1, m2, m3, E) of boundary sides of kind 1 (given state)."""
         ub = _c(ub)
         lib().orc_set_boundary_state(self.h, _p(ub))
+
+    def set_outflow_pressure(self, p: float):
+        """Pressure of boundary sides of kind 4 (pressure outflow)."""
+        lib().orc_set_outflow_pressure(self.h, float(p))
 
     def set_wall_temperature(self, tw: float):
         """Wall temperature of boundary sides of kind 3 (isothermal wall)."""

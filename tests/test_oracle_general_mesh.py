@@ -31,6 +31,11 @@ momentum changes.
 Isothermal walls: a fluid at rest at the wall temperature stays at rest; mass is conserved for
 arbitrary states; a fluid at rest hotter than the walls loses energy and a colder one gains it
 (the rate itself is parity unpinned).
+
+Pressure outflow: a uniform flow at the outflow pressure is preserved on a curved box; for the
+Euler equations on LGL nodes a periodic lattice whose shell elements hold, on the face layers
+they share with the inner elements, exactly the outflow state of the inner traces reproduces
+the box of the inner elements with outflow boundaries.
 """
 import math
 
@@ -310,3 +315,64 @@ def test_isothermal_walls(orc, eqn, form, vf, rs, nodes):
     tot = np.einsum("eq,evq->v", wq, Ut)
     scale = np.einsum("eq,evq->v", wq, np.abs(Ut))
     assert abs(tot[0]) < 1e-13 * scale[0]
+
+
+def _outflow_state(U, pout, gamma=1.4):
+    G = U.copy()
+    G[4] = pout / (gamma - 1.0) + 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
+    return G
+
+
+@pytest.mark.parametrize("eqn,form,vf,rs,nodes", [t for t in OCTANT_SCHEMES if t[4] == "lgl"])
+def test_outflow_preserves_uniform_flow(orc, eqn, form, vf, rs, nodes):
+    N, m = 4, 3
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3))
+    nbo, sdo, _ = inputs.box_lattice(m, m, m, kind=4)
+    M = orc.OracleMesh(X, nbo, sdo, N, nodes)
+    U0 = inputs.constant_state(M.K, M.n3, p=0.9)
+    M.set_outflow_pressure(0.9)
+    sc = orc.Scheme(eqn, form, vf, rs, mu=1e-2)
+    h = math.pi / m
+    assert np.abs(M.rhs(sc, U0)).max() < 1e-12 * np.abs(U0).max() * 2 * (N + 1) ** 2 / h
+
+
+@pytest.mark.parametrize("form,vf,rs", [("split", "ec", "roe"), ("split", "kep", "volflux_roe"),
+                                        ("strong", "central", "llf"), ("weak", "central", "roe")])
+def test_outflow_equals_matching_shell(orc, form, vf, rs):
+    N, k, pout = 3, 5, 50.0
+    n = N + 1
+    lgl = orc.basis(N, "lgl")["x"]
+    Xf = inputs.warp_sine(inputs.lattice_points(lgl, k, k, k), 0.05)
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    Mf = orc.OracleMesh(Xf, nbr, side, N, "lgl")
+    e3 = np.arange(k ** 3)
+    ex, ey, ez = e3 % k, (e3 // k) % k, e3 // (k * k)
+    inner = (ex > 0) & (ex < k - 1) & (ey > 0) & (ey < k - 1) & (ez > 0) & (ez < k - 1)
+    U = np.empty((k ** 3, 5, n ** 3))
+    U[:] = inputs.constant_state(1, 1, p=40.0)[0, :, 0][None, :, None]
+    U[inner] = inputs.random_perturbation(inputs.taylor_green(Mf.points()[inner], 1.0, 0.1), 3, 1e-2)
+
+    def node(d, a, b, m_):
+        idx = [0, 0, 0]
+        da, db = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+        idx[d], idx[da], idx[db] = m_, a, b
+        return idx[0] + n * (idx[1] + n * idx[2])
+
+    for e in np.nonzero(inner)[0]:
+        for s_ in range(6):
+            nb = nbr[e, s_]
+            if inner[nb]:
+                continue
+            d, plus = s_ // 2, s_ % 2
+            for a in range(n):
+                for b in range(n):
+                    qi, qs = node(d, a, b, N if plus else 0), node(d, a, b, 0 if plus else N)
+                    U[nb, :, qs] = _outflow_state(U[e, :, qi], pout)
+    nbo, sdo, _ = inputs.box_lattice(k - 2, k - 2, k - 2, kind=4)
+    Mb = orc.OracleMesh(Xf[inner], nbo, sdo, N, "lgl")
+    Mb.set_outflow_pressure(pout)
+    sc = orc.Scheme("euler", form, vf, rs)
+    ref = Mf.rhs(sc, U)[inner]
+    got = Mb.rhs(sc, U[inner])
+    assert np.all(np.abs(got - ref).max(axis=(0, 2)) <= 1e-12 * np.abs(ref).max(axis=(0, 2)))
