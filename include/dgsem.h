@@ -66,8 +66,11 @@ enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
  * gradient mirrored, so the surface means give zero velocity, no work and no heat flux.
  * DG_BC_WALL_ISOTHERMAL: a no-slip wall at temperature T_w (set with dg_set_wall_temperature):
  * the same outer state, outer (u, v, w, T) = (-u, -v, -w, 2 T_w - T), outer gradient equal to
- * the inner one, so the means give zero velocity, T_w, no work, and the inner heat flux. */
-enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2, DG_BC_WALL_ISOTHERMAL = 3 };
+ * the inner one, so the means give zero velocity, T_w, no work, and the inner heat flux.
+ * DG_BC_OUTFLOW: a subsonic pressure outflow (LGL nodes only): outer state with the inner
+ * density and velocity and the pressure p_out (set with dg_set_outflow_pressure), outer viscous
+ * flux equal to the inner one. */
+enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2, DG_BC_WALL_ISOTHERMAL = 3, DG_BC_OUTFLOW = 4 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
@@ -115,7 +118,8 @@ int dg_rk_coefficients(double *a, double *b, double *c);
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
  * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
- * symmetry-plane, given-state, adiabatic and isothermal wall boundaries; see dg_mesh).  hip_stream is a
+ * symmetry-plane, given-state, adiabatic and isothermal wall, and (LGL) pressure-outflow
+ * boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,
             dg_handle **out);
@@ -162,6 +166,10 @@ int dg_set_boundary_state(dg_handle *h, const double ub[5]);
  * same rules as for dg_set_boundary_state: required before launching calls on a mesh with such
  * sides, may be changed later.  Synchronous (host only). */
 int dg_set_wall_temperature(dg_handle *h, double T_w);
+
+/* Pressure p_out (> 0, finite; else DG_ERR_ARG) of the DG_BC_OUTFLOW sides, with the same rules
+ * as dg_set_boundary_state.  Synchronous (host only). */
+int dg_set_outflow_pressure(dg_handle *h, double p_out);
 
 /* U_t = L(U) (eq. semiDiscrete / semiDiscreteStrong / semiDiscreteSplit, BR1 lifting for
  * Navier-Stokes).  U, Ut: device [K][5][n^3]; Ut is overwritten; U and Ut must differ. */

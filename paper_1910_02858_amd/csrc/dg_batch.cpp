@@ -125,6 +125,7 @@ std::vector<dg::Member> describe(const dg_batch *b, const double *const *U_in, d
       d.ph.kappa = h->ph.kappa; d.ph.vf = h->ph.vf; d.ph.rs = h->ph.rs;
       for (int v = 0; v < 5; ++v) d.ph.ub[v] = h->ph.ub[v];
       d.ph.tw = h->ph.tw;
+      d.ph.pout = h->ph.pout;
       d.U = U_in[i];
       d.G = h->d_G;
       d.out = U_out[i];
@@ -212,6 +213,7 @@ int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {
     if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
     if (h->needs_state && !h->state_set) return DG_ERR_ARG;  // its boundary state is not set
     if (h->needs_tw && !h->tw_set) return DG_ERR_ARG;        // its wall temperature is not set
+    if (h->needs_pout && !h->pout_set) return DG_ERR_ARG;    // its outflow pressure is not set
     if (h->sc.eqn != h0->sc.eqn || h->sc.volflux != h0->sc.volflux || h->sc.riemann != h0->sc.riemann)
       return DG_ERR_UNSUPPORTED;
     for (int j = 0; j < i; ++j)

@@ -376,15 +376,15 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
   // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side:
-  // DG_BC_SYMMETRY, DG_BC_STATE, DG_BC_WALL or DG_BC_WALL_ISOTHERMAL, orientation 0) or has a neighbour that names it back, on the side and with
+  // DG_BC_SYMMETRY ... DG_BC_OUTFLOW, orientation 0) or has a neighbour that names it back, on the side and with
   // the inverse orientation it names
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
       const int o = mesh->flip ? mesh->flip[q] : 0;
       if (nb == -1) {
-        if (ns != DG_BC_SYMMETRY && ns != DG_BC_STATE && ns != DG_BC_WALL && ns != DG_BC_WALL_ISOTHERMAL)
-          return DG_ERR_UNSUPPORTED;
+        if (ns < DG_BC_SYMMETRY || ns > DG_BC_OUTFLOW) return DG_ERR_UNSUPPORTED;
+        if (ns == DG_BC_OUTFLOW && node_type != DG_NODES_LGL) return DG_ERR_UNSUPPORTED;
         if (o != 0) return DG_ERR_MESH;
         continue;
       }
@@ -445,6 +445,8 @@ int state_ready(dg_handle *h) {
     return fail(h, DG_ERR_ARG, "the mesh has given-state boundary sides: call dg_set_boundary_state first");
   if (h->needs_tw && !h->tw_set)
     return fail(h, DG_ERR_ARG, "the mesh has isothermal wall sides: call dg_set_wall_temperature first");
+  if (h->needs_pout && !h->pout_set)
+    return fail(h, DG_ERR_ARG, "the mesh has outflow sides: call dg_set_outflow_pressure first");
   return DG_OK;
 }
 
@@ -614,6 +616,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
       h->has_boundary = true;
       if (mesh->nbr_side[q] == DG_BC_STATE) h->needs_state = true;
       if (mesh->nbr_side[q] == DG_BC_WALL_ISOTHERMAL) h->needs_tw = true;
+      if (mesh->nbr_side[q] == DG_BC_OUTFLOW) h->needs_pout = true;
     }
   const std::vector<double> &sJ = G.sJ;
   h->x_nodes.swap(G.xs);
@@ -668,7 +671,7 @@ int dg_set_stream(dg_handle *h, void *stream) {
 int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
                     int32_t *nbr, int8_t *side, int8_t *flip) {
   if (n_elems < 1 || n_geo < 1 || n_geo > NMAX || !xgeo || !nbr || !side || !flip) return DG_ERR_ARG;
-  if (bc_kind < DG_BC_SYMMETRY || bc_kind > DG_BC_WALL_ISOTHERMAL) return DG_ERR_ARG;
+  if (bc_kind < DG_BC_SYMMETRY || bc_kind > DG_BC_OUTFLOW) return DG_ERR_ARG;
   const int K = n_elems, N = n_geo, n = N + 1, n3 = n * n * n;
   double L[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < 3 && period; ++d) {
@@ -816,6 +819,14 @@ int dg_mesh_sfc_order(int n_elems, int n_geo, const double *xgeo, int32_t *order
   }
   std::stable_sort(key.begin(), key.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
   for (int i = 0; i < K; ++i) order[i] = key[i].second;
+  return DG_OK;
+}
+
+int dg_set_outflow_pressure(dg_handle *h, double p_out) {
+  if (!h) return DG_ERR_ARG;
+  if (!(p_out > 0.0) || !std::isfinite(p_out)) return fail(h, DG_ERR_ARG, "outflow pressure must be positive");
+  h->ph.pout = p_out;
+  h->pout_set = true;
   return DG_OK;
 }
 

@@ -41,6 +41,7 @@ struct Phys {
   int vf, rs;
   double ub[5];                    // outer state of given-state boundary sides (conservative)
   double tw;                       // wall temperature of isothermal wall sides
+  double pout;                     // pressure of outflow sides
 };
 
 // Kernel launch entry points, one explicit instantiation per degree.
@@ -161,6 +162,8 @@ struct dg_handle {
   bool state_set = false;       // dg_set_boundary_state has been called
   bool needs_tw = false;        // some boundary side is an isothermal wall
   bool tw_set = false;          // dg_set_wall_temperature has been called
+  bool needs_pout = false;      // some boundary side is a pressure outflow
+  bool pout_set = false;        // dg_set_outflow_pressure has been called
   dg::Tab *d_tab = nullptr;
   double *d_G = nullptr;        // lifted gradients [K][12][n3] (Navier-Stokes)
   double *d_Pf = nullptr;       // face terms of the transposed lifting [K][6][4][n^2] (first VJP)

@@ -358,6 +358,14 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
       for (int v = 0; v < 3; ++v) WR[v] = -WL[v];
       WR[3] = 2.0 * ph.tw - WL[3];
+    } else if (GEN && f.bnd && f.kind == DG_BC_OUTFLOW) {
+      // pressure outflow (LGL nodes): the own trace's density and velocity with p_out
+      const int q = line_node<n>(dn, a, b, plus ? N : 0);
+      double Uq[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + q];
+      Uq[4] = ph.pout / gm1 + 0.5 * (Uq[1] * Uq[1] + Uq[2] * Uq[2] + Uq[3] * Uq[3]) / Uq[0];
+      grad_prim_to_W(Uq, gm1, ph.R, WR);
     } else if (GEN && f.bnd) {
       // symmetry plane: the outer W is the inner one with the velocity reflected
       const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
@@ -595,11 +603,18 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    const bool given = bnd && f.kind == DG_BC_STATE;
+    const bool given = bnd && (f.kind == DG_BC_STATE || f.kind == DG_BC_OUTFLOW);
     if (given) {
-      // given outer state; its viscous flux is taken equal to the inner one below
+      // given outer state, or the pressure outflow's (inner density and velocity, p_out); the
+      // outer viscous flux is taken equal to the inner one below
+      if (f.kind == DG_BC_OUTFLOW) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+        for (int v = 0; v < 4; ++v) Ux[v] = Uw[v];
+        Ux[4] = ph.pout / gm1 + 0.5 * (Uw[1] * Uw[1] + Uw[2] * Uw[2] + Uw[3] * Uw[3]) / Uw[0];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+      }
     } else if (bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
       // isothermal wall: velocity reversed; outer gradient equal to the inner one
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
@@ -950,10 +965,13 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    const bool given = bnd && f.kind == DG_BC_STATE;
+    const bool given = bnd && (f.kind == DG_BC_STATE || f.kind == DG_BC_OUTFLOW);
     const bool iso = bnd && f.kind == DG_BC_WALL_ISOTHERMAL;
     const bool wall = bnd && (f.kind == DG_BC_WALL || iso);
-    if (given) {
+    if (given && f.kind == DG_BC_OUTFLOW) {
+      // pressure outflow: the own trace's density and velocity with p_out
+      Ux[4] = ph.pout / gm1 + 0.5 * (Uw[1] * Uw[1] + Uw[2] * Uw[2] + Uw[3] * Uw[3]) / Uw[0];
+    } else if (given) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state
     } else if (wall) {

@@ -130,12 +130,13 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const bool plus = s & 1;
     const int qo = vline_node<n>(dn, a, b, plus ? N : 0);
     int qn, nb;
-    bool bnd = false, given = false, wall = false, iso = false;
+    bool bnd = false, given = false, wall = false, iso = false, outflow = false;
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
       qn = vline_node<n>(f.dn, f.a, f.b, f.plus ? N : 0);
       bnd = f.bnd;
-      given = bnd && f.kind == DG_BC_STATE;
+      outflow = bnd && f.kind == DG_BC_OUTFLOW;
+      given = bnd && (f.kind == DG_BC_STATE || outflow);
       iso = bnd && f.kind == DG_BC_WALL_ISOTHERMAL;
       wall = bnd && (f.kind == DG_BC_WALL || iso);
       nb = bnd ? e : g.nbr[(size_t)e * 6 + s];  // a boundary side reads nothing of a neighbour
@@ -157,7 +158,11 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
     const double ish = 1.0 / sh;
     const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    if (given) {
+    if (outflow) {
+      // pressure outflow: the own trace's density and velocity with p_out
+      Ux[0] = Uw[0]; Ux[1] = Uw[1]; Ux[2] = Uw[2]; Ux[3] = Uw[3];
+      Ux[4] = ph.pout / gm1 + 0.5 * (Uw[1] * Uw[1] + Uw[2] * Uw[2] + Uw[3] * Uw[3]) / Uw[0];
+    } else if (given) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];  // given outer state, independent of U
     } else if (wall) {
@@ -182,7 +187,11 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
     dgf::riemann_adj_prim(ph.rs, vf, PM, PS, UM, US, nh, gamma, Fbs, aM, aS);
     dgf::PA pc = plus ? aM : aS;
     const dgf::P Po = plus ? PM : PS;
-    if (wall) {
+    if (outflow) {
+      // the outer argument's density and velocity are the own trace's, its pressure is fixed
+      const dgf::PA ao = plus ? aS : aM;
+      pc.r += ao.r; pc.u += ao.u; pc.v += ao.v; pc.w += ao.w;
+    } else if (wall) {
       // the outer argument is the own trace with the velocity reversed
       const dgf::PA ao = plus ? aS : aM;
       pc.r += ao.r; pc.p += ao.p;
@@ -463,6 +472,7 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
   if (e >= g.K || t >= n3) return;
   const int id3[3] = {t % n, (t / n) % n, t / n2};
   double Wb[4] = {0.0, 0.0, 0.0, 0.0};
+  double tout = 0.0;  // adjoint of outflow sides' outer temperature p_out / (rho R)
   bool face = false;
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
@@ -473,7 +483,12 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
     // the neighbour's term at its matching face point (structured: side s ^ 1, same index)
     if constexpr (GEN) {
       const NbFace f = nbr_face<n, true>(g, e, s, a, b);
-      if (f.bnd && f.kind == DG_BC_STATE) {
+      if (f.bnd && f.kind == DG_BC_OUTFLOW) {
+        // pressure outflow: the outer W is (u, v, w, p_out / (rho R)) of this node
+        const double *pf = Pf + ((size_t)e * 6 + s) * 4 * n2 + a + n * b;
+        Wb[0] += pf[0]; Wb[1] += pf[n2]; Wb[2] += pf[2 * n2];
+        tout += pf[3 * n2];
+      } else if (f.bnd && f.kind == DG_BC_STATE) {
         // given outer state: W* depends on this element's W only through its own half
       } else if (f.bnd && f.kind == DG_BC_WALL) {
         // no-slip wall: the outer W is the own W with the velocity reversed
@@ -523,6 +538,7 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
     const dgf::P q = dgf::prim(Uq, ph.gamma - 1.0);
     dgf::PA pa = dgf::zero_pa();
     dgf::lift_vars_adj(q, ph.R, Wb, pa);
+    pa.r -= tout * ph.pout * q.ir * q.ir / ph.R;
     double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     dgf::cons_adj(q, ph.gamma - 1.0, pa, cb);
 #pragma unroll

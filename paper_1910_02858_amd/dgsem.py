@@ -25,7 +25,7 @@ VF = {"kep": 0, "ec": 1, "central": 2}
 RS = {"llf": 0, "roe": 1, "volflux": 2, "volflux_roe": 3}
 
 EXPORTS = [
-    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_set_wall_temperature", "dg_mesh_connect", "dg_mesh_sfc_order", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
+    "dg_nodes", "dg_rk_coefficients", "dg_init", "dg_set_stream", "dg_set_boundary_state", "dg_set_wall_temperature", "dg_set_outflow_pressure", "dg_mesh_connect", "dg_mesh_sfc_order", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp",
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
@@ -70,6 +70,7 @@ def lib():
         L.dg_set_stream.argtypes = [_VP, _VP]
         L.dg_set_boundary_state.argtypes = [_VP, ctypes.POINTER(ctypes.c_double)]
         L.dg_set_wall_temperature.argtypes = [_VP, ctypes.c_double]
+        L.dg_set_outflow_pressure.argtypes = [_VP, ctypes.c_double]
         L.dg_mesh_sfc_order.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32)]
         L.dg_mesh_connect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -231,6 +232,10 @@ class DGSolver:
         if rc:
             msg = lib().dg_last_error(self.h)
             raise DGError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_outflow_pressure(self, p: float):
+        """Pressure of the mesh's outflow sides."""
+        self._check(lib().dg_set_outflow_pressure(self.h, float(p)), "dg_set_outflow_pressure")
 
     def set_wall_temperature(self, tw: float):
         """Wall temperature of the mesh's isothermal wall sides."""

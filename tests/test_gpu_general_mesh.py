@@ -27,6 +27,10 @@ same bit for bit, element for element.  Mesh preprocessing end to end: from elem
 alone (rotated, shuffled), dg_mesh_connect and dg_mesh_sfc_order give a mesh whose operator
 matches the oracle on the mesh the coordinates came from (1e-12).
 
+Pressure outflow (LGL): boxes against the oracle (1e-12), a uniform flow at the outflow pressure
+at rest in time, the operator refusing to run before the pressure is set, J^T w against the
+assembled Jacobian and a mixed batch bitwise equal to the one-mesh stage.
+
 Isothermal walls: boxes against the oracle (1e-12), a fluid at rest at the wall temperature at
 rest, the operator refusing to run before the temperature is set, J^T w against the assembled
 Jacobian and a mixed batch bitwise equal to the one-mesh stage.
@@ -307,12 +311,15 @@ def box_problem(orc, wl, m, seed=None, curved=True, perturb=1e-2, kind=0):
         M.set_boundary_state(UB)
     if kind == 3:
         M.set_wall_temperature(TW)
+    if kind == 4:
+        M.set_outflow_pressure(POUT)
     U = inputs.initial_state(wl, M.points() + 0.3)
     if perturb:
         U = inputs.random_perturbation(U, 4, perturb)
     return M, (X, nbr, side, flip), U
 
 
+POUT = 68.0  # outflow pressure (the vortex's mean pressure is about 71 at Mach 0.1)
 TW = 65.0  # wall temperature of isothermal walls (below the vortex's, about 71 at Mach 0.1)
 
 
@@ -322,6 +329,8 @@ def box_solver(dg, wl, X, nbr, side, flip, kind=0):
         S.set_boundary_state(UB)
     if kind == 3:
         S.set_wall_temperature(TW)
+    if kind == 4:
+        S.set_outflow_pressure(POUT)
     return S
 
 
@@ -733,3 +742,88 @@ def test_mesh_from_coordinates_end_to_end(dg, orc):
     got = S.rhs(to_gpu(U[order])).cpu().numpy()
     ne, per = check_rhs(got, ref[order])
     print(f"normwise {ne:.2e} per-variable {per}")
+
+
+OUT_CASES = [
+    ("ns_split_kep_roe_lgl5_rotated", inputs.workload(2, N=5), 3, 41),
+    ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
+    ("ns_strong_lgl3_roe_rotated", inputs.workload(2, form="strong", volflux="central", N=3), 3, 42),
+    ("euler_weak_lgl4_llf", inputs.workload(1, nodes="lgl", N=4, curved=True), 3, None),
+]
+
+
+@pytest.mark.parametrize("name,wl,m,seed", OUT_CASES, ids=[c[0] for c in OUT_CASES])
+def test_rhs_parity_outflow_box(dg, orc, name, wl, m, seed):
+    print(f"case {name}", flush=True)
+    M, (X, nbr, side, flip), U = box_problem(orc, wl, m, seed, kind=4)
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=4)
+    ref = M.rhs(orc.Scheme.of(wl), U)
+    got = S.rhs(to_gpu(U)).cpu().numpy()
+    ne, per = check_rhs(got, ref)
+    print(f"normwise {ne:.2e} per-variable {per}")
+
+
+def test_outflow_uniform_flow_and_unset_pressure(dg, orc):
+    wl = inputs.workload(3, N=4)
+    M, (X, nbr, side, flip), _ = box_problem(orc, wl, 3, seed=43, kind=4)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    U0 = inputs.constant_state(M.K, M.n3, p=0.9)
+    with pytest.raises(dg.DGError) as ei:
+        S.rhs(to_gpu(U0))
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError):
+        S.set_outflow_pressure(0.0)
+    S.set_outflow_pressure(0.9)
+    Ut = S.rhs(to_gpu(U0)).cpu().numpy()
+    assert np.abs(Ut).max() < 1e-12 * np.abs(U0).max() * 2 * (wl.N + 1) ** 2 / (math.pi / 3)
+
+
+@pytest.mark.parametrize("seed", [None, 8], ids=["lattice", "rotated"])
+def test_vjp_outflow_elementwise_against_oracle_jacobian(dg, orc, seed):
+    wl = inputs.workload(2, N=2, mach=0.3)
+    M, (X, nbr, side, flip), U0 = box_problem(orc, wl, 2, seed=seed, perturb=2e-2, kind=4)
+    M.set_outflow_pressure(7.5)
+    sc = orc.Scheme.of(wl)
+    n = U0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        _, col = M.rhs_jvp(sc, U0, e.reshape(U0.shape))
+        J[:, j] = col.ravel()
+    S = box_solver(dg, wl, X, nbr, side, flip, kind=4)
+    S.set_outflow_pressure(7.5)
+    rng = np.random.default_rng(8)
+    for _ in range(2):
+        w = rng.standard_normal(U0.shape)
+        got = S.rhs_vjp(to_gpu(U0), to_gpu(w)).cpu().numpy().ravel()
+        ref = J.T @ w.ravel()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"max-norm relative error of J^T w {err:.2e}")
+        assert err <= 1e-12
+
+
+def test_batch_with_outflow_member(dg, orc):
+    import torch
+    wl = inputs.workload(2, N=4)
+    _, (X, nbr, side, flip), Uo = box_problem(orc, wl, 3, seed=44, kind=4)
+    _, (X2, nbr2, side2, flip2), U2 = box_problem(orc, wl, 3, seed=45, kind=3)
+    sols = [box_solver(dg, wl, X, nbr, side, flip, kind=4), box_solver(dg, wl, X2, nbr2, side2, flip2, kind=3)]
+    Us = [to_gpu(Uo), to_gpu(U2)]
+    a, b, _ = dg.rk_coefficients()
+    dts = [Si.timestep(Ui) for Si, Ui in zip(sols, Us)]
+    R0 = [torch.full_like(U, 1e-4) for U in Us]
+    ref = []
+    for Si, Ui, R, dt in zip(sols, Us, R0, dts):
+        out, Rr = Si.empty(), R.clone()
+        Si.rk_stage(Ui, out, Rr, a[3], b[3], dt)
+        ref.append((out, Rr))
+    B = dg.Batch(sols)
+    outs = [Si.empty() for Si in sols]
+    Rs = [R.clone() for R in R0]
+    B.rk_stage(Us, outs, Rs, a[3], b[3], dts)
+    torch.cuda.synchronize()
+    for i, ((ro, rR), o, Rb) in enumerate(zip(ref, outs, Rs)):
+        assert torch.equal(o, ro), f"member {i} U_out differs"
+        assert torch.equal(Rb, rR), f"member {i} R differs"

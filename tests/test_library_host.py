@@ -190,6 +190,7 @@ def test_null_arguments(dg):
     assert L.dg_rk_stage_keep(None, None, None, None, 0.0, 0.0, 0.0, None) == -1
     assert L.dg_set_boundary_state(None, None) == -1
     assert L.dg_set_wall_temperature(None, 1.0) == -1
+    assert L.dg_set_outflow_pressure(None, 1.0) == -1
     assert L.dg_nodes(0, 1, None, None) == -1
     b = ctypes.c_void_p()
     assert L.dg_batch_create(None, 0, ctypes.byref(b)) == -1 and not b.value
@@ -248,7 +249,7 @@ def test_mesh_connect_periodic(dg, k, curved, seed):
         np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 def test_mesh_connect_box(dg, kind):
     """Without periods the outer faces of a box become boundary sides of the requested kind."""
     N, m = 2, 3
@@ -309,3 +310,14 @@ def test_renumbered_mesh_connectivity(dg):
     for a, b in zip(got, (nbs, sds, fls)):
         np.testing.assert_array_equal(a, b)
     dg.host_geometry(Xs, nbs, sds, N, "lgl", flip=fls)
+
+
+def test_outflow_needs_lgl_nodes(dg):
+    N, m = 2, 2
+    lgl, _ = dg.nodes(N, "lgl")
+    X = inputs.lattice_points(lgl, m, m, m, box=(np.pi,) * 3)
+    nbr, side, flip = inputs.box_lattice(m, m, m, kind=4)
+    dg.host_geometry(X, nbr, side, N, "lgl", flip=flip)
+    with pytest.raises(dg.DGError) as ei:
+        dg.host_geometry(X, nbr, side, N, "lg", flip=flip)
+    assert ei.value.code == -3
