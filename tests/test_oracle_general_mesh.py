@@ -317,6 +317,57 @@ def test_isothermal_walls(orc, eqn, form, vf, rs, nodes):
     assert abs(tot[0]) < 1e-13 * scale[0]
 
 
+
+@pytest.mark.parametrize("eqn,form,vf,rs,nodes", [t for t in OCTANT_SCHEMES if t[0] == "ns"])
+def test_isothermal_wall_conducts_linear_profile_exactly(orc, eqn, form, vf, rs, nodes):
+    """Closed form of the wall heat flux (Sec. 2, isothermal wall; reading of its discrete form).
+
+    Fluid at rest at uniform pressure with T = T_w + g x on [0,pi]^3: isothermal wall at x = 0
+    (where T equals T_w), adiabatic walls elsewhere.  T is linear on the affine elements, the
+    lifting has no jump anywhere, so it returns the exact gradient and the energy flux k g is
+    constant: the x = 0 wall passes it without a surface correction (zero rate in its elements)
+    and the blocked flux at the adiabatic x = pi wall is the only imbalance, so the total energy
+    rate is the conductive flux through the isothermal wall, -k g pi^2 (each element at x = pi
+    loses k g h^2), with mass and momentum unchanged.  A mirrored temperature gradient at the isothermal wall, or an outer temperature
+    other than 2 T_w - T, breaks one of these.
+    """
+    N, m = 4, 3
+    lgl = orc.basis(N, "lgl")["x"]
+    X = inputs.lattice_points(lgl, m, m, m, box=(math.pi,) * 3)
+    nbo, sdo, _ = inputs.box_lattice(m, m, m, kind=2)
+    sdo[nbo[:, 0] < 0, 0] = 3
+    rot = np.random.default_rng(14).integers(0, 24, m ** 3)
+    X, nbo, sdo, flo, _ = inputs.rotate_elements(X, nbo, sdo, np.zeros_like(sdo), N, rot)
+    M = orc.OracleMesh(X, nbo, sdo, N, nodes, flip=flo)
+    sc = orc.Scheme(eqn, form, vf, rs, mu=2e-2)
+    P = M.points()
+    assert P.shape == (M.K, 3, M.n3)
+    p, Tw, g = 0.9, 0.75, 0.2
+    T = Tw + g * P[:, 0]
+    U = np.zeros((M.K, 5, M.n3))
+    U[:, 0] = p / (sc.R * T)
+    U[:, 4] = p / (sc.gamma - 1.0)
+    M.set_wall_temperature(Tw)
+    Ut = M.rhs(sc, U)
+    k = sc.mu * sc.gamma * sc.R / ((sc.gamma - 1.0) * sc.Pr)
+    w = orc.basis(N, nodes)["w"]
+    wq = np.einsum("k,j,i->kji", w, w, w).ravel()[None, :] * M.geometry()["J"]
+    tot = np.einsum("eq,evq->v", wq, Ut)
+    h = math.pi / m
+    tol = 1e-12 * (N + 1) ** 2 / h
+    assert abs(tot[4] - (-k * g * math.pi ** 2)) < 1e-11 * k * g * math.pi ** 2
+    assert np.abs(tot[:4]).max() < 1e-12
+    if nodes == "lgl":
+        # On LG nodes each side extrapolates rho = p/(R T), not a polynomial, to the face and
+        # the two values differ, so the Riemann dissipation moves mass between elements; the
+        # temperature (linear) and the energy (constant) stay exact.
+        assert np.abs(Ut[:, :4]).max() < tol
+    far = P[:, 0].max(axis=1) < math.pi - 0.5 * h       # elements off the adiabatic x = pi wall
+    assert far.sum() == m ** 3 - m ** 2
+    assert np.abs(Ut[far, 4]).max() < tol * k * g
+    per_elem = np.einsum("eq,eq->e", wq[~far], Ut[~far, 4])    # each loses k g through its face h^2
+    assert np.abs(per_elem + k * g * h * h).max() < 1e-11 * k * g * h * h
+
 def _outflow_state(U, pout, gamma=1.4):
     G = U.copy()
     G[4] = pout / (gamma - 1.0) + 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
