@@ -50,7 +50,9 @@
 //   * parity unpinned: the outer viscous flux of a given-state side (taken equal to the inner
 //     one) and the tangential part of the surface flux at a no-slip wall (the Riemann
 //     solver's dissipation of the reversed tangential velocity) are readings no closed form
-//     fixes; the tests pin what they imply (uniform flow, rest, conservation), not their values.
+//     fixes; the tests pin what they imply (uniform flow, rest, conservation), not their values,
+//     except for steady linear conduction, where the side's state equals the fluid's trace and
+//     the conducted heat flux is exact.
 //   * the lifted variables are W = (u, v, w, T); viscous fluxes are Newtonian with
 //     Stokes' hypothesis, Fourier heat flux, constant viscosity.
 //   * LLF speed max(|u_n|+c) over both sides; Roe without entropy fix.
