@@ -48,7 +48,8 @@ enum { DG_NODES_LG = 0, DG_NODES_LGL = 1 };
 /* equation system (Sec. 3.1, eq. 3DconsLaw; viscous part via BR1) */
 enum { DG_EULER = 0, DG_NAVIER_STOKES = 1 };
 /* discretisation of the volume integral: weak (eq. semiDiscrete), split flux
- * differencing (eq. semiDiscreteSplit, LGL only), strong (eq. semiDiscreteStrong, LGL only) */
+ * differencing (eq. semiDiscreteSplit, LGL only), strong (eq. semiDiscreteStrong; on LG nodes
+ * the interior flux of the surface term is the volume flux interpolated to the face) */
 enum { DG_FORM_WEAK = 0, DG_FORM_SPLIT = 1, DG_FORM_STRONG = 2 };
 /* two-point volume flux of the split form (Sec. 3.3): kinetic-energy preserving
  * (Pirozzoli), entropy conserving (Chandrashekar), or the mean of the two Euler fluxes */

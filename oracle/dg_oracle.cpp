@@ -20,7 +20,8 @@
 //     gives (the printed ratio is inverted).
 //   * LG prolongation contracts along the face-normal index.
 //   * every face term enters with the outward normal; the strong-form interior term is
-//     F_int . N_out (so -F^1 on the -xi1 face).
+//     F_int . N_out (so -F^1 on the -xi1 face), with F_int the volume flux interpolated to
+//     the face point (on LGL nodes the face node's own flux).
 //   * the split form carries the same -1/J scaling as the weak form.
 //   * geometry: mapping sampled at degree-N LGL nodes, curl form on LGL nodes, exact
 //     interpolation to LG nodes; J = det of the D-derived mapping Jacobian.
@@ -655,8 +656,6 @@ template <class T> static void mirror_W(const T* W, const double* nh, T* G) {
   G[3] = W[3];
 }
 
-// mirror image of the gradients g[d*4+v] = dW_v/dx_d: h = P g P for the velocity block,
-// h = P g for the temperature column
 // pressure outflow: the inner density and velocity with the pressure p_out
 template <class T> static void outflow_state(const T* U, double pout, double gamma, T* G) {
   G[0] = U[0];
@@ -683,6 +682,8 @@ template <class T> static void wall_grad(const T* g, const double* nh, T* h) {
   for (int d = 0; d < 3; ++d) h[d * 4 + 3] = m[d];
 }
 
+// mirror image of the gradients g[d*4+v] = dW_v/dx_d: h = P g P for the velocity block,
+// h = P g for the temperature column
 template <class T> static void mirror_grad(const T* g, const double* nh, T* h) {
   double P[3][3];
   for (int i = 0; i < 3; ++i)
@@ -936,15 +937,25 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
           }
           double sgn = mst ? 1.0 : -1.0;   // outward flux of this element
           double sgo = plus ? 1.0 : -1.0;  // outward sense of xi_dn on this side
+          // strong / split: the interior contravariant flux of direction dn interpolated to the
+          // face point, sum_o l_o(+-1) F_o (eq. semiDiscreteStrong; on LGL nodes this is the
+          // face node's own flux)
+          T Fin[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+          if (S.form != 0) {
+            const std::vector<double>& l = plus ? M.sol.lp : M.sol.lm;
+            for (int m = 0; m < n; ++m) {
+              int q = line_node(n, dn, a, b, m);
+              for (int v = 0; v < 5; ++v)
+                Fin[v] = Fin[v] + T(l[m]) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
+            }
+          }
           for (int m = 0; m < n; ++m) {
             if (lh[m] == 0.0) continue;
             int q = line_node(n, dn, a, b, m);
             for (int v = 0; v < 5; ++v) {
               T pen = T(sgn) * F[v];
-              if (S.form != 0) {
-                // strong / split: minus the interior contravariant flux in the outward direction
-                pen = pen - T(sgo) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
-              }
+              // strong / split: minus the interior flux in the outward direction
+              if (S.form != 0) pen = pen - T(sgo) * Fin[v];
               acc[v * n3 + q] = acc[v * n3 + q] + T(lh[m]) * pen;
             }
           }

@@ -586,7 +586,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!(sc->gamma > 1.0) || !(sc->R > 0.0) || !(sc->Pr > 0.0) || !(sc->mu >= 0.0)) return DG_ERR_ARG;
   int vrc = validate_mesh(mesh, N, node_type);
   if (vrc) return vrc;
-  if (sc->form != DG_FORM_WEAK && node_type != DG_NODES_LGL) return DG_ERR_UNSUPPORTED;
+  if (sc->form == DG_FORM_SPLIT && node_type != DG_NODES_LGL) return DG_ERR_UNSUPPORTED;
   const int K = mesh->n_elems;
   dg_handle *h = new (std::nothrow) dg_handle;
   if (!h) return DG_ERR_OOM;

@@ -722,10 +722,23 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
         const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
         const int ab = a + n * b;
         const double sg = sd ? 1.0 : -1.0;
+        // strong form: the interior flux at the face point, on LG nodes interpolated along the
+        // line with l(+-1) (eq. semiDiscreteStrong), on LGL nodes the face node's own
+        double Ff[5] = {Fint[0], Fint[1], Fint[2], Fint[3], Fint[4]};
+        if (FORM == 2 && !LGL) {
+          const double *lf = sl + (sd ? n : 0);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Ff[v] = 0.0;
+          for (int m = 0; m < n; ++m) {
+            const int qm = base + m * str;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Ff[v] += lf[m] * sX[v * n3 + qm];
+          }
+        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           double pen = sF[(s * 5 + v) * n2 + ab];
-          if (FORM != 0) pen -= sg * Fint[v];
+          if (FORM != 0) pen -= sg * Ff[v];
           acc[v] += lh * pen;
         }
       }
@@ -1390,13 +1403,14 @@ template <int N, bool LGL, bool NS>
 static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, const double *G, double *out,
                        double *R, double a, double b, double dt, int mode, hipStream_t st) {
   if (form == DG_FORM_WEAK) return launch_main_t<N, LGL, NS, 0>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  if (form == DG_FORM_STRONG) return launch_main_t<N, LGL, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
   if (!LGL) return DG_ERR_UNSUPPORTED;
   if (form == DG_FORM_SPLIT) {
     if (ph.vf == DG_VF_EC) return launch_split_t<N, NS, 1>(g, ph, U, G, out, R, a, b, dt, mode, st);
     if (ph.vf == DG_VF_KEP) return launch_split_t<N, NS, 0>(g, ph, U, G, out, R, a, b, dt, mode, st);
     return launch_split_t<N, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
   }
-  return launch_main_t<N, true, NS, 2>(g, ph, U, G, out, R, a, b, dt, mode, st);
+  return DG_ERR_UNSUPPORTED;
 }
 
 template <int N>

@@ -33,6 +33,8 @@ RHS_CASES = [
     ("cfg3_ns_split_ec_roe_lgl7_k3", inputs.workload(3, K1=3), None),
     ("ns_weak_lg4_llf_curved", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4, K1=3), None),
     ("ns_strong_lgl4_roe_curved", inputs.workload(2, form="strong", volflux="central", N=4, K1=3), None),
+    ("ns_strong_lg3_roe_curved", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3, K1=3), None),
+    ("euler_strong_lg5_llf_ragged", inputs.workload(1, form="strong", riemann="llf", N=5), (2, 3, 2)),
     ("euler_split_ec_volflux_roe_lgl6", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=6, K1=2,
                                                         curved=True), None),
     ("ns_split_ec_volflux_lgl3_ragged", inputs.workload(3, riemann="volflux", N=3), (3, 2, 5)),
@@ -171,6 +173,7 @@ def test_full_size_cfg3_sampled(dg, orc):
 @pytest.mark.parametrize("eqn,form,vf,rs,nodes", [
     ("euler", "weak", "central", "llf", "lg"), ("ns", "split", "ec", "roe", "lgl"),
     ("ns", "split", "kep", "roe", "lgl"), ("ns", "strong", "central", "llf", "lgl"),
+    ("ns", "strong", "central", "roe", "lg"),
 ])
 def test_freestream_and_conservation_gpu(dg, orc, eqn, form, vf, rs, nodes):
     wl = inputs.workload(2, eqn=eqn, form=form, volflux=vf, riemann=rs, nodes=nodes, N=4, K1=3)

@@ -40,6 +40,8 @@ SCHEMES = [
     ("ns", "split", "kep", "roe", "lgl"),
     ("ns", "split", "ec", "llf", "lgl"),
     ("ns", "strong", "central", "roe", "lgl"),
+    ("euler", "strong", "central", "llf", "lg"),
+    ("ns", "strong", "central", "roe", "lg"),
 ]
 
 
@@ -73,13 +75,47 @@ def test_conservation_curved(orc, eqn, form, vf, rs, nodes):
     assert np.all(np.abs(tot) < 1e-13 * scale)
 
 
+@pytest.mark.parametrize("nodes", ["lgl", "lg"])
+@pytest.mark.parametrize("curved", [False, True])
 @pytest.mark.parametrize("eqn", ["euler", "ns"])
-def test_weak_equals_strong_lgl(orc, eqn):
-    M = _mesh(orc, 3, 4, "lgl", True)
+def test_weak_equals_strong(orc, eqn, curved, nodes):
+    """Sec. 3.1: weak and strong forms agree discretely on LGL nodes, and on LG nodes when the
+    strong form's interior surface flux is the volume flux interpolated to the face (the
+    summation-by-parts property MD + (MD)^T = l(1)l(1)^T - l(-1)l(-1)^T holds for both)."""
+    M = _mesh(orc, 3, 4 if nodes == "lgl" else 3, nodes, curved)
     U = inputs.random_perturbation(inputs.taylor_green(M.points(), 1.0, 0.3), 6, 1e-2)
     a = M.rhs(orc.Scheme(eqn, "weak", "central", "roe", mu=1e-2), U)
     b = M.rhs(orc.Scheme(eqn, "strong", "central", "roe", mu=1e-2), U)
     assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_kinetic_energy_preservation_constant_pressure(orc, curved):
+    """Split form with a two-point flux whose momentum part is {u} F_rho + p~ n (Jameson's
+    kinetic-energy-preserving structure; both the Pirozzoli and the Chandrashekar flux have it,
+    and p~ = p when the pressure is uniform), no surface dissipation, periodic mesh, uniform
+    pressure, arbitrary density and velocity: the discrete kinetic energy rate
+    sum J w (u . m_t - |u|^2/2 rho_t) vanishes to rounding.  The mean of the Euler fluxes lacks
+    that structure and produces kinetic energy."""
+    M = _mesh(orc, 3, 4, "lgl", curved)
+    rng = np.random.default_rng(21)
+    K, n3 = M.K, M.n3
+    rho = 1.0 + 0.4 * rng.random((K, n3))
+    u = rng.standard_normal((K, 3, n3))
+    p = 2.0
+    U = np.zeros((K, 5, n3))
+    U[:, 0] = rho
+    U[:, 1:4] = rho[:, None] * u
+    U[:, 4] = p / (GAMMA - 1) + 0.5 * rho * (u * u).sum(axis=1)
+    wq = _wq(orc, M)
+    rates = {}
+    for vf in ("kep", "ec", "central"):
+        Ut = M.rhs(orc.Scheme("euler", "split", vf, "volflux"), U)
+        dke = (u * Ut[:, 1:4]).sum(axis=1) - 0.5 * (u * u).sum(axis=1) * Ut[:, 0]
+        scale = np.sum(wq * (np.abs(u * Ut[:, 1:4]).sum(axis=1) + 0.5 * (u * u).sum(axis=1) * np.abs(Ut[:, 0])))
+        rates[vf] = abs(np.sum(wq * dke)) / scale
+    assert rates["kep"] < 1e-13 and rates["ec"] < 1e-13, rates
+    assert rates["central"] > 1e-4, rates
 
 
 def test_split_central_equals_strong_affine(orc):
