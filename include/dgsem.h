@@ -68,14 +68,16 @@ enum { DG_RS_LLF = 0, DG_RS_ROE = 1, DG_RS_VOLFLUX = 2, DG_RS_VOLFLUX_ROE = 3 };
  * DG_BC_WALL_ISOTHERMAL: a no-slip wall at temperature T_w (set with dg_set_wall_temperature):
  * the same outer state, outer (u, v, w, T) = (-u, -v, -w, 2 T_w - T), outer gradient equal to
  * the inner one, so the means give zero velocity, T_w, no work, and the inner heat flux.
- * DG_BC_OUTFLOW: a subsonic pressure outflow (LGL nodes only): outer state with the inner
+ * DG_BC_OUTFLOW: a subsonic pressure outflow: outer state with the inner
  * density and velocity and the pressure p_out (set with dg_set_outflow_pressure), outer viscous
  * flux equal to the inner one. */
 enum { DG_BC_SYMMETRY = 0, DG_BC_STATE = 1, DG_BC_WALL = 2, DG_BC_WALL_ISOTHERMAL = 3, DG_BC_OUTFLOW = 4 };
 
 typedef struct {
   int32_t n_elems;         /* K >= 1                                                        */
-  int32_t n_geo;           /* polynomial degree of the geometry; must equal N               */
+  int32_t n_geo;           /* polynomial degree N_geo of the geometry, 1..16, independent of N
+                              (Sec. 2.1); the mapping is interpolated to the degree-N LGL nodes,
+                              where the curl-form metrics are taken                          */
   const double *xgeo;      /* HOST [K][3][(n_geo+1)^3] physical coordinates at the LGL nodes
                               of degree n_geo (node i + n*(j + n*k))                         */
   const int32_t *nbr_elem; /* HOST [K][6] element across each side, -1 on a boundary side     */
@@ -119,7 +121,7 @@ int dg_rk_coefficients(double *a, double *b, double *c);
  * contravariantBasisVectorsCurl; Jacobian; face normals and surface elements from the
  * master side, Sec. 5.1).  Mesh arrays are copied; they may be freed on return.
  * Supported: 1 <= N <= 8, conforming meshes (faces on any side and in any orientation,
- * symmetry-plane, given-state, adiabatic and isothermal wall, and (LGL) pressure-outflow
+ * symmetry-plane, given-state, adiabatic and isothermal wall, and pressure-outflow
  * boundaries; see dg_mesh).  hip_stream is a
  * hipStream_t (NULL = default stream).  Synchronous.  On error *out is NULL. */
 int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, void *hip_stream,

@@ -252,6 +252,13 @@ struct Mesh {
   std::vector<double> J;           // [e][node]
   std::vector<double> xs;          // [e][3][node] solution-node positions
   std::vector<double> fn;          // [e][s][3][p]: outward scaled normal of side s (master's)
+  // non-conforming faces (Sec. 3.2): mortar kind of every side, 0 conforming, 1..3 the big side of
+  // a mortar of that type, 4 + p the small side at position p (its neighbour fields name the big
+  // element and side, its orientation code maps its face points onto the big side's sub-face p)
+  std::vector<int8_t> mort;        // [e][6], all 0 on conforming meshes
+  std::vector<int32_t> msm;        // [e][6][4] small element at each position of a big side
+  std::vector<int8_t> mss;         // [e][6][4] its side
+  std::vector<double> IL, IU, PL, PU;  // [i*n+m] mortar interpolation / projection matrices
 };
 
 static inline int nid(int n, int i, int j, int k) { return i + n * (j + n * k); }
@@ -277,7 +284,7 @@ static void mate(const Mesh& M, int e, int s, int a, int b, int& a2, int& b2) {
 // whether side s of element e is the master of its face (a boundary side always is)
 static bool is_master(const Mesh& M, int e, int s) {
   const int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
-  if (nb < 0) return true;
+  if (nb < 0 || (!M.mort.empty() && M.mort[e * 6 + s] != 0)) return true;
   const bool plus = (s % 2) == 1, nplus = (ns % 2) == 1;
   if (plus != nplus) return plus;
   return e < nb || (e == nb && s < ns);
@@ -299,8 +306,62 @@ static void apply_dir(const std::vector<ld>& A, int n, int dir, const ld* f, ld*
       }
 }
 
-static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, const int32_t* nbr,
-                       const int8_t* nside, const int8_t* flip) {
+// Geometry of degree ngeo (Sec. 2.1: faces and mapping are polynomials of degree N_geo,
+// independent of N): the mapping sampled at the degree-ngeo LGL nodes is evaluated at the
+// degree-N LGL nodes by tensor-product Lagrange interpolation (exact when ngeo <= N), and the
+// curl form is then taken on the degree-N nodes as for ngeo = N.
+static std::vector<ld> geometry_to_degree_n(int K, int N, int ngeo, const double* xgeo) {
+  const int n = N + 1, n3 = n * n * n, ng = ngeo + 1, ng3 = ng * ng * ng;
+  Basis bg = make_basis(ngeo, 1), bn = make_basis(N, 1);
+  std::vector<ld> V((size_t)n * ng);  // V[i][j] = l^geo_j(x^N_i)
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < ng; ++j) V[(size_t)i * ng + j] = lagrange(bg.xl, bg.laml, j, bn.xl[i]);
+  std::vector<ld> out((size_t)K * 3 * n3);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < K; ++e)
+    for (int d = 0; d < 3; ++d) {
+      const double* f = xgeo + ((size_t)e * 3 + d) * ng3;
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            ld acc = 0;
+            for (int c = 0; c < ng; ++c)
+              for (int b = 0; b < ng; ++b)
+                for (int a = 0; a < ng; ++a)
+                  acc += V[(size_t)i * ng + a] * V[(size_t)j * ng + b] * V[(size_t)k * ng + c] *
+                         (ld)f[a + ng * (b + ng * c)];
+            out[((size_t)e * 3 + d) * n3 + nid(n, i, j, k)] = acc;
+          }
+    }
+  return out;
+}
+
+// number of small sides of a mortar of type t (Sec. 3.2: types 1 and 2 halve the big side in one
+// face direction, type 3 in both)
+static inline int mortar_count(int t) { return t == 3 ? 4 : 2; }
+
+// Mortar operators of the solution nodes (Sec. 3.2): interpolation from the big side to the lower
+// and upper half, I^L_im = l_m((eta_i - 1)/2), I^U_im = l_m((eta_i + 1)/2), and the L2 projection
+// back, P^L_ia = l_i((eta_a - 1)/2) w_a / w_i, P^U likewise.
+static void mortar_matrices(const Basis& b, std::vector<double>& IL, std::vector<double>& IU,
+                            std::vector<double>& PL, std::vector<double>& PU) {
+  const int n = b.n;
+  IL.assign(n * n, 0.0); IU.assign(n * n, 0.0); PL.assign(n * n, 0.0); PU.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < n; ++m) {
+      const ld lo = (b.xl[i] - 1.0L) / 2.0L, hi = (b.xl[i] + 1.0L) / 2.0L;
+      IL[i * n + m] = (double)lagrange(b.xl, b.laml, m, lo);
+      IU[i * n + m] = (double)lagrange(b.xl, b.laml, m, hi);
+      const ld la = (b.xl[m] - 1.0L) / 2.0L, ua = (b.xl[m] + 1.0L) / 2.0L;  // here m plays alpha
+      PL[i * n + m] = (double)(lagrange(b.xl, b.laml, i, la) * b.wl[m] / b.wl[i]);
+      PU[i * n + m] = (double)(lagrange(b.xl, b.laml, i, ua) * b.wl[m] / b.wl[i]);
+    }
+}
+
+// xgeo: the mapping at the degree-N LGL nodes (extended precision); mort: mortar kinds of the sides
+// (NULL on conforming meshes)
+static bool build_mesh(Mesh& M, int K, int N, int type, const ld* xgeo, const int32_t* nbr,
+                       const int8_t* nside, const int8_t* flip, const int8_t* mort) {
   M.K = K; M.N = N; M.n = N + 1; M.n2 = M.n * M.n; M.n3 = M.n2 * M.n; M.type = type;
   const int n = M.n, n2 = M.n2, n3 = M.n3;
   M.sol = make_basis(N, type);
@@ -311,6 +372,30 @@ static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, cons
     M.flip.assign(flip, flip + 6 * (size_t)K);
   else
     M.flip.assign(6 * (size_t)K, 0);
+  if (mort) {
+    M.mort.assign(mort, mort + 6 * (size_t)K);
+    M.msm.assign(24 * (size_t)K, -1);
+    M.mss.assign(24 * (size_t)K, -1);
+    for (int e = 0; e < K; ++e)
+      for (int s = 0; s < 6; ++s) {
+        const int m = M.mort[e * 6 + s];
+        if (m < 4) continue;
+        const int eb = M.nbr[e * 6 + s], sb = M.nside[e * 6 + s];
+        if (eb < 0 || eb >= K || sb < 0 || sb > 5) return false;
+        const int t = M.mort[eb * 6 + sb];
+        if (t < 1 || t > 3 || m - 4 >= mortar_count(t)) return false;
+        M.msm[((size_t)eb * 6 + sb) * 4 + m - 4] = e;
+        M.mss[((size_t)eb * 6 + sb) * 4 + m - 4] = s;
+      }
+    for (int e = 0; e < K; ++e)
+      for (int s = 0; s < 6; ++s) {
+        const int t = M.mort[e * 6 + s];
+        if (t < 1 || t > 3) continue;
+        for (int p = 0; p < mortar_count(t); ++p)
+          if (M.msm[((size_t)e * 6 + s) * 4 + p] < 0) return false;
+      }
+    mortar_matrices(M.sol, M.IL, M.IU, M.PL, M.PU);
+  }
   M.Ja.assign((size_t)K * 9 * n3, 0.0);
   M.J.assign((size_t)K * n3, 0.0);
   M.xs.assign((size_t)K * 3 * n3, 0.0);
@@ -329,9 +414,9 @@ static bool build_mesh(Mesh& M, int K, int N, int type, const double* xgeo, cons
     // no precision
     ld cen[3] = {0, 0, 0};
     for (int d = 0; d < 3; ++d) {
-      for (int q = 0; q < n3; ++q) cen[d] += (ld)xgeo[((size_t)e * 3 + d) * n3 + q];
+      for (int q = 0; q < n3; ++q) cen[d] += xgeo[((size_t)e * 3 + d) * n3 + q];
       cen[d] /= n3;
-      for (int q = 0; q < n3; ++q) xe[d * n3 + q] = (ld)xgeo[((size_t)e * 3 + d) * n3 + q] - cen[d];
+      for (int q = 0; q < n3; ++q) xe[d * n3 + q] = xgeo[((size_t)e * 3 + d) * n3 + q] - cen[d];
     }
     // dx[(d*3+k)] = d x_d / d xi_k on LGL nodes
     for (int d = 0; d < 3; ++d)
@@ -702,6 +787,45 @@ template <class T> static void mirror_grad(const T* g, const double* nh, T* h) {
     }
 }
 
+// ------------------------------------------------------------------ mortars (Sec. 3.2)
+// Operators of sub-face p of a mortar of type t along the big side's two face directions: the
+// interpolation (A1, A2) and projection (B1, B2) matrices, nullptr where the face is not cut.
+static void subface_ops(const Mesh& M, int t, int p, const double*& A1, const double*& A2, const double*& B1,
+                        const double*& B2) {
+  int p1 = -1, p2 = -1;
+  if (t == 1) p1 = p;
+  else if (t == 2) p2 = p;
+  else { p1 = p & 1; p2 = p >> 1; }
+  A1 = p1 < 0 ? nullptr : (p1 ? M.IU.data() : M.IL.data());
+  A2 = p2 < 0 ? nullptr : (p2 ? M.IU.data() : M.IL.data());
+  B1 = p1 < 0 ? nullptr : (p1 ? M.PU.data() : M.PL.data());
+  B2 = p2 < 0 ? nullptr : (p2 ? M.PU.data() : M.PL.data());
+}
+
+// entry (r, c) of an n x n matrix, or of the identity where A is nullptr
+static inline double mat_or_id(const double* A, int n, int r, int c) { return A ? A[r * n + c] : (r == c ? 1.0 : 0.0); }
+
+// field X (nv <= 12 components) of the big side (eb, sb) interpolated to point (a2, b2) of its
+// sub-face p: sum_m sum_l A1[a2][m] A2[b2][l] X^B(m, l)
+template <class T>
+static void subface_trace(const Mesh& M, const T* X, int nv, int eb, int sb, int t, int p, int a2, int b2, T* out) {
+  const double *A1, *A2, *B1, *B2;
+  subface_ops(M, t, p, A1, A2, B1, B2);
+  const int n = M.n;
+  for (int v = 0; v < nv; ++v) out[v] = T(0.0);
+  for (int l = 0; l < n; ++l) {
+    const double c2 = mat_or_id(A2, n, b2, l);
+    if (c2 == 0.0) continue;
+    for (int m = 0; m < n; ++m) {
+      const double c1 = mat_or_id(A1, n, a2, m);
+      if (c1 == 0.0) continue;
+      T q[12];
+      trace(M, X, nv, eb, sb, m, l, q);
+      for (int v = 0; v < nv; ++v) out[v] = out[v] + T(c1) * (T(c2) * q[v]);
+    }
+  }
+}
+
 // BR1 lifting of W = (u,v,w,T) for the elements with need[e] != 0
 template <class T>
 static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vector<char>& need, Work<T>& wk) {
@@ -713,8 +837,12 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
   for (int e = 0; e < K; ++e)
     if (need[e]) {
       needW[e] = 1;
-      for (int s = 0; s < 6; ++s)
+      for (int s = 0; s < 6; ++s) {
         if (M.nbr[e * 6 + s] >= 0) needW[M.nbr[e * 6 + s]] = 1;
+        const int t = M.mort.empty() ? 0 : M.mort[e * 6 + s];
+        if (t >= 1 && t <= 3)
+          for (int p = 0; p < mortar_count(t); ++p) needW[M.msm[((size_t)e * 6 + s) * 4 + p]] = 1;
+      }
     }
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < K; ++e) {
@@ -756,6 +884,58 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
       bool plus = (s % 2) == 1;
       int nb = M.nbr[e * 6 + s];
       const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
+      const int mk = M.mort.empty() ? 0 : M.mort[e * 6 + s];
+      if (mk != 0) {
+        // non-conforming face: on a small side W* takes the big side's trace interpolated to the
+        // sub-face; on the big side the small sides' surface terms W* nt (outward from the small
+        // element) are projected back with P, negated
+        std::vector<T> Lf((size_t)n2 * 12, T(0.0));
+        auto small_term = [&](int es, int ss, int a, int b, T* out12) {
+          const int eb = M.nbr[es * 6 + ss], sb = M.nside[es * 6 + ss];
+          const int t = M.mort[eb * 6 + sb], p = M.mort[es * 6 + ss] - 4;
+          int a2, b2;
+          mate(M, es, ss, a, b, a2, b2);
+          T WL[4], WR[4];
+          trace(M, wk.W.data(), 4, es, ss, a, b, WL);
+          subface_trace(M, wk.W.data(), 4, eb, sb, t, p, a2, b2, WR);
+          const double* nt = &M.fn[((size_t)es * 6 + ss) * 3 * n2];
+          for (int d = 0; d < 3; ++d)
+            for (int v = 0; v < 4; ++v) out12[d * 4 + v] = T(nt[d * n2 + a + n * b]) * (T(0.5) * (WL[v] + WR[v]));
+        };
+        if (mk >= 4) {
+          for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) small_term(e, s, a, b, &Lf[(size_t)(a + n * b) * 12]);
+        } else {
+          for (int p = 0; p < mortar_count(mk); ++p) {
+            const int es = M.msm[((size_t)e * 6 + s) * 4 + p], ss = M.mss[((size_t)e * 6 + s) * 4 + p];
+            const double *A1, *A2, *B1, *B2;
+            subface_ops(M, mk, p, A1, A2, B1, B2);
+            for (int b = 0; b < n; ++b)
+              for (int a = 0; a < n; ++a) {
+                T q[12];
+                small_term(es, ss, a, b, q);
+                int a2, b2;
+                mate(M, es, ss, a, b, a2, b2);
+                for (int jj = 0; jj < n; ++jj)
+                  for (int ii = 0; ii < n; ++ii) {
+                    const double c = mat_or_id(B1, n, ii, a2) * mat_or_id(B2, n, jj, b2);
+                    if (c == 0.0) continue;
+                    for (int k12 = 0; k12 < 12; ++k12)
+                      Lf[(size_t)(ii + n * jj) * 12 + k12] = Lf[(size_t)(ii + n * jj) * 12 + k12] - T(c) * q[k12];
+                  }
+              }
+          }
+        }
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a)
+            for (int m = 0; m < n; ++m) {
+              if (lh[m] == 0.0) continue;
+              int q = line_node(n, dn, a, b, m);
+              for (int c = 0; c < 12; ++c)
+                acc[c * n3 + q] = acc[c * n3 + q] + T(lh[m]) * Lf[(size_t)(a + n * b) * 12 + c];
+            }
+        continue;
+      }
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
           T WL[4], WR[4];
@@ -815,8 +995,12 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
     for (int e = 0; e < K; ++e)
       if (out_mask[e]) {
         need[e] = 1;
-        for (int s = 0; s < 6; ++s)
+        for (int s = 0; s < 6; ++s) {
           if (M.nbr[e * 6 + s] >= 0) need[M.nbr[e * 6 + s]] = 1;
+          const int t = M.mort.empty() ? 0 : M.mort[e * 6 + s];
+          if (t >= 1 && t <= 3)
+            for (int p = 0; p < mortar_count(t); ++p) need[M.msm[((size_t)e * 6 + s) * 4 + p]] = 1;
+        }
       }
     lifting(M, S, U, need, wk);
   }
@@ -886,8 +1070,86 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
       int nb = M.nbr[e * 6 + s], ns_ = M.nside[e * 6 + s];
       const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
       const bool mst = is_master(M, e, s);
+      const int mk = M.mort.empty() ? 0 : M.mort[e * 6 + s];
+      // non-conforming face: outward flux of every face point of this side (on a big side the
+      // projection of the small sides' fluxes, negated)
+      std::vector<T> Fm;
+      if (mk != 0) {
+        Fm.assign((size_t)n2 * 5, T(0.0));
+        auto small_flux = [&](int es, int ss, int a, int b, T* F) {
+          // the small side is the master of its part of the face: its own normal and surface
+          // element, its own state first, the big side's traces interpolated to the sub-face
+          const int eb = M.nbr[es * 6 + ss], sb = M.nside[es * 6 + ss];
+          const int t = M.mort[eb * 6 + sb], p = M.mort[es * 6 + ss] - 4;
+          int a2, b2;
+          mate(M, es, ss, a, b, a2, b2);
+          const double* ntp = &M.fn[((size_t)es * 6 + ss) * 3 * n2];
+          double nt[3] = {ntp[a + n * b], ntp[n2 + a + n * b], ntp[2 * n2 + a + n * b]};
+          double sh = std::sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+          double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
+          T UM[5], US[5];
+          trace(M, U, 5, es, ss, a, b, UM);
+          subface_trace(M, U, 5, eb, sb, t, p, a2, b2, US);
+          riemann(UM, US, nh, S, F);
+          for (int v = 0; v < 5; ++v) F[v] = F[v] * T(sh);
+          if (ns) {
+            T gM[12], gS[12], FvM[5], FvS[5];
+            trace(M, wk.G.data(), 12, es, ss, a, b, gM);
+            subface_trace(M, wk.G.data(), 12, eb, sb, t, p, a2, b2, gS);
+            Prim<T> PM = prim(UM, S.gamma), PS = prim(US, S.gamma);
+            viscous_flux(PM, gM, S, nt, FvM);
+            viscous_flux(PS, gS, S, nt, FvS);
+            for (int v = 0; v < 5; ++v) F[v] = F[v] - T(0.5) * (FvM[v] + FvS[v]);
+          }
+        };
+        if (mk >= 4) {
+          for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) small_flux(e, s, a, b, &Fm[(size_t)(a + n * b) * 5]);
+        } else {
+          for (int p = 0; p < mortar_count(mk); ++p) {
+            const int es = M.msm[((size_t)e * 6 + s) * 4 + p], ss = M.mss[((size_t)e * 6 + s) * 4 + p];
+            const double *A1, *A2, *B1, *B2;
+            subface_ops(M, mk, p, A1, A2, B1, B2);
+            for (int b = 0; b < n; ++b)
+              for (int a = 0; a < n; ++a) {
+                T f[5];
+                small_flux(es, ss, a, b, f);
+                int a2, b2;
+                mate(M, es, ss, a, b, a2, b2);
+                for (int jj = 0; jj < n; ++jj)
+                  for (int ii = 0; ii < n; ++ii) {
+                    const double c = mat_or_id(B1, n, ii, a2) * mat_or_id(B2, n, jj, b2);
+                    if (c == 0.0) continue;
+                    for (int v = 0; v < 5; ++v) Fm[(size_t)(ii + n * jj) * 5 + v] = Fm[(size_t)(ii + n * jj) * 5 + v] - T(c) * f[v];
+                  }
+              }
+          }
+        }
+      }
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
+          if (mk != 0) {
+            double sgo = plus ? 1.0 : -1.0;
+            T Fin[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+            if (S.form != 0) {
+              const std::vector<double>& l = plus ? M.sol.lp : M.sol.lm;
+              for (int m = 0; m < n; ++m) {
+                int q = line_node(n, dn, a, b, m);
+                for (int v = 0; v < 5; ++v)
+                  Fin[v] = Fin[v] + T(l[m]) * (Fc[(dn * 5 + v) * n3 + q] - Fv[(dn * 5 + v) * n3 + q]);
+              }
+            }
+            for (int m = 0; m < n; ++m) {
+              if (lh[m] == 0.0) continue;
+              int q = line_node(n, dn, a, b, m);
+              for (int v = 0; v < 5; ++v) {
+                T pen = Fm[(size_t)(a + n * b) * 5 + v];
+                if (S.form != 0) pen = pen - T(sgo) * Fin[v];
+                acc[v * n3 + q] = acc[v * n3 + q] + T(lh[m]) * pen;
+              }
+            }
+            continue;
+          }
           // the master's flux along the master's normal; the slave takes it negated
           int a2, b2;
           mate(M, e, s, a, b, a2, b2);
@@ -1009,11 +1271,41 @@ int orc_basis(int N, int type, double* x, double* w, double* D, double* Dhat, do
   return 0;
 }
 
+// as orc_create, with the mapping sampled at the LGL nodes of degree ngeo: xgeo [K][3][(ngeo+1)^3],
+// and (mort != NULL) non-conforming faces: mortar kind [K][6] of every side (0 conforming, 1..3
+// big side of that type, 4 + p small side at position p naming the big element and side)
+orc_handle* orc_create_mesh(int K, int N, int ngeo, int type, const double* xgeo, const int32_t* nbr,
+                            const int8_t* nside, const int8_t* flip, const int8_t* mort) {
+  if (ngeo < 1 || ngeo > 16) return nullptr;
+  std::vector<ld> xn;
+  if (ngeo == N)
+    xn.assign(xgeo, xgeo + (size_t)K * 3 * (N + 1) * (N + 1) * (N + 1));
+  else
+    xn = geometry_to_degree_n(K, N, ngeo, xgeo);
+  orc_handle* h = new orc_handle;
+  if (!build_mesh(h->M, K, N, type, xn.data(), nbr, nside, flip, mort)) { delete h; return nullptr; }
+  return h;
+}
+
+orc_handle* orc_create_geo(int K, int N, int ngeo, int type, const double* xgeo, const int32_t* nbr,
+                           const int8_t* nside, const int8_t* flip) {
+  return orc_create_mesh(K, N, ngeo, type, xgeo, nbr, nside, flip, nullptr);
+}
+
 orc_handle* orc_create(int K, int N, int type, const double* xgeo, const int32_t* nbr, const int8_t* nside,
                        const int8_t* flip) {
-  orc_handle* h = new orc_handle;
-  if (!build_mesh(h->M, K, N, type, xgeo, nbr, nside, flip)) { delete h; return nullptr; }
-  return h;
+  return orc_create_mesh(K, N, N, type, xgeo, nbr, nside, flip, nullptr);
+}
+
+// the mortar matrices of degree N on the node set type: I^L, I^U, P^L, P^U, each n x n row-major
+int orc_mortar_matrices(int N, int type, double* IL, double* IU, double* PL, double* PU) {
+  if (N < 1 || N > 16) return -1;
+  Basis b = make_basis(N, type);
+  std::vector<double> a, c, d, e;
+  mortar_matrices(b, a, c, d, e);
+  std::copy(a.begin(), a.end(), IL); std::copy(c.begin(), c.end(), IU);
+  std::copy(d.begin(), d.end(), PL); std::copy(e.begin(), e.end(), PU);
+  return 0;
 }
 
 void orc_destroy(orc_handle* h) { delete h; }

@@ -46,6 +46,11 @@ def lib():
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int] + [_D] * 6
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _I32, _I8, _I8]
+        L.orc_create_geo.restype = ctypes.c_void_p
+        L.orc_create_geo.argtypes = [ctypes.c_int] * 4 + [_D, _I32, _I8, _I8]
+        L.orc_create_mesh.restype = ctypes.c_void_p
+        L.orc_create_mesh.argtypes = [ctypes.c_int] * 4 + [_D, _I32, _I8, _I8, _I8]
+        L.orc_mortar_matrices.argtypes = [ctypes.c_int, ctypes.c_int] + [_D] * 4
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_set_boundary_state.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_wall_temperature.argtypes = [ctypes.c_void_p, ctypes.c_double]
@@ -94,6 +99,15 @@ def basis(N: int, nodes: str):
     return dict(x=x, w=w, D=D, Dhat=Dh, lm=lm, lp=lp)
 
 
+def mortar_matrices(N: int, nodes: str):
+    """The mortar operators of Sec. 3.2 on the solution nodes: (I^L, I^U, P^L, P^U), n x n each."""
+    n = N + 1
+    IL, IU, PL, PU = (np.zeros((n, n)) for _ in range(4))
+    if lib().orc_mortar_matrices(N, NODES[nodes], _p(IL), _p(IU), _p(PL), _p(PU)):
+        raise ValueError("unsupported N")
+    return IL, IU, PL, PU
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 
@@ -126,17 +140,28 @@ class OracleMesh:
     neighbour's face point matching face point (a, b) is reached by swapping (a, b) if bit 2
     is set, then reversing the first index if bit 0 and the second if bit 1 is set."""
 
-    def __init__(self, xgeo, nbr, nside, N: int, nodes: str, flip=None):
+    def __init__(self, xgeo, nbr, nside, N: int, nodes: str, flip=None, ngeo=None, mortar=None):
+        """``xgeo[K,3,(ngeo+1)^3]``: the mapping sampled at the LGL nodes of degree ``ngeo``
+        (default N; Sec. 2.1: the geometry degree is independent of N).  ``mortar[K,6]``
+        (optional): non-conforming faces (Sec. 3.2), 0 conforming side, 1..3 the big side of a
+        mortar of that type, 4 + p the small side at position p (its neighbour entries name the
+        big element and side, its orientation code maps onto the big side's sub-face p)."""
         xgeo = _c(xgeo)
         self.K = xgeo.shape[0]
         self.N, self.n = N, N + 1
         self.n3 = self.n ** 3
         self.nodes = nodes
+        self.ngeo = N if ngeo is None else int(ngeo)
+        if xgeo.shape[-1] != (self.ngeo + 1) ** 3:
+            raise ValueError("xgeo does not hold (ngeo+1)^3 points per element")
         nbr = _c(nbr, np.int32)
         nside = _c(nside, np.int8)
         self._flip = None if flip is None else _c(flip, np.int8)
         fl = None if self._flip is None else self._flip.ctypes.data_as(_I8)
-        h = lib().orc_create(self.K, N, NODES[nodes], _p(xgeo), nbr.ctypes.data_as(_I32), nside.ctypes.data_as(_I8), fl)
+        self._mortar = None if mortar is None else _c(mortar, np.int8)
+        mo = None if self._mortar is None else self._mortar.ctypes.data_as(_I8)
+        h = lib().orc_create_mesh(self.K, N, self.ngeo, NODES[nodes], _p(xgeo), nbr.ctypes.data_as(_I32),
+                                  nside.ctypes.data_as(_I8), fl, mo)
         if not h:
             raise ValueError("oracle: invalid mesh (J <= 0)")
         self.h = ctypes.c_void_p(h)

@@ -191,6 +191,32 @@ void tensor_apply(const xf *A, int n, int dir, const xf *x, xf *y) {
       }
 }
 
+// y (n^3) = x (ng^3) interpolated along every direction with the n x ng matrix A
+void tensor_interp(const xf *A, int n, int ng, const xf *x, xf *y) {
+  std::vector<xf> t1((size_t)n * ng * ng), t2((size_t)n * n * ng);
+  for (int c = 0; c < ng; ++c)
+    for (int b = 0; b < ng; ++b)
+      for (int i = 0; i < n; ++i) {
+        xf s = 0.0L;
+        for (int a = 0; a < ng; ++a) s += A[i * ng + a] * x[a + ng * (b + ng * c)];
+        t1[i + n * (b + ng * c)] = s;
+      }
+  for (int c = 0; c < ng; ++c)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        xf s = 0.0L;
+        for (int b = 0; b < ng; ++b) s += A[j * ng + b] * t1[i + n * (b + ng * c)];
+        t2[i + n * (j + n * c)] = s;
+      }
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        xf s = 0.0L;
+        for (int c = 0; c < ng; ++c) s += A[k * ng + c] * t2[i + n * (j + n * c)];
+        y[i + n * (j + n * k)] = s;
+      }
+}
+
 struct HostGeo {
   std::vector<double> Ja, J, sJ, xs, fn;
 };
@@ -218,10 +244,20 @@ inline bool face_master(int e, int s, int nb, int ns) {
   return e < nb || (e == nb && s < ns);
 }
 
-int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nbr, const int8_t *nside,
+// xgeo holds the mapping at the LGL nodes of degree ngeo (Sec. 2.1: the geometry degree N_geo is
+// independent of N); it is interpolated to the degree-N LGL nodes, where the curl form is taken
+int build_geometry(int K, int N, int ngeo, int type, const double *xgeo, const int32_t *nbr, const int8_t *nside,
                    const int8_t *flip, HostGeo &G, std::string &msg) {
   const int n = N + 1, n2 = n * n, n3 = n2 * n;
+  const int ng = ngeo + 1, ng3 = ng * ng * ng;
   const Basis1D L = make_basis(N, DG_NODES_LGL);
+  std::vector<xf> Vg;  // degree-ngeo LGL -> degree-N LGL nodes, n x ng
+  if (ngeo != N) {
+    const Basis1D Bg = make_basis(ngeo, DG_NODES_LGL);
+    Vg.resize((size_t)n * ng);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < ng; ++j) Vg[(size_t)i * ng + j] = lag_eval(Bg.x, Bg.bw, j, L.x[i]);
+  }
   const Basis1D S = (type == DG_NODES_LGL) ? L : make_basis(N, type);
   std::vector<xf> V(n * n);  // LGL -> solution nodes
   for (int i = 0; i < n; ++i)
@@ -240,7 +276,7 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
   std::vector<double> badv(nthr, 0.0);
   auto work = [&](unsigned tid) {
   std::vector<xf> X(3 * n3), dx(9 * n3), prod(3 * n3), c1(n3), c2(n3), JaL(9 * n3), Jas(9 * n3), t1(n3), t2(n3),
-      xs(3 * n3), jac(9 * n3);
+      xs(3 * n3), jac(9 * n3), xg(ng3);
   const int e0 = (int)((size_t)K * tid / nthr), e1 = (int)((size_t)K * (tid + 1) / nthr);
   for (int e = e0; e < e1; ++e) {
     // work relative to the element centroid; the curl form is translation invariant and the
@@ -248,9 +284,14 @@ int build_geometry(int K, int N, int type, const double *xgeo, const int32_t *nb
     xf c0[3];
     for (int d = 0; d < 3; ++d) {
       xf acc = 0.0L;
-      for (int q = 0; q < n3; ++q) acc += xgeo[((size_t)e * 3 + d) * n3 + q];
-      c0[d] = acc / n3;
-      for (int q = 0; q < n3; ++q) X[d * n3 + q] = xgeo[((size_t)e * 3 + d) * n3 + q] - c0[d];
+      for (int q = 0; q < ng3; ++q) acc += xgeo[((size_t)e * 3 + d) * ng3 + q];
+      c0[d] = acc / ng3;
+      if (ngeo == N) {
+        for (int q = 0; q < n3; ++q) X[d * n3 + q] = xgeo[((size_t)e * 3 + d) * n3 + q] - c0[d];
+      } else {
+        for (int q = 0; q < ng3; ++q) xg[q] = xgeo[((size_t)e * 3 + d) * ng3 + q] - c0[d];
+        tensor_interp(Vg.data(), n, ng, xg.data(), &X[d * n3]);
+      }
     }
     // dx[m*3+k] = d x_m / d xi_k on the LGL sample
     for (int m = 0; m < 3; ++m)
@@ -371,7 +412,7 @@ std::vector<uint8_t> face_codes(const dg_mesh *mesh) {
 int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   if (!mesh || !mesh->xgeo || !mesh->nbr_elem || !mesh->nbr_side) return DG_ERR_ARG;
   if (N < 1 || N > NMAX) return DG_ERR_UNSUPPORTED;
-  if (mesh->n_geo != N) return DG_ERR_UNSUPPORTED;
+  if (mesh->n_geo < 1 || mesh->n_geo > 2 * NMAX) return DG_ERR_UNSUPPORTED;
   if (node_type != DG_NODES_LG && node_type != DG_NODES_LGL) return DG_ERR_ARG;
   if (mesh->n_elems < 1) return DG_ERR_ARG;
   const int K = mesh->n_elems;
@@ -384,7 +425,6 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
       const int o = mesh->flip ? mesh->flip[q] : 0;
       if (nb == -1) {
         if (ns < DG_BC_SYMMETRY || ns > DG_BC_OUTFLOW) return DG_ERR_UNSUPPORTED;
-        if (ns == DG_BC_OUTFLOW && node_type != DG_NODES_LGL) return DG_ERR_UNSUPPORTED;
         if (o != 0) return DG_ERR_MESH;
         continue;
       }
@@ -394,8 +434,9 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
       if (mesh->nbr_elem[qn] != e || mesh->nbr_side[qn] != s) return DG_ERR_MESH;
       if ((mesh->flip ? mesh->flip[qn] : 0) != orientation_inverse(o)) return DG_ERR_MESH;
     }
-  // the matched face points coincide up to one translation per face (a periodic shift)
-  const int n = N + 1, n3 = n * n * n;
+  // the matched face points coincide up to one translation per face (a periodic shift); the
+  // faces are compared at the geometry's own nodes
+  const int NG = mesh->n_geo, n = NG + 1, n3 = n * n * n;
   for (int e = 0; e < K; ++e) {
     const double *xe = mesh->xgeo + (size_t)e * 3 * n3;
     double ext = 0.0;
@@ -412,7 +453,7 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
           int a2, b2;
-          face_mate(o, N, a, b, a2, b2);
+          face_mate(o, NG, a, b, a2, b2);
           const int qe = face_point_node(n, s, a, b), qn = face_point_node(n, ns, a2, b2);
           for (int d = 0; d < 3; ++d) {
             const double dx = xe[d * n3 + qe] - xn[d * n3 + qn];
@@ -608,7 +649,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   }
   HostGeo G;
   std::string msg;
-  int rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
+  int rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
   if (rc) { delete h; return rc; }
   const std::vector<uint8_t> fc = face_codes(mesh);
   for (int q = 0; q < 6 * K; ++q)
@@ -649,7 +690,7 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
   const int K = mesh->n_elems, n = N + 1;
   HostGeo G;
   std::string msg;
-  rc = build_geometry(K, N, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
+  rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
   if (rc) return rc;
   if (Ja) std::memcpy(Ja, G.Ja.data(), G.Ja.size() * sizeof(double));
   if (J) std::memcpy(J, G.J.data(), G.J.size() * sizeof(double));

@@ -359,11 +359,23 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       for (int v = 0; v < 3; ++v) WR[v] = -WL[v];
       WR[3] = 2.0 * ph.tw - WL[3];
     } else if (GEN && f.bnd && f.kind == DG_BC_OUTFLOW) {
-      // pressure outflow (LGL nodes): the own trace's density and velocity with p_out
-      const int q = line_node<n>(dn, a, b, plus ? N : 0);
+      // pressure outflow: the own trace's density and velocity with p_out (the conservative
+      // trace: the face node on LGL nodes, interpolated with l(+-1) on LG nodes)
       double Uq[5];
+      if (LGL) {
+        const int q = line_node<n>(dn, a, b, plus ? N : 0);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + q];
+        for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + q];
+      } else {
+        const double *lo = sl + (plus ? n : 0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Uq[v] = 0.0;
+        for (int m = 0; m < n; ++m) {
+          const int q = line_node<n>(dn, a, b, m);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Uq[v] += lo[m] * Ue[v * n3 + q];
+        }
+      }
       Uq[4] = ph.pout / gm1 + 0.5 * (Uq[1] * Uq[1] + Uq[2] * Uq[2] + Uq[3] * Uq[3]) / Uq[0];
       grad_prim_to_W(Uq, gm1, ph.R, WR);
     } else if (GEN && f.bnd) {

@@ -162,14 +162,23 @@ def mesh_sfc_order(xgeo, N: int):
     return order
 
 
-def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None):
-    """dg_init's geometry and 1D tables computed on the host only (no device needed)."""
+def _geo_degree(xgeo, N, ngeo):
+    ng = N if ngeo is None else int(ngeo)
+    if round(xgeo.shape[-1] ** (1.0 / 3.0)) ** 3 != xgeo.shape[-1] or xgeo.shape[-1] != (ng + 1) ** 3:
+        raise ValueError("xgeo must hold (ngeo+1)^3 points per element")
+    return ng
+
+
+def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None, ngeo=None):
+    """dg_init's geometry and 1D tables computed on the host only (no device needed).
+    ``xgeo[K,3,(ngeo+1)^3]``: the mapping at the LGL nodes of degree ``ngeo`` (default N)."""
     xgeo = np.ascontiguousarray(xgeo, np.float64)
     nbr = np.ascontiguousarray(nbr, np.int32)
     nside = np.ascontiguousarray(nside, np.int8)
     flip = None if flip is None else np.ascontiguousarray(flip, np.int8)
     K, n = xgeo.shape[0], N + 1
-    m = _Mesh(K, N, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+    ng = _geo_degree(xgeo, N, ngeo)
+    m = _Mesh(K, ng, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
               nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
               None if flip is None else flip.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
     Ja, J, fn = np.zeros((K, 9, n ** 3)), np.zeros((K, n ** 3)), np.zeros((K, 6, 3, n * n))
@@ -191,17 +200,18 @@ class DGSolver:
     """One mesh + scheme on the GPU (a ``dg_handle``)."""
 
     def __init__(self, xgeo, nbr, nside, N: int, nodes_: str, eqn="ns", form="split", volflux="kep",
-                 riemann="roe", gamma=1.4, R=1.0, mu=0.0, Pr=0.72, flip=None, stream=None):
+                 riemann="roe", gamma=1.4, R=1.0, mu=0.0, Pr=0.72, flip=None, stream=None, ngeo=None):
         import torch
         self.torch = torch
         xgeo = np.ascontiguousarray(xgeo, np.float64)
         nbr = np.ascontiguousarray(nbr, np.int32)
         nside = np.ascontiguousarray(nside, np.int8)
         K = xgeo.shape[0]
-        if xgeo.shape != (K, 3, (N + 1) ** 3) or nbr.shape != (K, 6) or nside.shape != (K, 6):
+        ng = N if ngeo is None else int(ngeo)
+        if xgeo.shape != (K, 3, (ng + 1) ** 3) or nbr.shape != (K, 6) or nside.shape != (K, 6):
             raise ValueError("mesh arrays have inconsistent shapes")
         flip_arr = None if flip is None else np.ascontiguousarray(flip, np.int8)
-        m = _Mesh(K, N, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        m = _Mesh(K, ng, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                   nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                   None if flip_arr is None else flip_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
         sc = _Scheme(EQN[eqn], FORM[form], VF[volflux], RS[riemann], gamma, R, mu, Pr)

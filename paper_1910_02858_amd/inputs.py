@@ -207,6 +207,206 @@ def renumber_elements(X, nbr, side, flip, order):
             np.ascontiguousarray(np.asarray(flip)[order]))
 
 
+# ----------------------------------------------------------------------------- non-conforming
+# Mortar kinds of a side (Sec. 3.2): 0 conforming; 1, 2, 3 the big side of a non-conforming face
+# cut in half along the side's first face direction (1), its second (2), or both (3); 4 + p the
+# small side at position p of such a face: p along the cut for types 1 and 2, p = p1 + 2 p2
+# (p1 along the first, p2 along the second face direction) for type 3.  Face point (a, b) of a
+# side runs along the element's two other directions in increasing order; on a small side the
+# orientation code maps it to the point of the big side's sub-face p, whose own (a', b') run
+# along the big side's face directions.
+MORTAR_SUBFACES = {1: [((-1, 0), (-1, 1)), ((0, 1), (-1, 1))],
+                   2: [((-1, 1), (-1, 0)), ((-1, 1), (0, 1))],
+                   3: [((-1, 0), (-1, 0)), ((0, 1), (-1, 0)), ((-1, 0), (0, 1)), ((0, 1), (0, 1))]}
+
+
+def refined_lattice(nodes_1d, k, split=(2, 2, 2), refine=None, box=(TWO_PI, TWO_PI, TWO_PI)):
+    """Undeformed node positions ``X[e][3][n^3]`` of a ``k^3`` (or ``kx*ky*kz``) lattice on ``box`` whose cells with
+    ``refine(ex, ey, ez)`` true (default: the half ``ex < k/2``) are split into ``split`` children
+    per direction (1 or 2 each); the other cells stay whole.  Whole cells come first in
+    lexicographic order, then the children of every refined cell (lexicographic, child x fastest).
+    Where a refined cell meets a whole one the faces are non-conforming."""
+    kx, ky, kz = (k, k, k) if np.isscalar(k) else tuple(k)
+    if refine is None:
+        def refine(ex, ey, ez):
+            return ex < kx // 2
+    r = np.asarray(nodes_1d, dtype=np.float64)
+    n = r.size
+    t = 0.5 * (r + 1.0)
+    tk, tj, ti = np.meshgrid(t, t, t, indexing="ij")
+    tt = np.stack([ti.ravel(), tj.ravel(), tk.ravel()])  # [3][n^3]
+    h = np.array(box, np.float64) / np.array([kx, ky, kz], np.float64)
+    whole, fine = [], []
+    for ez in range(kz):
+        for ey in range(ky):
+            for ex in range(kx):
+                lo = np.array([ex, ey, ez], np.float64) * h
+                if not refine(ex, ey, ez):
+                    whole.append((lo, h))
+                    continue
+                hc = h / np.array(split, np.float64)
+                for cz in range(split[2]):
+                    for cy in range(split[1]):
+                        for cx in range(split[0]):
+                            fine.append((lo + np.array([cx, cy, cz]) * hc, hc))
+    cells = whole + fine
+    X = np.empty((len(cells), 3, n ** 3), np.float64)
+    for e, (lo, hh) in enumerate(cells):
+        X[e] = lo[:, None] + hh[:, None] * tt
+    return X
+
+
+def warp_bubble(X, amp: float = 0.1, degree: int = 2):
+    """Curved map ``x_d = X_d + amp * prod_c b(X_c)`` for every d, with the bubble
+    ``b(t) = t(2pi - t)/pi^2`` (degree 2) or ``b(t) = t(2pi - t)(t - pi)/pi^3 * 2.6`` (degree 3).
+    It is a polynomial of that degree in each coordinate, so every cell of an affine lattice maps
+    to a polynomial element of that degree, children of a refined cell are exact restrictions of
+    their parent, and it vanishes on the faces of ``[0, 2pi]^3`` (periodic meshes stay periodic)."""
+    X = np.asarray(X)
+    if degree == 2:
+        b = X * (TWO_PI - X) / math.pi ** 2
+    else:
+        b = 2.6 * X * (TWO_PI - X) * (X - math.pi) / math.pi ** 3
+    s = amp * b[:, 0] * b[:, 1] * b[:, 2]
+    return X + s[:, None, :]
+
+
+def _face_corners(X, n):
+    """Corner positions [K][6][4][3] of every side in face-point order (a, b) = (0,0), (N,0),
+    (0,N), (N,N), from the element nodes."""
+    N = n - 1
+    K = X.shape[0]
+    out = np.empty((K, 6, 4, 3))
+    for s in range(6):
+        d, plus = s // 2, s % 2
+        for c, (a, b) in enumerate(((0, 0), (N, 0), (0, N), (N, N))):
+            idx = [0, 0, 0]
+            da, db = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+            idx[d], idx[da], idx[db] = (N if plus else 0), a, b
+            q = idx[0] + n * (idx[1] + n * idx[2])
+            out[:, s, c, :] = X[:, :, q]
+    return out
+
+
+def _orient(src, dst, tol):
+    """Orientation code o (swap the face indices if o & 4, then reverse the first if o & 1 and the
+    second if o & 2) that carries the corners src[(a,b)] onto dst[(a',b')], or None."""
+    pos = ((0, 0), (1, 0), (0, 1), (1, 1))
+    for o in range(8):
+        ok = True
+        for c, (a, b) in enumerate(pos):
+            p, q = (b, a) if o & 4 else (a, b)
+            a2 = 1 - p if o & 1 else p
+            b2 = 1 - q if o & 2 else q
+            if np.abs(src[c] - dst[pos.index((a2, b2))]).max() > tol:
+                ok = False
+                break
+        if ok:
+            return o
+    return None
+
+
+def connect_boxes(X, n: int, period=(TWO_PI, TWO_PI, TWO_PI), bc_kind: int = 0):
+    """Connectivity of a hexahedral mesh of straight-sided cells (undeformed coordinates, any
+    reference-axis orientation) by matching face corners, including non-conforming faces whose
+    big side is cut in half in one or both face directions: returns ``(nbr[K,6], side[K,6],
+    flip[K,6], mortar[K,6])`` in the conventions of :data:`MORTAR_SUBFACES`.  A big side has
+    ``nbr = -1``, ``side = 0``, ``flip = 0``; a small side names the big element and side.  Along
+    directions with a positive ``period`` coordinates are compared modulo the period; unmatched
+    sides become boundaries of kind ``bc_kind``."""
+    X = np.asarray(X, np.float64)
+    K = X.shape[0]
+    C = _face_corners(X, n)
+    ext = np.abs(C.max(axis=2) - C.min(axis=2)).max()
+    tol = 1e-9 * max(ext, 1e-300)
+    per = np.array([p if p and p > 0 else 0.0 for p in period]) if period is not None else np.zeros(3)
+
+    def wrap(P):
+        P = P.copy()
+        for d in range(3):
+            if per[d] > 0:
+                P[..., d] = np.mod(P[..., d] + 0.5 * tol, per[d]) - 0.5 * tol
+        return P
+
+    def key(P):
+        c = wrap(P).mean(axis=0)
+        return tuple(np.round(c / (1e4 * tol)).astype(np.int64))
+
+    def same(A, B):
+        # corner sets equal up to the periodic shift
+        dA, dB = wrap(A), wrap(B)
+        return all(any(np.abs(a - b).max() < 1e3 * tol or
+                       all(per[d] > 0 and abs(abs(a[d] - b[d]) - per[d]) < 1e3 * tol or abs(a[d] - b[d]) < 1e3 * tol
+                           for d in range(3)) for b in dB) for a in dA)
+
+    faces = {}
+    for e in range(K):
+        for s in range(6):
+            faces.setdefault(key(C[e, s]), []).append((e, s))
+    nbr = np.full((K, 6), -1, np.int32)
+    side = np.zeros((K, 6), np.int8)
+    flip = np.zeros((K, 6), np.int8)
+    mortar = np.zeros((K, 6), np.int8)
+
+    def corners_wrapped_to(A, B):
+        # shift A by whole periods so that its corners sit next to B's
+        A = A.copy()
+        for d in range(3):
+            if per[d] > 0:
+                A[:, d] += per[d] * np.round((B[:, d].mean() - A[:, d].mean()) / per[d])
+        return A
+
+    for e in range(K):
+        for s in range(6):
+            for (e2, s2) in faces[key(C[e, s])]:
+                if (e2, s2) == (e, s):
+                    continue
+                A = corners_wrapped_to(C[e, s], C[e2, s2])
+                o = _orient(A, C[e2, s2], 1e3 * tol)
+                if o is not None:
+                    nbr[e, s], side[e, s], flip[e, s] = e2, s2, o
+    # non-conforming faces: sub-faces of unmatched sides
+    for e in range(K):
+        for s in range(6):
+            if nbr[e, s] >= 0:
+                continue
+            c = C[e, s]  # corners at (eta1, eta2) = (-1,-1), (1,-1), (-1,1), (1,1)
+
+            def at(u, v):
+                # bilinear point of the (planar, straight-sided) face at reference (u, v)
+                return 0.25 * ((1 - u) * (1 - v) * c[0] + (1 + u) * (1 - v) * c[1] + (1 - u) * (1 + v) * c[2] +
+                               (1 + u) * (1 + v) * c[3])
+
+            for typ in (3, 1, 2):
+                subs = MORTAR_SUBFACES[typ]
+                found = []
+                for (u0, u1), (v0, v1) in subs:
+                    sub = np.array([at(u0, v0), at(u1, v0), at(u0, v1), at(u1, v1)])
+                    hit = None
+                    for (e2, s2) in faces.get(key(sub), []):
+                        if e2 == e or nbr[e2, s2] >= 0 or mortar[e2, s2]:
+                            continue
+                        A = corners_wrapped_to(C[e2, s2], sub)
+                        o = _orient(A, sub, 1e3 * tol)
+                        if o is not None:
+                            hit = (e2, s2, o)
+                            break
+                    if hit is None:
+                        break
+                    found.append(hit)
+                if len(found) == len(subs):
+                    mortar[e, s] = typ
+                    for p, (e2, s2, o) in enumerate(found):
+                        nbr[e2, s2], side[e2, s2], flip[e2, s2] = e, s, o
+                        mortar[e2, s2] = 4 + p
+                    break
+    for e in range(K):
+        for s in range(6):
+            if nbr[e, s] < 0 and mortar[e, s] == 0:
+                side[e, s] = bc_kind
+    return nbr, side, flip, mortar
+
+
 def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):
     """Undeformed positions ``X[e][3][n^3]`` of tensor nodes in every lattice cell.
 

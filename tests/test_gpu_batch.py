@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1910_02858_amd import inputs
-from gpu_common import norm_err, problem, to_gpu
+from gpu_common import norm_err, problem, rel_err, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -131,6 +131,14 @@ def test_graph_step_equals_eager_and_member_steps(dg):
 def test_tuned_tiles_and_oracle_parity(dg, orc):
     import torch
     sols, U0s = make_members(dg)
+    # member 1 (N=5, curved) takes its mesh, initial state and time step from the oracle side
+    j = 1
+    N, K1, cv, A, Ma = MEMBERS[j]
+    wl = inputs.workload(4, N=N, K1=K1, curved=cv, amp=A, mach=Ma)
+    M, xgeo, nbr, side, U0j = problem(orc, wl, perturb=1e-2, seed=j)
+    sols[j] = dg.DGSolver.from_workload(wl, xgeo, nbr, side)
+    U0s[j] = to_gpu(U0j)
+    dt_j = M.timestep(orc.Scheme.of(wl), U0j, wl.cfl, wl.dfl)
     B = dg.Batch(sols)
     info = B.tune(U0s, repeats=2)
     degrees = sorted({m[0] for m in MEMBERS})
@@ -141,6 +149,7 @@ def test_tuned_tiles_and_oracle_parity(dg, orc):
         assert count == sum(1 for m in MEMBERS if m[0] == N)
         assert elems == sum(m[1] ** 3 for m in MEMBERS if m[0] == N)
     dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    dts[j] = dt_j
     steps = 4
     cur = [U.clone() for U in U0s]
     nxt = [S.empty() for S in sols]
@@ -149,15 +158,55 @@ def test_tuned_tiles_and_oracle_parity(dg, orc):
         B.step(cur, nxt, Rs, dts, graph=True)
         cur, nxt = nxt, cur
     torch.cuda.synchronize()
-    # member 1: N=5 curved; the oracle integrates the same initial state on its own mesh
-    j = 1
-    N, K1, cv, A, Ma = MEMBERS[j]
-    wl = inputs.workload(4, N=N, K1=K1, curved=cv, amp=A, mach=Ma)
-    M, xgeo, nbr, side, _ = problem(orc, wl, perturb=0)
-    Uo = M.rk(orc.Scheme.of(wl), U0s[j].cpu().numpy(), steps, dts[j])
+    Uo = M.rk(orc.Scheme.of(wl), U0j, steps, dt_j)
     err = norm_err(cur[j].cpu().numpy(), Uo)
     print(f"batched member N={N} after {steps} steps: normwise error {err:.2e}")
     assert err <= 1e-10
+
+
+def test_ensemble_draw_graph_steps_oracle_parity(dg, orc):
+    """The benchmark's ensemble: the seeded 256-member draw (K1 ~ U{4..12}, N ~ U{3..7}, amplitude
+    and Mach per member), advanced together for 10 graph-replayed batched steps, then the largest
+    member of every degree compared with the oracle's own 10 steps (per variable 1e-10).  The
+    compared members take their mesh, initial state and time step from the oracle side."""
+    import torch
+    wls = inputs.ensemble_draw(256, 0)
+    steps = 10
+    check = {}
+    for i, wl in enumerate(wls):
+        if wl.N not in check or wl.K1 > wls[check[wl.N]].K1:
+            check[wl.N] = i
+    assert sorted(check) == [3, 4, 5, 6, 7]
+    sols, U0s, dts, refs = [], [], [], {}
+    for i, wl in enumerate(wls):
+        if i in check.values():
+            M, xgeo, nbr, side, U0 = problem(orc, wl, perturb=0)
+            sc = orc.Scheme.of(wl)
+            dt = M.timestep(sc, U0, wl.cfl, wl.dfl)
+            refs[i] = (M, sc, U0, dt)
+            S = dg.DGSolver.from_workload(wl, xgeo, nbr, side)
+            U = to_gpu(U0)
+        else:
+            S, U = dg.build_solver(wl)
+            dt = S.timestep(U, wl.cfl, wl.dfl)
+        sols.append(S)
+        U0s.append(U)
+        dts.append(dt)
+    B = dg.Batch(sols)
+    cur = [U.clone() for U in U0s]
+    nxt = [S.empty() for S in sols]
+    Rs = [torch.zeros_like(U) for U in U0s]
+    for _ in range(steps):
+        B.step(cur, nxt, Rs, dts, graph=True)
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    for N, i in sorted(check.items()):
+        M, sc, U0, dt = refs[i]
+        print(f"member {i}: N={N}, {wls[i].K1}^3 elements", flush=True)
+        ref = M.rk(sc, U0, steps, dt)
+        err = rel_err(cur[i].cpu().numpy(), ref)
+        print(f"  per-variable after {steps} steps {err}")
+        assert np.all(err <= 1e-10), err
 
 
 def test_batch_argument_errors(dg):

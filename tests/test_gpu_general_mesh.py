@@ -27,7 +27,7 @@ same bit for bit, element for element.  Mesh preprocessing end to end: from elem
 alone (rotated, shuffled), dg_mesh_connect and dg_mesh_sfc_order give a mesh whose operator
 matches the oracle on the mesh the coordinates came from (1e-12).
 
-Pressure outflow (LGL): boxes against the oracle (1e-12), a uniform flow at the outflow pressure
+Pressure outflow (LGL and LG nodes): boxes against the oracle (1e-12), a uniform flow at the outflow pressure
 at rest in time, the operator refusing to run before the pressure is set, J^T w against the
 assembled Jacobian and a mixed batch bitwise equal to the one-mesh stage.
 
@@ -749,6 +749,8 @@ OUT_CASES = [
     ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
     ("ns_strong_lgl3_roe_rotated", inputs.workload(2, form="strong", volflux="central", N=3), 3, 42),
     ("euler_weak_lgl4_llf", inputs.workload(1, nodes="lgl", N=4, curved=True), 3, None),
+    ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 44),
+    ("ns_strong_lg3_roe", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, None),
 ]
 
 

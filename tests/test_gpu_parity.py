@@ -67,7 +67,10 @@ def test_rhs_parity_full_cfg2(dg, orc):
 @pytest.mark.parametrize("name,wl,steps", [
     ("cfg1_full_10_steps", inputs.workload(1), 10),
     ("cfg2_k6_100_steps", inputs.workload(2, K1=6), 100),
+    ("cfg2_full_k16_100_steps", inputs.workload(2), 100),
     ("cfg3_k3_100_steps", inputs.workload(3, K1=3), 100),
+    ("cfg3_k6_50_steps", inputs.workload(3, K1=6), 50),
+    ("cfg5_full_k12_50_steps", inputs.workload(5), 50),
 ])
 def test_rk_parity(dg, orc, name, wl, steps):
     print(f"case {name}", flush=True)

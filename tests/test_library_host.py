@@ -312,12 +312,28 @@ def test_renumbered_mesh_connectivity(dg):
     dg.host_geometry(Xs, nbs, sds, N, "lgl", flip=fls)
 
 
-def test_outflow_needs_lgl_nodes(dg):
+def test_outflow_on_both_node_sets(dg):
     N, m = 2, 2
     lgl, _ = dg.nodes(N, "lgl")
     X = inputs.lattice_points(lgl, m, m, m, box=(np.pi,) * 3)
     nbr, side, flip = inputs.box_lattice(m, m, m, kind=4)
     dg.host_geometry(X, nbr, side, N, "lgl", flip=flip)
-    with pytest.raises(dg.DGError) as ei:
-        dg.host_geometry(X, nbr, side, N, "lg", flip=flip)
-    assert ei.value.code == -3
+    dg.host_geometry(X, nbr, side, N, "lg", flip=flip)
+
+
+@pytest.mark.parametrize("N,ngeo", [(5, 2), (3, 1), (4, 6), (7, 3)])
+@pytest.mark.parametrize("nodes", ["lg", "lgl"])
+def test_host_geometry_degree_matches_oracle(dg, orc, N, ngeo, nodes):
+    """Geometry of degree N_geo != N (Sec. 2.1): the library's tables, built from the mapping at
+    the degree-N_geo LGL nodes, agree with the oracle's to a few ulps of each table's scale."""
+    k = 3
+    xg = inputs.warp_sine(inputs.lattice_points(orc.basis(ngeo, "lgl")["x"], k, k, k))
+    nbr, side, _ = inputs.periodic_lattice(k, k, k)
+    M = orc.OracleMesh(xg, nbr, side, N, nodes, ngeo=ngeo)
+    g = M.geometry()
+    h = dg.host_geometry(xg, nbr, side, N, nodes, ngeo=ngeo)
+    eps = np.finfo(float).eps
+    for key in ("Ja", "J", "fn"):
+        assert np.abs(h[key] - g[key]).max() <= 2.0 * eps * np.abs(g[key]).max(), key
+    with pytest.raises(ValueError):
+        dg.host_geometry(xg, nbr, side, N, nodes)  # the point count names the degree
