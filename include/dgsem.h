@@ -236,6 +236,16 @@ int dg_timestep(dg_handle *h, const double *U, double cfl, double dfl, double *d
  * out[8] = {rho, rho u, rho v, rho w, E, kinetic energy, entropy -rho s/(gamma-1), min J}. */
 int dg_integrals(dg_handle *h, const double *U, double out[8]);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the integrals of dg_integrals written to the DEVICE array
+ * out_dev[8] (same order, same values bit for bit), asynchronous on the handle's stream.  Calls
+ * no hipMalloc, hipFree or allocating routine: the per-element partial sums go to a static
+ * device buffer of 2^20 doubles per GPU (8 per element, so at most 131072 elements; larger
+ * meshes get DG_ERR_UNSUPPORTED), which each GPU holds until the process ends.  All calls on
+ * one GPU share that buffer: calls that overlap in time on one GPU race.  DG_ERR_ARG for NULL
+ * or misaligned pointers. */
+int dg_integrals_noalloc(dg_handle *h, const double *U, double *out_dev);
+
 /* DG_ERR_NONFINITE if any entry of U is NaN or Inf, DG_OK otherwise.  Synchronous. */
 int dg_check_finite(dg_handle *h, const double *U);
 

@@ -647,6 +647,9 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
     h->tab.lhm[j] = (double)(B.lm[j] / B.w[j]); h->tab.lhp[j] = (double)(B.lp[j] / B.w[j]);
     h->tab.w[j] = (double)B.w[j];
   }
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return DG_ERR_HIP; }
+  // device address of the static scratch of the allocation-free entry points, once per device
+  if (int src = dg::static_scratch_setup(h->device)) { delete h; return src; }
   HostGeo G;
   std::string msg;
   int rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);

@@ -143,6 +143,10 @@ int launch_batch_split(const BatchView &bv, bool ns, int vf, int epb, hipStream_
 enum { RED_TIMESTEP = 0, RED_INTEGRALS = 1, RED_FINITE = 2 };
 
 int launch_final_reduce(int what, const double *partial, int K, double *out, hipStream_t st);
+// Static scratch of the entry points that allocate nothing (dg_static.hip): doubles per GPU, and
+// the once-per-device lookup of its device address, called by dg_init with that device current.
+#define DG_NOALLOC_SCRATCH_DOUBLES (1 << 20)
+int static_scratch_setup(int device);
 int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n, hipStream_t st);
 int launch_mass(const double *sJ, const double *w, int n, size_t total, double *out, hipStream_t st);
 
@@ -150,6 +154,7 @@ int launch_mass(const double *sJ, const double *w, int n, size_t total, double *
 
 struct dg_handle {
   int K = 0, N = 0, n = 0, n2 = 0, n3 = 0, node_type = 0;
+  int device = -1;  // HIP device current at dg_init
   dg_scheme sc{};
   dg::Phys ph{};
   hipStream_t stream = nullptr;

@@ -30,6 +30,7 @@ EXPORTS = [
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
     "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
+    "dg_integrals_noalloc",
 ]
 
 
@@ -87,6 +88,7 @@ def lib():
                                       ctypes.c_double]
         L.dg_timestep.argtypes = [_VP, _VP, ctypes.c_double, ctypes.c_double, _D]
         L.dg_integrals.argtypes = [_VP, _VP, _D]
+        L.dg_integrals_noalloc.argtypes = [_VP, _VP, _VP]
         L.dg_check_finite.argtypes = [_VP, _VP]
         L.dg_node_coords.argtypes = [_VP, _D]
         L.dg_mass_weights.argtypes = [_VP, _VP]
@@ -331,6 +333,14 @@ class DGSolver:
         out = np.zeros(8)
         self._check(lib().dg_integrals(self.h, _VP(_dptr(U)), _ptr(out)), "dg_integrals")
         return out
+
+    def integrals_noalloc(self, U, out):
+        """dg_integrals_noalloc: the integrals into the device tensor ``out`` (8 doubles),
+        asynchronous on the library stream, scratch in the library's static device buffer."""
+        self._sync_stream()
+        if out.dtype != self.torch.float64 or out.numel() < 8 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of at least 8 entries")
+        self._check(lib().dg_integrals_noalloc(self.h, _VP(_dptr(U)), _VP(_dptr(out))), "dg_integrals_noalloc")
 
     def check_finite(self, U) -> bool:
         self._sync_stream()
