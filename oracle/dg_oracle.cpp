@@ -984,9 +984,17 @@ static void lifting(const Mesh& M, const Scheme& S, const T* U, const std::vecto
   }
 }
 
-// full operator U_t = L(U) for the elements with out_mask[e] != 0
+// hybrid DG/FV state (Sec. 4): defined with the finite-volume operator below
+struct FvState;
 template <class T>
-static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::vector<char>& out_mask) {
+static void fv_mixed_face(const Mesh& M, const Scheme& S, const FvState& F, const T* U, int e, int s, T* fout);
+static bool fv_face_mixed(const FvState* F, const Mesh& M, int e, int s);
+
+// full operator U_t = L(U) for the elements with out_mask[e] != 0; with fvs, the DG elements' sides
+// that meet a finite-volume element take their flux from the mixed DG/FV face (Sec. 4.2)
+template <class T>
+static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::vector<char>& out_mask,
+                const FvState* fvs = nullptr) {
   const int K = M.K, n = M.n, n2 = M.n2, n3 = M.n3;
   const bool ns = (S.eqn == 1);
   Work<T> wk;
@@ -1070,11 +1078,17 @@ static void rhs(const Mesh& M, const Scheme& S, const T* U, T* Ut, const std::ve
       int nb = M.nbr[e * 6 + s], ns_ = M.nside[e * 6 + s];
       const std::vector<double>& lh = plus ? M.sol.lhp : M.sol.lhm;
       const bool mst = is_master(M, e, s);
-      const int mk = M.mort.empty() ? 0 : M.mort[e * 6 + s];
+      int mk = M.mort.empty() ? 0 : M.mort[e * 6 + s];
       // non-conforming face: outward flux of every face point of this side (on a big side the
       // projection of the small sides' fluxes, negated)
       std::vector<T> Fm;
-      if (mk != 0) {
+      if (fv_face_mixed(fvs, M, e, s)) {
+        // face shared with a finite-volume element: the outward flux at the face nodes (the
+        // subcell-face fluxes taken back to the nodes with the inverse of V_DG=>FV)
+        Fm.assign((size_t)n2 * 5, T(0.0));
+        fv_mixed_face(M, S, *fvs, U, e, s, Fm.data());
+        mk = -1;
+      } else if (mk != 0) {
         Fm.assign((size_t)n2 * 5, T(0.0));
         auto small_flux = [&](int es, int ss, int a, int b, T* F) {
           // the small side is the master of its part of the face: its own normal and surface
@@ -1251,6 +1265,434 @@ template <class T> static void rk_steps(const Mesh& M, const Scheme& S, T* U, in
     }
 }
 
+// ------------------------------------------------------------------------------ FV subcells
+// Shock capturing by finite volumes on subcells (Sec. 4): a troubled element reinterprets its
+// (N+1)^3 degrees of freedom as the means of U over (N+1)^3 equal subcells of width w = 2/(N+1) in
+// reference space, stored in place of the nodal values.  Euler equations, conforming meshes.
+//   V_DG=>FV (eq. FVvdm): V_ki = 1/2 sum_l w_l l_i(xi^k_l), xi^k_l the nodes mapped into subcell
+//   k, the subcell mean of the DG polynomial (exact); V_FV=>DG = its inverse (eq. dg2fv).
+//   FV update (eq. fv_dof_time_derivative, in 3D): w Jbar U_t = -sum over the subcell's six faces
+//   of the outward numerical flux times the face's mean metric; Jbar the subcell mean of J, the
+//   face metric the mean of Ja^dir over the subcell face (the metric terms enter the flux
+//   linearly, so for a state constant on the face this is the face integral exactly).
+//   Second-order reconstruction of the primitive variables (rho, u, v, w, p) from the subcell
+//   means with limited slopes (minmod or van Leer; 0 = first order) along each direction; at an
+//   element face the outer value is the neighbour's face datum: its adjacent subcell (FV), or its
+//   trace taken to subcell-face means with V_DG=>FV (DG).
+//   Faces between a DG and an FV element (Sec. 4.2): the DG trace is taken to the subcell faces
+//   with V (in both face directions), the numerical flux is evaluated there (with the master's
+//   state first and the master's face metric), applied to the FV subcells as is and brought back
+//   to the DG nodes with V^-1.
+//   Troubled-cell indicator (Sec. 4.3, Persson-Peraire modal decay): q = rho p at the nodes (of
+//   V^-1 U for FV elements), its coefficients in the tensor orthonormal Legendre basis, E_k the
+//   energy of the modes whose largest index is k; ind = log10 max(E_N / E_<=N, E_N-1 / E_<=N-1).
+//   An element switches to FV when ind > upper threshold, back to DG when ind < lower threshold
+//   (hysteresis, Fig. fv:indicator), evaluated at the start of each time step; switching applies
+//   V or V^-1 in place.
+struct FvState {
+  int limiter = 1;                // 0 first order, 1 minmod, 2 van Leer
+  std::vector<uint8_t> fv;        // [K] 1 = finite-volume element
+  std::vector<double> V, Vi;      // [k*n+i] V_DG=>FV and its inverse
+  std::vector<double> Jbar;       // [e][n3] subcell mean of J
+  std::vector<double> Nf;         // [e][dir][f][a+n*b][3]: mean of Ja^dir over subcell face f
+  double w = 0;                   // subcell width in reference space
+};
+
+// V_DG=>FV of the solution basis and its inverse
+static void fv_matrices(const Basis& b, std::vector<double>& V, std::vector<double>& Vi) {
+  const int n = b.n;
+  const ld w = 2.0L / n;
+  std::vector<ld> A((size_t)n * n), I((size_t)n * n, 0.0L);
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) {
+      ld acc = 0;
+      for (int l = 0; l < n; ++l) {
+        const ld xi = -1.0L + k * w + (b.xl[l] + 1.0L) * w / 2.0L;
+        acc += b.wl[l] * lagrange(b.xl, b.laml, i, xi);
+      }
+      A[(size_t)k * n + i] = acc / 2.0L;
+    }
+  // inverse by Gauss-Jordan elimination with partial pivoting (extended precision)
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0L;
+  std::vector<ld> B = A;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(B[(size_t)r * n + c]) > std::fabs(B[(size_t)piv * n + c])) piv = r;
+    for (int j = 0; j < n; ++j) { std::swap(B[(size_t)c * n + j], B[(size_t)piv * n + j]); std::swap(I[(size_t)c * n + j], I[(size_t)piv * n + j]); }
+    const ld d = B[(size_t)c * n + c];
+    for (int j = 0; j < n; ++j) { B[(size_t)c * n + j] /= d; I[(size_t)c * n + j] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const ld f = B[(size_t)r * n + c];
+      for (int j = 0; j < n; ++j) { B[(size_t)r * n + j] -= f * B[(size_t)c * n + j]; I[(size_t)r * n + j] -= f * I[(size_t)c * n + j]; }
+    }
+  }
+  V.resize((size_t)n * n); Vi.resize((size_t)n * n);
+  for (int q = 0; q < n * n; ++q) { V[q] = (double)A[q]; Vi[q] = (double)I[q]; }
+}
+
+// the geometry of the subcells: Jbar and the face-mean metric terms
+static void fv_geometry(const Mesh& M, FvState& F) {
+  const int K = M.K, N = M.N, n = M.n, n2 = M.n2, n3 = M.n3;
+  fv_matrices(M.sol, F.V, F.Vi);
+  F.w = 2.0 / n;
+  F.Jbar.assign((size_t)K * n3, 0.0);
+  F.Nf.assign((size_t)K * 3 * (n + 1) * n2 * 3, 0.0);
+  // l_m at the subcell face positions -1 + f w, f = 0..n
+  std::vector<double> Lf((size_t)(n + 1) * n);
+  for (int f = 0; f <= n; ++f)
+    for (int m = 0; m < n; ++m)
+      Lf[(size_t)f * n + m] = (double)lagrange(M.sol.xl, M.sol.laml, m, -1.0L + f * (2.0L / n));
+  for (int e = 0; e < K; ++e) {
+    // Jbar = (V x V x V) J
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double acc = 0;
+          for (int c = 0; c < n; ++c)
+            for (int b = 0; b < n; ++b)
+              for (int a = 0; a < n; ++a)
+                acc += F.V[i * n + a] * F.V[j * n + b] * F.V[k * n + c] * M.J[(size_t)e * n3 + nid(n, a, b, c)];
+          F.Jbar[(size_t)e * n3 + nid(n, i, j, k)] = acc;
+        }
+    // face means: Ja^dir restricted to xi_dir = -1 + f w, then subcell means along the face
+    for (int dir = 0; dir < 3; ++dir)
+      for (int f = 0; f <= n; ++f)
+        for (int bb = 0; bb < n; ++bb)
+          for (int aa = 0; aa < n; ++aa)
+            for (int d = 0; d < 3; ++d) {
+              double acc = 0;
+              for (int jb = 0; jb < n; ++jb)
+                for (int ia = 0; ia < n; ++ia) {
+                  double g = 0;
+                  for (int m = 0; m < n; ++m)
+                    g += Lf[(size_t)f * n + m] * M.Ja[((size_t)e * 9 + dir * 3 + d) * n3 + line_node(n, dir, ia, jb, m)];
+                  acc += F.V[aa * n + ia] * F.V[bb * n + jb] * g;
+                }
+              F.Nf[((((size_t)e * 3 + dir) * (n + 1) + f) * n2 + aa + n * bb) * 3 + d] = acc;
+            }
+  }
+  (void)N;
+}
+
+static bool fv_face_mixed(const FvState* F, const Mesh& M, int e, int s) {
+  if (!F) return false;
+  const int nb = M.nbr[e * 6 + s];
+  return nb >= 0 && (F->fv[e] || F->fv[nb]);
+}
+
+template <class T> static T fv_limit(int lim, T a, T b) {
+  if (lim == 0) return T(0.0);
+  if (val(a) * val(b) <= 0.0) return T(0.0);
+  if (lim == 1) return (std::fabs(val(a)) < std::fabs(val(b))) ? a : b;  // minmod
+  return T(2.0) * a * b / (a + b);                                        // van Leer
+}
+
+template <class T> static void cons_to_prim5(const T* U, double gamma, T* W) {
+  Prim<T> P = prim(U, gamma);
+  W[0] = P.rho; W[1] = P.u[0]; W[2] = P.u[1]; W[3] = P.u[2]; W[4] = P.p;
+}
+template <class T> static void prim5_to_cons(const T* W, double gamma, T* U) {
+  U[0] = W[0];
+  for (int d = 0; d < 3; ++d) U[1 + d] = W[0] * W[1 + d];
+  U[4] = W[4] / T(gamma - 1.0) + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+// conservative face datum of side s of element e at face point / subface (a,b) in subcell-face
+// form: for a DG element the mean of its trace over the subface ((V x V) of the trace), for an FV
+// element the mean of its adjacent subcell
+template <class T>
+static void fv_face_datum(const Mesh& M, const FvState& F, const T* U, int e, int s, int a, int b, T* out) {
+  const int n = M.n, dn = s / 2;
+  const bool plus = (s % 2) == 1;
+  if (F.fv[e]) {
+    const int q = line_node(n, dn, a, b, plus ? M.N : 0);
+    for (int v = 0; v < 5; ++v) out[v] = U[((size_t)e * 5 + v) * M.n3 + q];
+    return;
+  }
+  for (int v = 0; v < 5; ++v) out[v] = T(0.0);
+  for (int jb = 0; jb < n; ++jb)
+    for (int ia = 0; ia < n; ++ia) {
+      const double c = F.V[a * n + ia] * F.V[b * n + jb];
+      T tr[5];
+      trace(M, U, 5, e, s, ia, jb, tr);
+      for (int v = 0; v < 5; ++v) out[v] = out[v] + T(c) * tr[v];
+    }
+}
+
+// reconstructed state of FV element e at its boundary subface (a,b) of side s; outer = the
+// neighbour's face datum there (conservative)
+template <class T>
+static void fv_boundary_state(const Mesh& M, const FvState& F, const Scheme& S, const T* U, int e, int s, int a,
+                              int b, const T* outer, T* Uf) {
+  const int n = M.n, dn = s / 2;
+  const bool plus = (s % 2) == 1;
+  T U0[5], U1[5], W0[5], W1[5], Wo[5], Wf[5];
+  const int q0 = line_node(n, dn, a, b, plus ? M.N : 0), q1 = line_node(n, dn, a, b, plus ? M.N - 1 : 1);
+  for (int v = 0; v < 5; ++v) {
+    U0[v] = U[((size_t)e * 5 + v) * M.n3 + q0];
+    U1[v] = U[((size_t)e * 5 + v) * M.n3 + q1];
+  }
+  cons_to_prim5(U0, S.gamma, W0);
+  cons_to_prim5(U1, S.gamma, W1);
+  cons_to_prim5(outer, S.gamma, Wo);
+  for (int v = 0; v < 5; ++v) {
+    // along +xi_dn: minus side: slopes (W0 - Wo, W1 - W0), face value W0 - sigma/2;
+    // plus side: slopes (W0 - W1, Wo - W0), face value W0 + sigma/2
+    T sm = plus ? W0[v] - W1[v] : W0[v] - Wo[v];
+    T sp = plus ? Wo[v] - W0[v] : W1[v] - W0[v];
+    T sg = fv_limit(F.limiter, sm, sp);
+    Wf[v] = plus ? W0[v] + T(0.5) * sg : W0[v] - T(0.5) * sg;
+  }
+  prim5_to_cons(Wf, S.gamma, Uf);
+}
+
+// outward flux of side s of element e at its face points (DG: nodes, after V^-1 x V^-1; FV:
+// subfaces) on a face shared with at least one FV element
+template <class T>
+static void fv_mixed_face(const Mesh& M, const Scheme& S, const FvState& F, const T* U, int e, int s, T* fout) {
+  const int n = M.n, n2 = M.n2;
+  const int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
+  const bool mst = is_master(M, e, s);
+  std::vector<T> fs((size_t)n2 * 5);  // outward flux of this side at its subfaces
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a) {
+      int a2, b2;
+      mate(M, e, s, a, b, a2, b2);
+      T De[5], Dn[5], Ue[5], Un[5];
+      fv_face_datum(M, F, U, e, s, a, b, De);
+      fv_face_datum(M, F, U, nb, ns, a2, b2, Dn);
+      if (F.fv[e]) fv_boundary_state(M, F, S, U, e, s, a, b, Dn, Ue);
+      else for (int v = 0; v < 5; ++v) Ue[v] = De[v];
+      if (F.fv[nb]) fv_boundary_state(M, F, S, U, nb, ns, a2, b2, De, Un);
+      else for (int v = 0; v < 5; ++v) Un[v] = Dn[v];
+      // master's face mean metric, outward from the master
+      const int em = mst ? e : nb, sm = mst ? s : ns, am = mst ? a : a2, bm = mst ? b : b2;
+      const int dm = sm / 2;
+      const bool pm = (sm % 2) == 1;
+      const double* Nm = &F.Nf[((((size_t)em * 3 + dm) * (n + 1) + (pm ? n : 0)) * n2 + am + n * bm) * 3];
+      double nt[3] = {pm ? Nm[0] : -Nm[0], pm ? Nm[1] : -Nm[1], pm ? Nm[2] : -Nm[2]};
+      double sh = std::sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+      double nh[3] = {nt[0] / sh, nt[1] / sh, nt[2] / sh};
+      T Fl[5];
+      if (mst) riemann(Ue, Un, nh, S, Fl);
+      else riemann(Un, Ue, nh, S, Fl);
+      for (int v = 0; v < 5; ++v) fs[(size_t)(a + n * b) * 5 + v] = (mst ? T(sh) : T(-sh)) * Fl[v];
+    }
+  if (F.fv[e]) {
+    std::copy(fs.begin(), fs.end(), fout);
+    return;
+  }
+  // DG side: back to the face nodes with V^-1 along both face directions
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a)
+      for (int v = 0; v < 5; ++v) {
+        T acc = T(0.0);
+        for (int jb = 0; jb < n; ++jb)
+          for (int ia = 0; ia < n; ++ia) acc = acc + T(F.Vi[a * n + ia] * F.Vi[b * n + jb]) * fs[(size_t)(ia + n * jb) * 5 + v];
+        fout[(size_t)(a + n * b) * 5 + v] = acc;
+      }
+}
+
+// U_t of the FV elements (the DG elements are left to rhs())
+template <class T>
+static void fv_rhs(const Mesh& M, const Scheme& S, const FvState& F, const T* U, T* Ut) {
+  const int K = M.K, N = M.N, n = M.n, n2 = M.n2, n3 = M.n3;
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int e = 0; e < K; ++e) {
+    if (!F.fv[e]) continue;
+    std::vector<T> acc((size_t)5 * n3, T(0.0));
+    for (int dir = 0; dir < 3; ++dir) {
+      // element faces
+      for (int sd = 0; sd < 2; ++sd) {
+        const int s = 2 * dir + sd;
+        std::vector<T> fo((size_t)n2 * 5);
+        fv_mixed_face(M, S, F, U, e, s, fo.data());
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            const int q = line_node(n, dir, a, b, sd ? N : 0);
+            for (int v = 0; v < 5; ++v) acc[(size_t)v * n3 + q] = acc[(size_t)v * n3 + q] + fo[(size_t)(a + n * b) * 5 + v];
+          }
+      }
+      // inner subcell faces f = 1..N between subcells f-1 and f
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          std::vector<T> W((size_t)n * 5);
+          for (int m = 0; m < n; ++m) {
+            T Uq[5];
+            for (int v = 0; v < 5; ++v) Uq[v] = U[((size_t)e * 5 + v) * n3 + line_node(n, dir, a, b, m)];
+            cons_to_prim5(Uq, S.gamma, &W[(size_t)m * 5]);
+          }
+          // limited slope of every subcell; the end subcells use the neighbours' face data
+          std::vector<T> sig((size_t)n * 5);
+          for (int m = 0; m < n; ++m) {
+            T Wl[5], Wr[5];
+            for (int side = 0; side < 2; ++side) {
+              const int mm = side ? m + 1 : m - 1;
+              T* dst = side ? Wr : Wl;
+              if (mm >= 0 && mm < n) {
+                for (int v = 0; v < 5; ++v) dst[v] = W[(size_t)mm * 5 + v];
+              } else {
+                const int s = 2 * dir + (side ? 1 : 0);
+                const int nb = M.nbr[e * 6 + s], ns = M.nside[e * 6 + s];
+                int a2, b2;
+                mate(M, e, s, a, b, a2, b2);
+                T Dn[5];
+                fv_face_datum(M, F, U, nb, ns, a2, b2, Dn);
+                cons_to_prim5(Dn, S.gamma, dst);
+              }
+            }
+            for (int v = 0; v < 5; ++v)
+              sig[(size_t)m * 5 + v] = fv_limit(F.limiter, W[(size_t)m * 5 + v] - Wl[v], Wr[v] - W[(size_t)m * 5 + v]);
+          }
+          for (int f = 1; f <= N; ++f) {
+            T WL[5], WR[5], UL[5], UR[5];
+            for (int v = 0; v < 5; ++v) {
+              WL[v] = W[(size_t)(f - 1) * 5 + v] + T(0.5) * sig[(size_t)(f - 1) * 5 + v];
+              WR[v] = W[(size_t)f * 5 + v] - T(0.5) * sig[(size_t)f * 5 + v];
+            }
+            prim5_to_cons(WL, S.gamma, UL);
+            prim5_to_cons(WR, S.gamma, UR);
+            const double* Nm = &F.Nf[((((size_t)e * 3 + dir) * (n + 1) + f) * n2 + a + n * b) * 3];
+            double sh = std::sqrt(Nm[0] * Nm[0] + Nm[1] * Nm[1] + Nm[2] * Nm[2]);
+            double nh[3] = {Nm[0] / sh, Nm[1] / sh, Nm[2] / sh};
+            T Fl[5];
+            riemann(UL, UR, nh, S, Fl);
+            const int qm = line_node(n, dir, a, b, f - 1), qp = line_node(n, dir, a, b, f);
+            for (int v = 0; v < 5; ++v) {
+              acc[(size_t)v * n3 + qm] = acc[(size_t)v * n3 + qm] + T(sh) * Fl[v];
+              acc[(size_t)v * n3 + qp] = acc[(size_t)v * n3 + qp] - T(sh) * Fl[v];
+            }
+          }
+        }
+    }
+    for (int v = 0; v < 5; ++v)
+      for (int q = 0; q < n3; ++q)
+        Ut[((size_t)e * 5 + v) * n3 + q] = -acc[(size_t)v * n3 + q] / T(F.w * F.Jbar[(size_t)e * n3 + q]);
+  }
+}
+
+// mixed operator: DG elements by rhs() with the mixed faces, FV elements by fv_rhs()
+template <class T>
+static void hybrid_rhs(const Mesh& M, const Scheme& S, const FvState& F, const T* U, T* Ut) {
+  std::vector<char> dg(M.K, 0);
+  for (int e = 0; e < M.K; ++e) dg[e] = !F.fv[e];
+  rhs(M, S, U, Ut, dg, &F);
+  fv_rhs(M, S, F, U, Ut);
+}
+
+// orthonormal Legendre polynomial of degree k at x
+static ld legendre_on(int k, ld x) {
+  ld P, dP;
+  legendre(k, x, P, dP);
+  return P * std::sqrt((2.0L * k + 1.0L) / 2.0L);
+}
+
+// troubled-cell indicator of every element (nodal DG values; FV elements through V^-1)
+static void fv_indicator(const Mesh& M, const FvState& F, double gamma, const double* U, double* ind) {
+  const int K = M.K, N = M.N, n = M.n, n3 = M.n3;
+  // modal transform: L[i][k] = Ptilde_k(x_i), coefficients = L^-1 q along each direction
+  std::vector<ld> L((size_t)n * n), Li((size_t)n * n, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) L[(size_t)i * n + k] = legendre_on(k, M.sol.xl[i]);
+  {
+    std::vector<ld> B = L;
+    for (int i = 0; i < n; ++i) Li[(size_t)i * n + i] = 1.0L;
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs(B[(size_t)r * n + c]) > std::fabs(B[(size_t)piv * n + c])) piv = r;
+      for (int j = 0; j < n; ++j) { std::swap(B[(size_t)c * n + j], B[(size_t)piv * n + j]); std::swap(Li[(size_t)c * n + j], Li[(size_t)piv * n + j]); }
+      const ld d = B[(size_t)c * n + c];
+      for (int j = 0; j < n; ++j) { B[(size_t)c * n + j] /= d; Li[(size_t)c * n + j] /= d; }
+      for (int r = 0; r < n; ++r) {
+        if (r == c) continue;
+        const ld f = B[(size_t)r * n + c];
+        for (int j = 0; j < n; ++j) { B[(size_t)r * n + j] -= f * B[(size_t)c * n + j]; Li[(size_t)r * n + j] -= f * Li[(size_t)c * n + j]; }
+      }
+    }
+  }
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < K; ++e) {
+    std::vector<double> u((size_t)5 * n3), q(n3), t1(n3), t2(n3), c(n3);
+    for (int v = 0; v < 5; ++v)
+      for (int p = 0; p < n3; ++p) u[(size_t)v * n3 + p] = U[((size_t)e * 5 + v) * n3 + p];
+    if (F.fv[e]) {  // nodal values of the FV element's DG interpretation
+      std::vector<double> w5 = u;
+      for (int v = 0; v < 5; ++v)
+        for (int kk = 0; kk < n; ++kk)
+          for (int jj = 0; jj < n; ++jj)
+            for (int ii = 0; ii < n; ++ii) {
+              double acc = 0;
+              for (int cc = 0; cc < n; ++cc)
+                for (int bb = 0; bb < n; ++bb)
+                  for (int aa = 0; aa < n; ++aa)
+                    acc += F.Vi[ii * n + aa] * F.Vi[jj * n + bb] * F.Vi[kk * n + cc] * w5[(size_t)v * n3 + nid(n, aa, bb, cc)];
+              u[(size_t)v * n3 + nid(n, ii, jj, kk)] = acc;
+            }
+    }
+    for (int p = 0; p < n3; ++p) {
+      double Uq[5];
+      for (int v = 0; v < 5; ++v) Uq[v] = u[(size_t)v * n3 + p];
+      Prim<double> P = prim(Uq, gamma);
+      q[p] = P.rho * P.p;
+    }
+    // modal coefficients
+    for (int kk = 0; kk < n; ++kk)
+      for (int jj = 0; jj < n; ++jj)
+        for (int ii = 0; ii < n; ++ii) {
+          ld acc = 0;
+          for (int cc = 0; cc < n; ++cc)
+            for (int bb = 0; bb < n; ++bb)
+              for (int aa = 0; aa < n; ++aa)
+                acc += Li[(size_t)ii * n + aa] * Li[(size_t)jj * n + bb] * Li[(size_t)kk * n + cc] * (ld)q[nid(n, aa, bb, cc)];
+          c[nid(n, ii, jj, kk)] = (double)acc;
+        }
+    std::vector<double> Ek(n, 0.0);
+    for (int kk = 0; kk < n; ++kk)
+      for (int jj = 0; jj < n; ++jj)
+        for (int ii = 0; ii < n; ++ii) {
+          const int m = std::max(ii, std::max(jj, kk));
+          Ek[m] += c[nid(n, ii, jj, kk)] * c[nid(n, ii, jj, kk)];
+        }
+    double tot = 0;
+    for (int m = 0; m <= N; ++m) tot += Ek[m];
+    const double r1 = Ek[N] / std::max(tot, 1e-300);
+    const double r2 = N >= 1 ? Ek[N - 1] / std::max(tot - Ek[N], 1e-300) : 0.0;
+    ind[e] = std::log10(std::max(std::max(r1, r2), 1e-300));
+  }
+}
+
+// apply V (to FV) or V^-1 (to DG) to element e of U along all three directions, in place
+static void fv_transform(const Mesh& M, const std::vector<double>& A, double* U, int e) {
+  const int n = M.n, n3 = M.n3;
+  std::vector<double> x(n3);
+  for (int v = 0; v < 5; ++v) {
+    double* f = U + ((size_t)e * 5 + v) * n3;
+    for (int p = 0; p < n3; ++p) x[p] = f[p];
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double acc = 0;
+          for (int c = 0; c < n; ++c)
+            for (int b = 0; b < n; ++b)
+              for (int a = 0; a < n; ++a) acc += A[i * n + a] * A[j * n + b] * A[k * n + c] * x[nid(n, a, b, c)];
+          f[nid(n, i, j, k)] = acc;
+        }
+  }
+}
+
+// indicator + hysteresis switching at the start of a step
+static void fv_switch(const Mesh& M, FvState& F, double gamma, double lo, double hi, double* U) {
+  std::vector<double> ind(M.K);
+  fv_indicator(M, F, gamma, U, ind.data());
+  for (int e = 0; e < M.K; ++e) {
+    if (!F.fv[e] && ind[e] > hi) { fv_transform(M, F.V, U, e); F.fv[e] = 1; }
+    else if (F.fv[e] && ind[e] < lo) { fv_transform(M, F.Vi, U, e); F.fv[e] = 0; }
+  }
+}
+
 }  // namespace orc
 
 // ================================================================================ C interface
@@ -1258,7 +1700,16 @@ using namespace orc;
 
 struct orc_handle {
   Mesh M;
+  FvState F;        // finite-volume subcell geometry (built on first use)
+  bool fv_ready = false;
 };
+
+static FvState& fv_state(orc_handle* h, int limiter, const uint8_t* fv) {
+  if (!h->fv_ready) { fv_geometry(h->M, h->F); h->fv_ready = true; }
+  h->F.limiter = limiter;
+  h->F.fv.assign(fv, fv + h->M.K);
+  return h->F;
+}
 
 extern "C" {
 
@@ -1519,6 +1970,69 @@ extern "C" void orc_riemann_jvp(int rs, int vf, double gamma, const double* UL, 
   for (int v = 0; v < 5; ++v) { a[v] = dual(UL[v], dUL[v]); b[v] = dual(UR[v], dUR[v]); }
   riemann(a, b, nh, S, Fd);
   for (int v = 0; v < 5; ++v) { F[v] = Fd[v].v; dF[v] = Fd[v].d; }
+}
+
+// ---- finite-volume subcells (Sec. 4), Euler equations
+extern "C" int orc_fv_matrices(int N, int type, double* V, double* Vi) {
+  if (N < 1 || N > 16) return -1;
+  Basis b = make_basis(N, type);
+  std::vector<double> a, c;
+  fv_matrices(b, a, c);
+  std::copy(a.begin(), a.end(), V);
+  std::copy(c.begin(), c.end(), Vi);
+  return 0;
+}
+
+// Jbar [K][n3], face means Nf [K][3][n+1][n2][3]
+extern "C" void orc_fv_geometry(orc_handle* h, double* Jbar, double* Nf) {
+  std::vector<uint8_t> none(h->M.K, 0);
+  FvState& F = fv_state(h, 1, none.data());
+  if (Jbar) std::copy(F.Jbar.begin(), F.Jbar.end(), Jbar);
+  if (Nf) std::copy(F.Nf.begin(), F.Nf.end(), Nf);
+}
+
+// U_t of the hybrid operator; fv [K] flags the finite-volume elements (their U holds subcell means)
+extern "C" int orc_fv_rhs(orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double R, double mu,
+                          double Pr, int limiter, const uint8_t* fv, const double* U, double* Ut) {
+  if (eqn != 0) return -1;
+  FvState& F = fv_state(h, limiter, fv);
+  hybrid_rhs(h->M, mk(eqn, form, vf, rs, gamma, R, mu, Pr), F, U, Ut);
+  return 0;
+}
+
+extern "C" void orc_fv_indicator(orc_handle* h, double gamma, const uint8_t* fv, const double* U, double* ind) {
+  FvState& F = fv_state(h, 1, fv);
+  fv_indicator(h->M, F, gamma, U, ind);
+}
+
+// switching with hysteresis, in place on fv [K] and U
+extern "C" void orc_fv_switch(orc_handle* h, double gamma, double lo, double hi, uint8_t* fv, double* U) {
+  FvState& F = fv_state(h, 1, fv);
+  fv_switch(h->M, F, gamma, lo, hi, U);
+  std::copy(F.fv.begin(), F.fv.end(), fv);
+}
+
+// nsteps RK steps of the hybrid operator, each preceded by the indicator switching (lo < hi), or
+// with the element types held fixed (lo >= hi); in place on fv and U
+extern "C" int orc_fv_rk(orc_handle* h, int eqn, int form, int vf, int rs, double gamma, double Rg, double mu,
+                         double Pr, int limiter, double lo, double hi, uint8_t* fv, double* U, int nsteps, double dt) {
+  if (eqn != 0) return -1;
+  FvState& F = fv_state(h, limiter, fv);
+  const Scheme S = mk(eqn, form, vf, rs, gamma, Rg, mu, Pr);
+  const size_t N = (size_t)h->M.K * 5 * h->M.n3;
+  std::vector<double> R(N, 0.0), Ut(N);
+  for (int st = 0; st < nsteps; ++st) {
+    if (lo < hi) fv_switch(h->M, F, gamma, lo, hi, U);
+    for (int s = 0; s < 5; ++s) {
+      hybrid_rhs(h->M, S, F, U, Ut.data());
+      for (size_t q = 0; q < N; ++q) {
+        R[q] = RK_A[s] * R[q] + dt * Ut[q];
+        U[q] = U[q] + RK_B[s] * R[q];
+      }
+    }
+  }
+  std::copy(F.fv.begin(), F.fv.end(), fv);
+  return 0;
 }
 
 #ifdef _OPENMP

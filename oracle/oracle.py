@@ -51,6 +51,15 @@ def lib():
         L.orc_create_mesh.restype = ctypes.c_void_p
         L.orc_create_mesh.argtypes = [ctypes.c_int] * 4 + [_D, _I32, _I8, _I8, _I8]
         L.orc_mortar_matrices.argtypes = [ctypes.c_int, ctypes.c_int] + [_D] * 4
+        _U8 = ctypes.POINTER(ctypes.c_uint8)
+        L.orc_fv_matrices.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.orc_fv_geometry.argtypes = [ctypes.c_void_p, _D, _D]
+        L.orc_fv_rhs.argtypes = [ctypes.c_void_p] + [ctypes.c_int] * 4 + [ctypes.c_double] * 4 + [ctypes.c_int, _U8,
+                                                                                                    _D, _D]
+        L.orc_fv_indicator.argtypes = [ctypes.c_void_p, ctypes.c_double, _U8, _D, _D]
+        L.orc_fv_switch.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double, _U8, _D]
+        L.orc_fv_rk.argtypes = ([ctypes.c_void_p] + [ctypes.c_int] * 4 + [ctypes.c_double] * 4 + [ctypes.c_int] +
+                                [ctypes.c_double] * 2 + [_U8, _D, ctypes.c_int, ctypes.c_double])
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_set_boundary_state.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_wall_temperature.argtypes = [ctypes.c_void_p, ctypes.c_double]
@@ -106,6 +115,15 @@ def mortar_matrices(N: int, nodes: str):
     if lib().orc_mortar_matrices(N, NODES[nodes], _p(IL), _p(IU), _p(PL), _p(PU)):
         raise ValueError("unsupported N")
     return IL, IU, PL, PU
+
+
+def fv_matrices(N: int, nodes: str):
+    """V_DG=>FV (subcell means of the DG polynomial, eq. FVvdm) and its inverse, n x n each."""
+    n = N + 1
+    V, Vi = np.zeros((n, n)), np.zeros((n, n))
+    if lib().orc_fv_matrices(N, NODES[nodes], _p(V), _p(Vi)):
+        raise ValueError("unsupported N")
+    return V, Vi
 
 
 def num_threads() -> int:
@@ -234,6 +252,45 @@ class OracleMesh:
         U, dU = _c(U).copy(), _c(dU).copy()
         lib().orc_rk_jvp(self.h, *sc.args(), _p(U), _p(dU), int(nsteps), float(dt))
         return U, dU
+
+    # ---- finite-volume subcells (Sec. 4), Euler equations
+    def fv_geometry(self):
+        """Subcell mean Jacobian Jbar[K,n3] and subcell-face mean metrics Nf[K,3,n+1,n2,3]."""
+        n = self.n
+        Jb = np.zeros((self.K, self.n3))
+        Nf = np.zeros((self.K, 3, n + 1, n * n, 3))
+        lib().orc_fv_geometry(self.h, _p(Jb), _p(Nf))
+        return Jb, Nf
+
+    def fv_rhs(self, sc: Scheme, fv, U, limiter=1):
+        """U_t of the hybrid DG/FV operator; ``fv[K]`` flags the elements whose U holds subcell means."""
+        fv = _c(fv, np.uint8)
+        U = _c(U)
+        Ut = np.zeros_like(U)
+        if lib().orc_fv_rhs(self.h, *sc.args(), int(limiter), fv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            _p(U), _p(Ut)):
+            raise ValueError("the finite-volume operator is built for the Euler equations")
+        return Ut
+
+    def fv_indicator(self, fv, U, gamma=1.4):
+        fv = _c(fv, np.uint8)
+        ind = np.zeros(self.K)
+        lib().orc_fv_indicator(self.h, gamma, fv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _p(_c(U)), _p(ind))
+        return ind
+
+    def fv_switch(self, fv, U, lo, hi, gamma=1.4):
+        fv = _c(fv, np.uint8).copy()
+        U = _c(U).copy()
+        lib().orc_fv_switch(self.h, gamma, lo, hi, fv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _p(U))
+        return fv, U
+
+    def fv_rk(self, sc: Scheme, fv, U, nsteps, dt, limiter=1, lo=0.0, hi=0.0):
+        fv = _c(fv, np.uint8).copy()
+        U = _c(U).copy()
+        if lib().orc_fv_rk(self.h, *sc.args(), int(limiter), float(lo), float(hi),
+                           fv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _p(U), int(nsteps), float(dt)):
+            raise ValueError("the finite-volume operator is built for the Euler equations")
+        return fv, U
 
     def integrals(self, U, gamma=1.4):
         U = _c(U)
