@@ -85,6 +85,13 @@ typedef struct {
                               boundary side the boundary kind (DG_BC_SYMMETRY)                 */
   const int8_t *flip;      /* HOST [K][6] orientation code 0..7 of each face, NULL = all 0
                               (0 on boundary sides)                                            */
+  const int8_t *mortar;    /* HOST [K][6] non-conforming faces (Sec. 3.2), NULL = none: 0 a
+                              conforming side; 1, 2, 3 the big side of a face cut in half along
+                              its first face direction, its second, or both (its nbr_elem -1,
+                              nbr_side and flip 0); 4 + p the small side at position p of such a
+                              face (p along the cut; p1 + 2 p2 for type 3), whose nbr_elem and
+                              nbr_side name the big element and side and whose flip maps its face
+                              points onto the big side's sub-face p                            */
 } dg_mesh;
 /* Faces of conforming meshes (Sec. 5.1: each face has a master and a slave side).  Side 2d is
  * the face xi_d = -1 and side 2d+1 the face xi_d = +1 of direction d.  Face point (a,b) of a
@@ -185,8 +192,8 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on every mesh
- * dg_init accepts and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
+ * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on every conforming mesh
+ * dg_init accepts, without finite-volume subcells, and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
  * one-sided derivatives, the log means of the EC flux are differentiated with the forward's
  * branch threshold (series below ((a-b)/(a+b))^2 = 1e-4, logarithms above).  Device arrays [K][5][n^3], pairwise distinct.
  * Not in the paper: the reverse of its operator, for gradients of objectives of U. */
@@ -267,6 +274,37 @@ int dg_info(const dg_handle *h, int64_t out[4]);
 int dg_profile(dg_handle *h, int enable);
 int dg_profile_read(const dg_handle *h, double out[4]);
 
+/* ---- hybrid DG / finite-volume subcells (Sec. 4: shock capturing) ------------------------
+ * A troubled element is advanced by a finite-volume scheme on (N+1)^3 equal subcells of width
+ * w = 2/(N+1) in reference space; its entries of every solution array then hold the subcell
+ * means of U instead of nodal values (the same storage, eq. dg2fv: U_FV = V U with V the
+ * subcell-mean matrix of eq. FVvdm applied along the three directions).  Subcell fluxes use the
+ * handle's Riemann solver with a second-order reconstruction of (rho, u, v, w, p) limited per
+ * direction; at a face between a DG and an FV element the DG trace is taken to the subcell faces
+ * with V, the flux applied to the subcells as is and to the DG nodes through V^-1 (Sec. 4.2).
+ * The metric terms of a subcell face are the means of Ja over that face, Jbar the subcell mean of
+ * J.  Supported: the Euler equations on meshes without boundary sides or non-conforming faces
+ * (DG_ERR_UNSUPPORTED otherwise), every form and node type of the DG operator.
+ * dg_fv_enable     : builds the subcell geometry (synchronous, once) and sets the limiter (0 first
+ *                    order, 1 minmod, 2 van Leer) and the thresholds of the indicator (lo <= hi).
+ *                    Every element starts as DG; afterwards dg_rhs, dg_rk_stage and
+ *                    dg_rk_stage_keep evaluate the hybrid operator.  May be called again to change
+ *                    the limiter and thresholds.
+ * dg_fv_set_types  : element types from a HOST array [K] (0 DG, 1 FV) without converting U.
+ * dg_fv_types      : the current types into a HOST array [K].  Synchronous.
+ * dg_fv_indicator  : the troubled-cell indicator of every element (Sec. 4.3; modal decay of
+ *                    rho p in the orthonormal Legendre basis, log10 max(E_N/E, E_{N-1}/E_{<N}),
+ *                    FV elements read through V^-1) into a HOST array [K].  Synchronous.
+ * dg_fv_switch     : the indicator and the switch with hysteresis (Fig. fv:indicator): DG
+ *                    elements above hi become FV (U <- V U), FV elements below lo become DG
+ *                    (U <- V^-1 U), in place on the DEVICE array U.  Asynchronous.
+ * dg_integrals and dg_timestep treat every element as DG. */
+int dg_fv_enable(dg_handle *h, int limiter, double ind_lo, double ind_hi);
+int dg_fv_set_types(dg_handle *h, const uint8_t *types);
+int dg_fv_types(dg_handle *h, uint8_t *types);
+int dg_fv_indicator(dg_handle *h, const double *U, double *ind);
+int dg_fv_switch(dg_handle *h, double *U);
+
 void dg_destroy(dg_handle *h);
 const char *dg_status_string(int status);
 const char *dg_last_error(const dg_handle *h);
@@ -281,7 +319,8 @@ const char *dg_last_error(const dg_handle *h);
  * the batch, and their gradient scratch is used by the batch's kernels.  Arrays passed below
  * have one entry per member, in the order given to dg_batch_create.
  *
- * dg_batch_create  -> DG_ERR_UNSUPPORTED if a member is not split/LGL or the schemes differ;
+ * dg_batch_create  -> DG_ERR_UNSUPPORTED if a member is not split/LGL, has non-conforming faces or
+ *                     finite-volume subcells enabled, or the schemes differ;
  *                     DG_ERR_ARG for NULL entries, a member listed twice, or a member with
  *                     given-state boundary sides whose state is not set.  Members may have
  *                     any mesh dg_init accepts; a later dg_set_boundary_state on a member is

@@ -210,7 +210,7 @@ int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {
   const dg_handle *h0 = members[0];
   for (int i = 0; i < n_members; ++i) {
     const dg_handle *h = members[i];
-    if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
+    if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT || h->nm || h->fv_on) return DG_ERR_UNSUPPORTED;
     if (h->needs_state && !h->state_set) return DG_ERR_ARG;  // its boundary state is not set
     if (h->needs_tw && !h->tw_set) return DG_ERR_ARG;        // its wall temperature is not set
     if (h->needs_pout && !h->pout_set) return DG_ERR_ARG;    // its outflow pressure is not set

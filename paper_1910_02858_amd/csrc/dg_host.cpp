@@ -236,6 +236,10 @@ inline int face_point_node(int n, int s, int a, int b) {
   const int d = s >> 1, m = (s & 1) ? n - 1 : 0;
   return d == 0 ? m + n * (a + n * b) : (d == 1 ? a + n * (m + n * b) : a + n * (b + n * m));
 }
+// node of the line through face point (ia, jb) of direction dir at position m along dir
+inline int face_line_node(int n, int dir, int ia, int jb, int m) {
+  return dir == 0 ? m + n * (ia + n * jb) : (dir == 1 ? ia + n * (m + n * jb) : ia + n * (jb + n * m));
+}
 // master of a face: a boundary side (no neighbour) itself, the +xi side where a +xi side meets
 // a -xi side, else the element with the smaller index (the smaller side within one element)
 inline bool face_master(int e, int s, int nb, int ns) {
@@ -246,8 +250,10 @@ inline bool face_master(int e, int s, int nb, int ns) {
 
 // xgeo holds the mapping at the LGL nodes of degree ngeo (Sec. 2.1: the geometry degree N_geo is
 // independent of N); it is interpolated to the degree-N LGL nodes, where the curl form is taken
+inline bool is_mortar_side(const int8_t *mort, int q) { return mort && mort[q] != 0; }
+
 int build_geometry(int K, int N, int ngeo, int type, const double *xgeo, const int32_t *nbr, const int8_t *nside,
-                   const int8_t *flip, HostGeo &G, std::string &msg) {
+                   const int8_t *flip, const int8_t *mort, HostGeo &G, std::string &msg) {
   const int n = N + 1, n2 = n * n, n3 = n2 * n;
   const int ng = ngeo + 1, ng3 = ng * ng * ng;
   const Basis1D L = make_basis(N, DG_NODES_LGL);
@@ -344,7 +350,9 @@ int build_geometry(int K, int N, int ngeo, int type, const double *xgeo, const i
     // outward normal of every master side from the element's own metric: +-Ja^d at the face
     for (int s = 0; s < 6; ++s) {
       const int d = s >> 1;
-      if (!face_master(e, s, nbr[e * 6 + s], nside[e * 6 + s])) continue;
+      // a side of a non-conforming face keeps its own normal (a small side is the master of its
+      // part of the face; the big side's flux is projected from the small sides')
+      if (!is_mortar_side(mort, e * 6 + s) && !face_master(e, s, nbr[e * 6 + s], nside[e * 6 + s])) continue;
       const std::vector<xf> &l = (s & 1) ? S.lp : S.lm;
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a)
@@ -377,7 +385,7 @@ int build_geometry(int K, int N, int ngeo, int type, const double *xgeo, const i
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int nb = nbr[e * 6 + s], ns = nside[e * 6 + s], o = flip ? flip[e * 6 + s] : 0;
-      if (face_master(e, s, nb, ns)) continue;
+      if (is_mortar_side(mort, e * 6 + s) || face_master(e, s, nb, ns)) continue;
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
           int a2, b2;
@@ -394,14 +402,17 @@ std::vector<uint8_t> face_codes(const dg_mesh *mesh) {
   const int K = mesh->n_elems;
   bool structured = true;
   for (int q = 0; q < 6 * K && structured; ++q)
-    structured = mesh->nbr_elem[q] >= 0 && mesh->nbr_side[q] == ((q % 6) ^ 1) && (!mesh->flip || mesh->flip[q] == 0);
+    structured = mesh->nbr_elem[q] >= 0 && mesh->nbr_side[q] == ((q % 6) ^ 1) && (!mesh->flip || mesh->flip[q] == 0) &&
+                 !is_mortar_side(mesh->mortar, q);
   std::vector<uint8_t> fc;
   if (structured) return fc;
   fc.resize((size_t)6 * K);
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, ns = mesh->nbr_side[q], o = mesh->flip ? mesh->flip[q] : 0;
-      if (mesh->nbr_elem[q] < 0)
+      if (is_mortar_side(mesh->mortar, q))
+        fc[q] = (uint8_t)(128 | 64 | dg::FACE_MORTAR);  // fluxes from the mortar face arrays
+      else if (mesh->nbr_elem[q] < 0)
         fc[q] = (uint8_t)(128 | 64 | ns);  // boundary of kind ns, its own master
       else
         fc[q] = (uint8_t)(ns | (o << 3) | (face_master(e, s, mesh->nbr_elem[q], ns) ? 64 : 0));
@@ -419,10 +430,27 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
   // connectivity: every side either is a boundary (neighbour -1, kind in nbr_side:
   // DG_BC_SYMMETRY ... DG_BC_OUTFLOW, orientation 0) or has a neighbour that names it back, on the side and with
   // the inverse orientation it names
+  const int8_t *mort = mesh->mortar;
+  std::vector<uint8_t> taken;  // positions of every big side named by a small side
+  if (mort) taken.assign((size_t)6 * K, 0);
   for (int e = 0; e < K; ++e)
     for (int s = 0; s < 6; ++s) {
       const int q = e * 6 + s, nb = mesh->nbr_elem[q], ns = mesh->nbr_side[q];
       const int o = mesh->flip ? mesh->flip[q] : 0;
+      const int mk = mort ? mort[q] : 0;
+      if (mk < 0 || mk > 7) return DG_ERR_MESH;
+      if (mk >= 1 && mk <= 3) {  // big side of a non-conforming face
+        if (nb != -1 || o != 0) return DG_ERR_MESH;
+        continue;
+      }
+      if (mk >= 4) {  // small side at position mk - 4 of the big side (nb, ns)
+        if (nb < 0 || nb >= K || ns < 0 || ns > 5 || o < 0 || o > 7 || nb == e) return DG_ERR_MESH;
+        const int t = mort[nb * 6 + ns], p = mk - 4;
+        if (t < 1 || t > 3 || p >= (t == 3 ? 4 : 2)) return DG_ERR_MESH;
+        if (taken[nb * 6 + ns] & (1u << p)) return DG_ERR_MESH;
+        taken[nb * 6 + ns] |= (uint8_t)(1u << p);
+        continue;
+      }
       if (nb == -1) {
         if (ns < DG_BC_SYMMETRY || ns > DG_BC_OUTFLOW) return DG_ERR_UNSUPPORTED;
         if (o != 0) return DG_ERR_MESH;
@@ -432,11 +460,27 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
       if (ns < 0 || ns > 5 || o < 0 || o > 7 || (nb == e && ns == s)) return DG_ERR_MESH;
       const int qn = nb * 6 + ns;
       if (mesh->nbr_elem[qn] != e || mesh->nbr_side[qn] != s) return DG_ERR_MESH;
+      if (mort && mort[qn] != 0) return DG_ERR_MESH;
       if ((mesh->flip ? mesh->flip[qn] : 0) != orientation_inverse(o)) return DG_ERR_MESH;
     }
+  if (mort)
+    for (int q = 0; q < 6 * K; ++q)
+      if (mort[q] >= 1 && mort[q] <= 3 && taken[q] != (mort[q] == 3 ? 15 : 3)) return DG_ERR_MESH;
   // the matched face points coincide up to one translation per face (a periodic shift); the
   // faces are compared at the geometry's own nodes
   const int NG = mesh->n_geo, n = NG + 1, n3 = n * n * n;
+  // a small side's points lie on the big side's face polynomial at the points of its sub-face
+  std::vector<xf> gIL, gIU;  // geometry-degree interpolation to the lower / upper half
+  if (mort) {
+    const Basis1D Bg = make_basis(NG, DG_NODES_LGL);
+    gIL.resize((size_t)n * n);
+    gIU.resize((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m) {
+        gIL[i * n + m] = lag_eval(Bg.x, Bg.bw, m, (Bg.x[i] - 1.0L) / 2.0L);
+        gIU[i * n + m] = lag_eval(Bg.x, Bg.bw, m, (Bg.x[i] + 1.0L) / 2.0L);
+      }
+  }
   for (int e = 0; e < K; ++e) {
     const double *xe = mesh->xgeo + (size_t)e * 3 * n3;
     double ext = 0.0;
@@ -450,6 +494,29 @@ int validate_mesh(const dg_mesh *mesh, int N, int node_type) {
       if (nb < 0) continue;
       const double *xn = mesh->xgeo + (size_t)nb * 3 * n3;
       double shift[3];
+      if (mort && mort[q] >= 4) {
+        const int t = mort[nb * 6 + ns], p = mort[q] - 4;
+        const int p1 = t == 1 ? p : (t == 3 ? (p & 1) : -1), p2 = t == 2 ? p : (t == 3 ? (p >> 1) : -1);
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            int a2, b2;
+            face_mate(o, NG, a, b, a2, b2);
+            const int qe = face_point_node(n, s, a, b);
+            for (int d = 0; d < 3; ++d) {
+              xf v = 0.0L;
+              for (int l = 0; l < n; ++l)
+                for (int m = 0; m < n; ++m) {
+                  const xf c1 = p1 < 0 ? (m == a2 ? 1.0L : 0.0L) : (p1 ? gIU : gIL)[a2 * n + m];
+                  const xf c2 = p2 < 0 ? (l == b2 ? 1.0L : 0.0L) : (p2 ? gIU : gIL)[b2 * n + l];
+                  v += c1 * c2 * xn[d * n3 + face_point_node(n, ns, m, l)];
+                }
+              const double dx = xe[d * n3 + qe] - (double)v;
+              if (a == 0 && b == 0) shift[d] = dx;
+              else if (!(std::fabs(dx - shift[d]) <= 1e-9 * ext)) return DG_ERR_MESH;
+            }
+          }
+        continue;
+      }
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
           int a2, b2;
@@ -519,6 +586,40 @@ int main_dispatch(dg_handle *h, const double *U, const double *G, double *out, d
   }
 }
 
+// the kernels of the non-conforming faces: their lifting terms (flux = false) or their numerical
+// fluxes (flux = true; G = the lifting output, gradients on LG nodes)
+int mortar_dispatch(dg_handle *h, const double *U, const double *G, bool flux) {
+  const dg::Geo g = h->geo();
+  const bool lgl = h->node_type == DG_NODES_LGL;
+  switch (h->N) {
+#define DG_CASE(NN)                                                                                       \
+  case NN:                                                                                                \
+    return flux ? dg::launch_mortar_flux<NN>(g, h->ph, lgl, h->sc.eqn, h->d_md, h->nm, U, G, h->stream) \
+                : dg::launch_mortar_lift<NN>(g, h->ph, lgl, h->d_md, h->nm, U, h->stream);
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return DG_ERR_UNSUPPORTED;
+  }
+}
+
+// the hybrid DG/FV kernels: what 0 the faces touching FV elements, 1 the FV elements' operator,
+// 2 the indicator (3: with switching) in place on U
+int fv_dispatch(dg_handle *h, int what, const double *U, double *out, double *R, double a, double b, double dt,
+                int mode) {
+  const dg::Geo g = h->geo();
+  const bool lgl = h->node_type == DG_NODES_LGL;
+  switch (h->N) {
+#define DG_CASE(NN)                                                                                           \
+  case NN:                                                                                                    \
+    if (what == 0) return dg::launch_fv_face<NN>(g, h->ph, h->fvg, lgl, U, h->stream);                      \
+    if (what == 1) return dg::launch_fv_volume<NN>(g, h->ph, h->fvg, U, out, R, a, b, dt, mode, h->stream); \
+    return dg::launch_fv_switch<NN>(g, h->ph, h->fvg, const_cast<double *>(U), what == 3, h->stream);
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
+#undef DG_CASE
+    default: return DG_ERR_UNSUPPORTED;
+  }
+}
+
 // lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on.  The
 // split form takes the contravariant viscous fluxes, the other forms the gradients, in the
 // handle's scratch or, if Gkeep != NULL, in Gkeep (kept for a later reverse sweep).
@@ -528,14 +629,34 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
   const bool split = h->sc.form == DG_FORM_SPLIT;
   if (h->prof) (void)hipEventRecord(h->ev[0], h->stream);
   if (ns) {
+    if (h->nm) {
+      // lifting surface terms of the non-conforming faces, read by the lifting kernel
+      const int rc = mortar_dispatch(h, U, nullptr, false);
+      if (rc) return rc;
+    }
     double *dst = Gkeep ? Gkeep : h->d_G;
     const int rc = split ? lift_dispatch(h, U, 1, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
   const double *Gin = (ns && Gkeep) ? Gkeep : h->d_G;
+  if (h->fv_on) {
+    // hybrid DG/FV (Euler): fluxes of the faces that touch finite-volume elements first
+    const int rc = fv_dispatch(h, 0, U, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+    if (rc) return rc;
+  }
+  if (h->nm) {
+    // numerical fluxes of the non-conforming faces, read by the operator kernel
+    const int rc = mortar_dispatch(h, U, Gin, true);
+    if (rc) return rc;
+  }
   int rc = main_dispatch(h, U, Gin, out, R, a, b, dt, mode);
   if (rc) return rc;
+  if (h->fv_on) {
+    // the finite-volume elements' subcell operator (the DG kernel leaves them out)
+    rc = fv_dispatch(h, 1, U, out, R, a, b, dt, mode);
+    if (rc) return rc;
+  }
   if (h->prof) {
     (void)hipEventRecord(h->ev[2], h->stream);
     if (hipEventSynchronize(h->ev[2]) != hipSuccess) return DG_ERR_HIP;
@@ -647,12 +768,21 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
     h->tab.lhm[j] = (double)(B.lm[j] / B.w[j]); h->tab.lhp[j] = (double)(B.lp[j] / B.w[j]);
     h->tab.w[j] = (double)B.w[j];
   }
+  // mortar operators of the solution nodes (Sec. 3.2)
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < n; ++m) {
+      h->tab.IL[i * n + m] = (double)lag_eval(B.x, B.bw, m, (B.x[i] - 1.0L) / 2.0L);
+      h->tab.IU[i * n + m] = (double)lag_eval(B.x, B.bw, m, (B.x[i] + 1.0L) / 2.0L);
+      h->tab.PL[i * n + m] = (double)(lag_eval(B.x, B.bw, i, (B.x[m] - 1.0L) / 2.0L) * B.w[m] / B.w[i]);
+      h->tab.PU[i * n + m] = (double)(lag_eval(B.x, B.bw, i, (B.x[m] + 1.0L) / 2.0L) * B.w[m] / B.w[i]);
+    }
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return DG_ERR_HIP; }
   // device address of the static scratch of the allocation-free entry points, once per device
   if (int src = dg::static_scratch_setup(h->device)) { delete h; return src; }
   HostGeo G;
   std::string msg;
-  int rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
+  int rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip,
+                          mesh->mortar, G, msg);
   if (rc) { delete h; return rc; }
   const std::vector<uint8_t> fc = face_codes(mesh);
   for (int q = 0; q < 6 * K; ++q)
@@ -662,8 +792,34 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
       if (mesh->nbr_side[q] == DG_BC_WALL_ISOTHERMAL) h->needs_tw = true;
       if (mesh->nbr_side[q] == DG_BC_OUTFLOW) h->needs_pout = true;
     }
+  // non-conforming faces: one descriptor per big side, one face-array slot per mortar side
+  std::vector<dg::MortarDesc> md;
+  std::vector<int32_t> mslot;
+  if (mesh->mortar) {
+    mslot.assign((size_t)6 * K, -1);
+    std::vector<int> big_of((size_t)6 * K, -1);
+    int slots = 0;
+    for (int q = 0; q < 6 * K; ++q)
+      if (mesh->mortar[q] >= 1 && mesh->mortar[q] <= 3) {
+        dg::MortarDesc d{};
+        d.eb = q / 6; d.sb = q % 6; d.type = mesh->mortar[q]; d.slot = slots++;
+        mslot[q] = d.slot;
+        big_of[q] = (int)md.size();
+        md.push_back(d);
+      }
+    for (int q = 0; q < 6 * K; ++q)
+      if (mesh->mortar[q] >= 4) {
+        dg::MortarDesc &d = md[big_of[mesh->nbr_elem[q] * 6 + mesh->nbr_side[q]]];
+        const int p = mesh->mortar[q] - 4;
+        d.es[p] = q / 6; d.ss[p] = q % 6; d.o[p] = mesh->flip ? mesh->flip[q] : 0; d.sl[p] = slots++;
+        mslot[q] = d.sl[p];
+      }
+    h->nm = (int)md.size();
+    if (h->nm == 0) mslot.clear();
+  }
   const std::vector<double> &sJ = G.sJ;
   h->x_nodes.swap(G.xs);
+  h->J_nodes.swap(G.J);
   const bool ns = sc->eqn == DG_NAVIER_STOKES;
   rc = dev_alloc(&h->d_Ja, (size_t)K * 9 * n3);
   if (!rc) rc = dev_alloc(&h->d_sJ, (size_t)K * n3);
@@ -674,6 +830,15 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
   if (!rc) rc = dev_alloc(&h->d_partial, (size_t)K * 8);
   if (!rc) rc = dev_alloc(&h->d_red, 8);
+  if (!rc && h->nm) {
+    int slots = 0;
+    for (const dg::MortarDesc &d : md) slots += 1 + (d.type == 3 ? 4 : 2);
+    rc = dev_alloc(&h->d_md, md.size());
+    if (!rc) rc = dev_alloc(&h->d_mslot, mslot.size());
+    if (!rc) rc = dev_alloc(&h->d_mflux, (size_t)slots * 5 * n2);
+    if (!rc) rc = dev_alloc(&h->d_mlift, (size_t)slots * 12 * n2);
+    if (!rc) rc = dev_alloc(&h->d_mg, (size_t)slots * 12 * n2);
+  }
   if (rc) { dg_destroy(h); return rc; }
   bool ok = hipMemcpy(h->d_Ja, G.Ja.data(), G.Ja.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(h->d_sJ, sJ.data(), sJ.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
@@ -681,6 +846,10 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   ok = ok && hipMemcpy(h->d_nbr, mesh->nbr_elem, (size_t)K * 6 * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   if (!fc.empty()) ok = ok && hipMemcpy(h->d_fc, fc.data(), fc.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(h->d_tab, &h->tab, sizeof(dg::Tab), hipMemcpyHostToDevice) == hipSuccess;
+  if (h->nm) {
+    ok = ok && hipMemcpy(h->d_md, md.data(), md.size() * sizeof(dg::MortarDesc), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_mslot, mslot.data(), mslot.size() * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (!ok) { dg_destroy(h); return DG_ERR_HIP; }
   *out = h;
   return DG_OK;
@@ -693,7 +862,8 @@ int dg_host_geometry(const dg_mesh *mesh, int N, int node_type, double *Ja, doub
   const int K = mesh->n_elems, n = N + 1;
   HostGeo G;
   std::string msg;
-  rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip, G, msg);
+  rc = build_geometry(K, N, mesh->n_geo, node_type, mesh->xgeo, mesh->nbr_elem, mesh->nbr_side, mesh->flip,
+                      mesh->mortar, G, msg);
   if (rc) return rc;
   if (Ja) std::memcpy(Ja, G.Ja.data(), G.Ja.size() * sizeof(double));
   if (J) std::memcpy(J, G.J.data(), G.J.size() * sizeof(double));
@@ -999,6 +1169,167 @@ int dg_profile_read(const dg_handle *h, double out[4]) {
   return DG_OK;
 }
 
+// ---- hybrid DG/finite-volume subcells (Sec. 4)
+namespace {
+// inverse of an n x n matrix (Gauss-Jordan, partial pivoting, extended precision)
+std::vector<xf> invert(std::vector<xf> A, int n) {
+  std::vector<xf> I((size_t)n * n, 0.0L);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0L;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs((double)A[(size_t)r * n + c]) > std::fabs((double)A[(size_t)piv * n + c])) piv = r;
+    for (int j = 0; j < n; ++j) {
+      std::swap(A[(size_t)c * n + j], A[(size_t)piv * n + j]);
+      std::swap(I[(size_t)c * n + j], I[(size_t)piv * n + j]);
+    }
+    const xf d = A[(size_t)c * n + c];
+    for (int j = 0; j < n; ++j) { A[(size_t)c * n + j] /= d; I[(size_t)c * n + j] /= d; }
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const xf f = A[(size_t)r * n + c];
+        for (int j = 0; j < n; ++j) { A[(size_t)r * n + j] -= f * A[(size_t)c * n + j]; I[(size_t)r * n + j] -= f * I[(size_t)c * n + j]; }
+      }
+  }
+  return I;
+}
+}  // namespace
+
+int dg_fv_enable(dg_handle *h, int limiter, double ind_lo, double ind_hi) {
+  if (!h) return DG_ERR_ARG;
+  if (h->sc.eqn != DG_EULER) return fail(h, DG_ERR_UNSUPPORTED, "finite-volume subcells are built for the Euler equations");
+  if (h->has_boundary || h->nm)
+    return fail(h, DG_ERR_UNSUPPORTED, "finite-volume subcells are built for conforming meshes without boundary sides");
+  if (limiter < 0 || limiter > 2 || !std::isfinite(ind_lo) || !std::isfinite(ind_hi) || ind_lo > ind_hi)
+    return fail(h, DG_ERR_ARG, "limiter must be 0..2 and the thresholds finite with lo <= hi");
+  const int K = h->K, N = h->N, n = h->n, n2 = h->n2, n3 = h->n3;
+  if (!h->fv_on) {
+    const Basis1D B = make_basis(N, h->node_type);
+    const xf w = 2.0L / n;
+    // V_DG=>FV: subcell means of the Lagrange basis by the scheme's quadrature mapped into each subcell
+    std::vector<xf> V((size_t)n * n), L((size_t)n * n);
+    for (int k = 0; k < n; ++k)
+      for (int i = 0; i < n; ++i) {
+        xf acc = 0.0L;
+        for (int l = 0; l < n; ++l) acc += B.w[l] * lag_eval(B.x, B.bw, i, -1.0L + k * w + (B.x[l] + 1.0L) * w / 2.0L);
+        V[(size_t)k * n + i] = acc / 2.0L;
+      }
+    // orthonormal Legendre polynomials at the nodes, L[i][k] = sqrt((2k+1)/2) P_k(x_i)
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        xf P, dP;
+        legendre_pd(k, B.x[i], P, dP);
+        L[(size_t)i * n + k] = P * std::sqrt((2.0L * k + 1.0L) / 2.0L);
+      }
+    const std::vector<xf> Vi = invert(V, n), Li = invert(L, n);
+    std::vector<double> tab((size_t)3 * n * n);
+    for (int c = 0; c < n * n; ++c) { tab[c] = (double)V[c]; tab[n * n + c] = (double)Vi[c]; tab[2 * n * n + c] = (double)Li[c]; }
+    // subcell geometry from the metric terms: Jbar = (V x V x V) J, face means of Ja^dir
+    std::vector<double> Ja((size_t)K * 9 * n3);
+    if (hipMemcpy(Ja.data(), h->d_Ja, Ja.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(h, DG_ERR_HIP, "copy of the metric terms failed");
+    std::vector<xf> lf((size_t)(n + 1) * n);
+    for (int f = 0; f <= n; ++f)
+      for (int m = 0; m < n; ++m) lf[(size_t)f * n + m] = lag_eval(B.x, B.bw, m, -1.0L + f * w);
+    std::vector<double> Jbar((size_t)K * n3), Nf((size_t)K * 3 * (n + 1) * n2 * 3);
+    for (int e = 0; e < K; ++e) {
+      std::vector<xf> x(n3), y(n3);
+      for (int q = 0; q < n3; ++q) x[q] = h->J_nodes[(size_t)e * n3 + q];
+      for (int dir = 0; dir < 3; ++dir) {
+        tensor_apply(V.data(), n, dir, x.data(), y.data());
+        x.swap(y);
+      }
+      for (int q = 0; q < n3; ++q) Jbar[(size_t)e * n3 + q] = (double)x[q];
+      for (int dir = 0; dir < 3; ++dir)
+        for (int d = 0; d < 3; ++d) {
+          const double *J = Ja.data() + ((size_t)e * 9 + dir * 3 + d) * n3;
+          for (int f = 0; f <= n; ++f) {
+            std::vector<xf> gfa((size_t)n2);  // Ja^dir_d on the face position f, at face point (ia, jb)
+            for (int jb = 0; jb < n; ++jb)
+              for (int ia = 0; ia < n; ++ia) {
+                xf v = 0.0L;
+                for (int m = 0; m < n; ++m) v += lf[(size_t)f * n + m] * J[face_line_node(n, dir, ia, jb, m)];
+                gfa[ia + n * jb] = v;
+              }
+            for (int bb = 0; bb < n; ++bb)
+              for (int aa = 0; aa < n; ++aa) {
+                xf v = 0.0L;
+                for (int jb = 0; jb < n; ++jb)
+                  for (int ia = 0; ia < n; ++ia) v += V[(size_t)aa * n + ia] * V[(size_t)bb * n + jb] * gfa[ia + n * jb];
+                Nf[((((size_t)e * 3 + dir) * (n + 1) + f) * n2 + aa + n * bb) * 3 + d] = (double)v;
+              }
+          }
+        }
+    }
+    int rc = dev_alloc(&h->d_fvtab, tab.size());
+    if (!rc) rc = dev_alloc(&h->d_fvJbar, Jbar.size());
+    if (!rc) rc = dev_alloc(&h->d_fvNf, Nf.size());
+    if (!rc) rc = dev_alloc(&h->d_fvFx, (size_t)K * 30 * n2);
+    if (!rc) rc = dev_alloc(&h->d_fvDx, (size_t)K * 30 * n2);
+    if (!rc) rc = dev_alloc(&h->d_fvind, (size_t)K);
+    if (!rc) rc = dev_alloc(&h->d_fvflag, (size_t)K);
+    if (rc) return fail(h, rc, "allocation of the finite-volume tables failed");
+    bool ok = hipMemcpy(h->d_fvtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_fvJbar, Jbar.data(), Jbar.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_fvNf, Nf.data(), Nf.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(h->d_fvflag, 0, (size_t)K) == hipSuccess;
+    if (!ok) return fail(h, DG_ERR_HIP, "upload of the finite-volume tables failed");
+    h->fvg.V = h->d_fvtab; h->fvg.Vi = h->d_fvtab + n * n; h->fvg.Li = h->d_fvtab + 2 * n * n;
+    h->fvg.Jbar = h->d_fvJbar; h->fvg.Nf = h->d_fvNf; h->fvg.flag = h->d_fvflag;
+    h->fvg.Fx = h->d_fvFx; h->fvg.Dx = h->d_fvDx; h->fvg.ind = h->d_fvind;
+    h->fvg.w = (double)w;
+    h->fv_on = true;
+  }
+  h->fvg.limiter = limiter;
+  h->fvg.lo = ind_lo;
+  h->fvg.hi = ind_hi;
+  return DG_OK;
+}
+
+int dg_fv_set_types(dg_handle *h, const uint8_t *types) {
+  if (!h || !types) return DG_ERR_ARG;
+  if (!h->fv_on) return fail(h, DG_ERR_ARG, "call dg_fv_enable first");
+  std::vector<uint8_t> t(types, types + h->K);
+  for (uint8_t &c : t)
+    if (c > 1) return fail(h, DG_ERR_ARG, "element types are 0 (DG) or 1 (finite volume)");
+  if (hipMemcpyAsync(h->d_fvflag, t.data(), t.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(h, DG_ERR_HIP, "copy of the element types failed");
+  return DG_OK;
+}
+
+int dg_fv_types(dg_handle *h, uint8_t *types) {
+  if (!h || !types) return DG_ERR_ARG;
+  if (!h->fv_on) return fail(h, DG_ERR_ARG, "call dg_fv_enable first");
+  if (hipMemcpyAsync(types, h->d_fvflag, (size_t)h->K, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(h, DG_ERR_HIP, "copy of the element types failed");
+  return DG_OK;
+}
+
+int dg_fv_indicator(dg_handle *h, const double *U, double *ind) {
+  if (!h || !ind) return DG_ERR_ARG;
+  if (!h->fv_on) return fail(h, DG_ERR_ARG, "call dg_fv_enable first");
+  int rc = check_solution_ptr(h, U, "U");
+  if (rc) return rc;
+  rc = fv_dispatch(h, 2, U, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+  if (rc) return fail(h, rc, "launch of the indicator failed");
+  if (hipMemcpyAsync(ind, h->d_fvind, (size_t)h->K * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(h, DG_ERR_HIP, "copy of the indicator failed");
+  return DG_OK;
+}
+
+int dg_fv_switch(dg_handle *h, double *U) {
+  if (!h) return DG_ERR_ARG;
+  if (!h->fv_on) return fail(h, DG_ERR_ARG, "call dg_fv_enable first");
+  int rc = check_solution_ptr(h, U, "U");
+  if (rc) return rc;
+  rc = fv_dispatch(h, 3, U, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+  if (rc) return fail(h, rc, "launch of the indicator failed");
+  return DG_OK;
+}
+
 void dg_destroy(dg_handle *h) {
   if (!h) return;
   for (int i = 0; i < 3; ++i)
@@ -1006,6 +1337,10 @@ void dg_destroy(dg_handle *h) {
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_fc); (void)hipFree(h->d_tab);
   (void)hipFree(h->d_G); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
+  (void)hipFree(h->d_md); (void)hipFree(h->d_mslot); (void)hipFree(h->d_mflux); (void)hipFree(h->d_mlift);
+  (void)hipFree(h->d_mg);
+  (void)hipFree(h->d_fvtab); (void)hipFree(h->d_fvJbar); (void)hipFree(h->d_fvNf); (void)hipFree(h->d_fvFx);
+  (void)hipFree(h->d_fvDx); (void)hipFree(h->d_fvind); (void)hipFree(h->d_fvflag);
   delete h;
 }
 
@@ -1016,6 +1351,10 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
   if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
+  if (h->nm)
+    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for conforming meshes");
+  if (h->fv_on)
+    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the DG operator");
   if (int rc = state_ready(h)) return rc;
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
   if (ns && !h->d_Pf) {

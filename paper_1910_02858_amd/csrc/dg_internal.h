@@ -19,6 +19,22 @@ struct Tab {
   double D[(NMAX + 1) * (NMAX + 1)];
   double Dh[(NMAX + 1) * (NMAX + 1)];
   double lm[NMAX + 1], lp[NMAX + 1], lhm[NMAX + 1], lhp[NMAX + 1], w[NMAX + 1];
+  // mortar operators (Sec. 3.2): interpolation of the big side to its lower / upper half,
+  // IL[i*n+m] = l_m((x_i - 1)/2), IU likewise with +1, and the projection back,
+  // PL[i*n+a] = l_i((x_a - 1)/2) w_a / w_i, PU likewise
+  double IL[(NMAX + 1) * (NMAX + 1)], IU[(NMAX + 1) * (NMAX + 1)];
+  double PL[(NMAX + 1) * (NMAX + 1)], PU[(NMAX + 1) * (NMAX + 1)];
+};
+
+// Face code kind of a side of a non-conforming face (bits 0-2 of a boundary-flagged code): its
+// flux and lifting terms come from the mortar face arrays (Geo::mflux, Geo::mlift).
+constexpr int FACE_MORTAR = 7;
+
+// One non-conforming face (Sec. 3.2): the big side and its 2 (types 1, 2) or 4 (type 3) small
+// sides, each with its face-array slot.
+struct MortarDesc {
+  int eb, sb, type, slot;          // big element, side, mortar type 1..3, slot of the big side
+  int es[4], ss[4], o[4], sl[4];   // small sides by position: element, side, orientation code, slot
 };
 
 // Device-resident geometry of one mesh.
@@ -34,6 +50,30 @@ struct Geo {
   const uint8_t *fc;
   const Tab *tab;
   int K;
+  // non-conforming faces (NULL without): slot of every side [K][6] (-1 for conforming sides), and
+  // per slot the side's outward numerical flux times the surface element minus the BR1 viscous
+  // mean, mflux[slot][5][n^2], its lifting surface term W* s n_d, mlift[slot][d*4+c][n^2], and the
+  // lifted gradients at its face points (LGL nodes), mg[slot][d*4+c][n^2]
+  const int32_t *mslot;
+  double *mflux, *mlift, *mg;
+  // hybrid DG/FV operator (NULL without): element types [K] (1 = finite volume) and the outward
+  // fluxes [K][6][5][n^2] of the sides of faces that touch a finite-volume element
+  const uint8_t *fvflag;
+  const double *fvFx;
+};
+
+// Finite-volume subcells (Sec. 4) of one mesh on the device.
+struct FvGeo {
+  const double *V, *Vi, *Li;  // [n*n]: V_DG=>FV, its inverse, the inverse of Ptilde_k(x_i) (modal)
+  const double *Jbar;         // [K][n^3] subcell mean of J
+  const double *Nf;           // [K][3][n+1][n^2][3] mean of Ja^dir over subcell face f of direction dir
+  uint8_t *flag;              // [K] 1 = finite-volume element (U holds subcell means)
+  double *Fx;                 // [K][6][5][n^2] outward flux of sides of faces touching an FV element
+  double *Dx;                 // [K][6][5][n^2] the neighbour's face datum at those sides (conservative)
+  double *ind;                // [K] last troubled-cell indicator
+  int limiter;                // 0 first order, 1 minmod, 2 van Leer
+  double w;                   // subcell width 2/(N+1)
+  double lo, hi;              // switch to DG below lo, to FV above hi
 };
 
 struct Phys {
@@ -62,6 +102,23 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
 template <int N>
 int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double cfl_unused, double *partial,
                   hipStream_t st);
+// hybrid DG/FV (Euler): face fluxes of faces touching FV elements, the FV elements' operator with
+// the optional fused RK stage (mode as launch_main), and the indicator with switching in place
+template <int N>
+int launch_fv_face(const Geo &g, const Phys &ph, const FvGeo &f, bool lgl, const double *U, hipStream_t st);
+template <int N>
+int launch_fv_volume(const Geo &g, const Phys &ph, const FvGeo &f, const double *U, double *out, double *R, double a,
+                     double b, double dt, int mode, hipStream_t st);
+template <int N>
+int launch_fv_switch(const Geo &g, const Phys &ph, const FvGeo &f, double *U, int do_switch, hipStream_t st);
+// non-conforming faces: the lifting's surface terms (before the lifting) and the numerical fluxes
+// (after it) of every mortar's small and big sides, into Geo::mlift and Geo::mflux
+template <int N>
+int launch_mortar_lift(const Geo &g, const Phys &ph, bool lgl, const MortarDesc *md, int nm, const double *U,
+                       hipStream_t st);
+template <int N>
+int launch_mortar_flux(const Geo &g, const Phys &ph, bool lgl, int eqn, const MortarDesc *md, int nm,
+                       const double *U, const double *G, hipStream_t st);
 
 // One ensemble member as the batched kernels see it (entry of a device-resident table).
 struct Member {
@@ -162,6 +219,15 @@ struct dg_handle {
   double *d_Ja = nullptr, *d_sJ = nullptr, *d_fn = nullptr;
   int32_t *d_nbr = nullptr;
   uint8_t *d_fc = nullptr;      // face codes [K][6], only on meshes that are not structured
+  int nm = 0;                   // non-conforming faces (mortars)
+  dg::MortarDesc *d_md = nullptr;
+  int32_t *d_mslot = nullptr;   // [K][6] face-array slot of every side, -1 if conforming
+  bool fv_on = false;           // hybrid DG/FV operator enabled (dg_fv_enable)
+  dg::FvGeo fvg{};              // its device tables (owned: the pointers below)
+  double *d_fvtab = nullptr, *d_fvJbar = nullptr, *d_fvNf = nullptr, *d_fvFx = nullptr, *d_fvDx = nullptr;
+  double *d_fvind = nullptr;
+  uint8_t *d_fvflag = nullptr;
+  double *d_mflux = nullptr, *d_mlift = nullptr, *d_mg = nullptr;  // [slots][5|12|12][n^2]
   bool has_boundary = false;    // some side has no neighbour
   bool needs_state = false;     // some boundary side takes the given outer state
   bool state_set = false;       // dg_set_boundary_state has been called
@@ -180,10 +246,13 @@ struct dg_handle {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double prof_ms[4] = {0, 0, 0, 0};  // lift ms, lift launches, main ms, main launches
   std::vector<double> x_nodes;  // solution-node coordinates (host), [K][3][n3]
+  std::vector<double> J_nodes;  // Jacobian at the solution nodes (host), [K][n3]
   std::string err;
   dg::Geo geo() const {
     dg::Geo g;
     g.Ja = d_Ja; g.sJ = d_sJ; g.fn = d_fn; g.nbr = d_nbr; g.fc = d_fc; g.tab = d_tab; g.K = K;
+    g.mslot = d_mslot; g.mflux = d_mflux; g.mlift = d_mlift; g.mg = d_mg;
+    g.fvflag = fv_on ? d_fvflag : nullptr; g.fvFx = fv_on ? d_fvFx : nullptr;
     return g;
   }
 };

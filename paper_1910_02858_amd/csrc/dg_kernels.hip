@@ -61,6 +61,12 @@ __device__ __forceinline__ void mirror_grad(double *g, const double *nh) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) mirror3(g + 4 * d, nh);
 }
+// side s of element e belongs to a non-conforming face (its terms come from the mortar arrays)
+__device__ __forceinline__ bool is_mortar(const Geo &g, int e, int s) {
+  if (!g.fc) return false;
+  const int c = g.fc[(size_t)e * 6 + s];
+  return (c & 128) && (c & 7) == FACE_MORTAR;
+}
 __device__ __forceinline__ void unit3(const double *x, double *nh) {
   const double il = 1.0 / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
   nh[0] = x[0] * il; nh[1] = x[1] * il; nh[2] = x[2] * il;
@@ -378,6 +384,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       }
       Uq[4] = ph.pout / gm1 + 0.5 * (Uq[1] * Uq[1] + Uq[2] * Uq[2] + Uq[3] * Uq[3]) / Uq[0];
       grad_prim_to_W(Uq, gm1, ph.R, WR);
+    } else if (GEN && f.bnd && f.kind == FACE_MORTAR) {
+      // non-conforming face: the surface term comes from the mortar face array
+#pragma unroll
+      for (int v = 0; v < 4; ++v) WR[v] = WL[v];
     } else if (GEN && f.bnd) {
       // symmetry plane: the outer W is the inner one with the velocity reflected
       const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
@@ -438,11 +448,18 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
         const int ab = a + n * b;
         const double sl_ = plus ? lh : -lh;
+        if (GEN && is_mortar(g, e, s)) {
+          // non-conforming face: W* s n_d (outward) from the mortar face array
+          const double *ml = g.mlift + (size_t)g.mslot[(size_t)e * 6 + s] * 12 * n2 + ab;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const double c1 = sl_ * sJa[d * n3 + t];
+          for (int c = 0; c < 12; ++c) acc[c] += lh * ml[c * n2];
+        } else {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sWs[(s * 4 + v) * n2 + ab];
+          for (int d = 0; d < 3; ++d) {
+            const double c1 = sl_ * sJa[d * n3 + t];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[d * 4 + v] += c1 * sWs[(s * 4 + v) * n2 + ab];
+          }
         }
       }
     }
@@ -457,6 +474,12 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       if (LGL && lh == 0.0) continue;
       const int a = dn == 0 ? j : i, b = dn == 2 ? j : k;
       const int ab = a + n * b;
+      if (GEN && is_mortar(g, e, s)) {
+        const double *ml = g.mlift + (size_t)g.mslot[(size_t)e * 6 + s] * 12 * n2 + ab;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] += lh * ml[c * n2];
+        continue;
+      }
       const double *nt = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -474,6 +497,21 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma clang fp contract(off)
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] *= sj;
+    }
+    if (GEN && LGL && g.mslot) {
+      // face nodes of non-conforming sides keep their gradients for the mortar flux kernel
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+        const int id = dir == 0 ? i : (dir == 1 ? j : k);
+        if (id != 0 && id != N) continue;
+        const int s = 2 * dir + (id == N ? 1 : 0);
+        const int slot = g.mslot[(size_t)e * 6 + s];
+        if (slot < 0) continue;
+        const int ab = (dir == 0 ? j : i) + n * (dir == 2 ? j : k);
+        double *mg = g.mg + (size_t)slot * 12 * n2 + ab;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) mg[c * n2] = acc[c];
+      }
     }
     if (OUT == LIFT_G) {
       double *Ge = G + (size_t)e * 12 * n3;
@@ -526,7 +564,9 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
 
 // ----------------------------------------------------------------------------- operator
 // FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
-template <int N, bool LGL, bool NS, int FORM, int MODE, bool GEN>
+// FVM: hybrid DG/FV mesh (Euler): finite-volume elements are left to k_fv_volume, and the sides
+// that meet one take their flux from Geo::fvFx.
+template <int N, bool LGL, bool NS, int FORM, int MODE, bool GEN, bool FVM = false>
 __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double *__restrict__ U,
                                                     const double *__restrict__ G, double *__restrict__ out,
                                                     double *__restrict__ R, double ca, double cb, double dt) {
@@ -539,6 +579,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   __shared__ double sD[n * n], sl[2 * n], slh[2 * n];
   const int e = blockIdx.x;
   const int t = threadIdx.x;
+  if (FVM && g.fvflag[e]) return;  // a finite-volume element
   const double gm1 = ph.gamma - 1.0;
   const Tab *tb = g.tab;
   for (int c = t; c < n * n; c += NT) sD[c] = (FORM == 0) ? tb->Dh[c] : tb->D[c];
@@ -568,6 +609,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const int nb = g.nbr[(size_t)e * 6 + s];
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     const bool bnd = GEN && f.bnd;
+    if (bnd && f.kind == FACE_MORTAR) {
+      // non-conforming face: the outward flux from the mortar face array
+      const double *mf = g.mflux + (size_t)g.mslot[(size_t)e * 6 + s] * 5 * n2 + ab;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[(s * 5 + v) * n2 + ab] = mf[v * n2];
+      continue;
+    }
+    if (FVM && g.fvflag[nb]) {
+      // face shared with a finite-volume element: the outward flux at the face nodes
+      const double *fx = g.fvFx + ((size_t)e * 6 + s) * 5 * n2 + ab;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[(s * 5 + v) * n2 + ab] = fx[v * n2];
+      continue;
+    }
     const double *Un = U + (size_t)(bnd ? e : nb) * 5 * n3;
     const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     double Uw[5], Ux[5], gw[12], gx[12];  // w: this element's trace, x: neighbour's trace
@@ -943,7 +998,7 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
-template <int N, bool NS, int VF, int MODE, bool GEN>
+template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
 __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
@@ -976,6 +1031,20 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const int nb = g.nbr[(size_t)e * 6 + s];
     const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
     const bool bnd = GEN && f.bnd;
+    if (bnd && f.kind == FACE_MORTAR) {
+      // non-conforming face: the outward flux from the mortar face array
+      const double *mf = g.mflux + (size_t)g.mslot[(size_t)e * 6 + s] * 5 * n2 + ab;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = mf[v * n2];
+      continue;
+    }
+    if (FVM && g.fvflag[nb]) {
+      // face shared with a finite-volume element: the outward flux at the face nodes
+      const double *fx = g.fvFx + ((size_t)e * 6 + s) * 5 * n2 + ab;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sP[(s * 5 + v) * n2 + ab] = fx[v * n2];
+      continue;
+    }
     const double *Un = U + (size_t)(bnd ? e : nb) * 5 * n3;
     const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     const int qo = line_node<n>(dn, a, b, plus ? N : 0);
@@ -1228,7 +1297,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   }
 }
 
-template <int N, bool NS, int VF, int MODE, bool GEN>
+template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
 __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
@@ -1239,7 +1308,8 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
   split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  split_body<N, NS, VF, MODE, GEN>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
+  if (FVM && g.fvflag[e]) return;  // a finite-volume element
+  split_body<N, NS, VF, MODE, GEN, FVM>(g, ph, e, true, threadIdx.x, U, G, out, R, ca, cb, dt, sA, sP, sD, slh);
 }
 
 // ----------------------------------------------------------------------------- ensemble batch
@@ -1370,6 +1440,652 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_reduce(Geo g, Phys ph, int what, 
   if (t < 8) partial[(size_t)e * 8 + t] = red[t][0];
 }
 
+// ----------------------------------------------------------------------------- mortars
+// Non-conforming faces (Sec. 3.2), one workgroup per face: the big side's traces are
+// interpolated to every small side's points (I^L or I^U along each cut face direction), the
+// small side's term is evaluated there with the small element's own outward normal and written to
+// its face-array slot, and projected back to the big side (P^L, P^U; negated: outward of the big
+// element).  The element kernels read these slots for the sides their face codes mark.
+
+// value of the nv-component field X ([e][nv][n^3]) at face point (a,b) of side s of element e:
+// the face node on LGL nodes, interpolated along the face normal with l(+-1) on LG nodes
+template <int n, bool LGL>
+__device__ __forceinline__ void face_trace(const double *__restrict__ X, int nv, int e, int s, int a, int b,
+                                           const double *lm, const double *lp, double *out) {
+  constexpr int n3 = n * n * n;
+  const int dn = s >> 1;
+  const bool plus = s & 1;
+  const double *Xe = X + (size_t)e * nv * n3;
+  if (LGL) {
+    const int q = line_node<n>(dn, a, b, plus ? n - 1 : 0);
+    for (int v = 0; v < nv; ++v) out[v] = Xe[v * n3 + q];
+  } else {
+    const double *l = plus ? lp : lm;
+    for (int v = 0; v < nv; ++v) out[v] = 0.0;
+    for (int m = 0; m < n; ++m) {
+      const int q = line_node<n>(dn, a, b, m);
+      for (int v = 0; v < nv; ++v) out[v] += l[m] * Xe[v * n3 + q];
+    }
+  }
+}
+
+// lifted variables W = (u, v, w, T) at face point (a,b) of side s of element e: W of the face
+// node on LGL nodes; on LG nodes W at every node of the line, interpolated with l(+-1) (as the
+// conforming lifting does)
+template <int n, bool LGL>
+__device__ __forceinline__ void face_trace_W(const double *__restrict__ U, int e, int s, int a, int b,
+                                             const double *lm, const double *lp, double gm1, double Rg, double *W) {
+  constexpr int n3 = n * n * n;
+  const int dn = s >> 1;
+  const bool plus = s & 1;
+  const double *Ue = U + (size_t)e * 5 * n3;
+  double Uq[5];
+  if (LGL) {
+    const int q = line_node<n>(dn, a, b, plus ? n - 1 : 0);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + q];
+    grad_prim_to_W(Uq, gm1, Rg, W);
+    return;
+  }
+  const double *l = plus ? lp : lm;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) W[v] = 0.0;
+  for (int m = 0; m < n; ++m) {
+    const int q = line_node<n>(dn, a, b, m);
+    double Wq[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = Ue[v * n3 + q];
+    grad_prim_to_W(Uq, gm1, Rg, Wq);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[v] += l[m] * Wq[v];
+  }
+}
+
+// face point of the big side's sub-face that small-side point (a,b) meets (orientation code o:
+// swap if o & 4, then reverse the first index if o & 1, the second if o & 2)
+template <int n> __device__ __forceinline__ void sub_point(int o, int a, int b, int &a2, int &b2) {
+  const int p = (o & 4) ? b : a, q = (o & 4) ? a : b;
+  a2 = (o & 1) ? n - 1 - p : p;
+  b2 = (o & 2) ? n - 1 - q : q;
+}
+
+// interpolation (proj = false) or projection (proj = true) matrices of sub-face p of a mortar of
+// type t along the big side's two face directions, from sM = [IL | IU | PL | PU]; nullptr where
+// the face is not cut in that direction
+template <int n>
+__device__ __forceinline__ void sub_ops(const double *sM, int t, int p, bool proj, const double *&M1,
+                                        const double *&M2) {
+  const int p1 = t == 1 ? p : (t == 3 ? (p & 1) : -1);
+  const int p2 = t == 2 ? p : (t == 3 ? (p >> 1) : -1);
+  const double *base = sM + (proj ? 2 * n * n : 0);
+  M1 = p1 < 0 ? nullptr : base + p1 * n * n;
+  M2 = p2 < 0 ? nullptr : base + p2 * n * n;
+}
+__device__ __forceinline__ double mcoef(const double *M, int n, int r, int c) {
+  return M ? M[r * n + c] : (r == c ? 1.0 : 0.0);
+}
+
+// sum over the big side's points (m, l) of M1[r1][m] M2[r2][l] X[v][m + n l], v < nv
+template <int n>
+__device__ __forceinline__ void sub_apply(const double *M1, const double *M2, int r1, int r2, const double *X, int nv,
+                                          double *out) {
+  constexpr int n2 = n * n;
+  for (int v = 0; v < nv; ++v) out[v] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    const double c2 = mcoef(M2, n, r2, l);
+    if (c2 == 0.0) continue;
+    for (int m = 0; m < n; ++m) {
+      const double c1 = mcoef(M1, n, r1, m);
+      if (c1 == 0.0) continue;
+      for (int v = 0; v < nv; ++v) out[v] += c1 * (c2 * X[v * n2 + m + n * l]);
+    }
+  }
+}
+
+template <int N, bool LGL>
+__global__ void __launch_bounds__(256) k_mortar_lift(Geo g, Phys ph, const MortarDesc *__restrict__ md,
+                                                     const double *__restrict__ U) {
+  constexpr int n = N + 1, n2 = n * n;
+  __shared__ double sM[4 * n * n];    // IL, IU, PL, PU
+  __shared__ double sWB[4 * n2];      // W = (u, v, w, T) of the big side's trace
+  __shared__ double sT[4 * 12 * n2];  // the small sides' surface terms at their sub-face points
+  const int t = threadIdx.x, nth = blockDim.x;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += nth) {
+    sM[c] = tb->IL[c]; sM[n * n + c] = tb->IU[c]; sM[2 * n * n + c] = tb->PL[c]; sM[3 * n * n + c] = tb->PU[c];
+  }
+  const MortarDesc m = md[blockIdx.x];
+  const double gm1 = ph.gamma - 1.0;
+  for (int p = t; p < n2; p += nth) {
+    double W[4];
+    face_trace_W<n, LGL>(U, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, gm1, ph.R, W);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sWB[v * n2 + p] = W[v];
+  }
+  __syncthreads();
+  const int cnt = m.type == 3 ? 4 : 2;
+  for (int q = t; q < cnt * n2; q += nth) {
+    const int pos = q / n2, ab = q - pos * n2, a = ab % n, b = ab / n;
+    const int es = m.es[pos], ss = m.ss[pos];
+    int a2, b2;
+    sub_point<n>(m.o[pos], a, b, a2, b2);
+    const double *A1, *A2;
+    sub_ops<n>(sM, m.type, pos, false, A1, A2);
+    double WB[4], Ws[4];
+    sub_apply<n>(A1, A2, a2, b2, sWB, 4, WB);
+    face_trace_W<n, LGL>(U, es, ss, a, b, tb->lm, tb->lp, gm1, ph.R, Ws);
+    const double *fnp = g.fn + ((size_t)es * 6 + ss) * 3 * n2 + ab;
+    const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
+    double *ml = g.mlift + (size_t)m.sl[pos] * 12 * n2 + ab;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double tv = nt[d] * (0.5 * (Ws[v] + WB[v]));
+        ml[(d * 4 + v) * n2] = tv;
+        sT[(pos * 12 + d * 4 + v) * n2 + a2 + n * b2] = tv;
+      }
+  }
+  __syncthreads();
+  for (int q = t; q < n2; q += nth) {
+    const int i = q % n, j = q / n;
+    double acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+    for (int pos = 0; pos < cnt; ++pos) {
+      const double *B1, *B2;
+      sub_ops<n>(sM, m.type, pos, true, B1, B2);
+      for (int b2 = 0; b2 < n; ++b2) {
+        const double c2 = mcoef(B2, n, j, b2);
+        if (c2 == 0.0) continue;
+        for (int a2 = 0; a2 < n; ++a2) {
+          const double c = mcoef(B1, n, i, a2) * c2;
+          if (c == 0.0) continue;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) acc[k] -= c * sT[(pos * 12 + k) * n2 + a2 + n * b2];
+        }
+      }
+    }
+    double *ml = g.mlift + (size_t)m.slot * 12 * n2 + q;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ml[c * n2] = acc[c];
+  }
+}
+
+// G: the lifted gradients [K][12][n^3] (read on LG nodes); on LGL nodes the gradients at the
+// mortar sides' points come from Geo::mg, written by the lifting kernel
+template <int N, bool LGL, bool NS>
+__global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const MortarDesc *__restrict__ md,
+                                                     const double *__restrict__ U, const double *__restrict__ G) {
+  constexpr int n = N + 1, n2 = n * n;
+  __shared__ double sM[4 * n * n];
+  __shared__ double sUB[5 * n2];
+  __shared__ double sGB[NS ? 12 * n2 : 1];
+  __shared__ double sF[4 * 5 * n2];  // the small sides' fluxes at their sub-face points
+  const int t = threadIdx.x, nth = blockDim.x;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += nth) {
+    sM[c] = tb->IL[c]; sM[n * n + c] = tb->IU[c]; sM[2 * n * n + c] = tb->PL[c]; sM[3 * n * n + c] = tb->PU[c];
+  }
+  const MortarDesc m = md[blockIdx.x];
+  const double gm1 = ph.gamma - 1.0;
+  for (int p = t; p < n2; p += nth) {
+    double Uq[5];
+    face_trace<n, LGL>(U, 5, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, Uq);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sUB[v * n2 + p] = Uq[v];
+    if (NS) {
+      double gq[12];
+      if (LGL) {
+        const double *mg = g.mg + (size_t)m.slot * 12 * n2 + p;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gq[c] = mg[c * n2];
+      } else {
+        face_trace<n, false>(G, 12, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, gq);
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sGB[c * n2 + p] = gq[c];
+    }
+  }
+  __syncthreads();
+  const int cnt = m.type == 3 ? 4 : 2;
+  for (int q = t; q < cnt * n2; q += nth) {
+    const int pos = q / n2, ab = q - pos * n2, a = ab % n, b = ab / n;
+    const int es = m.es[pos], ss = m.ss[pos];
+    int a2, b2;
+    sub_point<n>(m.o[pos], a, b, a2, b2);
+    const double *A1, *A2;
+    sub_ops<n>(sM, m.type, pos, false, A1, A2);
+    // the small side is the master of its part of the face: its own normal, its state first
+    double UM[5], US[5];
+    face_trace<n, LGL>(U, 5, es, ss, a, b, tb->lm, tb->lp, UM);
+    sub_apply<n>(A1, A2, a2, b2, sUB, 5, US);
+    const double *fnp = g.fn + ((size_t)es * 6 + ss) * 3 * n2 + ab;
+    const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    double F[5];
+    riemann(ph, UM, US, nh, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] *= sh;
+    if (NS) {
+      // BR1: mean of the two sides' viscous fluxes, the big side's state and gradients interpolated
+      double gM[12], gS[12], FvM[5], FvS[5];
+      if (LGL) {
+        const double *mg = g.mg + (size_t)m.sl[pos] * 12 * n2 + ab;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gM[c] = mg[c * n2];
+      } else {
+        face_trace<n, false>(G, 12, es, ss, a, b, tb->lm, tb->lp, gM);
+      }
+      sub_apply<n>(A1, A2, a2, b2, sGB, 12, gS);
+      const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
+      flux_v(PM, gM, ph, nt, FvM);
+      flux_v(PS, gS, ph, nt, FvS);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * (FvM[v] + FvS[v]);
+    }
+    double *mf = g.mflux + (size_t)m.sl[pos] * 5 * n2 + ab;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      mf[v * n2] = F[v];
+      sF[(pos * 5 + v) * n2 + a2 + n * b2] = F[v];
+    }
+  }
+  __syncthreads();
+  for (int q = t; q < n2; q += nth) {
+    const int i = q % n, j = q / n;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int pos = 0; pos < cnt; ++pos) {
+      const double *B1, *B2;
+      sub_ops<n>(sM, m.type, pos, true, B1, B2);
+      for (int b2 = 0; b2 < n; ++b2) {
+        const double c2 = mcoef(B2, n, j, b2);
+        if (c2 == 0.0) continue;
+        for (int a2 = 0; a2 < n; ++a2) {
+          const double c = mcoef(B1, n, i, a2) * c2;
+          if (c == 0.0) continue;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v] -= c * sF[(pos * 5 + v) * n2 + a2 + n * b2];
+        }
+      }
+    }
+    double *mf = g.mflux + (size_t)m.slot * 5 * n2 + q;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) mf[v * n2] = acc[v];
+  }
+}
+
+// ----------------------------------------------------------------------------- FV subcells
+// Shock capturing with finite volumes on (N+1)^3 equal subcells of each troubled element (Sec. 4):
+// the element's U then holds subcell means; V = V_DG=>FV converts (eq. FVvdm, dg2fv).  Euler
+// equations, conforming meshes without boundary sides.
+
+__device__ __forceinline__ double fv_limit(int lim, double a, double b) {
+  if (lim == 0 || a * b <= 0.0) return 0.0;
+  if (lim == 1) return fabs(a) < fabs(b) ? a : b;  // minmod
+  return 2.0 * a * b / (a + b);                   // van Leer
+}
+__device__ __forceinline__ void fv_prim(const double *U, double gm1, double *W) {
+  const double ir = 1.0 / U[0];
+  W[0] = U[0]; W[1] = U[1] * ir; W[2] = U[2] * ir; W[3] = U[3] * ir;
+  W[4] = gm1 * (U[4] - 0.5 * U[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]));
+}
+__device__ __forceinline__ void fv_cons(const double *W, double gm1, double *U) {
+  U[0] = W[0]; U[1] = W[0] * W[1]; U[2] = W[0] * W[2]; U[3] = W[0] * W[3];
+  U[4] = W[4] / gm1 + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+// reconstructed state of finite-volume element e at its boundary subface (a,b) of side s: the
+// limited slope of the adjacent subcell from the next inner subcell and the outer datum Do
+template <int n>
+__device__ __forceinline__ void fv_recon(const double *__restrict__ U, const FvGeo &f, double gm1, int e, int s, int a,
+                                         int b, const double *Do, double *Uf) {
+  constexpr int n3 = n * n * n;
+  const int dn = s >> 1;
+  const bool plus = s & 1;
+  const double *Ue = U + (size_t)e * 5 * n3;
+  const int q0 = line_node<n>(dn, a, b, plus ? n - 1 : 0), q1 = line_node<n>(dn, a, b, plus ? n - 2 : 1);
+  double U0[5], U1[5], W0[5], W1[5], Wo[5], Wf[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { U0[v] = Ue[v * n3 + q0]; U1[v] = Ue[v * n3 + q1]; }
+  fv_prim(U0, gm1, W0);
+  fv_prim(U1, gm1, W1);
+  fv_prim(Do, gm1, Wo);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double sm = plus ? W0[v] - W1[v] : W0[v] - Wo[v];
+    const double sp = plus ? Wo[v] - W0[v] : W1[v] - W0[v];
+    const double sg = fv_limit(f.limiter, sm, sp);
+    Wf[v] = plus ? W0[v] + 0.5 * sg : W0[v] - 0.5 * sg;
+  }
+  fv_cons(Wf, gm1, Uf);
+}
+
+// One workgroup per side (6K); the master side of every face that touches a finite-volume element
+// evaluates the numerical flux at the (N+1)^2 subfaces (the DG side's trace taken to subface means
+// with V in both face directions, the FV side reconstructed), writes both sides' outward fluxes
+// (DG side: back to its face nodes with V^-1) and both sides' view of the other's face datum.
+template <int N, bool LGL, bool GEN>
+__global__ void __launch_bounds__(((N + 1) * (N + 1) + 63) / 64 * 64) k_fv_face(Geo g, Phys ph, FvGeo f,
+                                                                              const double *__restrict__ U) {
+  constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  __shared__ double sV[n * n], sVi[n * n];
+  __shared__ double sTe[5 * n2], sTn[5 * n2];  // DG traces (own / neighbour face coordinates)
+  __shared__ double sFe[5 * n2], sFn[5 * n2];  // outward subface fluxes of both sides
+  const int e = blockIdx.x / 6, s = blockIdx.x - 6 * (blockIdx.x / 6), t = threadIdx.x;
+  const NbFace f0 = nbr_face<n, GEN>(g, e, s, 0, 0);
+  if (!f0.master) return;
+  const int nb = g.nbr[(size_t)e * 6 + s], ns = GEN ? 2 * f0.dn + (f0.plus ? 1 : 0) : (s ^ 1);
+  const bool fe = f.flag[e], fn = f.flag[nb];
+  if (!fe && !fn) return;
+  for (int c = t; c < n * n; c += blockDim.x) { sV[c] = f.V[c]; sVi[c] = f.Vi[c]; }
+  const double gm1 = ph.gamma - 1.0;
+  const Tab *tb = g.tab;
+  const int a = t % n, b = t / n;
+  NbFace fm;
+  if (t < n2) {
+    fm = nbr_face<n, GEN>(g, e, s, a, b);
+    double tr[5];
+    if (!fe) {
+      face_trace<n, LGL>(U, 5, e, s, a, b, tb->lm, tb->lp, tr);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sTe[v * n2 + t] = tr[v];
+    }
+    if (!fn) {
+      face_trace<n, LGL>(U, 5, nb, ns, fm.a, fm.b, tb->lm, tb->lp, tr);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sTn[v * n2 + fm.a + n * fm.b] = tr[v];
+    }
+  }
+  __syncthreads();
+  if (t < n2) {
+    const int a2 = fm.a, b2 = fm.b;
+    double De[5], Dn[5], Ue[5], Un[5];
+    // face data: adjacent subcell (FV) or the subface mean of the trace (DG)
+    for (int side = 0; side < 2; ++side) {
+      const bool isfv = side ? fn : fe;
+      const int ee = side ? nb : e, ss = side ? ns : s, aa = side ? a2 : a, bb = side ? b2 : b;
+      double *D = side ? Dn : De;
+      const double *sT = side ? sTn : sTe;
+      if (isfv) {
+        const int q = line_node<n>(ss >> 1, aa, bb, (ss & 1) ? n - 1 : 0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) D[v] = U[((size_t)ee * 5 + v) * n3 + q];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) D[v] = 0.0;
+        for (int jb = 0; jb < n; ++jb)
+          for (int ia = 0; ia < n; ++ia) {
+            const double c = sV[aa * n + ia] * sV[bb * n + jb];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) D[v] += c * sT[v * n2 + ia + n * jb];
+          }
+      }
+    }
+    double *dxe = f.Dx + ((size_t)e * 6 + s) * 5 * n2 + t;
+    double *dxn = f.Dx + ((size_t)nb * 6 + ns) * 5 * n2 + a2 + n * b2;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { dxe[v * n2] = Dn[v]; dxn[v * n2] = De[v]; }
+    if (fe) fv_recon<n>(U, f, gm1, e, s, a, b, Dn, Ue);
+    else for (int v = 0; v < 5; ++v) Ue[v] = De[v];
+    if (fn) fv_recon<n>(U, f, gm1, nb, ns, a2, b2, De, Un);
+    else for (int v = 0; v < 5; ++v) Un[v] = Dn[v];
+    // the master's (this side's) face-mean metric, outward
+    const bool plus = s & 1;
+    const double *Nm = f.Nf + ((((size_t)e * 3 + (s >> 1)) * (n + 1) + (plus ? n : 0)) * n2 + t) * 3;
+    const double sgn = plus ? 1.0 : -1.0;
+    const double nt[3] = {sgn * Nm[0], sgn * Nm[1], sgn * Nm[2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    double F[5];
+    riemann(ph, Ue, Un, nh, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      sFe[v * n2 + t] = sh * F[v];
+      sFn[v * n2 + a2 + n * b2] = -(sh * F[v]);
+    }
+  }
+  __syncthreads();
+  if (t < n2) {
+    // thread t writes point t of either side (own face coordinates of that side)
+    for (int side = 0; side < 2; ++side) {
+      const bool isfv = side ? fn : fe;
+      const int ee = side ? nb : e, ss = side ? ns : s;
+      const double *sF = side ? sFn : sFe;
+      double *fx = f.Fx + ((size_t)ee * 6 + ss) * 5 * n2 + t;
+      if (isfv) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fx[v * n2] = sF[v * n2 + t];
+      } else {
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int jb = 0; jb < n; ++jb)
+          for (int ia = 0; ia < n; ++ia) {
+            const double c = sVi[a * n + ia] * sVi[b * n + jb];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] += c * sF[v * n2 + ia + n * jb];
+          }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fx[v * n2] = acc[v];
+      }
+    }
+  }
+}
+
+// the finite-volume elements' operator: reconstruction, inner subcell fluxes, element-face fluxes
+// from Fx, -1/(w Jbar), optional fused RK stage (MODE 1)
+template <int N, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) k_fv_volume(Geo g, Phys ph, FvGeo f, const double *__restrict__ U,
+                                                         double *__restrict__ out, double *__restrict__ R, double ca,
+                                                         double cb, double dt) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
+  __shared__ double sW[5 * n3];   // primitive subcell means
+  __shared__ double sL[5 * n3];   // reconstructed state at each subcell's +face (then its flux)
+  __shared__ double sR[5 * n3];   // reconstructed state at each subcell's -face
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (!f.flag[e]) return;
+  const bool act = t < n3;
+  const double gm1 = ph.gamma - 1.0;
+  double Uo[5];
+  if (act) {
+    double W[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uo[v] = U[((size_t)e * 5 + v) * n3 + t];
+    fv_prim(Uo, gm1, W);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sW[v * n3 + t] = W[v];
+  }
+  const int id3[3] = {t % n, (t / n) % n, t / n2};
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int dir = 0; dir < 3; ++dir) {
+    __syncthreads();
+    const int id = act ? id3[dir] : 0;
+    const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+    const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+    const int ab = a + n * b;
+    if (act) {
+      double Wl[5], Wr[5];
+      if (id > 0) {
+        for (int v = 0; v < 5; ++v) Wl[v] = sW[v * n3 + t - str];
+      } else {
+        double Do[5];
+        const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
+        for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
+        fv_prim(Do, gm1, Wl);
+      }
+      if (id < N) {
+        for (int v = 0; v < 5; ++v) Wr[v] = sW[v * n3 + t + str];
+      } else {
+        double Do[5];
+        const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+        for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
+        fv_prim(Do, gm1, Wr);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double w0 = sW[v * n3 + t];
+        const double sg = fv_limit(f.limiter, w0 - Wl[v], Wr[v] - w0);
+        sL[v * n3 + t] = w0 + 0.5 * sg;
+        sR[v * n3 + t] = w0 - 0.5 * sg;
+      }
+    }
+    __syncthreads();
+    double Fp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act && id < N) {
+      // inner face id + 1/2 between this subcell and the next along dir
+      double WL[5], WR[5], UL[5], UR[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { WL[v] = sL[v * n3 + t]; WR[v] = sR[v * n3 + t + str]; }
+      fv_cons(WL, gm1, UL);
+      fv_cons(WR, gm1, UR);
+      const double *Nm = f.Nf + ((((size_t)e * 3 + dir) * (n + 1) + id + 1) * n2 + ab) * 3;
+      const double sh = sqrt(Nm[0] * Nm[0] + Nm[1] * Nm[1] + Nm[2] * Nm[2]);
+      const double ish = 1.0 / sh;
+      const double nh[3] = {Nm[0] * ish, Nm[1] * ish, Nm[2] * ish};
+      double F[5];
+      riemann(ph, UL, UR, nh, F);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fp[v] = sh * F[v];
+    }
+    __syncthreads();  // sL is reused for the fluxes
+    if (act && id < N) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sL[v * n3 + t] = Fp[v];
+    }
+    __syncthreads();
+    if (act) {
+      const double *fx0 = f.Fx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
+      const double *fx1 = f.Fx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        // outward fluxes of the subcell: + face, then - face
+        acc[v] += (id < N) ? Fp[v] : fx1[v * n2];
+        acc[v] += (id > 0) ? -sL[v * n3 + t - str] : fx0[v * n2];
+      }
+    }
+  }
+  if (act) {
+    const double iwj = 1.0 / (f.w * f.Jbar[(size_t)e * n3 + t]);
+    double *Oe = out + (size_t)e * 5 * n3;
+    if (MODE == 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Oe[v * n3 + t] = -acc[v] * iwj;
+    } else {
+      double *Re = R + (size_t)e * 5 * n3;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * (-acc[v] * iwj);
+        Re[v * n3 + t] = r;
+        Oe[v * n3 + t] = Uo[v] + cb * r;
+      }
+    }
+  }
+}
+
+// apply the n x n matrix A along all three directions to the 5 fields of sX (in place through sY)
+template <int n>
+__device__ __forceinline__ void fv_tensor3(const double *A, double *sX, double *sY, int t, bool act) {
+  constexpr int n2 = n * n, n3 = n2 * n;
+  const int i = t % n, j = (t / n) % n, k = t / n2;
+  for (int dir = 0; dir < 3; ++dir) {
+    double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act) {
+      const int id = dir == 0 ? i : (dir == 1 ? j : k);
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      for (int m = 0; m < n; ++m) {
+        const double c = A[id * n + m];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) r[v] += c * sX[v * n3 + base + m * str];
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sY[v * n3 + t] = r[v];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sX[v * n3 + t] = sY[v * n3 + t];
+    }
+    __syncthreads();
+  }
+}
+
+// troubled-cell indicator (modal decay of rho p) and, with do_switch, the switch with hysteresis in
+// place (U <- V U to finite volume above hi, U <- V^-1 U back to DG below lo)
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f, double *__restrict__ U,
+                                                         int do_switch) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n3 = S::n3;
+  __shared__ double sX[5 * n3], sY[5 * n3], sU[5 * n3];
+  __shared__ double sA[3 * n * n];  // V, Vi, Li
+  __shared__ double sE[n];
+  __shared__ int sNew;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const bool act = t < n3;
+  for (int c = t; c < n * n; c += blockDim.x) { sA[c] = f.V[c]; sA[n * n + c] = f.Vi[c]; sA[2 * n * n + c] = f.Li[c]; }
+  const bool isfv = f.flag[e];
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double u = U[((size_t)e * 5 + v) * n3 + t];
+      sU[v * n3 + t] = u;
+      sX[v * n3 + t] = u;
+    }
+  }
+  __syncthreads();
+  if (isfv) fv_tensor3<n>(sA + n * n, sX, sY, t, act);  // nodal values of the element's DG reading
+  if (act) {
+    double W[5], Uq[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uq[v] = sX[v * n3 + t];
+    fv_prim(Uq, ph.gamma - 1.0, W);
+    sX[t] = W[0] * W[4];  // q = rho p in field 0
+  }
+  __syncthreads();
+  fv_tensor3<n>(sA + 2 * n * n, sX, sY, t, act);  // modal coefficients (field 0)
+  if (t < n) {
+    // energy of the modes whose largest index is t, summed in node order
+    double s = 0.0;
+    for (int q = 0; q < n3; ++q) {
+      const int i = q % n, j = (q / n) % n, k = q / (n * n);
+      const int m = i > j ? (i > k ? i : k) : (j > k ? j : k);
+      if (m == t) s += sX[q] * sX[q];
+    }
+    sE[t] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int m = 0; m < n; ++m) tot += sE[m];
+    const double r1 = sE[N] / fmax(tot, 1e-300);
+    const double r2 = sE[N - 1] / fmax(tot - sE[N], 1e-300);
+    const double ind = log10(fmax(fmax(r1, r2), 1e-300));
+    f.ind[e] = ind;
+    int nw = isfv ? 1 : 0;
+    if (do_switch) {
+      if (!isfv && ind > f.hi) nw = 1;
+      if (isfv && ind < f.lo) nw = 0;
+    }
+    sNew = nw;
+  }
+  __syncthreads();
+  const int nw = sNew;
+  if (nw == (isfv ? 1 : 0)) return;  // uniform across the workgroup
+  fv_tensor3<n>(nw ? sA : sA + n * n, sU, sY, t, act);
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) U[((size_t)e * 5 + v) * n3 + t] = sU[v * n3 + t];
+  }
+  if (t == 0) f.flag[e] = (uint8_t)nw;
+}
+
 // ----------------------------------------------------------------------------- launchers
 #define DG_CHECK_LAUNCH()                                   \
   do {                                                      \
@@ -1382,6 +2098,16 @@ static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const do
                          double a, double b, double dt, int mode, hipStream_t st) {
   dim3 grid(g.K), block(Sz<N>::NT);
   const bool gen = g.fc != nullptr;
+  if constexpr (!NS) {
+    if (g.fvflag) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+      else
+        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+      DG_CHECK_LAUNCH();
+      return DG_OK;
+    }
+  }
   if (mode == 0 && !gen)
     hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   else if (mode == 0)
@@ -1399,6 +2125,16 @@ static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const d
                           double a, double b, double dt, int mode, hipStream_t st) {
   dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
   const bool gen = g.fc != nullptr;
+  if constexpr (!NS) {
+    if (g.fvflag) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_split<N, NS, VF, 0, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+      else
+        hipLaunchKernelGGL((k_split<N, NS, VF, 1, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+      DG_CHECK_LAUNCH();
+      return DG_OK;
+    }
+  }
   if (mode == 0 && !gen)
     hipLaunchKernelGGL((k_split<N, NS, VF, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
   else if (mode == 0)
@@ -1511,6 +2247,58 @@ int launch_batch_split(const BatchView &bv, bool ns, int vf, int epb, hipStream_
 }
 
 template <int N>
+int launch_fv_face(const Geo &g, const Phys &ph, const FvGeo &f, bool lgl, const double *U, hipStream_t st) {
+  constexpr int nt = ((N + 1) * (N + 1) + 63) / 64 * 64;
+  const dim3 grid(6 * g.K), block(nt);
+  const bool gen = g.fc != nullptr;
+  if (lgl && gen) hipLaunchKernelGGL((k_fv_face<N, true, true>), grid, block, 0, st, g, ph, f, U);
+  else if (lgl) hipLaunchKernelGGL((k_fv_face<N, true, false>), grid, block, 0, st, g, ph, f, U);
+  else if (gen) hipLaunchKernelGGL((k_fv_face<N, false, true>), grid, block, 0, st, g, ph, f, U);
+  else hipLaunchKernelGGL((k_fv_face<N, false, false>), grid, block, 0, st, g, ph, f, U);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_fv_volume(const Geo &g, const Phys &ph, const FvGeo &f, const double *U, double *out, double *R, double a,
+                     double b, double dt, int mode, hipStream_t st) {
+  if (mode == 0) hipLaunchKernelGGL((k_fv_volume<N, 0>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, f, U, out, R, a, b, dt);
+  else hipLaunchKernelGGL((k_fv_volume<N, 1>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, f, U, out, R, a, b, dt);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_fv_switch(const Geo &g, const Phys &ph, const FvGeo &f, double *U, int do_switch, hipStream_t st) {
+  hipLaunchKernelGGL((k_fv_switch<N>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, f, U, do_switch);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_mortar_lift(const Geo &g, const Phys &ph, bool lgl, const MortarDesc *md, int nm, const double *U,
+                       hipStream_t st) {
+  if (nm <= 0) return DG_OK;
+  if (lgl) hipLaunchKernelGGL((k_mortar_lift<N, true>), dim3(nm), dim3(256), 0, st, g, ph, md, U);
+  else hipLaunchKernelGGL((k_mortar_lift<N, false>), dim3(nm), dim3(256), 0, st, g, ph, md, U);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_mortar_flux(const Geo &g, const Phys &ph, bool lgl, int eqn, const MortarDesc *md, int nm,
+                       const double *U, const double *G, hipStream_t st) {
+  if (nm <= 0) return DG_OK;
+  const bool ns = eqn == DG_NAVIER_STOKES;
+  if (lgl && ns) hipLaunchKernelGGL((k_mortar_flux<N, true, true>), dim3(nm), dim3(256), 0, st, g, ph, md, U, G);
+  else if (lgl) hipLaunchKernelGGL((k_mortar_flux<N, true, false>), dim3(nm), dim3(256), 0, st, g, ph, md, U, G);
+  else if (ns) hipLaunchKernelGGL((k_mortar_flux<N, false, true>), dim3(nm), dim3(256), 0, st, g, ph, md, U, G);
+  else hipLaunchKernelGGL((k_mortar_flux<N, false, false>), dim3(nm), dim3(256), 0, st, g, ph, md, U, G);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
 int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, double, double *partial, hipStream_t st) {
   hipLaunchKernelGGL((k_reduce<N>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, what, U, partial);
   DG_CHECK_LAUNCH();
@@ -1602,6 +2390,14 @@ template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, int, const 
 template int launch_main<DG_ONLY_N>(const Geo &, const Phys &, bool, int, int, const double *, const double *,
                                     double *, double *, double, double, double, int, hipStream_t);
 template int launch_reduce<DG_ONLY_N>(const Geo &, const Phys &, int, const double *, double, double *, hipStream_t);
+template int launch_mortar_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, const MortarDesc *, int, const double *,
+                                           hipStream_t);
+template int launch_fv_face<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &, bool, const double *, hipStream_t);
+template int launch_fv_volume<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &, const double *, double *, double *,
+                                         double, double, double, int, hipStream_t);
+template int launch_fv_switch<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &, double *, int, hipStream_t);
+template int launch_mortar_flux<DG_ONLY_N>(const Geo &, const Phys &, bool, int, const MortarDesc *, int,
+                                           const double *, const double *, hipStream_t);
 template int launch_batch_lift<DG_ONLY_N>(const BatchView &, int, hipStream_t);
 template int launch_batch_split<DG_ONLY_N>(const BatchView &, bool, int, int, hipStream_t);
 #endif

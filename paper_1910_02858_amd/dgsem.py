@@ -30,7 +30,7 @@ EXPORTS = [
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
     "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
-    "dg_integrals_noalloc",
+    "dg_integrals_noalloc", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
 ]
 
 
@@ -43,7 +43,7 @@ class DGError(RuntimeError):
 class _Mesh(ctypes.Structure):
     _fields_ = [("n_elems", ctypes.c_int32), ("n_geo", ctypes.c_int32), ("xgeo", ctypes.POINTER(ctypes.c_double)),
                 ("nbr_elem", ctypes.POINTER(ctypes.c_int32)), ("nbr_side", ctypes.POINTER(ctypes.c_int8)),
-                ("flip", ctypes.POINTER(ctypes.c_int8))]
+                ("flip", ctypes.POINTER(ctypes.c_int8)), ("mortar", ctypes.POINTER(ctypes.c_int8))]
 
 
 class _Scheme(ctypes.Structure):
@@ -89,6 +89,12 @@ def lib():
         L.dg_timestep.argtypes = [_VP, _VP, ctypes.c_double, ctypes.c_double, _D]
         L.dg_integrals.argtypes = [_VP, _VP, _D]
         L.dg_integrals_noalloc.argtypes = [_VP, _VP, _VP]
+        _U8 = ctypes.POINTER(ctypes.c_uint8)
+        L.dg_fv_enable.argtypes = [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.dg_fv_set_types.argtypes = [_VP, _U8]
+        L.dg_fv_types.argtypes = [_VP, _U8]
+        L.dg_fv_indicator.argtypes = [_VP, _VP, _D]
+        L.dg_fv_switch.argtypes = [_VP, _VP]
         L.dg_check_finite.argtypes = [_VP, _VP]
         L.dg_node_coords.argtypes = [_VP, _D]
         L.dg_mass_weights.argtypes = [_VP, _VP]
@@ -171,18 +177,23 @@ def _geo_degree(xgeo, N, ngeo):
     return ng
 
 
-def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None, ngeo=None):
+def _i8(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None, ngeo=None, mortar=None):
     """dg_init's geometry and 1D tables computed on the host only (no device needed).
-    ``xgeo[K,3,(ngeo+1)^3]``: the mapping at the LGL nodes of degree ``ngeo`` (default N)."""
+    ``xgeo[K,3,(ngeo+1)^3]``: the mapping at the LGL nodes of degree ``ngeo`` (default N);
+    ``mortar[K,6]``: non-conforming faces in the conventions of ``dg_mesh.mortar``."""
     xgeo = np.ascontiguousarray(xgeo, np.float64)
     nbr = np.ascontiguousarray(nbr, np.int32)
     nside = np.ascontiguousarray(nside, np.int8)
     flip = None if flip is None else np.ascontiguousarray(flip, np.int8)
+    mortar = None if mortar is None else np.ascontiguousarray(mortar, np.int8)
     K, n = xgeo.shape[0], N + 1
     ng = _geo_degree(xgeo, N, ngeo)
     m = _Mesh(K, ng, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-              nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
-              None if flip is None else flip.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+              nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _i8(flip), _i8(mortar))
     Ja, J, fn = np.zeros((K, 9, n ** 3)), np.zeros((K, n ** 3)), np.zeros((K, 6, 3, n * n))
     D, Dh = np.zeros((n, n)), np.zeros((n, n))
     rc = lib().dg_host_geometry(ctypes.byref(m), N, NODES[node_type], _ptr(Ja), _ptr(J), _ptr(fn), _ptr(D), _ptr(Dh))
@@ -202,7 +213,8 @@ class DGSolver:
     """One mesh + scheme on the GPU (a ``dg_handle``)."""
 
     def __init__(self, xgeo, nbr, nside, N: int, nodes_: str, eqn="ns", form="split", volflux="kep",
-                 riemann="roe", gamma=1.4, R=1.0, mu=0.0, Pr=0.72, flip=None, stream=None, ngeo=None):
+                 riemann="roe", gamma=1.4, R=1.0, mu=0.0, Pr=0.72, flip=None, stream=None, ngeo=None,
+                 mortar=None):
         import torch
         self.torch = torch
         xgeo = np.ascontiguousarray(xgeo, np.float64)
@@ -213,9 +225,9 @@ class DGSolver:
         if xgeo.shape != (K, 3, (ng + 1) ** 3) or nbr.shape != (K, 6) or nside.shape != (K, 6):
             raise ValueError("mesh arrays have inconsistent shapes")
         flip_arr = None if flip is None else np.ascontiguousarray(flip, np.int8)
+        mort_arr = None if mortar is None else np.ascontiguousarray(mortar, np.int8)
         m = _Mesh(K, ng, _ptr(xgeo), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                  nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
-                  None if flip_arr is None else flip_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+                  nside.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _i8(flip_arr), _i8(mort_arr))
         sc = _Scheme(EQN[eqn], FORM[form], VF[volflux], RS[riemann], gamma, R, mu, Pr)
         st = stream if stream is not None else torch.cuda.current_stream()
         h = _VP()
@@ -341,6 +353,32 @@ class DGSolver:
         if out.dtype != self.torch.float64 or out.numel() < 8 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 device tensor of at least 8 entries")
         self._check(lib().dg_integrals_noalloc(self.h, _VP(_dptr(U)), _VP(_dptr(out))), "dg_integrals_noalloc")
+
+    # ---- hybrid DG / finite-volume subcells (Sec. 4), Euler equations
+    def fv_enable(self, limiter: int = 1, lo: float = -4.0, hi: float = -3.0):
+        self._check(lib().dg_fv_enable(self.h, int(limiter), float(lo), float(hi)), "dg_fv_enable")
+
+    def fv_set_types(self, types):
+        t = np.ascontiguousarray(types, np.uint8)
+        self._sync_stream()
+        self._check(lib().dg_fv_set_types(self.h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), "dg_fv_set_types")
+
+    def fv_types(self):
+        t = np.zeros(self.K, np.uint8)
+        self._sync_stream()
+        self._check(lib().dg_fv_types(self.h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), "dg_fv_types")
+        return t
+
+    def fv_indicator(self, U):
+        ind = np.zeros(self.K)
+        self._sync_stream()
+        self._check(lib().dg_fv_indicator(self.h, _VP(_dptr(U)), _ptr(ind)), "dg_fv_indicator")
+        return ind
+
+    def fv_switch(self, U):
+        """Indicator and switching with hysteresis, in place on the device tensor U."""
+        self._sync_stream()
+        self._check(lib().dg_fv_switch(self.h, _VP(_dptr(U))), "dg_fv_switch")
 
     def check_finite(self, U) -> bool:
         self._sync_stream()

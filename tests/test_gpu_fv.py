@@ -1,0 +1,156 @@
+"""Hybrid DG / finite-volume subcells (Sec. 4) on the GPU against the oracle, Euler equations.
+
+Curved periodic lattices (and one with rotated element axes) with a seeded mix of DG and FV
+elements, the FV elements' U holding subcell means: one operator evaluation (1e-12) for every
+form, node type and limiter; 10 RK steps with the types held (1e-10); the indicator and the
+switch with hysteresis against the oracle's; RK steps with switching before every step on a
+periodic shock-tube state (types equal, state 1e-10).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1910_02858_amd import inputs
+from gpu_common import check_rhs, rel_err, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    from paper_1910_02858_amd import dgsem
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+def fv_problem(orc, wl, k=3, rot_seed=None, frac=0.5, seed=21):
+    lgl = orc.basis(wl.N, "lgl")["x"]
+    X = inputs.warp_sine(inputs.lattice_points(lgl, k, k, k))
+    nbr, side, flip = inputs.periodic_lattice(k, k, k)
+    if rot_seed is not None:
+        rot = np.random.default_rng(rot_seed).integers(0, 24, k ** 3)
+        X, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, wl.N, rot)
+    M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes, flip=flip)
+    U0 = inputs.random_perturbation(inputs.taylor_green(M.points(), 1.0, 0.3), seed, 1e-2)
+    fv = (np.random.default_rng(seed + 1).random(M.K) < frac).astype(np.uint8)
+    return M, (X, nbr, side, flip), U0, fv
+
+
+def fv_solver(dg, wl, mesh, fv, limiter):
+    X, nbr, side, flip = mesh
+    S = dg.DGSolver.from_workload(wl, X, nbr, side, flip=flip)
+    S.fv_enable(limiter, -5.0, -2.5)
+    S.fv_set_types(fv)
+    return S
+
+
+CASES = [
+    ("euler_weak_lg3_llf_minmod", inputs.workload(1, N=3), 1, None, 0.5),
+    ("euler_split_ec_roe_lgl4_vanleer", inputs.workload(3, eqn="euler", N=4), 2, None, 0.5),
+    ("euler_strong_lgl3_roe_first_order", inputs.workload(2, eqn="euler", form="strong", volflux="central", N=3), 0,
+     None, 0.5),
+    ("euler_split_kep_volflux_roe_lgl5_rotated", inputs.workload(2, eqn="euler", riemann="volflux_roe", N=5), 1, 31,
+     0.5),
+    ("euler_weak_lgl2_llf_all_fv", inputs.workload(1, nodes="lgl", N=2), 1, None, 1.0),
+    ("euler_split_ec_roe_lgl7_minmod", inputs.workload(3, eqn="euler"), 1, None, 0.3),
+]
+
+
+@pytest.mark.parametrize("name,wl,lim,rot,frac", CASES, ids=[c[0] for c in CASES])
+def test_fv_rhs_parity(dg, orc, name, wl, lim, rot, frac):
+    print(f"case {name}", flush=True)
+    M, mesh, U0, fv = fv_problem(orc, wl, k=3 if wl.N < 7 else 2, rot_seed=rot, frac=frac)
+    S = fv_solver(dg, wl, mesh, fv, lim)
+    ref = M.fv_rhs(orc.Scheme.of(wl), fv, U0, lim)
+    got = S.rhs(to_gpu(U0)).cpu().numpy()
+    ne, per = check_rhs(got, ref)
+    print(f"normwise {ne:.2e} per-variable {per}")
+    assert np.array_equal(S.fv_types(), fv)
+
+
+def test_fv_rk_parity_fixed_types(dg, orc):
+    wl = inputs.workload(3, eqn="euler", N=4)
+    M, mesh, U0, fv = fv_problem(orc, wl)
+    sc = orc.Scheme.of(wl)
+    dt = M.timestep(sc, U0, 0.5, 0.5)
+    _, ref = M.fv_rk(sc, fv, U0, 10, dt, limiter=1)
+    S = fv_solver(dg, wl, mesh, fv, 1)
+    got = S.steps(to_gpu(U0), 10, dt).cpu().numpy()
+    err = rel_err(got, ref)
+    print(f"per-variable after 10 steps {err}")
+    assert np.all(err <= 1e-10), err
+
+
+def shock_tube(M, gamma=1.4):
+    """Periodic shock tube along x: a high-pressure, high-density slab between x = 2 and 4."""
+    x = M.points()
+    inside = (x[:, 0] > 2.0) & (x[:, 0] < 4.0)
+    rho = np.where(inside, 1.0, 0.3)
+    p = np.where(inside, 1.0, 0.2)
+    zero = 0 * rho
+    return inputs.prim_to_cons(rho, zero + 0.1, zero, zero, p, gamma)
+
+
+def test_fv_indicator_and_switch_parity(dg, orc):
+    wl = inputs.workload(1, nodes="lgl", N=4)
+    M, mesh, _, _ = fv_problem(orc, wl, k=4)
+    U0 = shock_tube(M)
+    fv0 = np.zeros(M.K, np.uint8)
+    S = fv_solver(dg, wl, mesh, fv0, 1)
+    ind_ref = M.fv_indicator(fv0, U0)
+    ind = S.fv_indicator(to_gpu(U0))
+    np.testing.assert_allclose(ind, ind_ref, atol=1e-9)
+    fv_ref, U_ref = M.fv_switch(fv0, U0, -5.0, -2.5)
+    assert 0 < fv_ref.sum() < M.K
+    Ug = to_gpu(U0)
+    S.fv_switch(Ug)
+    assert np.array_equal(S.fv_types(), fv_ref)
+    assert np.all(rel_err(Ug.cpu().numpy(), U_ref) <= 1e-13)
+
+
+def test_fv_rk_with_switching_parity(dg, orc):
+    """10 RK steps of the periodic shock tube, the indicator switching before every step (the
+    oracle's and the library's types compared after the run, the state to 1e-10)."""
+    wl = inputs.workload(1, nodes="lgl", N=4)
+    M, mesh, _, _ = fv_problem(orc, wl, k=4)
+    U0 = shock_tube(M)
+    sc = orc.Scheme.of(wl)
+    dt = M.timestep(sc, U0, 0.5, 0.5)
+    fv0 = np.zeros(M.K, np.uint8)
+    fv_ref, U_ref = M.fv_rk(sc, fv0, U0, 10, dt, limiter=1, lo=-5.0, hi=-2.5)
+    S = fv_solver(dg, wl, mesh, fv0, 1)
+    U = to_gpu(U0)
+    for _ in range(10):
+        S.fv_switch(U)
+        U = S.steps(U, 1, dt)
+    got = U.cpu().numpy()
+    print(f"FV elements at the end: {int(fv_ref.sum())} of {M.K}")
+    assert np.array_equal(S.fv_types(), fv_ref)
+    err = rel_err(got, U_ref)
+    print(f"per-variable after 10 steps {err}")
+    assert np.all(err <= 1e-10), err
+
+
+def test_fv_unsupported(dg, orc):
+    import torch
+    wl = inputs.workload(2, N=3, K1=2)
+    lgl = orc.basis(3, "lgl")["x"]
+    X = inputs.lattice_points(lgl, 2, 2, 2)
+    nbr, side, _ = inputs.periodic_lattice(2, 2, 2)
+    S = dg.DGSolver.from_workload(wl, X, nbr, side)
+    with pytest.raises(dg.DGError) as ei:
+        S.fv_enable(1, -5, -2.5)  # Navier-Stokes
+    assert ei.value.code == -3
+    wl_e = inputs.workload(3, eqn="euler", N=3, K1=2)
+    S2 = dg.DGSolver.from_workload(wl_e, X, nbr, side)
+    S2.fv_enable(1, -5, -2.5)
+    U = torch.from_numpy(inputs.constant_state(S2.K, S2.n3)).cuda()
+    with pytest.raises(dg.DGError) as ei:
+        S2.rhs_vjp(U, torch.ones_like(U))
+    assert ei.value.code == -3
+    with pytest.raises(dg.DGError) as ei:
+        S2.fv_enable(3, -5, -2.5)
+    assert ei.value.code == -1
