@@ -31,6 +31,16 @@ METRIC = "DOF-updates/s (PID s/DOF/stage) at N=7 TGV; adjoint/forward cost ratio
 HBM_PEAK_GBS = 8000.0
 BYTES_MAIN = 42 * 8   # U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
 BYTES_LIFT = 27 * 8   # U 5 + Ja 9 + 1/J 1 read, grad W 12 written
+# reverse stage: k_vjp_main reads U 5, the kept viscous fluxes' momentum part 9, Ja 9, 1/J 1,
+# Ubar_t 5, Ubar 5 and writes Ubar 5; k_vjp_face reads Ubar 5, Rbar 5 and writes Rbar 5
+BYTES_VJP_MAIN = 39 * 8
+BYTES_VJP_FACE = 15 * 8
+
+
+def bytes_fv(n: int) -> float:
+    """Algorithmic bytes per subcell of the finite-volume kernel: U 5, R 5, Jbar 1 and the face-mean
+    metrics of the three directions (9 (n+1)/n) read, U_new 5 and R 5 written."""
+    return 8.0 * (5 + 5 + 1 + 9.0 * (n + 1) / n + 5 + 5)
 
 
 # HBM traffic of the split kernel from committed counter summaries: FETCH_SIZE and WRITE_SIZE
@@ -128,13 +138,15 @@ def cpu_pid_one_thread():
         return None
 
 
-def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2, general: bool = False):
+def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2, general: bool = False, k1=None, steps=None):
     """Wall time of the gradient (checkpoint recomputation + reverse stages) over the wall time
     of the forward rollout that stores the checkpoints: 12^3 curved hexes, N=5, split KEP + Roe +
     BR1, Taylor-Green vortex, 50 RK steps, checkpoint every 10 steps, objective = kinetic energy.
     With ``general`` the mesh is the vortex's symmetry octant with six symmetry planes and
     rotated element axes."""
-    wl = inputs.workload(5)
+    wl = inputs.workload(5) if k1 is None else inputs.workload(5, K1=k1)
+    if steps is not None:
+        wl.steps = steps
     S, U0 = (dgsem.build_solver(wl, rotate_seed=0, symmetry_box=True) if general else dgsem.build_solver(wl))
     dt = S.timestep(U0, wl.cfl, wl.dfl)
     wJ = S.mass_weights()
@@ -152,7 +164,8 @@ def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2, general: bool = False)
         t2 = time.perf_counter()
         best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
     return {"value": best_b / best_f, "forward_ms": best_f * 1e3, "backward_ms": best_b * 1e3,
-            "workload": wl.name + ("_octant_symmetry_planes_rotated_elements" if general else ""),
+            "workload": (wl.name.replace("_k12", f"_k{wl.K1}") +
+                         ("_octant_symmetry_planes_rotated_elements" if general else "")),
             "dof": S.K * S.n3, "steps": wl.steps, "checkpoint_every": 10}
 
 
@@ -247,6 +260,158 @@ def general_mesh_bench(dgsem, inputs, torch, wl, steps: int, structured_value: f
             "vs_structured": value / structured_value, "setup_s": setup_s}
 
 
+def _timed_steps(S, U, torch, dgsem, dt, steps, between=None):
+    """Wall time of ``steps`` RK steps after one warm-up step, then per-kernel times of 5 profiled
+    stages; ``between(U)`` runs before every step (e.g. the FV switch).  Returns (wall, prof, U)."""
+    a, b, _ = dgsem.rk_coefficients()
+    R = torch.zeros_like(U)
+    cur, nxt = U, S.empty()
+    for st in range(steps + 1):
+        if st == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        if between is not None:
+            between(cur)
+        for s_ in range(5):
+            S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+            cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if not S.check_finite(cur):
+        raise RuntimeError("non-finite state")
+    S.profile(True)
+    for s_ in range(5):
+        S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+        cur, nxt = nxt, cur
+    prof = S.profile_read()
+    S.profile(False)
+    return wall, prof, cur
+
+
+def _per_launch(prof, key):
+    n = prof[key + "_launches"]
+    return prof[key + "_ms"] / n if n else None
+
+
+def mortar_bench(dgsem, inputs, torch, steps: int, structured_value: float, k: int = 16):
+    """Non-conforming faces (Sec. 3.2): the headline scheme (N=7, split EC + Roe + BR1, TGV) on a
+    periodic k^3 lattice whose half x < pi is refined 2x2x2, so the two planes between refined and
+    whole cells carry type-3 mortars (4 small sides per big side).  DOF updates per second of
+    whole RK steps and the per-kernel times (the mortar flux kernel is the face entry)."""
+    wl = inputs.workload(3)
+    lgl, _ = dgsem.nodes(wl.N, "lgl")
+    t0 = time.perf_counter()
+    X = inputs.refined_lattice(lgl, k, (2, 2, 2))
+    nbr, side, flip, mort = inputs.connect_boxes(X, wl.N + 1)
+    S = dgsem.DGSolver.from_workload(wl, X, nbr, side, flip=flip, mortar=mort)
+    setup_s = time.perf_counter() - t0
+    del X
+    U = torch.from_numpy(inputs.initial_state(wl, S.node_coords())).cuda()
+    dt = S.timestep(U, wl.cfl, wl.dfl)
+    wall, prof, _ = _timed_steps(S, U, torch, dgsem, dt, steps)
+    dof = S.K * S.n3
+    value = dof * 5 * steps / wall
+    return {"workload": f"ns_tgv_ec_roe_lgl7_k{k}_half_refined_2x2x2", "elements": S.K,
+            "mortars": int(((mort >= 1) & (mort <= 3)).sum()), "dof": dof, "value": value, "unit": "DOF-updates/s",
+            "steps": steps, "ms_per_stage": wall * 1e3 / (5 * steps),
+            "kernels_ms": {"main": _per_launch(prof, "main"), "lift": _per_launch(prof, "lift"),
+                           "mortar_flux": _per_launch(prof, "face")},
+            "vs_structured": value / structured_value, "setup_s": setup_s}
+
+
+def fv_bench(dgsem, inputs, torch, steps: int, k: int = 32):
+    """Finite-volume subcells (Sec. 4), Euler equations, N=7, split EC volume flux + Roe, on a
+    periodic k^3 lattice: the pure DG step; the hybrid step on a periodic shock tube (a dense slab
+    2 < x < 4) with the indicator's switch before every step; and every element finite-volume
+    (the FV kernel's roofline, algorithmic bytes per subcell from bytes_fv)."""
+    import numpy as np
+    wl = inputs.workload(3, eqn="euler", K1=k)
+    S, _ = dgsem.build_solver(wl)
+    x = S.node_coords()
+    inside = (x[:, 0] > 2.0) & (x[:, 0] < 4.0)
+    rho = np.where(inside, 1.0, 0.3)
+    p = np.where(inside, 1.0, 0.2)
+    U0 = torch.from_numpy(np.ascontiguousarray(inputs.prim_to_cons(rho, 0 * rho + 0.1, 0 * rho, 0 * rho, p, 1.4))).cuda()
+    del x, inside, rho, p
+    dt = S.timestep(U0, 0.5, 0.5)
+    dof = S.K * S.n3
+    out = {"workload": f"euler_shock_tube_ec_roe_lgl7_k{k}", "elements": S.K, "dof": dof, "steps": steps}
+    wall, prof, _ = _timed_steps(S, U0.clone(), torch, dgsem, dt, steps)
+    out["dg"] = {"value": dof * 5 * steps / wall, "ms_per_stage": wall * 1e3 / (5 * steps)}
+    t0 = time.perf_counter()
+    S.fv_enable(1, -5.0, -2.5)
+    out["fv_setup_s"] = time.perf_counter() - t0
+    U = U0.clone()
+    wall, prof, U = _timed_steps(S, U, torch, dgsem, dt, steps, between=S.fv_switch)
+    fvn = int(S.fv_types().sum())
+    out["hybrid"] = {"value": dof * 5 * steps / wall, "ms_per_stage": wall * 1e3 / (5 * steps),
+                     "fv_elements": fvn, "fv_fraction": fvn / S.K,
+                     "kernels_ms": {"dg": _per_launch(prof, "main"), "faces": _per_launch(prof, "face"),
+                                    "fv": _per_launch(prof, "fv")}}
+    S.fv_set_types(np.ones(S.K, np.uint8))  # the slab's nodal values read as subcell means
+    wall, prof, _ = _timed_steps(S, U0.clone(), torch, dgsem, dt, steps)
+    fv_ms = _per_launch(prof, "fv")
+    fv_gbs = bytes_fv(wl.N + 1) * dof / (fv_ms * 1e-3) / 1e9
+    out["all_fv"] = {"value": dof * 5 * steps / wall, "ms_per_stage": wall * 1e3 / (5 * steps),
+                     "kernels_ms": {"dg": _per_launch(prof, "main"), "faces": _per_launch(prof, "face"),
+                                    "fv": fv_ms},
+                     "roofline": {"bound": "hbm", "kernel": "k_fv_volume", "achieved": fv_gbs, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": fv_gbs / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_dof": bytes_fv(wl.N + 1)}}
+    out["hybrid_vs_dg"] = out["hybrid"]["value"] / out["dg"]["value"]
+    return out
+
+
+def adjoint_roofline(dgsem, inputs, torch, k: int = 32, repeats: int = 3):
+    """The reverse sweep at an HBM-resident size: 32^3 curved hexes, N=5, split KEP + Roe + BR1
+    (7.1 M nodes, 283 MB per state, beyond the 256 MB last-level cache).  One forward step keeps
+    its stage inputs and lifting outputs; its reverse (five k_vjp_main + k_vjp_face pairs and one
+    register update) is applied ``repeats`` times (the adjoint of one step applied again: linear,
+    no reset needed) and timed with events on the library's stream, beside the same forward
+    stages, and priced at BYTES_VJP_MAIN + BYTES_VJP_FACE per node and stage."""
+    wl = inputs.workload(5, K1=k)
+    S, U0 = dgsem.build_solver(wl)
+    dt = S.timestep(U0, wl.cfl, wl.dfl)
+    a, b, _ = dgsem.rk_coefficients()
+    stage_U = [U0] + [S.empty() for _ in range(4)]
+    stage_G = [S.empty_grad() for _ in range(5)]
+    R = torch.zeros_like(U0)
+    out_U = S.empty()
+    st = torch.cuda.current_stream()
+
+    def forward():
+        for s_ in range(5):
+            S.rk_stage_keep(stage_U[s_], stage_U[s_ + 1] if s_ < 4 else out_U, R, a[s_], b[s_], dt, stage_G[s_])
+
+    forward()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(repeats):
+        forward()
+    e1.record(st)
+    torch.cuda.synchronize()
+    fwd_stage_ms = e0.elapsed_time(e1) / (5 * repeats)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    Ub = torch.randn(U0.shape, generator=g, dtype=torch.float64).cuda()
+    Rb = torch.zeros_like(U0)
+    S.rk_step_vjp(stage_U, stage_G, Ub, Rb, dt)
+    e0.record(st)
+    for _ in range(repeats):
+        S.rk_step_vjp(stage_U, stage_G, Ub, Rb, dt)
+    e1.record(st)
+    torch.cuda.synchronize()
+    if not bool(torch.isfinite(Ub).all()):
+        raise RuntimeError("non-finite adjoint")
+    rev_stage_ms = e0.elapsed_time(e1) / (5 * repeats)
+    dof = S.K * S.n3
+    gbs = (BYTES_VJP_MAIN + BYTES_VJP_FACE) * dof / (rev_stage_ms * 1e-3) / 1e9
+    return {"workload": f"ns_tgv_kep_roe_lgl5_k{k}_curved", "dof": dof, "forward_stage_ms": fwd_stage_ms,
+            "reverse_stage_ms": rev_stage_ms, "reverse_over_forward_stage": rev_stage_ms / fwd_stage_ms,
+            "roofline": {"bound": "hbm", "kernel": "k_vjp_main + k_vjp_face (one reverse stage)", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_dof": BYTES_VJP_MAIN + BYTES_VJP_FACE}}
+
+
 def order_bench(dgsem, inputs, torch, wl, steps: int, lexicographic_value: float):
     """Element order study on the headline lattice: the elements numbered at random, and the same
     mesh renumbered along the Hilbert curve of its element centroids (dg_mesh_sfc_order).  DOF
@@ -311,6 +476,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-general", action="store_true",
                     help="skip the measurement on the same mesh with rotated element axes")
+    ap.add_argument("--no-mortar", action="store_true", help="skip the non-conforming-mesh measurement")
+    ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume subcell measurement")
+    ap.add_argument("--no-adjoint-roofline", action="store_true",
+                    help="skip the reverse sweep's roofline at 32^3, N=5")
     ap.add_argument("--order-study", action="store_true",
                     help="also time the lattice with random and with Hilbert-curve element numbering")
     ap.add_argument("--calib-copy", action="store_true",
@@ -438,10 +607,23 @@ def main():
         out["general_mesh"] = general_mesh_bench(dgsem, inputs, torch, wl, 5, value)
         if not args.no_adjoint:
             out["general_mesh"]["adjoint"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, general=True)
-    if args.order_study:
-        if not freed:
-            del S, U, R, spare, cur, nxt
+    if (not args.no_mortar or not args.no_fv or not args.no_adjoint_roofline or args.order_study) and not freed:
+        del S, U, R, spare, cur, nxt
+        freed = True
+    torch.cuda.empty_cache()
+    if not args.no_adjoint_roofline:
+        out["adjoint_hbm"] = adjoint_roofline(dgsem, inputs, torch)
+        if not args.no_adjoint:
+            # the adjoint/forward rollout ratio at the same size (20 steps, checkpoint every 10)
+            out["adjoint_hbm"]["rollout"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, k1=32, steps=20)
         torch.cuda.empty_cache()
+    if not args.no_mortar:
+        out["mortar"] = mortar_bench(dgsem, inputs, torch, 5, value)
+        torch.cuda.empty_cache()
+    if not args.no_fv:
+        out["fv"] = fv_bench(dgsem, inputs, torch, 5)
+        torch.cuda.empty_cache()
+    if args.order_study:
         out["element_order"] = order_bench(dgsem, inputs, torch, wl, 5, value)
     if not args.no_cpu:
         cb = cpu_baseline(wl)

@@ -273,6 +273,10 @@ int dg_info(const dg_handle *h, int64_t out[4]);
  * main-kernel launches} accumulated since the last dg_profile call. */
 int dg_profile(dg_handle *h, int enable);
 int dg_profile_read(const dg_handle *h, double out[4]);
+/* The same with the kernels of non-conforming faces and finite-volume subcells apart: up to cap
+ * of {lifting ms (with the mortars' lifting kernel), launches, operator-kernel ms, launches,
+ * face-kernel ms (mortar fluxes, DG/FV faces), launches, finite-volume-kernel ms, launches}. */
+int dg_profile_read_ex(const dg_handle *h, double *out, int cap);
 
 /* ---- hybrid DG / finite-volume subcells (Sec. 4: shock capturing) ------------------------
  * A troubled element is advanced by a finite-volume scheme on (N+1)^3 equal subcells of width

@@ -650,8 +650,10 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
     const int rc = mortar_dispatch(h, U, Gin, true);
     if (rc) return rc;
   }
+  if (h->prof) (void)hipEventRecord(h->ev[3], h->stream);
   int rc = main_dispatch(h, U, Gin, out, R, a, b, dt, mode);
   if (rc) return rc;
+  if (h->prof) (void)hipEventRecord(h->ev[4], h->stream);
   if (h->fv_on) {
     // the finite-volume elements' subcell operator (the DG kernel leaves them out)
     rc = fv_dispatch(h, 1, U, out, R, a, b, dt, mode);
@@ -660,11 +662,15 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
   if (h->prof) {
     (void)hipEventRecord(h->ev[2], h->stream);
     if (hipEventSynchronize(h->ev[2]) != hipSuccess) return DG_ERR_HIP;
-    float m0 = 0.f, m1 = 0.f;
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
     (void)hipEventElapsedTime(&m0, h->ev[0], h->ev[1]);
-    (void)hipEventElapsedTime(&m1, h->ev[1], h->ev[2]);
+    (void)hipEventElapsedTime(&m1, h->ev[3], h->ev[4]);
+    (void)hipEventElapsedTime(&m2, h->ev[1], h->ev[3]);
+    (void)hipEventElapsedTime(&m3, h->ev[4], h->ev[2]);
     if (ns) { h->prof_ms[0] += m0; h->prof_ms[1] += 1; }
     h->prof_ms[2] += m1; h->prof_ms[3] += 1;
+    if (h->nm || h->fv_on) { h->prof_ms[4] += m2; h->prof_ms[5] += 1; }
+    if (h->fv_on) { h->prof_ms[6] += m3; h->prof_ms[7] += 1; }
   }
   return DG_OK;
 }
@@ -1155,17 +1161,23 @@ int dg_node_coords(dg_handle *h, double *x_host) {
 int dg_profile(dg_handle *h, int enable) {
   if (!h) return DG_ERR_ARG;
   if (enable && !h->ev[0]) {
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 5; ++i)
       if (hipEventCreate(&h->ev[i]) != hipSuccess) return fail(h, DG_ERR_HIP, "hipEventCreate failed");
   }
   h->prof = enable != 0;
-  for (int i = 0; i < 4; ++i) h->prof_ms[i] = 0.0;
+  for (int i = 0; i < 8; ++i) h->prof_ms[i] = 0.0;
   return DG_OK;
 }
 
 int dg_profile_read(const dg_handle *h, double out[4]) {
   if (!h || !out) return DG_ERR_ARG;
   for (int i = 0; i < 4; ++i) out[i] = h->prof_ms[i];
+  return DG_OK;
+}
+
+int dg_profile_read_ex(const dg_handle *h, double *out, int cap) {
+  if (!h || !out || cap < 0) return DG_ERR_ARG;
+  for (int i = 0; i < cap && i < 8; ++i) out[i] = h->prof_ms[i];
   return DG_OK;
 }
 
@@ -1232,34 +1244,55 @@ int dg_fv_enable(dg_handle *h, int limiter, double ind_lo, double ind_hi) {
     for (int f = 0; f <= n; ++f)
       for (int m = 0; m < n; ++m) lf[(size_t)f * n + m] = lag_eval(B.x, B.bw, m, -1.0L + f * w);
     std::vector<double> Jbar((size_t)K * n3), Nf((size_t)K * 3 * (n + 1) * n2 * 3);
-    for (int e = 0; e < K; ++e) {
-      std::vector<xf> x(n3), y(n3);
-      for (int q = 0; q < n3; ++q) x[q] = h->J_nodes[(size_t)e * n3 + q];
-      for (int dir = 0; dir < 3; ++dir) {
-        tensor_apply(V.data(), n, dir, x.data(), y.data());
-        x.swap(y);
-      }
-      for (int q = 0; q < n3; ++q) Jbar[(size_t)e * n3 + q] = (double)x[q];
-      for (int dir = 0; dir < 3; ++dir)
-        for (int d = 0; d < 3; ++d) {
-          const double *J = Ja.data() + ((size_t)e * 9 + dir * 3 + d) * n3;
-          for (int f = 0; f <= n; ++f) {
-            std::vector<xf> gfa((size_t)n2);  // Ja^dir_d on the face position f, at face point (ia, jb)
-            for (int jb = 0; jb < n; ++jb)
-              for (int ia = 0; ia < n; ++ia) {
-                xf v = 0.0L;
-                for (int m = 0; m < n; ++m) v += lf[(size_t)f * n + m] * J[face_line_node(n, dir, ia, jb, m)];
-                gfa[ia + n * jb] = v;
-              }
-            for (int bb = 0; bb < n; ++bb)
-              for (int aa = 0; aa < n; ++aa) {
-                xf v = 0.0L;
-                for (int jb = 0; jb < n; ++jb)
-                  for (int ia = 0; ia < n; ++ia) v += V[(size_t)aa * n + ia] * V[(size_t)bb * n + jb] * gfa[ia + n * jb];
-                Nf[((((size_t)e * 3 + dir) * (n + 1) + f) * n2 + aa + n * bb) * 3 + d] = (double)v;
-              }
-          }
+    // elements are independent: split them over host threads
+    unsigned nthr = std::thread::hardware_concurrency();
+    if (const char *env = std::getenv("OMP_NUM_THREADS")) nthr = (unsigned)std::max(1, std::atoi(env));
+    nthr = std::max(1u, std::min(nthr, 32u));
+    if ((size_t)K < 4 * (size_t)nthr) nthr = 1;
+    auto work = [&](unsigned tid) {
+      std::vector<xf> x(n3), y(n3), gfa((size_t)n2), ga((size_t)n2);
+      const int e0 = (int)((size_t)K * tid / nthr), e1 = (int)((size_t)K * (tid + 1) / nthr);
+      for (int e = e0; e < e1; ++e) {
+        for (int q = 0; q < n3; ++q) x[q] = h->J_nodes[(size_t)e * n3 + q];
+        for (int dir = 0; dir < 3; ++dir) {
+          tensor_apply(V.data(), n, dir, x.data(), y.data());
+          x.swap(y);
         }
+        for (int q = 0; q < n3; ++q) Jbar[(size_t)e * n3 + q] = (double)x[q];
+        for (int dir = 0; dir < 3; ++dir)
+          for (int d = 0; d < 3; ++d) {
+            const double *J = Ja.data() + ((size_t)e * 9 + dir * 3 + d) * n3;
+            for (int f = 0; f <= n; ++f) {
+              // Ja^dir_d on the face position f at face point (ia, jb), then subcell means along the
+              // face's first direction and then its second
+              for (int jb = 0; jb < n; ++jb)
+                for (int ia = 0; ia < n; ++ia) {
+                  xf v = 0.0L;
+                  for (int m = 0; m < n; ++m) v += lf[(size_t)f * n + m] * J[face_line_node(n, dir, ia, jb, m)];
+                  gfa[ia + n * jb] = v;
+                }
+              for (int jb = 0; jb < n; ++jb)
+                for (int aa = 0; aa < n; ++aa) {
+                  xf v = 0.0L;
+                  for (int ia = 0; ia < n; ++ia) v += V[(size_t)aa * n + ia] * gfa[ia + n * jb];
+                  ga[aa + n * jb] = v;
+                }
+              for (int bb = 0; bb < n; ++bb)
+                for (int aa = 0; aa < n; ++aa) {
+                  xf v = 0.0L;
+                  for (int jb = 0; jb < n; ++jb) v += V[(size_t)bb * n + jb] * ga[aa + n * jb];
+                  Nf[((((size_t)e * 3 + dir) * (n + 1) + f) * n2 + aa + n * bb) * 3 + d] = (double)v;
+                }
+            }
+          }
+      }
+    };
+    if (nthr == 1) {
+      work(0);
+    } else {
+      std::vector<std::thread> pool;
+      for (unsigned tt = 0; tt < nthr; ++tt) pool.emplace_back(work, tt);
+      for (auto &th : pool) th.join();
     }
     int rc = dev_alloc(&h->d_fvtab, tab.size());
     if (!rc) rc = dev_alloc(&h->d_fvJbar, Jbar.size());
@@ -1332,7 +1365,7 @@ int dg_fv_switch(dg_handle *h, double *U) {
 
 void dg_destroy(dg_handle *h) {
   if (!h) return;
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 5; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_fc); (void)hipFree(h->d_tab);

@@ -243,8 +243,10 @@ struct dg_handle {
   dg::Tab tab{};
   // optional per-kernel timing with HIP events (dg_profile)
   bool prof = false;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  double prof_ms[4] = {0, 0, 0, 0};  // lift ms, lift launches, main ms, main launches
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // lift ms, lift launches, main ms, main launches, face-kernel ms and launches (mortar fluxes,
+  // DG/FV faces), FV volume-kernel ms and launches
+  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<double> x_nodes;  // solution-node coordinates (host), [K][3][n3]
   std::vector<double> J_nodes;  // Jacobian at the solution nodes (host), [K][n3]
   std::string err;

@@ -30,7 +30,7 @@ EXPORTS = [
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
     "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
-    "dg_integrals_noalloc", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
+    "dg_integrals_noalloc", "dg_profile_read_ex", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
 ]
 
 
@@ -108,6 +108,7 @@ def lib():
         L.dg_host_geometry.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, ctypes.c_int] + [_D] * 5
         L.dg_profile.argtypes = [_VP, ctypes.c_int]
         L.dg_profile_read.argtypes = [_VP, _D]
+        L.dg_profile_read_ex.argtypes = [_VP, _D, ctypes.c_int]
         L.dg_batch_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
         L.dg_batch_rk_stage.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, _D, _D]
         L.dg_batch_destroy.argtypes = [_VP]
@@ -392,9 +393,10 @@ class DGSolver:
         self._check(lib().dg_profile(self.h, int(enable)), "dg_profile")
 
     def profile_read(self):
-        out = np.zeros(4)
-        self._check(lib().dg_profile_read(self.h, _ptr(out)), "dg_profile_read")
-        return {"lift_ms": out[0], "lift_launches": int(out[1]), "main_ms": out[2], "main_launches": int(out[3])}
+        out = np.zeros(8)
+        self._check(lib().dg_profile_read_ex(self.h, _ptr(out), 8), "dg_profile_read_ex")
+        return {"lift_ms": out[0], "lift_launches": int(out[1]), "main_ms": out[2], "main_launches": int(out[3]),
+                "face_ms": out[4], "face_launches": int(out[5]), "fv_ms": out[6], "fv_launches": int(out[7])}
 
     def mass_weights(self):
         """J w_i w_j w_k per node as a [K, n^3] device tensor."""

@@ -102,7 +102,12 @@ def test_fv_indicator_and_switch_parity(dg, orc):
     S = fv_solver(dg, wl, mesh, fv0, 1)
     ind_ref = M.fv_indicator(fv0, U0)
     ind = S.fv_indicator(to_gpu(U0))
-    np.testing.assert_allclose(ind, ind_ref, atol=1e-9)
+    # elements with a smooth state have rounding-level modal energies (log10 far below -12 on
+    # both sides, in values that depend on the rounding order); compare the others
+    sig = ind_ref > -12
+    assert sig.any() and not sig.all()
+    np.testing.assert_allclose(ind[sig], ind_ref[sig], atol=1e-9)
+    assert np.all(ind[~sig] < -12)
     fv_ref, U_ref = M.fv_switch(fv0, U0, -5.0, -2.5)
     assert 0 < fv_ref.sum() < M.K
     Ug = to_gpu(U0)
