@@ -147,6 +147,36 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *scheme, 
 int dg_mesh_connect(int n_elems, int n_geo, const double *xgeo, const double period[3], double tol, int bc_kind,
                     int32_t *nbr_elem, int8_t *nbr_side, int8_t *flip);
 
+/* Element-package mesh files (Sec. 2.1.1: per element one package of its side connectivity,
+ * conforming and non-conforming, and of its nodes' global indices and positions, so that any
+ * contiguous range of elements is one contiguous part of the file and is read on its own; a
+ * physical node shared by several elements is stored with each and tied by its global index).
+ * This library's own little-endian layout: a 64-byte header (magic "DGSEMMSH", int32 version 1,
+ * int32 n_geo, int64 K, int32 flags: bit 0 = mortar kinds present), then per element
+ * int64 node index [n^3], float64 coordinates [3][n^3], and 6 side records {int32 neighbour
+ * element, int8 neighbour side or boundary kind, int8 orientation code, int8 mortar kind, int8 0}
+ * in the conventions of dg_mesh.  Host only, synchronous; DG_ERR_ARG for I/O errors, a foreign
+ * or damaged file, or a range beyond the file.
+ * dg_mesh_file_write: writes K packages (flip and mortar may be NULL: zeros, no mortar flag).
+ * dg_mesh_file_info : out = {K, n_geo, flags}.
+ * dg_mesh_file_read : elements first .. first+count-1 into caller arrays laid out as in dg_mesh
+ *                     (xgeo [count][3][n^3], node_id [count][n^3], the side arrays [count][6]; any
+ *                     may be NULL); the neighbour indices are global element indices. */
+int dg_mesh_file_write(const char *path, int n_elems, int n_geo, const double *xgeo, const int64_t *node_id,
+                       const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip, const int8_t *mortar);
+int dg_mesh_file_info(const char *path, int64_t out[3]);
+int dg_mesh_file_read(const char *path, int64_t first, int count, double *xgeo, int64_t *node_id, int32_t *nbr_elem,
+                      int8_t *nbr_side, int8_t *flip, int8_t *mortar);
+
+/* Conforming connectivity from the global node indices of a mesh file, exactly (no tolerance):
+ * two sides whose four corner nodes have the same indices are one face, their orientation codes
+ * follow from the corners' order; a side no other side matches becomes a boundary of kind
+ * bc_kind (periodic faces, whose nodes differ, must come from the file's side records).
+ * node_id HOST [K][(n_geo+1)^3]; outputs HOST [K][6].  DG_ERR_MESH where more than two sides share
+ * a face or two matched faces admit no orientation; DG_ERR_ARG for bad arguments. */
+int dg_mesh_connect_nodes(int n_elems, int n_geo, const int64_t *node_id, int bc_kind, int32_t *nbr_elem,
+                          int8_t *nbr_side, int8_t *flip);
+
 /* Element order along a space-filling curve (Secs. 2.1.1 and 5.2: elements are stored in the
  * order of a space-filling curve, so neighbours are near in memory and in the launch order): order[i]
  * is the element (index into xgeo, HOST [K][3][(n_geo+1)^3]) at position i of the 3-D Hilbert

@@ -31,7 +31,7 @@ COMMON = [
 ]
 
 
-HOST_SOURCES = ("dg_host.cpp", "dg_batch.cpp")
+HOST_SOURCES = ("dg_host.cpp", "dg_batch.cpp", "dg_meshio.cpp")
 
 
 def _host_obj(src: str) -> str:

@@ -30,7 +30,8 @@ EXPORTS = [
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
     "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
-    "dg_integrals_noalloc", "dg_profile_read_ex", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
+    "dg_integrals_noalloc", "dg_profile_read_ex", "dg_mesh_file_write", "dg_mesh_file_info", "dg_mesh_file_read",
+    "dg_mesh_connect_nodes", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
 ]
 
 
@@ -109,6 +110,13 @@ def lib():
         L.dg_profile.argtypes = [_VP, ctypes.c_int]
         L.dg_profile_read.argtypes = [_VP, _D]
         L.dg_profile_read_ex.argtypes = [_VP, _D, ctypes.c_int]
+        _I64 = ctypes.POINTER(ctypes.c_int64)
+        _I32 = ctypes.POINTER(ctypes.c_int32)
+        _I8 = ctypes.POINTER(ctypes.c_int8)
+        L.dg_mesh_file_write.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, _D, _I64, _I32, _I8, _I8, _I8]
+        L.dg_mesh_file_info.argtypes = [ctypes.c_char_p, _I64]
+        L.dg_mesh_file_read.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int, _D, _I64, _I32, _I8, _I8, _I8]
+        L.dg_mesh_connect_nodes.argtypes = [ctypes.c_int, ctypes.c_int, _I64, ctypes.c_int, _I32, _I8, _I8]
         L.dg_batch_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP)]
         L.dg_batch_rk_stage.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, _D, _D]
         L.dg_batch_destroy.argtypes = [_VP]
@@ -180,6 +188,62 @@ def _geo_degree(xgeo, N, ngeo):
 
 def _i8(a):
     return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+def _p(a, ct):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def mesh_file_write(path: str, xgeo, node_id, nbr, side, flip=None, mortar=None):
+    """Write an element-package mesh file (``dg_mesh_file_write``); ``xgeo[K,3,(ngeo+1)^3]``."""
+    xgeo = np.ascontiguousarray(xgeo, np.float64)
+    K = xgeo.shape[0]
+    ngeo = round(xgeo.shape[-1] ** (1.0 / 3.0)) - 1
+    node_id = np.ascontiguousarray(node_id, np.int64)
+    nbr, side = np.ascontiguousarray(nbr, np.int32), np.ascontiguousarray(side, np.int8)
+    flip = None if flip is None else np.ascontiguousarray(flip, np.int8)
+    mortar = None if mortar is None else np.ascontiguousarray(mortar, np.int8)
+    rc = lib().dg_mesh_file_write(path.encode(), K, ngeo, _ptr(xgeo), _p(node_id, ctypes.c_int64),
+                                  _p(nbr, ctypes.c_int32), _p(side, ctypes.c_int8), _p(flip, ctypes.c_int8),
+                                  _p(mortar, ctypes.c_int8))
+    if rc:
+        raise DGError(rc, "dg_mesh_file_write")
+
+
+def mesh_file_read(path: str, first: int = 0, count: Optional[int] = None):
+    """Elements first .. first+count-1 of an element-package mesh file: a dict with xgeo, node_id,
+    nbr, side, flip, mortar (None without mortar kinds), ngeo."""
+    info = np.zeros(3, np.int64)
+    rc = lib().dg_mesh_file_info(path.encode(), _p(info, ctypes.c_int64))
+    if rc:
+        raise DGError(rc, "dg_mesh_file_info")
+    K, ngeo, flags = int(info[0]), int(info[1]), int(info[2])
+    count = K - first if count is None else count
+    n3 = (ngeo + 1) ** 3
+    xgeo = np.zeros((count, 3, n3))
+    node_id = np.zeros((count, n3), np.int64)
+    nbr = np.zeros((count, 6), np.int32)
+    side, flip, mortar = (np.zeros((count, 6), np.int8) for _ in range(3))
+    rc = lib().dg_mesh_file_read(path.encode(), int(first), int(count), _ptr(xgeo), _p(node_id, ctypes.c_int64),
+                                 _p(nbr, ctypes.c_int32), _p(side, ctypes.c_int8), _p(flip, ctypes.c_int8),
+                                 _p(mortar, ctypes.c_int8))
+    if rc:
+        raise DGError(rc, "dg_mesh_file_read")
+    return dict(xgeo=xgeo, node_id=node_id, nbr=nbr, side=side, flip=flip, mortar=mortar if flags & 1 else None,
+                ngeo=ngeo)
+
+
+def mesh_connect_nodes(node_id, ngeo: int, bc_kind: int = 0):
+    """Conforming connectivity (nbr, side, flip) from global node indices (``dg_mesh_connect_nodes``)."""
+    node_id = np.ascontiguousarray(node_id, np.int64)
+    K = node_id.shape[0]
+    nbr = np.zeros((K, 6), np.int32)
+    side, flip = np.zeros((K, 6), np.int8), np.zeros((K, 6), np.int8)
+    rc = lib().dg_mesh_connect_nodes(K, ngeo, _p(node_id, ctypes.c_int64), bc_kind, _p(nbr, ctypes.c_int32),
+                                     _p(side, ctypes.c_int8), _p(flip, ctypes.c_int8))
+    if rc:
+        raise DGError(rc, "dg_mesh_connect_nodes")
+    return nbr, side, flip
 
 
 def host_geometry(xgeo, nbr, nside, N: int, node_type: str, flip=None, ngeo=None, mortar=None):

@@ -407,6 +407,16 @@ def connect_boxes(X, n: int, period=(TWO_PI, TWO_PI, TWO_PI), bc_kind: int = 0):
     return nbr, side, flip, mortar
 
 
+def global_node_ids(X, digits: int = 9):
+    """A global index for every element node ``X[K][3][n^3]``: nodes at the same position (rounded
+    to ``digits`` decimals) share one index, as in a mesh file's node list."""
+    X = np.asarray(X)
+    K, _, n3 = X.shape
+    keys = np.round(np.transpose(X, (0, 2, 1)).reshape(-1, 3), digits)
+    _, ids = np.unique(keys, axis=0, return_inverse=True)
+    return ids.reshape(K, n3).astype(np.int64)
+
+
 def lattice_points(nodes_1d, kx: int, ky: int, kz: int, box=(TWO_PI, TWO_PI, TWO_PI)):
     """Undeformed positions ``X[e][3][n^3]`` of tensor nodes in every lattice cell.
 

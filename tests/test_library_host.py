@@ -337,3 +337,87 @@ def test_host_geometry_degree_matches_oracle(dg, orc, N, ngeo, nodes):
         assert np.abs(h[key] - g[key]).max() <= 2.0 * eps * np.abs(g[key]).max(), key
     with pytest.raises(ValueError):
         dg.host_geometry(xg, nbr, side, N, nodes)  # the point count names the degree
+
+
+def _box_mesh_with_ids(dg, ngeo, m=3, kind=4, seed=2):
+    lgl, _ = dg.nodes(ngeo, "lgl")
+    X = inputs.lattice_points(lgl, m, m, m, box=(np.pi,) * 3)
+    nbr, side, flip = inputs.box_lattice(m, m, m, kind=kind)
+    rot = np.random.default_rng(seed).integers(0, 24, m ** 3)
+    X, nbr, side, flip, _ = inputs.rotate_elements(X, nbr, side, flip, ngeo, rot)
+    ids = inputs.global_node_ids(X)
+    return inputs.warp_sine(X), ids, nbr, side, flip
+
+
+@pytest.mark.parametrize("ngeo", [1, 3])
+def test_mesh_file_round_trip(dg, tmp_path, ngeo):
+    """Element packages (Sec. 2.1.1): the file read back, whole or as any contiguous range of
+    elements, holds exactly what was written."""
+    X, ids, nbr, side, flip = _box_mesh_with_ids(dg, ngeo)
+    path = str(tmp_path / "box.mesh")
+    dg.mesh_file_write(path, X, ids, nbr, side, flip)
+    K = X.shape[0]
+    n3 = (ngeo + 1) ** 3
+    assert os.path.getsize(path) == 64 + K * (32 * n3 + 48)
+    got = dg.mesh_file_read(path)
+    assert got["ngeo"] == ngeo and got["mortar"] is None
+    for a, b in ((got["xgeo"], X), (got["node_id"], ids), (got["nbr"], nbr), (got["side"], side),
+                 (got["flip"], flip)):
+        assert np.array_equal(a, b)
+    for first, count in ((0, 1), (5, 7), (K - 4, 4)):
+        part = dg.mesh_file_read(path, first, count)
+        assert np.array_equal(part["xgeo"], X[first:first + count])
+        assert np.array_equal(part["nbr"], nbr[first:first + count])
+        assert np.array_equal(part["node_id"], ids[first:first + count])
+
+
+def test_mesh_file_with_mortars(dg, orc, tmp_path):
+    """A non-conforming mesh keeps its mortar kinds; the mesh read back gives the same geometry."""
+    r = orc.basis(2, "lgl")["x"]
+    X = inputs.refined_lattice(r, 2, (2, 2, 2))
+    nbr, side, flip, mort = inputs.connect_boxes(X, 3)
+    Xw = inputs.warp_bubble(X, 0.1, 2)
+    path = str(tmp_path / "mortar.mesh")
+    dg.mesh_file_write(path, Xw, inputs.global_node_ids(X), nbr, side, flip, mort)
+    got = dg.mesh_file_read(path)
+    assert np.array_equal(got["mortar"], mort) and np.array_equal(got["flip"], flip)
+    a = dg.host_geometry(Xw, nbr, side, 4, "lgl", flip=flip, ngeo=2, mortar=mort)
+    b = dg.host_geometry(got["xgeo"], got["nbr"], got["side"], 4, "lgl", flip=got["flip"], ngeo=2,
+                         mortar=got["mortar"])
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("ngeo,kind", [(1, 0), (2, 4), (3, 1)])
+def test_mesh_connect_nodes(dg, ngeo, kind):
+    """Connectivity from global node indices alone equals the lattice generator's, for elements
+    with rotated reference axes (every side and orientation code), no tolerance involved."""
+    X, ids, nbr, side, flip = _box_mesh_with_ids(dg, ngeo, kind=kind)
+    got = dg.mesh_connect_nodes(ids, ngeo, bc_kind=kind)
+    for a, b in zip(got, (nbr, side, flip)):
+        np.testing.assert_array_equal(a, b)
+    dg.host_geometry(X, *got[:2], 3, "lgl", flip=got[2], ngeo=ngeo)
+
+
+def test_mesh_file_errors(dg, tmp_path):
+    X, ids, nbr, side, flip = _box_mesh_with_ids(dg, 1, m=2)
+    path = str(tmp_path / "m.mesh")
+    dg.mesh_file_write(path, X, ids, nbr, side, flip)
+    with pytest.raises(dg.DGError):
+        dg.mesh_file_read(path, 6, 3)                       # beyond the last element
+    with pytest.raises(dg.DGError):
+        dg.mesh_file_read(str(tmp_path / "missing.mesh"))
+    bad = tmp_path / "bad.mesh"
+    bad.write_bytes(b"NOTAMESH" + bytes(120))
+    with pytest.raises(dg.DGError):
+        dg.mesh_file_read(str(bad))
+    short = tmp_path / "short.mesh"
+    short.write_bytes(open(path, "rb").read()[:200])
+    with pytest.raises(dg.DGError):
+        dg.mesh_file_read(str(short))
+    three = np.concatenate([ids, ids[:1]])                  # a face shared by three sides
+    with pytest.raises(dg.DGError) as ei:
+        dg.mesh_connect_nodes(three, 1)
+    assert ei.value.code == -2
+    with pytest.raises(dg.DGError):
+        dg.mesh_connect_nodes(ids, 1, bc_kind=9)
