@@ -232,7 +232,8 @@ int dg_rhs_vjp(dg_handle *h, const double *U, const double *Ut_bar, double *U_ba
 /* Reverse of dg_rk_stage at the stage input U_in.  On entry U_bar, R_bar hold the
  * adjoints of (U_out, R after the stage); on return they hold the adjoints of
  * (U_in, R before the stage):
- *   R_bar <- R_bar + b*U_bar;  U_bar <- U_bar + dt*(dL/dU)(U_in)^T R_bar;  R_bar <- a*R_bar. */
+ *   R_bar <- R_bar + b*U_bar;  U_bar <- U_bar + dt*(dL/dU)(U_in)^T R_bar;  R_bar <- a*R_bar.
+ * Not in the paper: the transpose of one stage of its low-storage Runge-Kutta scheme (Sec. 4.4). */
 int dg_rk_stage_vjp(dg_handle *h, const double *U_in, double *U_bar, double *R_bar, double a, double b, double dt);
 
 /* dg_rk_stage that also keeps the lifting output of U_in in G_out (Navier-Stokes: device
@@ -283,7 +284,8 @@ int dg_integrals(dg_handle *h, const double *U, double out[8]);
  * or misaligned pointers. */
 int dg_integrals_noalloc(dg_handle *h, const double *U, double *out_dev);
 
-/* DG_ERR_NONFINITE if any entry of U is NaN or Inf, DG_OK otherwise.  Synchronous. */
+/* DG_ERR_NONFINITE if any entry of U is NaN or Inf, DG_OK otherwise.  Synchronous.  Not in the
+ * paper: a guard a time loop may call between steps (a blown-up solution is NaN after a few). */
 int dg_check_finite(dg_handle *h, const double *U);
 
 /* Quadrature weight of every node, J w_i w_j w_k (the diagonal mass matrix of Sec. 3.1,

@@ -3,7 +3,7 @@
 // <adjoint, flux> along every input coordinate.  Prints one line per function with the largest
 // relative mismatch and returns non-zero if any exceeds the tolerance.
 #define DGFN inline
-#include "dg_flux.h"
+#include "../paper_1910_02858_amd/csrc/dg_flux.h"
 
 #include <cstdio>
 #include <cstdlib>

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_1910_02858_amd", "csrc", "flux_selftest.cpp")
+SRC = os.path.join(ROOT, "tests", "flux_selftest.cpp")
 
 
 def test_flux_adjoints_match_finite_differences(tmp_path):
