@@ -986,11 +986,24 @@ __device__ __forceinline__ void split_tables(const Tab *tb, int t, int nthreads,
   if (t < n) { slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t]; }
 }
 
+// Lane layout of the split-form kernel.  With n = 7 (N = 6) the element's 343 nodes are laid out
+// on padded 8 x 8 planes, one k-plane per 64-lane wave (lane i + 8 j + 64 k, lanes with i = 7 or
+// j = 7 idle): 448 lanes instead of 384, but the lines of the first two directions then lie
+// inside one wave, like those of n = 8.  Other degrees map lane t to node t.
+#ifndef DG_SPLIT_PAD7
+#define DG_SPLIT_PAD7 1
+#endif
+template <int N> struct SplitSz {
+  static constexpr int n = N + 1;
+  static constexpr bool PAD = DG_SPLIT_PAD7 && n == 7;
+  static constexpr int NT = PAD ? 64 * n : Sz<N>::NT;
+};
+
 // exchange rounds of direction dir stay inside one 64-lane wave: lines of the first two
-// directions when n divides 64 and n^2 divides 64 (n = 2, 4, 8); every line when the whole
-// element fits one wave
+// directions when n divides 64 and n^2 divides 64 (n = 2, 4, 8) or the planes are padded to
+// 8 x 8; every line when the whole element fits one wave
 template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
-  return (n * n * n <= 64) || (dir < 2 && (n == 2 || n == 4 || n == 8));
+  return (n * n * n <= 64) || (dir < 2 && (n == 2 || n == 4 || n == 8 || SplitSz<n - 1>::PAD));
 }
 
 // Split-form operator on LGL nodes (eq. semiDiscreteSplit) for element e by the NT threads t of
@@ -999,13 +1012,21 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
 template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
-__device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
+__device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int lane,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
                                            double dt, double *sA, double *sP, const double *sD, const double *slh) {
   using S = Sz<N>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  const bool act = valid && t < n3;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = SplitSz<N>::NT;
+  // t: this lane's node (lanes past the element, or on the padding, are idle)
+  int t = lane;
+  bool inb = lane < n3;
+  if constexpr (SplitSz<N>::PAD) {
+    const int i = lane & 7, j = (lane >> 3) & 7, k = lane >> 6;
+    inb = i < n && j < n && k < n;
+    t = i + n * (j + n * k);
+  }
+  const bool act = valid && inb;
   const double gm1 = ph.gamma - 1.0, kg = 1.0 / gm1, gg = gm1 / ph.gamma;
   const double *Ue = U + (size_t)e * 5 * n3;
   const double *Ge = G + (size_t)e * 12 * n3;
@@ -1025,7 +1046,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     for (int v = 0; v < 5; ++v) Uo[v] = Ue[v * n3 + t];
   }
   // numerical surface flux on the six faces, stored outward for this element
-  for (int q = valid ? t : 6 * n2; q < 6 * n2; q += NT) {
+  for (int q = valid ? lane : 6 * n2; q < 6 * n2; q += NT) {
     const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
@@ -1298,14 +1319,14 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 }
 
 template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
-__global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(SplitSz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
   using L = SplitLds<N>;
   constexpr int n = L::n;
   __shared__ double sA[L::A], sP[L::P];
   __shared__ double sD[n * n], slh[2 * n];
-  split_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sD, slh);
+  split_tables<N>(g.tab, threadIdx.x, SplitSz<N>::NT, sD, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
   if (FVM && g.fvflag[e]) return;  // a finite-volume element
@@ -1314,7 +1335,8 @@ __global__ void __launch_bounds__(Sz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys 
 
 // ----------------------------------------------------------------------------- ensemble batch
 // Workgroups of the batched kernels walk the concatenated element list of all members of one
-// degree; EPB elements share a workgroup (one slot of Sz<N>::NT threads each, wave aligned).
+// degree; EPB elements share a workgroup (one slot of Sz<N>::NT threads each, SplitSz<N>::NT in
+// the split-form kernel, wave aligned).
 // Each slot finds its member by bisection of the element prefix sums.
 __device__ __forceinline__ int member_of(const int *first, int count, int item) {
   int lo = 0, hi = count - 1;
@@ -1347,9 +1369,9 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
 }
 
 template <int N, bool NS, int VF, int EPB, bool GEN>
-__global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_SPLIT_MINB) k_split_b(BatchView bv) {
+__global__ void __launch_bounds__(SplitSz<N>::NT * EPB, DG_SPLIT_MINB) k_split_b(BatchView bv) {
   using L = SplitLds<N>;
-  constexpr int n = L::n, NT = Sz<N>::NT;
+  constexpr int n = L::n, NT = SplitSz<N>::NT;
   __shared__ double sA[EPB * L::A], sP[EPB * L::P];
   __shared__ double sD[n * n], slh[2 * n];
   split_tables<N>(bv.tab, threadIdx.x, NT * EPB, sD, slh);
@@ -2123,7 +2145,7 @@ static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const do
 template <int N, bool NS, int VF>
 static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const double *G, double *out, double *R,
                           double a, double b, double dt, int mode, hipStream_t st) {
-  dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
+  dim3 grid(xcd_grid(g.K)), block(SplitSz<N>::NT);
   const bool gen = g.fc != nullptr;
   if constexpr (!NS) {
     if (g.fvflag) {
@@ -2208,9 +2230,11 @@ template <int N, bool NS, int VF, int EPB>
 static int launch_batch_split_t(const BatchView &bv, hipStream_t st) {
   const int nblk = (bv.total + EPB - 1) / EPB;
   if (bv.general)
-    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, true>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, true>), dim3(xcd_grid(nblk)), dim3(SplitSz<N>::NT * EPB), 0, st,
+                       bv);
   else
-    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, false>), dim3(xcd_grid(nblk)), dim3(Sz<N>::NT * EPB), 0, st, bv);
+    hipLaunchKernelGGL((k_split_b<N, NS, VF, EPB, false>), dim3(xcd_grid(nblk)), dim3(SplitSz<N>::NT * EPB), 0, st,
+                       bv);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
