@@ -76,13 +76,12 @@ def counter_traffic():
         return None, False
 
 
-def cpu_baseline(wl, budget_s: float = 12.0):
-    """Time the oracle's RK stage on a bounded sample of the same workload (12^3 elements, N=7)."""
-    from oracle import oracle as orc
-    from paper_1910_02858_amd import inputs
-    k = 12
+def _oracle_stages(orc, inputs, wl, k, budget_s):
+    """(DOF updates per second, stages, DOF) of the oracle's RK stage for workload wl on k^3 elements."""
     lgl = orc.basis(wl.N, "lgl")["x"]
     X = inputs.lattice_points(lgl, k, k, k)
+    if wl.curved:
+        X = inputs.warp_sine(X)
     nbr, side, _ = inputs.periodic_lattice(k, k, k)
     M = orc.OracleMesh(X, nbr, side, wl.N, wl.nodes)
     U = inputs.initial_state(wl, M.points())
@@ -98,9 +97,27 @@ def cpu_baseline(wl, budget_s: float = 12.0):
             break
     wall = time.perf_counter() - t0
     dof = M.K * M.n3
-    return {"value": dof * stages / wall, "unit": "DOF-updates/s", "cores": orc.num_threads(), "kind": "oracle",
+    return dof * stages / wall, stages, dof, wall
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    """Time the oracle's RK stage on a bounded sample of the same workload (16^3 elements, N=7:
+    131 k nodes per host thread at 16 threads, where the cost per node no longer depends on the
+    size), and the small workloads in full (Euler density wave, the curved 16^3 N=5 TGV, the 12^3
+    N=5 adjoint workload's forward stage) for context."""
+    from oracle import oracle as orc
+    from paper_1910_02858_amd import inputs
+    k = 16
+    value, stages, dof, wall = _oracle_stages(orc, inputs, wl, k, budget_s)
+    configs = {}
+    for idx in (1, 2, 5):
+        w = inputs.workload(idx)
+        v, st, d, _ = _oracle_stages(orc, inputs, w, w.K1, 2.0)
+        configs[w.name] = {"value": v, "stages": st, "dof": d}
+    return {"value": value, "unit": "DOF-updates/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": f"{stages} RK stages of the same scheme on {k}^3 elements, N={wl.N} ({dof} nodes), FP64",
-            "pid_core_s": wall * orc.num_threads() / (dof * stages), "pid_1thread_s": cpu_pid_one_thread()}
+            "pid_core_s": wall * orc.num_threads() / (dof * stages), "pid_1thread_s": cpu_pid_one_thread(),
+            "configs": configs}
 
 
 _ONE_THREAD = r"""
@@ -217,6 +234,78 @@ def ensemble_bench(dgsem, inputs, torch, steps: int = 10, n_members: int = 256):
         raise RuntimeError("non-finite ensemble state")
     out["speedup_vs_per_member"] = out["batched_graph"] / out["per_member_launches"]
     return out
+
+
+def ec_branch_bench(S, U_smooth, torch, wl, smooth_main_ms: float, stages: int = 5):
+    """The EC flux's logarithmic means under real jumps: the headline state with every conservative
+    variable multiplied by 1 + 0.1 xi per node (xi ~ N(0,1), seeded), so that most node pairs'
+    density and beta ratios take the logarithm branch ((a-b)/(a+b))^2 >= 1e-4 instead of the
+    series; the operator kernel's time (HIP events, ``stages`` RK stages) against the smooth TGV's."""
+    g = torch.Generator(device="cuda").manual_seed(7)
+    U = U_smooth * (1.0 + 0.1 * torch.randn(U_smooth.shape, generator=g, device="cuda", dtype=torch.float64))
+    n = wl.N + 1
+    rho = U[:, 0].reshape(-1, n, n, n)
+    ke = 0.5 * (U[:, 1] ** 2 + U[:, 2] ** 2 + U[:, 3] ** 2) / U[:, 0]
+    p = 0.4 * (U[:, 4] - ke)  # gamma = 1.4
+    beta = (0.5 * U[:, 0] / p).reshape(-1, n, n, n)
+    del ke
+
+    def log_frac(a):
+        r = (a[..., 1:] - a[..., :-1]) / (a[..., 1:] + a[..., :-1])
+        return float(((r * r) >= 1e-4).double().mean())
+
+    fr, fb = log_frac(rho), log_frac(beta)
+    del rho, beta, p
+    dt = S.timestep(U, wl.cfl, wl.dfl)
+    R = torch.zeros_like(U)
+    nxt = S.empty()
+    from paper_1910_02858_amd import dgsem
+    a, b, _ = dgsem.rk_coefficients()
+    S.profile(True)
+    cur = U
+    for s_ in range(stages):
+        S.rk_stage(cur, nxt, R, a[s_ % 5], b[s_ % 5], dt)
+        cur, nxt = nxt, cur
+    prof = S.profile_read()
+    S.profile(False)
+    if not S.check_finite(cur):
+        raise RuntimeError("non-finite state in the EC branch measurement")
+    main_ms = prof["main_ms"] / max(prof["main_launches"], 1)
+    return {"state": "TGV x (1 + 0.1 xi) per node and variable", "pairs_log_branch_rho": fr,
+            "pairs_log_branch_beta": fb, "main_ms": main_ms, "smooth_main_ms": smooth_main_ms,
+            "slowdown": main_ms / smooth_main_ms, "stages": stages}
+
+
+def weak_form_bench(dgsem, inputs, torch, k: int = 48, stages: int = 10):
+    """The weak form on LG nodes (k_main: the D-hat contraction of the fluxes along every line, LG
+    face prolongation, BR1 gradients): the headline mesh and TGV with Navier-Stokes, central volume
+    flux, Roe; per-kernel times and the operator kernel priced at the same 336 B per node."""
+    wl = inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=k)
+    S, U = dgsem.build_solver(wl)
+    dt = S.timestep(U, wl.cfl, wl.dfl)
+    a, b, _ = dgsem.rk_coefficients()
+    R = torch.zeros_like(U)
+    nxt = S.empty()
+    cur = U
+    for s_ in range(5):  # warm-up
+        S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+        cur, nxt = nxt, cur
+    S.profile(True)
+    for s_ in range(stages):
+        S.rk_stage(cur, nxt, R, a[s_ % 5], b[s_ % 5], dt)
+        cur, nxt = nxt, cur
+    prof = S.profile_read()
+    S.profile(False)
+    if not S.check_finite(cur):
+        raise RuntimeError("non-finite state in the weak-form measurement")
+    dof = S.K * S.n3
+    main_ms = prof["main_ms"] / max(prof["main_launches"], 1)
+    lift_ms = prof["lift_ms"] / max(prof["lift_launches"], 1)
+    gbs = BYTES_MAIN * dof / (main_ms * 1e-3) / 1e9
+    return {"workload": f"ns_tgv_central_roe_lg7_k{k}_weak", "dof": dof, "kernels_ms": {"main": main_ms, "lift": lift_ms},
+            "value": dof / ((main_ms + lift_ms) * 1e-3),
+            "roofline": {"bound": "hbm", "kernel": "k_main (weak form, LG)", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_dof": BYTES_MAIN}}
 
 
 def general_mesh_bench(dgsem, inputs, torch, wl, steps: int, structured_value: float):
@@ -478,6 +567,9 @@ def main():
                     help="skip the measurement on the same mesh with rotated element axes")
     ap.add_argument("--no-mortar", action="store_true", help="skip the non-conforming-mesh measurement")
     ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume subcell measurement")
+    ap.add_argument("--no-weak", action="store_true", help="skip the weak-form (LG) operator measurement")
+    ap.add_argument("--no-ec-branch", action="store_true",
+                    help="skip the EC flux measurement on a state with jumps (logarithm branch)")
     ap.add_argument("--no-adjoint-roofline", action="store_true",
                     help="skip the reverse sweep's roofline at 32^3, N=5")
     ap.add_argument("--order-study", action="store_true",
@@ -532,6 +624,11 @@ def main():
     lift_ms = prof["lift_ms"] / max(prof["lift_launches"], 1)
     main_gbs = BYTES_MAIN * dof / (main_ms * 1e-3) / 1e9
     lift_gbs = BYTES_LIFT * dof / (lift_ms * 1e-3) / 1e9
+
+    ec_branch = None
+    if not args.no_ec_branch and wl.volflux == "ec":
+        ec_branch = ec_branch_bench(S, U, torch, wl, main_ms)
+        torch.cuda.empty_cache()
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -593,6 +690,8 @@ def main():
                                if copy_gbs else None),
         "adjoint_forward_ratio": None,
     }
+    if ec_branch is not None:
+        out["ec_log_branch"] = ec_branch
     if not args.no_adjoint:
         adj = adjoint_ratio(dgsem, inputs, torch)
         out["adjoint_forward_ratio"] = adj["value"]
@@ -607,7 +706,8 @@ def main():
         out["general_mesh"] = general_mesh_bench(dgsem, inputs, torch, wl, 5, value)
         if not args.no_adjoint:
             out["general_mesh"]["adjoint"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, general=True)
-    if (not args.no_mortar or not args.no_fv or not args.no_adjoint_roofline or args.order_study) and not freed:
+    if (not args.no_mortar or not args.no_fv or not args.no_weak or not args.no_adjoint_roofline or
+            args.order_study) and not freed:
         del S, U, R, spare, cur, nxt
         freed = True
     torch.cuda.empty_cache()
@@ -623,6 +723,9 @@ def main():
     if not args.no_fv:
         out["fv"] = fv_bench(dgsem, inputs, torch, 5)
         torch.cuda.empty_cache()
+    if not args.no_weak:
+        out["weak_form"] = weak_form_bench(dgsem, inputs, torch)
+        torch.cuda.empty_cache()
     if args.order_study:
         out["element_order"] = order_bench(dgsem, inputs, torch, wl, 5, value)
     if not args.no_cpu:
@@ -630,6 +733,7 @@ def main():
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["pid_core_s"] = cb["pid_core_s"]
         out["cpu_baseline"]["pid_1thread_s"] = cb["pid_1thread_s"]
+        out["cpu_baseline"]["configs"] = cb["configs"]
     print(json.dumps(out))
 
 

@@ -603,7 +603,7 @@ int mortar_dispatch(dg_handle *h, const double *U, const double *G, bool flux) {
 }
 
 // the hybrid DG/FV kernels: what 0 the faces touching FV elements, 1 the FV elements' operator,
-// 2 the indicator (3: with switching) in place on U
+// 2 the indicator (3: with switching) in place on U, 4 the work lists from the element types
 int fv_dispatch(dg_handle *h, int what, const double *U, double *out, double *R, double a, double b, double dt,
                 int mode) {
   const dg::Geo g = h->geo();
@@ -613,6 +613,7 @@ int fv_dispatch(dg_handle *h, int what, const double *U, double *out, double *R,
   case NN:                                                                                                    \
     if (what == 0) return dg::launch_fv_face<NN>(g, h->ph, h->fvg, lgl, U, h->stream);                      \
     if (what == 1) return dg::launch_fv_volume<NN>(g, h->ph, h->fvg, U, out, R, a, b, dt, mode, h->stream); \
+    if (what == 4) return dg::launch_fv_lists<NN>(g, h->fvg, h->stream);                                    \
     return dg::launch_fv_switch<NN>(g, h->ph, h->fvg, const_cast<double *>(U), what == 3, h->stream);
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
@@ -1301,6 +1302,9 @@ int dg_fv_enable(dg_handle *h, int limiter, double ind_lo, double ind_hi) {
     if (!rc) rc = dev_alloc(&h->d_fvDx, (size_t)K * 30 * n2);
     if (!rc) rc = dev_alloc(&h->d_fvind, (size_t)K);
     if (!rc) rc = dev_alloc(&h->d_fvflag, (size_t)K);
+    if (!rc) rc = dev_alloc(&h->d_fvlist, (size_t)K);
+    if (!rc) rc = dev_alloc(&h->d_fvfaces, (size_t)3 * K);
+    if (!rc) rc = dev_alloc(&h->d_fvcount, (size_t)2);
     if (rc) return fail(h, rc, "allocation of the finite-volume tables failed");
     bool ok = hipMemcpy(h->d_fvtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(h->d_fvJbar, Jbar.data(), Jbar.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
@@ -1310,8 +1314,13 @@ int dg_fv_enable(dg_handle *h, int limiter, double ind_lo, double ind_hi) {
     h->fvg.V = h->d_fvtab; h->fvg.Vi = h->d_fvtab + n * n; h->fvg.Li = h->d_fvtab + 2 * n * n;
     h->fvg.Jbar = h->d_fvJbar; h->fvg.Nf = h->d_fvNf; h->fvg.flag = h->d_fvflag;
     h->fvg.Fx = h->d_fvFx; h->fvg.Dx = h->d_fvDx; h->fvg.ind = h->d_fvind;
+    h->fvg.list = h->d_fvlist; h->fvg.faces = h->d_fvfaces; h->fvg.count = h->d_fvcount;
     h->fvg.w = (double)w;
     h->fv_on = true;
+    // every element DG: empty work lists
+    rc = fv_dispatch(h, 4, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+    if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = DG_ERR_HIP;
+    if (rc) return fail(h, rc, "the finite-volume work lists failed");
   }
   h->fvg.limiter = limiter;
   h->fvg.lo = ind_lo;
@@ -1325,9 +1334,11 @@ int dg_fv_set_types(dg_handle *h, const uint8_t *types) {
   std::vector<uint8_t> t(types, types + h->K);
   for (uint8_t &c : t)
     if (c > 1) return fail(h, DG_ERR_ARG, "element types are 0 (DG) or 1 (finite volume)");
-  if (hipMemcpyAsync(h->d_fvflag, t.data(), t.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      hipStreamSynchronize(h->stream) != hipSuccess)
+  if (hipMemcpyAsync(h->d_fvflag, t.data(), t.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess)
     return fail(h, DG_ERR_HIP, "copy of the element types failed");
+  const int rc = fv_dispatch(h, 4, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+  if (rc) return fail(h, rc, "the finite-volume work lists failed");
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, DG_ERR_HIP, "copy of the element types failed");
   return DG_OK;
 }
 
@@ -1360,6 +1371,8 @@ int dg_fv_switch(dg_handle *h, double *U) {
   if (rc) return rc;
   rc = fv_dispatch(h, 3, U, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
   if (rc) return fail(h, rc, "launch of the indicator failed");
+  rc = fv_dispatch(h, 4, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, 0);
+  if (rc) return fail(h, rc, "the finite-volume work lists failed");
   return DG_OK;
 }
 
@@ -1374,6 +1387,7 @@ void dg_destroy(dg_handle *h) {
   (void)hipFree(h->d_mg);
   (void)hipFree(h->d_fvtab); (void)hipFree(h->d_fvJbar); (void)hipFree(h->d_fvNf); (void)hipFree(h->d_fvFx);
   (void)hipFree(h->d_fvDx); (void)hipFree(h->d_fvind); (void)hipFree(h->d_fvflag);
+  (void)hipFree(h->d_fvlist); (void)hipFree(h->d_fvfaces); (void)hipFree(h->d_fvcount);
   delete h;
 }
 

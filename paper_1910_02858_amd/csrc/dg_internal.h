@@ -71,6 +71,9 @@ struct FvGeo {
   double *Fx;                 // [K][6][5][n^2] outward flux of sides of faces touching an FV element
   double *Dx;                 // [K][6][5][n^2] the neighbour's face datum at those sides (conservative)
   double *ind;                // [K] last troubled-cell indicator
+  int *list;                  // [K] the finite-volume elements (count[0] of them), any order
+  int *faces;                 // [3K] master sides e*6+s of faces touching one (count[1]), any order
+  int *count;                 // [2]
   int limiter;                // 0 first order, 1 minmod, 2 van Leer
   double w;                   // subcell width 2/(N+1)
   double lo, hi;              // switch to DG below lo, to FV above hi
@@ -111,6 +114,8 @@ int launch_fv_volume(const Geo &g, const Phys &ph, const FvGeo &f, const double 
                      double b, double dt, int mode, hipStream_t st);
 template <int N>
 int launch_fv_switch(const Geo &g, const Phys &ph, const FvGeo &f, double *U, int do_switch, hipStream_t st);
+template <int N>
+int launch_fv_lists(const Geo &g, const FvGeo &f, hipStream_t st);
 // non-conforming faces: the lifting's surface terms (before the lifting) and the numerical fluxes
 // (after it) of every mortar's small and big sides, into Geo::mlift and Geo::mflux
 template <int N>
@@ -227,6 +232,9 @@ struct dg_handle {
   double *d_fvtab = nullptr, *d_fvJbar = nullptr, *d_fvNf = nullptr, *d_fvFx = nullptr, *d_fvDx = nullptr;
   double *d_fvind = nullptr;
   uint8_t *d_fvflag = nullptr;
+  int *d_fvlist = nullptr;  // work lists of the hybrid kernels: [K] elements, [3K] sides, [2] counts
+  int *d_fvfaces = nullptr;
+  int *d_fvcount = nullptr;
   double *d_mflux = nullptr, *d_mlift = nullptr, *d_mg = nullptr;  // [slots][5|12|12][n^2]
   bool has_boundary = false;    // some side has no neighbour
   bool needs_state = false;     // some boundary side takes the given outer state

@@ -237,6 +237,40 @@ __device__ __forceinline__ void riemann(const Phys &ph, const double *UL, const 
   for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
 }
 
+// riemann() with the solver fixed at compile time (RS = ph.rs)
+template <int RS>
+__device__ __forceinline__ void riemann_t(const Phys &ph, const double *UL, const double *UR, const double *nh,
+                                          double *F) {
+  const double gm1 = ph.gamma - 1.0;
+  const Pr5 L = to_prim(UL, gm1), R = to_prim(UR, gm1);
+  if (RS >= 2) {
+    flux_2pt(ph.vf, UL, L, UR, R, nh, gm1, F);
+    if (RS == 3) {
+      double D[5];
+      roe_diss(UL, L, UR, R, nh, gm1, D);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[v] -= 0.5 * D[v];
+    }
+    return;
+  }
+  double FL[5], FR[5];
+  flux_c(UL, L, nh, FL);
+  flux_c(UR, R, nh, FR);
+  if (RS == 0) {
+    const double cL = sqrt(ph.gamma * L.p / L.rho), cR = sqrt(ph.gamma * R.p / R.rho);
+    const double unL = L.u * nh[0] + L.v * nh[1] + L.w * nh[2];
+    const double unR = R.u * nh[0] + R.v * nh[1] + R.w * nh[2];
+    const double lam = fmax(fabs(unL) + cL, fabs(unR) + cR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
+    return;
+  }
+  double D[5];
+  roe_diss(UL, L, UR, R, nh, gm1, D);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
 // numerical flux of the split-form kernel: as riemann(), with the two-point variants (rs 2, 3)
 // evaluated by the volume flux VF of the kernel (pair2, defined below)
 template <int VF>
@@ -1785,121 +1819,173 @@ __device__ __forceinline__ void fv_recon(const double *__restrict__ U, const FvG
   fv_cons(Wf, gm1, Uf);
 }
 
-// One workgroup per side (6K); the master side of every face that touches a finite-volume element
-// evaluates the numerical flux at the (N+1)^2 subfaces (the DG side's trace taken to subface means
-// with V in both face directions, the FV side reconstructed), writes both sides' outward fluxes
-// (DG side: back to its face nodes with V^-1) and both sides' view of the other's face datum.
+// (M x M) applied at face point (a,b) of a face field T[v][ia + n jb] (5 fields): sum over jb of
+// M[b][jb] (sum over ia of M[a][ia] T[ia + n jb])
+template <int n>
+__device__ __forceinline__ void face_mm(const double *M, int a, int b, const double *T, double *out) {
+  constexpr int n2 = n * n;
+  double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int jb = 0; jb < n; ++jb) {
+    double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ia = 0; ia < n; ++ia) {
+      const double m = M[a * n + ia];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) c[v] += m * T[v * n2 + ia + n * jb];
+    }
+    const double m2 = M[b * n + jb];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] += m2 * c[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v] = r[v];
+}
+
+// Work lists of the hybrid operator, rebuilt whenever the element types change: the finite-volume
+// elements (count[0] of them in list) and the master sides e*6+s of the faces that touch one
+// (count[1] in faces).  The order of either list is arbitrary: every item writes only its own
+// outputs.
+template <int N> __global__ void k_fv_lists_zero(FvGeo f) {
+  if (threadIdx.x == 0) { f.count[0] = 0; f.count[1] = 0; }
+}
+
+template <int N, bool GEN>
+__global__ void __launch_bounds__(256) k_fv_lists(Geo g, FvGeo f) {
+  constexpr int n = N + 1;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= 6 * g.K) return;
+  const int e = q / 6, s = q - 6 * e;
+  if (s == 0 && f.flag[e]) f.list[atomicAdd(&f.count[0], 1)] = e;
+  const int nb = g.nbr[q];
+  if (nb < 0) return;
+  const NbFace f0 = nbr_face<n, GEN>(g, e, s, 0, 0);
+  if (f0.master && (f.flag[e] || f.flag[nb])) f.faces[atomicAdd(&f.count[1], 1)] = q;
+}
+
+template <int N> struct FvFaceSz {
+  static constexpr int NT = ((N + 1) * (N + 1) + 63) / 64 * 64;  // threads: one face point each
+};
+
+// Faces that touch a finite-volume element, one workgroup per face of the work list (looping over
+// it): the numerical flux at the (N+1)^2 subfaces from both sides' face data (the DG side's trace
+// taken to subface means with V in both face directions, the FV side reconstructed); writes both
+// sides' outward fluxes (a DG side's back to its face nodes with V^-1) and both sides' view of the
+// other's face datum.
 template <int N, bool LGL, bool GEN>
-__global__ void __launch_bounds__(((N + 1) * (N + 1) + 63) / 64 * 64) k_fv_face(Geo g, Phys ph, FvGeo f,
-                                                                              const double *__restrict__ U) {
+__global__ void __launch_bounds__(FvFaceSz<N>::NT) k_fv_face(Geo g, Phys ph, FvGeo f, const double *__restrict__ U) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
   __shared__ double sV[n * n], sVi[n * n];
   __shared__ double sTe[5 * n2], sTn[5 * n2];  // DG traces (own / neighbour face coordinates)
   __shared__ double sFe[5 * n2], sFn[5 * n2];  // outward subface fluxes of both sides
-  const int e = blockIdx.x / 6, s = blockIdx.x - 6 * (blockIdx.x / 6), t = threadIdx.x;
-  const NbFace f0 = nbr_face<n, GEN>(g, e, s, 0, 0);
-  if (!f0.master) return;
-  const int nb = g.nbr[(size_t)e * 6 + s], ns = GEN ? 2 * f0.dn + (f0.plus ? 1 : 0) : (s ^ 1);
-  const bool fe = f.flag[e], fn = f.flag[nb];
-  if (!fe && !fn) return;
+  const int t = threadIdx.x;
   for (int c = t; c < n * n; c += blockDim.x) { sV[c] = f.V[c]; sVi[c] = f.Vi[c]; }
+  const int nf = f.count[1];
   const double gm1 = ph.gamma - 1.0;
   const Tab *tb = g.tab;
-  const int a = t % n, b = t / n;
-  NbFace fm;
-  if (t < n2) {
-    fm = nbr_face<n, GEN>(g, e, s, a, b);
-    double tr[5];
-    if (!fe) {
-      face_trace<n, LGL>(U, 5, e, s, a, b, tb->lm, tb->lp, tr);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sTe[v * n2 + t] = tr[v];
-    }
-    if (!fn) {
-      face_trace<n, LGL>(U, 5, nb, ns, fm.a, fm.b, tb->lm, tb->lp, tr);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sTn[v * n2 + fm.a + n * fm.b] = tr[v];
-    }
-  }
-  __syncthreads();
-  if (t < n2) {
+  const bool pt = t < n2;
+  const int a = pt ? t % n : 0, b = pt ? t / n : 0;
+  for (int it = blockIdx.x; it < nf; it += gridDim.x) {
+    const int q = f.faces[it], e = q / 6, s = q - 6 * e;
+    const int nb = g.nbr[q];
+    const NbFace fm = nbr_face<n, GEN>(g, e, s, a, b);
+    const int ns = GEN ? 2 * fm.dn + (fm.plus ? 1 : 0) : (s ^ 1);
     const int a2 = fm.a, b2 = fm.b;
-    double De[5], Dn[5], Ue[5], Un[5];
-    // face data: adjacent subcell (FV) or the subface mean of the trace (DG)
-    for (int side = 0; side < 2; ++side) {
-      const bool isfv = side ? fn : fe;
-      const int ee = side ? nb : e, ss = side ? ns : s, aa = side ? a2 : a, bb = side ? b2 : b;
-      double *D = side ? Dn : De;
-      const double *sT = side ? sTn : sTe;
-      if (isfv) {
-        const int q = line_node<n>(ss >> 1, aa, bb, (ss & 1) ? n - 1 : 0);
+    const bool fe = f.flag[e], fn = f.flag[nb];
+    __syncthreads();  // the previous face's reads of the LDS fields are done
+    if (pt) {
+      double tr[5];
+      if (!fe) {
+        face_trace<n, LGL>(U, 5, e, s, a, b, tb->lm, tb->lp, tr);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) D[v] = U[((size_t)ee * 5 + v) * n3 + q];
-      } else {
+        for (int v = 0; v < 5; ++v) sTe[v * n2 + t] = tr[v];
+      }
+      if (!fn) {
+        face_trace<n, LGL>(U, 5, nb, ns, a2, b2, tb->lm, tb->lp, tr);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) D[v] = 0.0;
-        for (int jb = 0; jb < n; ++jb)
-          for (int ia = 0; ia < n; ++ia) {
-            const double c = sV[aa * n + ia] * sV[bb * n + jb];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) D[v] += c * sT[v * n2 + ia + n * jb];
-          }
+        for (int v = 0; v < 5; ++v) sTn[v * n2 + a2 + n * b2] = tr[v];
       }
     }
-    double *dxe = f.Dx + ((size_t)e * 6 + s) * 5 * n2 + t;
-    double *dxn = f.Dx + ((size_t)nb * 6 + ns) * 5 * n2 + a2 + n * b2;
+    __syncthreads();
+    if (pt) {
+      // face data: the adjacent subcell (FV) or the subface mean of the trace (DG)
+      double De[5], Dn[5], Ue[5], Un[5];
+      if (fe) {
+        const int qe = line_node<n>(s >> 1, a, b, (s & 1) ? n - 1 : 0);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) { dxe[v * n2] = Dn[v]; dxn[v * n2] = De[v]; }
-    if (fe) fv_recon<n>(U, f, gm1, e, s, a, b, Dn, Ue);
-    else for (int v = 0; v < 5; ++v) Ue[v] = De[v];
-    if (fn) fv_recon<n>(U, f, gm1, nb, ns, a2, b2, De, Un);
-    else for (int v = 0; v < 5; ++v) Un[v] = Dn[v];
-    // the master's (this side's) face-mean metric, outward
-    const bool plus = s & 1;
-    const double *Nm = f.Nf + ((((size_t)e * 3 + (s >> 1)) * (n + 1) + (plus ? n : 0)) * n2 + t) * 3;
-    const double sgn = plus ? 1.0 : -1.0;
-    const double nt[3] = {sgn * Nm[0], sgn * Nm[1], sgn * Nm[2]};
-    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
-    const double ish = 1.0 / sh;
-    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
-    double F[5];
-    riemann(ph, Ue, Un, nh, F);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      sFe[v * n2 + t] = sh * F[v];
-      sFn[v * n2 + a2 + n * b2] = -(sh * F[v]);
-    }
-  }
-  __syncthreads();
-  if (t < n2) {
-    // thread t writes point t of either side (own face coordinates of that side)
-    for (int side = 0; side < 2; ++side) {
-      const bool isfv = side ? fn : fe;
-      const int ee = side ? nb : e, ss = side ? ns : s;
-      const double *sF = side ? sFn : sFe;
-      double *fx = f.Fx + ((size_t)ee * 6 + ss) * 5 * n2 + t;
-      if (isfv) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fx[v * n2] = sF[v * n2 + t];
+        for (int v = 0; v < 5; ++v) De[v] = U[((size_t)e * 5 + v) * n3 + qe];
       } else {
-        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int jb = 0; jb < n; ++jb)
-          for (int ia = 0; ia < n; ++ia) {
-            const double c = sVi[a * n + ia] * sVi[b * n + jb];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) acc[v] += c * sF[v * n2 + ia + n * jb];
-          }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fx[v * n2] = acc[v];
+        face_mm<n>(sV, a, b, sTe, De);
       }
+      if (fn) {
+        const int qn = line_node<n>(ns >> 1, a2, b2, (ns & 1) ? n - 1 : 0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Dn[v] = U[((size_t)nb * 5 + v) * n3 + qn];
+      } else {
+        face_mm<n>(sV, a2, b2, sTn, Dn);
+      }
+      double *dxe = f.Dx + ((size_t)e * 6 + s) * 5 * n2 + t;
+      double *dxn = f.Dx + ((size_t)nb * 6 + ns) * 5 * n2 + a2 + n * b2;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { dxe[v * n2] = Dn[v]; dxn[v * n2] = De[v]; }
+      if (fe) {
+        fv_recon<n>(U, f, gm1, e, s, a, b, Dn, Ue);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Ue[v] = De[v];
+      }
+      if (fn) {
+        fv_recon<n>(U, f, gm1, nb, ns, a2, b2, De, Un);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Un[v] = Dn[v];
+      }
+      // the master's (this side's) face-mean metric, outward
+      const bool plus = s & 1;
+      const double *Nm = f.Nf + ((((size_t)e * 3 + (s >> 1)) * (n + 1) + (plus ? n : 0)) * n2 + t) * 3;
+      const double sgn = plus ? 1.0 : -1.0;
+      const double nt[3] = {sgn * Nm[0], sgn * Nm[1], sgn * Nm[2]};
+      const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+      const double ish = 1.0 / sh;
+      const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+      double F[5];
+      riemann(ph, Ue, Un, nh, F);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        sFe[v * n2 + t] = sh * F[v];
+        sFn[v * n2 + a2 + n * b2] = -(sh * F[v]);
+      }
+    }
+    __syncthreads();
+    if (pt) {
+      // thread t writes point t of either side (in that side's own face coordinates)
+      double o[5];
+      double *fx = f.Fx + ((size_t)e * 6 + s) * 5 * n2 + t;
+      if (fe) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) o[v] = sFe[v * n2 + t];
+      } else {
+        face_mm<n>(sVi, a, b, sFe, o);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) fx[v * n2] = o[v];
+      fx = f.Fx + ((size_t)nb * 6 + ns) * 5 * n2 + t;
+      if (fn) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) o[v] = sFn[v * n2 + t];
+      } else {
+        face_mm<n>(sVi, a, b, sFn, o);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) fx[v * n2] = o[v];
     }
   }
 }
 
-// the finite-volume elements' operator: reconstruction, inner subcell fluxes, element-face fluxes
-// from Fx, -1/(w Jbar), optional fused RK stage (MODE 1)
-template <int N, int MODE>
-__global__ void __launch_bounds__(Sz<N>::NT) k_fv_volume(Geo g, Phys ph, FvGeo f, const double *__restrict__ U,
+// Finite-volume elements of the work list, one workgroup per element (looping over the list):
+// second-order subcell update, eq. fv_dof_time_derivative.
+template <int N, int MODE, int RS>
+__global__ void __launch_bounds__(Sz<N>::NT, 4) k_fv_volume(Geo g, Phys ph, FvGeo f, const double *__restrict__ U,
                                                          double *__restrict__ out, double *__restrict__ R, double ca,
                                                          double cb, double dt) {
   using S = Sz<N>;
@@ -1907,101 +1993,105 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_volume(Geo g, Phys ph, FvGeo f
   __shared__ double sW[5 * n3];   // primitive subcell means
   __shared__ double sL[5 * n3];   // reconstructed state at each subcell's +face (then its flux)
   __shared__ double sR[5 * n3];   // reconstructed state at each subcell's -face
-  const int e = blockIdx.x, t = threadIdx.x;
-  if (!f.flag[e]) return;
+  const int t = threadIdx.x;
   const bool act = t < n3;
   const double gm1 = ph.gamma - 1.0;
-  double Uo[5];
-  if (act) {
-    double W[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Uo[v] = U[((size_t)e * 5 + v) * n3 + t];
-    fv_prim(Uo, gm1, W);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sW[v * n3 + t] = W[v];
-  }
-  const int id3[3] = {t % n, (t / n) % n, t / n2};
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int dir = 0; dir < 3; ++dir) {
-    __syncthreads();
-    const int id = act ? id3[dir] : 0;
-    const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
-    const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
-    const int ab = a + n * b;
+  const int nfv = f.count[0];
+  for (int it = blockIdx.x; it < nfv; it += gridDim.x) {
+    const int e = f.list[it];
+    __syncthreads();  // the previous element's reads of the LDS fields are done
     if (act) {
-      double Wl[5], Wr[5];
-      if (id > 0) {
-        for (int v = 0; v < 5; ++v) Wl[v] = sW[v * n3 + t - str];
-      } else {
-        double Do[5];
-        const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
-        for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
-        fv_prim(Do, gm1, Wl);
-      }
-      if (id < N) {
-        for (int v = 0; v < 5; ++v) Wr[v] = sW[v * n3 + t + str];
-      } else {
-        double Do[5];
-        const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
-        for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
-        fv_prim(Do, gm1, Wr);
-      }
+      double Uo[5], W[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double w0 = sW[v * n3 + t];
-        const double sg = fv_limit(f.limiter, w0 - Wl[v], Wr[v] - w0);
-        sL[v * n3 + t] = w0 + 0.5 * sg;
-        sR[v * n3 + t] = w0 - 0.5 * sg;
+      for (int v = 0; v < 5; ++v) Uo[v] = U[((size_t)e * 5 + v) * n3 + t];
+      fv_prim(Uo, gm1, W);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sW[v * n3 + t] = W[v];
+    }
+    const int id3[3] = {t % n, (t / n) % n, t / n2};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int dir = 0; dir < 3; ++dir) {
+      __syncthreads();
+      const int id = act ? id3[dir] : 0;
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
+      const int ab = a + n * b;
+      if (act) {
+        double Wl[5], Wr[5];
+        if (id > 0) {
+          for (int v = 0; v < 5; ++v) Wl[v] = sW[v * n3 + t - str];
+        } else {
+          double Do[5];
+          const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
+          for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
+          fv_prim(Do, gm1, Wl);
+        }
+        if (id < N) {
+          for (int v = 0; v < 5; ++v) Wr[v] = sW[v * n3 + t + str];
+        } else {
+          double Do[5];
+          const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+          for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
+          fv_prim(Do, gm1, Wr);
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double w0 = sW[v * n3 + t];
+          const double sg = fv_limit(f.limiter, w0 - Wl[v], Wr[v] - w0);
+          sL[v * n3 + t] = w0 + 0.5 * sg;
+          sR[v * n3 + t] = w0 - 0.5 * sg;
+        }
+      }
+      __syncthreads();
+      if (act && id < N) {
+        // inner face id + 1/2 between this subcell and the next along dir
+        double WL[5], WR[5], UL[5], UR[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) { WL[v] = sL[v * n3 + t]; WR[v] = sR[v * n3 + t + str]; }
+        fv_cons(WL, gm1, UL);
+        fv_cons(WR, gm1, UR);
+        const double *Nm = f.Nf + ((((size_t)e * 3 + dir) * (n + 1) + id + 1) * n2 + ab) * 3;
+        const double sh = sqrt(Nm[0] * Nm[0] + Nm[1] * Nm[1] + Nm[2] * Nm[2]);
+        const double ish = 1.0 / sh;
+        const double nh[3] = {Nm[0] * ish, Nm[1] * ish, Nm[2] * ish};
+        double F[5];
+        riemann_t<RS>(ph, UL, UR, nh, F);
+        // the flux replaces this subcell's +face state in sL (no other thread reads that slot
+        // in this phase); it is the subcell's outward flux on its + face
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double fp = sh * F[v];
+          sL[v * n3 + t] = fp;
+          acc[v] += fp;
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const double *fx0 = f.Fx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
+        const double *fx1 = f.Fx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          // outward fluxes of the subcell: + face (above for inner faces), then - face
+          if (id == N) acc[v] += fx1[v * n2];
+          acc[v] += (id > 0) ? -sL[v * n3 + t - str] : fx0[v * n2];
+        }
       }
     }
-    __syncthreads();
-    double Fp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (act && id < N) {
-      // inner face id + 1/2 between this subcell and the next along dir
-      double WL[5], WR[5], UL[5], UR[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) { WL[v] = sL[v * n3 + t]; WR[v] = sR[v * n3 + t + str]; }
-      fv_cons(WL, gm1, UL);
-      fv_cons(WR, gm1, UR);
-      const double *Nm = f.Nf + ((((size_t)e * 3 + dir) * (n + 1) + id + 1) * n2 + ab) * 3;
-      const double sh = sqrt(Nm[0] * Nm[0] + Nm[1] * Nm[1] + Nm[2] * Nm[2]);
-      const double ish = 1.0 / sh;
-      const double nh[3] = {Nm[0] * ish, Nm[1] * ish, Nm[2] * ish};
-      double F[5];
-      riemann(ph, UL, UR, nh, F);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Fp[v] = sh * F[v];
-    }
-    __syncthreads();  // sL is reused for the fluxes
-    if (act && id < N) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sL[v * n3 + t] = Fp[v];
-    }
-    __syncthreads();
     if (act) {
-      const double *fx0 = f.Fx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
-      const double *fx1 = f.Fx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+      const double iwj = 1.0 / (f.w * f.Jbar[(size_t)e * n3 + t]);
+      double *Oe = out + (size_t)e * 5 * n3;
+      if (MODE == 0) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        // outward fluxes of the subcell: + face, then - face
-        acc[v] += (id < N) ? Fp[v] : fx1[v * n2];
-        acc[v] += (id > 0) ? -sL[v * n3 + t - str] : fx0[v * n2];
-      }
-    }
-  }
-  if (act) {
-    const double iwj = 1.0 / (f.w * f.Jbar[(size_t)e * n3 + t]);
-    double *Oe = out + (size_t)e * 5 * n3;
-    if (MODE == 0) {
+        for (int v = 0; v < 5; ++v) Oe[v * n3 + t] = -acc[v] * iwj;
+      } else {
+        double *Re = R + (size_t)e * 5 * n3;
+        const double *Ue = U + (size_t)e * 5 * n3;  // read again (from L2) rather than held
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Oe[v * n3 + t] = -acc[v] * iwj;
-    } else {
-      double *Re = R + (size_t)e * 5 * n3;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * (-acc[v] * iwj);
-        Re[v * n3 + t] = r;
-        Oe[v * n3 + t] = Uo[v] + cb * r;
+        for (int v = 0; v < 5; ++v) {
+          const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * (-acc[v] * iwj);
+          Re[v * n3 + t] = r;
+          Oe[v * n3 + t] = Ue[v * n3 + t] + cb * r;
+        }
       }
     }
   }
@@ -2047,7 +2137,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
   constexpr int n = S::n, n3 = S::n3;
   __shared__ double sX[5 * n3], sY[5 * n3], sU[5 * n3];
   __shared__ double sA[3 * n * n];  // V, Vi, Li
-  __shared__ double sE[n];
+  __shared__ double sE[3 * (Sz<N>::NT / 64)];
   __shared__ int sNew;
   const int e = blockIdx.x, t = threadIdx.x;
   const bool act = t < n3;
@@ -2072,22 +2162,33 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
   }
   __syncthreads();
   fv_tensor3<n>(sA + 2 * n * n, sX, sY, t, act);  // modal coefficients (field 0)
-  if (t < n) {
-    // energy of the modes whose largest index is t, summed in node order
-    double s = 0.0;
-    for (int q = 0; q < n3; ++q) {
-      const int i = q % n, j = (q / n) % n, k = q / (n * n);
+  {
+    // energies: of all modes, of those whose largest index is N, of those whose largest index is
+    // N-1; summed per wave by a fixed butterfly, then over the waves in order
+    double E3[3] = {0.0, 0.0, 0.0};
+    if (act) {
+      const int i = t % n, j = (t / n) % n, k = t / (n * n);
       const int m = i > j ? (i > k ? i : k) : (j > k ? j : k);
-      if (m == t) s += sX[q] * sX[q];
+      const double c2 = sX[t] * sX[t];
+      E3[0] = c2;
+      E3[1] = m == N ? c2 : 0.0;
+      E3[2] = m == N - 1 ? c2 : 0.0;
     }
-    sE[t] = s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) E3[c] += __shfl_xor(E3[c], off, 64);
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sE[3 * (t >> 6) + c] = E3[c];
+    }
   }
   __syncthreads();
   if (t == 0) {
-    double tot = 0.0;
-    for (int m = 0; m < n; ++m) tot += sE[m];
-    const double r1 = sE[N] / fmax(tot, 1e-300);
-    const double r2 = sE[N - 1] / fmax(tot - sE[N], 1e-300);
+    double tot = 0.0, eN = 0.0, eN1 = 0.0;
+    for (int w = 0; w < Sz<N>::NT / 64; ++w) { tot += sE[3 * w]; eN += sE[3 * w + 1]; eN1 += sE[3 * w + 2]; }
+    const double r1 = eN / fmax(tot, 1e-300);
+    const double r2 = eN1 / fmax(tot - eN, 1e-300);
     const double ind = log10(fmax(fmax(r1, r2), 1e-300));
     f.ind[e] = ind;
     int nw = isfv ? 1 : 0;
@@ -2272,8 +2373,7 @@ int launch_batch_split(const BatchView &bv, bool ns, int vf, int epb, hipStream_
 
 template <int N>
 int launch_fv_face(const Geo &g, const Phys &ph, const FvGeo &f, bool lgl, const double *U, hipStream_t st) {
-  constexpr int nt = ((N + 1) * (N + 1) + 63) / 64 * 64;
-  const dim3 grid(6 * g.K), block(nt);
+  const dim3 grid(std::min(3 * g.K, 4096)), block(FvFaceSz<N>::NT);
   const bool gen = g.fc != nullptr;
   if (lgl && gen) hipLaunchKernelGGL((k_fv_face<N, true, true>), grid, block, 0, st, g, ph, f, U);
   else if (lgl) hipLaunchKernelGGL((k_fv_face<N, true, false>), grid, block, 0, st, g, ph, f, U);
@@ -2286,8 +2386,24 @@ int launch_fv_face(const Geo &g, const Phys &ph, const FvGeo &f, bool lgl, const
 template <int N>
 int launch_fv_volume(const Geo &g, const Phys &ph, const FvGeo &f, const double *U, double *out, double *R, double a,
                      double b, double dt, int mode, hipStream_t st) {
-  if (mode == 0) hipLaunchKernelGGL((k_fv_volume<N, 0>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, f, U, out, R, a, b, dt);
-  else hipLaunchKernelGGL((k_fv_volume<N, 1>), dim3(g.K), dim3(Sz<N>::NT), 0, st, g, ph, f, U, out, R, a, b, dt);
+  const dim3 grid(std::min(g.K, 1024)), block(Sz<N>::NT);
+#define DG_FVV(RS)                                                                                       \
+  if (ph.rs == RS) {                                                                                     \
+    if (mode == 0) hipLaunchKernelGGL((k_fv_volume<N, 0, RS>), grid, block, 0, st, g, ph, f, U, out, R, a, b, dt); \
+    else hipLaunchKernelGGL((k_fv_volume<N, 1, RS>), grid, block, 0, st, g, ph, f, U, out, R, a, b, dt);           \
+  }
+  DG_FVV(0) DG_FVV(1) DG_FVV(2) DG_FVV(3)
+#undef DG_FVV
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
+int launch_fv_lists(const Geo &g, const FvGeo &f, hipStream_t st) {
+  hipLaunchKernelGGL(k_fv_lists_zero<N>, dim3(1), dim3(64), 0, st, f);
+  const dim3 grid((6 * g.K + 255) / 256);
+  if (g.fc) hipLaunchKernelGGL((k_fv_lists<N, true>), grid, dim3(256), 0, st, g, f);
+  else hipLaunchKernelGGL((k_fv_lists<N, false>), grid, dim3(256), 0, st, g, f);
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -2420,6 +2536,7 @@ template int launch_fv_face<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &,
 template int launch_fv_volume<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &, const double *, double *, double *,
                                          double, double, double, int, hipStream_t);
 template int launch_fv_switch<DG_ONLY_N>(const Geo &, const Phys &, const FvGeo &, double *, int, hipStream_t);
+template int launch_fv_lists<DG_ONLY_N>(const Geo &, const FvGeo &, hipStream_t);
 template int launch_mortar_flux<DG_ONLY_N>(const Geo &, const Phys &, bool, int, const MortarDesc *, int,
                                            const double *, const double *, hipStream_t);
 template int launch_batch_lift<DG_ONLY_N>(const BatchView &, int, hipStream_t);
