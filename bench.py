@@ -189,8 +189,10 @@ def adjoint_ratio(dgsem, inputs, torch, repeats: int = 2, general: bool = False,
 def ensemble_bench(dgsem, inputs, torch, steps: int = 10, n_members: int = 256):
     """Seeded ensemble of uneven members (K1 ~ U{4..12}, N ~ U{3..7}, amplitude and Mach drawn per
     member; split KEP + Roe + BR1, TGV): DOF updates per second of whole RK steps for
-    (a) the batched step replayed as one HIP graph, (b) the batched stages launched eagerly and
-    (c) every member advanced with its own one-mesh launches, all on the same GPU."""
+    (a) the batched step replayed as one HIP graph, with one lifting and one operator launch per
+    stage for all degrees (fused) and with one pair per degree, (b) the batched stages launched
+    eagerly and (c) every member advanced with its own one-mesh launches, all on the same GPU;
+    ``batched_graph`` is the launch mode the tuner chose."""
     wls = inputs.ensemble_draw(n_members, 0)
     sols, U0s = [], []
     for wl in wls:
@@ -220,9 +222,22 @@ def ensemble_bench(dgsem, inputs, torch, steps: int = 10, n_members: int = 256):
                     S.rk_stage(u, o, R, a[s], b[s], dt)
                 cur, nxt = nxt, cur
 
-    out = {"members": len(sols), "dof": dof, "steps": steps, "tiles": [list(t) for t in tiles]}
-    for name, fn in (("batched_graph", lambda k: batched(k, True)), ("batched_eager", lambda k: batched(k, False)),
-                     ("per_member_launches", unbatched)):
+    chosen = B.fused
+    out = {"members": len(sols), "dof": dof, "steps": steps, "tiles": [list(t) for t in tiles],
+           "launch": "fused" if chosen else "per_degree"}
+
+    def fused_graph(k):
+        B.fused = True
+        batched(k, True)
+
+    def per_degree_graph(k):
+        B.fused = False
+        batched(k, True)
+
+    for name, fn in (("batched_graph_fused", fused_graph), ("batched_graph_per_degree", per_degree_graph),
+                     ("batched_eager", lambda k: batched(k, False)), ("per_member_launches", unbatched)):
+        if name == "batched_eager":
+            B.fused = chosen
         fn(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -230,6 +245,8 @@ def ensemble_bench(dgsem, inputs, torch, steps: int = 10, n_members: int = 256):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out[name] = dof * 5 * steps / wall
+    B.fused = chosen
+    out["batched_graph"] = out["batched_graph_fused" if chosen else "batched_graph_per_degree"]
     if not all(S.check_finite(u) for S, u in zip(sols, cur)):
         raise RuntimeError("non-finite ensemble state")
     out["speedup_vs_per_member"] = out["batched_graph"] / out["per_member_launches"]
@@ -276,36 +293,45 @@ def ec_branch_bench(S, U_smooth, torch, wl, smooth_main_ms: float, stages: int =
             "slowdown": main_ms / smooth_main_ms, "stages": stages}
 
 
-def weak_form_bench(dgsem, inputs, torch, k: int = 48, stages: int = 10):
-    """The weak form on LG nodes (k_main: the D-hat contraction of the fluxes along every line, LG
-    face prolongation, BR1 gradients): the headline mesh and TGV with Navier-Stokes, central volume
-    flux, Roe; per-kernel times and the operator kernel priced at the same 336 B per node."""
-    wl = inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=k)
-    S, U = dgsem.build_solver(wl)
-    dt = S.timestep(U, wl.cfl, wl.dfl)
-    a, b, _ = dgsem.rk_coefficients()
-    R = torch.zeros_like(U)
-    nxt = S.empty()
-    cur = U
-    for s_ in range(5):  # warm-up
-        S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
-        cur, nxt = nxt, cur
-    S.profile(True)
-    for s_ in range(stages):
-        S.rk_stage(cur, nxt, R, a[s_ % 5], b[s_ % 5], dt)
-        cur, nxt = nxt, cur
-    prof = S.profile_read()
-    S.profile(False)
-    if not S.check_finite(cur):
-        raise RuntimeError("non-finite state in the weak-form measurement")
-    dof = S.K * S.n3
-    main_ms = prof["main_ms"] / max(prof["main_launches"], 1)
-    lift_ms = prof["lift_ms"] / max(prof["lift_launches"], 1)
-    gbs = BYTES_MAIN * dof / (main_ms * 1e-3) / 1e9
-    return {"workload": f"ns_tgv_central_roe_lg7_k{k}_weak", "dof": dof, "kernels_ms": {"main": main_ms, "lift": lift_ms},
-            "value": dof / ((main_ms + lift_ms) * 1e-3),
-            "roofline": {"bound": "hbm", "kernel": "k_main (weak form, LG)", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_dof": BYTES_MAIN}}
+def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
+    """The weak form on LG nodes (k_main: the D-hat contraction of the fluxes along every line and
+    the LG face prolongation): the Euler density-wave scheme at N=3 on 96^3 elements and the
+    Navier-Stokes TGV (central volume flux, Roe, BR1 gradients) at N=7 on 48^3, both 56.6 M nodes;
+    per-kernel times, the operator kernel priced at 336 B per node (Navier-Stokes) or at its
+    Euler reads and writes (U 5, Ja 9, 1/J 1, R 5 read, U_new 5, R 5 written: 240 B)."""
+    out = {}
+    for name, wl, nbytes in (("euler_dwave_lg3_k96_weak", inputs.workload(1, K1=96), 30 * 8),
+                             ("ns_tgv_central_roe_lg7_k48_weak",
+                              inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=48), BYTES_MAIN)):
+        S, U = dgsem.build_solver(wl)
+        dt = S.timestep(U, wl.cfl, wl.dfl)
+        a, b, _ = dgsem.rk_coefficients()
+        R = torch.zeros_like(U)
+        nxt = S.empty()
+        cur = U
+        for s_ in range(5):  # warm-up
+            S.rk_stage(cur, nxt, R, a[s_], b[s_], dt)
+            cur, nxt = nxt, cur
+        S.profile(True)
+        for s_ in range(stages):
+            S.rk_stage(cur, nxt, R, a[s_ % 5], b[s_ % 5], dt)
+            cur, nxt = nxt, cur
+        prof = S.profile_read()
+        S.profile(False)
+        if not S.check_finite(cur):
+            raise RuntimeError("non-finite state in the weak-form measurement")
+        dof = S.K * S.n3
+        main_ms = prof["main_ms"] / max(prof["main_launches"], 1)
+        lift_ms = prof["lift_ms"] / max(prof["lift_launches"], 1) if prof["lift_launches"] else 0.0
+        gbs = nbytes * dof / (main_ms * 1e-3) / 1e9
+        out[name] = {"dof": dof, "kernels_ms": {"main": main_ms, "lift": lift_ms},
+                     "value": dof / ((main_ms + lift_ms) * 1e-3),
+                     "roofline": {"bound": "hbm", "kernel": "k_main (weak form, LG)", "achieved": gbs,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_dof": nbytes}}
+        del S, U, R, nxt, cur
+        torch.cuda.empty_cache()
+    return out
 
 
 def general_mesh_bench(dgsem, inputs, torch, wl, steps: int, structured_value: float):
@@ -553,6 +579,10 @@ def order_bench(dgsem, inputs, torch, wl, steps: int, lexicographic_value: float
     return out
 
 
+# the optional measurements beside the headline, each switched off by --no-<name>
+LEGS = ("cpu", "adjoint", "ensemble", "general", "mortar", "fv", "weak", "ec-branch", "adjoint-roofline")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -576,7 +606,14 @@ def main():
                     help="also time the lattice with random and with Hilbert-curve element numbering")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM counters)")
+    ap.add_argument("--only", choices=LEGS + ("none",), default=None,
+                    help="run the headline and this one extra measurement only (none: the headline only; "
+                         "for profiler runs)")
     args = ap.parse_args()
+    if args.only is not None:
+        for leg in LEGS:
+            if leg != args.only:
+                setattr(args, "no_" + leg.replace("-", "_"), True)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the element decomposition across GPUs is a design, not an implementation)", file=sys.stderr)

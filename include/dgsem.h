@@ -376,7 +376,15 @@ const char *dg_last_error(const dg_handle *h);
  *                     degree) of both kernels of every degree on the states U (read only;
  *                     repeats launches per choice, scratch outputs allocated and freed here) and
  *                     keeps the fastest.  Synchronous.  Without it every choice is 1.
+ *                     Where one launch can cover every degree (all N <= 7, no member with face
+ *                     codes, at most 8 degrees), it then also times one stage of all members
+ *                     with the per-degree launches against one lifting and one operator launch
+ *                     for all degrees (512-lane workgroups of the degree's elements, the
+ *                     largest degree's LDS) and keeps the faster; the results are the same bits.
  * dg_batch_set_tile: fixes the choices of degree N by hand.
+ * dg_batch_set_fused: 1 selects the single pair of launches per stage, 0 the per-degree
+ *                     launches (DG_ERR_UNSUPPORTED where one launch cannot cover every degree).
+ * dg_batch_fused   : the current choice (0 or 1).
  * dg_batch_info    : writes N, members, elements, elements per workgroup of the lifting and of
  *                     the operator kernel for each degree present (5 ints each, up to cap ints)
  *                     and returns the number of degrees. */
@@ -387,6 +395,8 @@ int dg_batch_step(dg_batch *b, double *const *U, double *const *U_out, double *c
                   int use_graph);
 int dg_batch_tune(dg_batch *b, const double *const *U, int repeats);
 int dg_batch_set_tile(dg_batch *b, int N, int epb_lift, int epb_main);
+int dg_batch_set_fused(dg_batch *b, int fused);
+int dg_batch_fused(const dg_batch *b);
 int dg_batch_info(const dg_batch *b, int *out, int cap);
 const char *dg_batch_last_error(const dg_batch *b);
 void dg_batch_destroy(dg_batch *b);

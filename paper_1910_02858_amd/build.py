@@ -49,6 +49,7 @@ def kernel_units():
     units = [("dg_kernels.hip", [], "k_common.o")]
     for n in range(1, NMAX + 1):
         units.append(("dg_kernels.hip", [f"-DDG_ONLY_N={n}"], f"k_n{n}.o"))
+    units.append(("dg_kernels.hip", ["-DDG_FUSED_BATCH"], "k_fused.o"))
     units.append(("dg_static.hip", [], "dg_static.o"))
     units.append(("dg_vjp.hip", [], "dg_vjp_common.o"))
     for n in range(1, NMAX + 1):

@@ -64,6 +64,7 @@ struct dg_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool ns = false;
   int vf = 0;
+  int fused = 0;  // 1: one lifting and one operator launch per stage for all degrees
   std::string err;
 
   hipStream_t stream() const { return mem[0]->stream; }
@@ -172,7 +173,41 @@ int table_for(dg_batch *b, const std::vector<dg::Member> &m, const dg::Member **
   return DG_OK;
 }
 
+// whether one launch can cover every degree: degrees up to 7, structured meshes, few degrees
+bool fusable(const dg_batch *b) {
+  if ((int)b->groups.size() > dg::FUSED_MAXG) return false;
+  for (const Group &g : b->groups) {
+    if (dg::fused_epb(g.N, false) < 1) return false;
+    for (int i : g.idx)
+      if (b->mem[i]->d_fc) return false;
+  }
+  return true;
+}
+
+int launch_stage_fused(dg_batch *b, const dg::Member *table, hipStream_t st) {
+  dg::FusedView fl, fs;
+  std::memset(&fl, 0, sizeof(fl));
+  std::memset(&fs, 0, sizeof(fs));
+  fl.ng = fs.ng = (int)b->groups.size();
+  for (int gi = 0; gi < fl.ng; ++gi) {
+    const Group &g = b->groups[gi];
+    fl.v[gi] = fs.v[gi] = view(b, g, table);
+    fl.N[gi] = fs.N[gi] = g.N;
+    const int el = dg::fused_epb(g.N, true), es = dg::fused_epb(g.N, false);
+    fl.start[gi + 1] = fl.start[gi] + (g.total + el - 1) / el;
+    fs.start[gi + 1] = fs.start[gi] + (g.total + es - 1) / es;
+  }
+  if (b->ns) {
+    const int rc = dg::launch_fused_lift(fl, st);
+    if (rc) return bfail(b, rc, "launch of the fused lifting kernel failed");
+  }
+  const int rc = dg::launch_fused_split(fs, b->ns, b->vf, st);
+  if (rc) return bfail(b, rc, "launch of the fused operator kernel failed");
+  return DG_OK;
+}
+
 int launch_stage(dg_batch *b, const dg::Member *table, hipStream_t st) {
+  if (b->fused) return launch_stage_fused(b, table, st);
   for (const Group &g : b->groups) {
     const dg::BatchView v = view(b, g, table);
     if (b->ns) {
@@ -314,6 +349,7 @@ int dg_batch_step(dg_batch *b, double *const *U, double *const *U_out, double *c
     key = fnv1a(&g.epb_lift, sizeof(int), key);
     key = fnv1a(&g.epb_main, sizeof(int), key);
   }
+  key = fnv1a(&b->fused, sizeof(int), key);
   hipGraphExec_t exec = nullptr;
   for (const Graph &gr : b->graphs)
     if (gr.key == key) exec = gr.exec;
@@ -431,11 +467,56 @@ int dg_batch_tune(dg_batch *b, const double *const *U, int repeats) {
     }
     if (rc) break;
   }
+  if (!rc && fusable(b)) {
+    // one stage of every member, per-degree launches against the fused pair, the faster kept
+    std::vector<double *> outs(n, nullptr), Rs(n, nullptr);
+    for (size_t i = 0; i < n && !rc; ++i) {
+      const size_t bytes = (size_t)b->mem[i]->K * 5 * b->mem[i]->n3 * sizeof(double);
+      if (hipMalloc((void **)&outs[i], bytes) != hipSuccess || hipMalloc((void **)&Rs[i], bytes) != hipSuccess ||
+          hipMemsetAsync(Rs[i], 0, bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = bfail(b, DG_ERR_OOM, "allocation of tuning scratch failed");
+      }
+    }
+    const dg::Member *table = nullptr;
+    if (!rc) {
+      std::vector<double> av(n, A[1]), bv(n, B[1]), dtv(n, 1e-9);
+      rc = table_for(b, describe(b, U, outs.data(), Rs.data(), av.data(), bv.data(), dtv.data()), &table);
+    }
+    float t_mode[2] = {1e30f, 1e30f};
+    for (int mode = 0; mode < 2 && !rc; ++mode) {
+      b->fused = mode;
+      rc = launch_stage(b, table, st);  // warm-up
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < repeats && !rc; ++r) rc = launch_stage(b, table, st);
+      (void)hipEventRecord(e1, st);
+      if (rc || hipEventSynchronize(e1) != hipSuccess) {
+        rc = rc ? rc : DG_ERR_HIP;
+        break;
+      }
+      (void)hipEventElapsedTime(&t_mode[mode], e0, e1);
+    }
+    b->fused = (!rc && t_mode[1] < t_mode[0]) ? 1 : 0;
+    if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = bfail(b, DG_ERR_HIP, "stream synchronisation failed");
+    for (size_t i = 0; i < n; ++i) {
+      if (outs[i]) (void)hipFree(outs[i]);
+      if (Rs[i]) (void)hipFree(Rs[i]);
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc && b->err.empty()) b->err = "tuning launch failed";
   return rc;
 }
+
+int dg_batch_set_fused(dg_batch *b, int fused) {
+  if (!b || (fused != 0 && fused != 1)) return DG_ERR_ARG;
+  if (fused && !fusable(b)) return bfail(b, DG_ERR_UNSUPPORTED, "a degree above 7 or a member with face codes");
+  b->fused = fused;
+  return DG_OK;
+}
+
+int dg_batch_fused(const dg_batch *b) { return b ? b->fused : DG_ERR_ARG; }
 
 int dg_batch_info(const dg_batch *b, int *out, int cap) {
   if (!b) return DG_ERR_ARG;

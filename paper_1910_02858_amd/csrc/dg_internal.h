@@ -196,6 +196,19 @@ template <int n, bool GEN> __device__ __forceinline__ NbFace nbr_face(const Geo 
   return f;
 }
 
+// One launch over the structured members of every degree N <= 7: group g (degree N[g], its own
+// view) takes the workgroups [start[g], start[g+1]); start[ng] is the grid's work.
+constexpr int FUSED_MAXG = 8;
+struct FusedView {
+  BatchView v[FUSED_MAXG];
+  int N[FUSED_MAXG];
+  int start[FUSED_MAXG + 1];
+  int ng;
+};
+int fused_epb(int N, bool lift);  // elements per 512-lane workgroup; 0 where N is not fused
+int launch_fused_lift(const FusedView &fv, hipStream_t st);
+int launch_fused_split(const FusedView &fv, bool ns, int vf, hipStream_t st);
+
 template <int N>
 int launch_batch_lift(const BatchView &bv, int epb, hipStream_t st);
 template <int N>

@@ -130,7 +130,9 @@ __device__ __forceinline__ double logmean(double a, double b) {
   const double f = d / s;
   const double u = f * f;
   if (u < 1e-4) return s / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
-  return d / (log(a) - log(b));
+  // log(a) - log(b) as one logarithm, log1p of the difference over the smaller argument
+  const double ad = fabs(d);
+  return ad / log1p(ad / fmin(a, b));
 }
 
 // two-point flux along nv: vf 0 KEP (Pirozzoli), 1 EC (Chandrashekar), 2 central
@@ -623,16 +625,12 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   }
   const double *Ue = U + (size_t)e * 5 * n3;
   const double *Ge = G + (size_t)e * 12 * n3;
-  double Uo[5], go[12];
+  double Uo[5];
   if (t < n3) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       Uo[v] = Ue[v * n3 + t];
       sU[v * n3 + t] = Uo[v];
-    }
-    if (NS) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
     }
   }
   __syncthreads();
@@ -677,6 +675,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 #pragma unroll
         for (int c = 0; c < 12; ++c) { gw[c] = 0.0; gx[c] = 0.0; }
       }
+      // a rolled loop: unrolled, the early loads of all n nodes' 34 values spill
+#pragma unroll 1
       for (int m = 0; m < n; ++m) {
         const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
 #pragma unroll
@@ -769,7 +769,14 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int i = t % n, j = (t / n) % n, k = t / n2;
   Pr5 Po;
-  if (t < n3) Po = to_prim(Uo, gm1);
+  double go[12];  // the node's lifted gradients, loaded after the face phase
+  if (t < n3) {
+    Po = to_prim(Uo, gm1);
+    if (NS) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
+    }
+  }
   for (int dir = 0; dir < 3; ++dir) {
     double Fint[5], nv[3];
     __syncthreads();
@@ -919,18 +926,22 @@ __device__ __forceinline__ void pair2(const PS &A, const PS &B, const double *nS
     const double fr = dr * frcp1(sr);
     const double ur = fr * fr;
     double rl;  // rho^ln / 2
-    if (ur < 1e-4)
+    // beyond the series, log(a) - log(b) as one logarithm of the larger over the smaller
+    // argument (the same bits from either end of the pair)
+    if (ur < 1e-4) {
       rl = 0.25 * sr * fma(ur, fma(ur, fma(ur, DG_LM_C3, DG_LM_C2), DG_LM_C1), 1.0);
-    else
-      rl = 0.5 * dr / (log(A.r) - log(B.r));
+    } else {
+      rl = 0.5 * fabs(dr) / log(fmax(A.r, B.r) * frcp(fmin(A.r, B.r)));
+    }
     const double sb = A.b + B.b, db = A.b - B.b;
     const double rb = frcp(sb);
     const double fb = db * rb, ub = fb * fb;
     double eb;  // 1 / (2 (gamma-1) beta^ln)
-    if (ub < 1e-4)
+    if (ub < 1e-4) {
       eb = kg * rb * fma(ub, fma(ub, fma(ub, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
-    else
-      eb = 0.5 * kg * (log(A.b) - log(B.b)) / db;
+    } else {
+      eb = 0.5 * kg * log(fmax(A.b, B.b) * frcp(fmin(A.b, B.b))) / fabs(db);
+    }
     f0 = rl * un;                // 2 rho^ln {u}.{Ja}
     pp = 0.5 * sr * rb;          // {rho} / (2 {beta})
     e4 = eb - 0.25 * (A.q + B.q);
@@ -1505,22 +1516,26 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_reduce(Geo g, Phys ph, int what, 
 
 // value of the nv-component field X ([e][nv][n^3]) at face point (a,b) of side s of element e:
 // the face node on LGL nodes, interpolated along the face normal with l(+-1) on LG nodes
-template <int n, bool LGL>
-__device__ __forceinline__ void face_trace(const double *__restrict__ X, int nv, int e, int s, int a, int b,
+template <int n, bool LGL, int NV>
+__device__ __forceinline__ void face_trace(const double *__restrict__ X, int e, int s, int a, int b,
                                            const double *lm, const double *lp, double *out) {
   constexpr int n3 = n * n * n;
   const int dn = s >> 1;
   const bool plus = s & 1;
-  const double *Xe = X + (size_t)e * nv * n3;
+  const double *Xe = X + (size_t)e * NV * n3;
   if (LGL) {
     const int q = line_node<n>(dn, a, b, plus ? n - 1 : 0);
-    for (int v = 0; v < nv; ++v) out[v] = Xe[v * n3 + q];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = Xe[v * n3 + q];
   } else {
     const double *l = plus ? lp : lm;
-    for (int v = 0; v < nv; ++v) out[v] = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll 1
     for (int m = 0; m < n; ++m) {
       const int q = line_node<n>(dn, a, b, m);
-      for (int v = 0; v < nv; ++v) out[v] += l[m] * Xe[v * n3 + q];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] += l[m] * Xe[v * n3 + q];
     }
   }
 }
@@ -1581,19 +1596,23 @@ __device__ __forceinline__ double mcoef(const double *M, int n, int r, int c) {
   return M ? M[r * n + c] : (r == c ? 1.0 : 0.0);
 }
 
-// sum over the big side's points (m, l) of M1[r1][m] M2[r2][l] X[v][m + n l], v < nv
-template <int n>
-__device__ __forceinline__ void sub_apply(const double *M1, const double *M2, int r1, int r2, const double *X, int nv,
+// sum over the big side's points (m, l) of M1[r1][m] M2[r2][l] X[v][m + n l], v < NV
+template <int n, int NV>
+__device__ __forceinline__ void sub_apply(const double *M1, const double *M2, int r1, int r2, const double *X,
                                           double *out) {
   constexpr int n2 = n * n;
-  for (int v = 0; v < nv; ++v) out[v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll 1
   for (int l = 0; l < n; ++l) {
     const double c2 = mcoef(M2, n, r2, l);
     if (c2 == 0.0) continue;
+#pragma unroll 1
     for (int m = 0; m < n; ++m) {
       const double c1 = mcoef(M1, n, r1, m);
       if (c1 == 0.0) continue;
-      for (int v = 0; v < nv; ++v) out[v] += c1 * (c2 * X[v * n2 + m + n * l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] += c1 * (c2 * X[v * n2 + m + n * l]);
     }
   }
 }
@@ -1610,7 +1629,7 @@ __global__ void __launch_bounds__(256) k_mortar_lift(Geo g, Phys ph, const Morta
   for (int c = t; c < n * n; c += nth) {
     sM[c] = tb->IL[c]; sM[n * n + c] = tb->IU[c]; sM[2 * n * n + c] = tb->PL[c]; sM[3 * n * n + c] = tb->PU[c];
   }
-  const MortarDesc m = md[blockIdx.x];
+  const MortarDesc &m = md[blockIdx.x];  // read in place: its arrays are indexed by sub-face
   const double gm1 = ph.gamma - 1.0;
   for (int p = t; p < n2; p += nth) {
     double W[4];
@@ -1628,7 +1647,7 @@ __global__ void __launch_bounds__(256) k_mortar_lift(Geo g, Phys ph, const Morta
     const double *A1, *A2;
     sub_ops<n>(sM, m.type, pos, false, A1, A2);
     double WB[4], Ws[4];
-    sub_apply<n>(A1, A2, a2, b2, sWB, 4, WB);
+    sub_apply<n, 4>(A1, A2, a2, b2, sWB, WB);
     face_trace_W<n, LGL>(U, es, ss, a, b, tb->lm, tb->lp, gm1, ph.R, Ws);
     const double *fnp = g.fn + ((size_t)es * 6 + ss) * 3 * n2 + ab;
     const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
@@ -1651,9 +1670,11 @@ __global__ void __launch_bounds__(256) k_mortar_lift(Geo g, Phys ph, const Morta
     for (int pos = 0; pos < cnt; ++pos) {
       const double *B1, *B2;
       sub_ops<n>(sM, m.type, pos, true, B1, B2);
+#pragma unroll 1
       for (int b2 = 0; b2 < n; ++b2) {
         const double c2 = mcoef(B2, n, j, b2);
         if (c2 == 0.0) continue;
+#pragma unroll 1
         for (int a2 = 0; a2 < n; ++a2) {
           const double c = mcoef(B1, n, i, a2) * c2;
           if (c == 0.0) continue;
@@ -1683,11 +1704,11 @@ __global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const Morta
   for (int c = t; c < n * n; c += nth) {
     sM[c] = tb->IL[c]; sM[n * n + c] = tb->IU[c]; sM[2 * n * n + c] = tb->PL[c]; sM[3 * n * n + c] = tb->PU[c];
   }
-  const MortarDesc m = md[blockIdx.x];
+  const MortarDesc &m = md[blockIdx.x];  // read in place: its arrays are indexed by sub-face
   const double gm1 = ph.gamma - 1.0;
   for (int p = t; p < n2; p += nth) {
     double Uq[5];
-    face_trace<n, LGL>(U, 5, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, Uq);
+    face_trace<n, LGL, 5>(U, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, Uq);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sUB[v * n2 + p] = Uq[v];
     if (NS) {
@@ -1697,7 +1718,7 @@ __global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const Morta
 #pragma unroll
         for (int c = 0; c < 12; ++c) gq[c] = mg[c * n2];
       } else {
-        face_trace<n, false>(G, 12, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, gq);
+        face_trace<n, false, 12>(G, m.eb, m.sb, p % n, p / n, tb->lm, tb->lp, gq);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) sGB[c * n2 + p] = gq[c];
@@ -1714,8 +1735,8 @@ __global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const Morta
     sub_ops<n>(sM, m.type, pos, false, A1, A2);
     // the small side is the master of its part of the face: its own normal, its state first
     double UM[5], US[5];
-    face_trace<n, LGL>(U, 5, es, ss, a, b, tb->lm, tb->lp, UM);
-    sub_apply<n>(A1, A2, a2, b2, sUB, 5, US);
+    face_trace<n, LGL, 5>(U, es, ss, a, b, tb->lm, tb->lp, UM);
+    sub_apply<n, 5>(A1, A2, a2, b2, sUB, US);
     const double *fnp = g.fn + ((size_t)es * 6 + ss) * 3 * n2 + ab;
     const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
     const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
@@ -1733,9 +1754,9 @@ __global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const Morta
 #pragma unroll
         for (int c = 0; c < 12; ++c) gM[c] = mg[c * n2];
       } else {
-        face_trace<n, false>(G, 12, es, ss, a, b, tb->lm, tb->lp, gM);
+        face_trace<n, false, 12>(G, es, ss, a, b, tb->lm, tb->lp, gM);
       }
-      sub_apply<n>(A1, A2, a2, b2, sGB, 12, gS);
+      sub_apply<n, 12>(A1, A2, a2, b2, sGB, gS);
       const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
       flux_v(PM, gM, ph, nt, FvM);
       flux_v(PS, gS, ph, nt, FvS);
@@ -1756,9 +1777,11 @@ __global__ void __launch_bounds__(256) k_mortar_flux(Geo g, Phys ph, const Morta
     for (int pos = 0; pos < cnt; ++pos) {
       const double *B1, *B2;
       sub_ops<n>(sM, m.type, pos, true, B1, B2);
+#pragma unroll 1
       for (int b2 = 0; b2 < n; ++b2) {
         const double c2 = mcoef(B2, n, j, b2);
         if (c2 == 0.0) continue;
+#pragma unroll 1
         for (int a2 = 0; a2 < n; ++a2) {
           const double c = mcoef(B1, n, i, a2) * c2;
           if (c == 0.0) continue;
@@ -1896,12 +1919,12 @@ __global__ void __launch_bounds__(FvFaceSz<N>::NT) k_fv_face(Geo g, Phys ph, FvG
     if (pt) {
       double tr[5];
       if (!fe) {
-        face_trace<n, LGL>(U, 5, e, s, a, b, tb->lm, tb->lp, tr);
+        face_trace<n, LGL, 5>(U, e, s, a, b, tb->lm, tb->lp, tr);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sTe[v * n2 + t] = tr[v];
       }
       if (!fn) {
-        face_trace<n, LGL>(U, 5, nb, ns, a2, b2, tb->lm, tb->lp, tr);
+        face_trace<n, LGL, 5>(U, nb, ns, a2, b2, tb->lm, tb->lp, tr);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sTn[v * n2 + a2 + n * b2] = tr[v];
       }
@@ -2098,12 +2121,14 @@ __global__ void __launch_bounds__(Sz<N>::NT, 4) k_fv_volume(Geo g, Phys ph, FvGe
 }
 
 // apply the n x n matrix A along all three directions to the 5 fields of sX (in place through sY)
-template <int n>
-__device__ __forceinline__ void fv_tensor3(const double *A, double *sX, double *sY, int t, bool act) {
+template <int n, int NV = 5>
+__device__ __forceinline__ void fv_tensor3(const double *A, double *sX, int t, bool act) {
   constexpr int n2 = n * n, n3 = n2 * n;
   const int i = t % n, j = (t / n) % n, k = t / n2;
   for (int dir = 0; dir < 3; ++dir) {
-    double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = 0.0;
     if (act) {
       const int id = dir == 0 ? i : (dir == 1 ? j : k);
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
@@ -2111,18 +2136,13 @@ __device__ __forceinline__ void fv_tensor3(const double *A, double *sX, double *
       for (int m = 0; m < n; ++m) {
         const double c = A[id * n + m];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) r[v] += c * sX[v * n3 + base + m * str];
+        for (int v = 0; v < NV; ++v) r[v] += c * sX[v * n3 + base + m * str];
       }
     }
-    __syncthreads();
+    __syncthreads();  // every line is read before any node is overwritten
     if (act) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sY[v * n3 + t] = r[v];
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sX[v * n3 + t] = sY[v * n3 + t];
+      for (int v = 0; v < NV; ++v) sX[v * n3 + t] = r[v];
     }
     __syncthreads();
   }
@@ -2135,7 +2155,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
                                                          int do_switch) {
   using S = Sz<N>;
   constexpr int n = S::n, n3 = S::n3;
-  __shared__ double sX[5 * n3], sY[5 * n3], sU[5 * n3];
+  __shared__ double sX[5 * n3], sU[5 * n3];
   __shared__ double sA[3 * n * n];  // V, Vi, Li
   __shared__ double sE[3 * (Sz<N>::NT / 64)];
   __shared__ int sNew;
@@ -2152,7 +2172,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
     }
   }
   __syncthreads();
-  if (isfv) fv_tensor3<n>(sA + n * n, sX, sY, t, act);  // nodal values of the element's DG reading
+  if (isfv) fv_tensor3<n>(sA + n * n, sX, t, act);  // nodal values of the element's DG reading
   if (act) {
     double W[5], Uq[5];
 #pragma unroll
@@ -2161,7 +2181,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
     sX[t] = W[0] * W[4];  // q = rho p in field 0
   }
   __syncthreads();
-  fv_tensor3<n>(sA + 2 * n * n, sX, sY, t, act);  // modal coefficients (field 0)
+  fv_tensor3<n, 1>(sA + 2 * n * n, sX, t, act);  // modal coefficients (field 0)
   {
     // energies: of all modes, of those whose largest index is N, of those whose largest index is
     // N-1; summed per wave by a fixed butterfly, then over the waves in order
@@ -2201,7 +2221,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_fv_switch(Geo g, Phys ph, FvGeo f
   __syncthreads();
   const int nw = sNew;
   if (nw == (isfv ? 1 : 0)) return;  // uniform across the workgroup
-  fv_tensor3<n>(nw ? sA : sA + n * n, sU, sY, t, act);
+  fv_tensor3<n>(nw ? sA : sA + n * n, sU, t, act);
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) U[((size_t)e * 5 + v) * n3 + t] = sU[v * n3 + t];
@@ -2445,7 +2465,7 @@ int launch_reduce(const Geo &g, const Phys &ph, int what, const double *U, doubl
   return DG_OK;
 }
 
-#ifndef DG_ONLY_N
+#if !defined(DG_ONLY_N) && !defined(DG_FUSED_BATCH)
 // one workgroup folds the per-element partials in a fixed order
 __global__ void __launch_bounds__(256) k_final_reduce(int what, const double *__restrict__ partial, int K,
                                                       double *__restrict__ out) {
@@ -2519,6 +2539,138 @@ int launch_axpby(double *y, const double *x, double alpha, double beta, size_t n
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_axpby, dim3((unsigned)blocks), dim3(256), 0, st, y, x, alpha, beta, n);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+#endif
+
+#ifdef DG_FUSED_BATCH
+// ----------------------------------------------------------------------------- fused ensemble
+// One lifting and one operator launch per stage for the members of every degree (structured
+// members): group g of the work takes the workgroups [start[g], start[g+1]) of the grid, each
+// workgroup of 512 lanes holds fused_epb elements of its group's degree in slots of the degree's
+// own lane count, and the static LDS is the largest degree's, carved per slot.  Lanes past the
+// last slot run the per-element code as invalid slots (no memory access, every barrier).
+template <int N> constexpr int fused_epb_split() {
+  constexpr int by_lanes = 512 / SplitSz<N>::NT;
+  constexpr int by_lds = (SplitLds<7>::A + SplitLds<7>::P) / (SplitLds<N>::A + SplitLds<N>::P);
+  return by_lanes < by_lds ? by_lanes : by_lds;
+}
+template <int N> constexpr int fused_epb_lift() {
+  constexpr int by_lanes = 512 / Sz<N>::NT;
+  constexpr int by_lds = (LiftLds<7>::W + LiftLds<7>::JA + LiftLds<7>::WS) /
+                         (LiftLds<N>::W + LiftLds<N>::JA + LiftLds<N>::WS);
+  return by_lanes < by_lds ? by_lanes : by_lds;
+}
+
+__device__ __forceinline__ int fused_group(const FusedView &fv, int b) {
+  int gi = 0;
+  while (gi + 1 < fv.ng && b >= fv.start[gi + 1]) ++gi;
+  return gi;
+}
+
+template <int N, bool NS, int VF>
+__device__ __forceinline__ void fused_split_group(const BatchView &bv, int blk, double *smem, double *sD, double *slh) {
+  using L = SplitLds<N>;
+  constexpr int NT = SplitSz<N>::NT, EPB = fused_epb_split<N>();
+  split_tables<N>(bv.tab, threadIdx.x, 512, sD, slh);
+  const int raw = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
+  const int slot = raw < EPB ? raw : EPB - 1;
+  const int t = threadIdx.x - raw * NT;
+  const int item = blk * EPB + slot;
+  const bool valid = raw < EPB && item < bv.total;
+  const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
+  const Member &M = bv.m[mi];
+  split_body<N, NS, VF, 1, false>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, M.G, M.out, M.R, M.a,
+                                  M.b, M.dt, smem + slot * L::A, smem + EPB * L::A + slot * L::P, sD, slh);
+}
+
+template <bool NS, int VF>
+__global__ void __launch_bounds__(512, DG_SPLIT_MINB) k_split_f(FusedView fv) {
+  __shared__ double smem[SplitLds<7>::A + SplitLds<7>::P];
+  __shared__ double sD[64], slh[16];
+  const int nb = fv.start[fv.ng];
+  const int b = xcd_element(blockIdx.x, nb);
+  if (b >= nb) return;
+  const int gi = fused_group(fv, b);
+  const int lb = b - fv.start[gi];
+  switch (fv.N[gi]) {
+    case 1: fused_split_group<1, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    case 2: fused_split_group<2, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    case 3: fused_split_group<3, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    case 4: fused_split_group<4, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    case 5: fused_split_group<5, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    case 6: fused_split_group<6, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+    default: fused_split_group<7, NS, VF>(fv.v[gi], lb, smem, sD, slh); break;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void fused_lift_group(const BatchView &bv, int blk, double *smem, double *sDh, double *sl,
+                                                 double *slh) {
+  using L = LiftLds<N>;
+  constexpr int NT = Sz<N>::NT, EPB = fused_epb_lift<N>();
+  lift_tables<N>(bv.tab, threadIdx.x, 512, sDh, sl, slh);
+  const int raw = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
+  const int slot = raw < EPB ? raw : EPB - 1;
+  const int t = threadIdx.x - raw * NT;
+  const int item = blk * EPB + slot;
+  const bool valid = raw < EPB && item < bv.total;
+  const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
+  const Member &M = bv.m[mi];
+  lift_body<N, true, LIFT_FV, false>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
+                                     smem + slot * L::W, smem + EPB * L::W + slot * L::JA,
+                                     smem + EPB * (L::W + L::JA) + slot * L::WS, sDh, sl, slh);
+}
+
+__global__ void __launch_bounds__(512, DG_LIFT_MINB) k_lift_f(FusedView fv) {
+  __shared__ double smem[LiftLds<7>::W + LiftLds<7>::JA + LiftLds<7>::WS];
+  __shared__ double sDh[64], sl[16], slh[16];
+  const int nb = fv.start[fv.ng];
+  const int b = xcd_element(blockIdx.x, nb);
+  if (b >= nb) return;
+  const int gi = fused_group(fv, b);
+  const int lb = b - fv.start[gi];
+  switch (fv.N[gi]) {
+    case 1: fused_lift_group<1>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 2: fused_lift_group<2>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 3: fused_lift_group<3>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 4: fused_lift_group<4>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 5: fused_lift_group<5>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 6: fused_lift_group<6>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    default: fused_lift_group<7>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+  }
+}
+
+int fused_epb(int N, bool lift) {
+  switch (N) {
+#define DG_CASE(NN) \
+  case NN: return lift ? fused_epb_lift<NN>() : fused_epb_split<NN>();
+    DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7)
+#undef DG_CASE
+    default: return 0;
+  }
+}
+
+int launch_fused_lift(const FusedView &fv, hipStream_t st) {
+  hipLaunchKernelGGL(k_lift_f, dim3(xcd_grid(fv.start[fv.ng])), dim3(512), 0, st, fv);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+int launch_fused_split(const FusedView &fv, bool ns, int vf, hipStream_t st) {
+  const dim3 grid(xcd_grid(fv.start[fv.ng])), block(512);
+#define DG_FS(NS_, VF_) hipLaunchKernelGGL((k_split_f<NS_, VF_>), grid, block, 0, st, fv)
+  if (ns) {
+    if (vf == DG_VF_EC) DG_FS(true, 1);
+    else if (vf == DG_VF_KEP) DG_FS(true, 0);
+    else DG_FS(true, 2);
+  } else {
+    if (vf == DG_VF_EC) DG_FS(false, 1);
+    else if (vf == DG_VF_KEP) DG_FS(false, 0);
+    else DG_FS(false, 2);
+  }
+#undef DG_FS
   DG_CHECK_LAUNCH();
   return DG_OK;
 }

@@ -33,6 +33,10 @@
 #ifndef DG_VJP_MINB
 #define DG_VJP_MINB 2
 #endif
+// stage the metric terms and kept viscous fluxes in LDS where they fit
+#ifndef DG_VJP_STAGE
+#define DG_VJP_STAGE 1
+#endif
 
 namespace dg {
 
@@ -74,7 +78,7 @@ __global__ void __launch_bounds__(VSz<N>::NT, DG_VJP_MINB) k_vjp_main(Geo g, Phy
   // viscous fluxes (9 per node) are staged once at the start, so that no later phase waits on a
   // global load after a barrier
   constexpr int NST = 9 + (NS ? 9 : 0);
-  constexpr bool STAGE = (11 + NST) * n3 + NX + 2 * n * n <= 160 * 1024 / 8;
+  constexpr bool STAGE = DG_VJP_STAGE && (11 + NST) * n3 + NX + 2 * n * n <= 160 * 1024 / 8;
   __shared__ double sX[NX];
   __shared__ double sD[n * n], sDh[n * n];
   __shared__ double sM[STAGE ? NST * n3 : 1];  // Ja^i_d at (i*3+d)*n3, then Fv^dir_c at (9+dir*3+c)*n3

@@ -29,6 +29,7 @@ EXPORTS = [
     "dg_rk_stage_vjp", "dg_timestep", "dg_integrals", "dg_check_finite", "dg_node_coords", "dg_info", "dg_destroy",
     "dg_status_string", "dg_last_error", "dg_batch_create", "dg_batch_rk_stage", "dg_batch_destroy", "dg_profile",
     "dg_profile_read", "dg_host_geometry", "dg_mass_weights", "dg_batch_step", "dg_batch_tune", "dg_batch_set_tile",
+    "dg_batch_set_fused", "dg_batch_fused",
     "dg_batch_info", "dg_batch_last_error", "dg_rk_stage_keep", "dg_rk_step_vjp", "dg_rk_steps_vjp",
     "dg_integrals_noalloc", "dg_profile_read_ex", "dg_mesh_file_write", "dg_mesh_file_info", "dg_mesh_file_read",
     "dg_mesh_connect_nodes", "dg_fv_enable", "dg_fv_set_types", "dg_fv_types", "dg_fv_indicator", "dg_fv_switch",
@@ -124,6 +125,8 @@ def lib():
         L.dg_batch_step.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), _D, ctypes.c_int]
         L.dg_batch_tune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.c_int]
         L.dg_batch_set_tile.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.dg_batch_set_fused.argtypes = [_VP, ctypes.c_int]
+        L.dg_batch_fused.argtypes = [_VP]
         L.dg_batch_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.dg_batch_last_error.restype = ctypes.c_char_p
         L.dg_batch_last_error.argtypes = [_VP]
@@ -562,6 +565,15 @@ class Batch:
 
     def set_tile(self, N: int, epb_lift: int, epb_main: int):
         self._check(lib().dg_batch_set_tile(self.b, N, epb_lift, epb_main), "dg_batch_set_tile")
+
+    @property
+    def fused(self) -> bool:
+        """One lifting and one operator launch per stage for all degrees (else one pair per degree)."""
+        return bool(lib().dg_batch_fused(self.b))
+
+    @fused.setter
+    def fused(self, on: bool):
+        self._check(lib().dg_batch_set_fused(self.b, int(bool(on))), "dg_batch_set_fused")
 
     def info(self):
         """[(N, members, elements, elements per workgroup of lifting, of operator)] per degree."""

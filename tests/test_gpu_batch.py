@@ -76,6 +76,45 @@ def test_batched_stage_equals_member_stages(dg, volflux, eqn):
             assert torch.equal(Rb, rR), f"member {i} R differs at tile {tile}"
 
 
+@pytest.mark.parametrize("volflux,eqn", [("kep", "ns"), ("ec", "ns"), ("central", "euler")])
+def test_fused_launch_equals_member_stages(dg, volflux, eqn):
+    """One lifting and one operator launch for all degrees (1..7 here, degree 3 twice): the same
+    bits as every member's own stage, eagerly and replayed from a graph; with a degree-8 member
+    the single launch is refused."""
+    import torch
+    sols, U0s = make_members(dg, volflux, eqn)
+    with pytest.raises(dg.DGError) as ei:
+        dg.Batch(sols).fused = True  # degree 8 present
+    assert ei.value.code == -3
+    sols, U0s = sols[:-1], U0s[:-1]
+    B = dg.Batch(sols)
+    B.fused = True
+    assert B.fused
+    dts = [S.timestep(U) for S, U in zip(sols, U0s)]
+    a, b, _ = dg.rk_coefficients()
+    R0 = [rand_like(U, 20 + i) * 1e-3 for i, U in enumerate(U0s)]
+    outs = [S.empty() for S in sols]
+    Rs = [R.clone() for R in R0]
+    B.rk_stage(U0s, outs, Rs, a[3], b[3], dts)
+    torch.cuda.synchronize()
+    for i, (S, U, R, dt) in enumerate(zip(sols, U0s, R0, dts)):
+        out, Rr = S.empty(), R.clone()
+        S.rk_stage(U, out, Rr, a[3], b[3], dt)
+        assert torch.equal(outs[i], out), f"member {i} (N={MEMBERS[i][0]}) U_out differs"
+        assert torch.equal(Rs[i], Rr), f"member {i} R differs"
+    # full steps from a graph against the members' own steps
+    U = [u.clone() for u in U0s]
+    Uo = [S.empty() for S in sols]
+    Rb = [torch.zeros_like(u) for u in U0s]
+    for _ in range(3):
+        B.step(U, Uo, Rb, dts, graph=True)
+        U, Uo = Uo, U
+    torch.cuda.synchronize()
+    for i, (S, u0, dt) in enumerate(zip(sols, U0s, dts)):
+        ref = S.steps(u0.clone(), 3, dt)
+        assert torch.equal(U[i], ref), f"member {i} differs after three fused graph steps"
+
+
 def test_first_stage_ignores_R(dg):
     import torch
     sols, U0s = make_members(dg)
