@@ -579,6 +579,11 @@ def order_bench(dgsem, inputs, torch, wl, steps: int, lexicographic_value: float
     return out
 
 
+def progress(msg: str):
+    """One line on stderr as each measurement ends (the JSON result line goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 # the optional measurements beside the headline, each switched off by --no-<name>
 LEGS = ("cpu", "adjoint", "ensemble", "general", "mortar", "fv", "weak", "ec-branch", "adjoint-roofline")
 
@@ -665,6 +670,7 @@ def main():
     ec_branch = None
     if not args.no_ec_branch and wl.volflux == "ec":
         ec_branch = ec_branch_bench(S, U, torch, wl, main_ms)
+        progress("EC logarithm branch done")
         torch.cuda.empty_cache()
 
     if args.calib_copy:
@@ -693,6 +699,7 @@ def main():
 
     stages = args.steps * 5
     value = dof * stages / wall
+    progress(f"headline done: {value:.4g} DOF-updates/s")
     tbytes, tvalid = counter_traffic()
     traffic_gbs = tbytes / (main_ms * 1e-3) / 1e9 if (tbytes is not None and tvalid and args.elements == 48) else None
     out = {
@@ -731,16 +738,19 @@ def main():
         out["ec_log_branch"] = ec_branch
     if not args.no_adjoint:
         adj = adjoint_ratio(dgsem, inputs, torch)
+        progress("adjoint ratio done")
         out["adjoint_forward_ratio"] = adj["value"]
         out["adjoint"] = adj
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(dgsem, inputs, torch)
+        progress("ensemble done")
     freed = False
     if not args.no_general:
         del S, U, R, spare, cur, nxt
         freed = True
         torch.cuda.empty_cache()
         out["general_mesh"] = general_mesh_bench(dgsem, inputs, torch, wl, 5, value)
+        progress("general mesh done")
         if not args.no_adjoint:
             out["general_mesh"]["adjoint"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, general=True)
     if (not args.no_mortar or not args.no_fv or not args.no_weak or not args.no_adjoint_roofline or
@@ -750,23 +760,28 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_adjoint_roofline:
         out["adjoint_hbm"] = adjoint_roofline(dgsem, inputs, torch)
+        progress("reverse roofline done")
         if not args.no_adjoint:
             # the adjoint/forward rollout ratio at the same size (20 steps, checkpoint every 10)
             out["adjoint_hbm"]["rollout"] = adjoint_ratio(dgsem, inputs, torch, repeats=1, k1=32, steps=20)
         torch.cuda.empty_cache()
     if not args.no_mortar:
         out["mortar"] = mortar_bench(dgsem, inputs, torch, 5, value)
+        progress("mortars done")
         torch.cuda.empty_cache()
     if not args.no_fv:
         out["fv"] = fv_bench(dgsem, inputs, torch, 5)
+        progress("FV subcells done")
         torch.cuda.empty_cache()
     if not args.no_weak:
         out["weak_form"] = weak_form_bench(dgsem, inputs, torch)
+        progress("weak form done")
         torch.cuda.empty_cache()
     if args.order_study:
         out["element_order"] = order_bench(dgsem, inputs, torch, wl, 5, value)
     if not args.no_cpu:
         cb = cpu_baseline(wl)
+        progress("CPU baseline done")
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["pid_core_s"] = cb["pid_core_s"]
         out["cpu_baseline"]["pid_1thread_s"] = cb["pid_1thread_s"]

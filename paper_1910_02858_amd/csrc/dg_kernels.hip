@@ -309,7 +309,7 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // (F^v . Ja^dir)_{1+c} (momentum, energy) that the split-form kernels and their reverse consume.
 enum { LIFT_G = 0, LIFT_FV = 1 };
 
-template <int N, bool LGL, int OUT, bool GEN>
+template <int N, bool LGL, int OUT, int GEN>
 __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                           const double *__restrict__ U, double *__restrict__ G,
                                           double *__restrict__ Fv, double *sW, double *sJa, double *sWs,
@@ -334,7 +334,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   if (PF && valid && t < 6 * n2) {
     const int s = t / n2, ab = t - s * n2, a = ab % n, b = ab / n;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const NbFace f = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
     const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(s >> 1, a, b, (s & 1) ? 0 : N);
     if (!(GEN && f.bnd)) {
 #pragma unroll
@@ -355,7 +355,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const NbFace f = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
     const double *Un = U + (size_t)(GEN && f.bnd ? e : nb) * 5 * n3;
     double WL[4], WR[4];
     if (LGL) {
@@ -420,7 +420,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       }
       Uq[4] = ph.pout / gm1 + 0.5 * (Uq[1] * Uq[1] + Uq[2] * Uq[2] + Uq[3] * Uq[3]) / Uq[0];
       grad_prim_to_W(Uq, gm1, ph.R, WR);
-    } else if (GEN && f.bnd && f.kind == FACE_MORTAR) {
+    } else if (GEN == 2 && f.bnd && f.kind == FACE_MORTAR) {
       // non-conforming face: the surface term comes from the mortar face array
 #pragma unroll
       for (int v = 0; v < 4; ++v) WR[v] = WL[v];
@@ -484,7 +484,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
         const int ab = a + n * b;
         const double sl_ = plus ? lh : -lh;
-        if (GEN && is_mortar(g, e, s)) {
+        if (GEN == 2 && is_mortar(g, e, s)) {
           // non-conforming face: W* s n_d (outward) from the mortar face array
           const double *ml = g.mlift + (size_t)g.mslot[(size_t)e * 6 + s] * 12 * n2 + ab;
 #pragma unroll
@@ -510,7 +510,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       if (LGL && lh == 0.0) continue;
       const int a = dn == 0 ? j : i, b = dn == 2 ? j : k;
       const int ab = a + n * b;
-      if (GEN && is_mortar(g, e, s)) {
+      if (GEN == 2 && is_mortar(g, e, s)) {
         const double *ml = g.mlift + (size_t)g.mslot[(size_t)e * 6 + s] * 12 * n2 + ab;
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] += lh * ml[c * n2];
@@ -534,7 +534,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] *= sj;
     }
-    if (GEN && LGL && g.mslot) {
+    if (GEN == 2 && LGL) {
       // face nodes of non-conforming sides keep their gradients for the mortar flux kernel
 #pragma unroll
       for (int dir = 0; dir < 3; ++dir) {
@@ -585,7 +585,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   }
 }
 
-template <int N, bool LGL, int OUT, bool GEN>
+template <int N, bool LGL, int OUT, int GEN>
 __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
 // FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
 // FVM: hybrid DG/FV mesh (Euler): finite-volume elements are left to k_fv_volume, and the sides
 // that meet one take their flux from Geo::fvFx.
-template <int N, bool LGL, bool NS, int FORM, int MODE, bool GEN, bool FVM = false>
+template <int N, bool LGL, bool NS, int FORM, int MODE, int GEN, bool FVM = false>
 __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double *__restrict__ U,
                                                     const double *__restrict__ G, double *__restrict__ out,
                                                     double *__restrict__ R, double ca, double cb, double dt) {
@@ -639,9 +639,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const NbFace f = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
     const bool bnd = GEN && f.bnd;
-    if (bnd && f.kind == FACE_MORTAR) {
+    if (GEN == 2 && bnd && f.kind == FACE_MORTAR) {
       // non-conforming face: the outward flux from the mortar face array
       const double *mf = g.mflux + (size_t)g.mslot[(size_t)e * 6 + s] * 5 * n2 + ab;
 #pragma unroll
@@ -1056,7 +1056,7 @@ template <int n> __host__ __device__ constexpr bool wave_local(int dir) {
 // to the other node goes through an LDS accumulator.  Viscous part in strong form, surface
 // penalty f* s - F_int.N, -1/J, optional RK update.  Directions whose lines lie inside one wave
 // order their exchange rounds with a wave fence instead of a workgroup barrier.
-template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
+template <int N, bool NS, int VF, int MODE, int GEN, bool FVM = false>
 __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, bool valid, int lane,
                                            const double *__restrict__ U, const double *__restrict__ G,
                                            double *__restrict__ out, double *__restrict__ R, double ca, double cb,
@@ -1095,9 +1095,9 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const int s = q / n2, ab = q - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
     const bool plus = s & 1;
     const int nb = g.nbr[(size_t)e * 6 + s];
-    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const NbFace f = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
     const bool bnd = GEN && f.bnd;
-    if (bnd && f.kind == FACE_MORTAR) {
+    if (GEN == 2 && bnd && f.kind == FACE_MORTAR) {
       // non-conforming face: the outward flux from the mortar face array
       const double *mf = g.mflux + (size_t)g.mslot[(size_t)e * 6 + s] * 5 * n2 + ab;
 #pragma unroll
@@ -1363,7 +1363,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   }
 }
 
-template <int N, bool NS, int VF, int MODE, bool GEN, bool FVM = false>
+template <int N, bool NS, int VF, int MODE, int GEN, bool FVM = false>
 __global__ void __launch_bounds__(SplitSz<N>::NT, DG_SPLIT_MINB) k_split(Geo g, Phys ph, const double *__restrict__ U,
                                                      const double *__restrict__ G, double *__restrict__ out,
                                                      double *__restrict__ R, double ca, double cb, double dt) {
@@ -1882,7 +1882,7 @@ __global__ void __launch_bounds__(256) k_fv_lists(Geo g, FvGeo f) {
   if (s == 0 && f.flag[e]) f.list[atomicAdd(&f.count[0], 1)] = e;
   const int nb = g.nbr[q];
   if (nb < 0) return;
-  const NbFace f0 = nbr_face<n, GEN>(g, e, s, 0, 0);
+  const NbFace f0 = nbr_face<n, (GEN > 0)>(g, e, s, 0, 0);
   if (f0.master && (f.flag[e] || f.flag[nb])) f.faces[atomicAdd(&f.count[1], 1)] = q;
 }
 
@@ -1911,7 +1911,7 @@ __global__ void __launch_bounds__(FvFaceSz<N>::NT) k_fv_face(Geo g, Phys ph, FvG
   for (int it = blockIdx.x; it < nf; it += gridDim.x) {
     const int q = f.faces[it], e = q / 6, s = q - 6 * e;
     const int nb = g.nbr[q];
-    const NbFace fm = nbr_face<n, GEN>(g, e, s, a, b);
+    const NbFace fm = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
     const int ns = GEN ? 2 * fm.dn + (fm.plus ? 1 : 0) : (s ^ 1);
     const int a2 = fm.a, b2 = fm.b;
     const bool fe = f.flag[e], fn = f.flag[nb];
@@ -2013,9 +2013,8 @@ __global__ void __launch_bounds__(Sz<N>::NT, 4) k_fv_volume(Geo g, Phys ph, FvGe
                                                          double cb, double dt) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
-  __shared__ double sW[5 * n3];   // primitive subcell means
-  __shared__ double sL[5 * n3];   // reconstructed state at each subcell's +face (then its flux)
-  __shared__ double sR[5 * n3];   // reconstructed state at each subcell's -face
+  __shared__ double sW[5 * n3];  // primitive subcell means
+  __shared__ double sF[5 * n3];  // flux through each subcell's + face (inner faces)
   const int t = threadIdx.x;
   const bool act = t < n3;
   const double gm1 = ph.gamma - 1.0;
@@ -2034,57 +2033,59 @@ __global__ void __launch_bounds__(Sz<N>::NT, 4) k_fv_volume(Geo g, Phys ph, FvGe
     const int id3[3] = {t % n, (t / n) % n, t / n2};
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int dir = 0; dir < 3; ++dir) {
-      __syncthreads();
+      __syncthreads();  // sW is complete; the previous direction's reads of sF are done
       const int id = act ? id3[dir] : 0;
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
       const int a = dir == 0 ? id3[1] : id3[0], b = dir == 2 ? id3[1] : id3[2];
       const int ab = a + n * b;
-      if (act) {
-        double Wl[5], Wr[5];
+      if (act && id < N) {
+        // inner face id + 1/2 between subcells c0 = id and c1 = id + 1 along dir: the two
+        // reconstructed states from the stencil c0 - 1 .. c1 + 1, whose ends beyond the element
+        // are the outer face data of its sides
+        double Wm[5], Wp[5];
         if (id > 0) {
-          for (int v = 0; v < 5; ++v) Wl[v] = sW[v * n3 + t - str];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Wm[v] = sW[v * n3 + t - str];
         } else {
           double Do[5];
           const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir) * 5 * n2 + ab;
+#pragma unroll
           for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
-          fv_prim(Do, gm1, Wl);
+          fv_prim(Do, gm1, Wm);
         }
-        if (id < N) {
-          for (int v = 0; v < 5; ++v) Wr[v] = sW[v * n3 + t + str];
+        if (id + 1 < N) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Wp[v] = sW[v * n3 + t + 2 * str];
         } else {
           double Do[5];
           const double *dx = f.Dx + ((size_t)e * 6 + 2 * dir + 1) * 5 * n2 + ab;
+#pragma unroll
           for (int v = 0; v < 5; ++v) Do[v] = dx[v * n2];
-          fv_prim(Do, gm1, Wr);
+          fv_prim(Do, gm1, Wp);
         }
+        double UL[5], UR[5];
+        {
+          double WL[5], WR[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const double w0 = sW[v * n3 + t];
-          const double sg = fv_limit(f.limiter, w0 - Wl[v], Wr[v] - w0);
-          sL[v * n3 + t] = w0 + 0.5 * sg;
-          sR[v * n3 + t] = w0 - 0.5 * sg;
+          for (int v = 0; v < 5; ++v) {
+            const double w0 = sW[v * n3 + t], w1 = sW[v * n3 + t + str];
+            WL[v] = w0 + 0.5 * fv_limit(f.limiter, w0 - Wm[v], w1 - w0);
+            WR[v] = w1 - 0.5 * fv_limit(f.limiter, w1 - w0, Wp[v] - w1);
+          }
+          fv_cons(WL, gm1, UL);
+          fv_cons(WR, gm1, UR);
         }
-      }
-      __syncthreads();
-      if (act && id < N) {
-        // inner face id + 1/2 between this subcell and the next along dir
-        double WL[5], WR[5], UL[5], UR[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) { WL[v] = sL[v * n3 + t]; WR[v] = sR[v * n3 + t + str]; }
-        fv_cons(WL, gm1, UL);
-        fv_cons(WR, gm1, UR);
         const double *Nm = f.Nf + ((((size_t)e * 3 + dir) * (n + 1) + id + 1) * n2 + ab) * 3;
         const double sh = sqrt(Nm[0] * Nm[0] + Nm[1] * Nm[1] + Nm[2] * Nm[2]);
         const double ish = 1.0 / sh;
         const double nh[3] = {Nm[0] * ish, Nm[1] * ish, Nm[2] * ish};
         double F[5];
         riemann_t<RS>(ph, UL, UR, nh, F);
-        // the flux replaces this subcell's +face state in sL (no other thread reads that slot
-        // in this phase); it is the subcell's outward flux on its + face
+        // the subcell's outward flux on its + face; the next subcell's - face reads it from sF
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           const double fp = sh * F[v];
-          sL[v * n3 + t] = fp;
+          sF[v * n3 + t] = fp;
           acc[v] += fp;
         }
       }
@@ -2096,7 +2097,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, 4) k_fv_volume(Geo g, Phys ph, FvGe
         for (int v = 0; v < 5; ++v) {
           // outward fluxes of the subcell: + face (above for inner faces), then - face
           if (id == N) acc[v] += fx1[v * n2];
-          acc[v] += (id > 0) ? -sL[v * n3 + t - str] : fx0[v * n2];
+          acc[v] += (id > 0) ? -sF[v * n3 + t - str] : fx0[v * n2];
         }
       }
     }
@@ -2244,21 +2245,22 @@ static int launch_main_t(const Geo &g, const Phys &ph, const double *U, const do
   if constexpr (!NS) {
     if (g.fvflag) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
       else
-        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+        hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
       DG_CHECK_LAUNCH();
       return DG_OK;
     }
   }
-  if (mode == 0 && !gen)
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 0, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else if (!gen)
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else
-    hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  // GEN: 0 structured, 1 face codes, 2 face codes and non-conforming faces
+  const int lev = !gen ? 0 : (g.mslot ? 2 : 1);
+#define DG_KM(M_, G_) hipLaunchKernelGGL((k_main<N, LGL, NS, FORM, M_, G_>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt)
+  if (mode == 0) {
+    if (lev == 0) DG_KM(0, 0); else if (lev == 1) DG_KM(0, 1); else DG_KM(0, 2);
+  } else {
+    if (lev == 0) DG_KM(1, 0); else if (lev == 1) DG_KM(1, 1); else DG_KM(1, 2);
+  }
+#undef DG_KM
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -2271,21 +2273,22 @@ static int launch_split_t(const Geo &g, const Phys &ph, const double *U, const d
   if constexpr (!NS) {
     if (g.fvflag) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_split<N, NS, VF, 0, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+        hipLaunchKernelGGL((k_split<N, NS, VF, 0, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
       else
-        hipLaunchKernelGGL((k_split<N, NS, VF, 1, true, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+        hipLaunchKernelGGL((k_split<N, NS, VF, 1, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
       DG_CHECK_LAUNCH();
       return DG_OK;
     }
   }
-  if (mode == 0 && !gen)
-    hipLaunchKernelGGL((k_split<N, NS, VF, 0, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_split<N, NS, VF, 0, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else if (!gen)
-    hipLaunchKernelGGL((k_split<N, NS, VF, 1, false>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
-  else
-    hipLaunchKernelGGL((k_split<N, NS, VF, 1, true>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt);
+  // GEN: 0 structured, 1 face codes, 2 face codes and non-conforming faces
+  const int lev = !gen ? 0 : (g.mslot ? 2 : 1);
+#define DG_KS(M_, G_) hipLaunchKernelGGL((k_split<N, NS, VF, M_, G_>), grid, block, 0, st, g, ph, U, G, out, R, a, b, dt)
+  if (mode == 0) {
+    if (lev == 0) DG_KS(0, 0); else if (lev == 1) DG_KS(0, 1); else DG_KS(0, 2);
+  } else {
+    if (lev == 0) DG_KS(1, 0); else if (lev == 1) DG_KS(1, 1); else DG_KS(1, 2);
+  }
+#undef DG_KS
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
@@ -2308,18 +2311,23 @@ template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st) {
   dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
-  const bool gen = g.fc != nullptr;
+  // GEN: 0 structured, 1 face codes, 2 face codes and non-conforming faces
+  const int lev = g.fc == nullptr ? 0 : (g.mslot ? 2 : 1);
+#define DG_KL(L_, O_) \
+  do { \
+    if (lev == 0) hipLaunchKernelGGL((k_lift<N, L_, O_, 0>), grid, block, 0, st, g, ph, U, G, Fv); \
+    else if (lev == 1) hipLaunchKernelGGL((k_lift<N, L_, O_, 1>), grid, block, 0, st, g, ph, U, G, Fv); \
+    else hipLaunchKernelGGL((k_lift<N, L_, O_, 2>), grid, block, 0, st, g, ph, U, G, Fv); \
+  } while (0)
   if (!lgl) {
     if (out != LIFT_G) return DG_ERR_UNSUPPORTED;
-    if (gen) hipLaunchKernelGGL((k_lift<N, false, LIFT_G, true>), grid, block, 0, st, g, ph, U, G, Fv);
-    else hipLaunchKernelGGL((k_lift<N, false, LIFT_G, false>), grid, block, 0, st, g, ph, U, G, Fv);
+    DG_KL(false, LIFT_G);
   } else if (out == LIFT_G) {
-    if (gen) hipLaunchKernelGGL((k_lift<N, true, LIFT_G, true>), grid, block, 0, st, g, ph, U, G, Fv);
-    else hipLaunchKernelGGL((k_lift<N, true, LIFT_G, false>), grid, block, 0, st, g, ph, U, G, Fv);
+    DG_KL(true, LIFT_G);
   } else {
-    if (gen) hipLaunchKernelGGL((k_lift<N, true, LIFT_FV, true>), grid, block, 0, st, g, ph, U, G, Fv);
-    else hipLaunchKernelGGL((k_lift<N, true, LIFT_FV, false>), grid, block, 0, st, g, ph, U, G, Fv);
+    DG_KL(true, LIFT_FV);
   }
+#undef DG_KL
   DG_CHECK_LAUNCH();
   return DG_OK;
 }
