@@ -222,8 +222,10 @@ int dg_rhs(dg_handle *h, const double *U, double *Ut);
 int dg_rk_stage(dg_handle *h, const double *U_in, double *U_out, double *R, double a, double b, double dt);
 
 /* Vector-Jacobian product of the operator: U_bar = (dL/dU)(U)^T Ut_bar (overwritten).
- * Supported for the split form on LGL nodes (KEP, EC or central volume flux) on every conforming mesh
- * dg_init accepts, without finite-volume subcells, and N <= 7 (DG_ERR_UNSUPPORTED otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
+ * Supported for the split form on LGL nodes (KEP, EC or central volume flux; Euler or
+ * Navier-Stokes) and for the weak form of the Euler equations on LG or LGL nodes, on every
+ * conforming mesh dg_init accepts, without finite-volume subcells, N = 1..8 (DG_ERR_UNSUPPORTED
+ * otherwise); the derivative of |x| at 0 and of max at a tie is the mean of the
  * one-sided derivatives, the log means of the EC flux are differentiated with the forward's
  * branch threshold (series below ((a-b)/(a+b))^2 = 1e-4, logarithms above).  Device arrays [K][5][n^3], pairwise distinct.
  * Not in the paper: the reverse of its operator, for gradients of objectives of U. */

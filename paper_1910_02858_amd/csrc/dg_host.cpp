@@ -1396,8 +1396,10 @@ namespace {
 // they are recomputed into the handle's scratch
 int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, double scale, int accumulate,
                  const double *Gin = nullptr, double *Rb = nullptr, double ra = 0.0, double rb = 0.0) {
-  if (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT)
-    return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for the split form on LGL nodes");
+  const bool weak_euler = h->sc.form == DG_FORM_WEAK && h->sc.eqn == DG_EULER;
+  if (!weak_euler && (h->node_type != DG_NODES_LGL || h->sc.form != DG_FORM_SPLIT))
+    return fail(h, DG_ERR_UNSUPPORTED,
+                "the vector-Jacobian product is built for the split form on LGL nodes and the Euler weak form");
   if (h->nm)
     return fail(h, DG_ERR_UNSUPPORTED, "the vector-Jacobian product is built for conforming meshes");
   if (h->fv_on)
@@ -1417,7 +1419,8 @@ int vjp_dispatch(dg_handle *h, const double *U, const double *Utb, double *Ub, d
   int rc;
   switch (h->N) {
 #define DG_CASE(NN) \
-  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, U, Gin, h->d_Pf, Utb, Ub, scale, accumulate, \
+  case NN: rc = dg::launch_vjp<NN>(g, h->ph, h->sc.eqn, h->sc.form, h->node_type == DG_NODES_LGL, U, Gin, h->d_Pf, \
+                                   Utb, Ub, scale, accumulate, \
                                    ns ? Rb : nullptr, ra, rb, h->stream); break;
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE

@@ -99,7 +99,7 @@ int launch_main(const Geo &g, const Phys &ph, bool lgl, int eqn, int form, const
 // (Navier-Stokes); for Navier-Stokes with Rb != NULL the second reverse kernel then also sets
 // Rb = ra Rb + rb Ubar (Euler: the caller updates Rb)
 template <int N>
-int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Pf,
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, bool lgl, const double *U, const double *G, double *Pf,
                const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
                hipStream_t st);
 template <int N>

@@ -558,17 +558,210 @@ __global__ void __launch_bounds__(VSz<N>::NT) k_vjp_face(Geo g, Phys ph, const d
   }
 }
 
+// ---------------------------------------------------------------------------------- weak form
+// Reverse of the weak form (Sec. 3.1, eq. semiDiscreteWeak) for the Euler equations on LG or LGL
+// nodes.  The forward operator is
+//   U_t,i = -(1/J_i) [ sum_dir sum_m Dhat_{id m} F^dir(U_m) + sum_faces lhat_face(i) f*_face ],
+// with F^dir the contravariant Euler flux along Ja^dir_m at node m, f*_face the outward numerical
+// flux times the surface element at the face point of node i's line (one value per face, the
+// master's, entering the slave negated), evaluated from the two sides' traces prolonged with
+// l(+-1) (LG) or read at the face nodes (LGL).  With Abar = -(1/J) Utbar:
+//   * volume: Gbar^dir_m = sum_i Dhat_{id_i m} Abar_i along the line, then the flux Jacobian's
+//     transpose at node m;
+//   * faces: fbar = sg (sum_i lhat(i) Abar_i on this element's line - the same on the
+//     neighbour's), the Riemann solver's transposed Jacobian in this element's own trace only
+//     (the neighbour does the same for its trace), then the prolongation transposed onto the
+//     line (LG) or the face node (LGL); a boundary side's outer state is a function of the own
+//     trace and its adjoint comes back through that map.
+// Nothing is written into another element.
+template <int N, bool LGL, bool GEN>
+__global__ void __launch_bounds__(VSz<N>::NT) k_vjp_weak(Geo g, Phys ph, const double *__restrict__ U,
+                                                         const double *__restrict__ Utb, double *__restrict__ Ub,
+                                                         double scale, int accumulate) {
+  using S = VSz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  __shared__ double sA[5 * n3];   // Abar = -(1/J) Utbar
+  __shared__ double sU[5 * n3];   // the element's state
+  __shared__ double sT[30 * n2];  // conservative adjoint of the own trace at every face point
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  const int e = xcd_element(blockIdx.x, g.K), t = threadIdx.x;
+  if (e >= g.K) return;
+  const bool act = t < n3;
+  const double gamma = ph.gamma, gm1 = gamma - 1.0, g1 = gamma / gm1;
+  const Tab *tb = g.tab;
+  for (int c = t; c < n * n; c += NT) sDh[c] = tb->Dh[c];
+  if (t < n) {
+    sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
+    slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
+  }
+  const double *Ue = U + (size_t)e * 5 * n3;
+  double Uo[5];
+  if (act) {
+    const double sj = g.sJ[(size_t)e * n3 + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Uo[v] = Ue[v * n3 + t];
+      sU[v * n3 + t] = Uo[v];
+      sA[v * n3 + t] = -sj * Utb[((size_t)e * 5 + v) * n3 + t];
+    }
+  }
+  __syncthreads();
+  for (int p = t; p < 6 * n2; p += NT) {
+    const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const bool plus = s & 1;
+    const NbFace f = nbr_face<n, GEN>(g, e, s, a, b);
+    const bool bnd = GEN && f.bnd;
+    const int nb = bnd ? e : g.nbr[(size_t)e * 6 + s];
+    const int ns = GEN ? 2 * f.dn + (f.plus ? 1 : 0) : (s ^ 1);
+    const bool nplus = ns & 1;
+    // own and neighbour traces, and the weights of both sides' lines in the face adjoint
+    double Uw[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, Ux[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double Ao[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, An[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double *lo = sl + (plus ? n : 0), *ln = sl + (nplus ? n : 0);
+    const double *lho = slh + (plus ? n : 0), *lhn = slh + (nplus ? n : 0);
+    const double *Un = U + (size_t)nb * 5 * n3;
+    const double *Utn = Utb + (size_t)nb * 5 * n3;
+    const double *sJn = g.sJ + (size_t)nb * n3;
+#pragma unroll 1
+    for (int m = 0; m < n; ++m) {
+      if (LGL && m != (plus ? N : 0) && m != (nplus ? N : 0)) continue;
+      const int q = vline_node<n>(dn, a, b, m);
+      if (!LGL || m == (plus ? N : 0)) {
+        const double wo = LGL ? 1.0 : lo[m], who = lho[m];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          Uw[v] += wo * sU[v * n3 + q];
+          Ao[v] += who * sA[v * n3 + q];
+        }
+      }
+      if (!bnd && (!LGL || m == (nplus ? N : 0))) {
+        const int qn = vline_node<n>(f.dn, f.a, f.b, m);
+        const double wn = LGL ? 1.0 : ln[m], whn = lhn[m];
+        const double sjn = sJn[qn];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          Ux[v] += wn * Un[v * n3 + qn];
+          An[v] += whn * (-sjn * Utn[v * n3 + qn]);
+        }
+      }
+    }
+    const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+    const bool mst = GEN ? f.master : plus;
+    const double sg = mst ? 1.0 : -1.0;
+    const double nt[3] = {sg * fnp[0], sg * fnp[n2], sg * fnp[2 * n2]};
+    const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    const double ish = 1.0 / sh;
+    const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+    const bool outflow = bnd && f.kind == DG_BC_OUTFLOW;
+    const bool given = bnd && (f.kind == DG_BC_STATE || outflow);
+    const bool wall = bnd && (f.kind == DG_BC_WALL || f.kind == DG_BC_WALL_ISOTHERMAL);
+    if (outflow) {
+      Ux[0] = Uw[0]; Ux[1] = Uw[1]; Ux[2] = Uw[2]; Ux[3] = Uw[3];
+      Ux[4] = ph.pout / gm1 + 0.5 * (Uw[1] * Uw[1] + Uw[2] * Uw[2] + Uw[3] * Uw[3]) / Uw[0];
+    } else if (given) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ux[v] = ph.ub[v];
+    } else if (wall) {
+      Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
+    } else if (bnd) {
+      const double mn = 2.0 * (Uw[1] * nh[0] + Uw[2] * nh[1] + Uw[3] * nh[2]);
+      Ux[0] = Uw[0]; Ux[4] = Uw[4];
+      Ux[1] = Uw[1] - mn * nh[0]; Ux[2] = Uw[2] - mn * nh[1]; Ux[3] = Uw[3] - mn * nh[2];
+    }
+    // adjoint of the master's flux value (times s-hat): this element enters it with sign sg, the
+    // neighbour with -sg
+    double Fb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fb[v] = sg * sh * (Ao[v] - An[v]);
+    const double *UM = mst ? Uw : Ux, *US = mst ? Ux : Uw;
+    const dgf::P PM = dgf::prim(UM, gm1), PS = dgf::prim(US, gm1);
+    double bM[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, bS[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    dgf::riemann_adj(ph.rs, ph.vf, PM, PS, UM, US, nh, gamma, Fb, bM, bS);
+    double bw[5], bx[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { bw[v] = mst ? bM[v] : bS[v]; bx[v] = mst ? bS[v] : bM[v]; }
+    if (outflow) {
+      // outer state (rho, m, p_out/(gamma-1) + |m|^2/(2 rho)) of the own trace
+      const double ir = 1.0 / Uw[0];
+      const double k2 = (Uw[1] * Uw[1] + Uw[2] * Uw[2] + Uw[3] * Uw[3]) * ir * ir;
+      bw[0] += bx[0] - 0.5 * k2 * bx[4];
+      bw[1] += bx[1] + Uw[1] * ir * bx[4];
+      bw[2] += bx[2] + Uw[2] * ir * bx[4];
+      bw[3] += bx[3] + Uw[3] * ir * bx[4];
+    } else if (wall) {
+      bw[0] += bx[0]; bw[1] -= bx[1]; bw[2] -= bx[2]; bw[3] -= bx[3]; bw[4] += bx[4];
+    } else if (bnd && !given) {
+      // mirror image: the reflection is its own transpose
+      const double mn = 2.0 * (bx[1] * nh[0] + bx[2] * nh[1] + bx[3] * nh[2]);
+      bw[0] += bx[0]; bw[4] += bx[4];
+      bw[1] += bx[1] - mn * nh[0]; bw[2] += bx[2] - mn * nh[1]; bw[3] += bx[3] - mn * nh[2];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sT[(s * 5 + v) * n2 + ab] = bw[v];
+  }
+  __syncthreads();
+  if (act) {
+    const int id3[3] = {t % n, (t / n) % n, t / n2};
+    const dgf::P q = dgf::prim(Uo, gm1);
+    dgf::PA pa = dgf::zero_pa();
+    double ub[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double *Jae = g.Ja + (size_t)e * 9 * n3;
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      const int id = id3[dir];
+      const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
+      const int base = t - id * str;
+      // volume: Gbar = sum over the line of Dhat_{id_i, id} Abar_i
+      double Gb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int m = 0; m < n; ++m) {
+        const double d = sDh[m * n + id];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Gb[v] += d * sA[v * n3 + base + m * str];
+      }
+      const double nv[3] = {Jae[(dir * 3) * n3 + t], Jae[(dir * 3 + 1) * n3 + t], Jae[(dir * 3 + 2) * n3 + t]};
+      dgf::euler_flux_adj(q, nv, g1, Gb, pa);
+      // faces of this direction: the own trace's adjoint prolonged back onto this node
+      const int fa = dir == 0 ? id3[1] : id3[0], fb = dir == 2 ? id3[1] : id3[2];
+      const int ab = fa + n * fb;
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int s = 2 * dir + sd;
+        double w;
+        if (LGL) w = (id == (sd ? N : 0)) ? 1.0 : 0.0;
+        else w = sl[(sd ? n : 0) + id];
+        if (w == 0.0) continue;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ub[v] += w * sT[(s * 5 + v) * n2 + ab];
+      }
+    }
+    dgf::cons_adj(q, gm1, pa, ub);
+    double *Ube = Ub + (size_t)e * 5 * n3;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double r = scale * ub[v];
+      Ube[v * n3 + t] = accumulate ? Ube[v * n3 + t] + r : r;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------- launcher
 template <int N>
-int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U, const double *G, double *Pf,
+int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, bool lgl, const double *U, const double *G, double *Pf,
                const double *Ubar_t, double *Ubar, double scale, int accumulate, double *Rb, double ra, double rb,
                hipStream_t st) {
-  if (form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
-  if constexpr (N > 7) {
-    return DG_ERR_UNSUPPORTED;  // the reverse kernel's LDS staging exceeds 160 KB beyond N = 7
-  } else {
-  dim3 grid(xcd_grid(g.K)), block(VSz<N>::NT);
   const bool gen = g.fc != nullptr;
+  if (form == DG_FORM_WEAK) {
+    if (eqn != DG_EULER) return DG_ERR_UNSUPPORTED;
+    const dim3 grid(xcd_grid(g.K)), block(VSz<N>::NT);
+    if (lgl && gen) hipLaunchKernelGGL((k_vjp_weak<N, true, true>), grid, block, 0, st, g, ph, U, Ubar_t, Ubar, scale, accumulate);
+    else if (lgl) hipLaunchKernelGGL((k_vjp_weak<N, true, false>), grid, block, 0, st, g, ph, U, Ubar_t, Ubar, scale, accumulate);
+    else if (gen) hipLaunchKernelGGL((k_vjp_weak<N, false, true>), grid, block, 0, st, g, ph, U, Ubar_t, Ubar, scale, accumulate);
+    else hipLaunchKernelGGL((k_vjp_weak<N, false, false>), grid, block, 0, st, g, ph, U, Ubar_t, Ubar, scale, accumulate);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
+  }
+  if (form != DG_FORM_SPLIT) return DG_ERR_UNSUPPORTED;
+  {
+  dim3 grid(xcd_grid(g.K)), block(VSz<N>::NT);
   if (eqn == DG_NAVIER_STOKES) {
     if (gen)
       hipLaunchKernelGGL((k_vjp_main<N, true, true>), grid, block, 0, st, g, ph, U, G, Ubar_t, Ubar, Pf, scale,
@@ -595,7 +788,7 @@ int launch_vjp(const Geo &g, const Phys &ph, int eqn, int form, const double *U,
 }
 
 #ifdef DG_ONLY_N
-template int launch_vjp<DG_ONLY_N>(const Geo &, const Phys &, int, int, const double *, const double *, double *,
+template int launch_vjp<DG_ONLY_N>(const Geo &, const Phys &, int, int, bool, const double *, const double *, double *,
                                    const double *, double *, double, int, double *, double, double, hipStream_t);
 #endif
 
