@@ -10,7 +10,7 @@ Prints one JSON line.  value = DOF-updates/s = nodes * steps * 5 / wall (DOF cou
 variable, as the paper's performance index does); PID = 1/value seconds per DOF per stage.
 The roofline object is for the dominant kernel, timed with HIP events on the library's
 stream over extra profiled stages after the timed region; its algorithmic bytes are the
-compulsory HBM traffic per node (42 doubles read+write for the main kernel, 27 for the
+compulsory HBM traffic per node (37 doubles read+write for the main kernel, 22 for the
 lifting kernel).  cpu_baseline is the FP64 oracle on the host cores on a bounded sample.
 """
 from __future__ import annotations
@@ -29,8 +29,14 @@ if ROOT not in sys.path:
 
 METRIC = "DOF-updates/s (PID s/DOF/stage) at N=7 TGV; adjoint/forward cost ratio"
 HBM_PEAK_GBS = 8000.0
-BYTES_MAIN = 42 * 8   # U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
-BYTES_LIFT = 27 * 8   # U 5 + Ja 9 + 1/J 1 read, grad W 12 written
+# split-form operator at N = 7: U 5 + viscous divergence 4 + own face traces of the viscous
+# fluxes 3 (24 n^2 values per element, n = 8) + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
+BYTES_MAIN = 37 * 8
+# lifting for the split form: U 5 + Ja 9 + 1/J 1 read, viscous divergence 4 + face traces 3 written
+BYTES_LIFT = 22 * 8
+# weak-form operator with BR1 gradients: U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5
+# written
+BYTES_GRAD_MAIN = 42 * 8
 # reverse stage: k_vjp_main reads U 5, the kept viscous fluxes' momentum part 9, Ja 9, 1/J 1,
 # Ubar_t 5, Ubar 5 and writes Ubar 5; k_vjp_face reads Ubar 5, Rbar 5 and writes Rbar 5
 BYTES_VJP_MAIN = 39 * 8
@@ -302,7 +308,7 @@ def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
     out = {}
     for name, wl, nbytes in (("euler_dwave_lg3_k96_weak", inputs.workload(1, K1=96), 30 * 8),
                              ("ns_tgv_central_roe_lg7_k48_weak",
-                              inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=48), BYTES_MAIN)):
+                              inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=48), BYTES_GRAD_MAIN)):
         S, U = dgsem.build_solver(wl)
         dt = S.timestep(U, wl.cfl, wl.dfl)
         a, b, _ = dgsem.rk_coefficients()

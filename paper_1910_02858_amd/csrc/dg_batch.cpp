@@ -122,6 +122,7 @@ std::vector<dg::Member> describe(const dg_batch *b, const double *const *U_in, d
       dg::Member d;
       std::memset(&d, 0, sizeof(d));
       d.g.Ja = h->d_Ja; d.g.sJ = h->d_sJ; d.g.fn = h->d_fn; d.g.nbr = h->d_nbr; d.g.fc = h->d_fc; d.g.tab = h->d_tab; d.g.K = h->K;
+      d.g.Gd = h->d_Gd; d.g.Gf = h->d_Gf;
       d.ph.gamma = h->ph.gamma; d.ph.R = h->ph.R; d.ph.mu = h->ph.mu; d.ph.Pr = h->ph.Pr;
       d.ph.kappa = h->ph.kappa; d.ph.vf = h->ph.vf; d.ph.rs = h->ph.rs;
       for (int v = 0; v < 5; ++v) d.ph.ub[v] = h->ph.ub[v];

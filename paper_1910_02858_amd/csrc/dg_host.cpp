@@ -622,8 +622,10 @@ int fv_dispatch(dg_handle *h, int what, const double *U, double *out, double *R,
 }
 
 // lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on.  The
-// split form takes the contravariant viscous fluxes, the other forms the gradients, in the
-// handle's scratch or, if Gkeep != NULL, in Gkeep (kept for a later reverse sweep).
+// split form takes the strong-form divergence and face traces of the contravariant viscous
+// fluxes (Geo::Gd, Gf), or on meshes with non-conforming faces the fluxes themselves; the other
+// forms take the gradients.  Fluxes and gradients go to the handle's scratch or, if
+// Gkeep != NULL, to Gkeep (kept for a later reverse sweep).
 int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode,
                  double *Gkeep = nullptr) {
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
@@ -636,7 +638,9 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
       if (rc) return rc;
     }
     double *dst = Gkeep ? Gkeep : h->d_G;
-    const int rc = split ? lift_dispatch(h, U, 1, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
+    // lifting outputs: 0 gradients, 1 fluxes, 2 divergence, 3 divergence and fluxes
+    const int out = !split ? 0 : (h->nm ? 1 : (Gkeep ? 3 : 2));
+    const int rc = split ? lift_dispatch(h, U, out, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
@@ -835,6 +839,10 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc && !fc.empty()) rc = dev_alloc(&h->d_fc, fc.size());
   if (!rc) rc = dev_alloc(&h->d_tab, 1);
   if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
+  if (!rc && ns && sc->form == DG_FORM_SPLIT && h->nm == 0) {
+    rc = dev_alloc(&h->d_Gd, (size_t)K * 4 * n3);
+    if (!rc) rc = dev_alloc(&h->d_Gf, (size_t)K * 24 * n2);
+  }
   if (!rc) rc = dev_alloc(&h->d_partial, (size_t)K * 8);
   if (!rc) rc = dev_alloc(&h->d_red, 8);
   if (!rc && h->nm) {
@@ -1382,7 +1390,7 @@ void dg_destroy(dg_handle *h) {
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_fc); (void)hipFree(h->d_tab);
-  (void)hipFree(h->d_G); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
+  (void)hipFree(h->d_G); (void)hipFree(h->d_Gd); (void)hipFree(h->d_Gf); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
   (void)hipFree(h->d_md); (void)hipFree(h->d_mslot); (void)hipFree(h->d_mflux); (void)hipFree(h->d_mlift);
   (void)hipFree(h->d_mg);
   (void)hipFree(h->d_fvtab); (void)hipFree(h->d_fvJbar); (void)hipFree(h->d_fvNf); (void)hipFree(h->d_fvFx);

@@ -60,6 +60,11 @@ struct Geo {
   // fluxes [K][6][5][n^2] of the sides of faces that touch a finite-volume element
   const uint8_t *fvflag;
   const double *fvFx;
+  // split form, Navier-Stokes, conforming faces (NULL otherwise): the lifting's viscous terms as
+  // the operator reads them, the strong-form divergence Gd[e][c][node] = sum_dir (sum_m D_{id,m}
+  // Fv^dir_c(node m of the line) -+ lhat(+-1) Fv^dir_c on a +-face node) (c: momentum x, y, z,
+  // energy) and every side's face trace Gf[e][s][c][face point] = Fv^{dir(s)}_c at the face node
+  double *Gd, *Gf;
 };
 
 // Finite-volume subcells (Sec. 4) of one mesh on the device.
@@ -245,6 +250,7 @@ struct dg_handle {
   double *d_fvtab = nullptr, *d_fvJbar = nullptr, *d_fvNf = nullptr, *d_fvFx = nullptr, *d_fvDx = nullptr;
   double *d_fvind = nullptr;
   uint8_t *d_fvflag = nullptr;
+  double *d_Gd = nullptr, *d_Gf = nullptr;  // viscous volume term and face traces (Geo::Gd, Gf)
   int *d_fvlist = nullptr;  // work lists of the hybrid kernels: [K] elements, [3K] sides, [2] counts
   int *d_fvfaces = nullptr;
   int *d_fvcount = nullptr;
@@ -276,6 +282,7 @@ struct dg_handle {
     g.Ja = d_Ja; g.sJ = d_sJ; g.fn = d_fn; g.nbr = d_nbr; g.fc = d_fc; g.tab = d_tab; g.K = K;
     g.mslot = d_mslot; g.mflux = d_mflux; g.mlift = d_mlift; g.mg = d_mg;
     g.fvflag = fv_on ? d_fvflag : nullptr; g.fvFx = fv_on ? d_fvFx : nullptr;
+    g.Gd = d_Gd; g.Gf = d_Gf;
     return g;
   }
 };

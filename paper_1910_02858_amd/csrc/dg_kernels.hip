@@ -288,14 +288,20 @@ __device__ __forceinline__ void grad_prim_to_W(const double *U, double gm1, doub
 // LDS sizes (doubles) of one element in the lifting kernel
 template <int N> struct LiftLds {
   static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
-  static constexpr int W = 4 * n3, JA = 3 * n3, WS = 24 * n2;
+  // the three regions together hold 12 values per node at the end (the staged viscous fluxes of
+  // LIFT_DIV)
+  static constexpr int W = 4 * n3, JA = 3 * n3, WS = (24 * n2 > 5 * n3) ? 24 * n2 : 5 * n3;
 };
 
 // 1D tables of the lifting kernel into LDS (by the first threads of the workgroup)
 template <int N>
-__device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, double *sDh, double *sl, double *slh) {
+__device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, double *sDh, double *sl, double *slh,
+                                            double *sD = nullptr) {
   constexpr int n = N + 1;
-  for (int c = t; c < n * n; c += nthreads) sDh[c] = tb->Dh[c];
+  for (int c = t; c < n * n; c += nthreads) {
+    sDh[c] = tb->Dh[c];
+    if (sD) sD[c] = tb->D[c];
+  }
   if (t < n) {
     sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
     slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
@@ -306,16 +312,33 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // threads in step with the workgroup barriers without touching memory.
 // OUT: LIFT_G writes the gradients G[e][d*4+c][node] = dW_c/dx_d (weak and strong forms);
 // LIFT_FV writes instead the contravariant viscous fluxes Fv[e][dir*4+c][node] =
-// (F^v . Ja^dir)_{1+c} (momentum, energy) that the split-form kernels and their reverse consume.
-enum { LIFT_G = 0, LIFT_FV = 1 };
+// (F^v . Ja^dir)_{1+c} (momentum, energy), which the reverse sweep and the split-form kernels on
+// meshes with non-conforming faces consume; LIFT_DIV writes what the split-form operator reads
+// on conforming meshes, the volume term Geo::Gd (sum over the lines of D times Fv^dir) and the
+// face traces Geo::Gf of Fv; LIFT_DIVK writes both (the stage kept for a reverse sweep).
+enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3 };
 
+// LDS slot of node (i, j, k) in one component array of the viscous divergence stage.  For n = 8
+// the index bits are swizzled so that the 64 lanes that read the m-th node of 64 different lines
+// hit distinct banks in each direction (and in node order): i is XORed with two bits of j and k,
+// j with the low bits of k.
+template <int n> __device__ __forceinline__ int div_slot(int i, int j, int k) {
+  if constexpr (n == 8) return (i ^ ((j >> 2) | ((k & 3) << 1))) + 8 * (j ^ (k & 3)) + 64 * k;
+  else return i + n * (j + n * k);
+}
+
+// sm: the slot's LiftLds<N> regions, contiguous (W, JA, WS); sD the differentiation matrix
+// (LIFT_DIV, LIFT_DIVK only).
 template <int N, bool LGL, int OUT, int GEN>
 __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                           const double *__restrict__ U, double *__restrict__ G,
-                                          double *__restrict__ Fv, double *sW, double *sJa, double *sWs,
-                                          const double *sDh, const double *sl, const double *slh) {
+                                          double *__restrict__ Fv, double *sm, const double *sDh,
+                                          const double *sl, const double *slh, const double *sD = nullptr) {
   using S = Sz<N>;
+  using L = LiftLds<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
+  constexpr bool FVO = OUT != LIFT_G;  // the viscous fluxes are formed
+  double *sW = sm, *sJa = sm + L::W, *sWs = sm + L::W + L::JA;
   const double gm1 = ph.gamma - 1.0;
   const double *Ue = U + (size_t)e * 5 * n3;
   // the metric terms of the next direction (at most 3 per thread) and, in the last direction, the
@@ -441,7 +464,8 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = 0.0;
   const int i = t % n, j = (t / n) % n, k = t / n2;
-  double jo[9];  // this node's metric terms, kept for the viscous fluxes (LIFT_FV)
+  double jo[9];  // this node's metric terms, kept for the viscous fluxes
+  double gd[4] = {0.0, 0.0, 0.0, 0.0};  // the viscous divergence (LIFT_DIV, LIFT_DIVK)
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir) {
     __syncthreads();
@@ -455,7 +479,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
     if (dir == 2 && valid && t < n3) sjn = g.sJ[(size_t)e * n3 + t];  // for the epilogue
     __syncthreads();
-    if (OUT == LIFT_FV && valid && t < n3) {
+    if (FVO && valid && t < n3) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) jo[dir * 3 + d] = sJa[d * n3 + t];
     }
@@ -554,7 +578,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
 #pragma unroll
       for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
     }
-    if (OUT == LIFT_FV) {
+    if (FVO) {
       // Newtonian stress with Stokes' hypothesis and Fourier heat flux, contracted with Ja^dir.
       // Every rounding step is spelled out (explicit fma, no contraction), so every kernel that
       // runs this lifting produces the same fluxes bit for bit.
@@ -567,20 +591,94 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       const double t02 = mu * (acc[8] + acc[2]);
       const double t12 = mu * (acc[9] + acc[6]);
       const double u = sW[t], v = sW[n3 + t], w = sW[2 * n3 + t];
-      double *Fe = Fv + (size_t)e * 12 * n3;
+      const double dT0 = acc[3], dT1 = acc[7], dT2 = acc[11];
+      // acc takes the fluxes: acc[dir * 4 + c] = Fv^dir_c
 #pragma unroll
       for (int dir = 0; dir < 3; ++dir) {
         const double *nv = jo + 3 * dir;
-        const double f0 = fma(t02, nv[2], fma(t01, nv[1], t00 * nv[0]));
-        const double f1 = fma(t12, nv[2], fma(t11, nv[1], t01 * nv[0]));
-        const double f2 = fma(t22, nv[2], fma(t12, nv[1], t02 * nv[0]));
-        const double q = fma(acc[11], nv[2], fma(acc[7], nv[1], acc[3] * nv[0]));
-        const double f3 = fma(ph.kappa, q, fma(f2, w, fma(f1, v, f0 * u)));
-        Fe[(dir * 4) * n3 + t] = f0;
-        Fe[(dir * 4 + 1) * n3 + t] = f1;
-        Fe[(dir * 4 + 2) * n3 + t] = f2;
-        Fe[(dir * 4 + 3) * n3 + t] = f3;
+        acc[dir * 4] = fma(t02, nv[2], fma(t01, nv[1], t00 * nv[0]));
+        acc[dir * 4 + 1] = fma(t12, nv[2], fma(t11, nv[1], t01 * nv[0]));
+        acc[dir * 4 + 2] = fma(t22, nv[2], fma(t12, nv[1], t02 * nv[0]));
+        const double q = fma(dT2, nv[2], fma(dT1, nv[1], dT0 * nv[0]));
+        acc[dir * 4 + 3] = fma(ph.kappa, q, fma(acc[dir * 4 + 2], w, fma(acc[dir * 4 + 1], v, acc[dir * 4] * u)));
       }
+      if (OUT == LIFT_FV || OUT == LIFT_DIVK) {
+        double *Fe = Fv + (size_t)e * 12 * n3;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) Fe[c * n3 + t] = acc[c];
+      }
+      if (OUT == LIFT_DIV || OUT == LIFT_DIVK) {
+        // the traces Fv^dir on the element's faces through this node, and their interior part
+        // -+lhat(+-1) Fv^dir of the surface term
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+          const int id = dir == 0 ? i : (dir == 1 ? j : k);
+          if (id != 0 && id != N) continue;
+          const bool plus = id == N;
+          const int s = 2 * dir + (plus ? 1 : 0);
+          const int ab = (dir == 0 ? j : i) + n * (dir == 2 ? j : k);
+          double *gf = g.Gf + ((size_t)e * 6 + s) * 4 * n2 + ab;
+          const double lh = slh[(plus ? n : 0) + id];
+          const double sl_ = plus ? -lh : lh;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            gf[c * n2] = acc[dir * 4 + c];
+            gd[c] = fma(sl_, acc[dir * 4 + c], gd[c]);
+          }
+        }
+      }
+    }
+  }
+  if constexpr (OUT == LIFT_DIV || OUT == LIFT_DIVK) {
+    // strong-form divergence of the viscous fluxes for the split-form operator:
+    // Gd_c = sum_dir (sum_m D_{id,m} Fv^dir_c(m on the line) + [face node] -+lhat(+-1) Fv^dir_c),
+    // the interior part of the surface term taken with the volume term.  The three regions are
+    // free once every thread is past its last read of them.
+    __syncthreads();
+    if (valid && t < n3) {
+      const int q = div_slot<n>(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[c * n3 + q] = acc[c];
+    }
+    __syncthreads();
+    // one line, one direction and two components per task: the line's values are read once and
+    // its n results written back in place (each LDS value is read once, not n times)
+    for (int task = valid ? t : 6 * n2; task < 6 * n2; task += NT) {
+      const int dir = task / (2 * n2), r = task - dir * 2 * n2, cp = r / n2, ln = r - cp * n2;
+      const int a = ln % n, b = ln / n;
+      double *s0 = sm + (dir * 4 + 2 * cp) * n3, *s1 = s0 + n3;
+      double f0[n], f1[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        const int q = dir == 0 ? div_slot<n>(m, a, b) : (dir == 1 ? div_slot<n>(a, m, b) : div_slot<n>(a, b, m));
+        f0[m] = s0[q];
+        f1[m] = s1[q];
+      }
+#pragma unroll 1
+      for (int id = 0; id < n; ++id) {
+        double o0 = 0.0, o1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+          const double D = sD[id * n + m];
+          o0 = fma(D, f0[m], o0);
+          o1 = fma(D, f1[m], o1);
+        }
+        const int q = dir == 0 ? div_slot<n>(id, a, b) : (dir == 1 ? div_slot<n>(a, id, b) : div_slot<n>(a, b, id));
+        s0[q] = o0;
+        s1[q] = o1;
+      }
+    }
+    __syncthreads();
+    if (valid && t < n3) {
+      const int q = div_slot<n>(i, j, k);
+#pragma unroll
+      for (int dir = 0; dir < 3; ++dir) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gd[c] += sm[(dir * 4 + c) * n3 + q];
+      }
+      double *Gde = g.Gd + (size_t)e * 4 * n3 + t;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Gde[c * n3] = gd[c];
     }
   }
 }
@@ -590,12 +688,13 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
-  __shared__ double sW[L::W], sJa[L::JA], sWs[L::WS];
-  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
-  lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
+  constexpr bool DIV = OUT == LIFT_DIV || OUT == LIFT_DIVK;
+  __shared__ double sm[L::W + L::JA + L::WS];
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n], sD[DIV ? n * n : 1];
+  lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh, DIV ? sD : nullptr);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  lift_body<N, LGL, OUT, GEN>(g, ph, e, true, threadIdx.x, U, G, Fv, sW, sJa, sWs, sDh, sl, slh);
+  lift_body<N, LGL, OUT, GEN>(g, ph, e, true, threadIdx.x, U, G, Fv, sm, sDh, sl, slh, sD);
 }
 
 // ----------------------------------------------------------------------------- operator
@@ -1079,7 +1178,11 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   double *sS = sA;           // rho, u, v, w, beta (EC) or H (KEP, central) per node
   double *sJ = sA + 5 * n3;  // Ja^i_d at (i*3+d)*n3 + node
   double *sF = sA;           // first: the contravariant viscous fluxes of the three directions
-  if (NS && act) {
+  // VD: on conforming meshes the lifting kernel has formed the viscous divergence (Geo::Gd) and
+  // the face traces of Fv (Geo::Gf); with non-conforming faces the fluxes Fv (G) are read here
+  constexpr bool VD = NS && GEN < 2;
+  const double *Gfe = VD ? g.Gf + (size_t)e * 24 * n2 : nullptr;
+  if (NS && !VD && act) {
     // staged before the face phase, so that their loads overlap with the neighbours' face reads
 #pragma unroll
     for (int c = 0; c < 12; ++c) sF[c * n3 + t] = Ge[c * n3 + t];
@@ -1115,6 +1218,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     const int qo = line_node<n>(dn, a, b, plus ? N : 0);
     const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
+    // this side's trace of Fv^dn at the face point (component c at fo[c * fs]) and the
+    // neighbour's trace of Fv^{f.dn} on its side of the face (fnb[c * fs])
+    const int fs = VD ? n2 : n3;
+    const double *fo = VD ? Gfe + s * 4 * n2 + ab : Ge + dn * 4 * n3 + qo;
+    const double *fnb = VD ? g.Gf + ((size_t)(bnd ? e : nb) * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b
+                           : Gn + f.dn * 4 * n3 + qn;
     double Uw[5], Ux[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = bnd ? Uw[v] : Un[v * n3 + qn]; }
@@ -1152,7 +1261,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       if (given) {
         // given outer state: the outer viscous flux equals the inner one
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[1 + c] -= Ge[(dn * 4 + c) * n3 + qo];
+        for (int c = 0; c < 4; ++c) F[1 + c] -= fo[c * fs];
       } else if (wall) {
         // no-slip wall: the outer momentum flux equals the inner one, the outer energy flux is
         // its negative (reversed velocity, mirrored heat flux), so the mean keeps the momentum;
@@ -1161,29 +1270,26 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
         double g3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          g3[c] = Ge[(dn * 4 + c) * n3 + qo];
+          g3[c] = fo[c * fs];
           F[1 + c] -= g3[c];
         }
         if (iso) {
           const double ir = 1.0 / Uw[0];
-          F[4] -= Ge[(dn * 4 + 3) * n3 + qo] - (g3[0] * Uw[1] + g3[1] * Uw[2] + g3[2] * Uw[3]) * ir;
+          F[4] -= fo[3 * fs] - (g3[0] * Uw[1] + g3[1] * Uw[2] + g3[2] * Uw[3]) * ir;
         }
       } else if (bnd) {
         // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
         // mean keeps the normal part of the momentum flux
-        const double gm = Ge[(dn * 4) * n3 + qo] * nh[0] + Ge[(dn * 4 + 1) * n3 + qo] * nh[1] +
-                          Ge[(dn * 4 + 2) * n3 + qo] * nh[2];
+        const double gm = fo[0] * nh[0] + fo[fs] * nh[1] + fo[2 * fs] * nh[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) F[1 + c] -= gm * nh[c];
       } else if (GEN) {
         const double sn = (f.plus != plus) ? 1.0 : -1.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + sn * Gn[(f.dn * 4 + c) * n3 + qn]);
+        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * fs] + sn * fnb[c * fs]);
       } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          F[1 + c] -= 0.5 * (Ge[(dn * 4 + c) * n3 + qo] + Gn[(dn * 4 + c) * n3 + qn]);
+        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * fs] + fnb[c * fs]);
       }
     }
 #pragma unroll
@@ -1226,7 +1332,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
 #pragma unroll
     for (int c = 0; c < 9; ++c) ja[c] = Jae[c * n3 + t];
   }
-  if (NS) {
+  if (NS && !VD) {
     // viscous part in strong form: -sum_a D_ia Fv^dir_a along each line, and -Fv.N_out lhat(+-1)
     // on the faces through the node.  The contravariant viscous fluxes of all three directions
     // (from the lifting kernel) are staged once in region A.
@@ -1345,6 +1451,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     }
   }
   if (act) {
+    if (VD) {
+      // viscous part in strong form, formed by the lifting kernel (loaded here: held through the
+      // rounds, these four values push the operator past its register budget)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[1 + c] -= g.Gd[((size_t)e * 4 + c) * n3 + t];
+    }
     const double sj = sjq;
     double *Oe = out + (size_t)e * 5 * n3;
     if (MODE == 0) {
@@ -1396,10 +1508,10 @@ __device__ __forceinline__ int member_of(const int *first, int count, int item) 
 template <int N, int EPB, bool GEN>
 __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchView bv) {
   using L = LiftLds<N>;
-  constexpr int n = L::n, NT = Sz<N>::NT;
-  __shared__ double sW[EPB * L::W], sJa[EPB * L::JA], sWs[EPB * L::WS];
-  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
-  lift_tables<N>(bv.tab, threadIdx.x, NT * EPB, sDh, sl, slh);
+  constexpr int n = L::n, NT = Sz<N>::NT, SM = L::W + L::JA + L::WS;
+  __shared__ double sm[EPB * SM];
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n], sD[n * n];
+  lift_tables<N>(bv.tab, threadIdx.x, NT * EPB, sDh, sl, slh, sD);
   const int nblk = (bv.total + EPB - 1) / EPB;
   const int blk = xcd_element(blockIdx.x, nblk);
   if (blk >= nblk) return;
@@ -1409,8 +1521,8 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
   const bool valid = item < bv.total;
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
-  lift_body<N, true, LIFT_FV, GEN>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
-                              sW + slot * L::W, sJa + slot * L::JA, sWs + slot * L::WS, sDh, sl, slh);
+  lift_body<N, true, LIFT_DIV, GEN>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, nullptr,
+                                    sm + slot * SM, sDh, sl, slh, sD);
 }
 
 template <int N, bool NS, int VF, int EPB, bool GEN>
@@ -2324,8 +2436,18 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U
     DG_KL(false, LIFT_G);
   } else if (out == LIFT_G) {
     DG_KL(true, LIFT_G);
-  } else {
+  } else if (out == LIFT_FV) {
     DG_KL(true, LIFT_FV);
+  } else {
+    // the divergence output serves the split-form operator of conforming meshes
+    if (lev == 2 || (out != LIFT_DIV && out != LIFT_DIVK)) return DG_ERR_UNSUPPORTED;
+    if (out == LIFT_DIV) {
+      if (lev == 0) hipLaunchKernelGGL((k_lift<N, true, LIFT_DIV, 0>), grid, block, 0, st, g, ph, U, G, Fv);
+      else hipLaunchKernelGGL((k_lift<N, true, LIFT_DIV, 1>), grid, block, 0, st, g, ph, U, G, Fv);
+    } else {
+      if (lev == 0) hipLaunchKernelGGL((k_lift<N, true, LIFT_DIVK, 0>), grid, block, 0, st, g, ph, U, G, Fv);
+      else hipLaunchKernelGGL((k_lift<N, true, LIFT_DIVK, 1>), grid, block, 0, st, g, ph, U, G, Fv);
+    }
   }
 #undef DG_KL
   DG_CHECK_LAUNCH();
@@ -2615,10 +2737,10 @@ __global__ void __launch_bounds__(512, DG_SPLIT_MINB) k_split_f(FusedView fv) {
 
 template <int N>
 __device__ __forceinline__ void fused_lift_group(const BatchView &bv, int blk, double *smem, double *sDh, double *sl,
-                                                 double *slh) {
+                                                 double *slh, double *sD) {
   using L = LiftLds<N>;
   constexpr int NT = Sz<N>::NT, EPB = fused_epb_lift<N>();
-  lift_tables<N>(bv.tab, threadIdx.x, 512, sDh, sl, slh);
+  lift_tables<N>(bv.tab, threadIdx.x, 512, sDh, sl, slh, sD);
   const int raw = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
   const int slot = raw < EPB ? raw : EPB - 1;
   const int t = threadIdx.x - raw * NT;
@@ -2626,27 +2748,26 @@ __device__ __forceinline__ void fused_lift_group(const BatchView &bv, int blk, d
   const bool valid = raw < EPB && item < bv.total;
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
-  lift_body<N, true, LIFT_FV, false>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, M.G,
-                                     smem + slot * L::W, smem + EPB * L::W + slot * L::JA,
-                                     smem + EPB * (L::W + L::JA) + slot * L::WS, sDh, sl, slh);
+  lift_body<N, true, LIFT_DIV, false>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, nullptr,
+                                      smem + slot * (L::W + L::JA + L::WS), sDh, sl, slh, sD);
 }
 
 __global__ void __launch_bounds__(512, DG_LIFT_MINB) k_lift_f(FusedView fv) {
   __shared__ double smem[LiftLds<7>::W + LiftLds<7>::JA + LiftLds<7>::WS];
-  __shared__ double sDh[64], sl[16], slh[16];
+  __shared__ double sDh[64], sl[16], slh[16], sD[64];
   const int nb = fv.start[fv.ng];
   const int b = xcd_element(blockIdx.x, nb);
   if (b >= nb) return;
   const int gi = fused_group(fv, b);
   const int lb = b - fv.start[gi];
   switch (fv.N[gi]) {
-    case 1: fused_lift_group<1>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    case 2: fused_lift_group<2>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    case 3: fused_lift_group<3>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    case 4: fused_lift_group<4>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    case 5: fused_lift_group<5>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    case 6: fused_lift_group<6>(fv.v[gi], lb, smem, sDh, sl, slh); break;
-    default: fused_lift_group<7>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 1: fused_lift_group<1>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 2: fused_lift_group<2>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 3: fused_lift_group<3>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 4: fused_lift_group<4>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 5: fused_lift_group<5>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 6: fused_lift_group<6>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    default: fused_lift_group<7>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
   }
 }
 
