@@ -295,13 +295,9 @@ template <int N> struct LiftLds {
 
 // 1D tables of the lifting kernel into LDS (by the first threads of the workgroup)
 template <int N>
-__device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, double *sDh, double *sl, double *slh,
-                                            double *sD = nullptr) {
+__device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, double *sDh, double *sl, double *slh) {
   constexpr int n = N + 1;
-  for (int c = t; c < n * n; c += nthreads) {
-    sDh[c] = tb->Dh[c];
-    if (sD) sD[c] = tb->D[c];
-  }
+  for (int c = t; c < n * n; c += nthreads) sDh[c] = tb->Dh[c];
   if (t < n) {
     sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
     slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
@@ -327,13 +323,12 @@ template <int n> __device__ __forceinline__ int div_slot(int i, int j, int k) {
   else return i + n * (j + n * k);
 }
 
-// sm: the slot's LiftLds<N> regions, contiguous (W, JA, WS); sD the differentiation matrix
-// (LIFT_DIV, LIFT_DIVK only).
+// sm: the slot's LiftLds<N> regions, contiguous (W, JA, WS).
 template <int N, bool LGL, int OUT, int GEN>
 __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, bool valid, int t,
                                           const double *__restrict__ U, double *__restrict__ G,
                                           double *__restrict__ Fv, double *sm, const double *sDh,
-                                          const double *sl, const double *slh, const double *sD = nullptr) {
+                                          const double *sl, const double *slh) {
   using S = Sz<N>;
   using L = LiftLds<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
@@ -642,9 +637,13 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
     __syncthreads();
     // one line, one direction and two components per task: the line's values are read once and
-    // its n results written back in place (each LDS value is read once, not n times)
+    // its n results written back in place (each LDS value is read once, not n times); the
+    // matrix comes from the table through the scalar cache, the same for every lane
+    const __attribute__((address_space(4))) double *Dg = (const __attribute__((address_space(4))) double *)g.tab->D;
     for (int task = valid ? t : 6 * n2; task < 6 * n2; task += NT) {
-      const int dir = task / (2 * n2), r = task - dir * 2 * n2, cp = r / n2, ln = r - cp * n2;
+      // with 2 n^2 a multiple of the wave size every wave works on one direction
+      const int dir = (2 * n2) % 64 == 0 ? __builtin_amdgcn_readfirstlane(task / (2 * n2)) : task / (2 * n2);
+      const int r = task - dir * 2 * n2, cp = r / n2, ln = r - cp * n2;
       const int a = ln % n, b = ln / n;
       double *s0 = sm + (dir * 4 + 2 * cp) * n3, *s1 = s0 + n3;
       double f0[n], f1[n];
@@ -654,12 +653,12 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         f0[m] = s0[q];
         f1[m] = s1[q];
       }
-#pragma unroll 1
+#pragma unroll 2
       for (int id = 0; id < n; ++id) {
         double o0 = 0.0, o1 = 0.0;
 #pragma unroll
         for (int m = 0; m < n; ++m) {
-          const double D = sD[id * n + m];
+          const double D = Dg[id * n + m];
           o0 = fma(D, f0[m], o0);
           o1 = fma(D, f1[m], o1);
         }
@@ -688,13 +687,12 @@ __global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Ge
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
-  constexpr bool DIV = OUT == LIFT_DIV || OUT == LIFT_DIVK;
   __shared__ double sm[L::W + L::JA + L::WS];
-  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n], sD[DIV ? n * n : 1];
-  lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh, DIV ? sD : nullptr);
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  lift_tables<N>(g.tab, threadIdx.x, Sz<N>::NT, sDh, sl, slh);
   const int e = xcd_element(blockIdx.x, g.K);
   if (e >= g.K) return;
-  lift_body<N, LGL, OUT, GEN>(g, ph, e, true, threadIdx.x, U, G, Fv, sm, sDh, sl, slh, sD);
+  lift_body<N, LGL, OUT, GEN>(g, ph, e, true, threadIdx.x, U, G, Fv, sm, sDh, sl, slh);
 }
 
 // ----------------------------------------------------------------------------- operator
@@ -1510,8 +1508,8 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
   using L = LiftLds<N>;
   constexpr int n = L::n, NT = Sz<N>::NT, SM = L::W + L::JA + L::WS;
   __shared__ double sm[EPB * SM];
-  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n], sD[n * n];
-  lift_tables<N>(bv.tab, threadIdx.x, NT * EPB, sDh, sl, slh, sD);
+  __shared__ double sDh[n * n], sl[2 * n], slh[2 * n];
+  lift_tables<N>(bv.tab, threadIdx.x, NT * EPB, sDh, sl, slh);
   const int nblk = (bv.total + EPB - 1) / EPB;
   const int blk = xcd_element(blockIdx.x, nblk);
   if (blk >= nblk) return;
@@ -1522,7 +1520,7 @@ __global__ void __launch_bounds__(Sz<N>::NT * EPB, DG_LIFT_MINB) k_lift_b(BatchV
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
   lift_body<N, true, LIFT_DIV, GEN>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, nullptr,
-                                    sm + slot * SM, sDh, sl, slh, sD);
+                                    sm + slot * SM, sDh, sl, slh);
 }
 
 template <int N, bool NS, int VF, int EPB, bool GEN>
@@ -2737,10 +2735,10 @@ __global__ void __launch_bounds__(512, DG_SPLIT_MINB) k_split_f(FusedView fv) {
 
 template <int N>
 __device__ __forceinline__ void fused_lift_group(const BatchView &bv, int blk, double *smem, double *sDh, double *sl,
-                                                 double *slh, double *sD) {
+                                                 double *slh) {
   using L = LiftLds<N>;
   constexpr int NT = Sz<N>::NT, EPB = fused_epb_lift<N>();
-  lift_tables<N>(bv.tab, threadIdx.x, 512, sDh, sl, slh, sD);
+  lift_tables<N>(bv.tab, threadIdx.x, 512, sDh, sl, slh);
   const int raw = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
   const int slot = raw < EPB ? raw : EPB - 1;
   const int t = threadIdx.x - raw * NT;
@@ -2749,25 +2747,25 @@ __device__ __forceinline__ void fused_lift_group(const BatchView &bv, int blk, d
   const int mi = member_of(bv.first, bv.count, valid ? item : bv.total - 1);
   const Member &M = bv.m[mi];
   lift_body<N, true, LIFT_DIV, false>(M.g, M.ph, valid ? item - bv.first[mi] : 0, valid, t, M.U, nullptr, nullptr,
-                                      smem + slot * (L::W + L::JA + L::WS), sDh, sl, slh, sD);
+                                      smem + slot * (L::W + L::JA + L::WS), sDh, sl, slh);
 }
 
 __global__ void __launch_bounds__(512, DG_LIFT_MINB) k_lift_f(FusedView fv) {
   __shared__ double smem[LiftLds<7>::W + LiftLds<7>::JA + LiftLds<7>::WS];
-  __shared__ double sDh[64], sl[16], slh[16], sD[64];
+  __shared__ double sDh[64], sl[16], slh[16];
   const int nb = fv.start[fv.ng];
   const int b = xcd_element(blockIdx.x, nb);
   if (b >= nb) return;
   const int gi = fused_group(fv, b);
   const int lb = b - fv.start[gi];
   switch (fv.N[gi]) {
-    case 1: fused_lift_group<1>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    case 2: fused_lift_group<2>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    case 3: fused_lift_group<3>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    case 4: fused_lift_group<4>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    case 5: fused_lift_group<5>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    case 6: fused_lift_group<6>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
-    default: fused_lift_group<7>(fv.v[gi], lb, smem, sDh, sl, slh, sD); break;
+    case 1: fused_lift_group<1>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 2: fused_lift_group<2>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 3: fused_lift_group<3>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 4: fused_lift_group<4>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 5: fused_lift_group<5>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    case 6: fused_lift_group<6>(fv.v[gi], lb, smem, sDh, sl, slh); break;
+    default: fused_lift_group<7>(fv.v[gi], lb, smem, sDh, sl, slh); break;
   }
 }
 
