@@ -623,9 +623,9 @@ int fv_dispatch(dg_handle *h, int what, const double *U, double *out, double *R,
 
 // lifting (Navier-Stokes) then the main operator, timed per kernel when profiling is on.  The
 // split form takes the strong-form divergence and face traces of the contravariant viscous
-// fluxes (Geo::Gd, Gf), or on meshes with non-conforming faces the fluxes themselves; the other
-// forms take the gradients.  Fluxes and gradients go to the handle's scratch or, if
-// Gkeep != NULL, to Gkeep (kept for a later reverse sweep).
+// fluxes (Geo::Gd, Gf), the other forms the gradients (in the handle's scratch or, if
+// Gkeep != NULL, in Gkeep).  With Gkeep the split form also writes the fluxes there, kept for a
+// later reverse sweep.
 int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a, double b, double dt, int mode,
                  double *Gkeep = nullptr) {
   const bool ns = h->sc.eqn == DG_NAVIER_STOKES;
@@ -638,8 +638,8 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
       if (rc) return rc;
     }
     double *dst = Gkeep ? Gkeep : h->d_G;
-    // lifting outputs: 0 gradients, 1 fluxes, 2 divergence, 3 divergence and fluxes
-    const int out = !split ? 0 : (h->nm ? 1 : (Gkeep ? 3 : 2));
+    // lifting outputs: 0 gradients, 2 divergence, 3 divergence and fluxes
+    const int out = !split ? 0 : (Gkeep ? 3 : 2);
     const int rc = split ? lift_dispatch(h, U, out, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
     if (rc) return rc;
   }
@@ -839,7 +839,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc && !fc.empty()) rc = dev_alloc(&h->d_fc, fc.size());
   if (!rc) rc = dev_alloc(&h->d_tab, 1);
   if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
-  if (!rc && ns && sc->form == DG_FORM_SPLIT && h->nm == 0) {
+  if (!rc && ns && sc->form == DG_FORM_SPLIT) {
     rc = dev_alloc(&h->d_Gd, (size_t)K * 4 * n3);
     if (!rc) rc = dev_alloc(&h->d_Gf, (size_t)K * 24 * n2);
   }

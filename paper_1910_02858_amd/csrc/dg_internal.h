@@ -60,7 +60,7 @@ struct Geo {
   // fluxes [K][6][5][n^2] of the sides of faces that touch a finite-volume element
   const uint8_t *fvflag;
   const double *fvFx;
-  // split form, Navier-Stokes, conforming faces (NULL otherwise): the lifting's viscous terms as
+  // split form, Navier-Stokes (NULL otherwise): the lifting's viscous terms as
   // the operator reads them, the strong-form divergence Gd[e][c][node] = sum_dir (sum_m D_{id,m}
   // Fv^dir_c(node m of the line) -+ lhat(+-1) Fv^dir_c on a +-face node) (c: momentum x, y, z,
   // energy) and every side's face trace Gf[e][s][c][face point] = Fv^{dir(s)}_c at the face node

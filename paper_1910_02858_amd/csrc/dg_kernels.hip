@@ -308,10 +308,10 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // threads in step with the workgroup barriers without touching memory.
 // OUT: LIFT_G writes the gradients G[e][d*4+c][node] = dW_c/dx_d (weak and strong forms);
 // LIFT_FV writes instead the contravariant viscous fluxes Fv[e][dir*4+c][node] =
-// (F^v . Ja^dir)_{1+c} (momentum, energy), which the reverse sweep and the split-form kernels on
-// meshes with non-conforming faces consume; LIFT_DIV writes what the split-form operator reads
-// on conforming meshes, the volume term Geo::Gd (sum over the lines of D times Fv^dir) and the
-// face traces Geo::Gf of Fv; LIFT_DIVK writes both (the stage kept for a reverse sweep).
+// (F^v . Ja^dir)_{1+c} (momentum, energy), which the reverse sweep consumes; LIFT_DIV writes what
+// the split-form operator reads, the strong-form divergence Geo::Gd (sums along the lines of D
+// times Fv^dir, and the interior part of the surface term) and the face traces Geo::Gf of Fv;
+// LIFT_DIVK writes both (the stage kept for a reverse sweep).
 enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3 };
 
 // LDS slot of node (i, j, k) in one component array of the viscous divergence stage.  For n = 8
@@ -1171,20 +1171,12 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   const bool act = valid && inb;
   const double gm1 = ph.gamma - 1.0, kg = 1.0 / gm1, gg = gm1 / ph.gamma;
   const double *Ue = U + (size_t)e * 5 * n3;
-  const double *Ge = G + (size_t)e * 12 * n3;
   const double *Jae = g.Ja + (size_t)e * 9 * n3;
   double *sS = sA;           // rho, u, v, w, beta (EC) or H (KEP, central) per node
   double *sJ = sA + 5 * n3;  // Ja^i_d at (i*3+d)*n3 + node
-  double *sF = sA;           // first: the contravariant viscous fluxes of the three directions
-  // VD: on conforming meshes the lifting kernel has formed the viscous divergence (Geo::Gd) and
-  // the face traces of Fv (Geo::Gf); with non-conforming faces the fluxes Fv (G) are read here
-  constexpr bool VD = NS && GEN < 2;
-  const double *Gfe = VD ? g.Gf + (size_t)e * 24 * n2 : nullptr;
-  if (NS && !VD && act) {
-    // staged before the face phase, so that their loads overlap with the neighbours' face reads
-#pragma unroll
-    for (int c = 0; c < 12; ++c) sF[c * n3 + t] = Ge[c * n3 + t];
-  }
+  // Navier-Stokes: the lifting kernel has formed the viscous divergence (Geo::Gd) and the face
+  // traces of the viscous fluxes (Geo::Gf)
+  const double *Gfe = NS ? g.Gf + (size_t)e * 24 * n2 : nullptr;
   // the node's own state is loaded before the face phase, so that its latency overlaps with it
   double Uo[5];
   if (act) {
@@ -1213,15 +1205,13 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       continue;
     }
     const double *Un = U + (size_t)(bnd ? e : nb) * 5 * n3;
-    const double *Gn = G + (size_t)(bnd ? e : nb) * 12 * n3;
     const int qo = line_node<n>(dn, a, b, plus ? N : 0);
     const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
-    // this side's trace of Fv^dn at the face point (component c at fo[c * fs]) and the
-    // neighbour's trace of Fv^{f.dn} on its side of the face (fnb[c * fs])
-    const int fs = VD ? n2 : n3;
-    const double *fo = VD ? Gfe + s * 4 * n2 + ab : Ge + dn * 4 * n3 + qo;
-    const double *fnb = VD ? g.Gf + ((size_t)(bnd ? e : nb) * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b
-                           : Gn + f.dn * 4 * n3 + qn;
+    // this side's trace of Fv^dn at the face point (component c at fo[c * n2]) and the
+    // neighbour's trace of Fv^{f.dn} on its side of the face (fnb[c * n2])
+    const double *fo = NS ? Gfe + s * 4 * n2 + ab : nullptr;
+    const double *fnb = NS ? g.Gf + ((size_t)(bnd ? e : nb) * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b
+                           : nullptr;
     double Uw[5], Ux[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) { Uw[v] = Ue[v * n3 + qo]; Ux[v] = bnd ? Uw[v] : Un[v * n3 + qn]; }
@@ -1259,7 +1249,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
       if (given) {
         // given outer state: the outer viscous flux equals the inner one
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[1 + c] -= fo[c * fs];
+        for (int c = 0; c < 4; ++c) F[1 + c] -= fo[c * n2];
       } else if (wall) {
         // no-slip wall: the outer momentum flux equals the inner one, the outer energy flux is
         // its negative (reversed velocity, mirrored heat flux), so the mean keeps the momentum;
@@ -1268,26 +1258,26 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
         double g3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          g3[c] = fo[c * fs];
+          g3[c] = fo[c * n2];
           F[1 + c] -= g3[c];
         }
         if (iso) {
           const double ir = 1.0 / Uw[0];
-          F[4] -= fo[3 * fs] - (g3[0] * Uw[1] + g3[1] * Uw[2] + g3[2] * Uw[3]) * ir;
+          F[4] -= fo[3 * n2] - (g3[0] * Uw[1] + g3[1] * Uw[2] + g3[2] * Uw[3]) * ir;
         }
       } else if (bnd) {
         // symmetry plane: the mirrored outer flux cancels the inner shear and heat flux, the
         // mean keeps the normal part of the momentum flux
-        const double gm = fo[0] * nh[0] + fo[fs] * nh[1] + fo[2 * fs] * nh[2];
+        const double gm = fo[0] * nh[0] + fo[n2] * nh[1] + fo[2 * n2] * nh[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) F[1 + c] -= gm * nh[c];
       } else if (GEN) {
         const double sn = (f.plus != plus) ? 1.0 : -1.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * fs] + sn * fnb[c * fs]);
+        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * n2] + sn * fnb[c * n2]);
       } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * fs] + fnb[c * fs]);
+        for (int c = 0; c < 4; ++c) F[1 + c] -= 0.5 * (fo[c * n2] + fnb[c * n2]);
       }
     }
 #pragma unroll
@@ -1329,42 +1319,6 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
   if (act) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) ja[c] = Jae[c * n3 + t];
-  }
-  if (NS && !VD) {
-    // viscous part in strong form: -sum_a D_ia Fv^dir_a along each line, and -Fv.N_out lhat(+-1)
-    // on the faces through the node.  The contravariant viscous fluxes of all three directions
-    // (from the lifting kernel) are staged once in region A.
-    if (act) {
-#pragma unroll
-      for (int dir = 0; dir < 3; ++dir) {
-        double fv[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fv[c] = sF[(dir * 4 + c) * n3 + t];
-        const int id = id3[dir];
-        if (id == 0 || id == N) {
-          const bool plus = id == N;
-          const double lh = slh[(plus ? n : 0) + id];
-          const double sl_ = plus ? -lh : lh;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[1 + c] -= sl_ * fv[c];
-        }
-      }
-    }
-    if (act) {
-#pragma unroll
-      for (int dir = 0; dir < 3; ++dir) {
-        const int id = id3[dir];
-        const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
-        const int base = t - id * str;
-#pragma unroll
-        for (int m = 0; m < n; ++m) {
-          const double D = sD[id * n + m];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[1 + c] -= D * sF[(dir * 4 + c) * n3 + base + m * str];
-        }
-      }
-    }
-    __syncthreads();  // region A is reused below
   }
   if (act) {
     sS[t] = o.r; sS[n3 + t] = o.u; sS[2 * n3 + t] = o.v; sS[3 * n3 + t] = o.w;
@@ -1449,7 +1403,7 @@ __device__ __forceinline__ void split_body(const Geo &g, const Phys &ph, int e, 
     }
   }
   if (act) {
-    if (VD) {
+    if (NS) {
       // viscous part in strong form, formed by the lifting kernel (loaded here: held through the
       // rounds, these four values push the operator past its register budget)
 #pragma unroll
@@ -2436,16 +2390,12 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U
     DG_KL(true, LIFT_G);
   } else if (out == LIFT_FV) {
     DG_KL(true, LIFT_FV);
+  } else if (out == LIFT_DIV) {
+    DG_KL(true, LIFT_DIV);
+  } else if (out == LIFT_DIVK) {
+    DG_KL(true, LIFT_DIVK);
   } else {
-    // the divergence output serves the split-form operator of conforming meshes
-    if (lev == 2 || (out != LIFT_DIV && out != LIFT_DIVK)) return DG_ERR_UNSUPPORTED;
-    if (out == LIFT_DIV) {
-      if (lev == 0) hipLaunchKernelGGL((k_lift<N, true, LIFT_DIV, 0>), grid, block, 0, st, g, ph, U, G, Fv);
-      else hipLaunchKernelGGL((k_lift<N, true, LIFT_DIV, 1>), grid, block, 0, st, g, ph, U, G, Fv);
-    } else {
-      if (lev == 0) hipLaunchKernelGGL((k_lift<N, true, LIFT_DIVK, 0>), grid, block, 0, st, g, ph, U, G, Fv);
-      else hipLaunchKernelGGL((k_lift<N, true, LIFT_DIVK, 1>), grid, block, 0, st, g, ph, U, G, Fv);
-    }
+    return DG_ERR_UNSUPPORTED;
   }
 #undef DG_KL
   DG_CHECK_LAUNCH();
