@@ -562,9 +562,15 @@ int lift_dispatch(dg_handle *h, const double *U, int out, double *G, double *Fv)
   if (int rc = state_ready(h)) return rc;
   const dg::Geo g = h->geo();
   const bool lgl = h->node_type == DG_NODES_LGL;
+  // on LG nodes the traces of U and W are prolonged first (the lifting and the operator read them)
   switch (h->N) {
-#define DG_CASE(NN) \
-  case NN: return dg::launch_lift<NN>(g, h->ph, lgl, out, U, G, Fv, h->stream);
+#define DG_CASE(NN)                                                          \
+  case NN:                                                                   \
+    if (!lgl) {                                                              \
+      const int rc = dg::launch_prolong<NN>(g, h->ph, U, h->stream);         \
+      if (rc) return rc;                                                     \
+    }                                                                        \
+    return dg::launch_lift<NN>(g, h->ph, lgl, out, U, G, Fv, h->stream);
     DG_CASE(1) DG_CASE(2) DG_CASE(3) DG_CASE(4) DG_CASE(5) DG_CASE(6) DG_CASE(7) DG_CASE(8)
 #undef DG_CASE
     default: return DG_ERR_UNSUPPORTED;
@@ -638,9 +644,11 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
       if (rc) return rc;
     }
     double *dst = Gkeep ? Gkeep : h->d_G;
-    // lifting outputs: 0 gradients, 2 divergence, 3 divergence and fluxes
-    const int out = !split ? 0 : (Gkeep ? 3 : 2);
-    const int rc = split ? lift_dispatch(h, U, out, nullptr, dst) : lift_dispatch(h, U, 0, dst, nullptr);
+    // lifting outputs: 0 gradients, 2 divergence, 3 divergence and fluxes, 4 gradients and their
+    // face traces (LG nodes)
+    const bool lg = h->node_type != DG_NODES_LGL;
+    const int out = !split ? (lg ? 4 : 0) : (Gkeep ? 3 : 2);
+    const int rc = split ? lift_dispatch(h, U, out, nullptr, dst) : lift_dispatch(h, U, out, dst, nullptr);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
@@ -842,6 +850,11 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc && ns && sc->form == DG_FORM_SPLIT) {
     rc = dev_alloc(&h->d_Gd, (size_t)K * 4 * n3);
     if (!rc) rc = dev_alloc(&h->d_Gf, (size_t)K * 24 * n2);
+  }
+  if (!rc && ns && node_type != DG_NODES_LGL) {
+    rc = dev_alloc(&h->d_Utr, (size_t)K * 30 * n2);
+    if (!rc) rc = dev_alloc(&h->d_Wtr, (size_t)K * 24 * n2);
+    if (!rc) rc = dev_alloc(&h->d_Gtr, (size_t)K * 72 * n2);
   }
   if (!rc) rc = dev_alloc(&h->d_partial, (size_t)K * 8);
   if (!rc) rc = dev_alloc(&h->d_red, 8);
@@ -1390,7 +1403,8 @@ void dg_destroy(dg_handle *h) {
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   (void)hipFree(h->d_Ja); (void)hipFree(h->d_sJ); (void)hipFree(h->d_fn); (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_fc); (void)hipFree(h->d_tab);
-  (void)hipFree(h->d_G); (void)hipFree(h->d_Gd); (void)hipFree(h->d_Gf); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
+  (void)hipFree(h->d_G); (void)hipFree(h->d_Gd); (void)hipFree(h->d_Gf); (void)hipFree(h->d_Utr);
+  (void)hipFree(h->d_Wtr); (void)hipFree(h->d_Gtr); (void)hipFree(h->d_Pf); (void)hipFree(h->d_partial); (void)hipFree(h->d_red);
   (void)hipFree(h->d_md); (void)hipFree(h->d_mslot); (void)hipFree(h->d_mflux); (void)hipFree(h->d_mlift);
   (void)hipFree(h->d_mg);
   (void)hipFree(h->d_fvtab); (void)hipFree(h->d_fvJbar); (void)hipFree(h->d_fvNf); (void)hipFree(h->d_fvFx);

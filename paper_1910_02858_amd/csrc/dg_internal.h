@@ -65,6 +65,11 @@ struct Geo {
   // Fv^dir_c(node m of the line) -+ lhat(+-1) Fv^dir_c on a +-face node) (c: momentum x, y, z,
   // energy) and every side's face trace Gf[e][s][c][face point] = Fv^{dir(s)}_c at the face node
   double *Gd, *Gf;
+  // Navier-Stokes on LG nodes (NULL otherwise): every side's traces interpolated with l(+-1),
+  // of the conservative state Utr[e][s][v][face point] and of W = (u, v, w, T)
+  // Wtr[e][s][c][face point] (prolongation kernel), and of the lifted gradients
+  // Gtr[e][s][d*4+c][face point] (lifting kernel); read at the faces by the lifting and operator
+  double *Utr, *Wtr, *Gtr;
 };
 
 // Finite-volume subcells (Sec. 4) of one mesh on the device.
@@ -93,6 +98,9 @@ struct Phys {
 };
 
 // Kernel launch entry points, one explicit instantiation per degree.
+// prolongation on LG nodes (Navier-Stokes): every side's traces of U and W into Geo::Utr, Wtr
+template <int N>
+int launch_prolong(const Geo &g, const Phys &ph, const double *U, hipStream_t st);
 // lifting: out 0 writes G (gradients), 1 writes Fv (contravariant viscous fluxes, LGL only)
 template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
@@ -251,6 +259,7 @@ struct dg_handle {
   double *d_fvind = nullptr;
   uint8_t *d_fvflag = nullptr;
   double *d_Gd = nullptr, *d_Gf = nullptr;  // viscous volume term and face traces (Geo::Gd, Gf)
+  double *d_Utr = nullptr, *d_Wtr = nullptr, *d_Gtr = nullptr;  // LG face traces of U, W, gradients
   int *d_fvlist = nullptr;  // work lists of the hybrid kernels: [K] elements, [3K] sides, [2] counts
   int *d_fvfaces = nullptr;
   int *d_fvcount = nullptr;
@@ -283,6 +292,7 @@ struct dg_handle {
     g.mslot = d_mslot; g.mflux = d_mflux; g.mlift = d_mlift; g.mg = d_mg;
     g.fvflag = fv_on ? d_fvflag : nullptr; g.fvFx = fv_on ? d_fvFx : nullptr;
     g.Gd = d_Gd; g.Gf = d_Gf;
+    g.Utr = d_Utr; g.Wtr = d_Wtr; g.Gtr = d_Gtr;
     return g;
   }
 };

@@ -311,8 +311,11 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // (F^v . Ja^dir)_{1+c} (momentum, energy), which the reverse sweep consumes; LIFT_DIV writes what
 // the split-form operator reads, the strong-form divergence Geo::Gd (sums along the lines of D
 // times Fv^dir, and the interior part of the surface term) and the face traces Geo::Gf of Fv;
-// LIFT_DIVK writes both (the stage kept for a reverse sweep).
-enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3 };
+// LIFT_DIVK writes both (the stage kept for a reverse sweep).  LIFT_GT (LG nodes) writes the
+// gradients and every side's traces of them, interpolated with l(+-1) (Geo::Gtr), which the
+// operator kernel reads at its faces instead of interpolating along the lines of its own and the
+// neighbour's element.  On LG nodes the neighbours' traces of W come from k_prolong (Geo::Wtr).
+enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4 };
 
 // LDS slot of node (i, j, k) in one component array of the viscous divergence stage.  For n = 8
 // the index bits are swizzled so that the 64 lanes that read the m-th node of 64 different lines
@@ -332,7 +335,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
   using S = Sz<N>;
   using L = LiftLds<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
-  constexpr bool FVO = OUT != LIFT_G;  // the viscous fluxes are formed
+  constexpr bool FVO = OUT == LIFT_FV || OUT == LIFT_DIV || OUT == LIFT_DIVK;  // viscous fluxes formed
   double *sW = sm, *sJa = sm + L::W, *sWs = sm + L::W + L::JA;
   const double gm1 = ph.gamma - 1.0;
   const double *Ue = U + (size_t)e * 5 * n3;
@@ -391,18 +394,17 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       const double *lo = sl + (plus ? n : 0), *ln = GEN ? sl + (f.plus ? n : 0) : sl + (plus ? 0 : n);
 #pragma unroll
       for (int v = 0; v < 4; ++v) { WL[v] = 0.0; WR[v] = 0.0; }
+#pragma unroll 1
       for (int m = 0; m < n; ++m) {
-        const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
+        const int q = line_node<n>(dn, a, b, m);
 #pragma unroll
         for (int v = 0; v < 4; ++v) WL[v] += lo[m] * sW[v * n3 + q];
-        if (!(GEN && f.bnd)) {
-          double Uq[5], W[4];
+      }
+      if (!(GEN && f.bnd)) {
+        // the neighbour's trace of W on its side of the face, from the prolongation kernel
+        const double *wt = g.Wtr + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
 #pragma unroll
-          for (int v = 0; v < 5; ++v) Uq[v] = Un[v * n3 + qn];
-          grad_prim_to_W(Uq, gm1, ph.R, W);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) WR[v] += ln[m] * W[v];
-        }
+        for (int v = 0; v < 4; ++v) WR[v] = wt[v * n2];
       }
     }
     if (GEN && f.bnd && f.kind == DG_BC_STATE) {
@@ -568,7 +570,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         for (int c = 0; c < 12; ++c) mg[c * n2] = acc[c];
       }
     }
-    if (OUT == LIFT_G) {
+    if (OUT == LIFT_G || OUT == LIFT_GT) {
       double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
       for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
@@ -680,10 +682,86 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       for (int c = 0; c < 4; ++c) Gde[c * n3] = gd[c];
     }
   }
+  if constexpr (OUT == LIFT_GT) {
+    // LG face traces, each face point by one thread: the gradients (staged once the three
+    // regions are free), then the conservative state, each summed along the face-normal line
+    // with l(+-1) in the order the operator kernel would
+    __syncthreads();
+    if (valid && t < n3) {
+      const int q = div_slot<n>(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[c * n3 + q] = acc[c];
+    }
+    __syncthreads();
+    for (int p = valid ? t : 6 * n2; p < 6 * n2; p += NT) {
+      const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+      const double *lo = sl + ((s & 1) ? n : 0);
+      double gq[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gq[c] = 0.0;
+#pragma unroll 1
+      for (int m = 0; m < n; ++m) {
+        const int q = dn == 0 ? div_slot<n>(m, a, b) : (dn == 1 ? div_slot<n>(a, m, b) : div_slot<n>(a, b, m));
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gq[c] += lo[m] * sm[c * n3 + q];
+      }
+      double *gt = g.Gtr + ((size_t)e * 6 + s) * 12 * n2 + ab;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) gt[c * n2] = gq[c];
+    }
+  }
+}
+
+// Prolongation on LG nodes (Navier-Stokes): every side's traces of the conservative state and of
+// W = (u, v, w, T), each interpolated with l(+-1) along the face-normal lines of the element
+// (Utr, Wtr of Geo), so that the lifting and operator kernels read their neighbours' traces
+// contiguously instead of the neighbours' whole lines.
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_prolong(Geo g, Phys ph, const double *__restrict__ U) {
+  constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, NT = Sz<N>::NT;
+  __shared__ double sm[9 * n3];
+  __shared__ double sl[2 * n];
+  const int t = threadIdx.x;
+  if (t < n) { sl[t] = g.tab->lm[t]; sl[n + t] = g.tab->lp[t]; }
+  const int e = xcd_element(blockIdx.x, g.K);
+  if (e >= g.K) return;
+  if (t < n3) {
+    const double *Ue = U + (size_t)e * 5 * n3;
+    const int q = div_slot<n>(t % n, (t / n) % n, t / n2);
+    double Uq[5], W[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Uq[v] = Ue[v * n3 + t];
+      sm[v * n3 + q] = Uq[v];
+    }
+    grad_prim_to_W(Uq, ph.gamma - 1.0, ph.R, W);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sm[(5 + v) * n3 + q] = W[v];
+  }
+  __syncthreads();
+  for (int p = t; p < 6 * n2; p += NT) {
+    const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+    const double *lo = sl + ((s & 1) ? n : 0);
+    double x[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) x[v] = 0.0;
+#pragma unroll 1
+    for (int m = 0; m < n; ++m) {
+      const int q = dn == 0 ? div_slot<n>(m, a, b) : (dn == 1 ? div_slot<n>(a, m, b) : div_slot<n>(a, b, m));
+#pragma unroll
+      for (int v = 0; v < 9; ++v) x[v] += lo[m] * sm[v * n3 + q];
+    }
+    double *ut = g.Utr + ((size_t)e * 6 + s) * 5 * n2 + ab;
+    double *wt = g.Wtr + ((size_t)e * 6 + s) * 4 * n2 + ab;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ut[v * n2] = x[v];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wt[v * n2] = x[5 + v];
+  }
 }
 
 template <int N, bool LGL, int OUT, int GEN>
-__global__ void __launch_bounds__(Sz<N>::NT, (LGL ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, (LGL || GEN == 0 ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
@@ -772,22 +850,37 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 #pragma unroll
         for (int c = 0; c < 12; ++c) { gw[c] = 0.0; gx[c] = 0.0; }
       }
-      // a rolled loop: unrolled, the early loads of all n nodes' 34 values spill
+      if (NS) {
+        // Navier-Stokes: the lifting kernel has interpolated every side's traces of U and of the
+        // gradients; this side's U trace from LDS, the rest read contiguously
+        const double *gt = g.Gtr + ((size_t)e * 6 + s) * 12 * n2 + ab;
+        const size_t sn = (size_t)(bnd ? e : nb) * 6 + 2 * f.dn + (f.plus ? 1 : 0);
+        const double *utn = g.Utr + sn * 5 * n2 + f.a + n * f.b;
+        const double *gtn = g.Gtr + sn * 12 * n2 + f.a + n * f.b;
 #pragma unroll 1
-      for (int m = 0; m < n; ++m) {
-        const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
+        for (int m = 0; m < n; ++m) {
+          const int q = line_node<n>(dn, a, b, m);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
-        if (NS) {
-#pragma unroll
-          for (int c = 0; c < 12; ++c) gw[c] += lo[m] * Ge[c * n3 + q];
+          for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
         }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gw[c] = gt[c * n2];
         if (!bnd) {
 #pragma unroll
-          for (int v = 0; v < 5; ++v) Ux[v] += ln[m] * Un[v * n3 + qn];
-          if (NS) {
+          for (int v = 0; v < 5; ++v) Ux[v] = utn[v * n2];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) gx[c] += ln[m] * Gn[c * n3 + qn];
+          for (int c = 0; c < 12; ++c) gx[c] = gtn[c * n2];
+        }
+      } else {
+        // a rolled loop: unrolled, the early loads of all n nodes' values spill
+#pragma unroll 1
+        for (int m = 0; m < n; ++m) {
+          const int q = line_node<n>(dn, a, b, m), qn = GEN ? line_node<n>(f.dn, f.a, f.b, m) : q;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
+          if (!bnd) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Ux[v] += ln[m] * Un[v * n3 + qn];
           }
         }
       }
@@ -2372,6 +2465,13 @@ static int launch_form(const Geo &g, const Phys &ph, int form, const double *U, 
 }
 
 template <int N>
+int launch_prolong(const Geo &g, const Phys &ph, const double *U, hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong<N>), dim3(xcd_grid(g.K)), dim3(Sz<N>::NT), 0, st, g, ph, U);
+  DG_CHECK_LAUNCH();
+  return DG_OK;
+}
+
+template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st) {
   dim3 grid(xcd_grid(g.K)), block(Sz<N>::NT);
@@ -2384,8 +2484,9 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U
     else hipLaunchKernelGGL((k_lift<N, L_, O_, 2>), grid, block, 0, st, g, ph, U, G, Fv); \
   } while (0)
   if (!lgl) {
-    if (out != LIFT_G) return DG_ERR_UNSUPPORTED;
-    DG_KL(false, LIFT_G);
+    if (out == LIFT_G) DG_KL(false, LIFT_G);
+    else if (out == LIFT_GT) DG_KL(false, LIFT_GT);
+    else return DG_ERR_UNSUPPORTED;
   } else if (out == LIFT_G) {
     DG_KL(true, LIFT_G);
   } else if (out == LIFT_FV) {
@@ -2754,6 +2855,7 @@ int launch_fused_split(const FusedView &fv, bool ns, int vf, hipStream_t st) {
 #endif
 
 #ifdef DG_ONLY_N
+template int launch_prolong<DG_ONLY_N>(const Geo &, const Phys &, const double *, hipStream_t);
 template int launch_lift<DG_ONLY_N>(const Geo &, const Phys &, bool, int, const double *, double *, double *,
                                     hipStream_t);
 template int launch_main<DG_ONLY_N>(const Geo &, const Phys &, bool, int, int, const double *, const double *,
