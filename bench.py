@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_MAIN = 37 * 8
 # lifting for the split form: U 5 + Ja 9 + 1/J 1 read, viscous divergence 4 + face traces 3 written
 BYTES_LIFT = 22 * 8
-# weak-form operator with BR1 gradients: U 5 + grad W 12 + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5
-# written
-BYTES_GRAD_MAIN = 42 * 8
+# weak-form operator at N = 7 (Navier-Stokes): U 5 + viscous volume term 4 + own face viscous fluxes 3
+# (24 n^2 per element) + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
+BYTES_WEAK_MAIN = 37 * 8
 # reverse stage: k_vjp_main reads U 5, the kept viscous fluxes' momentum part 9, Ja 9, 1/J 1,
 # Ubar_t 5, Ubar 5 and writes Ubar 5; k_vjp_face reads Ubar 5, Rbar 5 and writes Rbar 5
 BYTES_VJP_MAIN = 39 * 8
@@ -300,15 +300,18 @@ def ec_branch_bench(S, U_smooth, torch, wl, smooth_main_ms: float, stages: int =
 
 
 def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
-    """The weak form on LG nodes (k_main: the D-hat contraction of the fluxes along every line and
-    the LG face prolongation): the Euler density-wave scheme at N=3 on 96^3 elements and the
-    Navier-Stokes TGV (central volume flux, Roe, BR1 gradients) at N=7 on 48^3, both 56.6 M nodes;
-    per-kernel times, the operator kernel priced at 336 B per node (Navier-Stokes) or at its
-    Euler reads and writes (U 5, Ja 9, 1/J 1, R 5 read, U_new 5, R 5 written: 240 B)."""
+    """The weak form (k_main: the D-hat contraction of the fluxes along every line, on LG nodes
+    the face prolongation): the Euler density-wave scheme at N=3 on 96^3 LG elements and the
+    Navier-Stokes TGV (central volume flux, Roe, BR1) at N=7 on 48^3 on LG and on LGL nodes, all
+    56.6 M nodes; per-kernel times (the lifting's includes the LG prolongation), the operator
+    kernel priced at 296 B per node (Navier-Stokes) or at its Euler reads and writes (U 5, Ja 9,
+    1/J 1, R 5 read, U_new 5, R 5 written: 240 B)."""
     out = {}
     for name, wl, nbytes in (("euler_dwave_lg3_k96_weak", inputs.workload(1, K1=96), 30 * 8),
                              ("ns_tgv_central_roe_lg7_k48_weak",
-                              inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=48), BYTES_GRAD_MAIN)):
+                              inputs.workload(3, form="weak", volflux="central", nodes="lg", K1=48), BYTES_WEAK_MAIN),
+                             ("ns_tgv_central_roe_lgl7_k48_weak",
+                              inputs.workload(3, form="weak", volflux="central", K1=48), BYTES_WEAK_MAIN)):
         S, U = dgsem.build_solver(wl)
         dt = S.timestep(U, wl.cfl, wl.dfl)
         a, b, _ = dgsem.rk_coefficients()

@@ -315,7 +315,38 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // gradients and every side's traces of them, interpolated with l(+-1) (Geo::Gtr), which the
 // operator kernel reads at its faces instead of interpolating along the lines of its own and the
 // neighbour's element.  On LG nodes the neighbours' traces of W come from k_prolong (Geo::Wtr).
-enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4 };
+// LIFT_WV (weak form, conforming meshes) writes what the weak-form operator reads: the volume
+// term Geo::Gd (sums along the lines of D-hat times Fv^dir) and every side's viscous flux at its
+// trace, F^v(U, grad W) . n with the side's own outward normal (Geo::Gf; on a boundary side
+// already the BR1 mean with the outer state), and the gradients too when G is not NULL.
+enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4, LIFT_WV = 5 };
+
+// The node's gradients acc[d*4+c] = dW_c/dx_d become its contravariant viscous fluxes
+// acc[dir*4+c] = (F^v . Ja^dir)_{1+c} (momentum, energy): Newtonian stress with Stokes'
+// hypothesis and Fourier heat flux, contracted with the metric terms jo[dir*3+d].  Every rounding
+// step is spelled out (explicit fma, no contraction), so every kernel that runs the lifting
+// produces the same fluxes bit for bit.
+__device__ __forceinline__ void contra_visc(double *acc, const double *jo, double u, double v, double w,
+                                            const Phys &ph) {
+#pragma clang fp contract(off)
+  const double mu = ph.mu, div = (acc[0] + acc[5]) + acc[10];
+  const double t00 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[0]);
+  const double t11 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[5]);
+  const double t22 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[10]);
+  const double t01 = mu * (acc[4] + acc[1]);
+  const double t02 = mu * (acc[8] + acc[2]);
+  const double t12 = mu * (acc[9] + acc[6]);
+  const double dT0 = acc[3], dT1 = acc[7], dT2 = acc[11];
+#pragma unroll
+  for (int dir = 0; dir < 3; ++dir) {
+    const double *nv = jo + 3 * dir;
+    acc[dir * 4] = fma(t02, nv[2], fma(t01, nv[1], t00 * nv[0]));
+    acc[dir * 4 + 1] = fma(t12, nv[2], fma(t11, nv[1], t01 * nv[0]));
+    acc[dir * 4 + 2] = fma(t22, nv[2], fma(t12, nv[1], t02 * nv[0]));
+    const double q = fma(dT2, nv[2], fma(dT1, nv[1], dT0 * nv[0]));
+    acc[dir * 4 + 3] = fma(ph.kappa, q, fma(acc[dir * 4 + 2], w, fma(acc[dir * 4 + 1], v, acc[dir * 4] * u)));
+  }
+}
 
 // LDS slot of node (i, j, k) in one component array of the viscous divergence stage.  For n = 8
 // the index bits are swizzled so that the 64 lanes that read the m-th node of 64 different lines
@@ -476,7 +507,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
     if (dir == 2 && valid && t < n3) sjn = g.sJ[(size_t)e * n3 + t];  // for the epilogue
     __syncthreads();
-    if (FVO && valid && t < n3) {
+    if ((FVO || OUT == LIFT_WV) && valid && t < n3) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) jo[dir * 3 + d] = sJa[d * n3 + t];
     }
@@ -570,35 +601,13 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         for (int c = 0; c < 12; ++c) mg[c * n2] = acc[c];
       }
     }
-    if (OUT == LIFT_G || OUT == LIFT_GT) {
+    if (OUT == LIFT_G || OUT == LIFT_GT || (OUT == LIFT_WV && G)) {
       double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
       for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
     }
     if (FVO) {
-      // Newtonian stress with Stokes' hypothesis and Fourier heat flux, contracted with Ja^dir.
-      // Every rounding step is spelled out (explicit fma, no contraction), so every kernel that
-      // runs this lifting produces the same fluxes bit for bit.
-#pragma clang fp contract(off)
-      const double mu = ph.mu, div = (acc[0] + acc[5]) + acc[10];
-      const double t00 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[0]);
-      const double t11 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[5]);
-      const double t22 = mu * fma(-2.0 / 3.0, div, 2.0 * acc[10]);
-      const double t01 = mu * (acc[4] + acc[1]);
-      const double t02 = mu * (acc[8] + acc[2]);
-      const double t12 = mu * (acc[9] + acc[6]);
-      const double u = sW[t], v = sW[n3 + t], w = sW[2 * n3 + t];
-      const double dT0 = acc[3], dT1 = acc[7], dT2 = acc[11];
-      // acc takes the fluxes: acc[dir * 4 + c] = Fv^dir_c
-#pragma unroll
-      for (int dir = 0; dir < 3; ++dir) {
-        const double *nv = jo + 3 * dir;
-        acc[dir * 4] = fma(t02, nv[2], fma(t01, nv[1], t00 * nv[0]));
-        acc[dir * 4 + 1] = fma(t12, nv[2], fma(t11, nv[1], t01 * nv[0]));
-        acc[dir * 4 + 2] = fma(t22, nv[2], fma(t12, nv[1], t02 * nv[0]));
-        const double q = fma(dT2, nv[2], fma(dT1, nv[1], dT0 * nv[0]));
-        acc[dir * 4 + 3] = fma(ph.kappa, q, fma(acc[dir * 4 + 2], w, fma(acc[dir * 4 + 1], v, acc[dir * 4] * u)));
-      }
+      contra_visc(acc, jo, sW[t], sW[n3 + t], sW[2 * n3 + t], ph);
       if (OUT == LIFT_FV || OUT == LIFT_DIVK) {
         double *Fe = Fv + (size_t)e * 12 * n3;
 #pragma unroll
@@ -626,10 +635,96 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       }
     }
   }
-  if constexpr (OUT == LIFT_DIV || OUT == LIFT_DIVK) {
+  if constexpr (OUT == LIFT_WV) {
+    // weak form: every side's viscous flux at its trace (LG: gradients interpolated from LDS, U
+    // from the prolongation; LGL: the face node's), with the side's own outward normal; on a
+    // boundary side the BR1 mean with the outer state as the operator would form it (this side
+    // is the master).  The node's contravariant fluxes for the volume term below are formed first.
+    double u = 0.0, v = 0.0, w = 0.0;
+    if (valid && t < n3) { u = sW[t]; v = sW[n3 + t]; w = sW[2 * n3 + t]; }
+    __syncthreads();
+    if (valid && t < n3) {
+      const int q = div_slot<n>(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[c * n3 + q] = acc[c];
+      // the node's contravariant fluxes now: 12 values held across the face loop instead of the
+      // gradients and the metric terms
+      contra_visc(acc, jo, u, v, w, ph);
+    }
+    __syncthreads();
+    for (int p = valid ? t : 6 * n2; p < 6 * n2; p += NT) {
+      const int s = p / n2, ab = p - s * n2, a = ab % n, b = ab / n, dn = s >> 1;
+      const bool plus = s & 1;
+      double gq[12], Uq[5];
+      if (LGL) {
+        const int m = plus ? N : 0;
+        const int q = dn == 0 ? div_slot<n>(m, a, b) : (dn == 1 ? div_slot<n>(a, m, b) : div_slot<n>(a, b, m));
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gq[c] = sm[c * n3 + q];
+        const int qn = line_node<n>(dn, a, b, m);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Uq[c] = Ue[c * n3 + qn];
+      } else {
+        const double *lo = sl + (plus ? n : 0);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gq[c] = 0.0;
+#pragma unroll 1
+        for (int m = 0; m < n; ++m) {
+          const int q = dn == 0 ? div_slot<n>(m, a, b) : (dn == 1 ? div_slot<n>(a, m, b) : div_slot<n>(a, b, m));
+#pragma unroll
+          for (int c = 0; c < 12; ++c) gq[c] += lo[m] * sm[c * n3 + q];
+        }
+        const double *ut = g.Utr + ((size_t)e * 6 + s) * 5 * n2 + ab;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Uq[c] = ut[c * n2];
+      }
+      const double *fnp = g.fn + ((size_t)e * 6 + s) * 3 * n2 + ab;
+      const double nt[3] = {fnp[0], fnp[n2], fnp[2 * n2]};
+      double Fo[5];
+      flux_v(to_prim(Uq, gm1), gq, ph, nt, Fo);
+      const NbFace f = nbr_face<n, (GEN > 0)>(g, e, s, a, b);
+      if (GEN && f.bnd && f.kind != DG_BC_STATE && f.kind != DG_BC_OUTFLOW) {
+        // walls and symmetry planes: the outer state and gradients; a given outer state or
+        // outflow takes the outer viscous flux equal to the inner one (the mean is Fo itself)
+        const double sh = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        const double ish = 1.0 / sh;
+        const double nh[3] = {nt[0] * ish, nt[1] * ish, nt[2] * ish};
+        double Ux[5], gx[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) gx[c] = gq[c];
+        if (f.kind == DG_BC_WALL_ISOTHERMAL || f.kind == DG_BC_WALL) {
+          // no-slip wall: velocity reversed; at an adiabatic wall the temperature gradient mirrored
+          Ux[0] = Uq[0]; Ux[1] = -Uq[1]; Ux[2] = -Uq[2]; Ux[3] = -Uq[3]; Ux[4] = Uq[4];
+          if (f.kind == DG_BC_WALL) {
+            double tg[3] = {gq[3], gq[7], gq[11]};
+            mirror3(tg, nh);
+            gx[3] = tg[0]; gx[7] = tg[1]; gx[11] = tg[2];
+          }
+        } else {
+          // symmetry plane: mirror image of the inner state and gradients
+#pragma unroll
+          for (int c = 0; c < 5; ++c) Ux[c] = Uq[c];
+          mirror3(Ux + 1, nh);
+          mirror_grad(gx, nh);
+        }
+        double Fx[5];
+        flux_v(to_prim(Ux, gm1), gx, ph, nt, Fx);
+#pragma unroll
+        for (int c = 1; c < 5; ++c) Fo[c] = 0.5 * (Fo[c] + Fx[c]);
+      } else if (GEN && f.bnd) {
+#pragma unroll
+        for (int c = 1; c < 5; ++c) Fo[c] = 0.5 * (Fo[c] + Fo[c]);
+      }
+      double *pv = g.Gf + ((size_t)e * 6 + s) * 4 * n2 + ab;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pv[c * n2] = Fo[1 + c];
+    }
+  }
+  if constexpr (OUT == LIFT_DIV || OUT == LIFT_DIVK || OUT == LIFT_WV) {
     // strong-form divergence of the viscous fluxes for the split-form operator:
     // Gd_c = sum_dir (sum_m D_{id,m} Fv^dir_c(m on the line) + [face node] -+lhat(+-1) Fv^dir_c),
-    // the interior part of the surface term taken with the volume term.  The three regions are
+    // the interior part of the surface term taken with the volume term; for the weak form
+    // (LIFT_WV) Gd_c = sum_dir sum_m Dhat_{id,m} Fv^dir_c(m on the line).  The three regions are
     // free once every thread is past its last read of them.
     __syncthreads();
     if (valid && t < n3) {
@@ -641,11 +736,17 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     // one line, one direction and two components per task: the line's values are read once and
     // its n results written back in place (each LDS value is read once, not n times); the
     // matrix comes from the table through the scalar cache, the same for every lane
-    const __attribute__((address_space(4))) double *Dg = (const __attribute__((address_space(4))) double *)g.tab->D;
-    for (int task = valid ? t : 6 * n2; task < 6 * n2; task += NT) {
-      // with 2 n^2 a multiple of the wave size every wave works on one direction
-      const int dir = (2 * n2) % 64 == 0 ? __builtin_amdgcn_readfirstlane(task / (2 * n2)) : task / (2 * n2);
-      const int r = task - dir * 2 * n2, cp = r / n2, ln = r - cp * n2;
+    const __attribute__((address_space(4))) double *Dg =
+        (const __attribute__((address_space(4))) double *)(OUT == LIFT_WV ? g.tab->Dh : g.tab->D);
+    // TPD task slots per direction: 2 n^2 rounded up to whole waves where the three directions
+    // then still fit the workgroup in one pass (n = 7: 98 -> 128, 384 lanes), so that every wave
+    // works on one direction
+    constexpr int TPW = (2 * n2 + 63) / 64 * 64;
+    constexpr int TPD = (2 * n2) % 64 != 0 && 3 * TPW <= NT ? TPW : 2 * n2;
+    for (int task = valid ? t : 3 * TPD; task < 3 * TPD; task += NT) {
+      const int dir = TPD % 64 == 0 ? __builtin_amdgcn_readfirstlane(task / TPD) : task / TPD;
+      const int r = task - dir * TPD, cp = r / n2, ln = r - cp * n2;
+      if (TPD != 2 * n2 && r >= 2 * n2) continue;  // a padding slot
       const int a = ln % n, b = ln / n;
       double *s0 = sm + (dir * 4 + 2 * cp) * n3, *s1 = s0 + n3;
       double f0[n], f1[n];
@@ -761,7 +862,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_prolong(Geo g, Phys ph, const dou
 }
 
 template <int N, bool LGL, int OUT, int GEN>
-__global__ void __launch_bounds__(Sz<N>::NT, (LGL || GEN == 0 ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (LGL || GEN == 0 ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
@@ -784,6 +885,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   constexpr int NX = (FORM == 1) ? 8 : 5;
+  // WVM: weak form, Navier-Stokes, conforming faces: the lifting kernel has formed the viscous
+  // volume term (Geo::Gd) and every side's viscous flux at its trace (Geo::Gf); no gradients
+  constexpr bool WVM = NS && FORM == 0 && GEN < 2;
   __shared__ double sU[5 * n3];
   __shared__ double sX[NX * n3];
   __shared__ double sF[6 * 5 * n2];
@@ -838,7 +942,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
       for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = bnd ? 0.0 : Un[v * n3 + qn]; }
-      if (NS) {
+      if (NS && !WVM) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = bnd ? 0.0 : Gn[c * n3 + qn]; }
       }
@@ -863,13 +967,17 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 #pragma unroll
           for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
         }
+        if (!WVM) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) gw[c] = gt[c * n2];
+          for (int c = 0; c < 12; ++c) gw[c] = gt[c * n2];
+        }
         if (!bnd) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) Ux[v] = utn[v * n2];
+          if (!WVM) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) gx[c] = gtn[c * n2];
+            for (int c = 0; c < 12; ++c) gx[c] = gtn[c * n2];
+          }
         }
       } else {
         // a rolled loop: unrolled, the early loads of all n nodes' values spill
@@ -909,14 +1017,14 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     } else if (bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
       // isothermal wall: velocity reversed; outer gradient equal to the inner one
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
-      if (NS) {
+      if (NS && !WVM) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
       }
     } else if (bnd && f.kind == DG_BC_WALL) {
       // no-slip wall: velocity reversed; velocity gradient kept, temperature gradient mirrored
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
-      if (NS) {
+      if (NS && !WVM) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
         double tg[3] = {gw[3], gw[7], gw[11]};
@@ -928,7 +1036,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = Uw[v];
       mirror3(Ux + 1, nh);
-      if (NS) {
+      if (NS && !WVM) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
         mirror_grad(gx, nh);
@@ -939,7 +1047,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     riemann(ph, UM, US, nh, F);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
-    if (NS) {
+    if (NS && !WVM) {
       const double *gM = mst ? gw : gx, *gS = mst ? gx : gw;
       double FvM[5], FvS[5];
       const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
@@ -955,6 +1063,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sF[(s * 5 + v) * n2 + ab] = sg * F[v];
+    if (WVM) {
+      // minus the outward BR1 mean of the viscous flux: each side's flux carries its own outward
+      // normal (the two normals of a face are negatives of each other), a boundary side's the
+      // mean itself
+      const double *po = g.Gf + ((size_t)e * 6 + s) * 4 * n2 + ab;
+      if (bnd) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sF[(s * 5 + 1 + c) * n2 + ab] -= po[c * n2];
+      } else {
+        const double *pn = g.Gf + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sF[(s * 5 + 1 + c) * n2 + ab] -= 0.5 * (po[c * n2] - pn[c * n2]);
+      }
+    }
   }
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int i = t % n, j = (t / n) % n, k = t / n2;
@@ -962,7 +1084,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
   double go[12];  // the node's lifted gradients, loaded after the face phase
   if (t < n3) {
     Po = to_prim(Uo, gm1);
-    if (NS) {
+    if (NS && !WVM) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
     }
@@ -975,7 +1097,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
       nv[0] = Jd[0]; nv[1] = Jd[n3]; nv[2] = Jd[2 * n3];
       double Fc[5], Fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       flux_c(Uo, Po, nv, Fc);
-      if (NS) flux_v(Po, go, ph, nv, Fv);
+      if (NS && !WVM) flux_v(Po, go, ph, nv, Fv);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fint[v] = Fc[v] - Fv[v];
       if (FORM == 1) {
@@ -1043,6 +1165,11 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double
     }
   }
   if (t < n3) {
+    if (WVM) {
+      // the viscous volume term, formed by the lifting kernel
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[1 + c] -= g.Gd[((size_t)e * 4 + c) * n3 + t];
+    }
     const double sj = g.sJ[(size_t)e * n3 + t];
     if (MODE == 0) {
       double *Oe = out + (size_t)e * 5 * n3;
@@ -2483,7 +2610,17 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U
     else if (lev == 1) hipLaunchKernelGGL((k_lift<N, L_, O_, 1>), grid, block, 0, st, g, ph, U, G, Fv); \
     else hipLaunchKernelGGL((k_lift<N, L_, O_, 2>), grid, block, 0, st, g, ph, U, G, Fv); \
   } while (0)
-  if (!lgl) {
+  if (out == LIFT_WV) {
+    // the weak-form operator of conforming meshes
+    if (lev == 2) return DG_ERR_UNSUPPORTED;
+    if (lgl) {
+      if (lev == 0) hipLaunchKernelGGL((k_lift<N, true, LIFT_WV, 0>), grid, block, 0, st, g, ph, U, G, Fv);
+      else hipLaunchKernelGGL((k_lift<N, true, LIFT_WV, 1>), grid, block, 0, st, g, ph, U, G, Fv);
+    } else {
+      if (lev == 0) hipLaunchKernelGGL((k_lift<N, false, LIFT_WV, 0>), grid, block, 0, st, g, ph, U, G, Fv);
+      else hipLaunchKernelGGL((k_lift<N, false, LIFT_WV, 1>), grid, block, 0, st, g, ph, U, G, Fv);
+    }
+  } else if (!lgl) {
     if (out == LIFT_G) DG_KL(false, LIFT_G);
     else if (out == LIFT_GT) DG_KL(false, LIFT_GT);
     else return DG_ERR_UNSUPPORTED;

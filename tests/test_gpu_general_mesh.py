@@ -85,6 +85,7 @@ CASES = [
     ("euler_split_ec_volflux_lgl6", inputs.workload(3, eqn="euler", riemann="volflux", N=6, curved=True), 2),
     ("ns_split_kep_roe_lgl1", inputs.workload(2, N=1), 4),
     ("ns_split_kep_roe_lgl8", inputs.workload(2, N=8), 2),
+    ("ns_weak_lgl4_roe", inputs.workload(2, form="weak", volflux="central", N=4, curved=True), 3),
 ]
 
 
@@ -339,6 +340,7 @@ BOX_CASES = [
     ("ns_split_ec_roe_lgl7_rotated", inputs.workload(3), 2, 1),
     ("ns_weak_lg4_llf", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, None),
     ("ns_strong_lgl4_roe_rotated", inputs.workload(2, form="strong", volflux="central", N=4), 3, 2),
+    ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 5),
     ("euler_split_ec_volflux_roe_lgl3", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, None),
     ("euler_weak_lg3_llf_rotated", inputs.workload(1), 3, 3),
     ("ns_split_kep_roe_lgl1", inputs.workload(2, N=1), 4, None),
@@ -424,6 +426,7 @@ STATE_CASES = [
     ("ns_split_ec_roe_lgl7_rotated", inputs.workload(3), 2, 1),
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 2),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+    ("ns_weak_lgl3_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=3), 3, 6),
     ("euler_split_ec_volflux_roe_lgl3", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 4),
 ]
 
@@ -526,6 +529,7 @@ WALL_CASES = [
     ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 12),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+    ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 14),
     ("euler_split_ec_volflux_roe_lgl3_rotated", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 13),
 ]
 
@@ -642,6 +646,7 @@ ISO_CASES = [
     ("ns_split_ec_roe_lgl7", inputs.workload(3), 2, None),
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 22),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
+    ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 23),
 ]
 
 
@@ -751,6 +756,7 @@ OUT_CASES = [
     ("euler_weak_lgl4_llf", inputs.workload(1, nodes="lgl", N=4, curved=True), 3, None),
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 44),
     ("ns_strong_lg3_roe", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, None),
+    ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 45),
 ]
 
 

@@ -32,6 +32,8 @@ RHS_CASES = [
     ("cfg2_ns_split_kep_roe_lgl5_curved_k4", inputs.workload(2, K1=4), None),
     ("cfg3_ns_split_ec_roe_lgl7_k3", inputs.workload(3, K1=3), None),
     ("ns_weak_lg4_llf_curved", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4, K1=3), None),
+    ("ns_weak_lgl5_roe_curved", inputs.workload(2, form="weak", volflux="central", N=5, K1=3), None),
+    ("ns_weak_lg7_roe_ragged", inputs.workload(3, nodes="lg", form="weak", volflux="central", N=7), (2, 3, 2)),
     ("ns_strong_lgl4_roe_curved", inputs.workload(2, form="strong", volflux="central", N=4, K1=3), None),
     ("ns_strong_lg3_roe_curved", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3, K1=3), None),
     ("euler_strong_lg5_llf_ragged", inputs.workload(1, form="strong", riemann="llf", N=5), (2, 3, 2)),
@@ -176,7 +178,8 @@ def test_full_size_cfg3_sampled(dg, orc):
 @pytest.mark.parametrize("eqn,form,vf,rs,nodes", [
     ("euler", "weak", "central", "llf", "lg"), ("ns", "split", "ec", "roe", "lgl"),
     ("ns", "split", "kep", "roe", "lgl"), ("ns", "strong", "central", "llf", "lgl"),
-    ("ns", "strong", "central", "roe", "lg"),
+    ("ns", "strong", "central", "roe", "lg"), ("ns", "weak", "central", "roe", "lgl"),
+    ("ns", "weak", "central", "llf", "lg"),
 ])
 def test_freestream_and_conservation_gpu(dg, orc, eqn, form, vf, rs, nodes):
     wl = inputs.workload(2, eqn=eqn, form=form, volflux=vf, riemann=rs, nodes=nodes, N=4, K1=3)
