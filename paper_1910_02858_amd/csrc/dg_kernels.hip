@@ -875,11 +875,18 @@ __global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (
 }
 
 // ----------------------------------------------------------------------------- operator
+// waves per SIMD the weak-form Navier-Stokes operator is built for: 4 (128 registers, two
+// workgroups per CU at N = 7; it spills 12 bytes on LGL nodes, 124 on LG nodes) against the 130-158
+// registers it takes unbounded (one workgroup per CU): 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG)
+// at 48^3, N = 7.  Degrees below 5 (one or two waves per element) keep their registers.
+#ifndef DG_WMAIN_MINB
+#define DG_WMAIN_MINB 4
+#endif
 // FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
 // FVM: hybrid DG/FV mesh (Euler): finite-volume elements are left to k_fv_volume, and the sides
 // that meet one take their flux from Geo::fvFx.
 template <int N, bool LGL, bool NS, int FORM, int MODE, int GEN, bool FVM = false>
-__global__ void __launch_bounds__(Sz<N>::NT) k_main(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >= 5) ? DG_WMAIN_MINB : 1) k_main(Geo g, Phys ph, const double *__restrict__ U,
                                                     const double *__restrict__ G, double *__restrict__ out,
                                                     double *__restrict__ R, double ca, double cb, double dt) {
   using S = Sz<N>;
