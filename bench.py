@@ -35,8 +35,8 @@ BYTES_MAIN = 37 * 8
 # lifting for the split form: U 5 + Ja 9 + 1/J 1 read, viscous divergence 4 + face traces 3 written
 BYTES_LIFT = 22 * 8
 # weak-form operator at N = 7 (Navier-Stokes): U 5 + viscous volume term 4 + own face viscous fluxes 3
-# (24 n^2 per element) + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
-BYTES_WEAK_MAIN = 37 * 8
+# (24 n^2 per element) + face normals 2.25 (18 n^2) + Ja 9 + 1/J 1 + R 5 read, U_new 5 + R 5 written
+BYTES_WEAK_MAIN = 39.25 * 8
 # reverse stage: k_vjp_main reads U 5, the kept viscous fluxes' momentum part 9, Ja 9, 1/J 1,
 # Ubar_t 5, Ubar 5 and writes Ubar 5; k_vjp_face reads Ubar 5, Rbar 5 and writes Rbar 5
 BYTES_VJP_MAIN = 39 * 8
@@ -304,7 +304,7 @@ def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
     the face prolongation): the Euler density-wave scheme at N=3 on 96^3 LG elements and the
     Navier-Stokes TGV (central volume flux, Roe, BR1) at N=7 on 48^3 on LG and on LGL nodes, all
     56.6 M nodes; per-kernel times (the lifting's includes the LG prolongation), the operator
-    kernel priced at 296 B per node (Navier-Stokes) or at its Euler reads and writes (U 5, Ja 9,
+    kernel priced at 314 B per node (Navier-Stokes) or at its Euler reads and writes (U 5, Ja 9,
     1/J 1, R 5 read, U_new 5, R 5 written: 240 B)."""
     out = {}
     for name, wl, nbytes in (("euler_dwave_lg3_k96_weak", inputs.workload(1, K1=96), 30 * 8),
