@@ -28,6 +28,11 @@
 #ifndef DG_LIFT_MINB
 #define DG_LIFT_MINB 6
 #endif
+// the lifting of meshes with non-conforming faces: at 80 registers it spills 44 bytes, at 128 (two
+// workgroups per CU) none: 0.73 -> 0.65 ms at 16^3 N=7 half refined
+#ifndef DG_LIFT_MORTAR_MINB
+#define DG_LIFT_MORTAR_MINB 4
+#endif
 
 namespace dg {
 
@@ -862,7 +867,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_prolong(Geo g, Phys ph, const dou
 }
 
 template <int N, bool LGL, int OUT, int GEN>
-__global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (LGL || GEN == 0 ? DG_LIFT_MINB : 2)) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (GEN == 2 && LGL ? DG_LIFT_MORTAR_MINB : (LGL || GEN == 0 ? DG_LIFT_MINB : 2))) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
@@ -878,7 +883,8 @@ __global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (
 // waves per SIMD the weak-form Navier-Stokes operator is built for: 4 (128 registers, two
 // workgroups per CU at N = 7; it spills 12 bytes on LGL nodes, 124 on LG nodes) against the 130-158
 // registers it takes unbounded (one workgroup per CU): 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG)
-// at 48^3, N = 7.  Degrees below 5 (one or two waves per element) keep their registers.
+// at 48^3, N = 7.  Degrees below 5 (one or two waves per element) keep their registers, and so
+// does the Euler weak form (at N = 3 on 96^3 a 128-register budget spills 108 bytes: 5.20 -> 6.15 ms).
 #ifndef DG_WMAIN_MINB
 #define DG_WMAIN_MINB 4
 #endif
