@@ -647,11 +647,14 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
     // lifting outputs: 0 gradients, 2 divergence, 3 divergence and fluxes, 4 gradients and their
     // face traces (LG nodes), 5 the weak form's viscous volume term and face fluxes (conforming
     // meshes; the gradients too when kept)
+    // (the strong form on LGL nodes takes the split form's 2; with a kept stage the weak and
+    // strong forms' liftings also write the gradients)
     const bool lg = h->node_type != DG_NODES_LGL;
     const bool weak_v = h->sc.form == DG_FORM_WEAK && !h->nm;
-    const int out = split ? (Gkeep ? 3 : 2) : (weak_v ? 5 : (lg ? 4 : 0));
+    const bool strong_v = h->sc.form == DG_FORM_STRONG && !lg && !h->nm;
+    const int out = split ? (Gkeep ? 3 : 2) : (weak_v ? 5 : (strong_v ? 2 : (lg ? 4 : 0)));
     const int rc = split ? lift_dispatch(h, U, out, nullptr, dst)
-                         : lift_dispatch(h, U, out, weak_v ? Gkeep : dst, nullptr);
+                         : lift_dispatch(h, U, out, (weak_v || strong_v) ? Gkeep : dst, nullptr);
     if (rc) return rc;
   }
   if (h->prof) (void)hipEventRecord(h->ev[1], h->stream);
@@ -850,7 +853,7 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
   if (!rc && !fc.empty()) rc = dev_alloc(&h->d_fc, fc.size());
   if (!rc) rc = dev_alloc(&h->d_tab, 1);
   if (!rc && ns) rc = dev_alloc(&h->d_G, (size_t)K * 12 * n3);
-  if (!rc && ns && (sc->form == DG_FORM_SPLIT || sc->form == DG_FORM_WEAK)) {
+  if (!rc && ns) {
     rc = dev_alloc(&h->d_Gd, (size_t)K * 4 * n3);
     if (!rc) rc = dev_alloc(&h->d_Gf, (size_t)K * 24 * n2);
   }

@@ -606,7 +606,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         for (int c = 0; c < 12; ++c) mg[c * n2] = acc[c];
       }
     }
-    if (OUT == LIFT_G || OUT == LIFT_GT || (OUT == LIFT_WV && G)) {
+    if (OUT == LIFT_G || OUT == LIFT_GT || ((OUT == LIFT_WV || OUT == LIFT_DIV) && G)) {
       double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
       for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
@@ -880,7 +880,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (
 }
 
 // ----------------------------------------------------------------------------- operator
-// waves per SIMD the weak-form Navier-Stokes operator is built for: 4 (128 registers, two
+// waves per SIMD the weak-form (and LGL strong-form) Navier-Stokes operator is built for: 4 (128 registers, two
 // workgroups per CU at N = 7; it spills 12 bytes on LGL nodes, 124 on LG nodes) against the 130-158
 // registers it takes unbounded (one workgroup per CU): 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG)
 // at 48^3, N = 7.  Degrees below 5 (one or two waves per element) keep their registers, and so
@@ -892,7 +892,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (
 // FVM: hybrid DG/FV mesh (Euler): finite-volume elements are left to k_fv_volume, and the sides
 // that meet one take their flux from Geo::fvFx.
 template <int N, bool LGL, bool NS, int FORM, int MODE, int GEN, bool FVM = false>
-__global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >= 5) ? DG_WMAIN_MINB : 1) k_main(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM == 0 || (FORM == 2 && LGL))) ? DG_WMAIN_MINB : 1) k_main(Geo g, Phys ph, const double *__restrict__ U,
                                                     const double *__restrict__ G, double *__restrict__ out,
                                                     double *__restrict__ R, double ca, double cb, double dt) {
   using S = Sz<N>;
@@ -901,6 +901,11 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
   // WVM: weak form, Navier-Stokes, conforming faces: the lifting kernel has formed the viscous
   // volume term (Geo::Gd) and every side's viscous flux at its trace (Geo::Gf); no gradients
   constexpr bool WVM = NS && FORM == 0 && GEN < 2;
+  // SVM: strong form on LGL nodes, Navier-Stokes, conforming faces: as for the split form, the
+  // lifting kernel has formed the strong-form viscous divergence (Geo::Gd) and the face traces of
+  // the contravariant viscous fluxes (Geo::Gf)
+  constexpr bool SVM = NS && FORM == 2 && LGL && GEN < 2;
+  constexpr bool VH = WVM || SVM;  // no gradients read
   __shared__ double sU[5 * n3];
   __shared__ double sX[NX * n3];
   __shared__ double sF[6 * 5 * n2];
@@ -955,7 +960,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
       const int qn = GEN ? line_node<n>(f.dn, f.a, f.b, f.plus ? N : 0) : line_node<n>(dn, a, b, plus ? 0 : N);
 #pragma unroll
       for (int v = 0; v < 5; ++v) { Uw[v] = sU[v * n3 + q]; Ux[v] = bnd ? 0.0 : Un[v * n3 + qn]; }
-      if (NS && !WVM) {
+      if (NS && !VH) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) { gw[c] = Ge[c * n3 + q]; gx[c] = bnd ? 0.0 : Gn[c * n3 + qn]; }
       }
@@ -1030,14 +1035,14 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
     } else if (bnd && f.kind == DG_BC_WALL_ISOTHERMAL) {
       // isothermal wall: velocity reversed; outer gradient equal to the inner one
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
-      if (NS && !WVM) {
+      if (NS && !VH) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
       }
     } else if (bnd && f.kind == DG_BC_WALL) {
       // no-slip wall: velocity reversed; velocity gradient kept, temperature gradient mirrored
       Ux[0] = Uw[0]; Ux[1] = -Uw[1]; Ux[2] = -Uw[2]; Ux[3] = -Uw[3]; Ux[4] = Uw[4];
-      if (NS && !WVM) {
+      if (NS && !VH) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
         double tg[3] = {gw[3], gw[7], gw[11]};
@@ -1049,7 +1054,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
 #pragma unroll
       for (int v = 0; v < 5; ++v) Ux[v] = Uw[v];
       mirror3(Ux + 1, nh);
-      if (NS && !WVM) {
+      if (NS && !VH) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) gx[c] = gw[c];
         mirror_grad(gx, nh);
@@ -1060,7 +1065,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
     riemann(ph, UM, US, nh, F);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] *= sh;
-    if (NS && !WVM) {
+    if (NS && !VH) {
       const double *gM = mst ? gw : gx, *gS = mst ? gx : gw;
       double FvM[5], FvS[5];
       const Pr5 PM = to_prim(UM, gm1), PS = to_prim(US, gm1);
@@ -1076,6 +1081,37 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sF[(s * 5 + v) * n2 + ab] = sg * F[v];
+    if (SVM) {
+      // minus the BR1 mean of the viscous flux along this side's +xi_dn direction (the split
+      // form's reading of the traces and boundary kinds), applied outward
+      const double *fo = g.Gf + ((size_t)e * 6 + s) * 4 * n2 + ab;
+      double V[4];
+      if (given) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) V[c] = fo[c * n2];
+      } else if (bnd && (f.kind == DG_BC_WALL || f.kind == DG_BC_WALL_ISOTHERMAL)) {
+        // no-slip wall: the momentum part of the inner flux; at an isothermal wall the inner heat
+        // flux (the energy flux minus the work of the stress)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[c] = fo[c * n2];
+        V[3] = f.kind == DG_BC_WALL_ISOTHERMAL ? fo[3 * n2] - (V[0] * Uw[1] + V[1] * Uw[2] + V[2] * Uw[3]) * (1.0 / Uw[0])
+                                             : 0.0;
+      } else if (bnd) {
+        // symmetry plane: the normal part of the momentum flux
+        const double gm = fo[0] * nh[0] + fo[n2] * nh[1] + fo[2 * n2] * nh[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[c] = gm * nh[c];
+        V[3] = 0.0;
+      } else {
+        const double *pn = g.Gf + ((size_t)nb * 6 + 2 * f.dn + (f.plus ? 1 : 0)) * 4 * n2 + f.a + n * f.b;
+        const double sn = (GEN && f.plus == plus) ? -1.0 : 1.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) V[c] = 0.5 * (fo[c * n2] + sn * pn[c * n2]);
+      }
+      const double sp = plus ? 1.0 : -1.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sF[(s * 5 + 1 + c) * n2 + ab] -= sp * V[c];
+    }
     if (WVM) {
       // minus the outward BR1 mean of the viscous flux: each side's flux carries its own outward
       // normal (the two normals of a face are negatives of each other), a boundary side's the
@@ -1097,7 +1133,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
   double go[12];  // the node's lifted gradients, loaded after the face phase
   if (t < n3) {
     Po = to_prim(Uo, gm1);
-    if (NS && !WVM) {
+    if (NS && !VH) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
     }
@@ -1110,7 +1146,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
       nv[0] = Jd[0]; nv[1] = Jd[n3]; nv[2] = Jd[2 * n3];
       double Fc[5], Fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       flux_c(Uo, Po, nv, Fc);
-      if (NS && !WVM) flux_v(Po, go, ph, nv, Fv);
+      if (NS && !VH) flux_v(Po, go, ph, nv, Fv);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fint[v] = Fc[v] - Fv[v];
       if (FORM == 1) {
@@ -1178,7 +1214,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && FORM == 0 && GEN < 2 && N >=
     }
   }
   if (t < n3) {
-    if (WVM) {
+    if (VH) {
       // the viscous volume term, formed by the lifting kernel
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[1 + c] -= g.Gd[((size_t)e * 4 + c) * n3 + t];
