@@ -241,3 +241,29 @@ def test_node_coords_match_oracle(dg, orc):
         M, xgeo, nbr, side, _ = problem(orc, wl)
         S = gpu_solver(dg, wl, xgeo, nbr, side)
         np.testing.assert_allclose(S.node_coords(), M.points(), atol=1e-13)
+
+
+@pytest.mark.parametrize("form,nodes", [("weak", "lgl"), ("weak", "lg"), ("strong", "lgl"), ("strong", "lg")])
+def test_stage_keep_gradients_weak_strong(dg, orc, form, nodes):
+    """dg_rk_stage_keep for the weak and strong forms (Navier-Stokes): the same stage bit for bit
+    as dg_rk_stage, and the kept lifting output is the gradients of the stage input (against the
+    oracle's BR1 lifting)."""
+    import torch
+    wl = inputs.workload(2, form=form, volflux="central", nodes=nodes, N=4, K1=3)
+    M, xgeo, nbr, side, U0 = problem(orc, wl)
+    S = gpu_solver(dg, wl, xgeo, nbr, side)
+    Ug = to_gpu(U0)
+    dt = S.timestep(Ug, wl.cfl, wl.dfl)
+    a, b, _ = dg.rk_coefficients()
+    o1, o2 = S.empty(), S.empty()
+    R1 = to_gpu(inputs.random_perturbation(U0, 5, 1.0))
+    R2 = R1.clone()
+    G = S.empty_grad()
+    S.rk_stage_keep(Ug, o1, R1, a[1], b[1], dt, G)
+    S.rk_stage(Ug, o2, R2, a[1], b[1], dt)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2) and torch.equal(R1, R2)
+    ref = M.lift(U0, wl.gamma, wl.R)
+    err = norm_err(G.cpu().numpy(), ref)
+    print(f"kept gradients against the oracle's lifting: {err:.2e}")
+    assert err <= 1e-12
