@@ -302,11 +302,12 @@ def ec_branch_bench(S, U_smooth, torch, wl, smooth_main_ms: float, stages: int =
 def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
     """The weak and strong forms (k_main: the D-hat or D contraction of the fluxes along every
     line, on LG nodes the face prolongation): the Euler density-wave scheme at N=3 on 96^3 LG
-    elements, the Navier-Stokes TGV (central volume flux, Roe, BR1) in weak form at N=7 on 48^3 on
-    LG and on LGL nodes and in strong form on LGL nodes, all 56.6 M nodes; per-kernel times (the
-    lifting's includes the LG prolongation), the operator kernel priced at 314 B per node (weak
-    form, Navier-Stokes), 296 B (strong form: the split form's reads) or at its Euler reads and
-    writes (U 5, Ja 9, 1/J 1, R 5 read, U_new 5, R 5 written: 240 B)."""
+    elements, the Navier-Stokes TGV (central volume flux, Roe, BR1) in weak and strong form at N=7
+    on 48^3 on LG and on LGL nodes (strong form on LGL nodes: the split form's reads), all
+    56.6 M nodes; per-kernel times (the lifting's includes the LG prolongation), the operator
+    kernel priced at 314 B per node (weak form, strong form on LG nodes: face normals and face
+    fluxes), 296 B (strong form on LGL nodes) or at its Euler reads and writes (U 5, Ja 9, 1/J 1,
+    R 5 read, U_new 5, R 5 written: 240 B)."""
     out = {}
     for name, wl, nbytes in (("euler_dwave_lg3_k96_weak", inputs.workload(1, K1=96), 30 * 8),
                              ("ns_tgv_central_roe_lg7_k48_weak",
@@ -314,7 +315,9 @@ def weak_form_bench(dgsem, inputs, torch, stages: int = 10):
                              ("ns_tgv_central_roe_lgl7_k48_weak",
                               inputs.workload(3, form="weak", volflux="central", K1=48), BYTES_WEAK_MAIN),
                              ("ns_tgv_central_roe_lgl7_k48_strong",
-                              inputs.workload(3, form="strong", volflux="central", K1=48), BYTES_MAIN)):
+                              inputs.workload(3, form="strong", volflux="central", K1=48), BYTES_MAIN),
+                             ("ns_tgv_central_roe_lg7_k48_strong",
+                              inputs.workload(3, form="strong", volflux="central", nodes="lg", K1=48), BYTES_WEAK_MAIN)):
         S, U = dgsem.build_solver(wl)
         dt = S.timestep(U, wl.cfl, wl.dfl)
         a, b, _ = dgsem.rk_coefficients()

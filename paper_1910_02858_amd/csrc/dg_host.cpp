@@ -647,12 +647,13 @@ int rhs_dispatch(dg_handle *h, const double *U, double *out, double *R, double a
     // lifting outputs: 0 gradients, 2 divergence, 3 divergence and fluxes, 4 gradients and their
     // face traces (LG nodes), 5 the weak form's viscous volume term and face fluxes (conforming
     // meshes; the gradients too when kept)
-    // (the strong form on LGL nodes takes the split form's 2; with a kept stage the weak and
+    // (the strong form takes the split form's 2 on LGL nodes, 6 on LG nodes: the divergence with
+    // the interpolated interior surface term and the face fluxes; with a kept stage the weak and
     // strong forms' liftings also write the gradients)
     const bool lg = h->node_type != DG_NODES_LGL;
     const bool weak_v = h->sc.form == DG_FORM_WEAK && !h->nm;
-    const bool strong_v = h->sc.form == DG_FORM_STRONG && !lg && !h->nm;
-    const int out = split ? (Gkeep ? 3 : 2) : (weak_v ? 5 : (strong_v ? 2 : (lg ? 4 : 0)));
+    const bool strong_v = h->sc.form == DG_FORM_STRONG && !h->nm;
+    const int out = split ? (Gkeep ? 3 : 2) : (weak_v ? 5 : (strong_v ? (lg ? 6 : 2) : (lg ? 4 : 0)));
     const int rc = split ? lift_dispatch(h, U, out, nullptr, dst)
                          : lift_dispatch(h, U, out, (weak_v || strong_v) ? Gkeep : dst, nullptr);
     if (rc) return rc;

@@ -104,7 +104,7 @@ int launch_prolong(const Geo &g, const Phys &ph, const double *U, hipStream_t st
 // lifting: out 0 writes G (gradients), 1 Fv (contravariant viscous fluxes, LGL only), 2 the split
 // form's viscous divergence and face traces (Geo::Gd, Gf; LGL only), 3 both 1 and 2, 4 G and its
 // LG face traces (Geo::Gtr), 5 the weak form's viscous volume term and face fluxes (Geo::Gd, Gf;
-// G too when not NULL; conforming meshes)
+// G too when not NULL; conforming meshes), 6 the strong form's on LG nodes
 template <int N>
 int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U, double *G, double *Fv,
                 hipStream_t st);

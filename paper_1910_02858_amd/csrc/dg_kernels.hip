@@ -324,7 +324,10 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // term Geo::Gd (sums along the lines of D-hat times Fv^dir) and every side's viscous flux at its
 // trace, F^v(U, grad W) . n with the side's own outward normal (Geo::Gf; on a boundary side
 // already the BR1 mean with the outer state), and the gradients too when G is not NULL.
-enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4, LIFT_WV = 5 };
+// LIFT_SV (strong form on LG nodes, conforming meshes) writes the face fluxes as LIFT_WV and as
+// Geo::Gd the strong-form viscous term: sums along the lines of D times Fv^dir minus, for both
+// faces of each line, lhat(+-1) times +- the interior viscous flux interpolated to the face.
+enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4, LIFT_WV = 5, LIFT_SV = 6 };
 
 // The node's gradients acc[d*4+c] = dW_c/dx_d become its contravariant viscous fluxes
 // acc[dir*4+c] = (F^v . Ja^dir)_{1+c} (momentum, energy): Newtonian stress with Stokes'
@@ -512,7 +515,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
     if (dir == 2 && valid && t < n3) sjn = g.sJ[(size_t)e * n3 + t];  // for the epilogue
     __syncthreads();
-    if ((FVO || OUT == LIFT_WV) && valid && t < n3) {
+    if ((FVO || OUT == LIFT_WV || OUT == LIFT_SV) && valid && t < n3) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) jo[dir * 3 + d] = sJa[d * n3 + t];
     }
@@ -606,7 +609,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         for (int c = 0; c < 12; ++c) mg[c * n2] = acc[c];
       }
     }
-    if (OUT == LIFT_G || OUT == LIFT_GT || ((OUT == LIFT_WV || OUT == LIFT_DIV) && G)) {
+    if (OUT == LIFT_G || OUT == LIFT_GT || ((OUT == LIFT_WV || OUT == LIFT_SV || OUT == LIFT_DIV) && G)) {
       double *Ge = G + (size_t)e * 12 * n3;
 #pragma unroll
       for (int c = 0; c < 12; ++c) Ge[c * n3 + t] = acc[c];
@@ -640,8 +643,8 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       }
     }
   }
-  if constexpr (OUT == LIFT_WV) {
-    // weak form: every side's viscous flux at its trace (LG: gradients interpolated from LDS, U
+  if constexpr (OUT == LIFT_WV || OUT == LIFT_SV) {
+    // weak form (and strong form on LG nodes): every side's viscous flux at its trace (LG: gradients interpolated from LDS, U
     // from the prolongation; LGL: the face node's), with the side's own outward normal; on a
     // boundary side the BR1 mean with the outer state as the operator would form it (this side
     // is the master).  The node's contravariant fluxes for the volume term below are formed first.
@@ -725,7 +728,7 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
       for (int c = 0; c < 4; ++c) pv[c * n2] = Fo[1 + c];
     }
   }
-  if constexpr (OUT == LIFT_DIV || OUT == LIFT_DIVK || OUT == LIFT_WV) {
+  if constexpr (OUT == LIFT_DIV || OUT == LIFT_DIVK || OUT == LIFT_WV || OUT == LIFT_SV) {
     // strong-form divergence of the viscous fluxes for the split-form operator:
     // Gd_c = sum_dir (sum_m D_{id,m} Fv^dir_c(m on the line) + [face node] -+lhat(+-1) Fv^dir_c),
     // the interior part of the surface term taken with the volume term; for the weak form
@@ -761,6 +764,17 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         f0[m] = s0[q];
         f1[m] = s1[q];
       }
+      // LIFT_SV: the interior fluxes interpolated to the line's two faces
+      double tm0 = 0.0, tm1 = 0.0, tp0 = 0.0, tp1 = 0.0;
+      if (OUT == LIFT_SV) {
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+          tm0 = fma(sl[m], f0[m], tm0);
+          tm1 = fma(sl[m], f1[m], tm1);
+          tp0 = fma(sl[n + m], f0[m], tp0);
+          tp1 = fma(sl[n + m], f1[m], tp1);
+        }
+      }
 #pragma unroll 2
       for (int id = 0; id < n; ++id) {
         double o0 = 0.0, o1 = 0.0;
@@ -769,6 +783,14 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
           const double D = Dg[id * n + m];
           o0 = fma(D, f0[m], o0);
           o1 = fma(D, f1[m], o1);
+        }
+        if (OUT == LIFT_SV) {
+          // minus lhat(+-1) times the outward interior flux: -(-1) at the minus face, -(+1) at
+          // the plus face
+          o0 = fma(slh[id], tm0, o0);
+          o1 = fma(slh[id], tm1, o1);
+          o0 = fma(-slh[n + id], tp0, o0);
+          o1 = fma(-slh[n + id], tp1, o1);
         }
         const int q = dir == 0 ? div_slot<n>(id, a, b) : (dir == 1 ? div_slot<n>(a, id, b) : div_slot<n>(a, b, id));
         s0[q] = o0;
@@ -867,7 +889,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_prolong(Geo g, Phys ph, const dou
 }
 
 template <int N, bool LGL, int OUT, int GEN>
-__global__ void __launch_bounds__(Sz<N>::NT, (OUT == LIFT_WV && GEN > 0) ? 4 : (GEN == 2 && LGL ? DG_LIFT_MORTAR_MINB : (LGL || GEN == 0 ? DG_LIFT_MINB : 2))) k_lift(Geo g, Phys ph, const double *__restrict__ U,
+__global__ void __launch_bounds__(Sz<N>::NT, ((OUT == LIFT_WV || OUT == LIFT_SV) && GEN > 0) ? 4 : (GEN == 2 && LGL ? DG_LIFT_MORTAR_MINB : (LGL || GEN == 0 ? DG_LIFT_MINB : 2))) k_lift(Geo g, Phys ph, const double *__restrict__ U,
                                                                   double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
@@ -905,7 +927,12 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM =
   // lifting kernel has formed the strong-form viscous divergence (Geo::Gd) and the face traces of
   // the contravariant viscous fluxes (Geo::Gf)
   constexpr bool SVM = NS && FORM == 2 && LGL && GEN < 2;
-  constexpr bool VH = WVM || SVM;  // no gradients read
+  // SVL: strong form on LG nodes, Navier-Stokes, conforming faces: the lifting kernel has formed
+  // the strong-form viscous volume and interior surface terms (Geo::Gd) and, as for the weak form,
+  // every side's viscous flux at its trace (Geo::Gf)
+  constexpr bool SVL = NS && FORM == 2 && !LGL && GEN < 2;
+  constexpr bool PFM = WVM || SVL;  // face viscous fluxes with each side's own normal
+  constexpr bool VH = WVM || SVM || SVL;  // no gradients read
   __shared__ double sU[5 * n3];
   __shared__ double sX[NX * n3];
   __shared__ double sF[6 * 5 * n2];
@@ -985,14 +1012,14 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM =
 #pragma unroll
           for (int v = 0; v < 5; ++v) Uw[v] += lo[m] * sU[v * n3 + q];
         }
-        if (!WVM) {
+        if (!VH) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) gw[c] = gt[c * n2];
         }
         if (!bnd) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) Ux[v] = utn[v * n2];
-          if (!WVM) {
+          if (!VH) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) gx[c] = gtn[c * n2];
           }
@@ -1112,7 +1139,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM =
 #pragma unroll
       for (int c = 0; c < 4; ++c) sF[(s * 5 + 1 + c) * n2 + ab] -= sp * V[c];
     }
-    if (WVM) {
+    if (PFM) {
       // minus the outward BR1 mean of the viscous flux: each side's flux carries its own outward
       // normal (the two normals of a face are negatives of each other), a boundary side's the
       // mean itself
@@ -2659,7 +2686,12 @@ int launch_lift(const Geo &g, const Phys &ph, bool lgl, int out, const double *U
     else if (lev == 1) hipLaunchKernelGGL((k_lift<N, L_, O_, 1>), grid, block, 0, st, g, ph, U, G, Fv); \
     else hipLaunchKernelGGL((k_lift<N, L_, O_, 2>), grid, block, 0, st, g, ph, U, G, Fv); \
   } while (0)
-  if (out == LIFT_WV) {
+  if (out == LIFT_SV) {
+    // the strong-form operator of conforming meshes on LG nodes
+    if (lev == 2 || lgl) return DG_ERR_UNSUPPORTED;
+    if (lev == 0) hipLaunchKernelGGL((k_lift<N, false, LIFT_SV, 0>), grid, block, 0, st, g, ph, U, G, Fv);
+    else hipLaunchKernelGGL((k_lift<N, false, LIFT_SV, 1>), grid, block, 0, st, g, ph, U, G, Fv);
+  } else if (out == LIFT_WV) {
     // the weak-form operator of conforming meshes
     if (lev == 2) return DG_ERR_UNSUPPORTED;
     if (lgl) {

@@ -86,6 +86,7 @@ CASES = [
     ("ns_split_kep_roe_lgl1", inputs.workload(2, N=1), 4),
     ("ns_split_kep_roe_lgl8", inputs.workload(2, N=8), 2),
     ("ns_weak_lgl4_roe", inputs.workload(2, form="weak", volflux="central", N=4, curved=True), 3),
+    ("ns_strong_lg3_roe", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3, curved=True), 3),
 ]
 
 
@@ -341,6 +342,7 @@ BOX_CASES = [
     ("ns_weak_lg4_llf", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, None),
     ("ns_strong_lgl4_roe_rotated", inputs.workload(2, form="strong", volflux="central", N=4), 3, 2),
     ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 5),
+    ("ns_strong_lg3_roe_rotated", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, 7),
     ("euler_split_ec_volflux_roe_lgl3", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, None),
     ("euler_weak_lg3_llf_rotated", inputs.workload(1), 3, 3),
     ("ns_split_kep_roe_lgl1", inputs.workload(2, N=1), 4, None),
@@ -427,6 +429,7 @@ STATE_CASES = [
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 2),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
     ("ns_weak_lgl3_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=3), 3, 6),
+    ("ns_strong_lg3_roe_rotated", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, 8),
     ("euler_split_ec_volflux_roe_lgl3", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 4),
 ]
 
@@ -530,6 +533,7 @@ WALL_CASES = [
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 12),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
     ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 14),
+    ("ns_strong_lg3_roe_rotated", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, 15),
     ("euler_split_ec_volflux_roe_lgl3_rotated", inputs.workload(3, eqn="euler", riemann="volflux_roe", N=3), 3, 13),
 ]
 
@@ -647,6 +651,7 @@ ISO_CASES = [
     ("ns_weak_lg4_llf_rotated", inputs.workload(2, nodes="lg", form="weak", riemann="llf", N=4), 3, 22),
     ("ns_strong_lgl3_roe", inputs.workload(2, form="strong", volflux="central", N=3), 3, None),
     ("ns_weak_lgl4_roe_rotated", inputs.workload(2, form="weak", volflux="central", N=4), 3, 23),
+    ("ns_strong_lg3_roe_rotated", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3), 3, 24),
 ]
 
 

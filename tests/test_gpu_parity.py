@@ -38,6 +38,10 @@ RHS_CASES = [
     ("ns_weak_lgl8_roe_ragged", inputs.workload(2, form="weak", volflux="central", N=8), (2, 2, 3)),
     ("ns_weak_lg8_roe_ragged", inputs.workload(2, nodes="lg", form="weak", volflux="central", N=8), (2, 3, 2)),
     ("ns_weak_lgl6_roe_ragged", inputs.workload(2, form="weak", volflux="central", N=6), (3, 2, 2)),
+    ("ns_strong_lg7_roe_ragged", inputs.workload(3, nodes="lg", form="strong", volflux="central", N=7), (2, 2, 3)),
+    ("ns_strong_lg1_llf_ragged", inputs.workload(2, nodes="lg", form="strong", volflux="central", riemann="llf",
+                                                 N=1), (3, 4, 2)),
+    ("ns_strong_lgl8_roe_ragged", inputs.workload(2, form="strong", volflux="central", N=8), (2, 3, 2)),
     ("ns_strong_lgl4_roe_curved", inputs.workload(2, form="strong", volflux="central", N=4, K1=3), None),
     ("ns_strong_lg3_roe_curved", inputs.workload(2, nodes="lg", form="strong", volflux="central", N=3, K1=3), None),
     ("euler_strong_lg5_llf_ragged", inputs.workload(1, form="strong", riemann="llf", N=5), (2, 3, 2)),
