@@ -145,6 +145,38 @@ def test_roe_property(orc):
     np.testing.assert_allclose(F, orc.euler_flux(U, np.array([1.0, 0, 0])), rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("mach", [1.2, 2.0, 5.0])
+def test_roe_stationary_shock_exact(orc, mach):
+    """A stationary normal shock (Rankine-Hugoniot states, any tangential velocity) is a single
+    wave of zero speed: without an entropy fix the Roe flux between its two states is the exact
+    flux F(U1) = F(U2), the dissipation term vanishing."""
+    rng = np.random.default_rng(int(mach * 10))
+    for _ in range(10):
+        nh = _unit(rng)
+        t1 = np.cross(nh, _unit(rng))
+        t1 /= np.linalg.norm(t1)
+        vt = rng.uniform(-2, 2) * t1
+        r1, p1 = rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0)
+        un1 = mach * np.sqrt(GAMMA * p1 / r1)
+        m2 = mach * mach
+        r2 = r1 * (GAMMA + 1) * m2 / ((GAMMA - 1) * m2 + 2)
+        p2 = p1 * (1 + 2 * GAMMA / (GAMMA + 1) * (m2 - 1))
+        un2 = un1 * r1 / r2
+
+        def state(r, un, p):
+            v = un * nh + vt
+            return np.array([r, *(r * v), p / (GAMMA - 1) + 0.5 * r * np.dot(v, v)])
+
+        U1, U2 = state(r1, un1, p1), state(r2, un2, p2)
+        F1, F2 = orc.euler_flux(U1, nh), orc.euler_flux(U2, nh)
+        np.testing.assert_allclose(F1, F2, rtol=1e-12, atol=1e-12 * np.abs(F1).max())
+        F = orc.riemann("roe", U1, U2, nh)
+        np.testing.assert_allclose(F, F1, rtol=0, atol=1e-12 * np.abs(F1).max())
+        # the same shock seen from the other side (flow towards -nh)
+        Fb = orc.riemann("roe", U2, U1, -nh)
+        np.testing.assert_allclose(Fb, -F1, rtol=0, atol=1e-12 * np.abs(F1).max())
+
+
 @pytest.mark.parametrize("spread", [1e-3, 0.3, 2.0])
 def test_ec_flux_tadmor_condition(orc, spread):
     """(w_b - w_a) . F#(a,b;n) = rho_b u_b.n - rho_a u_a.n (both log-mean branches)."""
