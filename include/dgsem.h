@@ -272,7 +272,8 @@ int dg_rk_steps_vjp(dg_handle *h, int nsteps, const double *const *stage_U, cons
  * reference direction from the metric terms).  Synchronous; result in *dt_out (host). */
 int dg_timestep(dg_handle *h, const double *U, double cfl, double dfl, double *dt_out);
 
-/* Quadrature integrals sum_e sum_ijk J w_i w_j w_k X over the mesh, synchronous, host
+/* Quadrature integrals sum_e sum_ijk J w_i w_j w_k X over the mesh (the collocated quadrature
+ * of the time-derivative term, Sec. 3.1 eq. discTemp), synchronous, host
  * out[8] = {rho, rho u, rho v, rho w, E, kinetic energy, entropy -rho s/(gamma-1), min J}. */
 int dg_integrals(dg_handle *h, const double *U, double out[8]);
 
