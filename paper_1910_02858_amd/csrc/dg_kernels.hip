@@ -644,10 +644,11 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     }
   }
   if constexpr (OUT == LIFT_WV || OUT == LIFT_SV) {
-    // weak form (and strong form on LG nodes): every side's viscous flux at its trace (LG: gradients interpolated from LDS, U
-    // from the prolongation; LGL: the face node's), with the side's own outward normal; on a
-    // boundary side the BR1 mean with the outer state as the operator would form it (this side
-    // is the master).  The node's contravariant fluxes for the volume term below are formed first.
+    // weak form (and strong form on LG nodes): every side's viscous flux at its trace (LG:
+    // gradients interpolated from LDS, U from the prolongation; LGL: the face node's), with the
+    // side's own outward normal; on a boundary side the BR1 mean with the outer state as the
+    // operator would form it (this side is the master).  The node's contravariant fluxes for the
+    // volume term below are formed first.
     double u = 0.0, v = 0.0, w = 0.0;
     if (valid && t < n3) { u = sW[t]; v = sW[n3 + t]; w = sW[2 * n3 + t]; }
     __syncthreads();
@@ -888,9 +889,16 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_prolong(Geo g, Phys ph, const dou
   }
 }
 
+// waves per SIMD each lifting instantiation is built for (caps its registers)
+template <bool LGL, int OUT, int GEN> constexpr int lift_minb() {
+  if ((OUT == LIFT_WV || OUT == LIFT_SV) && GEN > 0) return 4;  // boundary code: 128 registers
+  if (GEN == 2 && LGL) return DG_LIFT_MORTAR_MINB;
+  return (LGL || GEN == 0) ? DG_LIFT_MINB : 2;
+}
+
 template <int N, bool LGL, int OUT, int GEN>
-__global__ void __launch_bounds__(Sz<N>::NT, ((OUT == LIFT_WV || OUT == LIFT_SV) && GEN > 0) ? 4 : (GEN == 2 && LGL ? DG_LIFT_MORTAR_MINB : (LGL || GEN == 0 ? DG_LIFT_MINB : 2))) k_lift(Geo g, Phys ph, const double *__restrict__ U,
-                                                                  double *__restrict__ G, double *__restrict__ Fv) {
+__global__ void __launch_bounds__(Sz<N>::NT, (lift_minb<LGL, OUT, GEN>()))
+    k_lift(Geo g, Phys ph, const double *__restrict__ U, double *__restrict__ G, double *__restrict__ Fv) {
   using L = LiftLds<N>;
   constexpr int n = L::n;
   __shared__ double sm[L::W + L::JA + L::WS];
@@ -902,21 +910,27 @@ __global__ void __launch_bounds__(Sz<N>::NT, ((OUT == LIFT_WV || OUT == LIFT_SV)
 }
 
 // ----------------------------------------------------------------------------- operator
-// waves per SIMD the weak-form (and LGL strong-form) Navier-Stokes operator is built for: 4 (128 registers, two
-// workgroups per CU at N = 7; it spills 12 bytes on LGL nodes, 124 on LG nodes) against the 130-158
-// registers it takes unbounded (one workgroup per CU): 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG)
-// at 48^3, N = 7.  Degrees below 5 (one or two waves per element) keep their registers, and so
-// does the Euler weak form (at N = 3 on 96^3 a 128-register budget spills 108 bytes: 5.20 -> 6.15 ms).
+// waves per SIMD the Navier-Stokes weak-form operator and the LGL strong-form one are built for:
+// 4 (128 registers, two workgroups per CU at N = 7; they spill 12 bytes on LGL nodes, the weak
+// form 124 on LG nodes) against the 130-158 registers they take unbounded (one workgroup per CU):
+// weak form 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG) at 48^3, N = 7.  Degrees below 5 (one or
+// two waves per element) keep their registers, and so do the Euler forms (at N = 3 on 96^3 a
+// 128-register budget spills 108 bytes: 5.20 -> 6.15 ms) and the LG strong form (164 registers;
+// at 128 it spills 276 bytes).
 #ifndef DG_WMAIN_MINB
 #define DG_WMAIN_MINB 4
 #endif
+template <int N, bool LGL, bool NS, int FORM, int GEN> constexpr int main_minb() {
+  return (NS && GEN < 2 && N >= 5 && (FORM == 0 || (FORM == 2 && LGL))) ? DG_WMAIN_MINB : 1;
+}
+
 // FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
 // FVM: hybrid DG/FV mesh (Euler): finite-volume elements are left to k_fv_volume, and the sides
 // that meet one take their flux from Geo::fvFx.
 template <int N, bool LGL, bool NS, int FORM, int MODE, int GEN, bool FVM = false>
-__global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM == 0 || (FORM == 2 && LGL))) ? DG_WMAIN_MINB : 1) k_main(Geo g, Phys ph, const double *__restrict__ U,
-                                                    const double *__restrict__ G, double *__restrict__ out,
-                                                    double *__restrict__ R, double ca, double cb, double dt) {
+__global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()))
+    k_main(Geo g, Phys ph, const double *__restrict__ U, const double *__restrict__ G, double *__restrict__ out,
+           double *__restrict__ R, double ca, double cb, double dt) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, NT = S::NT;
   constexpr int NX = (FORM == 1) ? 8 : 5;
@@ -1121,8 +1135,9 @@ __global__ void __launch_bounds__(Sz<N>::NT, (NS && GEN < 2 && N >= 5 && (FORM =
         // flux (the energy flux minus the work of the stress)
 #pragma unroll
         for (int c = 0; c < 3; ++c) V[c] = fo[c * n2];
-        V[3] = f.kind == DG_BC_WALL_ISOTHERMAL ? fo[3 * n2] - (V[0] * Uw[1] + V[1] * Uw[2] + V[2] * Uw[3]) * (1.0 / Uw[0])
-                                             : 0.0;
+        V[3] = f.kind == DG_BC_WALL_ISOTHERMAL
+                   ? fo[3 * n2] - (V[0] * Uw[1] + V[1] * Uw[2] + V[2] * Uw[3]) * (1.0 / Uw[0])
+                   : 0.0;
       } else if (bnd) {
         // symmetry plane: the normal part of the momentum flux
         const double gm = fo[0] * nh[0] + fo[n2] * nh[1] + fo[2 * n2] * nh[2];
