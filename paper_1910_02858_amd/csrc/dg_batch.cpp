@@ -62,6 +62,11 @@ struct dg_batch {
   std::vector<Graph> graphs;
   hipStream_t cap = nullptr;  // private stream for graph capture and replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // one branch per degree group inside the step graph (the groups share no data), forked from
+  // and joined to the capture stream with events
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> br_ev;
+  hipEvent_t fork_ev = nullptr;
   bool ns = false;
   int vf = 0;
   int fused = 0;  // 1: one lifting and one operator launch per stage for all degrees
@@ -207,16 +212,45 @@ int launch_stage_fused(dg_batch *b, const dg::Member *table, hipStream_t st) {
   return DG_OK;
 }
 
+int launch_group_stage(dg_batch *b, const Group &g, const dg::Member *table, hipStream_t st) {
+  const dg::BatchView v = view(b, g, table);
+  if (b->ns) {
+    int rc = batch_lift(g.N, v, g.epb_lift, st);
+    if (rc) return bfail(b, rc, "launch of a batched lifting kernel failed");
+  }
+  int rc = batch_split(g.N, v, b->ns, b->vf, g.epb_main, st);
+  if (rc) return bfail(b, rc, "launch of a batched operator kernel failed");
+  return DG_OK;
+}
+
 int launch_stage(dg_batch *b, const dg::Member *table, hipStream_t st) {
   if (b->fused) return launch_stage_fused(b, table, st);
   for (const Group &g : b->groups) {
-    const dg::BatchView v = view(b, g, table);
-    if (b->ns) {
-      int rc = batch_lift(g.N, v, g.epb_lift, st);
-      if (rc) return bfail(b, rc, "launch of a batched lifting kernel failed");
-    }
-    int rc = batch_split(g.N, v, b->ns, b->vf, g.epb_main, st);
-    if (rc) return bfail(b, rc, "launch of a batched operator kernel failed");
+    const int rc = launch_group_stage(b, g, table, st);
+    if (rc) return rc;
+  }
+  return DG_OK;
+}
+
+#ifndef DG_BATCH_BRANCHES
+#define DG_BATCH_BRANCHES 1
+#endif
+// the five stages of a step into the capture stream: with several degree groups, each group's
+// ten launches on its own branch (fork and join through events), so that the graph lets the
+// groups' kernels overlap
+int capture_step(dg_batch *b, const dg::Member *const *tabs) {
+  if (b->fused || b->groups.size() < 2 || !DG_BATCH_BRANCHES) {
+    for (int s = 0; s < 5; ++s)
+      if (int rc = launch_stage(b, tabs[s], b->cap)) return rc;
+    return DG_OK;
+  }
+  if (hipEventRecord(b->fork_ev, b->cap) != hipSuccess) return bfail(b, DG_ERR_HIP, "graph fork failed");
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    if (hipStreamWaitEvent(b->br[gi], b->fork_ev, 0) != hipSuccess) return bfail(b, DG_ERR_HIP, "graph fork failed");
+    for (int s = 0; s < 5; ++s)
+      if (int rc = launch_group_stage(b, b->groups[gi], tabs[s], b->br[gi])) return rc;
+    if (hipEventRecord(b->br_ev[gi], b->br[gi]) != hipSuccess || hipStreamWaitEvent(b->cap, b->br_ev[gi], 0) != hipSuccess)
+      return bfail(b, DG_ERR_HIP, "graph join failed");
   }
   return DG_OK;
 }
@@ -281,9 +315,19 @@ int dg_batch_create(dg_handle *const *members, int n_members, dg_batch **out) {
     }
     b->groups.push_back(g);
   }
-  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+  bool ok = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (size_t gi = 0; ok && gi < b->groups.size(); ++gi) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    if (ok) b->br.push_back(st);
+    ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->br_ev.push_back(ev);
+  }
+  if (!ok) {
     (void)hipGetLastError();
     dg_batch_destroy(b);
     return DG_ERR_HIP;
@@ -362,8 +406,7 @@ int dg_batch_step(dg_batch *b, double *const *U, double *const *U_out, double *c
     }
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bfail(b, DG_ERR_HIP, "stream capture could not start");
-    int lrc = DG_OK;
-    for (int s = 0; s < 5 && !lrc; ++s) lrc = launch_stage(b, tabs[s], b->cap);
+    const int lrc = capture_step(b, tabs);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(b->cap, &graph);
     if (lrc) {
@@ -547,6 +590,9 @@ void dg_batch_destroy(dg_batch *b) {
     if (g.d_first) (void)hipFree(g.d_first);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  for (hipEvent_t ev : b->br_ev) (void)hipEventDestroy(ev);
+  for (hipStream_t st : b->br) (void)hipStreamDestroy(st);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
