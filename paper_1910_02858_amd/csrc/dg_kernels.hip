@@ -1174,7 +1174,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
   Pr5 Po;
   double go[12];  // the node's lifted gradients, loaded after the face phase
   if (t < n3) {
-    Po = to_prim(Uo, gm1);
+    if (!VH) Po = to_prim(Uo, gm1);
     if (NS && !VH) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) go[c] = Ge[c * n3 + t];
@@ -1187,7 +1187,11 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
       const double *Jd = g.Ja + ((size_t)e * 9 + dir * 3) * n3 + t;
       nv[0] = Jd[0]; nv[1] = Jd[n3]; nv[2] = Jd[2 * n3];
       double Fc[5], Fv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      flux_c(Uo, Po, nv, Fc);
+      double Un[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Un[v] = sU[v * n3 + t];
+      if (VH) Po = to_prim(Un, gm1);  // recomputed per direction: not held across the phases
+      flux_c(Un, Po, nv, Fc);
       if (NS && !VH) flux_v(Po, go, ph, nv, Fv);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fint[v] = Fc[v] - Fv[v];
@@ -1275,7 +1279,7 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
         // a = 0 (first stage) does not read R, so R may hold anything on entry
         const double r = (ca != 0.0 ? ca * Re[v * n3 + t] : 0.0) + dt * ut;
         Re[v * n3 + t] = r;
-        Oe[v * n3 + t] = Uo[v] + cb * r;
+        Oe[v * n3 + t] = sU[v * n3 + t] + cb * r;  // the node's state from LDS: not held in registers
       }
     }
   }
