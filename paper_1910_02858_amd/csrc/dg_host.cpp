@@ -794,6 +794,9 @@ int dg_init(const dg_mesh *mesh, int N, int node_type, const dg_scheme *sc, void
     h->tab.lhm[j] = (double)(B.lm[j] / B.w[j]); h->tab.lhp[j] = (double)(B.lp[j] / B.w[j]);
     h->tab.w[j] = (double)B.w[j];
   }
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < n; ++m)
+      h->tab.Ds[i * n + m] = (double)(B.D[i * n + m] - (B.lp[i] / B.w[i]) * B.lp[m] + (B.lm[i] / B.w[i]) * B.lm[m]);
   // mortar operators of the solution nodes (Sec. 3.2)
   for (int i = 0; i < n; ++i)
     for (int m = 0; m < n; ++m) {

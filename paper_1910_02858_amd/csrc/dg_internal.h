@@ -18,6 +18,10 @@ constexpr int NMAX = 8;  // highest supported polynomial degree
 struct Tab {
   double D[(NMAX + 1) * (NMAX + 1)];
   double Dh[(NMAX + 1) * (NMAX + 1)];
+  // strong form on LG nodes (eq. semiDiscreteStrong): the volume derivative together with the
+  // interior flux interpolated to both faces of the line and lifted back,
+  // Ds[i*n+m] = D[i*n+m] - lhat_i(+1) l_m(+1) + lhat_i(-1) l_m(-1), one contraction per line
+  double Ds[(NMAX + 1) * (NMAX + 1)];
   double lm[NMAX + 1], lp[NMAX + 1], lhm[NMAX + 1], lhp[NMAX + 1], w[NMAX + 1];
   // mortar operators (Sec. 3.2): interpolation of the big side to its lower / upper half,
   // IL[i*n+m] = l_m((x_i - 1)/2), IU likewise with +1, and the projection back,

@@ -326,7 +326,8 @@ __device__ __forceinline__ void lift_tables(const Tab *tb, int t, int nthreads, 
 // already the BR1 mean with the outer state), and the gradients too when G is not NULL.
 // LIFT_SV (strong form on LG nodes, conforming meshes) writes the face fluxes as LIFT_WV and as
 // Geo::Gd the strong-form viscous term: sums along the lines of D times Fv^dir minus, for both
-// faces of each line, lhat(+-1) times +- the interior viscous flux interpolated to the face.
+// faces of each line, lhat(+-1) times +- the interior viscous flux interpolated to the face (both
+// in one contraction with Tab::Ds).
 enum { LIFT_G = 0, LIFT_FV = 1, LIFT_DIV = 2, LIFT_DIVK = 3, LIFT_GT = 4, LIFT_WV = 5, LIFT_SV = 6 };
 
 // The node's gradients acc[d*4+c] = dW_c/dx_d become its contravariant viscous fluxes
@@ -733,7 +734,8 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     // strong-form divergence of the viscous fluxes for the split-form operator:
     // Gd_c = sum_dir (sum_m D_{id,m} Fv^dir_c(m on the line) + [face node] -+lhat(+-1) Fv^dir_c),
     // the interior part of the surface term taken with the volume term; for the weak form
-    // (LIFT_WV) Gd_c = sum_dir sum_m Dhat_{id,m} Fv^dir_c(m on the line).  The three regions are
+    // (LIFT_WV) Gd_c = sum_dir sum_m Dhat_{id,m} Fv^dir_c(m on the line), for the strong form on LG
+    // nodes (LIFT_SV) the same with Tab::Ds.  The three regions are
     // free once every thread is past its last read of them.
     __syncthreads();
     if (valid && t < n3) {
@@ -745,8 +747,10 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
     // one line, one direction and two components per task: the line's values are read once and
     // its n results written back in place (each LDS value is read once, not n times); the
     // matrix comes from the table through the scalar cache, the same for every lane
-    const __attribute__((address_space(4))) double *Dg =
-        (const __attribute__((address_space(4))) double *)(OUT == LIFT_WV ? g.tab->Dh : g.tab->D);
+    // (LIFT_SV: Tab::Ds, the strong-form derivative with the interior fluxes interpolated to the
+    // line's two faces and lifted back, -lhat(+1) l(+1) + lhat(-1) l(-1))
+    const __attribute__((address_space(4))) double *Dg = (const __attribute__((address_space(4))) double *)(
+        OUT == LIFT_WV ? g.tab->Dh : (OUT == LIFT_SV ? g.tab->Ds : g.tab->D));
     // TPD task slots per direction: 2 n^2 rounded up to whole waves where the three directions
     // then still fit the workgroup in one pass (n = 7: 98 -> 128, 384 lanes), so that every wave
     // works on one direction
@@ -765,17 +769,6 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
         f0[m] = s0[q];
         f1[m] = s1[q];
       }
-      // LIFT_SV: the interior fluxes interpolated to the line's two faces
-      double tm0 = 0.0, tm1 = 0.0, tp0 = 0.0, tp1 = 0.0;
-      if (OUT == LIFT_SV) {
-#pragma unroll
-        for (int m = 0; m < n; ++m) {
-          tm0 = fma(sl[m], f0[m], tm0);
-          tm1 = fma(sl[m], f1[m], tm1);
-          tp0 = fma(sl[n + m], f0[m], tp0);
-          tp1 = fma(sl[n + m], f1[m], tp1);
-        }
-      }
 #pragma unroll 2
       for (int id = 0; id < n; ++id) {
         double o0 = 0.0, o1 = 0.0;
@@ -784,14 +777,6 @@ __device__ __forceinline__ void lift_body(const Geo &g, const Phys &ph, int e, b
           const double D = Dg[id * n + m];
           o0 = fma(D, f0[m], o0);
           o1 = fma(D, f1[m], o1);
-        }
-        if (OUT == LIFT_SV) {
-          // minus lhat(+-1) times the outward interior flux: -(-1) at the minus face, -(+1) at
-          // the plus face
-          o0 = fma(slh[id], tm0, o0);
-          o1 = fma(slh[id], tm1, o1);
-          o0 = fma(-slh[n + id], tp0, o0);
-          o1 = fma(-slh[n + id], tp1, o1);
         }
         const int q = dir == 0 ? div_slot<n>(id, a, b) : (dir == 1 ? div_slot<n>(a, id, b) : div_slot<n>(a, b, id));
         s0[q] = o0;
@@ -910,18 +895,17 @@ __global__ void __launch_bounds__(Sz<N>::NT, (lift_minb<LGL, OUT, GEN>()))
 }
 
 // ----------------------------------------------------------------------------- operator
-// waves per SIMD the Navier-Stokes weak-form operator and the LGL strong-form one are built for:
-// 4 (128 registers, two workgroups per CU at N = 7; they spill 12 bytes on LGL nodes, the weak
-// form 124 on LG nodes) against the 130-158 registers they take unbounded (one workgroup per CU):
-// weak form 6.40 -> 4.14 ms (LGL), 6.66 -> 6.25 ms (LG) at 48^3, N = 7.  Degrees below 5 (one or
-// two waves per element) keep their registers, and so do the Euler forms (at N = 3 on 96^3 a
-// 128-register budget spills 108 bytes: 5.20 -> 6.15 ms) and the LG strong form (164 registers;
-// at 128 it spills 276 bytes).
+// waves per SIMD the Navier-Stokes weak- and strong-form operators are built for: 4 (128
+// registers, two workgroups per CU at N = 7; no spill on LGL nodes, 84 bytes on LG nodes) against
+// the 131-148 registers they take unbounded (one workgroup per CU): at 48^3, N = 7, weak form on
+// LG nodes 6.14 -> 5.17 ms.  Degrees below 5 (one or two waves per element) keep their registers,
+// and so do the Euler forms (at N = 3 on 96^3 a 128-register budget spills 108 bytes: 5.20 ->
+// 6.15 ms).
 #ifndef DG_WMAIN_MINB
 #define DG_WMAIN_MINB 4
 #endif
 template <int N, bool LGL, bool NS, int FORM, int GEN> constexpr int main_minb() {
-  return (NS && GEN < 2 && N >= 5 && (FORM == 0 || (FORM == 2 && LGL))) ? DG_WMAIN_MINB : 1;
+  return (NS && GEN < 2 && N >= 5 && FORM != 1) ? DG_WMAIN_MINB : 1;
 }
 
 // FORM: 0 weak, 1 split, 2 strong.  MODE: 0 write U_t, 1 fused RK stage.  GEN: face codes.
@@ -956,7 +940,9 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
   if (FVM && g.fvflag[e]) return;  // a finite-volume element
   const double gm1 = ph.gamma - 1.0;
   const Tab *tb = g.tab;
-  for (int c = t; c < n * n; c += NT) sD[c] = (FORM == 0) ? tb->Dh[c] : tb->D[c];
+  // strong form on LG nodes: the derivative matrix carries the interior flux's interpolation
+  // to the line's two faces (Tab::Ds), so the surface terms add the numerical flux alone
+  for (int c = t; c < n * n; c += NT) sD[c] = (FORM == 0) ? tb->Dh[c] : ((FORM == 2 && !LGL) ? tb->Ds[c] : tb->D[c]);
   if (t < n) {
     sl[t] = tb->lm[t]; sl[n + t] = tb->lp[t];
     slh[t] = tb->lhm[t]; slh[n + t] = tb->lhp[t];
@@ -1237,23 +1223,12 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
         const int a = dir == 0 ? j : i, b = dir == 2 ? j : k;
         const int ab = a + n * b;
         const double sg = sd ? 1.0 : -1.0;
-        // strong form: the interior flux at the face point, on LG nodes interpolated along the
-        // line with l(+-1) (eq. semiDiscreteStrong), on LGL nodes the face node's own
-        double Ff[5] = {Fint[0], Fint[1], Fint[2], Fint[3], Fint[4]};
-        if (FORM == 2 && !LGL) {
-          const double *lf = sl + (sd ? n : 0);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) Ff[v] = 0.0;
-          for (int m = 0; m < n; ++m) {
-            const int qm = base + m * str;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) Ff[v] += lf[m] * sX[v * n3 + qm];
-          }
-        }
+        // strong and split forms on LGL nodes: minus the face node's own interior flux (on LG
+        // nodes its interpolation is part of Tab::Ds)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           double pen = sF[(s * 5 + v) * n2 + ab];
-          if (FORM != 0) pen -= sg * Ff[v];
+          if (FORM != 0 && LGL) pen -= sg * Fint[v];
           acc[v] += lh * pen;
         }
       }
