@@ -1196,6 +1196,9 @@ __global__ void __launch_bounds__(Sz<N>::NT, (main_minb<N, LGL, NS, FORM, GEN>()
       const int id = dir == 0 ? i : (dir == 1 ? j : k);
       const int str = dir == 0 ? 1 : (dir == 1 ? n : n2);
       const int base = t - id * str;
+      // at most four nodes' loads in flight: with all n of the last direction's in flight beside
+      // the epilogue's loads the LG operators spilled 84 bytes
+#pragma unroll 4
       for (int m = 0; m < n; ++m) {
         const int qm = base + m * str;
         const double Dm = sD[id * n + m];
